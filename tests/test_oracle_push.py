@@ -1,0 +1,151 @@
+"""Oracle gather + leapfrog push pinned to closed forms (paper Sec. 3:
+explicit PIC, bilinear gather of nodal E).
+
+* constant force: leapfrog is exact, x(t) = x0 + v0 t + a t^2 / 2;
+* linear restoring field: the leapfrog recurrence has the closed form
+  A cos(n theta) + B sin(n theta), cos(theta) = 1 - w^2 dt^2 / 2, also on the
+  adaptive quadtree (bilinear interpolation reproduces a linear field);
+* cold-plasma oscillation of a quiet-start electron sheet: frequency
+  sin(w~ dt/2) = w' dt/2 with w'^2 = w_p^2 sinc^2(k dx/2) sinc(k dx) for CIC
+  scatter/gather with the 3-point Laplacian and the centred gradient.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07713_amd import inputs as I
+
+
+def one_species_1d(n=16, length=1.0, dt=1e-3, charge=1.0, mass=1.0, precision=64):
+    sp = I.species(charge, mass, 1.0, I.MCC_NONE)
+    return I.base_desc(dim=1, precision=precision, length=length, dt=dt, ncells=n, species=[sp],
+                       gas_mass=1.0, gas_density=0.0)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_free_particle_uniform_field(precision):
+    d = one_species_1d(precision=precision)
+    o = oracle.Oracle(d)
+    E0 = 0.05
+    o.field_set(oracle.NODE_E_1D, np.full(17, E0))
+    s0 = np.array([[0.25], [0.5]])
+    v0 = np.array([[0.3, 0, 0], [-0.2, 0, 0]])
+    o.load(0, s0, v0)
+    o.leapfrog_start()
+    nsteps = 1000
+    o.step(0, nsteps)
+    r = o.read(0)
+    t = nsteps * d["dt"]
+    exact = s0[:, 0] + (v0[:, 0] * t + 0.5 * E0 * t * t) / d["length"]
+    tol = 1e-12 if precision == 64 else 2e-5
+    assert np.allclose(r["s"][:, 0], exact, rtol=tol, atol=0)
+    vexact = v0[:, 0] + (nsteps - 0.5) * E0 * d["dt"]
+    assert np.allclose(r["v"][:, 0], vexact, rtol=tol * 10, atol=0)
+
+
+def _harmonic(xi0, v0, w, dt, n):
+    theta = math.acos(1.0 - 0.5 * (w * dt) ** 2)
+    xi1 = xi0 * (1 - 0.5 * (w * dt) ** 2) + v0 * dt
+    B = (xi1 - xi0 * math.cos(theta)) / math.sin(theta)
+    return xi0 * math.cos(n * theta) + B * math.sin(n * theta)
+
+
+def test_harmonic_1d():
+    n, L, dt = 64, 1.0, 1e-2
+    k = 4.0                       # E = -k (x - L/2), q/m = 1 -> w = 2
+    d = one_species_1d(n=n, length=L, dt=dt)
+    o = oracle.Oracle(d)
+    x = np.arange(n + 1) * (L / n)
+    o.field_set(oracle.NODE_E_1D, -k * (x - 0.5 * L))
+    xi0, v0 = 0.2, 0.1
+    o.load(0, [[0.5 + xi0]], [[v0, 0, 0]])
+    o.leapfrog_start()
+    nsteps = 2000
+    o.step(0, nsteps)
+    got = o.read(0)["s"][0, 0] - 0.5
+    assert abs(got - _harmonic(xi0, v0, math.sqrt(k), dt, nsteps)) < 1e-10
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_harmonic_2d_quadtree(precision):
+    """Separable linear field given at the corners of the refined quadtree;
+    the particle crosses leaves of levels 6..9."""
+    d = I.quadtree_static_desc(precision=precision)
+    d["species"] = [I.species(1.0, 1.0, 1.0, I.MCC_NONE)]
+    d["dt"] = 2e-3
+    o = oracle.Oracle(d)
+    keys, lv = o.leaves()
+    cx, cy = I.leaf_corners(keys, lv)
+    k1, k2 = 9.0, 4.0
+    E = np.stack([-k1 * (cx - 0.5), -k2 * (cy - 0.5)], axis=2)     # (nleaves, 4, 2)
+    o.field_set(oracle.CORNER_E_2D, E)
+    s0 = np.array([[0.5 + 0.3, 0.5 - 0.1], [0.52, 0.33]])
+    v0 = np.array([[0.0, 0.4, 0.0], [0.1, -0.2, 0.0]])
+    o.load(0, s0, v0)
+    o.leapfrog_start()
+    nsteps = 1500
+    o.step(0, nsteps)
+    r = o.read(0)
+    for j in range(2):
+        ex = _harmonic(s0[j, 0] - 0.5, v0[j, 0], 3.0, d["dt"], nsteps)
+        ey = _harmonic(s0[j, 1] - 0.5, v0[j, 1], 2.0, d["dt"], nsteps)
+        tol = 1e-10 if precision == 64 else 5e-5
+        assert abs(r["s"][j, 0] - 0.5 - ex) < tol
+        assert abs(r["s"][j, 1] - 0.5 - ey) < tol
+        # located leaf contains the particle
+        assert o.locate(r["s"][j:j + 1])[0] == r["cell"][j]
+
+
+def test_cold_plasma_oscillation():
+    n0, N, L, ppc = 1e14, 128, 0.067, 64
+    d0 = I.ccp_desc(ncells=N, ppc=ppc)
+    dt = d0["dt"]
+    ne = N * ppc
+    w0 = n0 * L / ne
+    e = I.species(-I.E_CHARGE, I.M_ELECTRON, w0, I.MCC_NONE)
+    ion = I.species(I.E_CHARGE, 1e6, w0, I.MCC_NONE)           # immobile background
+    d = I.base_desc(dim=1, precision=64, length=L, dt=dt, ncells=N, species=[e, ion],
+                    gas_mass=1.0)
+    o = oracle.Oracle(d)
+    s_eq = (np.arange(ne) + 0.5) / ne
+    delta = 1e-4
+    o.load(0, (s_eq + delta * np.sin(2 * np.pi * s_eq))[:, None], np.zeros((ne, 3)),
+           ids=np.arange(ne, dtype=np.uint32))
+    o.load(1, s_eq[:, None], np.zeros((ne, 3)), ids=np.arange(ne, 2 * ne, dtype=np.uint32))
+    o.deposit()
+    o.field_solve_1d(0.0)
+    o.leapfrog_start()
+    nsteps = 600
+    amp = np.empty(nsteps + 1)
+    basis = np.sin(2 * np.pi * s_eq)
+
+    def mode():
+        s = o.read(0)["s"][:, 0]
+        return 2.0 / ne * np.sum((s - s_eq) * basis)
+
+    amp[0] = mode()
+    for k in range(nsteps):
+        o.step(k, 1, np.zeros(1), True)
+        amp[k + 1] = mode()
+    wp = math.sqrt(n0 * I.E_CHARGE ** 2 / (8.8541878128e-12 * I.M_ELECTRON))
+    kdx = 2 * np.pi / N
+    sinc = lambda x: math.sin(x) / x
+    wprime = wp * sinc(kdx / 2) * math.sqrt(sinc(kdx))
+    w_expect = 2.0 / dt * math.asin(wprime * dt / 2)
+    # least-squares frequency: scan around the expectation
+    t = np.arange(nsteps + 1) * dt
+
+    def resid(w):
+        A = np.stack([np.cos(w * t), np.sin(w * t)], axis=1)
+        c, *_ = np.linalg.lstsq(A, amp, rcond=None)
+        return np.sum((A @ c - amp) ** 2)
+
+    ws = w_expect * (1 + np.linspace(-3e-3, 3e-3, 601))
+    r = np.array([resid(w) for w in ws])
+    w_fit = ws[np.argmin(r)]
+    assert abs(w_fit / w_expect - 1) < 5e-5
+    # the uncorrected plasma frequency is measurably off, so the grid factor matters
+    assert abs(2.0 / dt * math.asin(wp * dt / 2) / w_expect - 1) > 2e-4
+    assert abs(amp[0] - delta) < 1e-9
