@@ -1,0 +1,828 @@
+// extern "C" entry points of include/pic.h.  Argument checking, marshalling
+// between host arrays and device state, and the launch sequences; every
+// step of the particle loop and of the field solves runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "device_util.hpp"
+#include "pic_internal.hpp"
+
+using namespace pic;
+
+struct pic_ctx_s : public Ctx {};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define PIC_GUARD_BEGIN try {
+#define PIC_GUARD_END(ctx)                                   \
+  }                                                          \
+  catch (const Err& e) {                                     \
+    if (ctx) (ctx)->err = e.msg;                             \
+    g_last_error = e.msg;                                    \
+    return e.code;                                           \
+  }                                                          \
+  catch (const std::exception& e) {                          \
+    if (ctx) (ctx)->err = e.what();                          \
+    g_last_error = e.what();                                 \
+    return PIC_E_ARG;                                        \
+  }
+
+Slot& get_slot(pic_ctx c, int slot) {
+  if (!c) throw Err(PIC_E_ARG, "null context");
+  if (slot < 0 || slot >= (int)c->slots.size() || !c->slots[slot].live) throw Err(PIC_E_ARG, "no such slot");
+  return c->slots[slot];
+}
+
+Mesh2D mesh_of(const Slot& sl) {
+  Mesh2D m;
+  m.key = sl.key;
+  m.xy = sl.xy;
+  m.lv = sl.lv;
+  m.lut = sl.lut;
+  m.lut_level = sl.lut_level;
+  m.nleaves = sl.nleaves;
+  m.length = sl.d.length;
+  for (int i = 0; i < 4; ++i) {
+    m.field_bc[i] = sl.d.field_bc[i];
+    m.wall_phi[i] = sl.d.wall_phi[i];
+  }
+  return m;
+}
+
+void* dev_upload(Ctx& C, Slot& sl, const void* host, size_t bytes) {
+  void* d = sl.alloc(bytes);
+  hip_check(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, C.stream), "upload");
+  C.sync();
+  return d;
+}
+
+template <class T>
+int plain_grid(const Slot& sl) {
+  return grid_for(sl.cap[0] + sl.cap[1]);
+}
+
+__global__ void k_locate_points(const uint32_t* key, const uint8_t* lv, const uint32_t* lut, int L, const double* s,
+                                int64_t n, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t X = (uint32_t)(s[2 * i] * 65536.0), Y = (uint32_t)(s[2 * i + 1] * 65536.0);
+  out[i] = locate_leaf(key, lv, lut, L, X, Y);
+}
+
+__global__ void k_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x0 = ctr[4 * i], x1 = ctr[4 * i + 1], x2 = ctr[4 * i + 2], x3 = ctr[4 * i + 3];
+  philox4x32_10(x0, x1, x2, x3, k0, k1);
+  out[4 * i] = x0;
+  out[4 * i + 1] = x1;
+  out[4 * i + 2] = x2;
+  out[4 * i + 3] = x3;
+}
+
+// ---- one plain step of one slot ----
+template <class T>
+void plain_step(Ctx& C, Slot& sl, bool solve, hipEvent_t e0, hipEvent_t e1) {
+  InstDev<T> I = make_dev<T>(sl);
+  const int g = plain_grid<T>(sl);
+  I.nparts = (uint32_t)g;
+  if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
+  if (sl.d.dim == 1) hip_check(launch_step1d<T>(I, C.stream, g), "step1d");
+  else hip_check(launch_step2d<T>(I, C.stream, g), "step2d");
+  if (sl.ionizing) hip_check(launch_births<T>(I, C.stream, 64), "births");
+  if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
+  if (sl.d.dim == 1 && solve)
+    hip_check(launch_field1d<T>((const InstDev<T>*)sl.devI, 1, sl.d.ncells, 1, nullptr, sl.part, nullptr, C.stream),
+              "field1d");
+  else
+    hip_check(launch_commit<T>(I, (uint32_t)g, C.stream), "commit");
+}
+
+void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead) {
+  if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
+  if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
+  Counters cn = read_counters(C, sl);
+  cn.step = (uint32_t)a->step0;
+  cn.vstep0 = (uint32_t)a->step0 + 1u;
+  if (sl.d.dim == 1 && a->solve_field) {
+    if (!a->v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
+    if (sl.v_cap < (uint32_t)a->nsteps) {
+      sl.release(sl.v_table);
+      sl.v_cap = (uint32_t)std::max(a->nsteps, 64);
+      sl.v_table = (double*)sl.alloc(8 * sl.v_cap);
+    }
+    std::vector<double> vt(a->nsteps);
+    for (int k = 0; k < a->nsteps; ++k) vt[k] = a->v_next[(size_t)k * nsel + j];
+    hip_check(hipMemcpyAsync(sl.v_table, C.stage(vt.data(), 8 * vt.size()), 8 * vt.size(), hipMemcpyHostToDevice,
+                             C.stream),
+              "v table");
+    sl.v_len = (uint32_t)a->nsteps;
+  }
+  write_counters(C, sl, cn);
+  ensure_capacity(C, sl, cn, steps_ahead);
+  upload_dev(C, sl);
+}
+
+void finish_stats(Ctx& C, std::vector<Slot*>& sel, std::vector<Counters>& before, pic_step_stats* st) {
+  pic_step_stats out;
+  std::memset(&out, 0, sizeof(out));
+  std::string err;
+  for (size_t j = 0; j < sel.size(); ++j) {
+    Counters c = read_counters(C, *sel[j]);
+    const Counters& b = before[j];
+    out.alive_start[0] += (int64_t)(c.stats[kStAlive0] - b.stats[kStAlive0]);
+    out.alive_start[1] += (int64_t)(c.stats[kStAlive1] - b.stats[kStAlive1]);
+    out.absorbed[0] += (int64_t)(c.stats[kStAbs0] - b.stats[kStAbs0]);
+    out.absorbed[1] += (int64_t)(c.stats[kStAbs1] - b.stats[kStAbs1]);
+    out.elastic += (int64_t)(c.stats[kStElastic] - b.stats[kStElastic]);
+    out.ionization += (int64_t)(c.stats[kStIonization] - b.stats[kStIonization]);
+    out.cx += (int64_t)(c.stats[kStCx] - b.stats[kStCx]);
+    out.births += (int64_t)(c.stats[kStBirths] - b.stats[kStBirths]);
+    out.numax_violations[0] += (int64_t)(c.stats[kStViol0] - b.stats[kStViol0]);
+    out.numax_violations[1] += (int64_t)(c.stats[kStViol1] - b.stats[kStViol1]);
+    out.lost_reflect += (int64_t)(c.stats[kStLostReflect] - b.stats[kStLostReflect]);
+    if (c.flags) {
+      sel[j]->error_state = true;
+      err = "capacity exceeded on the device (flags " + std::to_string(c.flags) + ")";
+    }
+  }
+  if (st) {
+    const double lm = st->loop_ms, sm = st->step_ms;
+    *st = out;
+    st->loop_ms = lm;
+    st->step_ms = sm;
+  }
+  if (!err.empty()) throw Err(PIC_E_CAPACITY, err);
+}
+
+std::vector<Slot*> selection(pic_ctx c, const pic_step_args* a) {
+  std::vector<Slot*> sel;
+  if (a->slots) {
+    for (int j = 0; j < a->nslots; ++j) sel.push_back(&get_slot(c, a->slots[j]));
+  } else {
+    for (Slot& s : c->slots)
+      if (s.live) sel.push_back(&s);
+  }
+  if (sel.empty()) throw Err(PIC_E_ARG, "no slots selected");
+  return sel;
+}
+
+hipEvent_t get_event(Ctx& C, size_t i) {
+  while (C.ev.size() <= i) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    C.ev.push_back(e);
+  }
+  return C.ev[i];
+}
+
+template <class T>
+void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int64_t kbeg, int64_t kend,
+                   double* loop_ms) {
+  const int nsel = (int)sel.size();
+  const uint32_t tile = (uint32_t)(a->batched > 1 ? a->batched : 4096);
+  std::vector<WorkItem> items;
+  std::vector<uint32_t> rowbeg(nsel + 1, 0);
+  bool ionizing = false;
+  int maxn = 0;
+  for (int j = 0; j < nsel; ++j) {
+    Slot& sl = *sel[j];
+    rowbeg[j] = (uint32_t)items.size();
+    ionizing = ionizing || sl.ionizing;
+    maxn = std::max(maxn, sl.d.ncells);
+    for (int sp = 0; sp < sl.d.nspecies; ++sp)
+      for (int64_t b = 0; b < sl.cap[sp]; b += tile)
+        items.push_back(WorkItem{(uint32_t)j, (uint32_t)sp, (uint32_t)b, (uint32_t)std::min<int64_t>(b + tile, sl.cap[sp])});
+  }
+  rowbeg[nsel] = (uint32_t)items.size();
+  // largest instances first keeps the persistent grid's tail short
+  auto ensure = [&](void*& p, size_t& have, size_t need) {
+    if (have >= need) return;
+    if (p) (void)hipFree(p);
+    hip_check(hipMalloc(&p, need), "hipMalloc batched");
+    have = need;
+  };
+  ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * items.size());
+  ensure(C.b_insts, C.b_insts_bytes, sizeof(InstDev<T>) * nsel);
+  ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * items.size());
+  ensure(*(void**)&C.b_rowbeg, C.b_rowbeg_bytes, sizeof(uint32_t) * (nsel + 1));
+  hip_check(hipMemcpyAsync(C.b_items, C.stage(items.data(), sizeof(WorkItem) * items.size()),
+                           sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, C.stream),
+            "items");
+  hip_check(hipMemcpyAsync(C.b_rowbeg, C.stage(rowbeg.data(), 4 * rowbeg.size()), 4 * rowbeg.size(),
+                           hipMemcpyHostToDevice, C.stream),
+            "rowbeg");
+  auto upload_insts = [&]() {
+    std::vector<InstDev<T>> v(nsel);
+    for (int j = 0; j < nsel; ++j) v[j] = make_dev<T>(*sel[j]);
+    hip_check(hipMemcpyAsync(C.b_insts, C.stage(v.data(), sizeof(InstDev<T>) * nsel), sizeof(InstDev<T>) * nsel,
+                             hipMemcpyHostToDevice, C.stream),
+              "insts");
+  };
+  upload_insts();
+  const int grid = (int)std::min<size_t>(items.size(), 256 * 8);
+  const InstDev<T>* dI = (const InstDev<T>*)C.b_insts;
+  for (int64_t k = kbeg; k < kend; ++k) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (loop_ms) {
+      e0 = get_event(C, 2 * (k - kbeg));
+      e1 = get_event(C, 2 * (k - kbeg) + 1);
+      hip_check(hipEventRecord(e0, C.stream), "event");
+    }
+    hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)C.b_items, (uint32_t)items.size(), C.b_part, C.stream,
+                                       grid),
+              "step1d_batched");
+    if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, C.stream), "births_batched");
+    if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
+    if (a->solve_field)
+      hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, C.b_part, C.b_rowbeg, C.stream), "field1d batched");
+    else
+      hip_check(launch_commit_batched<T>(dI, C.b_part, C.b_rowbeg, nsel, C.stream), "commit batched");
+    if (a->sort_every > 0 && (k + 1) % a->sort_every == 0 && k + 1 < kend) {
+      for (Slot* s : sel) sort_slot(C, *s);
+      upload_insts();
+    }
+  }
+  if (loop_ms) {
+    C.sync();
+    for (int64_t k = kbeg; k < kend; ++k) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, C.ev[2 * (k - kbeg)], C.ev[2 * (k - kbeg) + 1]), "elapsed");
+      *loop_ms += ms;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_abi_version(void) { return PIC_ABI_VERSION; }
+
+const char* pic_last_error(pic_ctx c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+int pic_mesh_build(const pic_instance_desc* descs, int ninst, void* stream, pic_ctx* out) {
+  pic_ctx c = nullptr;
+  PIC_GUARD_BEGIN
+  if (!descs || ninst < 1 || !out) throw Err(PIC_E_ARG, "need descriptors and an output handle");
+  c = new pic_ctx_s();
+  c->stream = (hipStream_t)stream;
+  c->arena_size = 8u << 20;
+  hip_check(hipHostMalloc(&c->arena, c->arena_size, hipHostMallocDefault), "hipHostMalloc");
+  c->slots.resize(ninst);
+  for (int i = 0; i < ninst; ++i) build_slot(*c, c->slots[i], descs[i]);
+  for (int i = 0; i < ninst; ++i) upload_dev(*c, c->slots[i]);
+  c->sync();
+  *out = c;
+  return PIC_OK;
+  }
+  catch (const Err& e) {
+    g_last_error = e.msg;
+    if (c) pic_destroy(c);
+    return e.code;
+  }
+}
+
+void pic_destroy(pic_ctx c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (Slot& s : c->slots) s.release_all();
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (void* p : {c->b_insts, c->b_items, (void*)c->b_part, (void*)c->b_rowbeg})
+    if (p) (void)hipFree(p);
+  if (c->arena) (void)hipHostFree(c->arena);
+  delete c;
+}
+
+int pic_set_stream(pic_ctx c, void* stream) {
+  PIC_GUARD_BEGIN
+  if (!c) throw Err(PIC_E_ARG, "null context");
+  c->sync();
+  c->stream = (hipStream_t)stream;
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_sync(pic_ctx c) {
+  PIC_GUARD_BEGIN
+  if (!c) throw Err(PIC_E_ARG, "null context");
+  c->sync();
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_num_slots(pic_ctx c) { return c ? (int)c->slots.size() : 0; }
+
+int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double* s, const double* v,
+                       const uint32_t* w, const uint32_t* id) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (species < 0 || species >= sl.d.nspecies) throw Err(PIC_E_ARG, "bad species");
+  if (n < 0 || n > 0x7FFFFFFF || (n > 0 && (!s || !v))) throw Err(PIC_E_ARG, "bad particle arrays");
+  const int dim = sl.d.dim;
+  for (int64_t i = 0; i < n * dim; ++i)
+    if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "position outside [0,1)");
+  int64_t cap = std::max<int64_t>(sl.d.capacity[species], sl.ionizing ? 2 * n + 4096 : n);
+  cap = std::max<int64_t>(cap, 256);
+  cap = (cap + 255) & ~(int64_t)255;
+  Counters cn = read_counters(*c, sl);
+  if (cap > sl.cap[species] || !sl.pb[species][0].base) {
+    alloc_particles(sl, species, cap, 0);
+    alloc_particles(sl, species, cap, 1);
+    sl.cap[species] = cap;
+  }
+  sl.cur[species] = 0;
+  const PBuf& b = sl.pb[species][0];
+  const size_t e = sl.esz;
+  std::vector<char> tmp(e * (size_t)std::max<int64_t>(n, 1));
+  auto put = [&](void* dst, const double* src, int stride, int comp) {
+    if (e == 4) {
+      float* f = (float*)tmp.data();
+      for (int64_t i = 0; i < n; ++i) f[i] = (float)src[i * stride + comp];
+    } else {
+      double* f = (double*)tmp.data();
+      for (int64_t i = 0; i < n; ++i) f[i] = src[i * stride + comp];
+    }
+    hip_check(hipMemcpy(dst, tmp.data(), e * n, hipMemcpyHostToDevice), "load");
+  };
+  if (n) {
+    for (int k = 0; k < dim; ++k) put(b.s[k], s, dim, k);
+    for (int k = 0; k < 3; ++k) put(b.v[k], v, 3, k);
+    std::vector<uint32_t> ww(n), ii(n);
+    uint32_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      ww[i] = w ? w[i] : 65536u;
+      ii[i] = id ? id[i] : (uint32_t)i;
+      if (ww[i] == 0u) throw Err(PIC_E_ARG, "particle weight must be positive");
+      mx = std::max(mx, ii[i]);
+    }
+    hip_check(hipMemcpy(b.w, ww.data(), 4 * n, hipMemcpyHostToDevice), "load");
+    hip_check(hipMemcpy(b.id, ii.data(), 4 * n, hipMemcpyHostToDevice), "load");
+    sl.max_id_loaded[species] = mx + 1u;
+  } else {
+    sl.max_id_loaded[species] = 0;
+  }
+  cn.count[species] = (uint32_t)n;
+  cn.next_id = std::max(cn.next_id, std::max(sl.max_id_loaded[0], sl.max_id_loaded[1]));
+  write_counters(*c, sl, cn);
+  if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) alloc_births(sl, sl.cap[0]);
+  if (dim == 2 && n) {
+    if (sl.prec == 32) hip_check(launch_relocate<float>(make_dev<float>(sl), species, c->stream, grid_for(n)), "relocate");
+    else hip_check(launch_relocate<double>(make_dev<double>(sl), species, c->stream, grid_for(n)), "relocate");
+  }
+  upload_dev(*c, sl);
+  c->sync();
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int64_t pic_count(pic_ctx c, int slot, int species) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (species < 0 || species >= sl.d.nspecies) throw Err(PIC_E_ARG, "bad species");
+  Counters cn = read_counters(*c, sl);
+  const uint32_t n = cn.count[species];
+  if (!n) return 0;
+  std::vector<uint32_t> w(n);
+  hip_check(hipMemcpy(w.data(), sl.pb[species][sl.cur[species]].w, 4 * (size_t)n, hipMemcpyDeviceToHost), "read");
+  return (int64_t)std::count_if(w.begin(), w.end(), [](uint32_t x) { return x != 0u; });
+  PIC_GUARD_END(c)
+}
+
+uint32_t pic_next_id(pic_ctx c, int slot) {
+  try {
+    Slot& sl = get_slot(c, slot);
+    return read_counters(*c, sl).next_id;
+  } catch (...) {
+    return 0;
+  }
+}
+
+int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, uint32_t* w, uint32_t* id,
+                       uint32_t* cell) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (species < 0 || species >= sl.d.nspecies) throw Err(PIC_E_ARG, "bad species");
+  Counters cn = read_counters(*c, sl);
+  const size_t n = cn.count[species];
+  const PBuf& b = sl.pb[species][sl.cur[species]];
+  const int dim = sl.d.dim;
+  const size_t e = sl.esz;
+  std::vector<uint32_t> hw(n), hid(n), hc(n, 0);
+  std::vector<double> hs(n * dim), hv(n * 3);
+  if (n) {
+    hip_check(hipMemcpy(hw.data(), b.w, 4 * n, hipMemcpyDeviceToHost), "read");
+    hip_check(hipMemcpy(hid.data(), b.id, 4 * n, hipMemcpyDeviceToHost), "read");
+    if (dim == 2) hip_check(hipMemcpy(hc.data(), b.cell, 4 * n, hipMemcpyDeviceToHost), "read");
+    std::vector<char> tmp(e * n);
+    auto get = [&](const void* src, double* dst, int stride, int comp) {
+      hip_check(hipMemcpy(tmp.data(), src, e * n, hipMemcpyDeviceToHost), "read");
+      for (size_t i = 0; i < n; ++i)
+        dst[i * stride + comp] = e == 4 ? (double)((float*)tmp.data())[i] : ((double*)tmp.data())[i];
+    };
+    for (int k = 0; k < dim; ++k) get(b.s[k], hs.data(), dim, k);
+    for (int k = 0; k < 3; ++k) get(b.v[k], hv.data(), 3, k);
+  }
+  std::vector<size_t> order;
+  for (size_t i = 0; i < n; ++i)
+    if (hw[i]) order.push_back(i);
+  std::sort(order.begin(), order.end(), [&](size_t a, size_t bb) { return hid[a] < hid[bb]; });
+  for (size_t j = 0; j < order.size(); ++j) {
+    const size_t i = order[j];
+    if (s) for (int k = 0; k < dim; ++k) s[j * dim + k] = hs[i * dim + k];
+    if (v) for (int k = 0; k < 3; ++k) v[j * 3 + k] = hv[i * 3 + k];
+    if (w) w[j] = hw[i];
+    if (id) id[j] = hid[i];
+    if (cell) {
+      if (dim == 2) {
+        cell[j] = hc[i];
+      } else {
+        const int N = sl.d.ncells;
+        int64_t ic;
+        if (e == 4) ic = (int64_t)std::floor((float)hs[i] * (float)N);
+        else ic = (int64_t)std::floor(hs[i] * (double)N);
+        if (ic > N - 1) ic = N - 1;
+        cell[j] = (uint32_t)ic;
+      }
+    }
+  }
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int64_t pic_nleaves(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  return sl.d.dim == 2 ? (int64_t)sl.nleaves : 0;
+  PIC_GUARD_END(c)
+}
+
+int pic_leaves_read(pic_ctx c, int slot, uint32_t* keys, uint8_t* levels) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (sl.d.dim != 2) throw Err(PIC_E_ARG, "not a quadtree slot");
+  c->sync();
+  if (keys) hip_check(hipMemcpy(keys, sl.key, 4 * (size_t)sl.nleaves, hipMemcpyDeviceToHost), "read");
+  if (levels) hip_check(hipMemcpy(levels, sl.lv, sl.nleaves, hipMemcpyDeviceToHost), "read");
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int64_t pic_nq(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  return (int64_t)get_slot(c, slot).nq;
+  PIC_GUARD_END(c)
+}
+
+int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (!data) throw Err(PIC_E_ARG, "null data");
+  if (sl.d.dim == 1) {
+    if (kind != PIC_NODE_E_1D && kind != PIC_NODE_PHI_1D) throw Err(PIC_E_ARG, "bad field kind for 1D");
+    hip_check(hipMemcpy(sl.phi64, data, 8 * (size_t)(sl.d.ncells + 1), hipMemcpyHostToDevice), "upload");
+    // data staged in phi64 (node potential or node E) -> E table
+    if (sl.prec == 32) hip_check(launch_node_e_1d<float>(make_dev<float>(sl), sl.phi64, kind == PIC_NODE_PHI_1D, c->stream), "node_e");
+    else hip_check(launch_node_e_1d<double>(make_dev<double>(sl), sl.phi64, kind == PIC_NODE_PHI_1D, c->stream), "node_e");
+    c->sync();
+    return PIC_OK;
+  }
+  const Mesh2D m = mesh_of(sl);
+  const size_t n = sl.nleaves;
+  if (kind == PIC_CORNER_PHI_2D) {
+    hip_check(hipMemcpy(sl.cphi, data, 8 * 4 * n, hipMemcpyHostToDevice), "upload");
+  } else if (kind == PIC_CELL_PHI_2D) {
+    hip_check(hipMemcpy(sl.phi64, data, 8 * n, hipMemcpyHostToDevice), "upload");
+    hip_check(launch_cell_to_corner_phi(m, sl.phi64, sl.cphi, c->stream), "cell_to_corner");
+  } else if (kind == PIC_CORNER_E_2D) {
+    hip_check(hipMemcpy(sl.e64, data, 8 * 8 * n, hipMemcpyHostToDevice), "upload");
+    if (sl.prec == 32) hip_check(launch_round_table<float>(sl.e64, (float*)sl.E, (int64_t)(8 * n), c->stream), "round");
+    else hip_check(launch_round_table<double>(sl.e64, (double*)sl.E, (int64_t)(8 * n), c->stream), "round");
+    c->sync();
+    return PIC_OK;
+  } else {
+    throw Err(PIC_E_ARG, "bad field kind for 2D");
+  }
+  if (sl.prec == 32) hip_check(launch_corner_field<float>(m, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner");
+  else hip_check(launch_corner_field<double>(m, sl.cphi, sl.grad, sl.e64, (double*)sl.E, c->stream), "corner");
+  c->sync();
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_field_read(pic_ctx c, int slot, double* out) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1 : (size_t)sl.nleaves * 8;
+  std::vector<char> tmp(sl.esz * n);
+  c->sync();
+  hip_check(hipMemcpy(tmp.data(), sl.E, sl.esz * n, hipMemcpyDeviceToHost), "read");
+  for (size_t i = 0; i < n; ++i) out[i] = sl.esz == 4 ? (double)((float*)tmp.data())[i] : ((double*)tmp.data())[i];
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_leapfrog_start(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  const int g = grid_for(std::max(sl.cap[0], sl.cap[1]));
+  if (sl.prec == 32) hip_check(launch_leapfrog_start<float>(make_dev<float>(sl), c->stream, g), "leapfrog");
+  else hip_check(launch_leapfrog_start<double>(make_dev<double>(sl), c->stream, g), "leapfrog");
+  c->sync();
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_deposit(pic_ctx c, int slot, uint64_t* q_out) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, c->stream), "memset");
+  const int g = grid_for(std::max(sl.cap[0], sl.cap[1]));
+  if (sl.prec == 32) hip_check(launch_deposit<float>(make_dev<float>(sl), c->stream, g), "deposit");
+  else hip_check(launch_deposit<double>(make_dev<double>(sl), c->stream, g), "deposit");
+  Counters cn = read_counters(*c, sl);
+  if (q_out) {
+    const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
+    hip_check(hipMemcpy(q_out, latest, 8 * 2 * (size_t)sl.nq, hipMemcpyDeviceToHost), "read");
+  }
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init, double rtol, int maxit,
+                    double* phi_out, double* e_out, int* iters, double* relres) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (sl.d.dim == 1) {
+    double* pl = (double*)c->stage(&phi_left, sizeof(double));
+    upload_dev(*c, sl);
+    if (sl.prec == 32)
+      hip_check(launch_field1d<float>((const InstDev<float>*)sl.devI, 1, sl.d.ncells, 0, pl, nullptr, nullptr, c->stream), "field1d");
+    else
+      hip_check(launch_field1d<double>((const InstDev<double>*)sl.devI, 1, sl.d.ncells, 0, pl, nullptr, nullptr, c->stream), "field1d");
+    c->sync();
+    const size_t n = (size_t)sl.d.ncells + 1;
+    if (phi_out) hip_check(hipMemcpy(phi_out, sl.phi64, 8 * n, hipMemcpyDeviceToHost), "read");
+    if (e_out) hip_check(hipMemcpy(e_out, sl.e64, 8 * n, hipMemcpyDeviceToHost), "read");
+    if (iters) *iters = 1;
+    if (relres) *relres = 0.0;
+    return PIC_OK;
+  }
+  const Mesh2D m = mesh_of(sl);
+  const uint32_t n = sl.nleaves;
+  if (!sl.stencil_ok) {
+    for (void* p : {(void*)sl.st.nbr, (void*)sl.st.coef, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
+      sl.release(p);
+    sl.st.nbr = (uint32_t*)sl.alloc(4 * 8 * (size_t)n);
+    sl.st.coef = (double*)sl.alloc(8 * 8 * (size_t)n);
+    sl.st.diag = (double*)sl.alloc(8 * (size_t)n);
+    sl.st.bnd = (double*)sl.alloc(8 * (size_t)n);
+    sl.cg_ws = (double*)sl.alloc(8 * (size_t)cg_ws_doubles(n));
+    hip_check(launch_build_stencil(m, sl.st, c->stream), "stencil");
+    sl.stencil_ok = true;
+  }
+  if (phi_init) hip_check(hipMemcpy(sl.phi64, phi_init, 8 * (size_t)n, hipMemcpyHostToDevice), "upload");
+  Counters cn = read_counters(*c, sl);
+  const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
+  hip_check(launch_cg_setup(m, sl.st, latest, sl.d.nspecies, sl.kappa, sl.phi64, sl.cg_ws, c->stream), "cg_setup");
+  const int g = cg_grid(n);
+  const double* sc = sl.cg_ws + 4u * (size_t)n + 3u * (size_t)g;
+  int it = 0;
+  double rr = 0, bb = 0;
+  for (;;) {
+    double h[4];
+    hip_check(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, c->stream), "read");
+    c->sync();
+    rr = h[2];
+    bb = h[3];
+    if (std::sqrt(rr) <= rtol * std::sqrt(bb) || it >= maxit) break;
+    const int batch = std::min(4, maxit - it);
+    for (int q = 0; q < batch; ++q) hip_check(launch_cg_iter(m, sl.st, sl.phi64, sl.cg_ws, c->stream), "cg_iter");
+    it += batch;
+  }
+  hip_check(launch_cell_to_corner_phi(m, sl.phi64, sl.cphi, c->stream), "cell_to_corner");
+  if (sl.prec == 32) hip_check(launch_corner_field<float>(m, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner");
+  else hip_check(launch_corner_field<double>(m, sl.cphi, sl.grad, sl.e64, (double*)sl.E, c->stream), "corner");
+  c->sync();
+  if (phi_out) hip_check(hipMemcpy(phi_out, sl.phi64, 8 * (size_t)n, hipMemcpyDeviceToHost), "read");
+  if (e_out) hip_check(hipMemcpy(e_out, sl.e64, 8 * 8 * (size_t)n, hipMemcpyDeviceToHost), "read");
+  if (iters) *iters = it;
+  const double res = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
+  if (relres) *relres = res;
+  if (!(res <= rtol)) throw Err(PIC_E_NUMERIC, "CG did not reach the tolerance");
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
+  PIC_GUARD_BEGIN
+  if (!c || !a || a->nsteps < 0) throw Err(PIC_E_ARG, "bad step arguments");
+  std::vector<Slot*> sel = selection(c, a);
+  const int nsel = (int)sel.size();
+  if (stats) {
+    stats->loop_ms = 0;
+    stats->step_ms = 0;
+  }
+  std::vector<Counters> before(nsel);
+  bool any_ionizing = false;
+  for (Slot* s : sel) any_ionizing = any_ionizing || s->ionizing;
+  const int64_t chunk = any_ionizing ? 64 : std::max(a->nsteps, 1);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (a->timing) {
+    t0 = get_event(*c, 0);
+    t1 = get_event(*c, 1);
+  }
+  double loop_ms = 0;
+  bool started = false;
+  for (int64_t kb = 0; kb < a->nsteps; kb += chunk) {
+    const int64_t ke = std::min<int64_t>(a->nsteps, kb + chunk);
+    pic_step_args sub = *a;
+    sub.step0 = a->step0 + kb;
+    sub.nsteps = (int)(ke - kb);
+    std::vector<double> vn;
+    if (a->solve_field && a->v_next) {
+      vn.assign(a->v_next + (size_t)kb * nsel, a->v_next + (size_t)ke * nsel);
+      sub.v_next = vn.data();
+    }
+    for (int j = 0; j < nsel; ++j) {
+      if (kb == 0) before[j] = read_counters(*c, *sel[j]);
+      prepare_slot(*c, *sel[j], &sub, j, nsel, ke - kb);
+    }
+    if (a->timing && !started) {
+      hip_check(hipEventRecord(t0, c->stream), "event");
+      started = true;
+    }
+    if (a->batched) {
+      for (Slot* s : sel)
+        if (s->d.dim != 1 || s->prec != sel[0]->prec) throw Err(PIC_E_ARG, "batched steps need 1D slots of one precision");
+      double lm = 0;
+      if (sel[0]->prec == 32) batched_steps<float>(*c, sel, &sub, 0, sub.nsteps, a->timing ? &lm : nullptr);
+      else batched_steps<double>(*c, sel, &sub, 0, sub.nsteps, a->timing ? &lm : nullptr);
+      loop_ms += lm;
+    } else {
+      std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+      for (int64_t k = 0; k < sub.nsteps; ++k) {
+        for (int j = 0; j < nsel; ++j) {
+          Slot& sl = *sel[j];
+          hipEvent_t e0 = nullptr, e1 = nullptr;
+          if (a->timing) {
+            e0 = get_event(*c, 2 + 2 * evs.size());
+            e1 = get_event(*c, 3 + 2 * evs.size());
+            evs.push_back({e0, e1});
+          }
+          if (sl.prec == 32) plain_step<float>(*c, sl, a->solve_field != 0, e0, e1);
+          else plain_step<double>(*c, sl, a->solve_field != 0, e0, e1);
+          if (a->sort_every > 0 && (kb + k + 1) % a->sort_every == 0) sort_slot(*c, sl);
+        }
+      }
+      if (a->timing) {
+        c->sync();
+        for (auto& p : evs) {
+          float ms = 0;
+          hip_check(hipEventElapsedTime(&ms, p.first, p.second), "elapsed");
+          loop_ms += ms;
+        }
+      }
+    }
+  }
+  if (a->timing && started) {
+    hip_check(hipEventRecord(t1, c->stream), "event");
+    c->sync();
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, t0, t1), "elapsed");
+    if (stats) stats->step_ms = ms;
+  }
+  if (stats) stats->loop_ms = loop_ms;
+  finish_stats(*c, sel, before, stats);
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_sort(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  sort_slot(*c, sl);
+  c->sync();
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (sl.d.dim != 2) throw Err(PIC_E_ARG, "not a quadtree slot");
+  for (int64_t i = 0; i < 2 * n; ++i)
+    if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "point outside [0,1)");
+  double* ds = nullptr;
+  uint32_t* dl = nullptr;
+  hip_check(hipMalloc(&ds, 16 * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
+  hip_check(hipMalloc(&dl, 4 * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
+  hip_check(hipMemcpy(ds, s, 16 * (size_t)n, hipMemcpyHostToDevice), "upload");
+  hipLaunchKernelGGL(k_locate_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, sl.key, sl.lv,
+                     sl.lut, sl.lut_level, ds, n, dl);
+  hip_check(hipGetLastError(), "locate");
+  c->sync();
+  hip_check(hipMemcpy(leaf, dl, 4 * (size_t)n, hipMemcpyDeviceToHost), "read");
+  (void)hipFree(ds);
+  (void)hipFree(dl);
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_derived(pic_ctx c, int slot, int species, double* out) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (species < 0 || species > 1) throw Err(PIC_E_ARG, "bad species");
+  if (sl.prec == 32) {
+    SpeciesK<float> k = to_dev<float>(sl.hk[species]);
+    double v[] = {k.qm_dt, k.dt_L, (double)k.tcand, k.a_el, k.a_iz, k.v_iz2, k.mu2, k.vmax2, k.v_thg, k.a_cx, k.gmax, k.hqm_dt};
+    std::memcpy(out, v, sizeof(v));
+  } else {
+    SpeciesK<double> k = to_dev<double>(sl.hk[species]);
+    double v[] = {k.qm_dt, k.dt_L, (double)k.tcand, k.a_el, k.a_iz, k.v_iz2, k.mu2, k.vmax2, k.v_thg, k.a_cx, k.gmax, k.hqm_dt};
+    std::memcpy(out, v, sizeof(v));
+  }
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_philox(int64_t n, const uint32_t* ctr, const uint32_t key[2], uint32_t* out) {
+  pic_ctx c = nullptr;
+  PIC_GUARD_BEGIN
+  if (n < 0 || !ctr || !key || !out) throw Err(PIC_E_ARG, "bad arguments");
+  uint32_t *dc = nullptr, *dout = nullptr;
+  hip_check(hipMalloc(&dc, 16 * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
+  hip_check(hipMalloc(&dout, 16 * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
+  hip_check(hipMemcpy(dc, ctr, 16 * (size_t)n, hipMemcpyHostToDevice), "upload");
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nullptr, dc, key[0], key[1], dout, n);
+  hip_check(hipGetLastError(), "philox");
+  hip_check(hipDeviceSynchronize(), "sync");
+  hip_check(hipMemcpy(out, dout, 16 * (size_t)n, hipMemcpyDeviceToHost), "read");
+  (void)hipFree(dc);
+  (void)hipFree(dout);
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_admit(pic_ctx c, const pic_instance_desc* d, int* slot) {
+  PIC_GUARD_BEGIN
+  if (!c || !d || !slot) throw Err(PIC_E_ARG, "bad arguments");
+  int s = -1;
+  for (size_t i = 0; i < c->slots.size(); ++i)
+    if (!c->slots[i].live) {
+      s = (int)i;
+      break;
+    }
+  if (s < 0) {
+    c->slots.emplace_back();
+    s = (int)c->slots.size() - 1;
+  }
+  try {
+    build_slot(*c, c->slots[s], *d);
+    upload_dev(*c, c->slots[s]);
+    c->sync();
+  } catch (...) {
+    c->slots[s].release_all();
+    c->slots[s].live = false;
+    throw;
+  }
+  *slot = s;
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_retire(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  c->sync();
+  sl.release_all();
+  sl = Slot();
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int64_t pic_slot_bytes(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  return (int64_t)get_slot(c, slot).bytes_held;
+  PIC_GUARD_END(c)
+}
+
+int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s) {
+  PIC_GUARD_BEGIN
+  (void)get_slot(c, slot);
+  (void)a;
+  (void)s;
+  throw Err(PIC_E_STATE, "adapt not available");
+  PIC_GUARD_END(c)
+}
+
+}  // extern "C"

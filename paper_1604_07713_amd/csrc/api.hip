@@ -1,0 +1,568 @@
+// Host side of the C ABI declared in include/pic.h: instance state on the
+// device, derived constants, quadtree construction, and the launch sequences
+// of the ES-PIC step (arXiv:1604.07713, Sec. 3, 3.1, 4.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "k_mesh.hpp"
+#include "pic_internal.hpp"
+#include "api_internal.hpp"
+
+using namespace pic;
+
+namespace pic {
+
+const double kQE = 1.602176634e-19;
+const double kEPS0 = 8.8541878128e-12;
+const double kKB = 1.380649e-23;
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Err(PIC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* Slot::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Err(PIC_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  allocs.push_back(p);
+  alloc_bytes.push_back(bytes);
+  bytes_held += bytes;
+  return p;
+}
+
+void Slot::release(void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < allocs.size(); ++i)
+    if (allocs[i] == p) {
+      (void)hipFree(p);
+      bytes_held -= alloc_bytes[i];
+      allocs.erase(allocs.begin() + i);
+      alloc_bytes.erase(alloc_bytes.begin() + i);
+      return;
+    }
+}
+
+void Slot::release_all() {
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+  alloc_bytes.clear();
+  bytes_held = 0;
+}
+
+// ---------------------------------------------------------------------------
+// derived per-species constants (FP64 on the host, rounded to the precision)
+// ---------------------------------------------------------------------------
+void derive(Slot& sl) {
+  const pic_instance_desc& d = sl.d;
+  for (int s = 0; s < 2; ++s) {
+    HostK& k = sl.hk[s];
+    k = HostK();
+    if (s >= d.nspecies) continue;
+    const pic_species_desc& sp = d.species[s];
+    k.qm_dt = (sp.charge * d.dt) / sp.mass;
+    k.dt_L = d.dt / d.length;
+    k.v_thg = std::sqrt((kKB * d.gas_temperature) / d.gas_mass);
+    k.mcc = sp.mcc;
+    if (sp.mcc == PIC_MCC_ELECTRON) {
+      const double vmax = std::sqrt(((2.0 * kQE) * sp.eps_max) / sp.mass);
+      const double sig_t = sp.sigma_el + sp.sigma_iz;
+      const double nu_max = (d.gas_density * sig_t) * vmax;
+      const double pnull = -std::expm1(-(nu_max * d.dt));
+      k.tcand = (uint32_t)std::floor(std::ldexp(pnull, 24));
+      k.a_el = sp.sigma_el / (sig_t * vmax);
+      k.a_iz = sp.sigma_iz / (sig_t * vmax);
+      k.v_iz2 = ((2.0 * kQE) * sp.eps_iz) / sp.mass;
+      k.vmax2 = vmax * vmax;
+      k.mu2 = (2.0 * sp.mass) / d.gas_mass;
+    } else if (sp.mcc == PIC_MCC_ION_CX) {
+      const double g = std::sqrt(((2.0 * kQE) * sp.eps_max) / sp.mass) + 11.0 * k.v_thg;
+      const double nu_max = (d.gas_density * sp.sigma_cx) * g;
+      const double pnull = -std::expm1(-(nu_max * d.dt));
+      k.tcand = (uint32_t)std::floor(std::ldexp(pnull, 24));
+      k.gmax = g;
+      k.a_cx = 1.0 / g;
+    }
+    const int F = sl.prec == 32 ? 24 : 32;
+    if (d.dim == 1) {
+      const double dx = d.length / d.ncells;
+      sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -(16 + F))) * dx) / kEPS0;
+    } else {
+      sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -16)) / d.depth_z) / kEPS0;
+    }
+  }
+  if (d.dim == 1) sl.inv2dx = 1.0 / (2.0 * (d.length / d.ncells));
+}
+
+template <class T>
+SpeciesK<T> to_dev(const HostK& h) {
+  SpeciesK<T> k;
+  k.qm_dt = (T)h.qm_dt;
+  k.hqm_dt = (T)0.5 * k.qm_dt;
+  k.dt_L = (T)h.dt_L;
+  k.a_el = (T)h.a_el;
+  k.a_iz = (T)h.a_iz;
+  k.v_iz2 = (T)h.v_iz2;
+  k.mu2 = (T)h.mu2;
+  k.vmax2 = (T)h.vmax2;
+  k.v_thg = (T)h.v_thg;
+  k.a_cx = (T)h.a_cx;
+  k.gmax = (T)h.gmax;
+  k.tcand = h.tcand;
+  k.mcc = h.mcc;
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// host linear quadtree for mesh construction
+// ---------------------------------------------------------------------------
+uint32_t morton_host(uint32_t x, uint32_t y) {
+  uint32_t k = 0;
+  for (int b = 0; b < 16; ++b) {
+    k |= ((x >> b) & 1u) << (2 * b);
+    k |= ((y >> b) & 1u) << (2 * b + 1);
+  }
+  return k;
+}
+void unmorton_host(uint32_t k, uint32_t& x, uint32_t& y) {
+  x = y = 0;
+  for (int b = 0; b < 16; ++b) {
+    x |= ((k >> (2 * b)) & 1u) << b;
+    y |= ((k >> (2 * b + 1)) & 1u) << b;
+  }
+}
+
+size_t host_locate(const std::vector<HostLeaf>& L, uint32_t X, uint32_t Y) {
+  const uint32_t m = morton_host(X, Y);
+  size_t lo = 0, hi = L.size() - 1;
+  while (lo < hi) {
+    const size_t mid = (lo + hi + 1) / 2;
+    if (L[mid].key <= m) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+std::vector<HostLeaf> host_refine(const std::vector<HostLeaf>& L, const std::vector<char>& mark) {
+  std::vector<HostLeaf> out;
+  out.reserve(L.size() + 3 * std::count(mark.begin(), mark.end(), 1));
+  for (size_t i = 0; i < L.size(); ++i) {
+    if (!mark[i]) {
+      out.push_back(L[i]);
+      continue;
+    }
+    uint32_t X, Y;
+    unmorton_host(L[i].key, X, Y);
+    const uint32_t half = 1u << (16 - L[i].lv - 1);
+    for (int c = 0; c < 4; ++c)
+      out.push_back(HostLeaf{morton_host(X + (c & 1) * half, Y + (c >> 1) * half), (uint8_t)(L[i].lv + 1)});
+  }
+  return out;
+}
+
+// 2:1 balance over faces and corners: refine a leaf while a leaf touching it
+// is two or more levels finer.  Probes one unit outside each leaf's side
+// midpoints and corners find every coarser leaf that touches it.
+int64_t host_balance(std::vector<HostLeaf>& L) {
+  int64_t nref = 0;
+  for (;;) {
+    std::vector<char> mark(L.size(), 0);
+    bool any = false;
+    for (size_t i = 0; i < L.size(); ++i) {
+      uint32_t X, Y;
+      unmorton_host(L[i].key, X, Y);
+      const uint32_t S = 1u << (16 - L[i].lv);
+      const int64_t px[8] = {(int64_t)X - 1, (int64_t)X + S, (int64_t)X + S / 2, (int64_t)X + S / 2,
+                             (int64_t)X - 1, (int64_t)X + S, (int64_t)X - 1, (int64_t)X + S};
+      const int64_t py[8] = {(int64_t)Y + S / 2, (int64_t)Y + S / 2, (int64_t)Y - 1, (int64_t)Y + S,
+                             (int64_t)Y - 1, (int64_t)Y - 1, (int64_t)Y + S, (int64_t)Y + S};
+      for (int k = 0; k < 8; ++k) {
+        if (px[k] < 0 || py[k] < 0 || px[k] >= 65536 || py[k] >= 65536) continue;
+        const size_t j = host_locate(L, (uint32_t)px[k], (uint32_t)py[k]);
+        if ((int)L[j].lv < (int)L[i].lv - 1) {
+          if (!mark[j]) ++nref;
+          mark[j] = 1;
+          any = true;
+        }
+      }
+    }
+    if (!any) return nref;
+    L = host_refine(L, mark);
+  }
+}
+
+std::vector<HostLeaf> host_build_tree(const pic_instance_desc& d) {
+  std::vector<HostLeaf> L;
+  const int B = d.base_level;
+  const uint32_t n = 1u << B;
+  for (uint32_t iy = 0; iy < n; ++iy)
+    for (uint32_t ix = 0; ix < n; ++ix)
+      L.push_back(HostLeaf{morton_host(ix << (16 - B), iy << (16 - B)), (uint8_t)B});
+  std::sort(L.begin(), L.end(), [](const HostLeaf& a, const HostLeaf& b) { return a.key < b.key; });
+  if (d.refine_disk) {
+    for (;;) {
+      std::vector<char> mark(L.size(), 0);
+      bool any = false;
+      for (size_t i = 0; i < L.size(); ++i) {
+        if (L[i].lv >= d.disk_level || L[i].lv >= d.max_level) continue;
+        uint32_t X, Y;
+        unmorton_host(L[i].key, X, Y);
+        const double h = std::ldexp(1.0, -(int)L[i].lv);
+        const double x0 = X / 65536.0, y0 = Y / 65536.0, x1 = x0 + h, y1 = y0 + h;
+        const double dx = std::max(std::max(x0 - d.disk_cx, 0.0), d.disk_cx - x1);
+        const double dy = std::max(std::max(y0 - d.disk_cy, 0.0), d.disk_cy - y1);
+        if (dx * dx + dy * dy <= d.disk_r * d.disk_r) {
+          mark[i] = 1;
+          any = true;
+        }
+      }
+      if (!any) break;
+      L = host_refine(L, mark);
+    }
+  }
+  host_balance(L);
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// pinned staging arena for small host->device uploads
+// ---------------------------------------------------------------------------
+void* Ctx::stage(const void* src, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes > arena_size) throw Err(PIC_E_ARG, "staging upload too large");
+  if (arena_off + bytes > arena_size) {
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    arena_off = 0;
+  }
+  char* p = (char*)arena + arena_off;
+  arena_off += bytes;
+  std::memcpy(p, src, bytes);
+  return p;
+}
+
+void Ctx::sync() {
+  hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  arena_off = 0;
+}
+
+// ---------------------------------------------------------------------------
+// slot construction
+// ---------------------------------------------------------------------------
+void validate(const pic_instance_desc& d) {
+  if (d.dim != 1 && d.dim != 2) throw Err(PIC_E_ARG, "dim must be 1 or 2");
+  if (d.precision != PIC_FP32 && d.precision != PIC_FP64) throw Err(PIC_E_ARG, "precision must be 32 or 64");
+  if (!(d.length > 0) || !(d.dt > 0)) throw Err(PIC_E_ARG, "length and dt must be positive");
+  if (d.nspecies < 1 || d.nspecies > 2) throw Err(PIC_E_ARG, "nspecies must be 1 or 2");
+  if (d.dim == 1 && (d.ncells < 2 || d.ncells > 8192)) throw Err(PIC_E_ARG, "1D ncells must be in [2, 8192]");
+  if (d.dim == 2 && (d.min_level < 0 || d.max_level > 14 || d.min_level > d.max_level || d.base_level < d.min_level ||
+                     d.base_level > d.max_level))
+    throw Err(PIC_E_ARG, "2D levels must satisfy 0 <= min <= base <= max <= 14");
+  for (int s = 0; s < d.nspecies; ++s) {
+    const pic_species_desc& sp = d.species[s];
+    if (!(sp.mass > 0)) throw Err(PIC_E_ARG, "species mass must be positive");
+    if (sp.mcc == PIC_MCC_ELECTRON && d.nspecies < 2) throw Err(PIC_E_ARG, "ionization needs an ion species");
+    if (sp.mcc != PIC_MCC_NONE && !(d.gas_mass > 0 && d.gas_temperature > 0))
+      throw Err(PIC_E_ARG, "collisions need gas mass and temperature");
+    if (sp.mcc == PIC_MCC_ELECTRON && s != 0) throw Err(PIC_E_ARG, "electron collisions apply to species 0");
+  }
+}
+
+void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
+  (void)C;
+  sl.nleaves = (uint32_t)L.size();
+  std::vector<uint32_t> keys(L.size());
+  std::vector<uint8_t> lv(L.size());
+  for (size_t i = 0; i < L.size(); ++i) {
+    keys[i] = L[i].key;
+    lv[i] = L[i].lv;
+  }
+  sl.host_leaves = L;
+  sl.release(sl.key);
+  sl.release(sl.lv);
+  sl.release(sl.xy);
+  sl.release(sl.lut);
+  sl.key = (uint32_t*)sl.alloc(4 * L.size());
+  sl.lv = (uint8_t*)sl.alloc(L.size());
+  sl.xy = (uint32_t*)sl.alloc(4 * L.size());
+  sl.lut_level = std::min(sl.d.max_level, 9);
+  sl.lut = (uint32_t*)sl.alloc(4 * ((size_t(1) << (2 * sl.lut_level)) + 1));
+  hip_check(hipMemcpy(sl.key, keys.data(), 4 * L.size(), hipMemcpyHostToDevice), "upload keys");
+  hip_check(hipMemcpy(sl.lv, lv.data(), L.size(), hipMemcpyHostToDevice), "upload levels");
+  hip_check(launch_leaf_xy(sl.key, sl.lv, sl.nleaves, sl.xy, C.stream), "leaf_xy");
+  hip_check(launch_build_lut(sl.key, sl.lv, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut");
+  // per-leaf field and deposit arrays
+  for (void* p : {(void*)sl.E, (void*)sl.e64, (void*)sl.cphi, (void*)sl.grad, (void*)sl.phi64, (void*)sl.Q,
+                  (void*)sl.off, (void*)sl.st.nbr, (void*)sl.st.coef, (void*)sl.st.diag, (void*)sl.st.bnd,
+                  (void*)sl.cg_ws})
+    sl.release(p);
+  sl.st = Stencil2D{nullptr, nullptr, nullptr, nullptr};
+  sl.cg_ws = nullptr;
+  sl.stencil_ok = false;
+  sl.nq = sl.nleaves;
+  sl.E = sl.alloc(sl.esz * 8 * sl.nleaves);
+  sl.e64 = (double*)sl.alloc(8 * 8 * (size_t)sl.nleaves);
+  sl.cphi = (double*)sl.alloc(8 * 4 * (size_t)sl.nleaves);
+  sl.grad = (double*)sl.alloc(8 * 8 * (size_t)sl.nleaves);
+  sl.phi64 = (double*)sl.alloc(8 * (size_t)sl.nleaves);
+  sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
+  sl.off = (uint32_t*)sl.alloc(4 * ((size_t)sl.nq + 1));
+  hip_check(hipMemsetAsync(sl.E, 0, sl.esz * 8 * sl.nleaves, C.stream), "memset");
+  hip_check(hipMemsetAsync(sl.e64, 0, 64 * (size_t)sl.nleaves, C.stream), "memset");
+  hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (size_t)sl.nleaves, C.stream), "memset");
+  hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+}
+
+void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
+  validate(d);
+  sl = Slot();
+  sl.live = true;
+  sl.d = d;
+  sl.prec = d.precision;
+  sl.esz = d.precision == 32 ? 4 : 8;
+  derive(sl);
+  sl.ctr = (Counters*)sl.alloc(sizeof(Counters));
+  hip_check(hipMemsetAsync(sl.ctr, 0, sizeof(Counters), C.stream), "memset");
+  sl.part = (unsigned long long*)sl.alloc(sizeof(unsigned long long) * kNStat * kMaxGrid);
+  hip_check(hipMemsetAsync(sl.part, 0, sizeof(unsigned long long) * kNStat * kMaxGrid, C.stream), "memset");
+  sl.devI = sl.alloc(sizeof(InstDev<double>));
+  if (d.dim == 1) {
+    const int N = d.ncells;
+    sl.nq = N + 1;
+    std::vector<double> im(N + 1, 0.0);
+    double m = 2.0;
+    for (int i = 1; i < N; ++i) {
+      if (i > 1) m = 2.0 - im[i - 1];
+      im[i] = 1.0 / m;
+    }
+    sl.inv_m = (double*)sl.alloc(8 * (N + 1));
+    hip_check(hipMemcpy(sl.inv_m, im.data(), 8 * (N + 1), hipMemcpyHostToDevice), "upload pivots");
+    sl.E = sl.alloc(sl.esz * (N + 1));
+    sl.e64 = (double*)sl.alloc(8 * (N + 1));
+    sl.phi64 = (double*)sl.alloc(8 * (N + 1));
+    sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
+    sl.off = (uint32_t*)sl.alloc(4 * ((size_t)N + 1));
+    hip_check(hipMemsetAsync(sl.E, 0, sl.esz * (N + 1), C.stream), "memset");
+    hip_check(hipMemsetAsync(sl.e64, 0, 8 * (N + 1), C.stream), "memset");
+    hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (N + 1), C.stream), "memset");
+    hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+  } else {
+    set_mesh2d(C, sl, host_build_tree(d));
+  }
+  sl.ionizing = d.nspecies == 2 && d.species[0].mcc == PIC_MCC_ELECTRON;
+}
+
+// ---------------------------------------------------------------------------
+// particle buffers
+// ---------------------------------------------------------------------------
+void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
+  PBuf& b = sl.pb[sp][which];
+  if (b.base) sl.release(b.base);
+  const size_t e = sl.esz;
+  const size_t c = (size_t)cap;
+  const size_t bytes = (2 * e + 3 * e + 12) * c + 8 * 256;
+  char* p = (char*)sl.alloc(bytes);
+  b.base = p;
+  size_t o = 0;
+  auto carve = [&](size_t n) {
+    void* q = p + o;
+    o += (n + 255) & ~(size_t)255;
+    return q;
+  };
+  b.s[0] = carve(e * c);
+  b.s[1] = sl.d.dim == 2 ? carve(e * c) : nullptr;
+  for (int k = 0; k < 3; ++k) b.v[k] = carve(e * c);
+  b.w = (uint32_t*)carve(4 * c);
+  b.id = (uint32_t*)carve(4 * c);
+  b.cell = sl.d.dim == 2 ? (uint32_t*)carve(4 * c) : nullptr;
+}
+
+void alloc_births(Slot& sl, int64_t cap) {
+  if (sl.birth_base) sl.release(sl.birth_base);
+  sl.birth_base = nullptr;
+  sl.birth_cap = 0;
+  if (!sl.ionizing) return;
+  const size_t e = sl.esz, c = (size_t)cap;
+  char* p = (char*)sl.alloc((12 + 8 * e) * c + 16 * 256);
+  sl.birth_base = p;
+  size_t o = 0;
+  auto carve = [&](size_t n) {
+    void* q = p + o;
+    o += (n + 255) & ~(size_t)255;
+    return q;
+  };
+  sl.br_parent = (uint32_t*)carve(4 * c);
+  sl.br_cell = (uint32_t*)carve(4 * c);
+  sl.br_w = (uint32_t*)carve(4 * c);
+  for (int k = 0; k < 2; ++k) sl.br_s[k] = carve(e * c);
+  for (int k = 0; k < 3; ++k) sl.br_ve[k] = carve(e * c);
+  for (int k = 0; k < 3; ++k) sl.br_vi[k] = carve(e * c);
+  sl.birth_cap = (uint32_t)cap;
+}
+
+template <class T>
+InstDev<T> make_dev(const Slot& sl) {
+  InstDev<T> I;
+  std::memset(&I, 0, sizeof(I));
+  const pic_instance_desc& d = sl.d;
+  I.dim = d.dim;
+  I.N = d.dim == 1 ? d.ncells : 0;
+  I.particle_bc = d.particle_bc;
+  I.nspecies = d.nspecies;
+  I.key0 = (uint32_t)d.seed;
+  I.key1 = (uint32_t)(d.seed >> 32) ^ d.instance_key;
+  for (int s = 0; s < 2; ++s) {
+    I.sk[s] = to_dev<T>(sl.hk[s]);
+    const PBuf& b = sl.pb[s][sl.cur[s]];
+    I.s[s][0] = (T*)b.s[0];
+    I.s[s][1] = (T*)b.s[1];
+    for (int k = 0; k < 3; ++k) I.v[s][k] = (T*)b.v[k];
+    I.w[s] = b.w;
+    I.id[s] = b.id;
+    I.cell[s] = b.cell;
+    I.cap[s] = (uint32_t)sl.cap[s];
+  }
+  I.E = (const T*)sl.E;
+  I.leaf_key = sl.key;
+  I.leaf_xy = sl.xy;
+  I.leaf_lv = sl.lv;
+  I.lut = sl.lut;
+  I.lut_level = sl.lut_level;
+  I.nleaves = sl.nleaves;
+  I.Q = sl.Q;
+  I.nq = sl.nq;
+  I.br.parent = sl.br_parent;
+  I.br.cell = sl.br_cell;
+  I.br.w = sl.br_w;
+  for (int k = 0; k < 2; ++k) I.br.s[k] = (T*)sl.br_s[k];
+  for (int k = 0; k < 3; ++k) {
+    I.br.ve[k] = (T*)sl.br_ve[k];
+    I.br.vi[k] = (T*)sl.br_vi[k];
+  }
+  I.birth_cap = sl.birth_cap;
+  I.ctr = sl.ctr;
+  I.v_table = sl.v_table;
+  I.v_len = sl.v_len;
+  I.part = sl.part;
+  I.nparts = (uint32_t)grid_for(sl.cap[0] + sl.cap[1]);
+  I.inv_m = sl.inv_m;
+  I.kappa[0] = sl.kappa[0];
+  I.kappa[1] = sl.kappa[1];
+  I.inv2dx = sl.inv2dx;
+  I.phi64 = sl.phi64;
+  I.e64 = sl.e64;
+  return I;
+}
+
+// upload the kernel-side view of a slot (device copy used by table-driven kernels)
+void upload_dev(Ctx& C, Slot& sl) {
+  if (sl.prec == 32) {
+    InstDev<float> I = make_dev<float>(sl);
+    hip_check(hipMemcpyAsync(sl.devI, C.stage(&I, sizeof(I)), sizeof(I), hipMemcpyHostToDevice, C.stream), "upload");
+  } else {
+    InstDev<double> I = make_dev<double>(sl);
+    hip_check(hipMemcpyAsync(sl.devI, C.stage(&I, sizeof(I)), sizeof(I), hipMemcpyHostToDevice, C.stream), "upload");
+  }
+}
+
+Counters read_counters(Ctx& C, Slot& sl) {
+  Counters c;
+  hip_check(hipMemcpyAsync(&c, sl.ctr, sizeof(c), hipMemcpyDeviceToHost, C.stream), "read counters");
+  C.sync();
+  return c;
+}
+
+void write_counters(Ctx& C, Slot& sl, const Counters& c) {
+  hip_check(hipMemcpyAsync(sl.ctr, C.stage(&c, sizeof(c)), sizeof(c), hipMemcpyHostToDevice, C.stream),
+            "write counters");
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > kMaxGrid) g = kMaxGrid;
+  return (int)g;
+}
+
+// grow particle capacity of a species (keeps contents; count from counters)
+void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count) {
+  const int cur = sl.cur[sp];
+  PBuf old = sl.pb[sp][cur];
+  const int64_t oldcap = sl.cap[sp];
+  sl.pb[sp][cur] = PBuf();
+  alloc_particles(sl, sp, newcap, cur);
+  PBuf& nb = sl.pb[sp][cur];
+  const size_t e = sl.esz;
+  if (count) {
+    hip_check(hipMemcpyAsync(nb.s[0], old.s[0], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+    if (sl.d.dim == 2) {
+      hip_check(hipMemcpyAsync(nb.s[1], old.s[1], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+      hip_check(hipMemcpyAsync(nb.cell, old.cell, 4 * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+    }
+    for (int k = 0; k < 3; ++k)
+      hip_check(hipMemcpyAsync(nb.v[k], old.v[k], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+    hip_check(hipMemcpyAsync(nb.w, old.w, 4 * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+    hip_check(hipMemcpyAsync(nb.id, old.id, 4 * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+  }
+  C.sync();
+  sl.release(old.base);
+  (void)oldcap;
+  // the sort buffer follows the new capacity
+  const int other = 1 - cur;
+  if (sl.pb[sp][other].base) sl.release(sl.pb[sp][other].base);
+  sl.pb[sp][other] = PBuf();
+  alloc_particles(sl, sp, newcap, other);
+  sl.cap[sp] = newcap;
+}
+
+void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
+  bool changed = false;
+  for (int sp = 0; sp < sl.d.nspecies; ++sp) {
+    int64_t need = c.count[sp];
+    if (sl.ionizing) need += (int64_t)c.count[0] * std::max<int64_t>(1, std::min<int64_t>(steps_ahead, 4)) / 4 + 1024;
+    if (need > sl.cap[sp]) {
+      grow(C, sl, sp, (need * 3) / 2 + 1024, c.count[sp]);
+      changed = true;
+    }
+  }
+  if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) {
+    alloc_births(sl, sl.cap[0]);
+    changed = true;
+  }
+  if (changed) upload_dev(C, sl);
+}
+
+template <class T>
+void sort_species(Ctx& C, Slot& sl, int sp) {
+  InstDev<T> I = make_dev<T>(sl);
+  const int other = 1 - sl.cur[sp];
+  PBuf& d = sl.pb[sp][other];
+  SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
+  const uint32_t ncell = sl.d.dim == 1 ? (uint32_t)sl.d.ncells : sl.nleaves;
+  hip_check(launch_sort<T>(I, sp, ncell, sl.off, dst, grid_for(sl.cap[sp]), C.stream), "sort");
+  sl.cur[sp] = other;
+}
+
+void sort_slot(Ctx& C, Slot& sl) {
+  for (int sp = 0; sp < sl.d.nspecies; ++sp) {
+    if (!sl.pb[sp][0].base) continue;
+    if (sl.prec == 32) sort_species<float>(C, sl, sp); else sort_species<double>(C, sl, sp);
+  }
+  upload_dev(C, sl);
+}
+
+}  // namespace pic
+
+namespace pic {
+template InstDev<float> make_dev<float>(const Slot&);
+template InstDev<double> make_dev<double>(const Slot&);
+template SpeciesK<float> to_dev<float>(const HostK&);
+template SpeciesK<double> to_dev<double>(const HostK&);
+}  // namespace pic

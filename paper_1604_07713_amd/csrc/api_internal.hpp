@@ -1,0 +1,133 @@
+// Host-side state of the library (slots, context) shared by api.hip and abi.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pic_internal.hpp"
+
+namespace pic {
+
+constexpr int kMaxGrid = 4096;   // upper bound on the plain particle-kernel grid
+
+struct Err {
+  int code;
+  std::string msg;
+  Err(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+void hip_check(hipError_t e, const char* what);
+
+struct HostK {
+  double qm_dt = 0, dt_L = 0, a_el = 0, a_iz = 0, v_iz2 = 0, mu2 = 0, vmax2 = 0, v_thg = 0, a_cx = 0, gmax = 0;
+  uint32_t tcand = 0;
+  int mcc = 0;
+};
+
+struct HostLeaf {
+  uint32_t key;
+  uint8_t lv;
+};
+
+struct PBuf {
+  void* base = nullptr;
+  void* s[2] = {nullptr, nullptr};
+  void* v[3] = {nullptr, nullptr, nullptr};
+  uint32_t* w = nullptr;
+  uint32_t* id = nullptr;
+  uint32_t* cell = nullptr;
+};
+
+struct Slot {
+  bool live = false;
+  pic_instance_desc d{};
+  int prec = 64;
+  size_t esz = 8;
+  bool ionizing = false;
+  HostK hk[2];
+  double kappa[2] = {0, 0};
+  double inv2dx = 0;
+  // particles: [species][buffer]; cur = live buffer, the other is the sort target
+  PBuf pb[2][2];
+  int cur[2] = {0, 0};
+  int64_t cap[2] = {0, 0};
+  // births staging
+  void* birth_base = nullptr;
+  uint32_t *br_parent = nullptr, *br_cell = nullptr, *br_w = nullptr;
+  void* br_s[2] = {nullptr, nullptr};
+  void* br_ve[3] = {nullptr, nullptr, nullptr};
+  void* br_vi[3] = {nullptr, nullptr, nullptr};
+  uint32_t birth_cap = 0;
+  // field tables
+  void* E = nullptr;
+  double *e64 = nullptr, *phi64 = nullptr, *inv_m = nullptr, *cphi = nullptr, *grad = nullptr;
+  // 2D mesh
+  uint32_t *key = nullptr, *xy = nullptr, *lut = nullptr;
+  uint8_t* lv = nullptr;
+  int lut_level = 0;
+  uint32_t nleaves = 0;
+  std::vector<HostLeaf> host_leaves;
+  Stencil2D st{nullptr, nullptr, nullptr, nullptr};
+  double* cg_ws = nullptr;
+  bool stencil_ok = false;
+  // deposit, counters, stats rows, order scratch
+  unsigned long long* Q = nullptr;
+  uint32_t nq = 0;
+  Counters* ctr = nullptr;
+  unsigned long long* part = nullptr;
+  uint32_t* off = nullptr;
+  double* v_table = nullptr;
+  uint32_t v_len = 0, v_cap = 0;
+  void* devI = nullptr;    // device copy of InstDev<T>
+  uint32_t max_id_loaded[2] = {0, 0};
+  bool error_state = false;
+  // allocations
+  std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;
+  size_t bytes_held = 0;
+  void* alloc(size_t bytes);
+  void release(void* p);
+  void release_all();
+};
+
+struct Ctx {
+  std::vector<Slot> slots;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* arena = nullptr;
+  size_t arena_size = 0, arena_off = 0;
+  std::vector<hipEvent_t> ev;
+  // batched launch resources
+  void* b_insts = nullptr;
+  size_t b_insts_bytes = 0;
+  void* b_items = nullptr;
+  size_t b_items_bytes = 0;
+  unsigned long long* b_part = nullptr;
+  size_t b_part_bytes = 0;
+  uint32_t* b_rowbeg = nullptr;
+  size_t b_rowbeg_bytes = 0;
+  void* stage(const void* src, size_t bytes);
+  void sync();
+};
+
+void derive(Slot& sl);
+void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d);
+void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L);
+void alloc_particles(Slot& sl, int sp, int64_t cap, int which);
+void alloc_births(Slot& sl, int64_t cap);
+template <class T> InstDev<T> make_dev(const Slot& sl);
+void upload_dev(Ctx& C, Slot& sl);
+Counters read_counters(Ctx& C, Slot& sl);
+void write_counters(Ctx& C, Slot& sl, const Counters& c);
+int grid_for(int64_t n);
+void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead);
+void sort_slot(Ctx& C, Slot& sl);
+void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count);
+uint32_t morton_host(uint32_t x, uint32_t y);
+void unmorton_host(uint32_t k, uint32_t& x, uint32_t& y);
+size_t host_locate(const std::vector<HostLeaf>& L, uint32_t X, uint32_t Y);
+std::vector<HostLeaf> host_build_tree(const pic_instance_desc& d);
+template <class T> SpeciesK<T> to_dev(const HostK& h);
+
+}  // namespace pic

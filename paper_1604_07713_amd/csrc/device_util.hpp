@@ -1,0 +1,194 @@
+// Device helpers for the ES-PIC kernels (gfx950, wave64).
+//
+//  - Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,
+//    "Parallel random numbers: as easy as 1, 2, 3", SC'11), keyed so that a
+//    particle's draws depend only on (seed, instance, particle id, step);
+//  - uniform deviates on odd multiples of 2^-24 (exact in FP32 and FP64);
+//  - isotropic directions by Marsaglia's (1972) disk rejection;
+//  - normal deviates as the Irwin-Hall sum of twelve uniforms minus six;
+//  - wave-level segmented reductions that turn a wave's run of equal cell
+//    indices into one global atomic (deposits and counting-sort cursors).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * x0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
+    const uint32_t lo1 = 0xCD9E8D57u * x2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
+    const uint32_t y0 = hi1 ^ x1 ^ k0;
+    const uint32_t y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+}
+
+// Word stream of one particle in one step: blocks with counter (id, step, b, 0).
+struct WordStream {
+  uint32_t k0, k1, id, step, block;
+  uint32_t w0, w1, w2, w3;
+  int left;
+  __device__ __forceinline__ WordStream(uint32_t key0, uint32_t key1, uint32_t pid, uint32_t n)
+      : k0(key0), k1(key1), id(pid), step(n), block(0) {
+    gen();
+  }
+  __device__ __forceinline__ void gen() {
+    w0 = id;
+    w1 = step;
+    w2 = block;
+    w3 = 0u;
+    philox4x32_10(w0, w1, w2, w3, k0, k1);
+    left = 4;
+  }
+  __device__ __forceinline__ uint32_t next() {
+    if (left == 0) {
+      ++block;
+      gen();
+    }
+    const uint32_t r = w0;
+    w0 = w1;
+    w1 = w2;
+    w2 = w3;
+    --left;
+    return r;
+  }
+};
+
+template <class T>
+__device__ __forceinline__ T unit_uniform(uint32_t r) {
+  return (T)(2u * (r >> 9) + 1u) * (T)5.9604644775390625e-08;
+}
+
+template <class T>
+__device__ __forceinline__ void isotropic(WordStream& ws, T& dx, T& dy, T& dz) {
+  for (int k = 0; k < 32; ++k) {
+    const T a = (T)2 * unit_uniform<T>(ws.next()) - (T)1;
+    const T b = (T)2 * unit_uniform<T>(ws.next()) - (T)1;
+    const T s = a * a + b * b;
+    if (s < (T)1) {
+      const T t = (T)2 * sqrt((T)1 - s);
+      dx = a * t;
+      dy = b * t;
+      dz = (T)1 - (T)2 * s;
+      return;
+    }
+  }
+  dx = (T)0;
+  dy = (T)0;
+  dz = (T)1;
+}
+
+template <class T>
+__device__ __forceinline__ T normal12(WordStream& ws) {
+  int32_t S = 0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) S += (int32_t)(2u * (ws.next() >> 9) + 1u);
+  return (T)(S - 100663296) * (T)5.9604644775390625e-08;
+}
+
+// ---- wave64 helpers -------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanes_le(int lane) {
+  return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+}
+
+// Lane index of the first lane of this lane's run of equal keys.
+__device__ __forceinline__ int run_start(uint32_t key, int lane) {
+  const uint32_t kprev = __shfl_up(key, 1u);
+  const bool head = (lane == 0) || (kprev != key);
+  const uint64_t heads = __ballot(head);
+  return 63 - __clzll(heads & lanes_le(lane));
+}
+
+__device__ __forceinline__ bool run_tail(uint32_t key, int lane) {
+  const uint32_t knext = __shfl_down(key, 1u);
+  return (lane == 63) || (knext != key);
+}
+
+// Every lane of the wave must call this (no divergence).  Adds val to dst[key]
+// with one atomic per run of equal consecutive keys; kNoKey lanes add nothing.
+__device__ __forceinline__ void seg_atomic_add(unsigned long long* dst, uint32_t key, unsigned long long val) {
+  const int lane = lane_id();
+  const int start = run_start(key, lane);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long o = __shfl_up(val, (unsigned)off);
+    if (lane - off >= start) val += o;
+  }
+  if (run_tail(key, lane) && key != kNoKey && val != 0ull) atomicAdd(dst + key, val);
+}
+
+// Same for 32-bit counters; returns for each lane its rank in its run and
+// the run's base fetched from the atomic (cursor allocation).
+__device__ __forceinline__ uint32_t seg_atomic_claim(uint32_t* cursor, uint32_t key) {
+  const int lane = lane_id();
+  const int start = run_start(key, lane);
+  const uint32_t rank = (uint32_t)(lane - start);
+  const bool tail = run_tail(key, lane);
+  uint32_t base = 0;
+  if (tail && key != kNoKey) base = atomicAdd(cursor + key, rank + 1u);
+  // broadcast the base from the tail lane of the run to the whole run
+  const uint64_t tails = __ballot(tail);
+  const uint64_t above = tails & ~(lanes_le(lane) >> 1);   // tail lanes >= lane
+  const int tl = __ffsll((long long)above) - 1;
+  base = __shfl(base, tl);
+  return base + rank;
+}
+
+template <class V>
+__device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Morton interleave of two 16-bit coordinates (x in even bits).
+__device__ __forceinline__ uint32_t spread16(uint32_t v) {
+  v &= 0xFFFFu;
+  v = (v | (v << 8)) & 0x00FF00FFu;
+  v = (v | (v << 4)) & 0x0F0F0F0Fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+__device__ __forceinline__ uint32_t morton2(uint32_t x, uint32_t y) { return spread16(x) | (spread16(y) << 1); }
+
+
+// Leaf of a Morton-ordered quadtree containing the point (X, Y) given in
+// 16-bit units.  lut[c] is the leaf holding the low corner of level-lut_level
+// cell c (lut has 4^lut_level + 1 entries, the last = nleaves); when that
+// leaf is finer than lut_level, the cell's leaves are lut[c] .. lut[c+1]-1
+// and a binary search over their keys finds the last key <= Morton(X, Y).
+__device__ __forceinline__ uint32_t locate_leaf(const uint32_t* __restrict__ key, const uint8_t* __restrict__ lv,
+                                                const uint32_t* __restrict__ lut, int lut_level, uint32_t X,
+                                                uint32_t Y) {
+  const int sh = 16 - lut_level;
+  const uint32_t c = morton2(X >> sh, Y >> sh);
+  uint32_t lo = lut[c];
+  if ((int)lv[lo] <= lut_level) return lo;
+  uint32_t hi = lut[c + 1] - 1u;
+  const uint32_t m = morton2(X, Y);
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (key[mid] <= m) lo = mid; else hi = mid - 1u;
+  }
+  return lo;
+}
+
+}  // namespace pic

@@ -1,0 +1,524 @@
+// Field kernels (FP64): the Poisson solves of the ES-PIC step and the tables
+// the particle gather reads (arXiv:1604.07713, Sec. 3: potential at cell
+// centres, E at cell nodes/corners, bilinear gather).
+//
+//  1D: one workgroup per instance.  The right-hand side is built in parallel
+//      from the integer charge sums; the Thomas sweeps (tridiag(-1,2,-1) with
+//      the pivots inverted once per mesh) run in one lane over LDS; node E by
+//      centred differences inside, second-order one-sided at the walls.
+//  2D: cell-centred finite volumes on the leaves with two-point fluxes,
+//      solved by Jacobi-preconditioned CG; node potentials are the mean of
+//      the cell potentials of the leaves having the node as a corner
+//      (Dirichlet wall value on the walls), and nodal E the mean of those
+//      leaves' corner gradients.
+#include "device_util.hpp"
+#include "pic_internal.hpp"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// 1D
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict__ insts, int mode,
+                                                    const double* __restrict__ phi_left,
+                                                    const unsigned long long* __restrict__ rows,
+                                                    const uint32_t* __restrict__ row_begin) {
+  extern __shared__ double lds[];
+  const InstDev<T>& I = insts[blockIdx.x];
+  const int N = I.N;
+  double* b = lds;              // [N+1] right-hand side, then forward-sweep values, then phi
+  double* im = lds + (N + 1);   // [N+1] pivots
+  const uint32_t step = I.ctr->step;
+  const uint32_t par = mode == 1 ? (step & 1u) : ((step + 1u) & 1u);
+  const unsigned long long* Q = I.Q + (size_t)par * 2u * I.nq;
+  for (int i = threadIdx.x; i <= N; i += blockDim.x) {
+    double v = 0.0;
+    for (int sp = 0; sp < I.nspecies; ++sp) v = v + (double)(long long)Q[(size_t)sp * I.nq + i] * I.kappa[sp];
+    b[i] = v;
+    im[i] = I.inv_m[i];
+  }
+  double left;
+  if (mode == 1) {
+    const uint32_t k = step + 1u - I.ctr->vstep0;
+    left = (I.v_table && k < I.v_len) ? I.v_table[k] : 0.0;
+  } else {
+    left = phi_left ? phi_left[blockIdx.x] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // forward sweep: d'_i = (b_i + d'_{i-1}) / m_i with phi_0 folded into b_1
+    double prev = 0.0;
+    int i = 1;
+    for (; i + 3 < N; i += 4) {
+      const double b0 = b[i], b1 = b[i + 1], b2 = b[i + 2], b3 = b[i + 3];
+      const double m0 = im[i], m1 = im[i + 1], m2 = im[i + 2], m3 = im[i + 3];
+      const double c0 = (i == 1) ? b0 + left : b0;
+      const double d0 = (c0 + prev) * m0;
+      const double d1 = (b1 + d0) * m1;
+      const double d2 = (b2 + d1) * m2;
+      const double d3 = (b3 + d2) * m3;
+      b[i] = d0;
+      b[i + 1] = d1;
+      b[i + 2] = d2;
+      b[i + 3] = d3;
+      prev = d3;
+    }
+    for (; i < N; ++i) {
+      double c = (i == 1) ? b[i] + left : b[i];
+      if (i == N - 1) c = c + 0.0;   // phi_N = 0 folded into b_{N-1}
+      const double d = (c + prev) * im[i];
+      b[i] = d;
+      prev = d;
+    }
+    // back substitution: phi_{N-1} = d'_{N-1}, phi_i = d'_i + phi_{i+1} / m_i
+    double nxt = b[N - 1];
+    int j = N - 2;
+    for (; j - 3 >= 1; j -= 4) {
+      const double a0 = b[j], a1 = b[j - 1], a2 = b[j - 2], a3 = b[j - 3];
+      const double m0 = im[j], m1 = im[j - 1], m2 = im[j - 2], m3 = im[j - 3];
+      const double p0 = a0 + m0 * nxt;
+      const double p1 = a1 + m1 * p0;
+      const double p2 = a2 + m2 * p1;
+      const double p3 = a3 + m3 * p2;
+      b[j] = p0;
+      b[j - 1] = p1;
+      b[j - 2] = p2;
+      b[j - 3] = p3;
+      nxt = p3;
+    }
+    for (; j >= 1; --j) {
+      const double p = b[j] + im[j] * nxt;
+      b[j] = p;
+      nxt = p;
+    }
+    b[0] = left;
+    b[N] = 0.0;
+  }
+  __syncthreads();
+  T* E = const_cast<T*>(I.E);
+  const double h2 = I.inv2dx;
+  for (int i = threadIdx.x; i <= N; i += blockDim.x) {
+    double e;
+    if (i == 0) e = ((3.0 * b[0] - 4.0 * b[1]) + b[2]) * h2;
+    else if (i == N) e = ((-3.0 * b[N] + 4.0 * b[N - 1]) - b[N - 2]) * h2;
+    else e = (b[i - 1] - b[i + 1]) * h2;
+    E[i] = (T)e;
+    if (I.e64) I.e64[i] = e;
+    if (I.phi64) I.phi64[i] = b[i];
+  }
+  if (mode == 1) {
+    __syncthreads();
+    // commit the step: partial-stats rows of this instance, births, step index
+    __shared__ unsigned long long acc[kNStat];
+    if (threadIdx.x < kNStat) acc[threadIdx.x] = 0ull;
+    __syncthreads();
+    const uint32_t rb = row_begin ? row_begin[blockIdx.x] : 0u;
+    const uint32_t re = row_begin ? row_begin[blockIdx.x + 1] : I.nparts;
+    for (uint32_t r = rb + threadIdx.x / kNStat; r < re; r += kBlock / kNStat)
+      if (threadIdx.x < (kBlock / kNStat) * kNStat)
+        atomicAdd(&acc[threadIdx.x % kNStat], rows[(size_t)r * kNStat + threadIdx.x % kNStat]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Counters* c = I.ctr;
+      for (int q = 0; q < kNStat; ++q) c->stats[q] += acc[q];
+      const uint32_t nb = c->nbirths;
+      if (nb && !(c->flags & (kFlagBirthOverflow | kFlagIdOverflow))) {
+        c->count[0] += nb;
+        c->count[1] += nb;
+        c->next_id += 2u * nb;
+        c->stats[kStBirths] += nb;
+      }
+      c->nbirths = 0u;
+      c->step = step + 1u;
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mode, const double* phi_left,
+                          const unsigned long long* rows, const uint32_t* row_begin, hipStream_t s) {
+  const size_t lds = (size_t)2 * (max_n + 1) * sizeof(double);
+  hipLaunchKernelGGL(k_field1d<T>, dim3(ninst), dim3(kBlock), lds, s, insts, mode, phi_left, rows, row_begin);
+  return hipGetLastError();
+}
+
+// node E (or node potential -> E) given by the caller, rounded to T
+template <class T>
+__global__ void k_node_e_1d(T* E, double* e64, const double* data, int is_phi, int N, double inv2dx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > N) return;
+  double e;
+  if (!is_phi) {
+    e = data[i];
+  } else if (i == 0) {
+    e = ((3.0 * data[0] - 4.0 * data[1]) + data[2]) * inv2dx;
+  } else if (i == N) {
+    e = ((-3.0 * data[N] + 4.0 * data[N - 1]) - data[N - 2]) * inv2dx;
+  } else {
+    e = (data[i - 1] - data[i + 1]) * inv2dx;
+  }
+  E[i] = (T)e;
+  if (e64) e64[i] = e;
+}
+
+template <class T>
+hipError_t launch_node_e_1d(const InstDev<T>& I, const double* data, int is_phi, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_e_1d<T>, dim3(ceil_div(I.N + 1, kBlock)), dim3(kBlock), 0, s, const_cast<T*>(I.E),
+                     I.e64, data, is_phi, I.N, I.inv2dx);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 2D: nodes, corner gradients, nodal E
+// ---------------------------------------------------------------------------
+struct LeafBox {
+  uint32_t x0, y0, size;
+};
+__device__ __forceinline__ LeafBox leaf_box(const Mesh2D& m, uint32_t l) {
+  const uint32_t xy = m.xy[l];
+  return LeafBox{xy >> 16, xy & 0xFFFFu, 1u << (16 - m.lv[l])};
+}
+
+// Leaves having node (X, Y) as a corner, in quadrant order SW, SE, NW, NE;
+// returns their count and, per entry, the leaf and the corner index of the
+// node in that leaf (0 = low-low, 1 = high x, 2 = high y, 3 = high-high).
+__device__ __forceinline__ int node_leaves(const Mesh2D& m, uint32_t X, uint32_t Y, uint32_t* leaf, int* corner) {
+  int k = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int qx = q & 1, qy = q >> 1;        // 0: the quadrant below/left of the node
+    if ((qx == 0 && X == 0u) || (qx == 1 && X >= 65536u)) continue;
+    if ((qy == 0 && Y == 0u) || (qy == 1 && Y >= 65536u)) continue;
+    const uint32_t px = qx ? X : X - 1u, py = qy ? Y : Y - 1u;
+    const uint32_t l = locate_leaf(m.key, m.lv, m.lut, m.lut_level, px, py);
+    const LeafBox b = leaf_box(m, l);
+    if ((X & (b.size - 1u)) != 0u || (Y & (b.size - 1u)) != 0u) continue;   // node on an edge, not a corner
+    leaf[k] = l;
+    corner[k] = (qx ? 0 : 1) + (qy ? 0 : 2);
+    ++k;
+  }
+  return k;
+}
+
+__device__ __forceinline__ bool dirichlet_node(const Mesh2D& m, uint32_t X, uint32_t Y, double& v) {
+  if (X == 0u && m.field_bc[0] == PIC_WALL_DIRICHLET) { v = m.wall_phi[0]; return true; }
+  if (X == 65536u && m.field_bc[1] == PIC_WALL_DIRICHLET) { v = m.wall_phi[1]; return true; }
+  if (Y == 0u && m.field_bc[2] == PIC_WALL_DIRICHLET) { v = m.wall_phi[2]; return true; }
+  if (Y == 65536u && m.field_bc[3] == PIC_WALL_DIRICHLET) { v = m.wall_phi[3]; return true; }
+  return false;
+}
+
+__global__ void k_cell_to_corner_phi(Mesh2D m, const double* __restrict__ cell_phi, double* __restrict__ corner_phi) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4u * m.nleaves) return;
+  const uint32_t l = t >> 2;
+  const int c = (int)(t & 3u);
+  const LeafBox b = leaf_box(m, l);
+  const uint32_t X = b.x0 + ((c & 1) ? b.size : 0u), Y = b.y0 + ((c >> 1) ? b.size : 0u);
+  double v;
+  if (!dirichlet_node(m, X, Y, v)) {
+    uint32_t lf[4];
+    int cr[4];
+    const int k = node_leaves(m, X, Y, lf, cr);
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s = s + cell_phi[lf[j]];
+    v = s / (double)k;
+  }
+  corner_phi[t] = v;
+}
+
+hipError_t launch_cell_to_corner_phi(const Mesh2D& m, const double* cell_phi, double* corner_phi, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_to_corner_phi, dim3(ceil_div(4u * m.nleaves, kBlock)), dim3(kBlock), 0, s, m, cell_phi,
+                     corner_phi);
+  return hipGetLastError();
+}
+
+__global__ void k_corner_grad(Mesh2D m, const double* __restrict__ cphi, double* __restrict__ grad) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= m.nleaves) return;
+  const double h = ldexp(m.length, -(int)m.lv[l]);
+  const double* f = cphi + (size_t)l * 4u;
+  double* g = grad + (size_t)l * 8u;
+  for (int c = 0; c < 4; ++c) {
+    const int a = c & 1, bb = c >> 1;
+    g[c * 2 + 0] = (f[0 + 2 * bb] - f[1 + 2 * bb]) / h;
+    g[c * 2 + 1] = (f[a + 0] - f[a + 2]) / h;
+  }
+}
+
+template <class T>
+__global__ void k_nodal_e(Mesh2D m, const double* __restrict__ grad, double* __restrict__ ce64, T* __restrict__ ce) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4u * m.nleaves) return;
+  const uint32_t l = t >> 2;
+  const int c = (int)(t & 3u);
+  const LeafBox b = leaf_box(m, l);
+  const uint32_t X = b.x0 + ((c & 1) ? b.size : 0u), Y = b.y0 + ((c >> 1) ? b.size : 0u);
+  uint32_t lf[4];
+  int cr[4];
+  const int k = node_leaves(m, X, Y, lf, cr);
+  double sx = 0.0, sy = 0.0;
+  for (int j = 0; j < k; ++j) {
+    sx = sx + grad[(size_t)lf[j] * 8u + cr[j] * 2 + 0];
+    sy = sy + grad[(size_t)lf[j] * 8u + cr[j] * 2 + 1];
+  }
+  const double ex = sx / (double)k, ey = sy / (double)k;
+  ce64[(size_t)t * 2u + 0] = ex;
+  ce64[(size_t)t * 2u + 1] = ey;
+  ce[(size_t)t * 2u + 0] = (T)ex;
+  ce[(size_t)t * 2u + 1] = (T)ey;
+}
+
+template <class T>
+hipError_t launch_corner_field(const Mesh2D& m, const double* corner_phi, double* grad, double* corner_e64, T* corner_e,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_corner_grad, dim3(ceil_div(m.nleaves, kBlock)), dim3(kBlock), 0, s, m, corner_phi, grad);
+  hipLaunchKernelGGL(k_nodal_e<T>, dim3(ceil_div(4u * m.nleaves, kBlock)), dim3(kBlock), 0, s, m, grad, corner_e64,
+                     corner_e);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void k_round(const double* src, T* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (T)src[i];
+}
+template <class T>
+hipError_t launch_round_table(const double* src, T* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_round<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 2D finite-volume operator on the leaves
+// ---------------------------------------------------------------------------
+__global__ void k_build_stencil(Mesh2D m, Stencil2D st) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= m.nleaves) return;
+  const LeafBox b = leaf_box(m, l);
+  const int la = m.lv[l];
+  const double ha = ldexp(1.0, -la);
+  uint32_t* nb = st.nbr + (size_t)l * 8u;
+  double* cf = st.coef + (size_t)l * 8u;
+  int k = 0;
+  double diag = 0.0, bnd = 0.0;
+  const uint32_t half = b.size >> 1;
+  // sides: 0 west, 1 east, 2 south, 3 north
+  for (int side = 0; side < 4; ++side) {
+    bool wall;
+    uint32_t p1x, p1y, p2x, p2y;
+    switch (side) {
+      case 0: wall = b.x0 == 0u; p1x = b.x0 - 1u; p1y = b.y0; p2x = p1x; p2y = b.y0 + half; break;
+      case 1: wall = b.x0 + b.size >= 65536u; p1x = b.x0 + b.size; p1y = b.y0; p2x = p1x; p2y = b.y0 + half; break;
+      case 2: wall = b.y0 == 0u; p1x = b.x0; p1y = b.y0 - 1u; p2x = b.x0 + half; p2y = p1y; break;
+      default: wall = b.y0 + b.size >= 65536u; p1x = b.x0; p1y = b.y0 + b.size; p2x = b.x0 + half; p2y = p1y; break;
+    }
+    if (wall) {
+      if (m.field_bc[side] == PIC_WALL_DIRICHLET) {
+        diag = diag + 2.0;
+        bnd = bnd + 2.0 * m.wall_phi[side];
+      }
+      continue;
+    }
+    const uint32_t n1 = locate_leaf(m.key, m.lv, m.lut, m.lut_level, p1x, p1y);
+    const int l1 = m.lv[n1];
+    const double h1 = ldexp(1.0, -l1);
+    const double c1 = fmin(ha, h1) / ((ha + h1) / 2.0);
+    nb[k] = n1;
+    cf[k] = c1;
+    ++k;
+    diag = diag + c1;
+    if (l1 > la) {   // two finer neighbours share this side
+      const uint32_t n2 = locate_leaf(m.key, m.lv, m.lut, m.lut_level, p2x, p2y);
+      const double h2 = ldexp(1.0, -(int)m.lv[n2]);
+      const double c2 = fmin(ha, h2) / ((ha + h2) / 2.0);
+      nb[k] = n2;
+      cf[k] = c2;
+      ++k;
+      diag = diag + c2;
+    }
+  }
+  for (; k < 8; ++k) {
+    nb[k] = l;
+    cf[k] = 0.0;
+  }
+  st.diag[l] = diag;
+  st.bnd[l] = bnd;
+}
+
+hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_stencil, dim3(ceil_div(m.nleaves, kBlock)), dim3(kBlock), 0, s, m, st);
+  return hipGetLastError();
+}
+
+// CG workspace layout (doubles): r, z, p, q [4 n] then block partials
+// [3][grid] then scalars [8]: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha, 5 beta, 6 rz_new.
+int cg_grid(uint32_t n) {
+  int g = (int)ceil_div(n, kBlock);
+  return g < 1024 ? g : 1024;
+}
+int cg_ws_doubles(uint32_t n) { return (int)(4u * n + 3u * (uint32_t)cg_grid(n) + 8u); }
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  v = wave_sum(v);
+  if (lane_id() == 0) red[threadIdx.x / 64] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t = t + red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ double apply_row(const Stencil2D& st, const double* x, uint32_t i) {
+  double y = st.diag[i] * x[i];
+  const uint32_t* nb = st.nbr + (size_t)i * 8u;
+  const double* cf = st.coef + (size_t)i * 8u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) y = y - cf[k] * x[nb[k]];
+  return y;
+}
+
+// r = b - A x, z = r / diag, p = z; partial sums of r.z, r.r, b.b
+__global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, const unsigned long long* __restrict__ Q,
+                                                     int nspecies, double k0, double k1, const double* __restrict__ x,
+                                                     double* ws, int grid) {
+  const uint32_t n = m.nleaves;
+  double *r = ws, *z = ws + n, *p = ws + 2u * n, *part = ws + 4u * n;
+  double srz = 0.0, srr = 0.0, sbb = 0.0;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    double b = (double)(long long)Q[i] * k0;
+    if (nspecies > 1) b = b + (double)(long long)Q[(size_t)n + i] * k1;
+    b = b + st.bnd[i];
+    const double ri = b - apply_row(st, x, i);
+    const double zi = ri / st.diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    srz += ri * zi;
+    srr += ri * ri;
+    sbb += b * b;
+  }
+  srz = block_sum(srz);
+  srr = block_sum(srr);
+  sbb = block_sum(sbb);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[grid + blockIdx.x] = srr;
+    part[2 * grid + blockIdx.x] = sbb;
+  }
+}
+
+// one-block reduction of the partials into scalars; what = 0 (setup), 1 (alpha), 2 (beta)
+__global__ __launch_bounds__(kBlock) void k_cg_reduce(double* ws, uint32_t n, int grid, int what) {
+  double* part = ws + 4u * n;
+  double* sc = part + 3 * grid;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int j = threadIdx.x; j < grid; j += kBlock) {
+    a += part[j];
+    b += part[grid + j];
+    c += part[2 * grid + j];
+  }
+  a = block_sum(a);
+  b = block_sum(b);
+  c = block_sum(c);
+  if (threadIdx.x == 0) {
+    if (what == 0) {
+      sc[0] = a;
+      sc[2] = b;
+      sc[3] = c;
+    } else if (what == 1) {
+      sc[1] = a;
+      sc[4] = sc[0] / a;
+    } else {
+      sc[6] = a;
+      sc[2] = b;
+      sc[5] = a / sc[0];
+      sc[0] = a;
+    }
+  }
+}
+
+// q = A p; partial p.q
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(Mesh2D m, Stencil2D st, double* ws, int grid) {
+  const uint32_t n = m.nleaves;
+  const double* p = ws + 2u * n;
+  double* q = ws + 3u * n;
+  double* part = ws + 4u * n;
+  double s = 0.0;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double qi = apply_row(st, p, i);
+    q[i] = qi;
+    s += p[i] * qi;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    part[grid + blockIdx.x] = 0.0;
+    part[2 * grid + blockIdx.x] = 0.0;
+  }
+}
+
+// x += alpha p, r -= alpha q, z = r / diag; partial r.z, r.r
+__global__ __launch_bounds__(kBlock) void k_cg_axpy(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
+                                                    int grid) {
+  const uint32_t n = m.nleaves;
+  double *r = ws, *z = ws + n, *p = ws + 2u * n, *q = ws + 3u * n, *part = ws + 4u * n;
+  const double alpha = part[3 * grid + 4];
+  double srz = 0.0, srr = 0.0;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    x[i] = x[i] + alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    const double zi = ri / st.diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    srz += ri * zi;
+    srr += ri * ri;
+  }
+  srz = block_sum(srz);
+  srr = block_sum(srr);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[grid + blockIdx.x] = srr;
+    part[2 * grid + blockIdx.x] = 0.0;
+  }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(kBlock) void k_cg_p(uint32_t n, double* ws, int grid) {
+  const double* z = ws + n;
+  double* p = ws + 2u * n;
+  const double beta = ws[4u * n + 3 * grid + 5];
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
+}
+
+hipError_t launch_cg_setup(const Mesh2D& m, const Stencil2D& st, const unsigned long long* Q, int nspecies,
+                           const double* kappa, double* x, double* ws, hipStream_t s) {
+  const int g = cg_grid(m.nleaves);
+  hipLaunchKernelGGL(k_cg_setup, dim3(g), dim3(kBlock), 0, s, m, st, Q, nspecies, kappa[0], kappa[1], x, ws, g);
+  hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kBlock), 0, s, ws, m.nleaves, g, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, hipStream_t s) {
+  const int g = cg_grid(m.nleaves);
+  hipLaunchKernelGGL(k_cg_spmv, dim3(g), dim3(kBlock), 0, s, m, st, ws, g);
+  hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kBlock), 0, s, ws, m.nleaves, g, 1);
+  hipLaunchKernelGGL(k_cg_axpy, dim3(g), dim3(kBlock), 0, s, m, st, x, ws, g);
+  hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kBlock), 0, s, ws, m.nleaves, g, 2);
+  hipLaunchKernelGGL(k_cg_p, dim3(g), dim3(kBlock), 0, s, m.nleaves, ws, g);
+  return hipGetLastError();
+}
+
+#define PIC_FIELD_INST(T)                                                                                        \
+  template hipError_t launch_field1d<T>(const InstDev<T>*, int, int, int, const double*, const unsigned long long*, \
+                                        const uint32_t*, hipStream_t);                                           \
+  template hipError_t launch_node_e_1d<T>(const InstDev<T>&, const double*, int, hipStream_t);                 \
+  template hipError_t launch_corner_field<T>(const Mesh2D&, const double*, double*, double*, T*, hipStream_t);   \
+  template hipError_t launch_round_table<T>(const double*, T*, int64_t, hipStream_t);
+PIC_FIELD_INST(float)
+PIC_FIELD_INST(double)
+
+}  // namespace pic

@@ -1,0 +1,147 @@
+// Quadtree and particle-order kernels: the locate lookup table, leaf corner
+// coordinates, and the counting sort that keeps particles ordered by cell
+// (the GPU form of the paper's cell-based particle lists, Sec. 3.1: each
+// leaf's particles are a contiguous range of the arrays).
+#include "device_util.hpp"
+#include "pic_internal.hpp"
+#include "k_mesh.hpp"
+
+namespace pic {
+
+__device__ __forceinline__ uint32_t compact16(uint32_t v) {
+  v &= 0x55555555u;
+  v = (v | (v >> 1)) & 0x33333333u;
+  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+  v = (v | (v >> 4)) & 0x00FF00FFu;
+  v = (v | (v >> 8)) & 0x0000FFFFu;
+  return v;
+}
+
+__global__ void k_leaf_xy(const uint32_t* key, uint32_t n, uint32_t* xy) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < n) xy[l] = (compact16(key[l]) << 16) | compact16(key[l] >> 1);
+}
+
+hipError_t launch_leaf_xy(const uint32_t* key, const uint8_t* lv, uint32_t n, uint32_t* xy, hipStream_t s) {
+  (void)lv;
+  hipLaunchKernelGGL(k_leaf_xy, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, key, n, xy);
+  return hipGetLastError();
+}
+
+// lut[c] = last leaf whose key <= key of cell c's low corner; lut[4^L] = n
+__global__ void k_build_lut(const uint32_t* key, uint32_t n, uint32_t* lut, int L) {
+  const uint32_t ncell = 1u << (2 * L);
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncell) return;
+  if (c == ncell) {
+    lut[c] = n;
+    return;
+  }
+  const uint32_t k = c << (2 * (16 - L));
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (key[mid] <= k) lo = mid; else hi = mid - 1u;
+  }
+  lut[c] = lo;
+}
+
+hipError_t launch_build_lut(const uint32_t* key, const uint8_t* lv, uint32_t n, uint32_t* lut, int L, hipStream_t s) {
+  (void)lv;
+  hipLaunchKernelGGL(k_build_lut, dim3(ceil_div((1u << (2 * L)) + 1u, kBlock)), dim3(kBlock), 0, s, key, n, lut, L);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort of one species by cell (1D: floor(s N); 2D: leaf), dropping
+// holes.  hist/off has ncell + 1 entries.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint32_t i) {
+  if (I.dim == 2) return I.cell[sp][i];
+  const T g = I.s[sp][0][i] * (T)I.N;
+  int ic = (int)floor(g);
+  if (ic > I.N - 1) ic = I.N - 1;
+  return (uint32_t)ic;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint32_t* hist) {
+  const uint32_t count = I.ctr->count[sp];
+  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+    const uint32_t i = base + threadIdx.x;
+    const bool live = i < count && I.w[sp][i] != 0u;
+    const uint32_t c = live ? sort_cell<T>(I, sp, i) : kNoKey;
+    (void)seg_atomic_claim(hist, c);
+  }
+}
+
+// single-workgroup exclusive scan of n counts in place; a[n] = total
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t chunk = (n + 1023u) / 1024u;
+  const uint32_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
+  uint32_t s = 0;
+  for (uint32_t i = b; i < e; ++i) s += a[i];
+  part[t] = s;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024u; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (uint32_t i = b; i < e; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  if (t == 1023u) a[n] = part[1023];
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, uint32_t* off, T* ds0, T* ds1, T* dv0,
+                                                         T* dv1, T* dv2, uint32_t* dw, uint32_t* did, uint32_t* dcell) {
+  const uint32_t count = I.ctr->count[sp];
+  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+    const uint32_t i = base + threadIdx.x;
+    const bool live = i < count && I.w[sp][i] != 0u;
+    const uint32_t c = live ? sort_cell<T>(I, sp, i) : kNoKey;
+    const uint32_t pos = seg_atomic_claim(off, c);
+    if (live) {
+      ds0[pos] = I.s[sp][0][i];
+      if (I.dim == 2) {
+        ds1[pos] = I.s[sp][1][i];
+        dcell[pos] = I.cell[sp][i];
+      }
+      dv0[pos] = I.v[sp][0][i];
+      dv1[pos] = I.v[sp][1][i];
+      dv2[pos] = I.v[sp][2][i];
+      dw[pos] = I.w[sp][i];
+      did[pos] = I.id[sp][i];
+    }
+  }
+}
+
+__global__ void k_set_count(Counters* ctr, int sp, const uint32_t* total) { ctr->count[sp] = *total; }
+
+template <class T>
+hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* off, const SortDst<T>& d, int grid,
+                       hipStream_t s) {
+  hipMemsetAsync(off, 0, sizeof(uint32_t) * (ncell + 1u), s);
+  hipLaunchKernelGGL(k_sort_hist<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off);
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, off, ncell);
+  hipLaunchKernelGGL(k_sort_scatter<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, d.s0, d.s1, d.v0, d.v1, d.v2, d.w,
+                     d.id, d.cell);
+  hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, I.ctr, sp, off + ncell);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sort<float>(const InstDev<float>&, int, uint32_t, uint32_t*, const SortDst<float>&, int,
+                                       hipStream_t);
+template hipError_t launch_sort<double>(const InstDev<double>&, int, uint32_t, uint32_t*, const SortDst<double>&, int,
+                                        hipStream_t);
+
+}  // namespace pic

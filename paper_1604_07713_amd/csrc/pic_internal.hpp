@@ -1,0 +1,151 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+constexpr int kBlock = 256;          // threads per workgroup of the particle kernels
+constexpr int kKeyBits = 16;         // quadtree keys: Morton code of 16-bit coordinates
+
+// Per-instance device counters.  Updated only by kernels, so a sequence of
+// steps (or a captured graph) runs without host round trips.
+struct Counters {
+  uint32_t count[2];     // particle slots in use per species (live + holes)
+  uint32_t next_id;
+  uint32_t nbirths;      // staged births of the current step
+  uint32_t flags;        // kFlag* bits
+  uint32_t step;         // global index of the next step
+  uint32_t vstep0;       // step index of v_table[0]
+  uint32_t pad;
+  unsigned long long stats[12];
+};
+enum : uint32_t { kFlagBirthOverflow = 1u, kFlagIdOverflow = 2u, kFlagSplitOverflow = 4u };
+enum StatIdx {
+  kStAlive0 = 0, kStAlive1, kStAbs0, kStAbs1, kStElastic, kStIonization, kStCx, kStBirths,
+  kStViol0, kStViol1, kStLostReflect, kStUnused
+};
+
+template <class T>
+struct SpeciesK {
+  T qm_dt, hqm_dt, dt_L;
+  T a_el, a_iz, v_iz2, mu2, vmax2, v_thg, a_cx, gmax;
+  uint32_t tcand;
+  int mcc;
+};
+
+template <class T>
+struct Births {          // staging of one step's ionization births (SoA)
+  uint32_t* parent;
+  uint32_t* cell;
+  uint32_t* w;
+  T* s[2];
+  T* ve[3];
+  T* vi[3];
+};
+
+// Kernel-side view of one instance.
+template <class T>
+struct InstDev {
+  int dim, N, particle_bc, nspecies;
+  uint32_t key0, key1;           // Philox key
+  SpeciesK<T> sk[2];
+  T* s[2][2];                    // [species][axis]
+  T* v[2][3];
+  uint32_t* w[2];
+  uint32_t* id[2];
+  uint32_t* cell[2];
+  uint32_t cap[2];
+  const T* E;                    // 1D node E [N+1]; 2D corner E [nleaves][4][2]
+  const uint32_t* leaf_key;
+  const uint32_t* leaf_xy;       // (x0 << 16) | y0 in 16-bit units
+  const uint8_t* leaf_lv;
+  const uint32_t* lut;           // leaf containing each level-lut_level cell's low corner
+  int lut_level;
+  uint32_t nleaves;
+  unsigned long long* Q;         // [2 parity][2 species][nq]
+  uint32_t nq;
+  Births<T> br;
+  uint32_t birth_cap;
+  Counters* ctr;
+  const double* v_table;         // 1D drive potential per step (solve on device)
+  uint32_t v_len;
+  unsigned long long* part;      // per-block partial stats [nparts][kNStat]
+  uint32_t nparts;
+  // FP64 field data
+  const double* inv_m;           // 1D Thomas pivots 1/m_i (i = 1..N-1)
+  double kappa[2];               // charge-sum -> Poisson right-hand side factor per species
+  double inv2dx;                 // 1D: 1 / (2 dx)
+  double* phi64;                 // 1D: node potential; 2D: cell potential
+  double* e64;                   // 1D: node E; 2D: corner E [nleaves][8]
+};
+constexpr int kNStat = 12;
+
+// Work item of the batched (persistent) 1D launch.
+struct WorkItem {
+  uint32_t inst, species, begin, end;
+};
+
+// ---- launchers (k_step.hip) ----
+template <class T> hipError_t launch_step1d(const InstDev<T>& I, hipStream_t s, int grid);
+template <class T> hipError_t launch_step2d(const InstDev<T>& I, hipStream_t s, int grid);
+template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
+                                                    unsigned long long* bpart, hipStream_t s, int grid);
+template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid);
+template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s);
+template <class T> hipError_t launch_commit(const InstDev<T>& I, uint32_t nrows, hipStream_t s);
+template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, const unsigned long long* bpart,
+                                                    const uint32_t* item_begin, int ninst, hipStream_t s);
+template <class T> hipError_t launch_deposit(const InstDev<T>& I, hipStream_t s, int grid);
+template <class T> hipError_t launch_leapfrog_start(const InstDev<T>& I, hipStream_t s, int grid);
+template <class T> hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int grid);
+
+// ---- field (k_field.hip) ----
+// mode 0: solve from the latest deposit with phi(0) = phi_left[inst];
+// mode 1: after a step: solve from this step's deposit with phi(0) from the
+//         drive table, then commit the step (rows: partial-stats rows).
+template <class T> hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mode,
+                                             const double* phi_left, const unsigned long long* rows,
+                                             const uint32_t* row_begin, hipStream_t s);
+template <class T> hipError_t launch_node_e_1d(const InstDev<T>& I, const double* data, int is_phi, hipStream_t s);
+struct Mesh2D {
+  const uint32_t* key;
+  const uint32_t* xy;
+  const uint8_t* lv;
+  const uint32_t* lut;
+  int lut_level;
+  uint32_t nleaves;
+  double length;
+  int field_bc[4];
+  double wall_phi[4];
+};
+template <class T> hipError_t launch_corner_field(const Mesh2D& m, const double* corner_phi, double* grad,
+                                                  double* corner_e64, T* corner_e, hipStream_t s);
+hipError_t launch_cell_to_corner_phi(const Mesh2D& m, const double* cell_phi, double* corner_phi, hipStream_t s);
+template <class T> hipError_t launch_round_table(const double* src, T* dst, int64_t n, hipStream_t s);
+struct Stencil2D {
+  uint32_t* nbr;     // [nleaves][8], kNoKey-free: unused entries point at the leaf itself with coef 0
+  double* coef;      // [nleaves][8]
+  double* diag;      // [nleaves]
+  double* bnd;       // [nleaves] Dirichlet contribution to the right-hand side
+};
+hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_t s);
+// CG work vectors and scalars live in 'ws' (see k_field.hip for the layout)
+hipError_t launch_cg_setup(const Mesh2D& m, const Stencil2D& st, const unsigned long long* Q, int nspecies,
+                           const double* kappa, double* x, double* ws, hipStream_t s);
+hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, hipStream_t s);
+int cg_ws_doubles(uint32_t nleaves);
+int cg_grid(uint32_t nleaves);
+
+// ---- mesh (k_mesh.hip) ----
+hipError_t launch_build_lut(const uint32_t* key, const uint8_t* lv, uint32_t nleaves, uint32_t* lut, int lut_level,
+                            hipStream_t s);
+hipError_t launch_leaf_xy(const uint32_t* key, const uint8_t* lv, uint32_t nleaves, uint32_t* xy, hipStream_t s);
+__host__ __device__ inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+}  // namespace pic
