@@ -26,9 +26,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, GB/s
 # algorithmic bytes per particle-update of the 2D FP32 step kernel without
-# collisions: read sx, sy, vx, vy, w, leaf (6 x 4 B), write sx, sy, vx, vy,
-# leaf (5 x 4 B); the field and charge tables are cache resident.
-BYTES_PER_UPDATE_2D = 44
+# collisions: read sx, sy, vx, vy, w, leaf (6 x 4 B), write sx, sy, vx, vy
+# (4 x 4 B; the leaf index is rewritten only when it changes); the field,
+# leaf and charge tables are cache resident.
+BYTES_PER_UPDATE_2D = 40
 METRIC = "particle-updates/s (locate+gather+push+MCC+deposit), 2D AMR; batched vs plain"
 PROFILE_PMC = os.path.join(ROOT, "profiles", "step2d_quadtree_4M_pmc.json")
 
@@ -84,6 +85,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="instead of the benchmark, copy this many bytes 10 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -93,6 +96,15 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "repeats": 10}), flush=True)
+        return
     from paper_1604_07713_amd import binding as B
     from paper_1604_07713_amd import inputs as I
 

@@ -90,21 +90,33 @@ __global__ void k_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t
 }
 
 // ---- one plain step of one slot ----
+bool slot_has_mcc(const Slot& sl) {
+  for (int sp = 0; sp < sl.d.nspecies; ++sp)
+    if (sl.d.species[sp].mcc != PIC_MCC_NONE) return true;
+  return false;
+}
+
 template <class T>
 void plain_step(Ctx& C, Slot& sl, bool solve, hipEvent_t e0, hipEvent_t e1) {
   InstDev<T> I = make_dev<T>(sl);
   const int g = plain_grid<T>(sl);
-  I.nparts = (uint32_t)g;
+  const bool field = sl.d.dim == 1 && solve;
+  const int commit = (!sl.ionizing && !field) ? 1 : 0;
   if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
-  if (sl.d.dim == 1) hip_check(launch_step1d<T>(I, C.stream, g), "step1d");
-  else hip_check(launch_step2d<T>(I, C.stream, g), "step2d");
+  hip_check(launch_step<T>(I, C.stream, g, slot_has_mcc(sl), commit), "step");
   if (sl.ionizing) hip_check(launch_births<T>(I, C.stream, 64), "births");
   if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
-  if (sl.d.dim == 1 && solve)
-    hip_check(launch_field1d<T>((const InstDev<T>*)sl.devI, 1, sl.d.ncells, 1, nullptr, sl.part, nullptr, C.stream),
-              "field1d");
-  else
-    hip_check(launch_commit<T>(I, (uint32_t)g, C.stream), "commit");
+  if (field)
+    hip_check(launch_field1d<T>((const InstDev<T>*)sl.devI, 1, sl.d.ncells, 1, nullptr, C.stream), "field1d");
+  else if (!commit)
+    hip_check(launch_commit<T>(I, C.stream), "commit");
+}
+
+template <class T>
+void reduce_plain_stats(Ctx& C, Slot& sl) {
+  hip_check(launch_stats_reduce<T>((const InstDev<T>*)sl.devI, 1, nullptr, nullptr, (uint32_t)plain_grid<T>(sl),
+                                   C.stream),
+            "stats_reduce");
 }
 
 void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead) {
@@ -192,12 +204,13 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   const uint32_t tile = (uint32_t)(a->batched > 1 ? a->batched : 4096);
   std::vector<WorkItem> items;
   std::vector<uint32_t> rowbeg(nsel + 1, 0);
-  bool ionizing = false;
+  bool ionizing = false, any_mcc = false;
   int maxn = 0;
   for (int j = 0; j < nsel; ++j) {
     Slot& sl = *sel[j];
     rowbeg[j] = (uint32_t)items.size();
     ionizing = ionizing || sl.ionizing;
+    any_mcc = any_mcc || slot_has_mcc(sl);
     maxn = std::max(maxn, sl.d.ncells);
     for (int sp = 0; sp < sl.d.nspecies; ++sp)
       for (int64_t b = 0; b < sl.cap[sp]; b += tile)
@@ -213,7 +226,10 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   };
   ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * items.size());
   ensure(C.b_insts, C.b_insts_bytes, sizeof(InstDev<T>) * nsel);
-  ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * items.size());
+  if (C.b_part_bytes < sizeof(unsigned long long) * kNStat * items.size()) {
+    ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * items.size());
+    hip_check(hipMemsetAsync(C.b_part, 0, C.b_part_bytes, C.stream), "memset");
+  }
   ensure(*(void**)&C.b_rowbeg, C.b_rowbeg_bytes, sizeof(uint32_t) * (nsel + 1));
   hip_check(hipMemcpyAsync(C.b_items, C.stage(items.data(), sizeof(WorkItem) * items.size()),
                            sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, C.stream),
@@ -239,19 +255,20 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
       hip_check(hipEventRecord(e0, C.stream), "event");
     }
     hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)C.b_items, (uint32_t)items.size(), C.b_part, C.stream,
-                                       grid),
+                                       grid, any_mcc),
               "step1d_batched");
     if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, C.stream), "births_batched");
     if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
     if (a->solve_field)
-      hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, C.b_part, C.b_rowbeg, C.stream), "field1d batched");
+      hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, C.stream), "field1d batched");
     else
-      hip_check(launch_commit_batched<T>(dI, C.b_part, C.b_rowbeg, nsel, C.stream), "commit batched");
+      hip_check(launch_commit_batched<T>(dI, nsel, C.stream), "commit batched");
     if (a->sort_every > 0 && (k + 1) % a->sort_every == 0 && k + 1 < kend) {
       for (Slot* s : sel) sort_slot(C, *s);
       upload_insts();
     }
   }
+  hip_check(launch_stats_reduce<T>(dI, nsel, C.b_part, C.b_rowbeg, 0u, C.stream), "stats_reduce batched");
   if (loop_ms) {
     C.sync();
     for (int64_t k = kbeg; k < kend; ++k) {
@@ -566,9 +583,9 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
     double* pl = (double*)c->stage(&phi_left, sizeof(double));
     upload_dev(*c, sl);
     if (sl.prec == 32)
-      hip_check(launch_field1d<float>((const InstDev<float>*)sl.devI, 1, sl.d.ncells, 0, pl, nullptr, nullptr, c->stream), "field1d");
+      hip_check(launch_field1d<float>((const InstDev<float>*)sl.devI, 1, sl.d.ncells, 0, pl, c->stream), "field1d");
     else
-      hip_check(launch_field1d<double>((const InstDev<double>*)sl.devI, 1, sl.d.ncells, 0, pl, nullptr, nullptr, c->stream), "field1d");
+      hip_check(launch_field1d<double>((const InstDev<double>*)sl.devI, 1, sl.d.ncells, 0, pl, c->stream), "field1d");
     c->sync();
     const size_t n = (size_t)sl.d.ncells + 1;
     if (phi_out) hip_check(hipMemcpy(phi_out, sl.phi64, 8 * n, hipMemcpyDeviceToHost), "read");
@@ -683,6 +700,10 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
           else plain_step<double>(*c, sl, a->solve_field != 0, e0, e1);
           if (a->sort_every > 0 && (kb + k + 1) % a->sort_every == 0) sort_slot(*c, sl);
         }
+      }
+      for (int j = 0; j < nsel; ++j) {
+        if (sel[j]->prec == 32) reduce_plain_stats<float>(*c, *sel[j]);
+        else reduce_plain_stats<double>(*c, *sel[j]);
       }
       if (a->timing) {
         c->sync();

@@ -293,6 +293,11 @@ void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
   sl.lv = (uint8_t*)sl.alloc(L.size());
   sl.xy = (uint32_t*)sl.alloc(4 * L.size());
   sl.lut_level = std::min(sl.d.max_level, 9);
+  {
+    int mx = 0;
+    for (const HostLeaf& l : L) mx = std::max(mx, (int)l.lv);
+    sl.lut_direct = mx <= sl.lut_level;
+  }
   sl.lut = (uint32_t*)sl.alloc(4 * ((size_t(1) << (2 * sl.lut_level)) + 1));
   hip_check(hipMemcpy(sl.key, keys.data(), 4 * L.size(), hipMemcpyHostToDevice), "upload keys");
   hip_check(hipMemcpy(sl.lv, lv.data(), L.size(), hipMemcpyHostToDevice), "upload levels");
@@ -435,6 +440,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.leaf_lv = sl.lv;
   I.lut = sl.lut;
   I.lut_level = sl.lut_level;
+  I.lut_direct = sl.lut_direct ? 1 : 0;
   I.nleaves = sl.nleaves;
   I.Q = sl.Q;
   I.nq = sl.nq;

@@ -10,7 +10,7 @@
 
 namespace pic {
 
-constexpr int kMaxGrid = 4096;   // upper bound on the plain particle-kernel grid
+constexpr int kMaxGrid = 2048;   // upper bound on the plain particle-kernel grid
 
 struct Err {
   int code;
@@ -66,6 +66,7 @@ struct Slot {
   uint32_t *key = nullptr, *xy = nullptr, *lut = nullptr;
   uint8_t* lv = nullptr;
   int lut_level = 0;
+  bool lut_direct = false;
   uint32_t nleaves = 0;
   std::vector<HostLeaf> host_leaves;
   Stencil2D st{nullptr, nullptr, nullptr, nullptr};

@@ -16,6 +16,23 @@ namespace pic {
 
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
+// Global-address-space views.  Pointers read from a by-value descriptor lose
+// their address space; without these casts every access compiles to a FLAT
+// instruction, which also holds the LDS wait counter and serialises LDS
+// atomics behind outstanding memory loads.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> G(T* p) { return (gptr<T>)p; }
+template <class T>
+__device__ __forceinline__ gptr<const T> G(const T* p) { return (gptr<const T>)p; }
+__device__ __forceinline__ void gadd(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_fetch_add((gptr<unsigned long long>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t gadd32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add((gptr<uint32_t>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3,
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -131,7 +148,7 @@ __device__ __forceinline__ void seg_atomic_add(unsigned long long* dst, uint32_t
     const unsigned long long o = __shfl_up(val, (unsigned)off);
     if (lane - off >= start) val += o;
   }
-  if (run_tail(key, lane) && key != kNoKey && val != 0ull) atomicAdd(dst + key, val);
+  if (run_tail(key, lane) && key != kNoKey && val != 0ull) gadd(dst + key, val);
 }
 
 // Same for 32-bit counters; returns for each lane its rank in its run and
@@ -142,7 +159,7 @@ __device__ __forceinline__ uint32_t seg_atomic_claim(uint32_t* cursor, uint32_t 
   const uint32_t rank = (uint32_t)(lane - start);
   const bool tail = run_tail(key, lane);
   uint32_t base = 0;
-  if (tail && key != kNoKey) base = atomicAdd(cursor + key, rank + 1u);
+  if (tail && key != kNoKey) base = gadd32(cursor + key, rank + 1u);
   // broadcast the base from the tail lane of the run to the whole run
   const uint64_t tails = __ballot(tail);
   const uint64_t above = tails & ~(lanes_le(lane) >> 1);   // tail lanes >= lane
@@ -175,18 +192,19 @@ __device__ __forceinline__ uint32_t morton2(uint32_t x, uint32_t y) { return spr
 // cell c (lut has 4^lut_level + 1 entries, the last = nleaves); when that
 // leaf is finer than lut_level, the cell's leaves are lut[c] .. lut[c+1]-1
 // and a binary search over their keys finds the last key <= Morton(X, Y).
+// lut_direct: no leaf is finer than lut_level, so lut[c] is the answer.
 __device__ __forceinline__ uint32_t locate_leaf(const uint32_t* __restrict__ key, const uint8_t* __restrict__ lv,
                                                 const uint32_t* __restrict__ lut, int lut_level, uint32_t X,
-                                                uint32_t Y) {
+                                                uint32_t Y, bool lut_direct = false) {
   const int sh = 16 - lut_level;
   const uint32_t c = morton2(X >> sh, Y >> sh);
-  uint32_t lo = lut[c];
-  if ((int)lv[lo] <= lut_level) return lo;
-  uint32_t hi = lut[c + 1] - 1u;
+  uint32_t lo = G(lut)[c];
+  if (lut_direct || (int)G(lv)[lo] <= lut_level) return lo;
+  uint32_t hi = G(lut)[c + 1] - 1u;
   const uint32_t m = morton2(X, Y);
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1u) >> 1;
-    if (key[mid] <= m) lo = mid; else hi = mid - 1u;
+    if (G(key)[mid] <= m) lo = mid; else hi = mid - 1u;
   }
   return lo;
 }

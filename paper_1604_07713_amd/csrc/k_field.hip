@@ -21,9 +21,7 @@ namespace pic {
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict__ insts, int mode,
-                                                    const double* __restrict__ phi_left,
-                                                    const unsigned long long* __restrict__ rows,
-                                                    const uint32_t* __restrict__ row_begin) {
+                                                    const double* __restrict__ phi_left) {
   extern __shared__ double lds[];
   const InstDev<T>& I = insts[blockIdx.x];
   const int N = I.N;
@@ -107,39 +105,26 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
     if (I.e64) I.e64[i] = e;
     if (I.phi64) I.phi64[i] = b[i];
   }
-  if (mode == 1) {
-    __syncthreads();
-    // commit the step: partial-stats rows of this instance, births, step index
-    __shared__ unsigned long long acc[kNStat];
-    if (threadIdx.x < kNStat) acc[threadIdx.x] = 0ull;
-    __syncthreads();
-    const uint32_t rb = row_begin ? row_begin[blockIdx.x] : 0u;
-    const uint32_t re = row_begin ? row_begin[blockIdx.x + 1] : I.nparts;
-    for (uint32_t r = rb + threadIdx.x / kNStat; r < re; r += kBlock / kNStat)
-      if (threadIdx.x < (kBlock / kNStat) * kNStat)
-        atomicAdd(&acc[threadIdx.x % kNStat], rows[(size_t)r * kNStat + threadIdx.x % kNStat]);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      Counters* c = I.ctr;
-      for (int q = 0; q < kNStat; ++q) c->stats[q] += acc[q];
-      const uint32_t nb = c->nbirths;
-      if (nb && !(c->flags & (kFlagBirthOverflow | kFlagIdOverflow))) {
-        c->count[0] += nb;
-        c->count[1] += nb;
-        c->next_id += 2u * nb;
-        c->stats[kStBirths] += nb;
-      }
-      c->nbirths = 0u;
-      c->step = step + 1u;
+  if (mode == 1 && threadIdx.x == 0) {
+    // commit the step: births join the counts, the step index advances
+    Counters* c = I.ctr;
+    const uint32_t nb = c->nbirths;
+    if (nb && !(c->flags & (kFlagBirthOverflow | kFlagIdOverflow))) {
+      c->count[0] += nb;
+      c->count[1] += nb;
+      c->next_id += 2u * nb;
+      c->stats[kStBirths] += nb;
     }
+    c->nbirths = 0u;
+    c->step = step + 1u;
   }
 }
 
 template <class T>
 hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mode, const double* phi_left,
-                          const unsigned long long* rows, const uint32_t* row_begin, hipStream_t s) {
+                          hipStream_t s) {
   const size_t lds = (size_t)2 * (max_n + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_field1d<T>, dim3(ninst), dim3(kBlock), lds, s, insts, mode, phi_left, rows, row_begin);
+  hipLaunchKernelGGL(k_field1d<T>, dim3(ninst), dim3(kBlock), lds, s, insts, mode, phi_left);
   return hipGetLastError();
 }
 
@@ -513,8 +498,7 @@ hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, doubl
 }
 
 #define PIC_FIELD_INST(T)                                                                                        \
-  template hipError_t launch_field1d<T>(const InstDev<T>*, int, int, int, const double*, const unsigned long long*, \
-                                        const uint32_t*, hipStream_t);                                           \
+  template hipError_t launch_field1d<T>(const InstDev<T>*, int, int, int, const double*, hipStream_t);          \
   template hipError_t launch_node_e_1d<T>(const InstDev<T>&, const double*, int, hipStream_t);                 \
   template hipError_t launch_corner_field<T>(const Mesh2D&, const double*, double*, double*, T*, hipStream_t);   \
   template hipError_t launch_round_table<T>(const double*, T*, int64_t, hipStream_t);

@@ -58,22 +58,42 @@ hipError_t launch_build_lut(const uint32_t* key, const uint8_t* lv, uint32_t n, 
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint32_t i) {
-  if (I.dim == 2) return I.cell[sp][i];
-  const T g = I.s[sp][0][i] * (T)I.N;
+  if (I.dim == 2) return G(I.cell[sp])[i];
+  const T g = G(I.s[sp][0])[i] * (T)I.N;
   int ic = (int)floor(g);
   if (ic > I.N - 1) ic = I.N - 1;
   return (uint32_t)ic;
 }
 
+constexpr uint32_t kSortWin = 1024;
+constexpr uint32_t kSortMargin = 64;
+
+// Histogram of cells over one contiguous chunk per workgroup, pre-aggregated
+// in an LDS window of cells.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint32_t* hist) {
+__global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint32_t* hist, uint32_t chunk) {
+  __shared__ uint32_t win[kSortWin];
+  __shared__ uint32_t base_s;
   const uint32_t count = I.ctr->count[sp];
-  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
-    const uint32_t i = base + threadIdx.x;
-    const bool live = i < count && I.w[sp][i] != 0u;
-    const uint32_t c = live ? sort_cell<T>(I, sp, i) : kNoKey;
-    (void)seg_atomic_claim(hist, c);
+  const uint32_t begin = blockIdx.x * chunk;
+  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) win[j] = 0u;
+  if (threadIdx.x == 0) {
+    const uint32_t c0 = begin < end ? sort_cell<T>(I, sp, begin) : 0u;
+    base_s = c0 > kSortMargin ? c0 - kSortMargin : 0u;
   }
+  __syncthreads();
+  const uint32_t base = base_s;
+  for (uint32_t i = begin + threadIdx.x; i < end; i += kBlock) {
+    if (G(I.w[sp])[i] == 0u) continue;
+    const uint32_t c = sort_cell<T>(I, sp, i);
+    const uint32_t o = c - base;
+    if (o < kSortWin) atomicAdd(&win[o], 1u);
+    else gadd32(hist + c, 1u);
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock)
+    if (win[j]) gadd32(hist + base + j, win[j]);
 }
 
 // single-workgroup exclusive scan of n counts in place; a[n] = total
@@ -101,28 +121,59 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) {
   if (t == 1023u) a[n] = part[1023];
 }
 
+// Scatter to the sorted position: per tile of kBlock particles, ranks within
+// the tile come from LDS atomics on a window of cells, and one global atomic
+// per touched cell reserves the tile's range in that cell.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, uint32_t* off, T* ds0, T* ds1, T* dv0,
-                                                         T* dv1, T* dv2, uint32_t* dw, uint32_t* did, uint32_t* dcell) {
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, uint32_t* off, uint32_t chunk, T* ds0,
+                                                         T* ds1, T* dv0, T* dv1, T* dv2, uint32_t* dw, uint32_t* did,
+                                                         uint32_t* dcell) {
+  __shared__ uint32_t lcnt[kSortWin];
+  __shared__ uint32_t gbase[kSortWin];
+  __shared__ uint32_t base_s;
   const uint32_t count = I.ctr->count[sp];
-  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
-    const uint32_t i = base + threadIdx.x;
-    const bool live = i < count && I.w[sp][i] != 0u;
-    const uint32_t c = live ? sort_cell<T>(I, sp, i) : kNoKey;
-    const uint32_t pos = seg_atomic_claim(off, c);
-    if (live) {
-      ds0[pos] = I.s[sp][0][i];
-      if (I.dim == 2) {
-        ds1[pos] = I.s[sp][1][i];
-        dcell[pos] = I.cell[sp][i];
-      }
-      dv0[pos] = I.v[sp][0][i];
-      dv1[pos] = I.v[sp][1][i];
-      dv2[pos] = I.v[sp][2][i];
-      dw[pos] = I.w[sp][i];
-      did[pos] = I.id[sp][i];
+  const uint32_t begin = blockIdx.x * chunk;
+  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  for (uint32_t t0 = begin; t0 < end; t0 += kBlock) {
+    for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) lcnt[j] = 0u;
+    if (threadIdx.x == 0) {
+      const uint32_t c0 = sort_cell<T>(I, sp, t0);
+      base_s = c0 > kSortMargin ? c0 - kSortMargin : 0u;
     }
+    __syncthreads();
+    const uint32_t base = base_s;
+    const uint32_t i = t0 + threadIdx.x;
+    const bool live = i < end && G(I.w[sp])[i] != 0u;
+    uint32_t c = 0, o = kSortWin, pos = 0, rank = 0;
+    if (live) {
+      c = sort_cell<T>(I, sp, i);
+      o = c - base;
+      if (o < kSortWin) rank = atomicAdd(&lcnt[o], 1u);
+      else pos = gadd32(off + c, 1u);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock)
+      if (lcnt[j]) gbase[j] = gadd32(off + base + j, lcnt[j]);
+    __syncthreads();
+    if (live) {
+      if (o < kSortWin) pos = gbase[o] + rank;
+      G(ds0)[pos] = G(I.s[sp][0])[i];
+      if (I.dim == 2) {
+        G(ds1)[pos] = G(I.s[sp][1])[i];
+        G(dcell)[pos] = G(I.cell[sp])[i];
+      }
+      G(dv0)[pos] = G(I.v[sp][0])[i];
+      G(dv1)[pos] = G(I.v[sp][1])[i];
+      G(dv2)[pos] = G(I.v[sp][2])[i];
+      G(dw)[pos] = G(I.w[sp])[i];
+      G(did)[pos] = G(I.id[sp])[i];
+    }
+    __syncthreads();
   }
+}
+
+__global__ void k_fill_u32(uint32_t* a, uint32_t n, uint32_t v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = v;
 }
 
 __global__ void k_set_count(Counters* ctr, int sp, const uint32_t* total) { ctr->count[sp] = *total; }
@@ -130,11 +181,13 @@ __global__ void k_set_count(Counters* ctr, int sp, const uint32_t* total) { ctr-
 template <class T>
 hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* off, const SortDst<T>& d, int grid,
                        hipStream_t s) {
-  hipMemsetAsync(off, 0, sizeof(uint32_t) * (ncell + 1u), s);
-  hipLaunchKernelGGL(k_sort_hist<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off);
+  const uint32_t chunk = (ceil_div(I.cap[sp], (uint32_t)grid) + kBlock - 1) / kBlock * kBlock;
+  hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(ncell + 1u, kBlock) < 1024 ? ceil_div(ncell + 1u, kBlock) : 1024),
+                     dim3(kBlock), 0, s, off, ncell + 1u, 0u);
+  hipLaunchKernelGGL(k_sort_hist<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk);
   hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, off, ncell);
-  hipLaunchKernelGGL(k_sort_scatter<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, d.s0, d.s1, d.v0, d.v1, d.v2, d.w,
-                     d.id, d.cell);
+  hipLaunchKernelGGL(k_sort_scatter<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk, d.s0, d.s1, d.v0, d.v1,
+                     d.v2, d.w, d.id, d.cell);
   hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, I.ctr, sp, off + ncell);
   return hipGetLastError();
 }

@@ -122,17 +122,17 @@ __device__ __forceinline__ void stage_birth(const InstDev<T>& I, bool birth, uin
     atomicOr(&I.ctr->flags, kFlagBirthOverflow);
     return;
   }
-  I.br.parent[slot] = pid;
-  I.br.cell[slot] = cell;
-  I.br.w[slot] = w;
-  I.br.s[0][slot] = s0;
-  if (I.dim == 2) I.br.s[1][slot] = s1;
-  I.br.ve[0][slot] = rec.ve0;
-  I.br.ve[1][slot] = rec.ve1;
-  I.br.ve[2][slot] = rec.ve2;
-  I.br.vi[0][slot] = rec.vi0;
-  I.br.vi[1][slot] = rec.vi1;
-  I.br.vi[2][slot] = rec.vi2;
+  G(I.br.parent)[slot] = pid;
+  G(I.br.cell)[slot] = cell;
+  G(I.br.w)[slot] = w;
+  G(I.br.s[0])[slot] = s0;
+  if (I.dim == 2) G(I.br.s[1])[slot] = s1;
+  G(I.br.ve[0])[slot] = rec.ve0;
+  G(I.br.ve[1])[slot] = rec.ve1;
+  G(I.br.ve[2])[slot] = rec.ve2;
+  G(I.br.vi[0])[slot] = rec.vi0;
+  G(I.br.vi[1])[slot] = rec.vi1;
+  G(I.br.vi[2])[slot] = rec.vi2;
 }
 
 template <class T>
@@ -147,32 +147,94 @@ struct FixedPoint<double> {
 };
 
 // ---------------------------------------------------------------------------
-// 1D: one tile of kBlock particles of species sp.
+// Deposit pre-aggregation: each workgroup owns a window of kWin consecutive
+// cells in LDS (its particles are a contiguous, cell-ordered range, so their
+// cells cluster); deposits inside the window are LDS atomics, the rest go
+// straight to global memory, and the window is flushed once per workgroup.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kWin = 2048;
+constexpr uint32_t kWinMargin = 128;
+
+__device__ __forceinline__ void win_add(unsigned long long* win, uint32_t base, unsigned long long* g, uint32_t key,
+                                        unsigned long long val) {
+  if (key == kNoKey || val == 0ull) return;
+  const uint32_t o = key - base;
+  if (o < kWin) atomicAdd(win + o, val);
+  else gadd(g + key, val);
+}
+
+__device__ __forceinline__ void win_zero(unsigned long long* win) {
+  for (uint32_t j = threadIdx.x; j < kWin; j += kBlock) win[j] = 0ull;
+}
+
+__device__ __forceinline__ void win_flush(const unsigned long long* win, uint32_t base, unsigned long long* g,
+                                          uint32_t nq) {
+  for (uint32_t j = threadIdx.x; j < kWin; j += kBlock) {
+    const unsigned long long v = win[j];
+    if (v && base + j < nq) gadd(g + base + j, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D: one particle per lane
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void tile1d(const InstDev<T>& I, int sp, uint32_t i, uint32_t limit, uint32_t step,
-                                       unsigned long long* Qpar, LStat& st) {
+__device__ __forceinline__ uint32_t cell1d(const InstDev<T>& I, T s) {
+  const T g = s * (T)I.N;
+  int ic = (int)floor(g);
+  if (ic > I.N - 1) ic = I.N - 1;
+  return (uint32_t)ic;
+}
+
+// Particle state loaded for one lane.  Loads are issued unconditionally and
+// one tile ahead (software pipelining), so the latency of the particle
+// arrays overlaps the work on the previous tile.
+template <class T>
+struct PState {
+  uint32_t w, cell;
+  T s0, s1, v0, v1;
+};
+
+template <class T, int DIM>
+__device__ __forceinline__ PState<T> load_particle(const InstDev<T>& I, int sp, uint32_t i, bool valid) {
+  PState<T> p;
+  p.w = 0u;
+  p.cell = 0u;
+  p.s0 = p.s1 = p.v0 = p.v1 = (T)0;
+  if (valid) {
+    p.w = G(I.w[sp])[i];
+    p.s0 = G(I.s[sp][0])[i];
+    p.v0 = G(I.v[sp][0])[i];
+    if (DIM == 2) {
+      p.cell = G(I.cell[sp])[i];
+      p.s1 = G(I.s[sp][1])[i];
+      p.v1 = G(I.v[sp][1])[i];
+    }
+  }
+  return p;
+}
+
+template <class T, bool MCC>
+__device__ __forceinline__ void particle1d(const InstDev<T>& I, int sp, uint32_t i, PState<T> p, uint32_t step,
+                                           unsigned long long* Qpar, unsigned long long* win, uint32_t wbase,
+                                           LStat& st) {
   const SpeciesK<T>& k = I.sk[sp];
   const int N = I.N;
   const T Nt = (T)N;
-  const bool valid = i < limit;
-  uint32_t w = valid ? I.w[sp][i] : 0u;
-  uint32_t key0 = kNoKey, key1 = kNoKey;
-  unsigned long long q0 = 0ull, q1 = 0ull;
+  uint32_t w = p.w;
   bool birth = false;
   BirthRec<T> rec;
-  T s = (T)0;
+  T s = p.s0;
   uint32_t pid = 0;
   if (w != 0u) {
     st.alive++;
-    s = I.s[sp][0][i];
-    T vx = I.v[sp][0][i];
+    T vx = p.v0;
     {
       const T g = s * Nt;
       int ic = (int)floor(g);
       if (ic > N - 1) ic = N - 1;
       const T f = g - (T)ic;
-      const T e0 = I.E[ic], e1 = I.E[ic + 1];
+      const T e0 = G(I.E)[ic], e1 = G(I.E)[ic + 1];
       const T E = e0 + f * (e1 - e0);
       vx = vx + k.qm_dt * E;
       s = s + vx * k.dt_L;
@@ -181,23 +243,23 @@ __device__ __forceinline__ void tile1d(const InstDev<T>& I, int sp, uint32_t i, 
     if (!wall_rule<T>(I.particle_bc, s, vx, lost)) {
       st.absorbed++;
       st.lost += lost ? 1u : 0u;
-      I.w[sp][i] = 0u;
+      G(I.w[sp])[i] = 0u;
       w = 0u;
     } else {
-      if (k.mcc != PIC_MCC_NONE) {
-        pid = I.id[sp][i];
+      if (MCC && k.mcc != PIC_MCC_NONE) {
+        pid = G(I.id[sp])[i];
         WordStream ws(I.key0, I.key1, pid, step);
         const uint32_t r0 = ws.next();
         const uint32_t r1 = ws.next();
         if ((r0 >> 8) < k.tcand) {
-          T vy = I.v[sp][1][i], vz = I.v[sp][2][i];
+          T vy = G(I.v[sp][1])[i], vz = G(I.v[sp][2])[i];
           birth = collide<T>(I, k, pid, step, r1, ws, vx, vy, vz, st, rec);
-          I.v[sp][1][i] = vy;
-          I.v[sp][2][i] = vz;
+          G(I.v[sp][1])[i] = vy;
+          G(I.v[sp][2])[i] = vz;
         }
       }
-      I.s[sp][0][i] = s;
-      I.v[sp][0][i] = vx;
+      G(I.s[sp][0])[i] = s;
+      G(I.v[sp][0])[i] = vx;
       // CIC shares in 64-bit fixed point
       const T g = s * Nt;
       int ic = (int)floor(g);
@@ -206,116 +268,31 @@ __device__ __forceinline__ void tile1d(const InstDev<T>& I, int sp, uint32_t i, 
       const unsigned long long r = (unsigned long long)(long long)rint(f * (T)(1ull << FixedPoint<T>::F));
       const unsigned long long one = 1ull << FixedPoint<T>::F;
       const unsigned long long mult = birth ? 2ull : 1ull;
-      key0 = (uint32_t)ic;
-      key1 = (uint32_t)ic + 1u;
-      q0 = mult * (unsigned long long)w * (one - r);
-      q1 = mult * (unsigned long long)w * r;
-      if (birth) {   // the newborn ion sits on the parent
+      unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
+      win_add(win, wbase, Qs, (uint32_t)ic, mult * (unsigned long long)w * (one - r));
+      win_add(win, wbase, Qs, (uint32_t)ic + 1u, mult * (unsigned long long)w * r);
+      if (MCC && birth) {   // the newborn ion sits on the parent
         unsigned long long* Qi = Qpar + I.nq;
-        if (one - r) atomicAdd(Qi + ic, (unsigned long long)w * (one - r));
-        if (r) atomicAdd(Qi + ic + 1, (unsigned long long)w * r);
+        if (one - r) gadd(Qi + ic, (unsigned long long)w * (one - r));
+        if (r) gadd(Qi + ic + 1, (unsigned long long)w * r);
       }
     }
   }
-  stage_birth<T>(I, birth, pid, 0u, w, s, (T)0, rec);
-  unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
-  seg_atomic_add(Qs, key0, q0);
-  seg_atomic_add(Qs, key1, q1);
-}
-
-// Per-block sum of the per-lane counters into one row of a partial-stats
-// table (plain writes, no atomics; the commit kernel adds the rows up).
-__device__ __forceinline__ void write_stats_row(unsigned long long* row, const LStat& st, int sp) {
-  __shared__ uint32_t red[kBlock / 64][7];
-  const int lane = lane_id(), wv = threadIdx.x / 64;
-  const uint32_t vals[7] = {st.alive, st.absorbed, st.elastic, st.ionization, st.cx, st.viol, st.lost};
-#pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    const uint32_t s = wave_sum(vals[q]);
-    if (lane == 0) red[wv][q] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < kNStat) {
-    uint32_t tot[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < kBlock / 64; ++w)
-      for (int q = 0; q < 7; ++q) tot[q] += red[w][q];
-    unsigned long long v = 0ull;
-    switch (threadIdx.x) {
-      case kStAlive0: v = sp == 0 ? tot[0] : 0u; break;
-      case kStAlive1: v = sp == 1 ? tot[0] : 0u; break;
-      case kStAbs0: v = sp == 0 ? tot[1] : 0u; break;
-      case kStAbs1: v = sp == 1 ? tot[1] : 0u; break;
-      case kStElastic: v = tot[2]; break;
-      case kStIonization: v = tot[3]; break;
-      case kStCx: v = tot[4]; break;
-      case kStViol0: v = sp == 0 ? tot[5] : 0u; break;
-      case kStViol1: v = sp == 1 ? tot[5] : 0u; break;
-      case kStLostReflect: v = tot[6]; break;
-      default: v = 0ull; break;
-    }
-    row[threadIdx.x] = v;
-  }
-  __syncthreads();
-}
-
-// Zero the deposit buffer of the other step parity (it held the previous
-// step's charge, already consumed by the field solve).
-__device__ __forceinline__ void zero_other_parity(unsigned long long* Q, uint32_t nq, uint32_t step, int nspecies,
-                                                  uint32_t tid, uint32_t nthreads) {
-  unsigned long long* Z = Q + (size_t)((step + 1u) & 1u) * 2u * nq;
-  const uint32_t n = (uint32_t)nspecies * nq;
-  for (uint32_t j = tid; j < n; j += nthreads) Z[j] = 0ull;
-}
-
-// Plain 1D launch: blocks [0, gs) advance species 0, [gs, grid) species 1.
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_step1d(InstDev<T> I, int gs) {
-  const int sp = (I.nspecies == 2 && (int)blockIdx.x >= gs) ? 1 : 0;
-  const int b0 = sp == 0 ? 0 : gs;
-  const int nb = sp == 0 ? (I.nspecies == 2 ? gs : (int)gridDim.x) : (int)gridDim.x - gs;
-  const uint32_t step = I.ctr->step;
-  const uint32_t count = I.ctr->count[sp];
-  unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
-  zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
-  LStat st = {0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t base = (uint32_t)((int)blockIdx.x - b0) * kBlock; base < count; base += (uint32_t)nb * kBlock)
-    tile1d<T>(I, sp, base + threadIdx.x, count, step, Qpar, st);
-  write_stats_row(I.part + (size_t)blockIdx.x * kNStat, st, sp);
-}
-
-// Batched 1D launch: a persistent grid walks a list of (instance, species,
-// range) work items; per-instance constants come from the descriptor table.
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __restrict__ insts,
-                                                           const WorkItem* __restrict__ items, uint32_t nitems,
-                                                           unsigned long long* bpart) {
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const WorkItem wi = items[it];
-    const InstDev<T>& I = insts[wi.inst];
-    const int sp = (int)wi.species;
-    const uint32_t step = I.ctr->step;
-    const uint32_t count = I.ctr->count[sp];
-    const uint32_t limit = wi.end < count ? wi.end : count;
-    unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
-    if (wi.begin == 0 && sp == 0) zero_other_parity(I.Q, I.nq, step, I.nspecies, threadIdx.x, kBlock);
-    LStat st = {0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t base = wi.begin; base < limit; base += kBlock) tile1d<T>(I, sp, base + threadIdx.x, limit, step, Qpar, st);
-    write_stats_row(bpart + (size_t)it * kNStat, st, sp);
-  }
+  if (MCC) stage_birth<T>(I, birth, pid, 0u, w, s, (T)0, rec);
 }
 
 // ---------------------------------------------------------------------------
-// 2D quadtree
+// 2D quadtree: one particle per lane
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ uint32_t locate2d(const InstDev<T>& I, uint32_t X, uint32_t Y) {
-  return locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, X, Y);
+  return locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, X, Y, I.lut_direct != 0);
 }
 
 template <class T>
 __device__ __forceinline__ void gather2d(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T& ex, T& ey) {
-  const uint32_t xy = I.leaf_xy[leaf];
-  const int lv = I.leaf_lv[leaf];
+  const uint32_t xy = G(I.leaf_xy)[leaf];
+  const int lv = G(I.leaf_lv)[leaf];
   const int sh = kKeyBits - lv;
   const T sc = (T)(1u << lv);
   const T xi = sx * sc - (T)((xy >> 16) >> sh);
@@ -324,30 +301,25 @@ __device__ __forceinline__ void gather2d(const InstDev<T>& I, uint32_t leaf, T s
   const T w10 = xi * ((T)1 - eta);
   const T w01 = ((T)1 - xi) * eta;
   const T w11 = xi * eta;
-  const T* c = I.E + (size_t)leaf * 8u;
+  const gptr<const T> c = G(I.E) + (size_t)leaf * 8u;
   ex = ((w00 * c[0] + w10 * c[2]) + w01 * c[4]) + w11 * c[6];
   ey = ((w00 * c[1] + w10 * c[3]) + w01 * c[5]) + w11 * c[7];
 }
 
-template <class T>
-__device__ __forceinline__ void tile2d(const InstDev<T>& I, int sp, uint32_t i, uint32_t limit, uint32_t step,
-                                       unsigned long long* Qpar, LStat& st) {
+template <class T, bool MCC>
+__device__ __forceinline__ void particle2d(const InstDev<T>& I, int sp, uint32_t i, PState<T> p, uint32_t step,
+                                           unsigned long long* Qpar, unsigned long long* win, uint32_t wbase,
+                                           LStat& st) {
   const SpeciesK<T>& k = I.sk[sp];
-  const bool valid = i < limit;
-  uint32_t w = valid ? I.w[sp][i] : 0u;
-  uint32_t key = kNoKey;
-  unsigned long long q = 0ull;
+  uint32_t w = p.w;
   bool birth = false;
   BirthRec<T> rec;
-  T sx = (T)0, sy = (T)0;
-  uint32_t pid = 0, leaf = 0;
+  T sx = p.s0, sy = p.s1;
+  uint32_t pid = 0, leaf = p.cell;
   if (w != 0u) {
     st.alive++;
-    leaf = I.cell[sp][i];
-    sx = I.s[sp][0][i];
-    sy = I.s[sp][1][i];
-    T vx = I.v[sp][0][i];
-    T vy = I.v[sp][1][i];
+    T vx = p.v0;
+    T vy = p.v1;
     T ex, ey;
     gather2d<T>(I, leaf, sx, sy, ex, ey);
     vx = vx + k.qm_dt * ex;
@@ -360,52 +332,156 @@ __device__ __forceinline__ void tile2d(const InstDev<T>& I, int sp, uint32_t i, 
     if (!ok) {
       st.absorbed++;
       st.lost += lost ? 1u : 0u;
-      I.w[sp][i] = 0u;
+      G(I.w[sp])[i] = 0u;
       w = 0u;
     } else {
       const uint32_t X = (uint32_t)(sx * (T)65536);
       const uint32_t Y = (uint32_t)(sy * (T)65536);
-      const uint32_t xy = I.leaf_xy[leaf];
-      const int sh = kKeyBits - (int)I.leaf_lv[leaf];
+      const uint32_t xy = G(I.leaf_xy)[leaf];
+      const int sh = kKeyBits - (int)G(I.leaf_lv)[leaf];
       if ((X >> sh) != ((xy >> 16) >> sh) || (Y >> sh) != ((xy & 0xFFFFu) >> sh)) leaf = locate2d<T>(I, X, Y);
-      if (k.mcc != PIC_MCC_NONE) {
-        pid = I.id[sp][i];
+      if (MCC && k.mcc != PIC_MCC_NONE) {
+        pid = G(I.id[sp])[i];
         WordStream ws(I.key0, I.key1, pid, step);
         const uint32_t r0 = ws.next();
         const uint32_t r1 = ws.next();
         if ((r0 >> 8) < k.tcand) {
-          T vz = I.v[sp][2][i];
+          T vz = G(I.v[sp][2])[i];
           birth = collide<T>(I, k, pid, step, r1, ws, vx, vy, vz, st, rec);
-          I.v[sp][2][i] = vz;
+          G(I.v[sp][2])[i] = vz;
         }
       }
-      I.s[sp][0][i] = sx;
-      I.s[sp][1][i] = sy;
-      I.v[sp][0][i] = vx;
-      I.v[sp][1][i] = vy;
-      I.cell[sp][i] = leaf;
-      key = leaf;
-      q = (birth ? 2ull : 1ull) * (unsigned long long)w;
-      if (birth) atomicAdd(Qpar + I.nq + leaf, (unsigned long long)w);
+      G(I.s[sp][0])[i] = sx;
+      G(I.s[sp][1])[i] = sy;
+      G(I.v[sp][0])[i] = vx;
+      G(I.v[sp][1])[i] = vy;
+      if (leaf != p.cell) G(I.cell[sp])[i] = leaf;
+      win_add(win, wbase, Qpar + (size_t)sp * I.nq, leaf, (birth ? 2ull : 1ull) * (unsigned long long)w);
+      if (MCC && birth) gadd(Qpar + I.nq + leaf, (unsigned long long)w);
     }
   }
-  stage_birth<T>(I, birth, pid, leaf, w, sx, sy, rec);
-  seg_atomic_add(Qpar + (size_t)sp * I.nq, key, q);
+  if (MCC) stage_birth<T>(I, birth, pid, leaf, w, sx, sy, rec);
 }
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_step2d(InstDev<T> I, int gs) {
+// Per-workgroup counters are added into the workgroup's own row of a
+// partial-stats table (no atomics); the rows are summed once per pic_step call.
+__device__ __forceinline__ void add_stats_row(unsigned long long* row, const LStat& st, int sp) {
+  __shared__ uint32_t red[kBlock / 64][7];
+  const int lane = lane_id(), wv = threadIdx.x / 64;
+  const uint32_t vals[7] = {st.alive, st.absorbed, st.elastic, st.ionization, st.cx, st.viol, st.lost};
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const uint32_t s = wave_sum(vals[q]);
+    if (lane == 0) red[wv][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) tot += red[w][threadIdx.x];
+    if (tot) {
+      int idx;
+      switch (threadIdx.x) {
+        case 0: idx = kStAlive0 + sp; break;
+        case 1: idx = kStAbs0 + sp; break;
+        case 2: idx = kStElastic; break;
+        case 3: idx = kStIonization; break;
+        case 4: idx = kStCx; break;
+        case 5: idx = kStViol0 + sp; break;
+        default: idx = kStLostReflect; break;
+      }
+      row[idx] += tot;
+    }
+  }
+}
+
+// Zero the deposit buffer of the other step parity (it held the previous
+// step's charge, already consumed by the field solve).
+__device__ __forceinline__ void zero_other_parity(unsigned long long* Q, uint32_t nq, uint32_t step, int nspecies,
+                                                  uint32_t tid, uint32_t nthreads) {
+  unsigned long long* Z = Q + (size_t)((step + 1u) & 1u) * 2u * nq;
+  const uint32_t n = (uint32_t)nspecies * nq;
+  for (uint32_t j = tid; j < n; j += nthreads) Z[j] = 0ull;
+}
+
+// Last workgroup to finish advances the step index (used when no births
+// kernel or field solve follows in the same step).  No fence is needed: the
+// step index is read only by later launches, and no workgroup of this launch
+// reads what the others wrote.
+__device__ __forceinline__ void last_block_commit(Counters* c, uint32_t step) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = gadd32(&c->done, 1u);
+    if (prev == gridDim.x - 1u) {
+      c->done = 0u;
+      c->step = step + 1u;
+    }
+  }
+}
+
+template <class T, bool MCC, int DIM>
+__device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end, uint32_t step,
+                                          unsigned long long* Qpar, unsigned long long* row) {
+  __shared__ unsigned long long win[kWin];
+  __shared__ uint32_t wbase_s;
+  win_zero(win);
+  if (threadIdx.x == 0) {
+    uint32_t c0 = 0;
+    if (begin < end) c0 = DIM == 2 ? G(I.cell[sp])[begin] : cell1d<T>(I, G(I.s[sp][0])[begin]);
+    wbase_s = c0 > kWinMargin ? c0 - kWinMargin : 0u;
+  }
+  __syncthreads();
+  const uint32_t wbase = wbase_s;
+  LStat st = {0, 0, 0, 0, 0, 0, 0};
+  uint32_t i = begin + threadIdx.x;
+  PState<T> cur = load_particle<T, DIM>(I, sp, i, i < end);
+  for (uint32_t base = begin; base < end; base += kBlock) {
+    const uint32_t inext = i + kBlock;
+    const PState<T> nxt = load_particle<T, DIM>(I, sp, inext, inext < end);
+    if (DIM == 2) particle2d<T, MCC>(I, sp, i, cur, step, Qpar, win, wbase, st);
+    else particle1d<T, MCC>(I, sp, i, cur, step, Qpar, win, wbase, st);
+    cur = nxt;
+    i = inext;
+  }
+  __syncthreads();
+  win_flush(win, wbase, Qpar + (size_t)sp * I.nq, I.nq);
+  add_stats_row(row, st, sp);
+  __syncthreads();
+}
+
+// Plain launch over one instance: workgroups [0, gs) own consecutive chunks
+// of species 0, [gs, grid) of species 1.
+template <class T, bool MCC, int DIM>
+__global__ __launch_bounds__(kBlock) void k_step(InstDev<T> I, int gs, uint32_t chunk0, uint32_t chunk1, int commit) {
   const int sp = (I.nspecies == 2 && (int)blockIdx.x >= gs) ? 1 : 0;
-  const int b0 = sp == 0 ? 0 : gs;
-  const int nb = sp == 0 ? (I.nspecies == 2 ? gs : (int)gridDim.x) : (int)gridDim.x - gs;
+  const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - (uint32_t)gs;
+  const uint32_t chunk = sp == 0 ? chunk0 : chunk1;
   const uint32_t step = I.ctr->step;
   const uint32_t count = I.ctr->count[sp];
   unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
   zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
-  LStat st = {0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t base = (uint32_t)((int)blockIdx.x - b0) * kBlock; base < count; base += (uint32_t)nb * kBlock)
-    tile2d<T>(I, sp, base + threadIdx.x, count, step, Qpar, st);
-  write_stats_row(I.part + (size_t)blockIdx.x * kNStat, st, sp);
+  const uint32_t begin = b * chunk;
+  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  run_range<T, MCC, DIM>(I, sp, begin, end, step, Qpar, I.part + (size_t)blockIdx.x * kNStat);
+  if (commit) last_block_commit(I.ctr, step);
+}
+
+// Batched 1D launch: a persistent grid walks a list of (instance, species,
+// range) work items; per-instance constants come from the descriptor table.
+template <class T, bool MCC>
+__global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __restrict__ insts,
+                                                           const WorkItem* __restrict__ items, uint32_t nitems,
+                                                           unsigned long long* bpart) {
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const InstDev<T>& I = insts[wi.inst];
+    const int sp = (int)wi.species;
+    const uint32_t step = I.ctr->step;
+    const uint32_t count = I.ctr->count[sp];
+    const uint32_t end = wi.end < count ? wi.end : count;
+    unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
+    if (wi.begin == 0 && sp == 0) zero_other_parity(I.Q, I.nq, step, I.nspecies, threadIdx.x, kBlock);
+    run_range<T, MCC, 1>(I, sp, wi.begin, end, step, Qpar, bpart + (size_t)it * kNStat);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -468,20 +544,12 @@ __global__ __launch_bounds__(kBlock) void k_births_batched(const InstDev<T>* ins
   births_body<T>(insts[blockIdx.x], 0u, 1u);
 }
 
-// Commit a step: sum the partial-stats rows, append births to the counts,
-// advance the step index.  One block.
+// Commit a step after the births kernel: append births to the counts,
+// advance the step index.  One thread.
 template <class T>
-__device__ void commit_body(const InstDev<T>& I, const unsigned long long* rows, uint32_t nrows) {
-  __shared__ unsigned long long acc[kNStat];
-  if (threadIdx.x < kNStat) acc[threadIdx.x] = 0ull;
-  __syncthreads();
-  for (uint32_t r = threadIdx.x / kNStat; r < nrows; r += kBlock / kNStat) {
-    if (threadIdx.x < (kBlock / kNStat) * kNStat) atomicAdd(&acc[threadIdx.x % kNStat], rows[(size_t)r * kNStat + threadIdx.x % kNStat]);
-  }
-  __syncthreads();
+__device__ void commit_body(const InstDev<T>& I) {
   if (threadIdx.x == 0) {
     Counters* c = I.ctr;
-    for (int q = 0; q < kNStat; ++q) c->stats[q] += acc[q];
     const uint32_t nb = c->nbirths;
     if (nb && !(c->flags & (kFlagBirthOverflow | kFlagIdOverflow))) {
       c->count[0] += nb;
@@ -495,7 +563,43 @@ __device__ void commit_body(const InstDev<T>& I, const unsigned long long* rows,
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_commit(InstDev<T> I, uint32_t nrows) { commit_body<T>(I, I.part, nrows); }
+__global__ void k_commit(InstDev<T> I) { commit_body<T>(I); }
+
+template <class T>
+__global__ void k_commit_batched(const InstDev<T>* insts) { commit_body<T>(insts[blockIdx.x]); }
+
+// Sum partial-stats rows [row_begin[b], row_begin[b+1]) into instance b's
+// counters and clear them.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_stats_reduce(const InstDev<T>* insts, unsigned long long* rows,
+                                                         const uint32_t* row_begin, uint32_t nrows_plain) {
+  const InstDev<T>& I = insts[blockIdx.x];
+  const uint32_t rb = row_begin ? row_begin[blockIdx.x] : 0u;
+  const uint32_t re = row_begin ? row_begin[blockIdx.x + 1] : nrows_plain;
+  unsigned long long* R = rows ? rows : I.part;
+  __shared__ unsigned long long acc[kBlock / 64][kNStat];
+  unsigned long long loc[kNStat];
+#pragma unroll
+  for (int q = 0; q < kNStat; ++q) loc[q] = 0ull;
+  for (uint32_t r = rb + threadIdx.x; r < re; r += kBlock) {
+#pragma unroll
+    for (int q = 0; q < kNStat; ++q) {
+      loc[q] += R[(size_t)r * kNStat + q];
+      R[(size_t)r * kNStat + q] = 0ull;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kNStat; ++q) {
+    const unsigned long long s = wave_sum(loc[q]);
+    if (lane_id() == 0) acc[threadIdx.x / 64][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNStat) {
+    unsigned long long t = 0ull;
+    for (int w = 0; w < kBlock / 64; ++w) t += acc[w][threadIdx.x];
+    I.ctr->stats[threadIdx.x] += t;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Standalone deposit of the current particles into the latest buffer
@@ -509,12 +613,12 @@ __global__ __launch_bounds__(kBlock) void k_deposit(InstDev<T> I) {
     const uint32_t count = I.ctr->count[sp];
     for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
       const uint32_t i = base + threadIdx.x;
-      const uint32_t w = i < count ? I.w[sp][i] : 0u;
+      const uint32_t w = i < count ? G(I.w[sp])[i] : 0u;
       uint32_t k0 = kNoKey, k1 = kNoKey;
       unsigned long long q0 = 0ull, q1 = 0ull;
       if (w) {
         if (I.dim == 1) {
-          const T g = I.s[sp][0][i] * (T)I.N;
+          const T g = G(I.s[sp][0])[i] * (T)I.N;
           int ic = (int)floor(g);
           if (ic > I.N - 1) ic = I.N - 1;
           const T f = g - (T)ic;
@@ -525,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(InstDev<T> I) {
           q0 = (unsigned long long)w * (one - r);
           q1 = (unsigned long long)w * r;
         } else {
-          k0 = I.cell[sp][i];
+          k0 = G(I.cell[sp])[i];
           q0 = w;
         }
       }
@@ -542,19 +646,19 @@ __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
     const uint32_t count = I.ctr->count[sp];
     const T h = I.sk[sp].hqm_dt;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
-      if (!I.w[sp][i]) continue;
+      if (!G(I.w[sp])[i]) continue;
       if (I.dim == 1) {
-        const T g = I.s[sp][0][i] * (T)I.N;
+        const T g = G(I.s[sp][0])[i] * (T)I.N;
         int ic = (int)floor(g);
         if (ic > I.N - 1) ic = I.N - 1;
         const T f = g - (T)ic;
-        const T E = I.E[ic] + f * (I.E[ic + 1] - I.E[ic]);
-        I.v[sp][0][i] = I.v[sp][0][i] - h * E;
+        const T E = G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]);
+        G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * E;
       } else {
         T ex, ey;
-        gather2d<T>(I, I.cell[sp][i], I.s[sp][0][i], I.s[sp][1][i], ex, ey);
-        I.v[sp][0][i] = I.v[sp][0][i] - h * ex;
-        I.v[sp][1][i] = I.v[sp][1][i] - h * ey;
+        gather2d<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], ex, ey);
+        G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * ex;
+        G(I.v[sp][1])[i] = G(I.v[sp][1])[i] - h * ey;
       }
     }
   }
@@ -565,10 +669,10 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_relocate(InstDev<T> I, int sp) {
   const uint32_t count = I.ctr->count[sp];
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
-    if (!I.w[sp][i]) continue;
-    const uint32_t X = (uint32_t)(I.s[sp][0][i] * (T)65536);
-    const uint32_t Y = (uint32_t)(I.s[sp][1][i] * (T)65536);
-    I.cell[sp][i] = locate2d<T>(I, X, Y);
+    if (!G(I.w[sp])[i]) continue;
+    const uint32_t X = (uint32_t)(G(I.s[sp][0])[i] * (T)65536);
+    const uint32_t Y = (uint32_t)(G(I.s[sp][1])[i] * (T)65536);
+    G(I.cell[sp])[i] = locate2d<T>(I, X, Y);
   }
 }
 
@@ -584,19 +688,27 @@ static int species_split(const InstDev<T>& I, int grid) {
 }
 
 template <class T>
-hipError_t launch_step1d(const InstDev<T>& I, hipStream_t s, int grid) {
-  hipLaunchKernelGGL(k_step1d<T>, dim3(grid), dim3(kBlock), 0, s, I, species_split(I, grid));
-  return hipGetLastError();
-}
-template <class T>
-hipError_t launch_step2d(const InstDev<T>& I, hipStream_t s, int grid) {
-  hipLaunchKernelGGL(k_step2d<T>, dim3(grid), dim3(kBlock), 0, s, I, species_split(I, grid));
+hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit) {
+  const int gs = species_split(I, grid);
+  const int g0 = gs, g1 = I.nspecies == 2 ? grid - gs : 1;
+  uint32_t c0 = (ceil_div(I.cap[0], (uint32_t)g0) + kBlock - 1) / kBlock * kBlock;
+  uint32_t c1 = (ceil_div(I.cap[1] ? I.cap[1] : 1u, (uint32_t)g1) + kBlock - 1) / kBlock * kBlock;
+  if (c0 < kBlock) c0 = kBlock;
+  if (c1 < kBlock) c1 = kBlock;
+  if (I.dim == 1) {
+    if (mcc) hipLaunchKernelGGL((k_step<T, true, 1>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
+    else hipLaunchKernelGGL((k_step<T, false, 1>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
+  } else {
+    if (mcc) hipLaunchKernelGGL((k_step<T, true, 2>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
+    else hipLaunchKernelGGL((k_step<T, false, 2>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
+  }
   return hipGetLastError();
 }
 template <class T>
 hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
-                                 unsigned long long* bpart, hipStream_t s, int grid) {
-  hipLaunchKernelGGL(k_step1d_batched<T>, dim3(grid), dim3(kBlock), 0, s, I, items, nitems, bpart);
+                                 unsigned long long* bpart, hipStream_t s, int grid, bool mcc) {
+  if (mcc) hipLaunchKernelGGL((k_step1d_batched<T, true>), dim3(grid), dim3(kBlock), 0, s, I, items, nitems, bpart);
+  else hipLaunchKernelGGL((k_step1d_batched<T, false>), dim3(grid), dim3(kBlock), 0, s, I, items, nitems, bpart);
   return hipGetLastError();
 }
 template <class T>
@@ -610,8 +722,19 @@ hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s) 
   return hipGetLastError();
 }
 template <class T>
-hipError_t launch_commit(const InstDev<T>& I, uint32_t nrows, hipStream_t s) {
-  hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(kBlock), 0, s, I, nrows);
+hipError_t launch_commit(const InstDev<T>& I, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(64), 0, s, I);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t launch_commit_batched(const InstDev<T>* I, int ninst, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit_batched<T>, dim3(ninst), dim3(64), 0, s, I);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long long* rows, const uint32_t* row_begin,
+                               uint32_t nrows_plain, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reduce<T>, dim3(ninst), dim3(kBlock), 0, s, I, rows, row_begin, nrows_plain);
   return hipGetLastError();
 }
 template <class T>
@@ -631,35 +754,19 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
 }
 
 #define PIC_INSTANTIATE(T)                                                                                 \
-  template hipError_t launch_step1d<T>(const InstDev<T>&, hipStream_t, int);                               \
-  template hipError_t launch_step2d<T>(const InstDev<T>&, hipStream_t, int);                               \
+  template hipError_t launch_step<T>(const InstDev<T>&, hipStream_t, int, bool, int);                      \
   template hipError_t launch_step1d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
-                                               unsigned long long*, hipStream_t, int);                     \
+                                               unsigned long long*, hipStream_t, int, bool);               \
   template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, int);                               \
   template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
-  template hipError_t launch_commit<T>(const InstDev<T>&, uint32_t, hipStream_t);                          \
+  template hipError_t launch_commit<T>(const InstDev<T>&, hipStream_t);                                    \
+  template hipError_t launch_commit_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
+  template hipError_t launch_stats_reduce<T>(const InstDev<T>*, int, unsigned long long*, const uint32_t*, \
+                                             uint32_t, hipStream_t);                                       \
   template hipError_t launch_deposit<T>(const InstDev<T>&, hipStream_t, int);                              \
   template hipError_t launch_leapfrog_start<T>(const InstDev<T>&, hipStream_t, int);                       \
   template hipError_t launch_relocate<T>(const InstDev<T>&, int, hipStream_t, int);
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)
-
-// commit entry for the batched 1D path without a field solve (one block per slot)
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_commit_batched(const InstDev<T>* insts, const unsigned long long* bpart,
-                                                           const uint32_t* item_begin) {
-  const uint32_t b = item_begin[blockIdx.x], e = item_begin[blockIdx.x + 1];
-  commit_body<T>(insts[blockIdx.x], bpart + (size_t)b * kNStat, e - b);
-}
-template <class T>
-hipError_t launch_commit_batched(const InstDev<T>* I, const unsigned long long* bpart, const uint32_t* item_begin,
-                                 int ninst, hipStream_t s) {
-  hipLaunchKernelGGL(k_commit_batched<T>, dim3(ninst), dim3(kBlock), 0, s, I, bpart, item_begin);
-  return hipGetLastError();
-}
-template hipError_t launch_commit_batched<float>(const InstDev<float>*, const unsigned long long*, const uint32_t*,
-                                                 int, hipStream_t);
-template hipError_t launch_commit_batched<double>(const InstDev<double>*, const unsigned long long*, const uint32_t*,
-                                                  int, hipStream_t);
 
 }  // namespace pic

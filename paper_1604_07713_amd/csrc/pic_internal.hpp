@@ -22,7 +22,7 @@ struct Counters {
   uint32_t flags;        // kFlag* bits
   uint32_t step;         // global index of the next step
   uint32_t vstep0;       // step index of v_table[0]
-  uint32_t pad;
+  uint32_t done;         // workgroups finished in the current launch
   unsigned long long stats[12];
 };
 enum : uint32_t { kFlagBirthOverflow = 1u, kFlagIdOverflow = 2u, kFlagSplitOverflow = 4u };
@@ -67,6 +67,7 @@ struct InstDev {
   const uint8_t* leaf_lv;
   const uint32_t* lut;           // leaf containing each level-lut_level cell's low corner
   int lut_level;
+  int lut_direct;                // no leaf finer than lut_level
   uint32_t nleaves;
   unsigned long long* Q;         // [2 parity][2 species][nq]
   uint32_t nq;
@@ -92,15 +93,17 @@ struct WorkItem {
 };
 
 // ---- launchers (k_step.hip) ----
-template <class T> hipError_t launch_step1d(const InstDev<T>& I, hipStream_t s, int grid);
-template <class T> hipError_t launch_step2d(const InstDev<T>& I, hipStream_t s, int grid);
+// commit != 0: the last workgroup advances the step index (no births kernel
+// or field solve follows in this step).
+template <class T> hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit);
 template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
-                                                    unsigned long long* bpart, hipStream_t s, int grid);
+                                                    unsigned long long* bpart, hipStream_t s, int grid, bool mcc);
 template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid);
 template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s);
-template <class T> hipError_t launch_commit(const InstDev<T>& I, uint32_t nrows, hipStream_t s);
-template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, const unsigned long long* bpart,
-                                                    const uint32_t* item_begin, int ninst, hipStream_t s);
+template <class T> hipError_t launch_commit(const InstDev<T>& I, hipStream_t s);
+template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, int ninst, hipStream_t s);
+template <class T> hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long long* rows,
+                                                  const uint32_t* row_begin, uint32_t nrows_plain, hipStream_t s);
 template <class T> hipError_t launch_deposit(const InstDev<T>& I, hipStream_t s, int grid);
 template <class T> hipError_t launch_leapfrog_start(const InstDev<T>& I, hipStream_t s, int grid);
 template <class T> hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int grid);
@@ -110,8 +113,7 @@ template <class T> hipError_t launch_relocate(const InstDev<T>& I, int species, 
 // mode 1: after a step: solve from this step's deposit with phi(0) from the
 //         drive table, then commit the step (rows: partial-stats rows).
 template <class T> hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mode,
-                                             const double* phi_left, const unsigned long long* rows,
-                                             const uint32_t* row_begin, hipStream_t s);
+                                             const double* phi_left, hipStream_t s);
 template <class T> hipError_t launch_node_e_1d(const InstDev<T>& I, const double* data, int is_phi, hipStream_t s);
 struct Mesh2D {
   const uint32_t* key;
