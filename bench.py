@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=4194304)
-    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-every", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--copy-probe", type=int, default=0,

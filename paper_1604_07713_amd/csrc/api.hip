@@ -368,6 +368,9 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
 // particle buffers
 // ---------------------------------------------------------------------------
 void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
+  // kernels address each particle array with 32-bit byte offsets
+  if ((uint64_t)cap * sl.esz >= (1ull << 32) || cap > 0x7FFFFFFF)
+    throw Err(PIC_E_CAPACITY, "particle capacity exceeds the per-array limit of 4 GiB");
   PBuf& b = sl.pb[sp][which];
   if (b.base) sl.release(b.base);
   const size_t e = sl.esz;

@@ -26,6 +26,24 @@ template <class T>
 __device__ __forceinline__ gptr<T> G(T* p) { return (gptr<T>)p; }
 template <class T>
 __device__ __forceinline__ gptr<const T> G(const T* p) { return (gptr<const T>)p; }
+// Wave-uniform copy of a pointer (forces it into scalar registers).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t a = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+// Element i of a global array addressed with a 32-bit byte offset (arrays are
+// kept below 4 GiB), so loads and stores use scalar-base + vector-offset form.
+template <class T>
+__device__ __forceinline__ gptr<T> at(T* base, uint32_t i) {
+  return (gptr<T>)((gptr<char>)base + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ gptr<const T> at(const T* base, uint32_t i) {
+  return (gptr<const T>)((gptr<const char>)base + i * (uint32_t)sizeof(T));
+}
 __device__ __forceinline__ void gadd(unsigned long long* p, unsigned long long v) {
   __hip_atomic_fetch_add((gptr<unsigned long long>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

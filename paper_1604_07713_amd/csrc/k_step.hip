@@ -152,26 +152,53 @@ struct FixedPoint<double> {
 // cells cluster); deposits inside the window are LDS atomics, the rest go
 // straight to global memory, and the window is flushed once per workgroup.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kWin = 2048;
+constexpr uint32_t kWin = 1024;
 constexpr uint32_t kWinMargin = 128;
+constexpr uint32_t kHash = 512;      // open-addressed LDS table for cells outside the window
+constexpr uint32_t kHashProbe = 8;
 
-__device__ __forceinline__ void win_add(unsigned long long* win, uint32_t base, unsigned long long* g, uint32_t key,
-                                        unsigned long long val) {
+struct DepCache {
+  unsigned long long* win;     // [kWin]
+  uint32_t* hkey;              // [kHash], kNoKey = empty
+  unsigned long long* hval;    // [kHash]
+  uint32_t base;
+};
+
+__device__ __forceinline__ void dep_add(DepCache& D, unsigned long long* g, uint32_t key, unsigned long long val) {
   if (key == kNoKey || val == 0ull) return;
-  const uint32_t o = key - base;
-  if (o < kWin) atomicAdd(win + o, val);
-  else gadd(g + key, val);
+  const uint32_t o = key - D.base;
+  if (o < kWin) {
+    atomicAdd(D.win + o, val);
+    return;
+  }
+  uint32_t h = (key * 2654435761u) >> 23;   // 9 bits
+  for (uint32_t p = 0; p < kHashProbe; ++p) {
+    const uint32_t slot = (h + p) & (kHash - 1u);
+    const uint32_t k = atomicCAS(D.hkey + slot, kNoKey, key);
+    if (k == kNoKey || k == key) {
+      atomicAdd(D.hval + slot, val);
+      return;
+    }
+  }
+  gadd(g + key, val);
 }
 
-__device__ __forceinline__ void win_zero(unsigned long long* win) {
-  for (uint32_t j = threadIdx.x; j < kWin; j += kBlock) win[j] = 0ull;
+__device__ __forceinline__ void dep_zero(DepCache& D) {
+  for (uint32_t j = threadIdx.x; j < kWin; j += kBlock) D.win[j] = 0ull;
+  for (uint32_t j = threadIdx.x; j < kHash; j += kBlock) {
+    D.hkey[j] = kNoKey;
+    D.hval[j] = 0ull;
+  }
 }
 
-__device__ __forceinline__ void win_flush(const unsigned long long* win, uint32_t base, unsigned long long* g,
-                                          uint32_t nq) {
+__device__ __forceinline__ void dep_flush(const DepCache& D, unsigned long long* g, uint32_t nq) {
   for (uint32_t j = threadIdx.x; j < kWin; j += kBlock) {
-    const unsigned long long v = win[j];
-    if (v && base + j < nq) gadd(g + base + j, v);
+    const unsigned long long v = D.win[j];
+    if (v && D.base + j < nq) gadd(g + D.base + j, v);
+  }
+  for (uint32_t j = threadIdx.x; j < kHash; j += kBlock) {
+    const uint32_t k = D.hkey[j];
+    if (k != kNoKey && D.hval[j]) gadd(g + k, D.hval[j]);
   }
 }
 
@@ -186,6 +213,26 @@ __device__ __forceinline__ uint32_t cell1d(const InstDev<T>& I, T s) {
   return (uint32_t)ic;
 }
 
+// Wave-uniform pointers of one species' arrays.
+template <class T>
+struct SpPtr {
+  T *s0, *s1, *v0, *v1, *v2;
+  uint32_t *w, *id, *cell;
+};
+template <class T>
+__device__ __forceinline__ SpPtr<T> species_ptrs(const InstDev<T>& I, int sp) {
+  SpPtr<T> p;
+  p.s0 = uniform_ptr(I.s[sp][0]);
+  p.s1 = uniform_ptr(I.s[sp][1]);
+  p.v0 = uniform_ptr(I.v[sp][0]);
+  p.v1 = uniform_ptr(I.v[sp][1]);
+  p.v2 = uniform_ptr(I.v[sp][2]);
+  p.w = uniform_ptr(I.w[sp]);
+  p.id = uniform_ptr(I.id[sp]);
+  p.cell = uniform_ptr(I.cell[sp]);
+  return p;
+}
+
 // Particle state loaded for one lane.  Loads are issued unconditionally and
 // one tile ahead (software pipelining), so the latency of the particle
 // arrays overlaps the work on the previous tile.
@@ -196,27 +243,28 @@ struct PState {
 };
 
 template <class T, int DIM>
-__device__ __forceinline__ PState<T> load_particle(const InstDev<T>& I, int sp, uint32_t i, bool valid) {
+__device__ __forceinline__ PState<T> load_particle(const SpPtr<T>& P, uint32_t i, bool valid) {
   PState<T> p;
   p.w = 0u;
   p.cell = 0u;
   p.s0 = p.s1 = p.v0 = p.v1 = (T)0;
   if (valid) {
-    p.w = G(I.w[sp])[i];
-    p.s0 = G(I.s[sp][0])[i];
-    p.v0 = G(I.v[sp][0])[i];
+    p.w = *at(P.w, i);
+    p.s0 = *at(P.s0, i);
+    p.v0 = *at(P.v0, i);
     if (DIM == 2) {
-      p.cell = G(I.cell[sp])[i];
-      p.s1 = G(I.s[sp][1])[i];
-      p.v1 = G(I.v[sp][1])[i];
+      p.cell = *at(P.cell, i);
+      p.s1 = *at(P.s1, i);
+      p.v1 = *at(P.v1, i);
     }
   }
   return p;
 }
 
 template <class T, bool MCC>
-__device__ __forceinline__ void particle1d(const InstDev<T>& I, int sp, uint32_t i, PState<T> p, uint32_t step,
-                                           unsigned long long* Qpar, unsigned long long* win, uint32_t wbase,
+__device__ __forceinline__ void particle1d(const InstDev<T>& I, const SpPtr<T>& P, int sp, uint32_t i, PState<T> p,
+                                           uint32_t step,
+                                           unsigned long long* Qpar, DepCache& D,
                                            LStat& st) {
   const SpeciesK<T>& k = I.sk[sp];
   const int N = I.N;
@@ -234,7 +282,7 @@ __device__ __forceinline__ void particle1d(const InstDev<T>& I, int sp, uint32_t
       int ic = (int)floor(g);
       if (ic > N - 1) ic = N - 1;
       const T f = g - (T)ic;
-      const T e0 = G(I.E)[ic], e1 = G(I.E)[ic + 1];
+      const T e0 = *at(I.E, (uint32_t)ic), e1 = *at(I.E, (uint32_t)ic + 1u);
       const T E = e0 + f * (e1 - e0);
       vx = vx + k.qm_dt * E;
       s = s + vx * k.dt_L;
@@ -243,23 +291,23 @@ __device__ __forceinline__ void particle1d(const InstDev<T>& I, int sp, uint32_t
     if (!wall_rule<T>(I.particle_bc, s, vx, lost)) {
       st.absorbed++;
       st.lost += lost ? 1u : 0u;
-      G(I.w[sp])[i] = 0u;
+      *at(P.w, i) = 0u;
       w = 0u;
     } else {
       if (MCC && k.mcc != PIC_MCC_NONE) {
-        pid = G(I.id[sp])[i];
+        pid = *at(P.id, i);
         WordStream ws(I.key0, I.key1, pid, step);
         const uint32_t r0 = ws.next();
         const uint32_t r1 = ws.next();
         if ((r0 >> 8) < k.tcand) {
-          T vy = G(I.v[sp][1])[i], vz = G(I.v[sp][2])[i];
+          T vy = *at(P.v1, i), vz = *at(P.v2, i);
           birth = collide<T>(I, k, pid, step, r1, ws, vx, vy, vz, st, rec);
-          G(I.v[sp][1])[i] = vy;
-          G(I.v[sp][2])[i] = vz;
+          *at(P.v1, i) = vy;
+          *at(P.v2, i) = vz;
         }
       }
-      G(I.s[sp][0])[i] = s;
-      G(I.v[sp][0])[i] = vx;
+      *at(P.s0, i) = s;
+      *at(P.v0, i) = vx;
       // CIC shares in 64-bit fixed point
       const T g = s * Nt;
       int ic = (int)floor(g);
@@ -269,8 +317,8 @@ __device__ __forceinline__ void particle1d(const InstDev<T>& I, int sp, uint32_t
       const unsigned long long one = 1ull << FixedPoint<T>::F;
       const unsigned long long mult = birth ? 2ull : 1ull;
       unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
-      win_add(win, wbase, Qs, (uint32_t)ic, mult * (unsigned long long)w * (one - r));
-      win_add(win, wbase, Qs, (uint32_t)ic + 1u, mult * (unsigned long long)w * r);
+      dep_add(D, Qs, (uint32_t)ic, mult * (unsigned long long)w * (one - r));
+      dep_add(D, Qs, (uint32_t)ic + 1u, mult * (unsigned long long)w * r);
       if (MCC && birth) {   // the newborn ion sits on the parent
         unsigned long long* Qi = Qpar + I.nq;
         if (one - r) gadd(Qi + ic, (unsigned long long)w * (one - r));
@@ -291,8 +339,8 @@ __device__ __forceinline__ uint32_t locate2d(const InstDev<T>& I, uint32_t X, ui
 
 template <class T>
 __device__ __forceinline__ void gather2d(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T& ex, T& ey) {
-  const uint32_t xy = G(I.leaf_xy)[leaf];
-  const int lv = G(I.leaf_lv)[leaf];
+  const uint32_t xy = *at(I.leaf_xy, leaf);
+  const int lv = *at(I.leaf_lv, leaf);
   const int sh = kKeyBits - lv;
   const T sc = (T)(1u << lv);
   const T xi = sx * sc - (T)((xy >> 16) >> sh);
@@ -301,14 +349,15 @@ __device__ __forceinline__ void gather2d(const InstDev<T>& I, uint32_t leaf, T s
   const T w10 = xi * ((T)1 - eta);
   const T w01 = ((T)1 - xi) * eta;
   const T w11 = xi * eta;
-  const gptr<const T> c = G(I.E) + (size_t)leaf * 8u;
+  const gptr<const T> c = at(I.E, leaf * 8u);
   ex = ((w00 * c[0] + w10 * c[2]) + w01 * c[4]) + w11 * c[6];
   ey = ((w00 * c[1] + w10 * c[3]) + w01 * c[5]) + w11 * c[7];
 }
 
 template <class T, bool MCC>
-__device__ __forceinline__ void particle2d(const InstDev<T>& I, int sp, uint32_t i, PState<T> p, uint32_t step,
-                                           unsigned long long* Qpar, unsigned long long* win, uint32_t wbase,
+__device__ __forceinline__ void particle2d(const InstDev<T>& I, const SpPtr<T>& P, int sp, uint32_t i, PState<T> p,
+                                           uint32_t step,
+                                           unsigned long long* Qpar, DepCache& D,
                                            LStat& st) {
   const SpeciesK<T>& k = I.sk[sp];
   uint32_t w = p.w;
@@ -332,31 +381,31 @@ __device__ __forceinline__ void particle2d(const InstDev<T>& I, int sp, uint32_t
     if (!ok) {
       st.absorbed++;
       st.lost += lost ? 1u : 0u;
-      G(I.w[sp])[i] = 0u;
+      *at(P.w, i) = 0u;
       w = 0u;
     } else {
       const uint32_t X = (uint32_t)(sx * (T)65536);
       const uint32_t Y = (uint32_t)(sy * (T)65536);
-      const uint32_t xy = G(I.leaf_xy)[leaf];
-      const int sh = kKeyBits - (int)G(I.leaf_lv)[leaf];
+      const uint32_t xy = *at(I.leaf_xy, leaf);
+      const int sh = kKeyBits - (int)*at(I.leaf_lv, leaf);
       if ((X >> sh) != ((xy >> 16) >> sh) || (Y >> sh) != ((xy & 0xFFFFu) >> sh)) leaf = locate2d<T>(I, X, Y);
       if (MCC && k.mcc != PIC_MCC_NONE) {
-        pid = G(I.id[sp])[i];
+        pid = *at(P.id, i);
         WordStream ws(I.key0, I.key1, pid, step);
         const uint32_t r0 = ws.next();
         const uint32_t r1 = ws.next();
         if ((r0 >> 8) < k.tcand) {
-          T vz = G(I.v[sp][2])[i];
+          T vz = *at(P.v2, i);
           birth = collide<T>(I, k, pid, step, r1, ws, vx, vy, vz, st, rec);
-          G(I.v[sp][2])[i] = vz;
+          *at(P.v2, i) = vz;
         }
       }
-      G(I.s[sp][0])[i] = sx;
-      G(I.s[sp][1])[i] = sy;
-      G(I.v[sp][0])[i] = vx;
-      G(I.v[sp][1])[i] = vy;
-      if (leaf != p.cell) G(I.cell[sp])[i] = leaf;
-      win_add(win, wbase, Qpar + (size_t)sp * I.nq, leaf, (birth ? 2ull : 1ull) * (unsigned long long)w);
+      *at(P.s0, i) = sx;
+      *at(P.s1, i) = sy;
+      *at(P.v0, i) = vx;
+      *at(P.v1, i) = vy;
+      if (leaf != p.cell) *at(P.cell, i) = leaf;
+      dep_add(D, Qpar + (size_t)sp * I.nq, leaf, (birth ? 2ull : 1ull) * (unsigned long long)w);
       if (MCC && birth) gadd(Qpar + I.nq + leaf, (unsigned long long)w);
     }
   }
@@ -422,28 +471,32 @@ template <class T, bool MCC, int DIM>
 __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end, uint32_t step,
                                           unsigned long long* Qpar, unsigned long long* row) {
   __shared__ unsigned long long win[kWin];
+  __shared__ uint32_t hkey[kHash];
+  __shared__ unsigned long long hval[kHash];
   __shared__ uint32_t wbase_s;
-  win_zero(win);
+  const SpPtr<T> P = species_ptrs<T>(I, sp);
+  DepCache D{win, hkey, hval, 0u};
+  dep_zero(D);
   if (threadIdx.x == 0) {
     uint32_t c0 = 0;
-    if (begin < end) c0 = DIM == 2 ? G(I.cell[sp])[begin] : cell1d<T>(I, G(I.s[sp][0])[begin]);
+    if (begin < end) c0 = DIM == 2 ? *at(P.cell, begin) : cell1d<T>(I, *at(P.s0, begin));
     wbase_s = c0 > kWinMargin ? c0 - kWinMargin : 0u;
   }
   __syncthreads();
-  const uint32_t wbase = wbase_s;
+  D.base = wbase_s;
   LStat st = {0, 0, 0, 0, 0, 0, 0};
   uint32_t i = begin + threadIdx.x;
-  PState<T> cur = load_particle<T, DIM>(I, sp, i, i < end);
+  PState<T> cur = load_particle<T, DIM>(P, i, i < end);
   for (uint32_t base = begin; base < end; base += kBlock) {
     const uint32_t inext = i + kBlock;
-    const PState<T> nxt = load_particle<T, DIM>(I, sp, inext, inext < end);
-    if (DIM == 2) particle2d<T, MCC>(I, sp, i, cur, step, Qpar, win, wbase, st);
-    else particle1d<T, MCC>(I, sp, i, cur, step, Qpar, win, wbase, st);
+    const PState<T> nxt = load_particle<T, DIM>(P, inext, inext < end);
+    if (DIM == 2) particle2d<T, MCC>(I, P, sp, i, cur, step, Qpar, D, st);
+    else particle1d<T, MCC>(I, P, sp, i, cur, step, Qpar, D, st);
     cur = nxt;
     i = inext;
   }
   __syncthreads();
-  win_flush(win, wbase, Qpar + (size_t)sp * I.nq, I.nq);
+  dep_flush(D, Qpar + (size_t)sp * I.nq, I.nq);
   add_stats_row(row, st, sp);
   __syncthreads();
 }
