@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["k_step.hip", "k_field.hip", "k_mesh.hip", "k_adapt.hip", "api.hip", "abi.hip"]
+SOURCES = ["k_step.hip", "k_field.hip", "k_mesh.hip", "k_adapt.hip", "api.hip", "adapt.hip", "abi.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fno-fast-math",

@@ -839,10 +839,10 @@ int64_t pic_slot_bytes(pic_ctx c, int slot) {
 
 int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s) {
   PIC_GUARD_BEGIN
-  (void)get_slot(c, slot);
-  (void)a;
-  (void)s;
-  throw Err(PIC_E_STATE, "adapt not available");
+  Slot& sl = get_slot(c, slot);
+  if (!a) throw Err(PIC_E_ARG, "null adapt arguments");
+  adapt_slot(*c, sl, a->n_lo, a->n_hi, s);
+  return PIC_OK;
   PIC_GUARD_END(c)
 }
 

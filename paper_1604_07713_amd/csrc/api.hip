@@ -275,32 +275,20 @@ void validate(const pic_instance_desc& d) {
   }
 }
 
-void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
-  (void)C;
-  sl.nleaves = (uint32_t)L.size();
-  std::vector<uint32_t> keys(L.size());
-  std::vector<uint8_t> lv(L.size());
-  for (size_t i = 0; i < L.size(); ++i) {
-    keys[i] = L[i].key;
-    lv[i] = L[i].lv;
-  }
-  sl.host_leaves = L;
-  sl.release(sl.key);
-  sl.release(sl.lv);
+// Adopt device leaf arrays (allocated through sl.alloc) as the slot's tree and
+// size every per-leaf array for it.
+void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n, int maxlv) {
+  if (sl.key != key) sl.release(sl.key);
+  if (sl.lv != lv) sl.release(sl.lv);
   sl.release(sl.xy);
   sl.release(sl.lut);
-  sl.key = (uint32_t*)sl.alloc(4 * L.size());
-  sl.lv = (uint8_t*)sl.alloc(L.size());
-  sl.xy = (uint32_t*)sl.alloc(4 * L.size());
+  sl.key = key;
+  sl.lv = lv;
+  sl.nleaves = n;
+  sl.xy = (uint32_t*)sl.alloc(4 * (size_t)n);
   sl.lut_level = std::min(sl.d.max_level, 9);
-  {
-    int mx = 0;
-    for (const HostLeaf& l : L) mx = std::max(mx, (int)l.lv);
-    sl.lut_direct = mx <= sl.lut_level;
-  }
+  sl.lut_direct = maxlv <= sl.lut_level;
   sl.lut = (uint32_t*)sl.alloc(4 * ((size_t(1) << (2 * sl.lut_level)) + 1));
-  hip_check(hipMemcpy(sl.key, keys.data(), 4 * L.size(), hipMemcpyHostToDevice), "upload keys");
-  hip_check(hipMemcpy(sl.lv, lv.data(), L.size(), hipMemcpyHostToDevice), "upload levels");
   hip_check(launch_leaf_xy(sl.key, sl.lv, sl.nleaves, sl.xy, C.stream), "leaf_xy");
   hip_check(launch_build_lut(sl.key, sl.lv, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut");
   // per-leaf field and deposit arrays
@@ -323,6 +311,22 @@ void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
   hip_check(hipMemsetAsync(sl.e64, 0, 64 * (size_t)sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (size_t)sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+}
+
+void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
+  std::vector<uint32_t> keys(L.size());
+  std::vector<uint8_t> lv(L.size());
+  int mx = 0;
+  for (size_t i = 0; i < L.size(); ++i) {
+    keys[i] = L[i].key;
+    lv[i] = L[i].lv;
+    mx = std::max(mx, (int)L[i].lv);
+  }
+  uint32_t* dk = (uint32_t*)sl.alloc(4 * L.size());
+  uint8_t* dl = (uint8_t*)sl.alloc(L.size());
+  hip_check(hipMemcpy(dk, keys.data(), 4 * L.size(), hipMemcpyHostToDevice), "upload keys");
+  hip_check(hipMemcpy(dl, lv.data(), L.size(), hipMemcpyHostToDevice), "upload levels");
+  set_mesh2d_device(C, sl, dk, dl, (uint32_t)L.size(), mx);
 }
 
 void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {

@@ -68,7 +68,6 @@ struct Slot {
   int lut_level = 0;
   bool lut_direct = false;
   uint32_t nleaves = 0;
-  std::vector<HostLeaf> host_leaves;
   Stencil2D st{nullptr, nullptr, nullptr, nullptr};
   double* cg_ws = nullptr;
   bool stencil_ok = false;
@@ -115,6 +114,8 @@ struct Ctx {
 void derive(Slot& sl);
 void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d);
 void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L);
+void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n, int maxlv);
+void adapt_slot(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out);
 void alloc_particles(Slot& sl, int sp, int64_t cap, int which);
 void alloc_births(Slot& sl, int64_t cap);
 template <class T> InstDev<T> make_dev(const Slot& sl);
