@@ -124,7 +124,12 @@ typedef struct {
   int solve_field;      /* 1D: after each step solve Poisson on the device with   */
   const double* v_next; /* ... phi(0) = v_next[k*ninst_sel + j] for step k, slot j */
   int sort_every;       /* re-sort particles by cell every n steps (0 = never)    */
-  int batched;          /* 1D slots: one persistent launch over all selected slots */
+  int batched;          /* 0: launches per slot; > 0: one persistent launch over   */
+                        /* all selected 1D slots of one precision, with this many  */
+                        /* particles per work item (1 = 4096)                      */
+  int grid;             /* persistent grid size of the batched launch (0 = 2048)   */
+  int graph_steps;      /* batched only: capture this many steps into a HIP graph  */
+                        /* and replay it (0 = no graph)                            */
   const int* slots;     /* selected slots (NULL = all live slots)                 */
   int nslots;
   int timing;           /* record HIP events around the particle-loop kernels     */

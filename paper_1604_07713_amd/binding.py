@@ -61,8 +61,8 @@ class StepStats(C.Structure):
 
 class StepArgs(C.Structure):
     _fields_ = [("step0", C.c_int64), ("nsteps", C.c_int), ("solve_field", C.c_int),
-                ("v_next", C.c_void_p), ("sort_every", C.c_int), ("batched", C.c_int),
-                ("slots", C.c_void_p), ("nslots", C.c_int), ("timing", C.c_int)]
+                ("v_next", C.c_void_p), ("sort_every", C.c_int), ("batched", C.c_int), ("grid", C.c_int),
+                ("graph_steps", C.c_int), ("slots", C.c_void_p), ("nslots", C.c_int), ("timing", C.c_int)]
 
 
 class AdaptArgs(C.Structure):
@@ -219,7 +219,7 @@ class Context:
         self._check(lib().pic_particles_load(self.h, slot, species, len(s), _p(s), _p(v), _p(w), _p(ids)))
 
     def step(self, step0, nsteps=1, v_next=None, solve_field=False, sort_every=0, batched=0, slots=None,
-             timing=False):
+             timing=False, grid=0, graph_steps=0):
         a = StepArgs()
         a.step0 = int(step0)
         a.nsteps = int(nsteps)
@@ -230,6 +230,8 @@ class Context:
             a.v_next = vn.ctypes.data
         a.sort_every = int(sort_every)
         a.batched = int(batched)
+        a.grid = int(grid)
+        a.graph_steps = int(graph_steps)
         sl = None
         if slots is not None:
             sl = np.ascontiguousarray(slots, dtype=np.int32)

@@ -197,45 +197,60 @@ hipEvent_t get_event(Ctx& C, size_t i) {
   return C.ev[i];
 }
 
+// One persistent launch per step over all selected 1D slots: the work items
+// (slot, species, particle range) are listed largest slot first; per-slot
+// constants come from a device table of InstDev.  With graph_steps > 0 the
+// step sequence (particle loop, births, field solve + commit) is captured
+// once into a HIP graph on the context's capture stream and replayed.
 template <class T>
 void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int64_t kbeg, int64_t kend,
                    double* loop_ms) {
   const int nsel = (int)sel.size();
   const uint32_t tile = (uint32_t)(a->batched > 1 ? a->batched : 4096);
-  std::vector<WorkItem> items;
-  std::vector<uint32_t> rowbeg(nsel + 1, 0);
+  if (tile % kBlock) throw Err(PIC_E_ARG, "batched tile must be a multiple of 256");
   bool ionizing = false, any_mcc = false;
   int maxn = 0;
-  for (int j = 0; j < nsel; ++j) {
+  std::vector<int> order(nsel);
+  for (int j = 0; j < nsel; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return sel[x]->cap[0] + sel[x]->cap[1] > sel[y]->cap[0] + sel[y]->cap[1];
+  });
+  // work items grouped per slot, largest slot first; item k owns stats row k
+  std::vector<WorkItem> issued;
+  std::vector<uint32_t> rb(2 * (nsel + 1), 0);   // [row begin per slot][row end per slot]
+  for (int j : order) {
     Slot& sl = *sel[j];
-    rowbeg[j] = (uint32_t)items.size();
     ionizing = ionizing || sl.ionizing;
     any_mcc = any_mcc || slot_has_mcc(sl);
     maxn = std::max(maxn, sl.d.ncells);
+    rb[j] = (uint32_t)issued.size();
     for (int sp = 0; sp < sl.d.nspecies; ++sp)
       for (int64_t b = 0; b < sl.cap[sp]; b += tile)
-        items.push_back(WorkItem{(uint32_t)j, (uint32_t)sp, (uint32_t)b, (uint32_t)std::min<int64_t>(b + tile, sl.cap[sp])});
+        issued.push_back(WorkItem{(uint32_t)j, (uint32_t)sp, (uint32_t)b,
+                                  (uint32_t)std::min<int64_t>(b + tile, sl.cap[sp])});
+    rb[nsel + 1 + j] = (uint32_t)issued.size();
   }
-  rowbeg[nsel] = (uint32_t)items.size();
-  // largest instances first keeps the persistent grid's tail short
   auto ensure = [&](void*& p, size_t& have, size_t need) {
     if (have >= need) return;
-    if (p) (void)hipFree(p);
+    if (p) {
+      C.sync();
+      (void)hipFree(p);
+    }
     hip_check(hipMalloc(&p, need), "hipMalloc batched");
     have = need;
   };
-  ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * items.size());
+  ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * issued.size());
   ensure(C.b_insts, C.b_insts_bytes, sizeof(InstDev<T>) * nsel);
-  if (C.b_part_bytes < sizeof(unsigned long long) * kNStat * items.size()) {
-    ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * items.size());
+  if (C.b_part_bytes < sizeof(unsigned long long) * kNStat * issued.size()) {
+    ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * issued.size());
     hip_check(hipMemsetAsync(C.b_part, 0, C.b_part_bytes, C.stream), "memset");
   }
-  ensure(*(void**)&C.b_rowbeg, C.b_rowbeg_bytes, sizeof(uint32_t) * (nsel + 1));
-  hip_check(hipMemcpyAsync(C.b_items, C.stage(items.data(), sizeof(WorkItem) * items.size()),
-                           sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, C.stream),
+  ensure(*(void**)&C.b_rowbeg, C.b_rowbeg_bytes, sizeof(uint32_t) * rb.size());
+  hip_check(hipMemcpyAsync(C.b_items, C.stage(issued.data(), sizeof(WorkItem) * issued.size()),
+                           sizeof(WorkItem) * issued.size(), hipMemcpyHostToDevice, C.stream),
             "items");
-  hip_check(hipMemcpyAsync(C.b_rowbeg, C.stage(rowbeg.data(), 4 * rowbeg.size()), 4 * rowbeg.size(),
-                           hipMemcpyHostToDevice, C.stream),
+  hip_check(hipMemcpyAsync(C.b_rowbeg, C.stage(rb.data(), 4 * rb.size()), 4 * rb.size(), hipMemcpyHostToDevice,
+                           C.stream),
             "rowbeg");
   auto upload_insts = [&]() {
     std::vector<InstDev<T>> v(nsel);
@@ -245,27 +260,75 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
               "insts");
   };
   upload_insts();
-  const int grid = (int)std::min<size_t>(items.size(), 256 * 8);
+  const int grid = (int)std::min<size_t>(issued.size(), (size_t)(a->grid > 0 ? a->grid : 2048));
   const InstDev<T>* dI = (const InstDev<T>*)C.b_insts;
-  for (int64_t k = kbeg; k < kend; ++k) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (loop_ms) {
-      e0 = get_event(C, 2 * (k - kbeg));
-      e1 = get_event(C, 2 * (k - kbeg) + 1);
-      hip_check(hipEventRecord(e0, C.stream), "event");
-    }
-    hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)C.b_items, (uint32_t)items.size(), C.b_part, C.stream,
-                                       grid, any_mcc),
+  auto one_step = [&](hipStream_t st) {
+    hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)C.b_items, (uint32_t)issued.size(), C.b_part, st, grid,
+                                       any_mcc),
               "step1d_batched");
-    if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, C.stream), "births_batched");
-    if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
-    if (a->solve_field)
-      hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, C.stream), "field1d batched");
-    else
-      hip_check(launch_commit_batched<T>(dI, nsel, C.stream), "commit batched");
-    if (a->sort_every > 0 && (k + 1) % a->sort_every == 0 && k + 1 < kend) {
-      for (Slot* s : sel) sort_slot(C, *s);
-      upload_insts();
+    if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, st), "births_batched");
+  };
+  auto one_commit = [&](hipStream_t st) {
+    if (a->solve_field) hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, st), "field1d batched");
+    else hip_check(launch_commit_batched<T>(dI, nsel, st), "commit batched");
+  };
+  const int gsteps = a->graph_steps;
+  if (gsteps > 0) {
+    if (loop_ms) throw Err(PIC_E_ARG, "timing is not available with graph replay");
+    // capture gsteps steps once; replay between sorts
+    if (!C.cap_stream) hip_check(hipStreamCreateWithFlags(&C.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (!C.ev_a) hip_check(hipEventCreateWithFlags(&C.ev_a, hipEventDisableTiming), "event");
+    if (!C.ev_b) hip_check(hipEventCreateWithFlags(&C.ev_b, hipEventDisableTiming), "event");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    C.sync();
+    hip_check(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    for (int k = 0; k < gsteps; ++k) {
+      one_step(C.cap_stream);
+      one_commit(C.cap_stream);
+    }
+    hip_check(hipStreamEndCapture(C.cap_stream, &graph), "end capture");
+    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+    int64_t k = kbeg, since_sort = 0;
+    while (k < kend) {
+      const int64_t k_prev = k;
+      if (kend - k >= gsteps) {
+        hip_check(hipEventRecord(C.ev_a, C.stream), "event");
+        hip_check(hipStreamWaitEvent(C.cap_stream, C.ev_a, 0), "wait");
+        hip_check(hipGraphLaunch(exec, C.cap_stream), "graph launch");
+        hip_check(hipEventRecord(C.ev_b, C.cap_stream), "event");
+        hip_check(hipStreamWaitEvent(C.stream, C.ev_b, 0), "wait");
+        k += gsteps;
+      } else {
+        one_step(C.stream);
+        one_commit(C.stream);
+        ++k;
+      }
+      since_sort += k - k_prev;
+      if (a->sort_every > 0 && k < kend && since_sort >= a->sort_every) {
+        for (Slot* s : sel) sort_slot(C, *s);
+        upload_insts();
+        since_sort = 0;
+      }
+    }
+    C.sync();
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+  } else {
+    for (int64_t k = kbeg; k < kend; ++k) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (loop_ms) {
+        e0 = get_event(C, 2 + 2 * (k - kbeg));
+        e1 = get_event(C, 3 + 2 * (k - kbeg));
+        hip_check(hipEventRecord(e0, C.stream), "event");
+      }
+      one_step(C.stream);
+      if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
+      one_commit(C.stream);
+      if (a->sort_every > 0 && (k + 1) % a->sort_every == 0 && k + 1 < kend) {
+        for (Slot* s : sel) sort_slot(C, *s);
+        upload_insts();
+      }
     }
   }
   hip_check(launch_stats_reduce<T>(dI, nsel, C.b_part, C.b_rowbeg, 0u, C.stream), "stats_reduce batched");
@@ -273,7 +336,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     C.sync();
     for (int64_t k = kbeg; k < kend; ++k) {
       float ms = 0.f;
-      hip_check(hipEventElapsedTime(&ms, C.ev[2 * (k - kbeg)], C.ev[2 * (k - kbeg) + 1]), "elapsed");
+      hip_check(hipEventElapsedTime(&ms, C.ev[2 + 2 * (k - kbeg)], C.ev[3 + 2 * (k - kbeg)]), "elapsed");
       *loop_ms += ms;
     }
   }
@@ -314,6 +377,9 @@ void pic_destroy(pic_ctx c) {
   (void)hipStreamSynchronize(c->stream);
   for (Slot& s : c->slots) s.release_all();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+  if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : {c->b_insts, c->b_items, (void*)c->b_part, (void*)c->b_rowbeg})
     if (p) (void)hipFree(p);
   if (c->arena) (void)hipHostFree(c->arena);

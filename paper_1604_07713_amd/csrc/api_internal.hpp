@@ -107,6 +107,9 @@ struct Ctx {
   size_t b_part_bytes = 0;
   uint32_t* b_rowbeg = nullptr;
   size_t b_rowbeg_bytes = 0;
+  // graph capture stream (default priority) and the events joining it to the caller's stream
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
   void* stage(const void* src, size_t bytes);
   void sync();
 };

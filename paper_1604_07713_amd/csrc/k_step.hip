@@ -627,8 +627,9 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_stats_reduce(const InstDev<T>* insts, unsigned long long* rows,
                                                          const uint32_t* row_begin, uint32_t nrows_plain) {
   const InstDev<T>& I = insts[blockIdx.x];
+  // row_begin: [ninst + 1] first rows followed by [ninst + 1] end rows
   const uint32_t rb = row_begin ? row_begin[blockIdx.x] : 0u;
-  const uint32_t re = row_begin ? row_begin[blockIdx.x + 1] : nrows_plain;
+  const uint32_t re = row_begin ? row_begin[gridDim.x + 1 + blockIdx.x] : nrows_plain;
   unsigned long long* R = rows ? rows : I.part;
   __shared__ unsigned long long acc[kBlock / 64][kNStat];
   unsigned long long loc[kNStat];
