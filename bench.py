@@ -76,6 +76,60 @@ def cpu_baseline(nparticles, nsteps, seed=2):
                        f"FP32-mirror oracle, {dt:.1f} s")
 
 
+def ensemble_bench(nsteps, ninst=96, tune=True):
+    """Batched ensemble of 1D CCP instances (config-0 physics, 96 uneven
+    meshes): the FP32 batched path (one persistent launch per step, graph
+    replay, autotuned work items) vs the FP64 plain path (per-instance
+    launches), both with the on-device field solve."""
+    import numpy as np
+    import torch
+    from paper_1604_07713_amd import autotune
+    from paper_1604_07713_amd import binding as B
+    from paper_1604_07713_amd import inputs as I
+    out = {}
+    for mode, prec in (("batched", 32), ("plain", 64)):
+        descs = I.ensemble_descs(count=ninst, precision=prec)
+        vtab = np.stack([I.drive_voltage(d, np.arange(1, 4000)) for d in descs], axis=1)
+
+        def make():
+            g = B.Context(descs)
+            for j, d in enumerate(descs):
+                for sp, (s, v, w, ids) in enumerate(I.ensemble_particles(d)):
+                    g.load(j, sp, s, v, w, ids)
+                g.deposit(j)
+                g.field_solve_1d(j, float(I.drive_voltage(d, 0)))
+                g.leapfrog_start(j)
+            return g
+        g = make()
+        kw = dict(solve_field=True, sort_every=20)
+        tuned = None
+        if mode == "batched":
+            tuned = autotune.tune(make, descs, vtab) if tune else dict(tile=4096, grid=2048)
+            kw.update(batched=tuned["tile"], grid=tuned["grid"])
+        g.step(0, 10, vtab[:10], **kw)          # warm-up
+        st = g.step(10, nsteps, vtab[10:10 + nsteps], timing=True, **kw)
+        kern = st["loop_ms"]
+        if mode == "batched":
+            kw["graph_steps"] = 25
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st2 = g.step(10 + nsteps, nsteps, vtab[10 + nsteps:10 + 2 * nsteps], **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        upd = st2["alive_start"][0] + st2["alive_start"][1]
+        out[mode] = dict(precision=f"fp{prec}", updates_per_s=upd / dt, ms_per_step=dt * 1e3 / nsteps,
+                         births_per_step=st2["births"] / nsteps,
+                         loop_kernel_ms_per_step=kern / nsteps, particles=upd // nsteps,
+                         launch="one persistent launch per step, HIP graph of 25 steps" if mode == "batched"
+                         else "per-instance launches")
+        if tuned:
+            out[mode]["tile"] = tuned["tile"]
+            out[mode]["grid"] = tuned["grid"]
+        g.close()
+    out["batched_over_plain"] = out["batched"]["updates_per_s"] / out["plain"]["updates_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +139,9 @@ def main():
     ap.add_argument("--sort-every", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
+    ap.add_argument("--ensemble-steps", type=int, default=100)
+    ap.add_argument("--only-ensemble", action="store_true", help="measure only the ensemble (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="instead of the benchmark, copy this many bytes 10 times (counter calibration)")
     args = ap.parse_args()
@@ -107,6 +164,9 @@ def main():
         return
     from paper_1604_07713_amd import binding as B
     from paper_1604_07713_amd import inputs as I
+    if args.only_ensemble:
+        print(json.dumps({"ensemble": ensemble_bench(args.ensemble_steps, tune=False)}), flush=True)
+        return
 
     d = I.quadtree_static_desc()
     n = args.particles
@@ -154,6 +214,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
     }
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_bench(args.ensemble_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,70 @@
+"""Autotuner for the batched (persistent) 1D launch: particles per work item
+and grid size, chosen by timing the step kernels on a scratch copy of the
+ensemble.  Results are cached as JSON keyed by GPU architecture and a size
+class of the ensemble."""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+CACHE = os.environ.get("PIC_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "pic_mi355x_tuning.json"))
+TILES = (1024, 2048, 4096, 8192)
+GRIDS = (512, 1024, 2048, 4096)
+
+
+def size_class(descs):
+    tot = sum(d["extra"]["npart"] * 2 for d in descs)
+    prec = {d["precision"] for d in descs}
+    return f"1d-fp{min(prec)}-n{len(descs)}-p2e{int(round(math.log2(max(tot, 1))))}"
+
+
+def arch():
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def load_cache():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(c):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE, "w") as f:
+            json.dump(c, f, indent=1)
+    except OSError:
+        pass
+
+
+def tune(make_ctx, descs, v_next, steps=8, tiles=TILES, grids=GRIDS, use_cache=True):
+    """make_ctx(): a fresh, loaded and started context of the ensemble.
+    v_next: [steps][nslots] drive table.  Returns dict(tile=, grid=, ms=)."""
+    key = f"{arch()}/{size_class(descs)}"
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        return dict(cache[key], cached=True)
+    g = make_ctx()
+    results = []
+    step0 = 0
+    g.step(step0, 2, v_next[:2], solve_field=True, batched=4096)     # warm up
+    step0 += 2
+    for t in tiles:
+        for gr in grids:
+            st = g.step(step0, steps, v_next[step0:step0 + steps], solve_field=True, batched=t, grid=gr, timing=True)
+            step0 += steps
+            results.append((st["loop_ms"] / steps, t, gr))
+    g.close()
+    ms, t, gr = min(results)
+    best = dict(tile=t, grid=gr, ms=ms, table=[dict(tile=x, grid=y, ms=m) for m, x, y in sorted(results)])
+    cache[key] = best
+    if use_cache:
+        save_cache(cache)
+    return dict(best, cached=False)

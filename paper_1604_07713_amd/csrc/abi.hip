@@ -119,10 +119,9 @@ void reduce_plain_stats(Ctx& C, Slot& sl) {
             "stats_reduce");
 }
 
-void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead) {
+void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead, Counters cn) {
   if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
-  Counters cn = read_counters(C, sl);
   cn.step = (uint32_t)a->step0;
   cn.vstep0 = (uint32_t)a->step0 + 1u;
   if (sl.d.dim == 1 && a->solve_field) {
@@ -148,8 +147,9 @@ void finish_stats(Ctx& C, std::vector<Slot*>& sel, std::vector<Counters>& before
   pic_step_stats out;
   std::memset(&out, 0, sizeof(out));
   std::string err;
+  const std::vector<Counters> now = read_counters_many(C, sel);
   for (size_t j = 0; j < sel.size(); ++j) {
-    Counters c = read_counters(C, *sel[j]);
+    const Counters& c = now[j];
     const Counters& b = before[j];
     out.alive_start[0] += (int64_t)(c.stats[kStAlive0] - b.stats[kStAlive0]);
     out.alive_start[1] += (int64_t)(c.stats[kStAlive1] - b.stats[kStAlive1]);
@@ -462,6 +462,8 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
     if (sl.prec == 32) hip_check(launch_relocate<float>(make_dev<float>(sl), species, c->stream, grid_for(n)), "relocate");
     else hip_check(launch_relocate<double>(make_dev<double>(sl), species, c->stream, grid_for(n)), "relocate");
   }
+  // start cell-ordered, so deposits and gathers of a workgroup cluster
+  if (n) sort_slot(*c, sl);
   upload_dev(*c, sl);
   c->sync();
   return PIC_OK;
@@ -736,10 +738,9 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
       vn.assign(a->v_next + (size_t)kb * nsel, a->v_next + (size_t)ke * nsel);
       sub.v_next = vn.data();
     }
-    for (int j = 0; j < nsel; ++j) {
-      if (kb == 0) before[j] = read_counters(*c, *sel[j]);
-      prepare_slot(*c, *sel[j], &sub, j, nsel, ke - kb);
-    }
+    const std::vector<Counters> cur = read_counters_many(*c, sel);
+    if (kb == 0) before = cur;
+    for (int j = 0; j < nsel; ++j) prepare_slot(*c, *sel[j], &sub, j, nsel, ke - kb, cur[j]);
     if (a->timing && !started) {
       hip_check(hipEventRecord(t0, c->stream), "event");
       started = true;

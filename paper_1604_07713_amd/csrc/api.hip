@@ -248,6 +248,29 @@ void* Ctx::stage(const void* src, size_t bytes) {
   return p;
 }
 
+void* Ctx::pinned(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes > arena_size) throw Err(PIC_E_ARG, "pinned scratch too large");
+  if (arena_off + bytes > arena_size) {
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    arena_off = 0;
+  }
+  char* p = (char*)arena + arena_off;
+  arena_off += bytes;
+  return p;
+}
+
+std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel) {
+  Counters* h = (Counters*)C.pinned(sizeof(Counters) * sel.size());
+  for (size_t j = 0; j < sel.size(); ++j)
+    hip_check(hipMemcpyAsync(h + j, sel[j]->ctr, sizeof(Counters), hipMemcpyDeviceToHost, C.stream), "read counters");
+  std::vector<Counters> out(sel.size());
+  hip_check(hipStreamSynchronize(C.stream), "hipStreamSynchronize");
+  std::memcpy(out.data(), h, sizeof(Counters) * sel.size());
+  C.sync();
+  return out;
+}
+
 void Ctx::sync() {
   hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
   arena_off = 0;

@@ -111,6 +111,7 @@ struct Ctx {
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   void* stage(const void* src, size_t bytes);
+  void* pinned(size_t bytes);   // pinned host scratch from the staging arena
   void sync();
 };
 
@@ -124,6 +125,7 @@ void alloc_births(Slot& sl, int64_t cap);
 template <class T> InstDev<T> make_dev(const Slot& sl);
 void upload_dev(Ctx& C, Slot& sl);
 Counters read_counters(Ctx& C, Slot& sl);
+std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel);
 void write_counters(Ctx& C, Slot& sl, const Counters& c);
 int grid_for(int64_t n);
 void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead);

@@ -470,6 +470,7 @@ __device__ __forceinline__ void last_block_commit(Counters* c, uint32_t step) {
 template <class T, bool MCC, int DIM>
 __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end, uint32_t step,
                                           unsigned long long* Qpar, unsigned long long* row) {
+  if (begin >= end) return;   // uniform: the whole workgroup has no particles here
   __shared__ unsigned long long win[kWin];
   __shared__ uint32_t hkey[kHash];
   __shared__ unsigned long long hval[kHash];
@@ -592,9 +593,11 @@ __device__ void births_body(const InstDev<T>& I, uint32_t first_block, uint32_t 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_births(InstDev<T> I) { births_body<T>(I, blockIdx.x, gridDim.x); }
 
+// grid (per_inst, ninst): blockIdx.y selects the instance, blockIdx.x the
+// share of its births
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_births_batched(const InstDev<T>* insts) {
-  births_body<T>(insts[blockIdx.x], 0u, 1u);
+  births_body<T>(insts[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // Commit a step after the births kernel: append births to the counts,
@@ -772,7 +775,7 @@ hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid) {
 }
 template <class T>
 hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s) {
-  hipLaunchKernelGGL(k_births_batched<T>, dim3(ninst), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_births_batched<T>, dim3(32, ninst), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
 template <class T>
