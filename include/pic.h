@@ -119,7 +119,8 @@ typedef struct {
 } pic_step_stats;
 
 typedef struct {
-  int64_t step0;        /* global index of the first step (Philox counter word 1) */
+  int64_t step0;        /* global index of the first step (Philox counter word 1); */
+                        /* < 0: every slot continues from its own step index      */
   int nsteps;
   int solve_field;      /* 1D: after each step solve Poisson on the device with   */
   const double* v_next; /* ... phi(0) = v_next[k*ninst_sel + j] for step k, slot j */
@@ -146,7 +147,8 @@ typedef struct {
   double merge_energy_change;   /* sum over merges of w (|v'|^2) - (w1|v1|^2 + w2|v2|^2) */
 } pic_adapt_stats;
 
-/* Build a context holding ninst instances (slots 0..ninst-1): uniform 1D mesh,
+/* Build a context holding ninst >= 0 instances (slots 0..ninst-1; more can be
+ * admitted later with pic_admit): uniform 1D mesh,
  * or quadtree (uniform at base_level, optional disk refinement, 2:1 balance
  * across faces and corners; Sec. 3.1).  'stream' is a hipStream_t (NULL =
  * default stream).  On success *out owns all device state. */

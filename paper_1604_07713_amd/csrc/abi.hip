@@ -122,8 +122,8 @@ void reduce_plain_stats(Ctx& C, Slot& sl) {
 void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead, Counters cn) {
   if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
-  cn.step = (uint32_t)a->step0;
-  cn.vstep0 = (uint32_t)a->step0 + 1u;
+  if (a->step0 >= 0) cn.step = (uint32_t)a->step0;   // else: continue from the slot's own step index
+  cn.vstep0 = cn.step + 1u;
   if (sl.d.dim == 1 && a->solve_field) {
     if (!a->v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
     if (sl.v_cap < (uint32_t)a->nsteps) {
@@ -353,7 +353,7 @@ const char* pic_last_error(pic_ctx c) { return c ? c->err.c_str() : g_last_error
 int pic_mesh_build(const pic_instance_desc* descs, int ninst, void* stream, pic_ctx* out) {
   pic_ctx c = nullptr;
   PIC_GUARD_BEGIN
-  if (!descs || ninst < 1 || !out) throw Err(PIC_E_ARG, "need descriptors and an output handle");
+  if (ninst < 0 || (ninst > 0 && !descs) || !out) throw Err(PIC_E_ARG, "need descriptors and an output handle");
   c = new pic_ctx_s();
   c->stream = (hipStream_t)stream;
   c->arena_size = 8u << 20;
@@ -731,7 +731,7 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
   for (int64_t kb = 0; kb < a->nsteps; kb += chunk) {
     const int64_t ke = std::min<int64_t>(a->nsteps, kb + chunk);
     pic_step_args sub = *a;
-    sub.step0 = a->step0 + kb;
+    sub.step0 = a->step0 >= 0 ? a->step0 + kb : -1;
     sub.nsteps = (int)(ke - kb);
     std::vector<double> vn;
     if (a->solve_field && a->v_next) {
