@@ -128,7 +128,10 @@ typedef struct {
   int batched;          /* 0: launches per slot; > 0: one persistent launch over   */
                         /* all selected 1D slots of one precision, with this many  */
                         /* particles per work item (1 = 4096)                      */
-  int grid;             /* persistent grid size of the batched launch (0 = 2048)   */
+  int grid;             /* workgroups of the particle kernel: persistent grid of the
+                           batched launch (0 = 2048), or grid of the per-slot launch
+                           (0 = one workgroup per 256 particles, at most 2048);
+                           at most 8192                                         */
   int graph_steps;      /* batched only: capture this many steps into a HIP graph  */
                         /* and replay it (0 = no graph)                            */
   const int* slots;     /* selected slots (NULL = all live slots)                 */

@@ -65,9 +65,21 @@ void* dev_upload(Ctx& C, Slot& sl, const void* host, size_t bytes) {
   return d;
 }
 
-template <class T>
-int plain_grid(const Slot& sl) {
-  return grid_for(sl.cap[0] + sl.cap[1]);
+bool slot_has_mcc(const Slot& sl);
+
+// Grid of the per-slot step kernel: by default one workgroup per 256
+// particles of capacity, at most as many as are resident on the device at
+// once (each workgroup walks its chunk in one pass); or the caller's choice.
+int step_grid(const Slot& sl, int requested) {
+  int g;
+  if (requested > 0) {
+    g = std::min(requested, kMaxStepGrid);
+  } else {
+    const int res = sl.prec == 32 ? step_resident_grid<float>(sl.d.dim, slot_has_mcc(sl), sl.lut_direct)
+                                  : step_resident_grid<double>(sl.d.dim, slot_has_mcc(sl), sl.lut_direct);
+    g = std::min(grid_for(sl.cap[0] + sl.cap[1]), std::min(res, kMaxStepGrid));
+  }
+  return sl.d.nspecies == 2 ? std::max(g, 2) : g;   // one workgroup per species at least
 }
 
 __global__ void k_locate_points(const uint32_t* key, const uint8_t* lv, const uint32_t* lut, int L, const double* s,
@@ -97,9 +109,8 @@ bool slot_has_mcc(const Slot& sl) {
 }
 
 template <class T>
-void plain_step(Ctx& C, Slot& sl, bool solve, hipEvent_t e0, hipEvent_t e1) {
+void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e1) {
   InstDev<T> I = make_dev<T>(sl);
-  const int g = plain_grid<T>(sl);
   const bool field = sl.d.dim == 1 && solve;
   const int commit = (!sl.ionizing && !field) ? 1 : 0;
   if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
@@ -113,8 +124,8 @@ void plain_step(Ctx& C, Slot& sl, bool solve, hipEvent_t e0, hipEvent_t e1) {
 }
 
 template <class T>
-void reduce_plain_stats(Ctx& C, Slot& sl) {
-  hip_check(launch_stats_reduce<T>((const InstDev<T>*)sl.devI, 1, nullptr, nullptr, (uint32_t)plain_grid<T>(sl),
+void reduce_plain_stats(Ctx& C, Slot& sl, int g) {
+  hip_check(launch_stats_reduce<T>((const InstDev<T>*)sl.devI, 1, nullptr, nullptr, (uint32_t)g,
                                    C.stream),
             "stats_reduce");
 }
@@ -763,14 +774,16 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
             e1 = get_event(*c, 3 + 2 * evs.size());
             evs.push_back({e0, e1});
           }
-          if (sl.prec == 32) plain_step<float>(*c, sl, a->solve_field != 0, e0, e1);
-          else plain_step<double>(*c, sl, a->solve_field != 0, e0, e1);
+          const int g = step_grid(sl, a->grid);
+          if (sl.prec == 32) plain_step<float>(*c, sl, a->solve_field != 0, g, e0, e1);
+          else plain_step<double>(*c, sl, a->solve_field != 0, g, e0, e1);
           if (a->sort_every > 0 && (kb + k + 1) % a->sort_every == 0) sort_slot(*c, sl);
         }
       }
       for (int j = 0; j < nsel; ++j) {
-        if (sel[j]->prec == 32) reduce_plain_stats<float>(*c, *sel[j]);
-        else reduce_plain_stats<double>(*c, *sel[j]);
+        const int g = step_grid(*sel[j], a->grid);
+        if (sel[j]->prec == 32) reduce_plain_stats<float>(*c, *sel[j], g);
+        else reduce_plain_stats<double>(*c, *sel[j], g);
       }
       if (a->timing) {
         c->sync();

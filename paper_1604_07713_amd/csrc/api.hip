@@ -362,8 +362,8 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
   derive(sl);
   sl.ctr = (Counters*)sl.alloc(sizeof(Counters));
   hip_check(hipMemsetAsync(sl.ctr, 0, sizeof(Counters), C.stream), "memset");
-  sl.part = (unsigned long long*)sl.alloc(sizeof(unsigned long long) * kNStat * kMaxGrid);
-  hip_check(hipMemsetAsync(sl.part, 0, sizeof(unsigned long long) * kNStat * kMaxGrid, C.stream), "memset");
+  sl.part = (unsigned long long*)sl.alloc(sizeof(unsigned long long) * kNStat * kMaxStepGrid);
+  hip_check(hipMemsetAsync(sl.part, 0, sizeof(unsigned long long) * kNStat * kMaxStepGrid, C.stream), "memset");
   sl.devI = sl.alloc(sizeof(InstDev<double>));
   if (d.dim == 1) {
     const int N = d.ncells;

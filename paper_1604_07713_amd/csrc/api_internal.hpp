@@ -10,7 +10,8 @@
 
 namespace pic {
 
-constexpr int kMaxGrid = 2048;   // upper bound on the plain particle-kernel grid
+constexpr int kMaxGrid = 2048;       // default upper bound on helper-kernel grids
+constexpr int kMaxStepGrid = 8192;   // upper bound on the per-slot step-kernel grid (stats rows)
 
 struct Err {
   int code;

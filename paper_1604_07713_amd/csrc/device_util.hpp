@@ -81,6 +81,11 @@ struct WordStream {
       : k0(key0), k1(key1), id(pid), step(n), block(0) {
     gen();
   }
+  // The same stream after its first two words were drawn: (a, b) are the
+  // remaining words 2 and 3 of block 0.
+  __device__ __forceinline__ WordStream(uint32_t key0, uint32_t key1, uint32_t pid, uint32_t n, uint32_t a,
+                                        uint32_t b)
+      : k0(key0), k1(key1), id(pid), step(n), block(0), w0(a), w1(b), w2(0u), w3(0u), left(2) {}
   __device__ __forceinline__ void gen() {
     w0 = id;
     w1 = step;

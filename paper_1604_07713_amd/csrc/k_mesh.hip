@@ -68,6 +68,15 @@ __device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint3
 constexpr uint32_t kSortWin = 1024;
 constexpr uint32_t kSortMargin = 64;
 
+// Base of a chunk's LDS window of cells: the cell of the chunk's first
+// particle if that particle is live (a hole's position and leaf carry no
+// meaning), less a margin.  Window slots map to cells base + slot.
+template <class T>
+__device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp, uint32_t i) {
+  const uint32_t c0 = G(I.w[sp])[i] != 0u ? sort_cell<T>(I, sp, i) : 0u;
+  return c0 > kSortMargin ? c0 - kSortMargin : 0u;
+}
+
 // Histogram of cells over one contiguous chunk per workgroup, pre-aggregated
 // in an LDS window of cells.
 template <class T>
@@ -79,8 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint
   const uint32_t end = begin + chunk < count ? begin + chunk : count;
   for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) win[j] = 0u;
   if (threadIdx.x == 0) {
-    const uint32_t c0 = begin < end ? sort_cell<T>(I, sp, begin) : 0u;
-    base_s = c0 > kSortMargin ? c0 - kSortMargin : 0u;
+    base_s = begin < end ? sort_window_base<T>(I, sp, begin) : 0u;
   }
   __syncthreads();
   const uint32_t base = base_s;
@@ -93,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint
   }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock)
-    if (win[j]) gadd32(hist + base + j, win[j]);
+    if (win[j]) gadd32(hist + (uint32_t)(base + j), win[j]);
 }
 
 // single-workgroup exclusive scan of n counts in place; a[n] = total
@@ -137,8 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, u
   for (uint32_t t0 = begin; t0 < end; t0 += kBlock) {
     for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) lcnt[j] = 0u;
     if (threadIdx.x == 0) {
-      const uint32_t c0 = sort_cell<T>(I, sp, t0);
-      base_s = c0 > kSortMargin ? c0 - kSortMargin : 0u;
+      base_s = sort_window_base<T>(I, sp, t0);
     }
     __syncthreads();
     const uint32_t base = base_s;
@@ -153,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, u
     }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock)
-      if (lcnt[j]) gbase[j] = gadd32(off + base + j, lcnt[j]);
+      if (lcnt[j]) gbase[j] = gadd32(off + (uint32_t)(base + j), lcnt[j]);
     __syncthreads();
     if (live) {
       if (o < kSortWin) pos = gbase[o] + rank;

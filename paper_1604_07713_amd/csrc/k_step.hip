@@ -3,11 +3,12 @@
 // null-collision MCC with ionization births, charge deposit.
 //
 // One lane per particle.  Particles of a species are stored as structure of
-// arrays; when they are ordered by cell, neighbouring lanes read the same
-// field-table entries and deposit into the same cell, so a wave's run of
-// equal cells becomes a single 64-bit integer atomic (seg_atomic_add).  The
-// deposit is integer (64-bit fixed point), hence exact and independent of the
-// order in which lanes and waves add.
+// arrays and kept ordered by cell, so a workgroup's contiguous range of
+// particles touches a compact set of cells: its deposits are summed in LDS
+// (a window of consecutive cells plus a small hash table) and flushed to
+// global memory once per workgroup.  The deposit is integer (64-bit fixed
+// point), hence exact and independent of the order in which lanes and
+// workgroups add.
 #include "device_util.hpp"
 #include "pic_internal.hpp"
 
@@ -23,22 +24,22 @@ struct BirthRec {
 };
 
 // Wall rule on one normalised coordinate.  Returns false if the particle
-// leaves the domain (absorbed, or reflected but still outside).
+// leaves the domain (absorbed, or reflected but still outside).  Written
+// with selects: the hot loop evaluates it for every lane without branching.
 template <class T>
-__device__ __forceinline__ bool wall_rule(int bc, T& s, T& v, bool& lost) {
-  if (s >= (T)0 && s < (T)1) return true;
-  if (bc == PIC_ABSORB) return false;
-  if (s < (T)0) {
-    s = -s;
-    v = -v;
-  } else if (s >= (T)1) {
-    s = (T)2 - s;
-    v = -v;
-    if (s == (T)1) s = (T)1 - (T)(sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
-  }
-  if (s >= (T)0 && s < (T)1) return true;
-  lost = true;
-  return false;
+__device__ __forceinline__ bool wall_rule(bool reflect, T& s, T& v, bool& lost) {
+  const bool in0 = s >= (T)0 && s < (T)1;
+  if (!reflect) return in0;   // uniform
+  const bool lo = s < (T)0;
+  const bool hi = s >= (T)1;
+  const T pred1 = (T)1 - (T)(sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
+  T s2 = lo ? -s : (hi ? (T)2 - s : s);
+  s2 = (hi && s2 == (T)1) ? pred1 : s2;
+  v = (lo || hi) ? -v : v;
+  s = s2;
+  const bool in1 = s2 >= (T)0 && s2 < (T)1;
+  lost = lost || !in1;
+  return in1;
 }
 
 // Null-collision MCC for one particle (v in registers; vy/vz already loaded).
@@ -194,7 +195,8 @@ __device__ __forceinline__ void dep_zero(DepCache& D) {
 __device__ __forceinline__ void dep_flush(const DepCache& D, unsigned long long* g, uint32_t nq) {
   for (uint32_t j = threadIdx.x; j < kWin; j += kBlock) {
     const unsigned long long v = D.win[j];
-    if (v && D.base + j < nq) gadd(g + D.base + j, v);
+    const uint32_t key = D.base + j;   // the same modular key dep_add used
+    if (v && key < nq) gadd(g + key, v);
   }
   for (uint32_t j = threadIdx.x; j < kHash; j += kBlock) {
     const uint32_t k = D.hkey[j];
@@ -233,183 +235,378 @@ __device__ __forceinline__ SpPtr<T> species_ptrs(const InstDev<T>& I, int sp) {
   return p;
 }
 
-// Particle state loaded for one lane.  Loads are issued unconditionally and
-// one tile ahead (software pipelining), so the latency of the particle
-// arrays overlaps the work on the previous tile.
+// Full batches store weight and leaf for every lane too (branch-free) when
+// set, else only where they changed (absorbed / moved).
+#ifndef PIC_FULL_WC
+#define PIC_FULL_WC 0
+#endif
+constexpr bool kFullWC = PIC_FULL_WC != 0;
+
+// Per-species constants and table pointers of the hot loop, copied into
+// registers once per workgroup (the loop's compiler fences would otherwise
+// make every batch reload them from the kernel arguments).
+template <class T>
+struct HotK {
+  const T* E;
+  const uint32_t* leaf_xy;
+  const uint8_t* leaf_lv;
+  const uint32_t* lut;
+  int N, lut_level;
+  bool reflect;
+  uint32_t nq, key0, key1;
+  SpeciesK<T> k;
+};
+template <class T>
+__device__ __forceinline__ HotK<T> hot_constants(const InstDev<T>& I, int sp) {
+  HotK<T> h;
+  h.E = uniform_ptr(I.E);
+  h.leaf_xy = uniform_ptr(I.leaf_xy);
+  h.leaf_lv = uniform_ptr(I.leaf_lv);
+  h.lut = uniform_ptr(I.lut);
+  h.N = I.N;
+  h.lut_level = I.lut_level;
+  h.reflect = I.particle_bc == PIC_REFLECT;
+  h.nq = I.nq;
+  h.key0 = I.key0;
+  h.key1 = I.key1;
+  h.k = I.sk[sp];
+  return h;
+}
+
+// Particle state of one lane.  A workgroup walks its contiguous range in
+// batches of K particles per lane.  Vector memory operations of a wave retire
+// in issue order, so a wait for any load also waits for everything issued
+// before it; the batch loop therefore issues its loads in the order they are
+// needed and keeps every load outside data-dependent branches (loads index
+// element min(i, end - 1) and lanes past the end become holes), which keeps
+// the wait counts exact:
+//   1. field at the particles of batch t (leaf corners / node values);
+//   2. stage A of batch t+1: weight, leaf (2D) or position (1D), id;
+//   3. push and wall rule of batch t;
+//   4. point location of the particles that left their leaf (lookup table);
+//   5. collision candidate test; velocity components of the candidates;
+//   6. stage B of batch t+1: the rest of the particle state;
+//   7. collisions, births, stores and deposit of batch t.
+// Stage B of batch t+1 thus overlaps the locate and collision round trips of
+// batch t, and stage A overlaps the push.
+// Compiler-only fence: loads issued above it stay above it (they are not sunk
+// into the branches that use them), without waiting for their data.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
 template <class T>
 struct PState {
-  uint32_t w, cell;
+  uint32_t w, cell, id;
   T s0, s1, v0, v1;
 };
 
+template <class T, bool MCC, int DIM>
+__device__ __forceinline__ void load_a(const SpPtr<T>& P, uint32_t i, uint32_t end, PState<T>& p) {
+  const uint32_t ii = i < end ? i : end - 1u;
+  const uint32_t w = *at(P.w, ii);
+  if (DIM == 2) p.cell = *at(P.cell, ii);
+  else p.s0 = *at(P.s0, ii);
+  p.id = MCC ? *at(P.id, ii) : 0u;
+  p.w = i < end ? w : 0u;
+}
 template <class T, int DIM>
-__device__ __forceinline__ PState<T> load_particle(const SpPtr<T>& P, uint32_t i, bool valid) {
-  PState<T> p;
-  p.w = 0u;
-  p.cell = 0u;
-  p.s0 = p.s1 = p.v0 = p.v1 = (T)0;
-  if (valid) {
-    p.w = *at(P.w, i);
-    p.s0 = *at(P.s0, i);
-    p.v0 = *at(P.v0, i);
-    if (DIM == 2) {
-      p.cell = *at(P.cell, i);
-      p.s1 = *at(P.s1, i);
-      p.v1 = *at(P.v1, i);
-    }
+__device__ __forceinline__ void load_b(const SpPtr<T>& P, uint32_t i, uint32_t end, PState<T>& p) {
+  const uint32_t ii = i < end ? i : end - 1u;
+  if (DIM == 2) {
+    p.s0 = *at(P.s0, ii);
+    p.s1 = *at(P.s1, ii);
+    p.v1 = *at(P.v1, ii);
+  } else {
+    p.cell = 0u;
+    p.s1 = (T)0;
+    p.v1 = (T)0;
   }
-  return p;
+  p.v0 = *at(P.v0, ii);
 }
 
-template <class T, bool MCC>
-__device__ __forceinline__ void particle1d(const InstDev<T>& I, const SpPtr<T>& P, int sp, uint32_t i, PState<T> p,
-                                           uint32_t step,
-                                           unsigned long long* Qpar, DepCache& D,
-                                           LStat& st) {
-  const SpeciesK<T>& k = I.sk[sp];
-  const int N = I.N;
-  const T Nt = (T)N;
-  uint32_t w = p.w;
-  bool birth = false;
-  BirthRec<T> rec;
-  T s = p.s0;
-  uint32_t pid = 0;
-  if (w != 0u) {
-    st.alive++;
-    T vx = p.v0;
-    {
-      const T g = s * Nt;
-      int ic = (int)floor(g);
-      if (ic > N - 1) ic = N - 1;
-      const T f = g - (T)ic;
-      const T e0 = *at(I.E, (uint32_t)ic), e1 = *at(I.E, (uint32_t)ic + 1u);
-      const T E = e0 + f * (e1 - e0);
-      vx = vx + k.qm_dt * E;
-      s = s + vx * k.dt_L;
-    }
-    bool lost = false;
-    if (!wall_rule<T>(I.particle_bc, s, vx, lost)) {
-      st.absorbed++;
-      st.lost += lost ? 1u : 0u;
-      *at(P.w, i) = 0u;
-      w = 0u;
-    } else {
-      if (MCC && k.mcc != PIC_MCC_NONE) {
-        pid = *at(P.id, i);
-        WordStream ws(I.key0, I.key1, pid, step);
-        const uint32_t r0 = ws.next();
-        const uint32_t r1 = ws.next();
-        if ((r0 >> 8) < k.tcand) {
-          T vy = *at(P.v1, i), vz = *at(P.v2, i);
-          birth = collide<T>(I, k, pid, step, r1, ws, vx, vy, vz, st, rec);
-          *at(P.v1, i) = vy;
-          *at(P.v2, i) = vz;
-        }
-      }
-      *at(P.s0, i) = s;
-      *at(P.v0, i) = vx;
-      // CIC shares in 64-bit fixed point
-      const T g = s * Nt;
-      int ic = (int)floor(g);
-      if (ic > N - 1) ic = N - 1;
-      const T f = g - (T)ic;
-      const unsigned long long r = (unsigned long long)(long long)rint(f * (T)(1ull << FixedPoint<T>::F));
-      const unsigned long long one = 1ull << FixedPoint<T>::F;
-      const unsigned long long mult = birth ? 2ull : 1ull;
-      unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
-      dep_add(D, Qs, (uint32_t)ic, mult * (unsigned long long)w * (one - r));
-      dep_add(D, Qs, (uint32_t)ic + 1u, mult * (unsigned long long)w * r);
-      if (MCC && birth) {   // the newborn ion sits on the parent
-        unsigned long long* Qi = Qpar + I.nq;
-        if (one - r) gadd(Qi + ic, (unsigned long long)w * (one - r));
-        if (r) gadd(Qi + ic + 1, (unsigned long long)w * r);
-      }
-    }
-  }
-  if (MCC) stage_birth<T>(I, birth, pid, 0u, w, s, (T)0, rec);
+// Field data at one particle: the two node values around it (1D) or the
+// leaf's corner coordinates, level and corner E (2D).
+template <class T, int DIM>
+struct FieldAt;
+template <class T>
+struct FieldAt<T, 1> {
+  T e0, e1;
+};
+template <class T>
+struct FieldAt<T, 2> {
+  uint32_t xy;
+  int lv;
+  T c[8];
+};
+
+template <class T>
+__device__ __forceinline__ uint32_t cell1d_h(const HotK<T>& H, T s) {
+  const T g = s * (T)H.N;
+  int ic = (int)floor(g);
+  if (ic > H.N - 1) ic = H.N - 1;
+  return (uint32_t)ic;
+}
+template <class T>
+__device__ __forceinline__ void fetch_field(const HotK<T>& H, const PState<T>& p, FieldAt<T, 1>& f) {
+  const uint32_t ic = cell1d_h<T>(H, p.w ? p.s0 : (T)0);
+  f.e0 = *at(H.E, ic);
+  f.e1 = *at(H.E, ic + 1u);
+}
+template <class T>
+__device__ __forceinline__ void fetch_leaf(const InstDev<T>& I, uint32_t leaf, FieldAt<T, 2>& f) {
+  f.xy = *at(I.leaf_xy, leaf);
+  f.lv = *at(I.leaf_lv, leaf);
+  const gptr<const T> c = at(I.E, leaf * 8u);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) f.c[q] = c[q];
+}
+template <class T>
+__device__ __forceinline__ void fetch_field(const HotK<T>& H, const PState<T>& p, FieldAt<T, 2>& f) {
+  const uint32_t leaf = p.w ? p.cell : 0u;
+  f.xy = *at(H.leaf_xy, leaf);
+  f.lv = *at(H.leaf_lv, leaf);
+  const gptr<const T> c = at(H.E, leaf * 8u);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) f.c[q] = c[q];
 }
 
-// ---------------------------------------------------------------------------
-// 2D quadtree: one particle per lane
-// ---------------------------------------------------------------------------
+// Bilinear interpolation of the leaf's corner E (corners SW, SE, NW, NE).
+template <class T>
+__device__ __forceinline__ void interp2d(const FieldAt<T, 2>& f, T sx, T sy, T& ex, T& ey) {
+  const int sh = kKeyBits - f.lv;
+  const T sc = (T)(1u << f.lv);
+  const T xi = sx * sc - (T)((f.xy >> 16) >> sh);
+  const T eta = sy * sc - (T)((f.xy & 0xFFFFu) >> sh);
+  const T w00 = ((T)1 - xi) * ((T)1 - eta);
+  const T w10 = xi * ((T)1 - eta);
+  const T w01 = ((T)1 - xi) * eta;
+  const T w11 = xi * eta;
+  ex = ((w00 * f.c[0] + w10 * f.c[2]) + w01 * f.c[4]) + w11 * f.c[6];
+  ey = ((w00 * f.c[1] + w10 * f.c[3]) + w01 * f.c[5]) + w11 * f.c[7];
+}
+
+template <class T>
+__device__ __forceinline__ void gather2d(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T& ex, T& ey) {
+  FieldAt<T, 2> f;
+  fetch_leaf<T>(I, leaf, f);
+  interp2d<T>(f, sx, sy, ex, ey);
+}
+
 template <class T>
 __device__ __forceinline__ uint32_t locate2d(const InstDev<T>& I, uint32_t X, uint32_t Y) {
   return locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, X, Y, I.lut_direct != 0);
 }
 
-template <class T>
-__device__ __forceinline__ void gather2d(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T& ex, T& ey) {
-  const uint32_t xy = *at(I.leaf_xy, leaf);
-  const int lv = *at(I.leaf_lv, leaf);
-  const int sh = kKeyBits - lv;
-  const T sc = (T)(1u << lv);
-  const T xi = sx * sc - (T)((xy >> 16) >> sh);
-  const T eta = sy * sc - (T)((xy & 0xFFFFu) >> sh);
-  const T w00 = ((T)1 - xi) * ((T)1 - eta);
-  const T w10 = xi * ((T)1 - eta);
-  const T w01 = ((T)1 - xi) * eta;
-  const T w11 = xi * eta;
-  const gptr<const T> c = at(I.E, leaf * 8u);
-  ex = ((w00 * c[0] + w10 * c[2]) + w01 * c[4]) + w11 * c[6];
-  ey = ((w00 * c[1] + w10 * c[3]) + w01 * c[5]) + w11 * c[7];
+// Gather, leapfrog push and wall rule of one particle, evaluated for every
+// lane (holes and lanes past the end compute and discard).  An absorbed
+// particle becomes a hole (w = 0; stored at once in a partial batch, with
+// the other stores in a full one).  Returns true when a live
+// 2D particle has left its leaf and must be located.
+template <class T, int DIM, bool FULL>
+__device__ __forceinline__ bool push_one(const HotK<T>& H, const SpPtr<T>& P, uint32_t i, PState<T>& p,
+                                         const FieldAt<T, DIM>& f, LStat& st) {
+  const SpeciesK<T>& k = H.k;
+  const bool alive = p.w != 0u;
+  bool ok;
+  bool lost = false;
+  if constexpr (DIM == 1) {
+    const T g = p.s0 * (T)H.N;
+    int ic = (int)floor(g);
+    if (ic > H.N - 1) ic = H.N - 1;
+    const T fr = g - (T)ic;
+    const T E = f.e0 + fr * (f.e1 - f.e0);
+    p.v0 = p.v0 + k.qm_dt * E;
+    p.s0 = p.s0 + p.v0 * k.dt_L;
+    ok = wall_rule<T>(H.reflect, p.s0, p.v0, lost);
+  } else {
+    T ex, ey;
+    interp2d<T>(f, p.s0, p.s1, ex, ey);
+    p.v0 = p.v0 + k.qm_dt * ex;
+    p.v1 = p.v1 + k.qm_dt * ey;
+    p.s0 = p.s0 + p.v0 * k.dt_L;
+    p.s1 = p.s1 + p.v1 * k.dt_L;
+    const bool okx = wall_rule<T>(H.reflect, p.s0, p.v0, lost);
+    const bool oky = wall_rule<T>(H.reflect, p.s1, p.v1, lost);
+    ok = okx && oky;
+  }
+  const bool absorbed = alive && !ok;
+  st.alive += alive ? 1u : 0u;
+  st.absorbed += absorbed ? 1u : 0u;
+  st.lost += (absorbed && lost) ? 1u : 0u;
+  if ((!FULL || !kFullWC) && absorbed) *at(P.w, i) = 0u;   // else stored with the rest
+  p.w = ok ? p.w : 0u;
+  if constexpr (DIM == 1) {
+    return false;
+  } else {
+    const uint32_t X = (uint32_t)(p.s0 * (T)65536);
+    const uint32_t Y = (uint32_t)(p.s1 * (T)65536);
+    const int sh = kKeyBits - f.lv;
+    const bool left = (X >> sh) != ((f.xy >> 16) >> sh) || (Y >> sh) != ((f.xy & 0xFFFFu) >> sh);
+    return p.w != 0u && left;
+  }
 }
 
-template <class T, bool MCC>
-__device__ __forceinline__ void particle2d(const InstDev<T>& I, const SpPtr<T>& P, int sp, uint32_t i, PState<T> p,
-                                           uint32_t step,
-                                           unsigned long long* Qpar, DepCache& D,
-                                           LStat& st) {
-  const SpeciesK<T>& k = I.sk[sp];
-  uint32_t w = p.w;
-  bool birth = false;
-  BirthRec<T> rec;
-  T sx = p.s0, sy = p.s1;
-  uint32_t pid = 0, leaf = p.cell;
-  if (w != 0u) {
-    st.alive++;
-    T vx = p.v0;
-    T vy = p.v1;
-    T ex, ey;
-    gather2d<T>(I, leaf, sx, sy, ex, ey);
-    vx = vx + k.qm_dt * ex;
-    vy = vy + k.qm_dt * ey;
-    sx = sx + vx * k.dt_L;
-    sy = sy + vy * k.dt_L;
-    bool lost = false;
-    const bool okx = wall_rule<T>(I.particle_bc, sx, vx, lost);
-    const bool ok = okx && wall_rule<T>(I.particle_bc, sy, vy, lost);
-    if (!ok) {
-      st.absorbed++;
-      st.lost += lost ? 1u : 0u;
-      *at(P.w, i) = 0u;
-      w = 0u;
-    } else {
-      const uint32_t X = (uint32_t)(sx * (T)65536);
-      const uint32_t Y = (uint32_t)(sy * (T)65536);
-      const uint32_t xy = *at(I.leaf_xy, leaf);
-      const int sh = kKeyBits - (int)*at(I.leaf_lv, leaf);
-      if ((X >> sh) != ((xy >> 16) >> sh) || (Y >> sh) != ((xy & 0xFFFFu) >> sh)) leaf = locate2d<T>(I, X, Y);
-      if (MCC && k.mcc != PIC_MCC_NONE) {
-        pid = *at(P.id, i);
-        WordStream ws(I.key0, I.key1, pid, step);
-        const uint32_t r0 = ws.next();
-        const uint32_t r1 = ws.next();
-        if ((r0 >> 8) < k.tcand) {
-          T vz = *at(P.v2, i);
-          birth = collide<T>(I, k, pid, step, r1, ws, vx, vy, vz, st, rec);
-          *at(P.v2, i) = vz;
-        }
+// Collision inputs of one particle carried from the candidate test to the
+// collision: the second word of its stream, the two words left in block 0,
+// and the velocity components the push does not keep in registers.
+template <class T>
+struct CollIn {
+  bool cand;
+  uint32_t r1, wa, wb;
+  T vy, vz;
+};
+
+// One batch of K particles per lane (stages 1-7 above).  DIRECT: the lookup
+// table alone locates a point (no leaf is finer than its level).  FULL: every
+// lane of the batch holds a slot of the workgroup's range, so the state is
+// stored without a branch, holes included (a hole's position and velocity
+// are never read; its leaf stays a valid index); the stores of a partial
+// batch are masked by liveness.  Stores that depend on data (collision
+// velocities, a partial batch) come after every load of the batch, so they
+// do not disturb the exact wait counts of the loads.
+template <class T, bool MCC, int DIM, int K, bool DIRECT, bool FULL>
+__device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>& H, const SpPtr<T>& P, int sp, uint32_t i0,
+                                              PState<T> (&p)[K], PState<T> (&nxt)[K], uint32_t end, uint32_t step,
+                                              unsigned long long* Qpar, DepCache& D, LStat& st) {
+  const SpeciesK<T>& k = H.k;
+  const bool mcc = MCC && k.mcc != PIC_MCC_NONE;
+  const uint32_t inext0 = i0 + (uint32_t)K * kBlock;
+  // 1. field at the particles
+  FieldAt<T, DIM> f[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) fetch_field<T>(H, p[j], f[j]);
+  // 2. stage A of the next batch
+#pragma unroll
+  for (int j = 0; j < K; ++j) load_a<T, MCC, DIM>(P, inext0 + (uint32_t)j * kBlock, end, nxt[j]);
+  issue_fence();
+  // 3. push
+  bool moved[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) moved[j] = push_one<T, DIM, FULL>(H, P, i0 + (uint32_t)j * kBlock, p[j], f[j], st);
+  // 4. locate
+  uint32_t leaf[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) leaf[j] = p[j].cell;
+  if constexpr (DIM == 2) {
+    if constexpr (DIRECT) {
+      const int sh = kKeyBits - H.lut_level;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t X = moved[j] ? (uint32_t)(p[j].s0 * (T)65536) : 0u;
+        const uint32_t Y = moved[j] ? (uint32_t)(p[j].s1 * (T)65536) : 0u;
+        leaf[j] = *at(H.lut, morton2(X >> sh, Y >> sh));
       }
-      *at(P.s0, i) = sx;
-      *at(P.s1, i) = sy;
-      *at(P.v0, i) = vx;
-      *at(P.v1, i) = vy;
-      if (leaf != p.cell) *at(P.cell, i) = leaf;
-      dep_add(D, Qpar + (size_t)sp * I.nq, leaf, (birth ? 2ull : 1ull) * (unsigned long long)w);
-      if (MCC && birth) gadd(Qpar + I.nq + leaf, (unsigned long long)w);
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (moved[j]) leaf[j] = locate2d<T>(I, (uint32_t)(p[j].s0 * (T)65536), (uint32_t)(p[j].s1 * (T)65536));
     }
   }
-  if (MCC) stage_birth<T>(I, birth, pid, leaf, w, sx, sy, rec);
+  // 5. collision candidates and their velocity components
+  CollIn<T> ci[K];
+  if constexpr (MCC) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      ci[j].cand = false;
+      ci[j].r1 = ci[j].wa = ci[j].wb = 0u;
+      if (mcc && p[j].w) {
+        WordStream ws(H.key0, H.key1, p[j].id, step);
+        const uint32_t r0 = ws.next();
+        ci[j].r1 = ws.next();
+        ci[j].wa = ws.w0;
+        ci[j].wb = ws.w1;
+        ci[j].cand = (r0 >> 8) < k.tcand;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const uint32_t i = i0 + (uint32_t)j * kBlock;
+      ci[j].vy = (T)0;
+      ci[j].vz = (T)0;
+      if (ci[j].cand) {
+        if (DIM == 1) ci[j].vy = *at(P.v1, i);
+        ci[j].vz = *at(P.v2, i);
+      }
+    }
+  }
+  // 6. stage B of the next batch
+#pragma unroll
+  for (int j = 0; j < K; ++j) load_b<T, DIM>(P, inext0 + (uint32_t)j * kBlock, end, nxt[j]);
+  issue_fence();
+  // 7. collisions, births, stores, deposit
+  if constexpr (DIM == 2 && DIRECT) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) leaf[j] = moved[j] ? leaf[j] : p[j].cell;
+  }
+  bool birth[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) birth[j] = false;
+  if constexpr (MCC) {
+    if (mcc) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        BirthRec<T> rec;
+        if (ci[j].cand) {
+          const uint32_t i = i0 + (uint32_t)j * kBlock;
+          T vy = DIM == 1 ? ci[j].vy : p[j].v1;
+          T vz = ci[j].vz;
+          WordStream ws(H.key0, H.key1, p[j].id, step, ci[j].wa, ci[j].wb);
+          birth[j] = collide<T>(I, k, p[j].id, step, ci[j].r1, ws, p[j].v0, vy, vz, st, rec);
+          if (DIM == 1) *at(P.v1, i) = vy;
+          else p[j].v1 = vy;
+          *at(P.v2, i) = vz;
+        }
+        stage_birth<T>(I, birth[j], p[j].id, DIM == 2 ? leaf[j] : 0u, p[j].w, p[j].s0, p[j].s1, rec);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t i = i0 + (uint32_t)j * kBlock;
+    if (FULL) {
+      if (kFullWC) *at(P.w, i) = p[j].w;
+      *at(P.s0, i) = p[j].s0;
+      *at(P.v0, i) = p[j].v0;
+      if (DIM == 2) {
+        *at(P.s1, i) = p[j].s1;
+        *at(P.v1, i) = p[j].v1;
+        if (kFullWC || moved[j]) *at(P.cell, i) = leaf[j];
+      }
+    } else if (p[j].w != 0u) {
+      *at(P.s0, i) = p[j].s0;
+      *at(P.v0, i) = p[j].v0;
+      if (DIM == 2) {
+        *at(P.s1, i) = p[j].s1;
+        *at(P.v1, i) = p[j].v1;
+        if (moved[j]) *at(P.cell, i) = leaf[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (p[j].w == 0u) continue;
+    const unsigned long long w = p[j].w;
+    unsigned long long* Qs = Qpar + (size_t)sp * H.nq;
+    if (DIM == 2) {
+      dep_add(D, Qs, leaf[j], (birth[j] ? 2ull : 1ull) * w);
+      if (MCC && birth[j]) gadd(Qpar + H.nq + leaf[j], w);
+    } else {
+      // CIC shares in 64-bit fixed point
+      const T g = p[j].s0 * (T)H.N;
+      int ic = (int)floor(g);
+      if (ic > H.N - 1) ic = H.N - 1;
+      const T fr = g - (T)ic;
+      const unsigned long long r = (unsigned long long)(long long)rint(fr * (T)(1ull << FixedPoint<T>::F));
+      const unsigned long long one = 1ull << FixedPoint<T>::F;
+      const unsigned long long mult = birth[j] ? 2ull : 1ull;
+      dep_add(D, Qs, (uint32_t)ic, mult * w * (one - r));
+      dep_add(D, Qs, (uint32_t)ic + 1u, mult * w * r);
+      if (MCC && birth[j]) {   // the newborn ion sits on the parent
+        unsigned long long* Qi = Qpar + H.nq;
+        if (one - r) gadd(Qi + ic, w * (one - r));
+        if (r) gadd(Qi + ic + 1, w * r);
+      }
+    }
+  }
 }
 
 // Per-workgroup counters are added into the workgroup's own row of a
@@ -467,7 +664,7 @@ __device__ __forceinline__ void last_block_commit(Counters* c, uint32_t step) {
   }
 }
 
-template <class T, bool MCC, int DIM>
+template <class T, bool MCC, int DIM, int K, bool DIRECT>
 __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end, uint32_t step,
                                           unsigned long long* Qpar, unsigned long long* row) {
   if (begin >= end) return;   // uniform: the whole workgroup has no particles here
@@ -476,25 +673,47 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   __shared__ unsigned long long hval[kHash];
   __shared__ uint32_t wbase_s;
   const SpPtr<T> P = species_ptrs<T>(I, sp);
+  const HotK<T> H = hot_constants<T>(I, sp);
   DepCache D{win, hkey, hval, 0u};
   dep_zero(D);
   if (threadIdx.x == 0) {
-    uint32_t c0 = 0;
-    if (begin < end) c0 = DIM == 2 ? *at(P.cell, begin) : cell1d<T>(I, *at(P.s0, begin));
+    // window from the first particle of the range if it is live: a hole's
+    // stored position and leaf carry no meaning (full batches overwrite them)
+    uint32_t c0 = 0u;
+    if (*at(P.w, begin) != 0u) c0 = DIM == 2 ? *at(P.cell, begin) : cell1d<T>(I, *at(P.s0, begin));
     wbase_s = c0 > kWinMargin ? c0 - kWinMargin : 0u;
   }
+  // first batch: stage A, then stage B, in the same order as the loop issues
+  // them for later batches
+  PState<T> cur[K], nxt[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) load_a<T, MCC, DIM>(P, begin + (uint32_t)j * kBlock + threadIdx.x, end, cur[j]);
+  issue_fence();
+#pragma unroll
+  for (int j = 0; j < K; ++j) load_b<T, DIM>(P, begin + (uint32_t)j * kBlock + threadIdx.x, end, cur[j]);
+  issue_fence();
   __syncthreads();
   D.base = wbase_s;
   LStat st = {0, 0, 0, 0, 0, 0, 0};
-  uint32_t i = begin + threadIdx.x;
-  PState<T> cur = load_particle<T, DIM>(P, i, i < end);
-  for (uint32_t base = begin; base < end; base += kBlock) {
-    const uint32_t inext = i + kBlock;
-    const PState<T> nxt = load_particle<T, DIM>(P, inext, inext < end);
-    if (DIM == 2) particle2d<T, MCC>(I, P, sp, i, cur, step, Qpar, D, st);
-    else particle1d<T, MCC>(I, P, sp, i, cur, step, Qpar, D, st);
-    cur = nxt;
-    i = inext;
+  // Full batches two per trip with the state buffers swapping roles, so the
+  // prefetched state is never copied between registers (a copy would wait);
+  // then the partial batch, if any.
+  const uint32_t unit = (uint32_t)K * kBlock;
+  uint32_t base = begin;
+  bool in_cur = true;
+  while (end - base >= unit) {
+    process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, base + threadIdx.x, cur, nxt, end, step, Qpar, D, st);
+    base += unit;
+    if (end - base < unit) {
+      in_cur = false;
+      break;
+    }
+    process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st);
+    base += unit;
+  }
+  if (base < end) {
+    if (in_cur) process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, cur, nxt, end, step, Qpar, D, st);
+    else process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st);
   }
   __syncthreads();
   dep_flush(D, Qpar + (size_t)sp * I.nq, I.nq);
@@ -502,20 +721,58 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   __syncthreads();
 }
 
+// Particles per lane per batch of the step kernels.
+#ifndef PIC_BATCH_2D
+#define PIC_BATCH_2D 2
+#endif
+#ifndef PIC_BATCH_1D
+#define PIC_BATCH_1D 2
+#endif
+#ifndef PIC_BATCH_MCC
+#define PIC_BATCH_MCC 1
+#endif
+template <int DIM, bool MCC>
+constexpr int batch_k() {
+  return MCC ? PIC_BATCH_MCC : DIM == 2 ? PIC_BATCH_2D : PIC_BATCH_1D;
+}
+
 // Plain launch over one instance: workgroups [0, gs) own consecutive chunks
-// of species 0, [gs, grid) of species 1.
-template <class T, bool MCC, int DIM>
-__global__ __launch_bounds__(kBlock) void k_step(InstDev<T> I, int gs, uint32_t chunk0, uint32_t chunk1, int commit) {
-  const int sp = (I.nspecies == 2 && (int)blockIdx.x >= gs) ? 1 : 0;
-  const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - (uint32_t)gs;
-  const uint32_t chunk = sp == 0 ? chunk0 : chunk1;
+// of species 0, [gs, grid) of species 1, gs in proportion to the live counts
+// (read from the device counters, so the split follows births and losses
+// without host round trips).
+#ifndef PIC_STEP_WAVES
+#define PIC_STEP_WAVES 0
+#endif
+#if PIC_STEP_WAVES > 0
+#define PIC_STEP_ATTR __attribute__((amdgpu_waves_per_eu(PIC_STEP_WAVES)))
+#else
+#define PIC_STEP_ATTR
+#endif
+template <class T, bool MCC, int DIM, bool DIRECT>
+__global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int commit) {
+  constexpr int K = batch_k<DIM, MCC>();
   const uint32_t step = I.ctr->step;
-  const uint32_t count = I.ctr->count[sp];
+  const uint32_t n0 = I.ctr->count[0];
+  const uint32_t n1 = I.nspecies == 2 ? I.ctr->count[1] : 0u;
+  const uint32_t grid = gridDim.x;
+  uint32_t gs = grid;
+  if (I.nspecies == 2) {
+    gs = (uint32_t)(((uint64_t)grid * n0 + ((uint64_t)n0 + n1) / 2u) / ((uint64_t)n0 + n1 + 1u));
+    if (gs < 1u) gs = 1u;
+    if (gs > grid - 1u) gs = grid - 1u;
+  }
+  const int sp = blockIdx.x >= gs ? 1 : 0;
+  const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - gs;
+  const uint32_t nb = sp == 0 ? gs : grid - gs;
+  const uint32_t count = sp == 0 ? n0 : n1;
+  const uint32_t unit = (uint32_t)K * kBlock;
+  const uint32_t chunk = ((count + nb - 1u) / nb + unit - 1u) / unit * unit;
   unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
   zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
-  const uint32_t begin = b * chunk;
-  const uint32_t end = begin + chunk < count ? begin + chunk : count;
-  run_range<T, MCC, DIM>(I, sp, begin, end, step, Qpar, I.part + (size_t)blockIdx.x * kNStat);
+  const uint64_t begin64 = (uint64_t)b * chunk;
+  const uint32_t begin = begin64 < count ? (uint32_t)begin64 : count;
+  const uint32_t end = (uint64_t)begin + chunk < count ? begin + chunk : count;
+  run_range<T, MCC, DIM, K, DIRECT>(I, sp, begin, end, step, Qpar, I.part + (size_t)blockIdx.x * kNStat);
   if (commit) last_block_commit(I.ctr, step);
 }
 
@@ -534,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
     const uint32_t end = wi.end < count ? wi.end : count;
     unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
     if (wi.begin == 0 && sp == 0) zero_other_parity(I.Q, I.nq, step, I.nspecies, threadIdx.x, kBlock);
-    run_range<T, MCC, 1>(I, sp, wi.begin, end, step, Qpar, bpart + (size_t)it * kNStat);
+    run_range<T, MCC, 1, batch_k<1, MCC>(), false>(I, sp, wi.begin, end, step, Qpar, bpart + (size_t)it * kNStat);
   }
 }
 
@@ -735,32 +992,42 @@ __global__ __launch_bounds__(kBlock) void k_relocate(InstDev<T> I, int sp) {
 
 // ---- launchers ----
 template <class T>
-static int species_split(const InstDev<T>& I, int grid) {
-  if (I.nspecies < 2) return grid;
-  const double f = (double)I.cap[0] / ((double)I.cap[0] + (double)I.cap[1] + 1.0);
-  int gs = (int)(grid * f + 0.5);
-  if (gs < 1) gs = 1;
-  if (gs > grid - 1) gs = grid - 1;
-  return gs;
-}
-
-template <class T>
 hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit) {
-  const int gs = species_split(I, grid);
-  const int g0 = gs, g1 = I.nspecies == 2 ? grid - gs : 1;
-  uint32_t c0 = (ceil_div(I.cap[0], (uint32_t)g0) + kBlock - 1) / kBlock * kBlock;
-  uint32_t c1 = (ceil_div(I.cap[1] ? I.cap[1] : 1u, (uint32_t)g1) + kBlock - 1) / kBlock * kBlock;
-  if (c0 < kBlock) c0 = kBlock;
-  if (c1 < kBlock) c1 = kBlock;
+  if (I.nspecies == 2 && grid < 2) return hipErrorInvalidValue;   // the species split needs two workgroups
+  const dim3 g(grid), b(kBlock);
   if (I.dim == 1) {
-    if (mcc) hipLaunchKernelGGL((k_step<T, true, 1>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
-    else hipLaunchKernelGGL((k_step<T, false, 1>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
+    if (mcc) hipLaunchKernelGGL((k_step<T, true, 1, false>), g, b, 0, s, I, commit);
+    else hipLaunchKernelGGL((k_step<T, false, 1, false>), g, b, 0, s, I, commit);
+  } else if (I.lut_direct) {
+    if (mcc) hipLaunchKernelGGL((k_step<T, true, 2, true>), g, b, 0, s, I, commit);
+    else hipLaunchKernelGGL((k_step<T, false, 2, true>), g, b, 0, s, I, commit);
   } else {
-    if (mcc) hipLaunchKernelGGL((k_step<T, true, 2>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
-    else hipLaunchKernelGGL((k_step<T, false, 2>), dim3(grid), dim3(kBlock), 0, s, I, gs, c0, c1, commit);
+    if (mcc) hipLaunchKernelGGL((k_step<T, true, 2, false>), g, b, 0, s, I, commit);
+    else hipLaunchKernelGGL((k_step<T, false, 2, false>), g, b, 0, s, I, commit);
   }
   return hipGetLastError();
 }
+// Workgroups of the step kernel variant that fit on the device at once
+// (occupancy per compute unit x compute units), cached per variant.
+template <class T>
+int step_resident_grid(int dim, bool mcc, bool direct) {
+  static int cache[2][2][2] = {};
+  int& c = cache[dim == 2 ? 1 : 0][mcc ? 1 : 0][direct ? 1 : 0];
+  if (c == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    const void* fn;
+    if (dim == 1) fn = mcc ? (const void*)k_step<T, true, 1, false> : (const void*)k_step<T, false, 1, false>;
+    else if (direct) fn = mcc ? (const void*)k_step<T, true, 2, true> : (const void*)k_step<T, false, 2, true>;
+    else fn = mcc ? (const void*)k_step<T, true, 2, false> : (const void*)k_step<T, false, 2, false>;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess)
+      return 2048;
+    c = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  }
+  return c;
+}
+
 template <class T>
 hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
                                  unsigned long long* bpart, hipStream_t s, int grid, bool mcc) {
@@ -811,7 +1078,8 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
 }
 
 #define PIC_INSTANTIATE(T)                                                                                 \
-  template hipError_t launch_step<T>(const InstDev<T>&, hipStream_t, int, bool, int);                      \
+  template hipError_t launch_step<T>(const InstDev<T>&, hipStream_t, int, bool, int);                                                     \
+  template int step_resident_grid<T>(int, bool, bool);                      \
   template hipError_t launch_step1d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
                                                unsigned long long*, hipStream_t, int, bool);               \
   template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, int);                               \

@@ -96,6 +96,7 @@ struct WorkItem {
 // commit != 0: the last workgroup advances the step index (no births kernel
 // or field solve follows in this step).
 template <class T> hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit);
+template <class T> int step_resident_grid(int dim, bool mcc, bool direct);
 template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
                                                     unsigned long long* bpart, hipStream_t s, int grid, bool mcc);
 template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid);
