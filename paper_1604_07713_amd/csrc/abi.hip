@@ -115,7 +115,7 @@ void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e
   const int commit = (!sl.ionizing && !field) ? 1 : 0;
   if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
   hip_check(launch_step<T>(I, C.stream, g, slot_has_mcc(sl), commit), "step");
-  if (sl.ionizing) hip_check(launch_births<T>(I, C.stream, 64), "births");
+  if (sl.ionizing) hip_check(launch_births<T>(I, C.stream, 256), "births");
   if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
   if (field)
     hip_check(launch_field1d<T>((const InstDev<T>*)sl.devI, 1, sl.d.ncells, 1, nullptr, C.stream), "field1d");

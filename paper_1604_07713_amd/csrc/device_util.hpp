@@ -115,6 +115,7 @@ __device__ __forceinline__ T unit_uniform(uint32_t r) {
 
 template <class T>
 __device__ __forceinline__ void isotropic(WordStream& ws, T& dx, T& dy, T& dz) {
+#pragma unroll 1
   for (int k = 0; k < 32; ++k) {
     const T a = (T)2 * unit_uniform<T>(ws.next()) - (T)1;
     const T b = (T)2 * unit_uniform<T>(ws.next()) - (T)1;
@@ -135,7 +136,7 @@ __device__ __forceinline__ void isotropic(WordStream& ws, T& dx, T& dy, T& dz) {
 template <class T>
 __device__ __forceinline__ T normal12(WordStream& ws) {
   int32_t S = 0;
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < 12; ++k) S += (int32_t)(2u * (ws.next() >> 9) + 1u);
   return (T)(S - 100663296) * (T)5.9604644775390625e-08;
 }

@@ -445,15 +445,116 @@ __device__ __forceinline__ bool push_one(const HotK<T>& H, const SpPtr<T>& P, ui
   }
 }
 
-// Collision inputs of one particle carried from the candidate test to the
-// collision: the second word of its stream, the two words left in block 0,
-// and the velocity components the push does not keep in registers.
+// Candidate test result of one particle carried to the collision queue: the
+// second word of its stream and the two words left in block 0.
 template <class T>
 struct CollIn {
   bool cand;
   uint32_t r1, wa, wb;
-  T vy, vz;
 };
+
+// Collision candidates of a workgroup wait in an LDS queue and are handled
+// densely (consecutive lanes take consecutive candidates), so the lanes of a
+// wave that do not collide do not pay for the collision of those that do.
+// The queue is drained once it holds kQDrain entries after a batch, and at
+// the end of the range; a batch adds at most K x kBlock entries.
+constexpr uint32_t kQCap = 384;
+constexpr uint32_t kQDrain = 128;
+
+template <class T, int DIM>
+struct CollQueue {
+  uint32_t* n;
+  uint32_t *i, *id, *r1, *wa, *wb, *w, *leaf;
+  T *v0, *s0, *s1, *v1;
+};
+template <class T, int DIM>
+__device__ __forceinline__ CollQueue<T, DIM> coll_queue() {
+  __shared__ uint32_t qn;
+  __shared__ uint32_t qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
+  __shared__ T qv0[kQCap], qs0[kQCap];
+  CollQueue<T, DIM> q;
+  q.n = &qn;
+  q.i = qi;
+  q.id = qid;
+  q.r1 = qr1;
+  q.wa = qwa;
+  q.wb = qwb;
+  q.w = qw;
+  q.v0 = qv0;
+  q.s0 = qs0;
+  if constexpr (DIM == 2) {
+    __shared__ uint32_t qleaf[kQCap];
+    __shared__ T qs1[kQCap], qv1[kQCap];
+    q.leaf = qleaf;
+    q.s1 = qs1;
+    q.v1 = qv1;
+  } else {
+    q.leaf = nullptr;
+    q.s1 = nullptr;
+    q.v1 = nullptr;
+  }
+  return q;
+}
+
+// Collide the queued candidates, write their velocities, stage the births
+// and add the newborn pairs' charge; empties the queue.  Every lane of the
+// workgroup calls it.
+template <class T, int DIM>
+__device__ void drain_queue(const InstDev<T>& I, const HotK<T>& H, const SpPtr<T>& P, int sp, uint32_t step,
+                            const CollQueue<T, DIM>& Q, unsigned long long* Qpar, DepCache& D, LStat& st) {
+  __syncthreads();
+  const uint32_t n = *Q.n;
+  for (uint32_t t0 = 0; t0 < n; t0 += kBlock) {
+    const uint32_t t = t0 + threadIdx.x;
+    bool birth = false;
+    BirthRec<T> rec;
+    uint32_t id = 0u, w = 0u, leaf = 0u;
+    T s0 = (T)0, s1 = (T)0;
+    if (t < n) {
+      const uint32_t i = Q.i[t];
+      id = Q.id[t];
+      w = Q.w[t];
+      s0 = Q.s0[t];
+      T vx = Q.v0[t], vy, vz = *at(P.v2, i);
+      if constexpr (DIM == 2) {
+        s1 = Q.s1[t];
+        leaf = Q.leaf[t];
+        vy = Q.v1[t];
+      } else {
+        vy = *at(P.v1, i);
+      }
+      WordStream ws(H.key0, H.key1, id, step, Q.wa[t], Q.wb[t]);
+      birth = collide<T>(I, H.k, id, step, Q.r1[t], ws, vx, vy, vz, st, rec);
+      *at(P.v0, i) = vx;
+      *at(P.v1, i) = vy;
+      *at(P.v2, i) = vz;
+    }
+    stage_birth<T>(I, birth, id, leaf, w, s0, s1, rec);
+    if (birth) {   // the newborn electron and ion sit on the parent
+      unsigned long long* Qs = Qpar + (size_t)sp * H.nq;
+      unsigned long long* Qi = Qpar + H.nq;
+      const unsigned long long ww = w;
+      if constexpr (DIM == 2) {
+        dep_add(D, Qs, leaf, ww);
+        gadd(Qi + leaf, ww);
+      } else {
+        const T g = s0 * (T)H.N;
+        int ic = (int)floor(g);
+        if (ic > H.N - 1) ic = H.N - 1;
+        const T fr = g - (T)ic;
+        const unsigned long long r = (unsigned long long)(long long)rint(fr * (T)(1ull << FixedPoint<T>::F));
+        const unsigned long long one = 1ull << FixedPoint<T>::F;
+        dep_add(D, Qs, (uint32_t)ic, ww * (one - r));
+        dep_add(D, Qs, (uint32_t)ic + 1u, ww * r);
+        if (one - r) gadd(Qi + ic, ww * (one - r));
+        if (r) gadd(Qi + ic + 1, ww * r);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *Q.n = 0u;
+  __syncthreads();
+}
 
 // One batch of K particles per lane (stages 1-7 above).  DIRECT: the lookup
 // table alone locates a point (no leaf is finer than its level).  FULL: every
@@ -466,7 +567,8 @@ struct CollIn {
 template <class T, bool MCC, int DIM, int K, bool DIRECT, bool FULL>
 __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>& H, const SpPtr<T>& P, int sp, uint32_t i0,
                                               PState<T> (&p)[K], PState<T> (&nxt)[K], uint32_t end, uint32_t step,
-                                              unsigned long long* Qpar, DepCache& D, LStat& st) {
+                                              unsigned long long* Qpar, DepCache& D, LStat& st,
+                                              const CollQueue<T, DIM>& Q) {
   const SpeciesK<T>& k = H.k;
   const bool mcc = MCC && k.mcc != PIC_MCC_NONE;
   const uint32_t inext0 = i0 + (uint32_t)K * kBlock;
@@ -517,16 +619,6 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
         ci[j].cand = (r0 >> 8) < k.tcand;
       }
     }
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const uint32_t i = i0 + (uint32_t)j * kBlock;
-      ci[j].vy = (T)0;
-      ci[j].vz = (T)0;
-      if (ci[j].cand) {
-        if (DIM == 1) ci[j].vy = *at(P.v1, i);
-        ci[j].vz = *at(P.v2, i);
-      }
-    }
   }
   // 6. stage B of the next batch
 #pragma unroll
@@ -537,25 +629,32 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
 #pragma unroll
     for (int j = 0; j < K; ++j) leaf[j] = moved[j] ? leaf[j] : p[j].cell;
   }
-  bool birth[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) birth[j] = false;
   if constexpr (MCC) {
     if (mcc) {
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        BirthRec<T> rec;
-        if (ci[j].cand) {
-          const uint32_t i = i0 + (uint32_t)j * kBlock;
-          T vy = DIM == 1 ? ci[j].vy : p[j].v1;
-          T vz = ci[j].vz;
-          WordStream ws(H.key0, H.key1, p[j].id, step, ci[j].wa, ci[j].wb);
-          birth[j] = collide<T>(I, k, p[j].id, step, ci[j].r1, ws, p[j].v0, vy, vz, st, rec);
-          if (DIM == 1) *at(P.v1, i) = vy;
-          else p[j].v1 = vy;
-          *at(P.v2, i) = vz;
+        const uint64_t bm = __ballot(ci[j].cand);
+        if (bm == 0ull) continue;
+        const int lane = lane_id();
+        const int leader = __ffsll((long long)bm) - 1;
+        uint32_t base = 0u;
+        if (lane == leader) base = atomicAdd(Q.n, (uint32_t)__popcll(bm));
+        base = __shfl(base, leader);
+        if (!ci[j].cand) continue;
+        const uint32_t t = base + (uint32_t)__popcll(bm & (lanes_le(lane) >> 1));
+        Q.i[t] = i0 + (uint32_t)j * kBlock;
+        Q.id[t] = p[j].id;
+        Q.r1[t] = ci[j].r1;
+        Q.wa[t] = ci[j].wa;
+        Q.wb[t] = ci[j].wb;
+        Q.w[t] = p[j].w;
+        Q.v0[t] = p[j].v0;
+        Q.s0[t] = p[j].s0;
+        if constexpr (DIM == 2) {
+          Q.s1[t] = p[j].s1;
+          Q.v1[t] = p[j].v1;
+          Q.leaf[t] = leaf[j];
         }
-        stage_birth<T>(I, birth[j], p[j].id, DIM == 2 ? leaf[j] : 0u, p[j].w, p[j].s0, p[j].s1, rec);
       }
     }
   }
@@ -587,8 +686,7 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
     const unsigned long long w = p[j].w;
     unsigned long long* Qs = Qpar + (size_t)sp * H.nq;
     if (DIM == 2) {
-      dep_add(D, Qs, leaf[j], (birth[j] ? 2ull : 1ull) * w);
-      if (MCC && birth[j]) gadd(Qpar + H.nq + leaf[j], w);
+      dep_add(D, Qs, leaf[j], w);
     } else {
       // CIC shares in 64-bit fixed point
       const T g = p[j].s0 * (T)H.N;
@@ -597,14 +695,8 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
       const T fr = g - (T)ic;
       const unsigned long long r = (unsigned long long)(long long)rint(fr * (T)(1ull << FixedPoint<T>::F));
       const unsigned long long one = 1ull << FixedPoint<T>::F;
-      const unsigned long long mult = birth[j] ? 2ull : 1ull;
-      dep_add(D, Qs, (uint32_t)ic, mult * w * (one - r));
-      dep_add(D, Qs, (uint32_t)ic + 1u, mult * w * r);
-      if (MCC && birth[j]) {   // the newborn ion sits on the parent
-        unsigned long long* Qi = Qpar + H.nq;
-        if (one - r) gadd(Qi + ic, w * (one - r));
-        if (r) gadd(Qi + ic + 1, w * r);
-      }
+      dep_add(D, Qs, (uint32_t)ic, w * (one - r));
+      dep_add(D, Qs, (uint32_t)ic + 1u, w * r);
     }
   }
 }
@@ -674,6 +766,13 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   __shared__ uint32_t wbase_s;
   const SpPtr<T> P = species_ptrs<T>(I, sp);
   const HotK<T> H = hot_constants<T>(I, sp);
+  const bool mcc = MCC && H.k.mcc != PIC_MCC_NONE;   // uniform over the workgroup
+  CollQueue<T, DIM> Q{};
+  if constexpr (MCC) {
+    static_assert(kQDrain - 1u + (uint32_t)K * kBlock <= kQCap, "collision queue too small for a batch");
+    Q = coll_queue<T, DIM>();
+    if (threadIdx.x == 0) *Q.n = 0u;
+  }
   DepCache D{win, hkey, hval, 0u};
   dep_zero(D);
   if (threadIdx.x == 0) {
@@ -695,25 +794,53 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   __syncthreads();
   D.base = wbase_s;
   LStat st = {0, 0, 0, 0, 0, 0, 0};
-  // Full batches two per trip with the state buffers swapping roles, so the
-  // prefetched state is never copied between registers (a copy would wait);
-  // then the partial batch, if any.
+  // Batches with the state buffers swapping roles (cur -> nxt, then nxt ->
+  // cur), so the prefetched state is never copied between registers (a copy
+  // would wait for it).
   const uint32_t unit = (uint32_t)K * kBlock;
   uint32_t base = begin;
-  bool in_cur = true;
-  while (end - base >= unit) {
-    process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, base + threadIdx.x, cur, nxt, end, step, Qpar, D, st);
-    base += unit;
-    if (end - base < unit) {
-      in_cur = false;
-      break;
+  if constexpr (!MCC) {
+    // two full batches per trip, then the partial batch
+    bool in_cur = true;
+    while (end - base >= unit) {
+      process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, base + threadIdx.x, cur, nxt, end, step, Qpar, D, st, Q);
+      base += unit;
+      if (end - base < unit) {
+        in_cur = false;
+        break;
+      }
+      process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st, Q);
+      base += unit;
     }
-    process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st);
-    base += unit;
-  }
-  if (base < end) {
-    if (in_cur) process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, cur, nxt, end, step, Qpar, D, st);
-    else process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st);
+    if (base < end) {
+      if (in_cur) process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, cur, nxt, end, step, Qpar, D, st, Q);
+      else process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st, Q);
+    }
+  } else {
+    // collision kernels: one batch per trip; the candidate queue is drained
+    // at the top of a trip once it holds kQDrain entries, and at the end.
+    // The single drain site keeps the collision code in the kernel once.
+    bool in_cur = true;
+    for (;;) {
+      const bool done = base >= end;
+      if (mcc) {
+        __syncthreads();
+        const uint32_t nq = *Q.n;
+        if (nq >= kQDrain || (done && nq > 0u)) drain_queue<T, DIM>(I, H, P, sp, step, Q, Qpar, D, st);
+      }
+      if (done) break;
+      const uint32_t i0 = base + threadIdx.x;
+      if (end - base >= unit) {
+        if (in_cur) process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, i0, cur, nxt, end, step, Qpar, D, st, Q);
+        else process_batch<T, MCC, DIM, K, DIRECT, true>(I, H, P, sp, i0, nxt, cur, end, step, Qpar, D, st, Q);
+        base += unit;
+      } else {
+        if (in_cur) process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, i0, cur, nxt, end, step, Qpar, D, st, Q);
+        else process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, i0, nxt, cur, end, step, Qpar, D, st, Q);
+        base = end;
+      }
+      in_cur = !in_cur;
+    }
   }
   __syncthreads();
   dep_flush(D, Qpar + (size_t)sp * I.nq, I.nq);
@@ -796,10 +923,15 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
 }
 
 // ---------------------------------------------------------------------------
-// Births: rank by parent id (count of smaller staged parent ids), then append
-// the electron at count[0] + r with id next_id + 2r and the ion at
-// count[1] + r with id next_id + 2r + 1.
+// Births: rank by parent id (count of smaller staged parent ids; the ids are
+// distinct), then append the electron at count[0] + r with id next_id + 2r
+// and the ion at count[1] + r with id next_id + 2r + 1.  A workgroup ranks
+// kRankPer births per lane at a time against all staged parent ids streamed
+// through LDS, so each LDS read serves kRankPer comparisons.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kRankPer = 4;
+constexpr int kBirthBlocks = 256;   // workgroups per instance of the births kernels
+
 template <class T>
 __device__ void births_body(const InstDev<T>& I, uint32_t first_block, uint32_t nblocks) {
   __shared__ uint32_t sh[1024];
@@ -813,19 +945,31 @@ __device__ void births_body(const InstDev<T>& I, uint32_t first_block, uint32_t 
       atomicOr(&I.ctr->flags, (!cap_ok ? kFlagBirthOverflow : 0u) | (!id_ok ? kFlagIdOverflow : 0u));
     return;
   }
-  for (uint32_t ib = first_block * kBlock; ib < nb; ib += nblocks * kBlock) {
-    const uint32_t i = ib + threadIdx.x;
-    const uint32_t mine = i < nb ? I.br.parent[i] : 0xFFFFFFFFu;
-    uint32_t r = 0;
+  const uint32_t tile = kRankPer * kBlock;
+  for (uint32_t ib = first_block * tile; ib < nb; ib += nblocks * tile) {
+    uint32_t mine[kRankPer], r[kRankPer];
+#pragma unroll
+    for (uint32_t q = 0; q < kRankPer; ++q) {
+      const uint32_t i = ib + q * kBlock + threadIdx.x;
+      mine[q] = i < nb ? I.br.parent[i] : 0xFFFFFFFFu;
+      r[q] = 0u;
+    }
     for (uint32_t jb = 0; jb < nb; jb += 1024u) {
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < 1024u && jb + t < nb; t += kBlock) sh[t] = I.br.parent[jb + t];
       __syncthreads();
       const uint32_t lim = (nb - jb) < 1024u ? (nb - jb) : 1024u;
-      for (uint32_t j = 0; j < lim; ++j) r += (sh[j] < mine) ? 1u : 0u;
+      for (uint32_t j = 0; j < lim; ++j) {
+        const uint32_t v = sh[j];
+#pragma unroll
+        for (uint32_t q = 0; q < kRankPer; ++q) r[q] += (v < mine[q]) ? 1u : 0u;
+      }
     }
-    if (i < nb) {
-      const uint32_t pe = c0 + r, pi = c1 + r;
+#pragma unroll
+    for (uint32_t q = 0; q < kRankPer; ++q) {
+      const uint32_t i = ib + q * kBlock + threadIdx.x;
+      if (i >= nb) continue;
+      const uint32_t pe = c0 + r[q], pi = c1 + r[q];
       const uint32_t w = I.br.w[i];
       I.s[0][0][pe] = I.br.s[0][i];
       I.s[1][0][pi] = I.br.s[0][i];
@@ -841,8 +985,8 @@ __device__ void births_body(const InstDev<T>& I, uint32_t first_block, uint32_t 
       }
       I.w[0][pe] = w;
       I.w[1][pi] = w;
-      I.id[0][pe] = nid + 2u * r;
-      I.id[1][pi] = nid + 2u * r + 1u;
+      I.id[0][pe] = nid + 2u * r[q];
+      I.id[1][pi] = nid + 2u * r[q] + 1u;
     }
   }
 }
@@ -1042,7 +1186,7 @@ hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid) {
 }
 template <class T>
 hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s) {
-  hipLaunchKernelGGL(k_births_batched<T>, dim3(32, ninst), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_births_batched<T>, dim3(kBirthBlocks, ninst), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
 template <class T>
