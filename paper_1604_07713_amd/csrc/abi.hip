@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "api_internal.hpp"
+#include "k_mesh.hpp"
 #include "device_util.hpp"
 #include "pic_internal.hpp"
 
@@ -263,6 +264,40 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   hip_check(hipMemcpyAsync(C.b_rowbeg, C.stage(rb.data(), 4 * rb.size()), 4 * rb.size(), hipMemcpyHostToDevice,
                            C.stream),
             "rowbeg");
+  // Batched sort of every selected slot (both species at once), replacing
+  // per-slot sorts; the slots' own device descriptors are refreshed once at
+  // the end of the call.
+  bool sorted_any = false;
+  auto sort_all = [&]() {
+    std::vector<SortJob<T>> jobs(2 * (size_t)nsel);
+    uint32_t max_ncell = 0;
+    for (int j = 0; j < nsel; ++j) {
+      Slot& sl = *sel[j];
+      const uint32_t N = (uint32_t)sl.d.ncells;
+      for (int sp = 0; sp < 2; ++sp) {
+        SortJob<T>& J = jobs[2 * (size_t)j + sp];
+        J.off = nullptr;
+        J.ncell = N;
+        if (sp >= sl.d.nspecies || !sl.pb[sp][0].base) continue;
+        PBuf& d = sl.pb[sp][1 - sl.cur[sp]];
+        J.off = sl.off + (size_t)sp * (N + 1);
+        J.dst = SortDst<T>{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
+        max_ncell = std::max(max_ncell, N);
+      }
+    }
+    ensure(C.b_jobs, C.b_jobs_bytes, sizeof(SortJob<T>) * jobs.size());
+    hip_check(hipMemcpyAsync(C.b_jobs, C.stage(jobs.data(), sizeof(SortJob<T>) * jobs.size()),
+                             sizeof(SortJob<T>) * jobs.size(), hipMemcpyHostToDevice, C.stream),
+              "sort jobs");
+    hip_check(launch_sort_batched<T>((const InstDev<T>*)C.b_insts, (const SortJob<T>*)C.b_jobs, 2 * nsel, max_ncell,
+                                     (const WorkItem*)C.b_items, (uint32_t)issued.size(),
+                                     (int)std::min<size_t>(issued.size(), 2048), C.stream),
+              "sort batched");
+    for (int j = 0; j < nsel; ++j)
+      for (int sp = 0; sp < sel[j]->d.nspecies; ++sp)
+        if (jobs[2 * (size_t)j + sp].off) sel[j]->cur[sp] = 1 - sel[j]->cur[sp];
+    sorted_any = true;
+  };
   auto upload_insts = [&]() {
     std::vector<InstDev<T>> v(nsel);
     for (int j = 0; j < nsel; ++j) v[j] = make_dev<T>(*sel[j]);
@@ -317,7 +352,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
       }
       since_sort += k - k_prev;
       if (a->sort_every > 0 && k < kend && since_sort >= a->sort_every) {
-        for (Slot* s : sel) sort_slot(C, *s);
+        sort_all();
         upload_insts();
         since_sort = 0;
       }
@@ -337,12 +372,14 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
       if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
       one_commit(C.stream);
       if (a->sort_every > 0 && (k + 1) % a->sort_every == 0 && k + 1 < kend) {
-        for (Slot* s : sel) sort_slot(C, *s);
+        sort_all();
         upload_insts();
       }
     }
   }
   hip_check(launch_stats_reduce<T>(dI, nsel, C.b_part, C.b_rowbeg, 0u, C.stream), "stats_reduce batched");
+  if (sorted_any)
+    for (Slot* s : sel) upload_dev(C, *s);
   if (loop_ms) {
     C.sync();
     for (int64_t k = kbeg; k < kend; ++k) {
@@ -391,7 +428,7 @@ void pic_destroy(pic_ctx c) {
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  for (void* p : {c->b_insts, c->b_items, (void*)c->b_part, (void*)c->b_rowbeg})
+  for (void* p : {c->b_insts, c->b_items, (void*)c->b_part, (void*)c->b_rowbeg, c->b_jobs})
     if (p) (void)hipFree(p);
   if (c->arena) (void)hipHostFree(c->arena);
   delete c;
@@ -468,7 +505,7 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
   cn.count[species] = (uint32_t)n;
   cn.next_id = std::max(cn.next_id, std::max(sl.max_id_loaded[0], sl.max_id_loaded[1]));
   write_counters(*c, sl, cn);
-  if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) alloc_births(sl, sl.cap[0]);
+  if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) alloc_births(*c, sl, sl.cap[0]);
   if (dim == 2 && n) {
     if (sl.prec == 32) hip_check(launch_relocate<float>(make_dev<float>(sl), species, c->stream, grid_for(n)), "relocate");
     else hip_check(launch_relocate<double>(make_dev<double>(sl), species, c->stream, grid_for(n)), "relocate");

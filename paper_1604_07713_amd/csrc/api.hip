@@ -380,7 +380,7 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
     sl.e64 = (double*)sl.alloc(8 * (N + 1));
     sl.phi64 = (double*)sl.alloc(8 * (N + 1));
     sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
-    sl.off = (uint32_t*)sl.alloc(4 * ((size_t)N + 1));
+    sl.off = (uint32_t*)sl.alloc(8 * ((size_t)N + 1));   // one offset array per species (batched sort)
     hip_check(hipMemsetAsync(sl.E, 0, sl.esz * (N + 1), C.stream), "memset");
     hip_check(hipMemsetAsync(sl.e64, 0, 8 * (N + 1), C.stream), "memset");
     hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (N + 1), C.stream), "memset");
@@ -419,13 +419,13 @@ void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
   b.cell = sl.d.dim == 2 ? (uint32_t*)carve(4 * c) : nullptr;
 }
 
-void alloc_births(Slot& sl, int64_t cap) {
+void alloc_births(Ctx& C, Slot& sl, int64_t cap) {
   if (sl.birth_base) sl.release(sl.birth_base);
   sl.birth_base = nullptr;
   sl.birth_cap = 0;
   if (!sl.ionizing) return;
   const size_t e = sl.esz, c = (size_t)cap;
-  char* p = (char*)sl.alloc((12 + 8 * e) * c + 16 * 256);
+  char* p = (char*)sl.alloc((16 + 8 * e) * c + 16 * 256);
   sl.birth_base = p;
   size_t o = 0;
   auto carve = [&](size_t n) {
@@ -434,6 +434,8 @@ void alloc_births(Slot& sl, int64_t cap) {
     return q;
   };
   sl.br_parent = (uint32_t*)carve(4 * c);
+  sl.br_rank = (uint32_t*)carve(4 * c);
+  hip_check(hipMemsetAsync(sl.br_rank, 0, 4 * c, C.stream), "memset");   // the births kernels keep it zero
   sl.br_cell = (uint32_t*)carve(4 * c);
   sl.br_w = (uint32_t*)carve(4 * c);
   for (int k = 0; k < 2; ++k) sl.br_s[k] = carve(e * c);
@@ -475,6 +477,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.Q = sl.Q;
   I.nq = sl.nq;
   I.br.parent = sl.br_parent;
+  I.br.rank = sl.br_rank;
   I.br.cell = sl.br_cell;
   I.br.w = sl.br_w;
   for (int k = 0; k < 2; ++k) I.br.s[k] = (T*)sl.br_s[k];
@@ -569,7 +572,7 @@ void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
     }
   }
   if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) {
-    alloc_births(sl, sl.cap[0]);
+    alloc_births(C, sl, sl.cap[0]);
     changed = true;
   }
   if (changed) upload_dev(C, sl);

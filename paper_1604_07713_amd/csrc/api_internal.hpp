@@ -55,7 +55,7 @@ struct Slot {
   int64_t cap[2] = {0, 0};
   // births staging
   void* birth_base = nullptr;
-  uint32_t *br_parent = nullptr, *br_cell = nullptr, *br_w = nullptr;
+  uint32_t *br_parent = nullptr, *br_rank = nullptr, *br_cell = nullptr, *br_w = nullptr;
   void* br_s[2] = {nullptr, nullptr};
   void* br_ve[3] = {nullptr, nullptr, nullptr};
   void* br_vi[3] = {nullptr, nullptr, nullptr};
@@ -108,6 +108,8 @@ struct Ctx {
   size_t b_part_bytes = 0;
   uint32_t* b_rowbeg = nullptr;
   size_t b_rowbeg_bytes = 0;
+  void* b_jobs = nullptr;   // batched sort jobs, two per slot
+  size_t b_jobs_bytes = 0;
   // graph capture stream (default priority) and the events joining it to the caller's stream
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -122,7 +124,7 @@ void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L);
 void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n, int maxlv);
 void adapt_slot(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out);
 void alloc_particles(Slot& sl, int sp, int64_t cap, int which);
-void alloc_births(Slot& sl, int64_t cap);
+void alloc_births(Ctx& C, Slot& sl, int64_t cap);
 template <class T> InstDev<T> make_dev(const Slot& sl);
 void upload_dev(Ctx& C, Slot& sl);
 Counters read_counters(Ctx& C, Slot& sl);

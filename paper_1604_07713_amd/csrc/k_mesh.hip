@@ -77,15 +77,13 @@ __device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp
   return c0 > kSortMargin ? c0 - kSortMargin : 0u;
 }
 
-// Histogram of cells over one contiguous chunk per workgroup, pre-aggregated
-// in an LDS window of cells.
+// Histogram of cells over one contiguous range [begin, end) per workgroup,
+// pre-aggregated in an LDS window of cells.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint32_t* hist, uint32_t chunk) {
+__device__ void sort_hist_range(const InstDev<T>& I, int sp, uint32_t* hist, uint32_t begin, uint32_t end) {
   __shared__ uint32_t win[kSortWin];
   __shared__ uint32_t base_s;
-  const uint32_t count = I.ctr->count[sp];
-  const uint32_t begin = blockIdx.x * chunk;
-  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  __syncthreads();   // the window may still be read by a previous range
   for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) win[j] = 0u;
   if (threadIdx.x == 0) {
     base_s = begin < end ? sort_window_base<T>(I, sp, begin) : 0u;
@@ -104,8 +102,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint
     if (win[j]) gadd32(hist + (uint32_t)(base + j), win[j]);
 }
 
-// single-workgroup exclusive scan of n counts in place; a[n] = total
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_hist(InstDev<T> I, int sp, uint32_t* hist, uint32_t chunk) {
+  const uint32_t count = I.ctr->count[sp];
+  const uint32_t begin = blockIdx.x * chunk;
+  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  sort_hist_range<T>(I, sp, hist, begin, end);
+}
+
+// Single-workgroup exclusive scan of n counts in place; a[n] = total.
+__device__ void scan_excl_body(uint32_t* a, uint32_t n) {
   __shared__ uint32_t part[1024];
   const uint32_t t = threadIdx.x;
   const uint32_t chunk = (n + 1023u) / 1024u;
@@ -129,19 +135,19 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) {
   if (t == 1023u) a[n] = part[1023];
 }
 
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) { scan_excl_body(a, n); }
+
 // Scatter to the sorted position: per tile of kBlock particles, ranks within
 // the tile come from LDS atomics on a window of cells, and one global atomic
 // per touched cell reserves the tile's range in that cell.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, uint32_t* off, uint32_t chunk, T* ds0,
-                                                         T* ds1, T* dv0, T* dv1, T* dv2, uint32_t* dw, uint32_t* did,
-                                                         uint32_t* dcell) {
+__device__ void sort_scatter_range(const InstDev<T>& I, int sp, uint32_t* off, uint32_t begin, uint32_t end,
+                                   const SortDst<T>& d) {
   __shared__ uint32_t lcnt[kSortWin];
   __shared__ uint32_t gbase[kSortWin];
   __shared__ uint32_t base_s;
-  const uint32_t count = I.ctr->count[sp];
-  const uint32_t begin = blockIdx.x * chunk;
-  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  T *ds0 = d.s0, *ds1 = d.s1, *dv0 = d.v0, *dv1 = d.v1, *dv2 = d.v2;
+  uint32_t *dw = d.w, *did = d.id, *dcell = d.cell;
   for (uint32_t t0 = begin; t0 < end; t0 += kBlock) {
     for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) lcnt[j] = 0u;
     if (threadIdx.x == 0) {
@@ -179,6 +185,60 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, u
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, uint32_t* off, uint32_t chunk,
+                                                         SortDst<T> d) {
+  const uint32_t count = I.ctr->count[sp];
+  const uint32_t begin = blockIdx.x * chunk;
+  const uint32_t end = begin + chunk < count ? begin + chunk : count;
+  sort_scatter_range<T>(I, sp, off, begin, end, d);
+}
+
+// ---- batched: one launch per phase over (slot, species) jobs ----
+// Work items are (slot, species, particle range) as in the batched step;
+// job 2 * slot + species holds that species' counters and destination.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_fill_batched(const SortJob<T>* jobs) {
+  const SortJob<T>& J = jobs[blockIdx.y];
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i <= J.ncell; i += gridDim.x * kBlock) J.off[i] = 0u;
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_hist_batched(const InstDev<T>* insts, const SortJob<T>* jobs,
+                                                              const WorkItem* items, uint32_t nitems) {
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const SortJob<T>& J = jobs[2u * wi.inst + wi.species];
+    if (!J.off) continue;
+    const InstDev<T>& I = insts[wi.inst];
+    const uint32_t count = I.ctr->count[wi.species];
+    const uint32_t end = wi.end < count ? wi.end : count;
+    if (wi.begin < end) sort_hist_range<T>(I, (int)wi.species, J.off, wi.begin, end);
+  }
+}
+template <class T>
+__global__ __launch_bounds__(1024) void k_sort_scan_batched(const SortJob<T>* jobs) {
+  const SortJob<T>& J = jobs[blockIdx.x];
+  if (J.off) scan_excl_body(J.off, J.ncell);
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter_batched(const InstDev<T>* insts, const SortJob<T>* jobs,
+                                                                 const WorkItem* items, uint32_t nitems) {
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const SortJob<T>& J = jobs[2u * wi.inst + wi.species];
+    if (!J.off) continue;
+    const InstDev<T>& I = insts[wi.inst];
+    const uint32_t count = I.ctr->count[wi.species];
+    const uint32_t end = wi.end < count ? wi.end : count;
+    if (wi.begin < end) sort_scatter_range<T>(I, (int)wi.species, J.off, wi.begin, end, J.dst);
+  }
+}
+template <class T>
+__global__ void k_sort_count_batched(const InstDev<T>* insts, const SortJob<T>* jobs) {
+  const SortJob<T>& J = jobs[blockIdx.x];
+  if (threadIdx.x == 0 && J.off) insts[blockIdx.x / 2u].ctr->count[blockIdx.x % 2u] = J.off[J.ncell];
+}
+
 __global__ void k_fill_u32(uint32_t* a, uint32_t n, uint32_t v) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = v;
 }
@@ -193,12 +253,27 @@ hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* of
                      dim3(kBlock), 0, s, off, ncell + 1u, 0u);
   hipLaunchKernelGGL(k_sort_hist<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk);
   hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, off, ncell);
-  hipLaunchKernelGGL(k_sort_scatter<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk, d.s0, d.s1, d.v0, d.v1,
-                     d.v2, d.w, d.id, d.cell);
+  hipLaunchKernelGGL(k_sort_scatter<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk, d);
   hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, I.ctr, sp, off + ncell);
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_sort_batched(const InstDev<T>* insts, const SortJob<T>* jobs, int njobs, uint32_t max_ncell,
+                               const WorkItem* items, uint32_t nitems, int grid, hipStream_t s) {
+  const uint32_t fill_x = ceil_div(max_ncell + 1u, kBlock) < 64u ? ceil_div(max_ncell + 1u, kBlock) : 64u;
+  hipLaunchKernelGGL(k_sort_fill_batched<T>, dim3(fill_x, njobs), dim3(kBlock), 0, s, jobs);
+  hipLaunchKernelGGL(k_sort_hist_batched<T>, dim3(grid), dim3(kBlock), 0, s, insts, jobs, items, nitems);
+  hipLaunchKernelGGL(k_sort_scan_batched<T>, dim3(njobs), dim3(1024), 0, s, jobs);
+  hipLaunchKernelGGL(k_sort_scatter_batched<T>, dim3(grid), dim3(kBlock), 0, s, insts, jobs, items, nitems);
+  hipLaunchKernelGGL(k_sort_count_batched<T>, dim3(njobs), dim3(64), 0, s, insts, jobs);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sort_batched<float>(const InstDev<float>*, const SortJob<float>*, int, uint32_t,
+                                               const WorkItem*, uint32_t, int, hipStream_t);
+template hipError_t launch_sort_batched<double>(const InstDev<double>*, const SortJob<double>*, int, uint32_t,
+                                                const WorkItem*, uint32_t, int, hipStream_t);
 template hipError_t launch_sort<float>(const InstDev<float>&, int, uint32_t, uint32_t*, const SortDst<float>&, int,
                                        hipStream_t);
 template hipError_t launch_sort<double>(const InstDev<double>&, int, uint32_t, uint32_t*, const SortDst<double>&, int,

@@ -10,6 +10,22 @@ struct SortDst {
   uint32_t *w, *id, *cell;
 };
 
+// One (slot, species) of a batched sort: its offsets (ncell + 1 words, or
+// null to skip), its cell count and its destination arrays.
+template <class T>
+struct SortJob {
+  uint32_t* off;
+  uint32_t ncell;
+  SortDst<T> dst;
+};
+
+// Batched sort of many slots: jobs[2 * slot + species], work items as in the
+// batched step (slot, species, particle range); every job's species is
+// reordered by cell and its count set.
+template <class T>
+hipError_t launch_sort_batched(const InstDev<T>* insts, const SortJob<T>* jobs, int njobs, uint32_t max_ncell,
+                               const WorkItem* items, uint32_t nitems, int grid, hipStream_t s);
+
 // Reorder one species by cell into the arrays of d, dropping holes; the new
 // particle count is written to the instance counters.  off: ncell + 1 words.
 template <class T>

@@ -42,55 +42,71 @@ __device__ __forceinline__ bool wall_rule(bool reflect, T& s, T& v, bool& lost) 
   return in1;
 }
 
-// Null-collision MCC for one particle (v in registers; vy/vz already loaded).
-// Returns true if an ionization produced a birth (rec filled).
+// Null-collision MCC of one candidate (v in registers), in two parts so a
+// workgroup can first sort its candidates by what happens to them and then
+// run each process densely.  collision_kind: electron elastic scattering,
+// ionization or a null collision (from u1 = the candidate's second word);
+// ions always go on to the charge-exchange test, whose partner velocity is
+// needed to decide.  collide_as: that process; returns true when an
+// ionization produced a birth (rec filled).
+enum : uint32_t { kCollNone = 0u, kCollElastic = 1u, kCollIonize = 2u, kCollCx = 3u };
+
 template <class T>
-__device__ __forceinline__ bool collide(const InstDev<T>& I, const SpeciesK<T>& k, uint32_t pid, uint32_t step,
-                                        uint32_t r1, WordStream& ws, T& vx, T& vy, T& vz, LStat& st,
-                                        BirthRec<T>& rec) {
+__device__ __forceinline__ uint32_t collision_kind(const SpeciesK<T>& k, uint32_t r1, T vx, T vy, T vz,
+                                                   LStat& st) {
+  if (k.mcc != PIC_MCC_ELECTRON) return kCollCx;
   const T u1 = unit_uniform<T>(r1);
-  if (k.mcc == PIC_MCC_ELECTRON) {
+  const T v2 = (vx * vx + vy * vy) + vz * vz;
+  st.viol += (v2 > k.vmax2) ? 1u : 0u;
+  const T vmag = sqrt(v2);
+  const T x_el = k.a_el * vmag;
+  if (u1 < x_el) return kCollElastic;
+  if (v2 >= k.v_iz2 && u1 < x_el + k.a_iz * vmag) return kCollIonize;
+  return kCollNone;
+}
+
+template <class T>
+__device__ __forceinline__ bool collide_as(uint32_t kind, const SpeciesK<T>& k, uint32_t r1, WordStream& ws, T& vx,
+                                           T& vy, T& vz, LStat& st, BirthRec<T>& rec) {
+  if (kind == kCollElastic) {
     const T v2 = (vx * vx + vy * vy) + vz * vz;
-    st.viol += (v2 > k.vmax2) ? 1u : 0u;
     const T vmag = sqrt(v2);
-    const T x_el = k.a_el * vmag;
-    if (u1 < x_el) {
-      T dx, dy, dz;
-      isotropic<T>(ws, dx, dy, dz);
-      const T vd = (vx * dx + vy * dy) + vz * dz;
-      T vp2 = v2 - k.mu2 * (v2 - vmag * vd);
-      if (vp2 < (T)0) vp2 = (T)0;
-      const T vpm = sqrt(vp2);
-      vx = vpm * dx;
-      vy = vpm * dy;
-      vz = vpm * dz;
-      st.elastic++;
-      return false;
-    }
-    if (v2 >= k.v_iz2 && u1 < x_el + k.a_iz * vmag) {
-      const T u0 = unit_uniform<T>(ws.next());
-      const T v2ex = v2 - k.v_iz2;
-      const T v2a = u0 * v2ex;
-      const T v2b = v2ex - v2a;
-      T ax, ay, az, bx, by, bz;
-      isotropic<T>(ws, ax, ay, az);
-      isotropic<T>(ws, bx, by, bz);
-      const T va = sqrt(v2a), vb = sqrt(v2b);
-      vx = va * ax;
-      vy = va * ay;
-      vz = va * az;
-      rec.ve0 = vb * bx;
-      rec.ve1 = vb * by;
-      rec.ve2 = vb * bz;
-      rec.vi0 = k.v_thg * normal12<T>(ws);
-      rec.vi1 = k.v_thg * normal12<T>(ws);
-      rec.vi2 = k.v_thg * normal12<T>(ws);
-      st.ionization++;
-      return true;
-    }
+    T dx, dy, dz;
+    isotropic<T>(ws, dx, dy, dz);
+    const T vd = (vx * dx + vy * dy) + vz * dz;
+    T vp2 = v2 - k.mu2 * (v2 - vmag * vd);
+    if (vp2 < (T)0) vp2 = (T)0;
+    const T vpm = sqrt(vp2);
+    vx = vpm * dx;
+    vy = vpm * dy;
+    vz = vpm * dz;
+    st.elastic++;
     return false;
   }
+  if (kind == kCollIonize) {
+    const T v2 = (vx * vx + vy * vy) + vz * vz;
+    const T u0 = unit_uniform<T>(ws.next());
+    const T v2ex = v2 - k.v_iz2;
+    const T v2a = u0 * v2ex;
+    const T v2b = v2ex - v2a;
+    T ax, ay, az, bx, by, bz;
+    isotropic<T>(ws, ax, ay, az);
+    isotropic<T>(ws, bx, by, bz);
+    const T va = sqrt(v2a), vb = sqrt(v2b);
+    vx = va * ax;
+    vy = va * ay;
+    vz = va * az;
+    rec.ve0 = vb * bx;
+    rec.ve1 = vb * by;
+    rec.ve2 = vb * bz;
+    rec.vi0 = k.v_thg * normal12<T>(ws);
+    rec.vi1 = k.v_thg * normal12<T>(ws);
+    rec.vi2 = k.v_thg * normal12<T>(ws);
+    st.ionization++;
+    return true;
+  }
   // ion charge exchange with a gas atom drawn from the gas Maxwellian
+  const T u1 = unit_uniform<T>(r1);
   const T n0 = k.v_thg * normal12<T>(ws);
   const T n1 = k.v_thg * normal12<T>(ws);
   const T n2 = k.v_thg * normal12<T>(ws);
@@ -463,17 +479,21 @@ constexpr uint32_t kQDrain = 128;
 
 template <class T, int DIM>
 struct CollQueue {
-  uint32_t* n;
+  uint32_t *n, *nel, *nx;   // candidates; elastic and expensive collisions found among them
+  uint32_t* e;              // collision list: elastic from the front, others from the back
   uint32_t *i, *id, *r1, *wa, *wb, *w, *leaf;
   T *v0, *s0, *s1, *v1;
 };
 template <class T, int DIM>
 __device__ __forceinline__ CollQueue<T, DIM> coll_queue() {
-  __shared__ uint32_t qn;
-  __shared__ uint32_t qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
+  __shared__ uint32_t qn, qnel, qnx;
+  __shared__ uint32_t qe[kQCap], qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
   __shared__ T qv0[kQCap], qs0[kQCap];
   CollQueue<T, DIM> q;
   q.n = &qn;
+  q.nel = &qnel;
+  q.nx = &qnx;
+  q.e = qe;
   q.i = qi;
   q.id = qid;
   q.r1 = qr1;
@@ -496,35 +516,80 @@ __device__ __forceinline__ CollQueue<T, DIM> coll_queue() {
   return q;
 }
 
-// Collide the queued candidates, write their velocities, stage the births
-// and add the newborn pairs' charge; empties the queue.  Every lane of the
-// workgroup calls it.
+// Collide the queued candidates: classify them (null collisions end there),
+// then run elastic scattering and the expensive processes (ionization with
+// its newborn pair, charge exchange with its Maxwellian partner) each one
+// collision per lane; write the velocities, stage the births and add the
+// newborn pairs' charge.  Empties the queue.  Every lane of the workgroup
+// calls it.
 template <class T, int DIM>
-__device__ void drain_queue(const InstDev<T>& I, const HotK<T>& H, const SpPtr<T>& P, int sp, uint32_t step,
-                            const CollQueue<T, DIM>& Q, unsigned long long* Qpar, DepCache& D, LStat& st) {
+__device__ __forceinline__ void drain_queue(const InstDev<T>& I, const HotK<T>& H, const SpPtr<T>& P, int sp,
+                                         uint32_t step, const CollQueue<T, DIM>& Q, unsigned long long* Qpar,
+                                         DepCache& D, LStat& st) {
+  if (threadIdx.x == 0) {
+    *Q.nel = 0u;
+    *Q.nx = 0u;
+  }
   __syncthreads();
   const uint32_t n = *Q.n;
+  const int lane = lane_id();
   for (uint32_t t0 = 0; t0 < n; t0 += kBlock) {
     const uint32_t t = t0 + threadIdx.x;
+    uint32_t kind = kCollNone;
+    if (t < n) {
+      const uint32_t i = Q.i[t];
+      const T vy = DIM == 2 ? Q.v1[t] : *at(P.v1, i);
+      const T vz = *at(P.v2, i);
+      kind = collision_kind<T>(H.k, Q.r1[t], Q.v0[t], vy, vz, st);
+    }
+    const uint64_t be = __ballot(kind == kCollElastic);
+    const uint64_t bx = __ballot(kind == kCollIonize || kind == kCollCx);
+    uint32_t base_e = 0u, base_x = 0u;
+    if (lane == 0) {
+      if (be) base_e = atomicAdd(Q.nel, (uint32_t)__popcll(be));
+      if (bx) base_x = atomicAdd(Q.nx, (uint32_t)__popcll(bx));
+    }
+    base_e = __shfl(base_e, 0);
+    base_x = __shfl(base_x, 0);
+    const uint64_t below = lanes_le(lane) >> 1;
+    if (kind == kCollElastic) Q.e[base_e + (uint32_t)__popcll(be & below)] = t;
+    else if (kind != kCollNone) Q.e[kQCap - 1u - (base_x + (uint32_t)__popcll(bx & below))] = t | (kind << 16);
+  }
+  __syncthreads();
+  const uint32_t nel = *Q.nel, nx = *Q.nx;
+  for (uint32_t t0 = 0; t0 < nel; t0 += kBlock) {
+    const uint32_t t2 = t0 + threadIdx.x;
+    if (t2 < nel) {
+      const uint32_t t = Q.e[t2], i = Q.i[t];
+      T vx = Q.v0[t], vy = DIM == 2 ? Q.v1[t] : *at(P.v1, i), vz = *at(P.v2, i);
+      WordStream ws(H.key0, H.key1, Q.id[t], step, Q.wa[t], Q.wb[t]);
+      BirthRec<T> rec;
+      (void)collide_as<T>(kCollElastic, H.k, Q.r1[t], ws, vx, vy, vz, st, rec);
+      *at(P.v0, i) = vx;
+      *at(P.v1, i) = vy;
+      *at(P.v2, i) = vz;
+    }
+  }
+  for (uint32_t t0 = 0; t0 < nx; t0 += kBlock) {
+    const uint32_t t2 = t0 + threadIdx.x;
     bool birth = false;
     BirthRec<T> rec;
     uint32_t id = 0u, w = 0u, leaf = 0u;
     T s0 = (T)0, s1 = (T)0;
-    if (t < n) {
+    if (t2 < nx) {
+      const uint32_t e = Q.e[kQCap - 1u - t2];
+      const uint32_t t = e & 0xFFFFu, kind = e >> 16;
       const uint32_t i = Q.i[t];
       id = Q.id[t];
       w = Q.w[t];
       s0 = Q.s0[t];
-      T vx = Q.v0[t], vy, vz = *at(P.v2, i);
       if constexpr (DIM == 2) {
         s1 = Q.s1[t];
         leaf = Q.leaf[t];
-        vy = Q.v1[t];
-      } else {
-        vy = *at(P.v1, i);
       }
+      T vx = Q.v0[t], vy = DIM == 2 ? Q.v1[t] : *at(P.v1, i), vz = *at(P.v2, i);
       WordStream ws(H.key0, H.key1, id, step, Q.wa[t], Q.wb[t]);
-      birth = collide<T>(I, H.k, id, step, Q.r1[t], ws, vx, vy, vz, st, rec);
+      birth = collide_as<T>(kind, H.k, Q.r1[t], ws, vx, vy, vz, st, rec);
       *at(P.v0, i) = vx;
       *at(P.v1, i) = vy;
       *at(P.v2, i) = vz;
@@ -925,80 +990,110 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
 // ---------------------------------------------------------------------------
 // Births: rank by parent id (count of smaller staged parent ids; the ids are
 // distinct), then append the electron at count[0] + r with id next_id + 2r
-// and the ion at count[1] + r with id next_id + 2r + 1.  A workgroup ranks
-// kRankPer births per lane at a time against all staged parent ids streamed
-// through LDS, so each LDS read serves kRankPer comparisons.
+// and the ion at count[1] + r with id next_id + 2r + 1.
+// The ranking is split into work items (key tile a, chunk c): the kRankPer x
+// kBlock staged births of tile a are compared with the kRankChunk staged
+// parent ids of chunk c held in LDS, and each adds its count of smaller ids
+// to rank[i].  No lane walks all staged ids, so the time does not grow with
+// the number of births as long as work items remain to spread.  A second
+// kernel writes the newborn particles and clears rank[] for the next step.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRankPer = 4;
-constexpr int kBirthBlocks = 256;   // workgroups per instance of the births kernels
+constexpr uint32_t kRankChunk = 256;
+constexpr int kRankBlocks = 256;   // workgroups per instance of the ranking kernel
+constexpr int kWriteBlocks = 64;   // workgroups per instance of the writing kernel
 
 template <class T>
-__device__ void births_body(const InstDev<T>& I, uint32_t first_block, uint32_t nblocks) {
-  __shared__ uint32_t sh[1024];
-  const uint32_t nb = I.ctr->nbirths;
-  if (nb == 0u) return;
+__device__ __forceinline__ bool births_fit(const InstDev<T>& I, uint32_t nb, bool& cap_ok, bool& id_ok) {
   const uint32_t c0 = I.ctr->count[0], c1 = I.ctr->count[1], nid = I.ctr->next_id;
-  const bool cap_ok = (uint64_t)c0 + nb <= I.cap[0] && (uint64_t)c1 + nb <= I.cap[1] && nb <= I.birth_cap;
-  const bool id_ok = (uint64_t)nid + 2ull * nb <= 0xFFFFFFFFull;
-  if (!cap_ok || !id_ok) {
-    if (threadIdx.x == 0 && first_block == 0)
-      atomicOr(&I.ctr->flags, (!cap_ok ? kFlagBirthOverflow : 0u) | (!id_ok ? kFlagIdOverflow : 0u));
-    return;
-  }
+  cap_ok = (uint64_t)c0 + nb <= I.cap[0] && (uint64_t)c1 + nb <= I.cap[1] && nb <= I.birth_cap;
+  id_ok = (uint64_t)nid + 2ull * nb <= 0xFFFFFFFFull;
+  return cap_ok && id_ok;
+}
+
+template <class T>
+__device__ void birth_rank_body(const InstDev<T>& I, uint32_t first, uint32_t nblocks) {
+  __shared__ uint32_t sh[kRankChunk];
+  const uint32_t nb = I.ctr->nbirths;
+  bool cap_ok, id_ok;
+  if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
   const uint32_t tile = kRankPer * kBlock;
-  for (uint32_t ib = first_block * tile; ib < nb; ib += nblocks * tile) {
-    uint32_t mine[kRankPer], r[kRankPer];
+  const uint32_t na = (nb + tile - 1u) / tile, nc = (nb + kRankChunk - 1u) / kRankChunk;
+  for (uint32_t wi = first; wi < na * nc; wi += nblocks) {
+    const uint32_t a = wi / nc, jb = (wi % nc) * kRankChunk;
+    const uint32_t lim = (nb - jb) < kRankChunk ? (nb - jb) : kRankChunk;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < lim; t += kBlock) sh[t] = I.br.parent[jb + t];
+    __syncthreads();
+    uint32_t mine[kRankPer], cnt[kRankPer];
 #pragma unroll
     for (uint32_t q = 0; q < kRankPer; ++q) {
-      const uint32_t i = ib + q * kBlock + threadIdx.x;
-      mine[q] = i < nb ? I.br.parent[i] : 0xFFFFFFFFu;
-      r[q] = 0u;
+      const uint32_t i = a * tile + q * kBlock + threadIdx.x;
+      mine[q] = i < nb ? I.br.parent[i] : 0u;
+      cnt[q] = 0u;
     }
-    for (uint32_t jb = 0; jb < nb; jb += 1024u) {
-      __syncthreads();
-      for (uint32_t t = threadIdx.x; t < 1024u && jb + t < nb; t += kBlock) sh[t] = I.br.parent[jb + t];
-      __syncthreads();
-      const uint32_t lim = (nb - jb) < 1024u ? (nb - jb) : 1024u;
-      for (uint32_t j = 0; j < lim; ++j) {
-        const uint32_t v = sh[j];
+    for (uint32_t j = 0; j < lim; ++j) {
+      const uint32_t v = sh[j];
 #pragma unroll
-        for (uint32_t q = 0; q < kRankPer; ++q) r[q] += (v < mine[q]) ? 1u : 0u;
-      }
+      for (uint32_t q = 0; q < kRankPer; ++q) cnt[q] += (v < mine[q]) ? 1u : 0u;
     }
 #pragma unroll
     for (uint32_t q = 0; q < kRankPer; ++q) {
-      const uint32_t i = ib + q * kBlock + threadIdx.x;
-      if (i >= nb) continue;
-      const uint32_t pe = c0 + r[q], pi = c1 + r[q];
-      const uint32_t w = I.br.w[i];
-      I.s[0][0][pe] = I.br.s[0][i];
-      I.s[1][0][pi] = I.br.s[0][i];
-      if (I.dim == 2) {
-        I.s[0][1][pe] = I.br.s[1][i];
-        I.s[1][1][pi] = I.br.s[1][i];
-        I.cell[0][pe] = I.br.cell[i];
-        I.cell[1][pi] = I.br.cell[i];
-      }
-      for (int c = 0; c < 3; ++c) {
-        I.v[0][c][pe] = I.br.ve[c][i];
-        I.v[1][c][pi] = I.br.vi[c][i];
-      }
-      I.w[0][pe] = w;
-      I.w[1][pi] = w;
-      I.id[0][pe] = nid + 2u * r[q];
-      I.id[1][pi] = nid + 2u * r[q] + 1u;
+      const uint32_t i = a * tile + q * kBlock + threadIdx.x;
+      if (i < nb && cnt[q]) atomicAdd(&I.br.rank[i], cnt[q]);
     }
   }
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_births(InstDev<T> I) { births_body<T>(I, blockIdx.x, gridDim.x); }
+__device__ void birth_write_body(const InstDev<T>& I, uint32_t first, uint32_t nblocks) {
+  const uint32_t nb = I.ctr->nbirths;
+  if (nb == 0u) return;
+  bool cap_ok, id_ok;
+  if (!births_fit(I, nb, cap_ok, id_ok)) {
+    if (threadIdx.x == 0 && first == 0)
+      atomicOr(&I.ctr->flags, (!cap_ok ? kFlagBirthOverflow : 0u) | (!id_ok ? kFlagIdOverflow : 0u));
+    return;
+  }
+  const uint32_t c0 = I.ctr->count[0], c1 = I.ctr->count[1], nid = I.ctr->next_id;
+  for (uint32_t i = first * kBlock + threadIdx.x; i < nb; i += nblocks * kBlock) {
+    const uint32_t r = I.br.rank[i];
+    I.br.rank[i] = 0u;
+    const uint32_t pe = c0 + r, pi = c1 + r;
+    const uint32_t w = I.br.w[i];
+    I.s[0][0][pe] = I.br.s[0][i];
+    I.s[1][0][pi] = I.br.s[0][i];
+    if (I.dim == 2) {
+      I.s[0][1][pe] = I.br.s[1][i];
+      I.s[1][1][pi] = I.br.s[1][i];
+      I.cell[0][pe] = I.br.cell[i];
+      I.cell[1][pi] = I.br.cell[i];
+    }
+    for (int c = 0; c < 3; ++c) {
+      I.v[0][c][pe] = I.br.ve[c][i];
+      I.v[1][c][pi] = I.br.vi[c][i];
+    }
+    I.w[0][pe] = w;
+    I.w[1][pi] = w;
+    I.id[0][pe] = nid + 2u * r;
+    I.id[1][pi] = nid + 2u * r + 1u;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_rank(InstDev<T> I) { birth_rank_body<T>(I, blockIdx.x, gridDim.x); }
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_write(InstDev<T> I) { birth_write_body<T>(I, blockIdx.x, gridDim.x); }
 
 // grid (per_inst, ninst): blockIdx.y selects the instance, blockIdx.x the
-// share of its births
+// share of its work
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_births_batched(const InstDev<T>* insts) {
-  births_body<T>(insts[blockIdx.y], blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kBlock) void k_birth_rank_batched(const InstDev<T>* insts) {
+  birth_rank_body<T>(insts[blockIdx.y], blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_write_batched(const InstDev<T>* insts) {
+  birth_write_body<T>(insts[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // Commit a step after the births kernel: append births to the counts,
@@ -1181,12 +1276,15 @@ hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uin
 }
 template <class T>
 hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid) {
-  hipLaunchKernelGGL(k_births<T>, dim3(grid), dim3(kBlock), 0, s, I);
+  (void)grid;
+  hipLaunchKernelGGL(k_birth_rank<T>, dim3(kRankBlocks), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_birth_write<T>, dim3(kWriteBlocks), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
 template <class T>
 hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s) {
-  hipLaunchKernelGGL(k_births_batched<T>, dim3(kBirthBlocks, ninst), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_birth_rank_batched<T>, dim3(kRankBlocks, ninst), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_birth_write_batched<T>, dim3(kWriteBlocks, ninst), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
 template <class T>

@@ -42,6 +42,7 @@ struct SpeciesK {
 template <class T>
 struct Births {          // staging of one step's ionization births (SoA)
   uint32_t* parent;
+  uint32_t* rank;        // rank of the parent id among the staged ones (kept zero between steps)
   uint32_t* cell;
   uint32_t* w;
   T* s[2];
