@@ -105,7 +105,9 @@ typedef struct {
   uint32_t instance_key;
   int nspecies;         /* 1 or 2: [0] electrons, [1] ions (births need both)    */
   pic_species_desc species[2];
-  int64_t capacity[2];  /* particle slots per species; 0 = sized from the load   */
+  int64_t capacity[2];  /* particle slots per species; 0 = sized from the load
+                           (3x the loaded count + 4096 when ionizing); grows to
+                           2x the projected need between chunks of steps       */
 } pic_instance_desc;
 
 typedef struct {

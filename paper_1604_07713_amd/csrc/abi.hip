@@ -462,7 +462,7 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
   const int dim = sl.d.dim;
   for (int64_t i = 0; i < n * dim; ++i)
     if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "position outside [0,1)");
-  int64_t cap = std::max<int64_t>(sl.d.capacity[species], sl.ionizing ? 2 * n + 4096 : n);
+  int64_t cap = std::max<int64_t>(sl.d.capacity[species], sl.ionizing ? 3 * n + 4096 : n);
   cap = std::max<int64_t>(cap, 256);
   cap = (cap + 255) & ~(int64_t)255;
   Counters cn = read_counters(*c, sl);

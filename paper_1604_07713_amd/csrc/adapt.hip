@@ -216,7 +216,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
         const int other = 1 - sl.cur[sp];
         PBuf& d = sl.pb[sp][other];
         SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
-        hip_check(launch_sort<T>(I, sp, n, sl.off, dst, grid_for(sl.cap[sp]), C.stream), "sort");
+        hip_check(launch_sort<T>(I, sp, n, sl.off, sl.scan_tmp, dst, grid_for(sl.cap[sp]), C.stream), "sort");
         sl.cur[sp] = other;
       }
       upload_dev(C, sl);

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "k_mesh.hpp"
+#include "k_adapt.hpp"
 #include "pic_internal.hpp"
 #include "api_internal.hpp"
 
@@ -329,7 +330,8 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   sl.grad = (double*)sl.alloc(8 * 8 * (size_t)sl.nleaves);
   sl.phi64 = (double*)sl.alloc(8 * (size_t)sl.nleaves);
   sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
-  sl.off = (uint32_t*)sl.alloc(4 * ((size_t)sl.nq + 1));
+  sl.off = (uint32_t*)sl.alloc(4 * ((size_t)sl.nq + 1 + scan_tmp_words((uint32_t)sl.nq)));
+  sl.scan_tmp = sl.off + sl.nq + 1;   // scratch of the multi-block scan of the sort
   hip_check(hipMemsetAsync(sl.E, 0, sl.esz * 8 * sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.e64, 0, 64 * (size_t)sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (size_t)sl.nleaves, C.stream), "memset");
@@ -567,7 +569,7 @@ void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
     int64_t need = c.count[sp];
     if (sl.ionizing) need += (int64_t)c.count[0] * std::max<int64_t>(1, std::min<int64_t>(steps_ahead, 4)) / 4 + 1024;
     if (need > sl.cap[sp]) {
-      grow(C, sl, sp, (need * 3) / 2 + 1024, c.count[sp]);
+      grow(C, sl, sp, 2 * need + 1024, c.count[sp]);
       changed = true;
     }
   }
@@ -585,7 +587,7 @@ void sort_species(Ctx& C, Slot& sl, int sp) {
   PBuf& d = sl.pb[sp][other];
   SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
   const uint32_t ncell = sl.d.dim == 1 ? (uint32_t)sl.d.ncells : sl.nleaves;
-  hip_check(launch_sort<T>(I, sp, ncell, sl.off, dst, grid_for(sl.cap[sp]), C.stream), "sort");
+  hip_check(launch_sort<T>(I, sp, ncell, sl.off, sl.scan_tmp, dst, grid_for(sl.cap[sp]), C.stream), "sort");
   sl.cur[sp] = other;
 }
 

@@ -55,6 +55,7 @@ struct Slot {
   int64_t cap[2] = {0, 0};
   // births staging
   void* birth_base = nullptr;
+  uint32_t* scan_tmp = nullptr;   // 2D: scratch of the sort's multi-block scan (after off)
   uint32_t *br_parent = nullptr, *br_rank = nullptr, *br_cell = nullptr, *br_w = nullptr;
   void* br_s[2] = {nullptr, nullptr};
   void* br_ve[3] = {nullptr, nullptr, nullptr};

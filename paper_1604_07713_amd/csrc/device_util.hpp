@@ -192,6 +192,25 @@ __device__ __forceinline__ uint32_t seg_atomic_claim(uint32_t* cursor, uint32_t 
   return base + rank;
 }
 
+// LDS version of seg_atomic_claim: for the lanes with valid set, claims
+// one slot of counter cnt[o] per lane with one LDS atomic per run of equal
+// consecutive o in the wave; returns the lane's slot (counter value before
+// its run plus its rank in the run).  Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t lds_seg_claim(uint32_t* cnt, uint32_t o, bool valid) {
+  const uint32_t key = valid ? o : kNoKey;
+  const int lane = lane_id();
+  const int start = run_start(key, lane);
+  const uint32_t rank = (uint32_t)(lane - start);
+  const bool tail = run_tail(key, lane);
+  uint32_t base = 0;
+  if (tail && key != kNoKey) base = atomicAdd(cnt + key, rank + 1u);
+  const uint64_t tails = __ballot(tail);
+  const uint64_t above = tails & ~(lanes_le(lane) >> 1);   // tail lanes >= lane
+  const int tl = __ffsll((long long)above) - 1;
+  base = __shfl(base, tl);
+  return base + rank;
+}
+
 template <class V>
 __device__ __forceinline__ V wave_sum(V v) {
 #pragma unroll

@@ -5,6 +5,7 @@
 #include "device_util.hpp"
 #include "pic_internal.hpp"
 #include "k_mesh.hpp"
+#include "k_adapt.hpp"
 
 namespace pic {
 
@@ -66,19 +67,32 @@ __device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint3
 }
 
 constexpr uint32_t kSortWin = 1024;
-constexpr uint32_t kSortMargin = 64;
 
-// Base of a chunk's LDS window of cells: the cell of the chunk's first
-// particle if that particle is live (a hole's position and leaf carry no
-// meaning), less a margin.  Window slots map to cells base + slot.
+// Base of the LDS window of cells of the particle range [begin, end): the
+// window is centred on the median of the cells of three live particles
+// sampled at the start, middle and end of the range.  Particles are ordered
+// by cell as of the last sort and drift since, and in Morton order a small
+// move can change a leaf index a lot; a window anchored on one sample would
+// miss the whole range whenever that sample has jumped.  Window slots map to
+// cells base + slot.
 template <class T>
-__device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp, uint32_t i) {
-  const uint32_t c0 = G(I.w[sp])[i] != 0u ? sort_cell<T>(I, sp, i) : 0u;
-  return c0 > kSortMargin ? c0 - kSortMargin : 0u;
+__device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end) {
+  uint32_t c[3];
+  int n = 0;
+  const uint32_t at3[3] = {begin, begin + (end - begin) / 2u, end - 1u};
+  for (int k = 0; k < 3; ++k)
+    if (G(I.w[sp])[at3[k]] != 0u) c[n++] = sort_cell<T>(I, sp, at3[k]);
+  uint32_t m = 0u;
+  if (n == 1) m = c[0];
+  else if (n == 2) m = c[0] < c[1] ? c[0] : c[1];
+  else if (n == 3) m = c[0] < c[1] ? (c[1] < c[2] ? c[1] : (c[0] < c[2] ? c[2] : c[0]))
+                                   : (c[0] < c[2] ? c[0] : (c[1] < c[2] ? c[2] : c[1]));
+  return m > kSortWin / 2u ? m - kSortWin / 2u : 0u;
 }
 
 // Histogram of cells over one contiguous range [begin, end) per workgroup,
-// pre-aggregated in an LDS window of cells.
+// pre-aggregated in an LDS window of cells; within a wave, a run of equal
+// cells (particles are nearly cell-ordered) costs one atomic.
 template <class T>
 __device__ void sort_hist_range(const InstDev<T>& I, int sp, uint32_t* hist, uint32_t begin, uint32_t end) {
   __shared__ uint32_t win[kSortWin];
@@ -86,16 +100,18 @@ __device__ void sort_hist_range(const InstDev<T>& I, int sp, uint32_t* hist, uin
   __syncthreads();   // the window may still be read by a previous range
   for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) win[j] = 0u;
   if (threadIdx.x == 0) {
-    base_s = begin < end ? sort_window_base<T>(I, sp, begin) : 0u;
+    base_s = begin < end ? sort_window_base<T>(I, sp, begin, end) : 0u;
   }
   __syncthreads();
   const uint32_t base = base_s;
-  for (uint32_t i = begin + threadIdx.x; i < end; i += kBlock) {
-    if (G(I.w[sp])[i] == 0u) continue;
-    const uint32_t c = sort_cell<T>(I, sp, i);
+  for (uint32_t i0 = begin; i0 < end; i0 += kBlock) {
+    const uint32_t i = i0 + threadIdx.x;
+    const bool live = i < end && G(I.w[sp])[i] != 0u;
+    const uint32_t c = live ? sort_cell<T>(I, sp, i) : 0u;
     const uint32_t o = c - base;
-    if (o < kSortWin) atomicAdd(&win[o], 1u);
-    else gadd32(hist + c, 1u);
+    const bool inwin = live && o < kSortWin;
+    (void)lds_seg_claim(win, o, inwin);
+    (void)seg_atomic_claim(hist, (live && !inwin) ? c : kNoKey);
   }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock)
@@ -137,49 +153,55 @@ __device__ void scan_excl_body(uint32_t* a, uint32_t n) {
 
 __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) { scan_excl_body(a, n); }
 
-// Scatter to the sorted position: per tile of kBlock particles, ranks within
-// the tile come from LDS atomics on a window of cells, and one global atomic
-// per touched cell reserves the tile's range in that cell.
+// Scatter to the sorted position: per tile of 4 x kBlock particles, slots
+// within the tile come from LDS atomics on a window of cells (one per run of
+// equal cells in a wave), and one global atomic per touched cell reserves the
+// tile's range in that cell; particles outside the window claim their slot
+// from the global cursor directly (again one atomic per run).
 template <class T>
 __device__ void sort_scatter_range(const InstDev<T>& I, int sp, uint32_t* off, uint32_t begin, uint32_t end,
                                    const SortDst<T>& d) {
+  constexpr uint32_t kSub = 4;   // particles per lane per window pass
   __shared__ uint32_t lcnt[kSortWin];
   __shared__ uint32_t gbase[kSortWin];
   __shared__ uint32_t base_s;
-  T *ds0 = d.s0, *ds1 = d.s1, *dv0 = d.v0, *dv1 = d.v1, *dv2 = d.v2;
-  uint32_t *dw = d.w, *did = d.id, *dcell = d.cell;
-  for (uint32_t t0 = begin; t0 < end; t0 += kBlock) {
+  for (uint32_t t0 = begin; t0 < end; t0 += kSub * kBlock) {
     for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) lcnt[j] = 0u;
-    if (threadIdx.x == 0) {
-      base_s = sort_window_base<T>(I, sp, t0);
-    }
+    if (threadIdx.x == 0) base_s = sort_window_base<T>(I, sp, t0, t0 + kSub * kBlock < end ? t0 + kSub * kBlock : end);
     __syncthreads();
     const uint32_t base = base_s;
-    const uint32_t i = t0 + threadIdx.x;
-    const bool live = i < end && G(I.w[sp])[i] != 0u;
-    uint32_t c = 0, o = kSortWin, pos = 0, rank = 0;
-    if (live) {
-      c = sort_cell<T>(I, sp, i);
-      o = c - base;
-      if (o < kSortWin) rank = atomicAdd(&lcnt[o], 1u);
-      else pos = gadd32(off + c, 1u);
+    uint32_t o[kSub], slot[kSub];
+    bool live[kSub], inwin[kSub];
+#pragma unroll
+    for (uint32_t q = 0; q < kSub; ++q) {
+      const uint32_t i = t0 + q * kBlock + threadIdx.x;
+      live[q] = i < end && G(I.w[sp])[i] != 0u;
+      const uint32_t c = live[q] ? sort_cell<T>(I, sp, i) : 0u;
+      o[q] = c - base;
+      inwin[q] = live[q] && o[q] < kSortWin;
+      const uint32_t r = lds_seg_claim(lcnt, o[q], inwin[q]);
+      const uint32_t g = seg_atomic_claim(off, (live[q] && !inwin[q]) ? c : kNoKey);
+      slot[q] = inwin[q] ? r : g;
     }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock)
       if (lcnt[j]) gbase[j] = gadd32(off + (uint32_t)(base + j), lcnt[j]);
     __syncthreads();
-    if (live) {
-      if (o < kSortWin) pos = gbase[o] + rank;
-      G(ds0)[pos] = G(I.s[sp][0])[i];
+#pragma unroll
+    for (uint32_t q = 0; q < kSub; ++q) {
+      if (!live[q]) continue;
+      const uint32_t i = t0 + q * kBlock + threadIdx.x;
+      const uint32_t pos = inwin[q] ? gbase[o[q]] + slot[q] : slot[q];
+      G(d.s0)[pos] = G(I.s[sp][0])[i];
       if (I.dim == 2) {
-        G(ds1)[pos] = G(I.s[sp][1])[i];
-        G(dcell)[pos] = G(I.cell[sp])[i];
+        G(d.s1)[pos] = G(I.s[sp][1])[i];
+        G(d.cell)[pos] = G(I.cell[sp])[i];
       }
-      G(dv0)[pos] = G(I.v[sp][0])[i];
-      G(dv1)[pos] = G(I.v[sp][1])[i];
-      G(dv2)[pos] = G(I.v[sp][2])[i];
-      G(dw)[pos] = G(I.w[sp])[i];
-      G(did)[pos] = G(I.id[sp])[i];
+      G(d.v0)[pos] = G(I.v[sp][0])[i];
+      G(d.v1)[pos] = G(I.v[sp][1])[i];
+      G(d.v2)[pos] = G(I.v[sp][2])[i];
+      G(d.w)[pos] = G(I.w[sp])[i];
+      G(d.id)[pos] = G(I.id[sp])[i];
     }
     __syncthreads();
   }
@@ -246,13 +268,18 @@ __global__ void k_fill_u32(uint32_t* a, uint32_t n, uint32_t v) {
 __global__ void k_set_count(Counters* ctr, int sp, const uint32_t* total) { ctr->count[sp] = *total; }
 
 template <class T>
-hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* off, const SortDst<T>& d, int grid,
-                       hipStream_t s) {
+hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* off, uint32_t* tmp, const SortDst<T>& d,
+                       int grid, hipStream_t s) {
   const uint32_t chunk = (ceil_div(I.cap[sp], (uint32_t)grid) + kBlock - 1) / kBlock * kBlock;
   hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(ncell + 1u, kBlock) < 1024 ? ceil_div(ncell + 1u, kBlock) : 1024),
                      dim3(kBlock), 0, s, off, ncell + 1u, 0u);
   hipLaunchKernelGGL(k_sort_hist<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, off, ncell);
+  if (ncell > 8192u && tmp) {
+    const hipError_t e = launch_scan_u32(off, ncell, tmp, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, off, ncell);
+  }
   hipLaunchKernelGGL(k_sort_scatter<T>, dim3(grid), dim3(kBlock), 0, s, I, sp, off, chunk, d);
   hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, I.ctr, sp, off + ncell);
   return hipGetLastError();
@@ -274,9 +301,9 @@ template hipError_t launch_sort_batched<float>(const InstDev<float>*, const Sort
                                                const WorkItem*, uint32_t, int, hipStream_t);
 template hipError_t launch_sort_batched<double>(const InstDev<double>*, const SortJob<double>*, int, uint32_t,
                                                 const WorkItem*, uint32_t, int, hipStream_t);
-template hipError_t launch_sort<float>(const InstDev<float>&, int, uint32_t, uint32_t*, const SortDst<float>&, int,
-                                       hipStream_t);
-template hipError_t launch_sort<double>(const InstDev<double>&, int, uint32_t, uint32_t*, const SortDst<double>&, int,
-                                        hipStream_t);
+template hipError_t launch_sort<float>(const InstDev<float>&, int, uint32_t, uint32_t*, uint32_t*,
+                                       const SortDst<float>&, int, hipStream_t);
+template hipError_t launch_sort<double>(const InstDev<double>&, int, uint32_t, uint32_t*, uint32_t*,
+                                        const SortDst<double>&, int, hipStream_t);
 
 }  // namespace pic

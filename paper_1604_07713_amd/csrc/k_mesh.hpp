@@ -27,9 +27,11 @@ hipError_t launch_sort_batched(const InstDev<T>* insts, const SortJob<T>* jobs, 
                                const WorkItem* items, uint32_t nitems, int grid, hipStream_t s);
 
 // Reorder one species by cell into the arrays of d, dropping holes; the new
-// particle count is written to the instance counters.  off: ncell + 1 words.
+// particle count is written to the instance counters.  off: ncell + 1 words;
+// tmp: scratch of the multi-block scan (scan_tmp_words(ncell) words) used
+// when ncell > 8192, or null.
 template <class T>
-hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* off, const SortDst<T>& d, int grid,
-                       hipStream_t s);
+hipError_t launch_sort(const InstDev<T>& I, int sp, uint32_t ncell, uint32_t* off, uint32_t* tmp, const SortDst<T>& d,
+                       int grid, hipStream_t s);
 
 }  // namespace pic

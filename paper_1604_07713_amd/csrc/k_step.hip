@@ -170,7 +170,6 @@ struct FixedPoint<double> {
 // straight to global memory, and the window is flushed once per workgroup.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kWin = 1024;
-constexpr uint32_t kWinMargin = 128;
 constexpr uint32_t kHash = 512;      // open-addressed LDS table for cells outside the window
 constexpr uint32_t kHashProbe = 8;
 
@@ -841,11 +840,21 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   DepCache D{win, hkey, hval, 0u};
   dep_zero(D);
   if (threadIdx.x == 0) {
-    // window from the first particle of the range if it is live: a hole's
-    // stored position and leaf carry no meaning (full batches overwrite them)
-    uint32_t c0 = 0u;
-    if (*at(P.w, begin) != 0u) c0 = DIM == 2 ? *at(P.cell, begin) : cell1d<T>(I, *at(P.s0, begin));
-    wbase_s = c0 > kWinMargin ? c0 - kWinMargin : 0u;
+    // window centred on the median cell of three live particles sampled at
+    // the start, middle and end of the range (particles drift from cell
+    // order between sorts, and a hole's stored position or leaf carries no
+    // meaning: full batches overwrite them)
+    uint32_t c[3];
+    int n = 0;
+    const uint32_t at3[3] = {begin, begin + (end - begin) / 2u, end - 1u};
+    for (int k = 0; k < 3; ++k)
+      if (*at(P.w, at3[k]) != 0u) c[n++] = DIM == 2 ? *at(P.cell, at3[k]) : cell1d<T>(I, *at(P.s0, at3[k]));
+    uint32_t m = 0u;
+    if (n == 1) m = c[0];
+    else if (n == 2) m = c[0] < c[1] ? c[0] : c[1];
+    else if (n == 3) m = c[0] < c[1] ? (c[1] < c[2] ? c[1] : (c[0] < c[2] ? c[2] : c[0]))
+                                     : (c[0] < c[2] ? c[0] : (c[1] < c[2] ? c[2] : c[1]));
+    wbase_s = m > kWin / 2u ? m - kWin / 2u : 0u;
   }
   // first batch: stage A, then stage B, in the same order as the loop issues
   // them for later batches
