@@ -24,12 +24,14 @@ struct BirthRec {
 };
 
 // Wall rule on one normalised coordinate.  Returns false if the particle
-// leaves the domain (absorbed, or reflected but still outside).  Written
-// with selects: the hot loop evaluates it for every lane without branching.
+// leaves the domain (absorbed, or reflected but still outside).  Inside the
+// domain it returns at once (a wave with no lane at a wall skips the rest);
+// the reflection itself is written with selects.
 template <class T>
 __device__ __forceinline__ bool wall_rule(bool reflect, T& s, T& v, bool& lost) {
   const bool in0 = s >= (T)0 && s < (T)1;
   if (!reflect) return in0;   // uniform
+  if (in0) return true;
   const bool lo = s < (T)0;
   const bool hi = s >= (T)1;
   const T pred1 = (T)1 - (T)(sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
