@@ -55,6 +55,59 @@ def traffic_from_profile():
     return p.get("hbm_bytes_per_launch")
 
 
+def streamer_bench(nsteps=2000, npairs=10000, field_every=10, max_wall=120.0):
+    """2D streamer breakdown on the dynamic quadtree (1 cm square, levels
+    5-11, 30 kV/cm, Gaussian seed of 1e4 pairs, FP32 particles): every 10
+    steps the tree is adapted (refine / coarsen with particle split / merge)
+    and the FP64 CG field solve is redone.  Reports the particle-loop rate
+    (collisions and births included) and the whole-run rate with adaptation
+    and field solves."""
+    import numpy as np
+    import torch
+    from paper_1604_07713_amd import binding as B
+    from paper_1604_07713_amd import inputs as I
+    d = I.streamer_desc(side=0.01, precision=32)
+    g = B.Context(d)
+    for sp, (s, v, w, ids) in enumerate(I.streamer_particles(d, npairs=npairs)):
+        g.load(0, sp, s, v, w, ids)
+    g.adapt(0)
+    g.field_solve_2d(0, rtol=1e-8, maxit=4000)
+    g.leapfrog_start(0)
+    t = dict(step=0.0, adapt=0.0, solve=0.0)
+    upd = births = cg = 0
+    step = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    while step < nsteps and time.perf_counter() - t_start < max_wall:
+        t0 = time.perf_counter()
+        st = g.step(-1, field_every, sort_every=0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.adapt(0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, it, _, _ = g.field_solve_2d(0, rtol=1e-8, maxit=4000)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t["step"] += t1 - t0
+        t["adapt"] += t2 - t1
+        t["solve"] += t3 - t2
+        upd += int(st["alive_start"][0] + st["alive_start"][1])
+        births += int(st["births"])
+        cg += it
+        step += field_every
+    wall = time.perf_counter() - t_start
+    keys, _ = g.leaves(0)
+    out = dict(steps=step, particles_end=int(g.count(0, 0) + g.count(0, 1)), leaves_end=int(len(keys)),
+               births=births, particle_loop_updates_per_s=upd / max(t["step"], 1e-12),
+               updates_per_s_with_adapt_and_field=upd / wall, particle_loop_s=t["step"], adapt_s=t["adapt"],
+               field_solve_s=t["solve"], cg_iterations=cg, wall_s=wall,
+               workload="1 cm x 1 cm, N2-like gas at 1 atm, 30 kV/cm, 1e4 seed pairs (sigma 0.5 mm), "
+                        "levels 5-11, 16-64 particles per leaf, dt 1e-13 s, adapt + FP64 CG every 10 steps")
+    g.close()
+    return out
+
+
 def cpu_baseline(nparticles, nsteps, seed=2):
     import numpy as np
     import oracle
@@ -140,6 +193,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
+    ap.add_argument("--no-streamer", action="store_true", help="skip the 2D streamer breakdown measurement")
+    ap.add_argument("--streamer-steps", type=int, default=2000)
+    ap.add_argument("--only-streamer", action="store_true", help="measure only the streamer (profiling)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--only-ensemble", action="store_true", help="measure only the ensemble (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -166,6 +222,9 @@ def main():
     from paper_1604_07713_amd import inputs as I
     if args.only_ensemble:
         print(json.dumps({"ensemble": ensemble_bench(args.ensemble_steps, tune=False)}), flush=True)
+        return
+    if args.only_streamer:
+        print(json.dumps({"streamer": streamer_bench(args.streamer_steps)}), flush=True)
         return
 
     d = I.quadtree_static_desc()
@@ -216,6 +275,8 @@ def main():
     }
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(args.ensemble_steps)
+    if not args.no_streamer:
+        out["streamer"] = streamer_bench(args.streamer_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)
