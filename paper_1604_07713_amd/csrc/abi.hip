@@ -726,22 +726,28 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   if (phi_init) hip_check(hipMemcpy(sl.phi64, phi_init, 8 * (size_t)n, hipMemcpyHostToDevice), "upload");
   Counters cn = read_counters(*c, sl);
   const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
+  const double rtol2 = rtol * rtol;
+  const uint32_t maxit_u = maxit > 0 ? (uint32_t)maxit : 0u;
   hip_check(launch_cg_setup(m, sl.st, latest, sl.d.nspecies, sl.kappa, sl.phi64, sl.cg_ws, c->stream), "cg_setup");
-  const int g = cg_grid(n);
-  const double* sc = sl.cg_ws + 4u * (size_t)n + 3u * (size_t)g;
-  int it = 0;
-  double rr = 0, bb = 0;
+  // Iterations are queued in growing batches; the device stops them itself
+  // once the residual test holds (a batch may end in no-op launches).  The
+  // launch of iteration maxit only checks, so the loop always ends.
+  const CgScal* scd = (const CgScal*)(sl.cg_ws + cg_scalars_offset(n));
+  CgScal sc{};
+  uint32_t k = 0;
+  int batch = 4;
   for (;;) {
-    double h[4];
-    hip_check(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, c->stream), "read");
+    const uint32_t kend = (uint32_t)std::min<uint64_t>((uint64_t)k + (uint64_t)batch, (uint64_t)maxit_u + 1u);
+    for (; k < kend; ++k)
+      hip_check(launch_cg_iter(m, sl.st, sl.phi64, sl.cg_ws, k, rtol2, maxit_u, c->stream), "cg_iter");
+    hip_check(hipMemcpyAsync(&sc, scd, sizeof(sc), hipMemcpyDeviceToHost, c->stream), "read");
     c->sync();
-    rr = h[2];
-    bb = h[3];
-    if (std::sqrt(rr) <= rtol * std::sqrt(bb) || it >= maxit) break;
-    const int batch = std::min(4, maxit - it);
-    for (int q = 0; q < batch; ++q) hip_check(launch_cg_iter(m, sl.st, sl.phi64, sl.cg_ws, c->stream), "cg_iter");
-    it += batch;
+    if (sc.done) break;
+    if (k > maxit_u) throw Err(PIC_E_STATE, "CG did not stop");
+    batch = std::min(batch * 2, 32);
   }
+  const int it = (int)sc.it;
+  const double rr = sc.rr, bb = sc.bb;
   hip_check(launch_cell_to_corner_phi(m, sl.phi64, sl.cphi, c->stream), "cell_to_corner");
   if (sl.prec == 32) hip_check(launch_corner_field<float>(m, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner");
   else hip_check(launch_corner_field<double>(m, sl.cphi, sl.grad, sl.e64, (double*)sl.E, c->stream), "corner");
@@ -751,7 +757,8 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   if (iters) *iters = it;
   const double res = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
   if (relres) *relres = res;
-  if (!(res <= rtol)) throw Err(PIC_E_NUMERIC, "CG did not reach the tolerance");
+  // the device's stopping test, repeated: rr <= rtol^2 bb
+  if (!(bb > 0 ? rr <= rtol2 * bb : true)) throw Err(PIC_E_NUMERIC, "CG did not reach the tolerance");
   return PIC_OK;
   PIC_GUARD_END(c)
 }

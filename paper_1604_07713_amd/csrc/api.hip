@@ -302,10 +302,14 @@ void validate(const pic_instance_desc& d) {
 // Adopt device leaf arrays (allocated through sl.alloc) as the slot's tree and
 // size every per-leaf array for it.
 void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n, int maxlv) {
-  if (sl.key != key) sl.release(sl.key);
-  if (sl.lv != lv) sl.release(sl.lv);
+  // the old tree and cell potential stay until the potential is carried over
+  uint32_t* okey = sl.key;
+  uint8_t* olv = sl.lv;
+  uint32_t* olut = sl.lut;
+  double* ophi = sl.phi64;
+  const int olut_level = sl.lut_level;
+  const bool carry = okey && olv && olut && ophi && sl.nleaves > 0;
   sl.release(sl.xy);
-  sl.release(sl.lut);
   sl.key = key;
   sl.lv = lv;
   sl.nleaves = n;
@@ -316,9 +320,8 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   hip_check(launch_leaf_xy(sl.key, sl.lv, sl.nleaves, sl.xy, C.stream), "leaf_xy");
   hip_check(launch_build_lut(sl.key, sl.lv, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut");
   // per-leaf field and deposit arrays
-  for (void* p : {(void*)sl.E, (void*)sl.e64, (void*)sl.cphi, (void*)sl.grad, (void*)sl.phi64, (void*)sl.Q,
-                  (void*)sl.off, (void*)sl.st.nbr, (void*)sl.st.coef, (void*)sl.st.diag, (void*)sl.st.bnd,
-                  (void*)sl.cg_ws})
+  for (void* p : {(void*)sl.E, (void*)sl.e64, (void*)sl.cphi, (void*)sl.grad, (void*)sl.Q, (void*)sl.off,
+                  (void*)sl.st.nbr, (void*)sl.st.coef, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
     sl.release(p);
   sl.st = Stencil2D{nullptr, nullptr, nullptr, nullptr};
   sl.cg_ws = nullptr;
@@ -334,8 +337,17 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   sl.scan_tmp = sl.off + sl.nq + 1;   // scratch of the multi-block scan of the sort
   hip_check(hipMemsetAsync(sl.E, 0, sl.esz * 8 * sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.e64, 0, 64 * (size_t)sl.nleaves, C.stream), "memset");
-  hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (size_t)sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+  // the next 2D solve starts from the potential of the old tree
+  if (carry)
+    hip_check(launch_remap_cells(sl.xy, sl.lv, sl.nleaves, okey, olv, olut, olut_level, ophi, sl.phi64, C.stream),
+              "remap");
+  else
+    hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (size_t)sl.nleaves, C.stream), "memset");
+  if (okey != key) sl.release(okey);
+  if (olv != lv) sl.release(olv);
+  sl.release(olut);
+  sl.release(ophi);
 }
 
 void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {

@@ -337,163 +337,196 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
   return hipGetLastError();
 }
 
-// CG workspace layout (doubles): r, z, p, q [4 n] then block partials
-// [3][grid] then scalars [8]: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha, 5 beta, 6 rz_new.
+// CG workspace (doubles): r, z, p[0], p[1], q [5 n], block partials of p.q,
+// r.z, r.r and b.b [4][grid], then the scalars (CgScal).  One iteration k is
+// two launches: the direction and its image under A (with the partials of
+// p.q), then the updates of x, r and z (with the partials of r.z and r.r).
+// Each launch begins by summing the partials the previous launch left, in
+// the same fixed order in every workgroup, so every workgroup holds the same
+// alpha, beta and stopping test without a reduction launch, a fence or an
+// atomic.  Once the stopping test holds every later launch returns at once,
+// so the host queues many iterations between reads of the scalars.
 int cg_grid(uint32_t n) {
   int g = (int)ceil_div(n, kBlock);
   return g < 1024 ? g : 1024;
 }
-int cg_ws_doubles(uint32_t n) { return (int)(4u * n + 3u * (uint32_t)cg_grid(n) + 8u); }
+int cg_ws_doubles(uint32_t n) {
+  return (int)(5u * n + 4u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
+}
+size_t cg_scalars_offset(uint32_t n) { return 5u * (size_t)n + 4u * (size_t)cg_grid(n); }
 
-__device__ __forceinline__ double block_sum(double v) {
+struct CgView {
+  double *r, *z, *p0, *p1, *q;
+  double *ppq, *prz, *prr, *pbb;
+  CgScal* sc;
+};
+__device__ __forceinline__ CgView cg_view(double* ws, uint32_t n, int grid) {
+  CgView v;
+  v.r = ws;
+  v.z = ws + n;
+  v.p0 = ws + 2u * (size_t)n;
+  v.p1 = ws + 3u * (size_t)n;
+  v.q = ws + 4u * (size_t)n;
+  v.ppq = ws + 5u * (size_t)n;
+  v.prz = v.ppq + grid;
+  v.prr = v.prz + grid;
+  v.pbb = v.prr + grid;
+  v.sc = (CgScal*)(v.pbb + grid);
+  return v;
+}
+
+// Sum over the workgroup; the result is valid in every thread.
+__device__ __forceinline__ double block_sum_all(double v) {
   __shared__ double red[kBlock / 64];
   v = wave_sum(v);
   if (lane_id() == 0) red[threadIdx.x / 64] = v;
   __syncthreads();
   double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kBlock / 64; ++w) t = t + red[w];
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) t = t + red[w];
   __syncthreads();
   return t;
 }
 
-__device__ __forceinline__ double apply_row(const Stencil2D& st, const double* x, uint32_t i) {
-  double y = st.diag[i] * x[i];
-  const uint32_t* nb = st.nbr + (size_t)i * 8u;
-  const double* cf = st.coef + (size_t)i * 8u;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) y = y - cf[k] * x[nb[k]];
-  return y;
+// Sum of the partials part[0 .. gridDim.x) in a fixed order; every
+// workgroup gets the same value, valid in every thread.
+__device__ __forceinline__ double sum_partials(const double* part) {
+  double a = 0.0;
+  for (uint32_t j = threadIdx.x; j < gridDim.x; j += kBlock) a += part[j];
+  return block_sum_all(a);
 }
 
-// r = b - A x, z = r / diag, p = z; partial sums of r.z, r.r, b.b
+// r = b - A x, z = r / diag, p[0] = 0 (the first direction is z); partials
+// of r.z, r.r and b.b
 __global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, const unsigned long long* __restrict__ Q,
                                                      int nspecies, double k0, double k1, const double* __restrict__ x,
-                                                     double* ws, int grid) {
+                                                     double* ws) {
   const uint32_t n = m.nleaves;
-  double *r = ws, *z = ws + n, *p = ws + 2u * n, *part = ws + 4u * n;
+  const CgView w = cg_view(ws, n, (int)gridDim.x);
   double srz = 0.0, srr = 0.0, sbb = 0.0;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     double b = (double)(long long)Q[i] * k0;
     if (nspecies > 1) b = b + (double)(long long)Q[(size_t)n + i] * k1;
     b = b + st.bnd[i];
-    const double ri = b - apply_row(st, x, i);
+    double ax = st.diag[i] * x[i];
+    const uint32_t* nb = st.nbr + (size_t)i * 8u;
+    const double* cf = st.coef + (size_t)i * 8u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ax = ax - cf[k] * x[nb[k]];
+    const double ri = b - ax;
     const double zi = ri / st.diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    p[i] = zi;
+    w.r[i] = ri;
+    w.z[i] = zi;
+    w.p0[i] = 0.0;
     srz += ri * zi;
     srr += ri * ri;
     sbb += b * b;
   }
-  srz = block_sum(srz);
-  srr = block_sum(srr);
-  sbb = block_sum(sbb);
+  srz = block_sum_all(srz);
+  srr = block_sum_all(srr);
+  sbb = block_sum_all(sbb);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = srz;
-    part[grid + blockIdx.x] = srr;
-    part[2 * grid + blockIdx.x] = sbb;
-  }
-}
-
-// one-block reduction of the partials into scalars; what = 0 (setup), 1 (alpha), 2 (beta)
-__global__ __launch_bounds__(kBlock) void k_cg_reduce(double* ws, uint32_t n, int grid, int what) {
-  double* part = ws + 4u * n;
-  double* sc = part + 3 * grid;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int j = threadIdx.x; j < grid; j += kBlock) {
-    a += part[j];
-    b += part[grid + j];
-    c += part[2 * grid + j];
-  }
-  a = block_sum(a);
-  b = block_sum(b);
-  c = block_sum(c);
-  if (threadIdx.x == 0) {
-    if (what == 0) {
-      sc[0] = a;
-      sc[2] = b;
-      sc[3] = c;
-    } else if (what == 1) {
-      sc[1] = a;
-      sc[4] = sc[0] / a;
-    } else {
-      sc[6] = a;
-      sc[2] = b;
-      sc[5] = a / sc[0];
-      sc[0] = a;
+    w.prz[blockIdx.x] = srz;
+    w.prr[blockIdx.x] = srr;
+    w.pbb[blockIdx.x] = sbb;
+    if (blockIdx.x == 0) {
+      w.sc->done = 0u;
+      w.sc->it = 0u;
     }
   }
 }
 
-// q = A p; partial p.q
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(Mesh2D m, Stencil2D st, double* ws, int grid) {
+// Iteration k, first half: r.z and r.r after k updates and the stopping test
+// (rr <= rtol2 bb, or k = maxit); beta = r.z / previous r.z (0 at k = 0);
+// p_new = z + beta p_old and q = A p_new (the neighbours' directions are
+// formed on the fly from their z and p_old with the same operation);
+// partials of p.q.
+__global__ __launch_bounds__(kBlock) void k_cg_dir(Mesh2D m, Stencil2D st, double* ws, uint32_t k, double rtol2,
+                                                   uint32_t maxit) {
   const uint32_t n = m.nleaves;
-  const double* p = ws + 2u * n;
-  double* q = ws + 3u * n;
-  double* part = ws + 4u * n;
+  const CgView w = cg_view(ws, n, (int)gridDim.x);
+  CgScal* S = w.sc;
+  if (S->done) return;   // uniform over the launch
+  const double rz = sum_partials(w.prz);
+  const double rr = sum_partials(w.prr);
+  double bb;
+  if (k == 0u) {
+    bb = sum_partials(w.pbb);
+  } else {
+    bb = S->bb;
+  }
+  const bool stop = rr <= rtol2 * bb || k >= maxit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->rz2[k & 1u] = rz;
+    S->rr = rr;
+    if (k == 0u) S->bb = bb;
+    S->it = k;
+    if (stop) S->done = 1u;
+  }
+  if (stop) return;
+  const double beta = k == 0u ? 0.0 : rz / S->rz2[(k - 1u) & 1u];
+  const double* __restrict__ po = (k & 1u) ? w.p1 : w.p0;
+  double* __restrict__ pn = (k & 1u) ? w.p0 : w.p1;
+  const double* __restrict__ z = w.z;
   double s = 0.0;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const double qi = apply_row(st, p, i);
-    q[i] = qi;
-    s += p[i] * qi;
+    const double pi = fma(beta, po[i], z[i]);
+    double y = st.diag[i] * pi;
+    const uint32_t* nb = st.nbr + (size_t)i * 8u;
+    const double* cf = st.coef + (size_t)i * 8u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t j = nb[c];
+      y = y - cf[c] * fma(beta, po[j], z[j]);
+    }
+    pn[i] = pi;
+    w.q[i] = y;
+    s += pi * y;
   }
-  s = block_sum(s);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = s;
-    part[grid + blockIdx.x] = 0.0;
-    part[2 * grid + blockIdx.x] = 0.0;
-  }
+  s = block_sum_all(s);
+  if (threadIdx.x == 0) w.ppq[blockIdx.x] = s;
 }
 
-// x += alpha p, r -= alpha q, z = r / diag; partial r.z, r.r
-__global__ __launch_bounds__(kBlock) void k_cg_axpy(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
-                                                    int grid) {
+// Iteration k, second half: alpha = r.z / p.q; x += alpha p, r -= alpha q,
+// z = r / diag; partials of r.z and r.r.
+__global__ __launch_bounds__(kBlock) void k_cg_update(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
+                                                      uint32_t k) {
   const uint32_t n = m.nleaves;
-  double *r = ws, *z = ws + n, *p = ws + 2u * n, *q = ws + 3u * n, *part = ws + 4u * n;
-  const double alpha = part[3 * grid + 4];
+  const CgView w = cg_view(ws, n, (int)gridDim.x);
+  if (w.sc->done) return;   // uniform over the launch
+  const double pq = sum_partials(w.ppq);
+  const double alpha = w.sc->rz2[k & 1u] / pq;
+  const double* __restrict__ p = (k & 1u) ? w.p0 : w.p1;
   double srz = 0.0, srr = 0.0;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     x[i] = x[i] + alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+    const double ri = w.r[i] - alpha * w.q[i];
     const double zi = ri / st.diag[i];
-    r[i] = ri;
-    z[i] = zi;
+    w.r[i] = ri;
+    w.z[i] = zi;
     srz += ri * zi;
     srr += ri * ri;
   }
-  srz = block_sum(srz);
-  srr = block_sum(srr);
+  srz = block_sum_all(srz);
+  srr = block_sum_all(srr);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = srz;
-    part[grid + blockIdx.x] = srr;
-    part[2 * grid + blockIdx.x] = 0.0;
+    w.prz[blockIdx.x] = srz;
+    w.prr[blockIdx.x] = srr;
   }
-}
-
-// p = z + beta p
-__global__ __launch_bounds__(kBlock) void k_cg_p(uint32_t n, double* ws, int grid) {
-  const double* z = ws + n;
-  double* p = ws + 2u * n;
-  const double beta = ws[4u * n + 3 * grid + 5];
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + beta * p[i];
 }
 
 hipError_t launch_cg_setup(const Mesh2D& m, const Stencil2D& st, const unsigned long long* Q, int nspecies,
                            const double* kappa, double* x, double* ws, hipStream_t s) {
   const int g = cg_grid(m.nleaves);
-  hipLaunchKernelGGL(k_cg_setup, dim3(g), dim3(kBlock), 0, s, m, st, Q, nspecies, kappa[0], kappa[1], x, ws, g);
-  hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kBlock), 0, s, ws, m.nleaves, g, 0);
+  hipLaunchKernelGGL(k_cg_setup, dim3(g), dim3(kBlock), 0, s, m, st, Q, nspecies, kappa[0], kappa[1], x, ws);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, hipStream_t s) {
+hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, uint32_t k, double rtol2,
+                          uint32_t maxit, hipStream_t s) {
   const int g = cg_grid(m.nleaves);
-  hipLaunchKernelGGL(k_cg_spmv, dim3(g), dim3(kBlock), 0, s, m, st, ws, g);
-  hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kBlock), 0, s, ws, m.nleaves, g, 1);
-  hipLaunchKernelGGL(k_cg_axpy, dim3(g), dim3(kBlock), 0, s, m, st, x, ws, g);
-  hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(kBlock), 0, s, ws, m.nleaves, g, 2);
-  hipLaunchKernelGGL(k_cg_p, dim3(g), dim3(kBlock), 0, s, m.nleaves, ws, g);
+  hipLaunchKernelGGL(k_cg_dir, dim3(g), dim3(kBlock), 0, s, m, st, ws, k, rtol2, maxit);
+  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, m, st, x, ws, k);
   return hipGetLastError();
 }
 

@@ -29,6 +29,28 @@ hipError_t launch_leaf_xy(const uint32_t* key, const uint8_t* lv, uint32_t n, ui
   return hipGetLastError();
 }
 
+// Cell values carried over to a new tree (the starting guess of the next
+// field solve): each new leaf takes the value of the old leaf holding its
+// centre.
+__global__ void k_remap_cells(const uint32_t* __restrict__ nxy, const uint8_t* __restrict__ nlv, uint32_t n,
+                              const uint32_t* okey, const uint8_t* olv, const uint32_t* olut, int olut_level,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  const uint32_t xy = nxy[l];
+  const uint32_t half = (1u << (16 - nlv[l])) >> 1;
+  dst[l] = src[locate_leaf(okey, olv, olut, olut_level, (xy >> 16) + half, (xy & 0xFFFFu) + half)];
+}
+
+hipError_t launch_remap_cells(const uint32_t* nxy, const uint8_t* nlv, uint32_t n, const uint32_t* okey,
+                              const uint8_t* olv, const uint32_t* olut, int olut_level, const double* src, double* dst,
+                              hipStream_t s) {
+  if (n == 0u) return hipSuccess;
+  hipLaunchKernelGGL(k_remap_cells, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, nxy, nlv, n, okey, olv, olut,
+                     olut_level, src, dst);
+  return hipGetLastError();
+}
+
 // lut[c] = last leaf whose key <= key of cell c's low corner; lut[4^L] = n
 __global__ void k_build_lut(const uint32_t* key, uint32_t n, uint32_t* lut, int L) {
   const uint32_t ncell = 1u << (2 * L);

@@ -139,16 +139,31 @@ struct Stencil2D {
   double* bnd;       // [nleaves] Dirichlet contribution to the right-hand side
 };
 hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_t s);
-// CG work vectors and scalars live in 'ws' (see k_field.hip for the layout)
+// CG work vectors, block partials and scalars live in 'ws' (layout in
+// k_field.hip); the scalars sit at cg_scalars_offset(nleaves) doubles.
+struct CgScal {
+  double rz2[2];   // r.z of the last two iterations (by parity)
+  double rr, bb;   // r.r of the last iteration checked, b.b
+  uint32_t it;     // iterations done when the stopping test was last checked
+  uint32_t done;   // stopping test met: later launches return at once
+};
 hipError_t launch_cg_setup(const Mesh2D& m, const Stencil2D& st, const unsigned long long* Q, int nspecies,
                            const double* kappa, double* x, double* ws, hipStream_t s);
-hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, hipStream_t s);
+// iteration k = 0, 1, 2, ... in order after the setup; the launch of k = maxit
+// only checks and stops
+hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, uint32_t k, double rtol2,
+                          uint32_t maxit, hipStream_t s);
 int cg_ws_doubles(uint32_t nleaves);
 int cg_grid(uint32_t nleaves);
+size_t cg_scalars_offset(uint32_t nleaves);
 
 // ---- mesh (k_mesh.hip) ----
 hipError_t launch_build_lut(const uint32_t* key, const uint8_t* lv, uint32_t nleaves, uint32_t* lut, int lut_level,
                             hipStream_t s);
+// dst[l] = src[old leaf holding the centre of new leaf l]
+hipError_t launch_remap_cells(const uint32_t* nxy, const uint8_t* nlv, uint32_t n, const uint32_t* okey,
+                              const uint8_t* olv, const uint32_t* olut, int olut_level, const double* src, double* dst,
+                              hipStream_t s);
 hipError_t launch_leaf_xy(const uint32_t* key, const uint8_t* lv, uint32_t nleaves, uint32_t* xy, hipStream_t s);
 __host__ __device__ inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
