@@ -44,13 +44,14 @@ __device__ __forceinline__ bool wall_rule(bool reflect, T& s, T& v, bool& lost) 
   return in1;
 }
 
-// Null-collision MCC of one candidate (v in registers), in two parts so a
-// workgroup can first sort its candidates by what happens to them and then
-// run each process densely.  collision_kind: electron elastic scattering,
-// ionization or a null collision (from u1 = the candidate's second word);
-// ions always go on to the charge-exchange test, whose partner velocity is
-// needed to decide.  collide_as: that process; returns true when an
-// ionization produced a birth (rec filled).
+// Null-collision MCC of one candidate (v in registers).  collision_kind:
+// electron elastic scattering, ionization or a null collision (from u1 = the
+// candidate's second word); ions always go on to the charge-exchange test,
+// whose partner velocity is needed to decide.  The processes are separate
+// functions: elastic scattering runs in place, in the lane of its particle;
+// ionization (with its newborn pair) and charge exchange are rarer and
+// dearer and run densely from a workgroup queue.  Event counts are kept by
+// the callers.
 enum : uint32_t { kCollNone = 0u, kCollElastic = 1u, kCollIonize = 2u, kCollCx = 3u };
 
 template <class T>
@@ -68,46 +69,48 @@ __device__ __forceinline__ uint32_t collision_kind(const SpeciesK<T>& k, uint32_
 }
 
 template <class T>
-__device__ __forceinline__ bool collide_as(uint32_t kind, const SpeciesK<T>& k, uint32_t r1, WordStream& ws, T& vx,
-                                           T& vy, T& vz, LStat& st, BirthRec<T>& rec) {
-  if (kind == kCollElastic) {
-    const T v2 = (vx * vx + vy * vy) + vz * vz;
-    const T vmag = sqrt(v2);
-    T dx, dy, dz;
-    isotropic<T>(ws, dx, dy, dz);
-    const T vd = (vx * dx + vy * dy) + vz * dz;
-    T vp2 = v2 - k.mu2 * (v2 - vmag * vd);
-    if (vp2 < (T)0) vp2 = (T)0;
-    const T vpm = sqrt(vp2);
-    vx = vpm * dx;
-    vy = vpm * dy;
-    vz = vpm * dz;
-    st.elastic++;
-    return false;
-  }
-  if (kind == kCollIonize) {
-    const T v2 = (vx * vx + vy * vy) + vz * vz;
-    const T u0 = unit_uniform<T>(ws.next());
-    const T v2ex = v2 - k.v_iz2;
-    const T v2a = u0 * v2ex;
-    const T v2b = v2ex - v2a;
-    T ax, ay, az, bx, by, bz;
-    isotropic<T>(ws, ax, ay, az);
-    isotropic<T>(ws, bx, by, bz);
-    const T va = sqrt(v2a), vb = sqrt(v2b);
-    vx = va * ax;
-    vy = va * ay;
-    vz = va * az;
-    rec.ve0 = vb * bx;
-    rec.ve1 = vb * by;
-    rec.ve2 = vb * bz;
-    rec.vi0 = k.v_thg * normal12<T>(ws);
-    rec.vi1 = k.v_thg * normal12<T>(ws);
-    rec.vi2 = k.v_thg * normal12<T>(ws);
-    st.ionization++;
-    return true;
-  }
-  // ion charge exchange with a gas atom drawn from the gas Maxwellian
+__device__ __forceinline__ void collide_elastic(const SpeciesK<T>& k, WordStream& ws, T& vx, T& vy, T& vz) {
+  const T v2 = (vx * vx + vy * vy) + vz * vz;
+  const T vmag = sqrt(v2);
+  T dx, dy, dz;
+  isotropic<T>(ws, dx, dy, dz);
+  const T vd = (vx * dx + vy * dy) + vz * dz;
+  T vp2 = v2 - k.mu2 * (v2 - vmag * vd);
+  if (vp2 < (T)0) vp2 = (T)0;
+  const T vpm = sqrt(vp2);
+  vx = vpm * dx;
+  vy = vpm * dy;
+  vz = vpm * dz;
+}
+
+template <class T>
+__device__ __forceinline__ void collide_ionize(const SpeciesK<T>& k, WordStream& ws, T& vx, T& vy, T& vz,
+                                               BirthRec<T>& rec) {
+  const T v2 = (vx * vx + vy * vy) + vz * vz;
+  const T u0 = unit_uniform<T>(ws.next());
+  const T v2ex = v2 - k.v_iz2;
+  const T v2a = u0 * v2ex;
+  const T v2b = v2ex - v2a;
+  T ax, ay, az, bx, by, bz;
+  isotropic<T>(ws, ax, ay, az);
+  isotropic<T>(ws, bx, by, bz);
+  const T va = sqrt(v2a), vb = sqrt(v2b);
+  vx = va * ax;
+  vy = va * ay;
+  vz = va * az;
+  rec.ve0 = vb * bx;
+  rec.ve1 = vb * by;
+  rec.ve2 = vb * bz;
+  rec.vi0 = k.v_thg * normal12<T>(ws);
+  rec.vi1 = k.v_thg * normal12<T>(ws);
+  rec.vi2 = k.v_thg * normal12<T>(ws);
+}
+
+// ion charge exchange with a gas atom drawn from the gas Maxwellian; true
+// when it happened
+template <class T>
+__device__ __forceinline__ bool collide_cx(const SpeciesK<T>& k, uint32_t r1, WordStream& ws, T& vx, T& vy, T& vz,
+                                           LStat& st) {
   const T u1 = unit_uniform<T>(r1);
   const T n0 = k.v_thg * normal12<T>(ws);
   const T n1 = k.v_thg * normal12<T>(ws);
@@ -115,13 +118,11 @@ __device__ __forceinline__ bool collide_as(uint32_t kind, const SpeciesK<T>& k, 
   const T dx = vx - n0, dy = vy - n1, dz = vz - n2;
   const T g = sqrt((dx * dx + dy * dy) + dz * dz);
   st.viol += (g > k.gmax) ? 1u : 0u;
-  if (u1 < k.a_cx * g) {
-    vx = n0;
-    vy = n1;
-    vz = n2;
-    st.cx++;
-  }
-  return false;
+  const bool hit = u1 < k.a_cx * g;
+  vx = hit ? n0 : vx;
+  vy = hit ? n1 : vy;
+  vz = hit ? n2 : vz;
+  return hit;
 }
 
 // Stage a birth: slot from one atomic per wave.
@@ -462,125 +463,77 @@ __device__ __forceinline__ bool push_one(const HotK<T>& H, const SpPtr<T>& P, ui
   }
 }
 
-// Candidate test result of one particle carried to the collision queue: the
-// second word of its stream and the two words left in block 0.
+// Candidate test result of one particle: the second word of its stream, the
+// two words left in block 0, and the velocity components the push does not
+// load (v_z; v_y too in 1D), fetched for candidates only.
 template <class T>
 struct CollIn {
   bool cand;
   uint32_t r1, wa, wb;
+  T vy, vz;
 };
 
-// Collision candidates of a workgroup wait in an LDS queue and are handled
-// densely (consecutive lanes take consecutive candidates), so the lanes of a
-// wave that do not collide do not pay for the collision of those that do.
-// The queue is drained once it holds kQDrain entries after a batch, and at
-// the end of the range; a batch adds at most K x kBlock entries.
-constexpr uint32_t kQCap = 384;
-constexpr uint32_t kQDrain = 128;
+// Ionizations and charge exchanges of a workgroup wait in an LDS queue and
+// are handled densely (consecutive lanes take consecutive entries), so the
+// lanes of a wave that do not take part do not pay for the long draws of the
+// few that do.  The queue is drained once it holds kQDrain entries after a
+// batch, and at the end of the range; a batch adds at most K x kBlock.
+constexpr uint32_t kQCap = 320;
+constexpr uint32_t kQDrain = 64;
 
 template <class T, int DIM>
 struct CollQueue {
-  uint32_t *n, *nel, *nx;   // candidates; elastic and expensive collisions found among them
-  uint32_t* e;              // collision list: elastic from the front, others from the back
-  uint32_t *i, *id, *r1, *wa, *wb, *w, *leaf;
-  T *v0, *s0, *s1, *v1;
+  uint32_t* n;
+  uint32_t *kind, *i, *id, *r1, *wa, *wb, *w, *leaf;
+  T *s0, *s1, *v0, *v1, *v2;
 };
 template <class T, int DIM>
 __device__ __forceinline__ CollQueue<T, DIM> coll_queue() {
-  __shared__ uint32_t qn, qnel, qnx;
-  __shared__ uint32_t qe[kQCap], qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
-  __shared__ T qv0[kQCap], qs0[kQCap];
+  __shared__ uint32_t qn;
+  __shared__ uint32_t qkind[kQCap], qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
+  __shared__ T qs0[kQCap], qv0[kQCap], qv1[kQCap], qv2[kQCap];
   CollQueue<T, DIM> q;
   q.n = &qn;
-  q.nel = &qnel;
-  q.nx = &qnx;
-  q.e = qe;
+  q.kind = qkind;
   q.i = qi;
   q.id = qid;
   q.r1 = qr1;
   q.wa = qwa;
   q.wb = qwb;
   q.w = qw;
-  q.v0 = qv0;
   q.s0 = qs0;
+  q.v0 = qv0;
+  q.v1 = qv1;
+  q.v2 = qv2;
   if constexpr (DIM == 2) {
     __shared__ uint32_t qleaf[kQCap];
-    __shared__ T qs1[kQCap], qv1[kQCap];
+    __shared__ T qs1[kQCap];
     q.leaf = qleaf;
     q.s1 = qs1;
-    q.v1 = qv1;
   } else {
     q.leaf = nullptr;
     q.s1 = nullptr;
-    q.v1 = nullptr;
   }
   return q;
 }
 
-// Collide the queued candidates: classify them (null collisions end there),
-// then run elastic scattering and the expensive processes (ionization with
-// its newborn pair, charge exchange with its Maxwellian partner) each one
-// collision per lane; write the velocities, stage the births and add the
-// newborn pairs' charge.  Empties the queue.  Every lane of the workgroup
-// calls it.
+// Run the queued ionizations and charge exchanges, one per lane: write the
+// velocities, stage the births and add the newborn pairs' charge.  Empties
+// the queue.  Every lane of the workgroup calls it.
 template <class T, int DIM>
 __device__ __forceinline__ void drain_queue(const InstDev<T>& I, const HotK<T>& H, const SpPtr<T>& P, int sp,
                                          uint32_t step, const CollQueue<T, DIM>& Q, unsigned long long* Qpar,
                                          DepCache& D, LStat& st) {
-  if (threadIdx.x == 0) {
-    *Q.nel = 0u;
-    *Q.nx = 0u;
-  }
-  __syncthreads();
   const uint32_t n = *Q.n;
-  const int lane = lane_id();
+#pragma unroll 1
   for (uint32_t t0 = 0; t0 < n; t0 += kBlock) {
     const uint32_t t = t0 + threadIdx.x;
-    uint32_t kind = kCollNone;
-    if (t < n) {
-      const uint32_t i = Q.i[t];
-      const T vy = DIM == 2 ? Q.v1[t] : *at(P.v1, i);
-      const T vz = *at(P.v2, i);
-      kind = collision_kind<T>(H.k, Q.r1[t], Q.v0[t], vy, vz, st);
-    }
-    const uint64_t be = __ballot(kind == kCollElastic);
-    const uint64_t bx = __ballot(kind == kCollIonize || kind == kCollCx);
-    uint32_t base_e = 0u, base_x = 0u;
-    if (lane == 0) {
-      if (be) base_e = atomicAdd(Q.nel, (uint32_t)__popcll(be));
-      if (bx) base_x = atomicAdd(Q.nx, (uint32_t)__popcll(bx));
-    }
-    base_e = __shfl(base_e, 0);
-    base_x = __shfl(base_x, 0);
-    const uint64_t below = lanes_le(lane) >> 1;
-    if (kind == kCollElastic) Q.e[base_e + (uint32_t)__popcll(be & below)] = t;
-    else if (kind != kCollNone) Q.e[kQCap - 1u - (base_x + (uint32_t)__popcll(bx & below))] = t | (kind << 16);
-  }
-  __syncthreads();
-  const uint32_t nel = *Q.nel, nx = *Q.nx;
-  for (uint32_t t0 = 0; t0 < nel; t0 += kBlock) {
-    const uint32_t t2 = t0 + threadIdx.x;
-    if (t2 < nel) {
-      const uint32_t t = Q.e[t2], i = Q.i[t];
-      T vx = Q.v0[t], vy = DIM == 2 ? Q.v1[t] : *at(P.v1, i), vz = *at(P.v2, i);
-      WordStream ws(H.key0, H.key1, Q.id[t], step, Q.wa[t], Q.wb[t]);
-      BirthRec<T> rec;
-      (void)collide_as<T>(kCollElastic, H.k, Q.r1[t], ws, vx, vy, vz, st, rec);
-      *at(P.v0, i) = vx;
-      *at(P.v1, i) = vy;
-      *at(P.v2, i) = vz;
-    }
-  }
-  for (uint32_t t0 = 0; t0 < nx; t0 += kBlock) {
-    const uint32_t t2 = t0 + threadIdx.x;
     bool birth = false;
     BirthRec<T> rec;
     uint32_t id = 0u, w = 0u, leaf = 0u;
     T s0 = (T)0, s1 = (T)0;
-    if (t2 < nx) {
-      const uint32_t e = Q.e[kQCap - 1u - t2];
-      const uint32_t t = e & 0xFFFFu, kind = e >> 16;
-      const uint32_t i = Q.i[t];
+    if (t < n) {
+      const uint32_t kind = Q.kind[t], i = Q.i[t];
       id = Q.id[t];
       w = Q.w[t];
       s0 = Q.s0[t];
@@ -588,9 +541,15 @@ __device__ __forceinline__ void drain_queue(const InstDev<T>& I, const HotK<T>& 
         s1 = Q.s1[t];
         leaf = Q.leaf[t];
       }
-      T vx = Q.v0[t], vy = DIM == 2 ? Q.v1[t] : *at(P.v1, i), vz = *at(P.v2, i);
+      T vx = Q.v0[t], vy = Q.v1[t], vz = Q.v2[t];
       WordStream ws(H.key0, H.key1, id, step, Q.wa[t], Q.wb[t]);
-      birth = collide_as<T>(kind, H.k, Q.r1[t], ws, vx, vy, vz, st, rec);
+      if (kind == kCollIonize) {
+        collide_ionize<T>(H.k, ws, vx, vy, vz, rec);
+        birth = true;
+        st.ionization++;
+      } else {
+        st.cx += collide_cx<T>(H.k, Q.r1[t], ws, vx, vy, vz, st) ? 1u : 0u;
+      }
       *at(P.v0, i) = vx;
       *at(P.v1, i) = vy;
       *at(P.v2, i) = vz;
@@ -669,7 +628,9 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
         if (moved[j]) leaf[j] = locate2d<T>(I, (uint32_t)(p[j].s0 * (T)65536), (uint32_t)(p[j].s1 * (T)65536));
     }
   }
-  // 5. collision candidates and their velocity components
+  // 5. collision candidates and their velocity components (a lane that is
+  // not a candidate reads the wave's first element instead, so the load is
+  // issued by every lane and costs no extra memory traffic)
   CollIn<T> ci[K];
   if constexpr (MCC) {
 #pragma unroll
@@ -684,7 +645,14 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
         ci[j].wb = ws.w1;
         ci[j].cand = (r0 >> 8) < k.tcand;
       }
+      const uint32_t i = i0 + (uint32_t)j * kBlock;
+      const uint32_t first = i - (uint32_t)lane_id();
+      const uint32_t iz = ci[j].cand ? i : (first < end ? first : end - 1u);
+      ci[j].vz = *at(P.v2, iz);
+      if constexpr (DIM == 1) ci[j].vy = *at(P.v1, iz);
+      else ci[j].vy = (T)0;
     }
+    issue_fence();
   }
   // 6. stage B of the next batch
 #pragma unroll
@@ -699,26 +667,45 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
     if (mcc) {
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const uint64_t bm = __ballot(ci[j].cand);
+        const uint32_t i = i0 + (uint32_t)j * kBlock;
+        T vy = DIM == 2 ? p[j].v1 : ci[j].vy;
+        T vz = ci[j].vz;
+        uint32_t kind = kCollNone;
+        if (ci[j].cand) kind = collision_kind<T>(k, ci[j].r1, p[j].v0, vy, vz, st);
+        // elastic scattering in place
+        const bool el = kind == kCollElastic;
+        st.elastic += el ? 1u : 0u;
+        if (el) {
+          WordStream ws(H.key0, H.key1, p[j].id, step, ci[j].wa, ci[j].wb);
+          collide_elastic<T>(k, ws, p[j].v0, vy, vz);
+          if constexpr (DIM == 2) p[j].v1 = vy;
+          else *at(P.v1, i) = vy;
+          *at(P.v2, i) = vz;
+        }
+        // ionization and charge exchange to the queue
+        const bool qx = kind == kCollIonize || kind == kCollCx;
+        const uint64_t bm = __ballot(qx);
         if (bm == 0ull) continue;
         const int lane = lane_id();
         const int leader = __ffsll((long long)bm) - 1;
         uint32_t base = 0u;
         if (lane == leader) base = atomicAdd(Q.n, (uint32_t)__popcll(bm));
         base = __shfl(base, leader);
-        if (!ci[j].cand) continue;
+        if (!qx) continue;
         const uint32_t t = base + (uint32_t)__popcll(bm & (lanes_le(lane) >> 1));
-        Q.i[t] = i0 + (uint32_t)j * kBlock;
+        Q.kind[t] = kind;
+        Q.i[t] = i;
         Q.id[t] = p[j].id;
         Q.r1[t] = ci[j].r1;
         Q.wa[t] = ci[j].wa;
         Q.wb[t] = ci[j].wb;
         Q.w[t] = p[j].w;
-        Q.v0[t] = p[j].v0;
         Q.s0[t] = p[j].s0;
+        Q.v0[t] = p[j].v0;
+        Q.v1[t] = vy;
+        Q.v2[t] = vz;
         if constexpr (DIM == 2) {
           Q.s1[t] = p[j].s1;
-          Q.v1[t] = p[j].v1;
           Q.leaf[t] = leaf[j];
         }
       }
