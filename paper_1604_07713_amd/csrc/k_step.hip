@@ -183,6 +183,22 @@ struct DepCache {
   uint32_t base;
 };
 
+// The workgroup's deposit window and hash in LDS (one allocation, whichever
+// variant of the particle loop a kernel runs).
+struct DepLds {
+  unsigned long long* win;
+  uint32_t* hkey;
+  unsigned long long* hval;
+  uint32_t* wbase;
+};
+__device__ __forceinline__ DepLds dep_lds() {
+  __shared__ unsigned long long win[kWin];
+  __shared__ uint32_t hkey[kHash];
+  __shared__ unsigned long long hval[kHash];
+  __shared__ uint32_t wbase;
+  return DepLds{win, hkey, hval, &wbase};
+}
+
 __device__ __forceinline__ void dep_add(DepCache& D, unsigned long long* g, uint32_t key, unsigned long long val) {
   if (key == kNoKey || val == 0ull) return;
   const uint32_t o = key - D.base;
@@ -314,8 +330,15 @@ __device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
 template <class T>
 struct PState {
   uint32_t w, cell, id;
-  T s0, s1, v0, v1;
+  T s0, s1, v0, v1, v2;
 };
+
+// 2D collision loop: v_z of every particle is prefetched with the rest of
+// its state (else loaded for the collision candidates only).
+#ifndef PIC_VZ_PRE
+#define PIC_VZ_PRE 1
+#endif
+constexpr bool kVzPre = PIC_VZ_PRE != 0;
 
 template <class T, bool MCC, int DIM>
 __device__ __forceinline__ void load_a(const SpPtr<T>& P, uint32_t i, uint32_t end, PState<T>& p) {
@@ -326,13 +349,14 @@ __device__ __forceinline__ void load_a(const SpPtr<T>& P, uint32_t i, uint32_t e
   p.id = MCC ? *at(P.id, ii) : 0u;
   p.w = i < end ? w : 0u;
 }
-template <class T, int DIM>
+template <class T, bool MCC, int DIM>
 __device__ __forceinline__ void load_b(const SpPtr<T>& P, uint32_t i, uint32_t end, PState<T>& p) {
   const uint32_t ii = i < end ? i : end - 1u;
   if (DIM == 2) {
     p.s0 = *at(P.s0, ii);
     p.s1 = *at(P.s1, ii);
     p.v1 = *at(P.v1, ii);
+    if (MCC && kVzPre) p.v2 = *at(P.v2, ii);
   } else {
     p.cell = 0u;
     p.s1 = (T)0;
@@ -645,18 +669,23 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
         ci[j].wb = ws.w1;
         ci[j].cand = (r0 >> 8) < k.tcand;
       }
-      const uint32_t i = i0 + (uint32_t)j * kBlock;
-      const uint32_t first = i - (uint32_t)lane_id();
-      const uint32_t iz = ci[j].cand ? i : (first < end ? first : end - 1u);
-      ci[j].vz = *at(P.v2, iz);
-      if constexpr (DIM == 1) ci[j].vy = *at(P.v1, iz);
-      else ci[j].vy = (T)0;
+      if constexpr (DIM == 2 && kVzPre) {
+        ci[j].vz = p[j].v2;
+        ci[j].vy = (T)0;
+      } else {
+        const uint32_t i = i0 + (uint32_t)j * kBlock;
+        const uint32_t first = i - (uint32_t)lane_id();
+        const uint32_t iz = ci[j].cand ? i : (first < end ? first : end - 1u);
+        ci[j].vz = *at(P.v2, iz);
+        if constexpr (DIM == 1) ci[j].vy = *at(P.v1, iz);
+        else ci[j].vy = (T)0;
+      }
     }
     issue_fence();
   }
   // 6. stage B of the next batch
 #pragma unroll
-  for (int j = 0; j < K; ++j) load_b<T, DIM>(P, inext0 + (uint32_t)j * kBlock, end, nxt[j]);
+  for (int j = 0; j < K; ++j) load_b<T, MCC, DIM>(P, inext0 + (uint32_t)j * kBlock, end, nxt[j]);
   issue_fence();
   // 7. collisions, births, stores, deposit
   if constexpr (DIM == 2 && DIRECT) {
@@ -813,10 +842,11 @@ template <class T, bool MCC, int DIM, int K, bool DIRECT>
 __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end, uint32_t step,
                                           unsigned long long* Qpar, unsigned long long* row) {
   if (begin >= end) return;   // uniform: the whole workgroup has no particles here
-  __shared__ unsigned long long win[kWin];
-  __shared__ uint32_t hkey[kHash];
-  __shared__ unsigned long long hval[kHash];
-  __shared__ uint32_t wbase_s;
+  const DepLds L = dep_lds();
+  unsigned long long* win = L.win;
+  uint32_t* hkey = L.hkey;
+  unsigned long long* hval = L.hval;
+  uint32_t& wbase_s = *L.wbase;
   const SpPtr<T> P = species_ptrs<T>(I, sp);
   const HotK<T> H = hot_constants<T>(I, sp);
   const bool mcc = MCC && H.k.mcc != PIC_MCC_NONE;   // uniform over the workgroup
@@ -852,7 +882,7 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   for (int j = 0; j < K; ++j) load_a<T, MCC, DIM>(P, begin + (uint32_t)j * kBlock + threadIdx.x, end, cur[j]);
   issue_fence();
 #pragma unroll
-  for (int j = 0; j < K; ++j) load_b<T, DIM>(P, begin + (uint32_t)j * kBlock + threadIdx.x, end, cur[j]);
+  for (int j = 0; j < K; ++j) load_b<T, MCC, DIM>(P, begin + (uint32_t)j * kBlock + threadIdx.x, end, cur[j]);
   issue_fence();
   __syncthreads();
   D.base = wbase_s;
@@ -955,14 +985,22 @@ __global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int
   const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - gs;
   const uint32_t nb = sp == 0 ? gs : grid - gs;
   const uint32_t count = sp == 0 ? n0 : n1;
-  const uint32_t unit = (uint32_t)K * kBlock;
+  constexpr int KU = K > batch_k<DIM, false>() ? K : batch_k<DIM, false>();
+  const uint32_t unit = (uint32_t)KU * kBlock;
   const uint32_t chunk = ((count + nb - 1u) / nb + unit - 1u) / unit * unit;
   unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
   zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
   const uint64_t begin64 = (uint64_t)b * chunk;
   const uint32_t begin = begin64 < count ? (uint32_t)begin64 : count;
   const uint32_t end = (uint64_t)begin + chunk < count ? begin + chunk : count;
-  run_range<T, MCC, DIM, K, DIRECT>(I, sp, begin, end, step, Qpar, I.part + (size_t)blockIdx.x * kNStat);
+  unsigned long long* row = I.part + (size_t)blockIdx.x * kNStat;
+  if constexpr (MCC) {
+    // a species without collisions takes the collisionless loop (uniform)
+    if (I.sk[sp].mcc == PIC_MCC_NONE) run_range<T, false, DIM, batch_k<DIM, false>(), DIRECT>(I, sp, begin, end, step, Qpar, row);
+    else run_range<T, true, DIM, K, DIRECT>(I, sp, begin, end, step, Qpar, row);
+  } else {
+    run_range<T, false, DIM, K, DIRECT>(I, sp, begin, end, step, Qpar, row);
+  }
   if (commit) last_block_commit(I.ctr, step);
 }
 
