@@ -424,6 +424,7 @@ void pic_destroy(pic_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (Slot& s : c->slots) s.release_all();
+  c->pool.clear();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);

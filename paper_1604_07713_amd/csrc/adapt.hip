@@ -17,20 +17,36 @@ namespace pic {
 namespace {
 
 // scoped device scratch, freed after the stream has drained
+// Scratch of one adaptation pass, from the context's device cache (blocks
+// are reusable after the context's next stream synchronization).
 struct Scratch {
-  hipStream_t stream = nullptr;
-  std::vector<void*> ptrs;
+  DevPool& pool;
+  std::vector<std::pair<size_t, void*>> blocks;
+  explicit Scratch(Ctx& C) : pool(C.pool) {}
   template <class T>
   T* get(size_t n) {
+    const size_t cls = DevPool::class_of(std::max<size_t>(n, 1) * sizeof(T));
     void* p = nullptr;
-    hip_check(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)), "hipMalloc scratch");
-    ptrs.push_back(p);
+    if (DevPool::pooled(cls)) {
+      p = pool.get(cls);
+    } else {
+      hip_check(hipMalloc(&p, cls), "hipMalloc scratch");
+    }
+    blocks.emplace_back(cls, p);
     return (T*)p;
   }
   ~Scratch() {
-    if (!ptrs.empty()) (void)hipDeviceSynchronize();
-    for (void* p : ptrs) (void)hipFree(p);
+    for (auto& b : blocks) {
+      if (DevPool::pooled(b.first)) {
+        pool.put(b.second, b.first);
+      } else {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.second);
+      }
+    }
   }
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
 };
 
 TreeView view(const Slot& sl) {
@@ -95,7 +111,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   relocate_all<T>(C, sl);
   // ---- coarsen and refine decided on the current tree ----
   {
-    Scratch S;
+    Scratch S(C);
     uint32_t* cnt = count_all<T>(C, sl, S);
     const uint32_t n = sl.nleaves;
     uint32_t* cflag = S.get<uint32_t>(n);
@@ -116,7 +132,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   }
   // ---- refine again while a leaf is over the upper bound ----
   for (;;) {
-    Scratch S;
+    Scratch S(C);
     uint32_t* cnt = count_all<T>(C, sl, S);
     const uint32_t n = sl.nleaves;
     uint32_t* emit = S.get<uint32_t>(n + 1);
@@ -133,7 +149,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   }
   // ---- 2:1 balance by refinement ----
   for (;;) {
-    Scratch S;
+    Scratch S(C);
     const uint32_t n = sl.nleaves;
     uint32_t* mark = S.get<uint32_t>(n);
     uint32_t* nmark = S.get<uint32_t>(1);
@@ -152,7 +168,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   relocate_all<T>(C, sl);
   // ---- split rounds ----
   for (;;) {
-    Scratch S;
+    Scratch S(C);
     uint32_t* cnt = count_all<T>(C, sl, S);
     Counters cn = read_counters(C, sl);
     const uint32_t nw = cn.next_id / 32u + 1u;
@@ -194,7 +210,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   // ---- merge rounds (leaves at the finest level over the upper bound) ----
   for (int sp = 0; sp < ns; ++sp) {
     for (;;) {
-      Scratch S;
+      Scratch S(C);
       uint32_t* cnt = count_all<T>(C, sl, S);
       const uint32_t n = sl.nleaves;
       uint32_t* groups = S.get<uint32_t>(n);

@@ -28,24 +28,87 @@ void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Err(PIC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+size_t DevPool::class_of(size_t bytes) {
+  if (bytes <= 4096) return 4096;
+  int top = 63 - __builtin_clzll((unsigned long long)bytes);
+  const size_t q = size_t(1) << (top - 2);   // four classes per power of two
+  return (bytes + q - 1) / q * q;
+}
+
+void* DevPool::get(size_t cls) {
+  auto it = free_.find(cls);
+  if (it != free_.end()) {
+    void* p = it->second;
+    free_.erase(it);
+    free_bytes -= cls;
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, cls) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    // give the cached blocks back and try once more
+    for (auto& kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+    free_bytes = 0;
+    if (hipMalloc(&p, cls) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Err(PIC_E_NOMEM, "device allocation of " + std::to_string(cls) + " bytes failed");
+    }
+  }
+  return p;
+}
+
+void DevPool::put(void* p, size_t cls) { pending_.emplace_back(cls, p); }
+
+void DevPool::synced() {
+  for (auto& e : pending_) {
+    if (free_bytes + e.first > kMaxFree) {
+      (void)hipFree(e.second);
+    } else {
+      free_.emplace(e.first, e.second);
+      free_bytes += e.first;
+    }
+  }
+  pending_.clear();
+}
+
+void DevPool::clear() {
+  for (auto& e : pending_) (void)hipFree(e.second);
+  pending_.clear();
+  for (auto& kv : free_) (void)hipFree(kv.second);
+  free_.clear();
+  free_bytes = 0;
+}
+
 void* Slot::alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
+  const size_t cls = DevPool::class_of(bytes);
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+  size_t held = bytes;
+  if (pool && DevPool::pooled(cls)) {
+    p = pool->get(cls);
+    held = cls;
+  } else if (hipMalloc(&p, bytes) != hipSuccess || !p) {
     (void)hipGetLastError();
     throw Err(PIC_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
   allocs.push_back(p);
-  alloc_bytes.push_back(bytes);
-  bytes_held += bytes;
+  alloc_bytes.push_back(held);
+  bytes_held += held;
   return p;
+}
+
+// Blocks taken from the pool carry their class size in alloc_bytes.
+static void give_back(DevPool* pool, void* p, size_t held) {
+  if (pool && DevPool::pooled(held) && held == DevPool::class_of(held)) pool->put(p, held);
+  else (void)hipFree(p);
 }
 
 void Slot::release(void* p) {
   if (!p) return;
   for (size_t i = 0; i < allocs.size(); ++i)
     if (allocs[i] == p) {
-      (void)hipFree(p);
+      give_back(pool, p, alloc_bytes[i]);
       bytes_held -= alloc_bytes[i];
       allocs.erase(allocs.begin() + i);
       alloc_bytes.erase(alloc_bytes.begin() + i);
@@ -54,7 +117,7 @@ void Slot::release(void* p) {
 }
 
 void Slot::release_all() {
-  for (void* p : allocs) (void)hipFree(p);
+  for (size_t i = 0; i < allocs.size(); ++i) give_back(pool, allocs[i], alloc_bytes[i]);
   allocs.clear();
   alloc_bytes.clear();
   bytes_held = 0;
@@ -275,6 +338,7 @@ std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel) 
 void Ctx::sync() {
   hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
   arena_off = 0;
+  pool.synced();
 }
 
 // ---------------------------------------------------------------------------
@@ -370,6 +434,7 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
   validate(d);
   sl = Slot();
   sl.live = true;
+  sl.pool = &C.pool;
   sl.d = d;
   sl.prec = d.precision;
   sl.esz = d.precision == 32 ? 4 : 8;

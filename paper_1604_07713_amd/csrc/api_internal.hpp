@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <map>
 #include <vector>
 
 #include "pic_internal.hpp"
@@ -40,8 +41,29 @@ struct PBuf {
   uint32_t* cell = nullptr;
 };
 
+// Device memory cache of a context.  Blocks of up to kMaxBlock bytes are
+// kept after release and handed out again (sizes rounded up to a class of at
+// most 25 % slack), so the tree rebuilds and the scratch of adaptation do not
+// call hipMalloc / hipFree (whose free synchronizes the device).  A released
+// block becomes reusable only after the context's next stream
+// synchronization, when no queued work can still read or write it.
+struct DevPool {
+  static constexpr size_t kMaxBlock = size_t(256) << 20;
+  static constexpr size_t kMaxFree = size_t(4) << 30;   // cached bytes beyond this are freed
+  std::multimap<size_t, void*> free_;
+  std::vector<std::pair<size_t, void*>> pending_;
+  size_t free_bytes = 0;
+  static size_t class_of(size_t bytes);
+  static bool pooled(size_t cls) { return cls <= kMaxBlock; }
+  void* get(size_t cls);   // cls from class_of; throws PIC_E_NOMEM
+  void put(void* p, size_t cls);
+  void synced();
+  void clear();
+};
+
 struct Slot {
   bool live = false;
+  DevPool* pool = nullptr;   // the context's cache (set when the slot is built)
   pic_instance_desc d{};
   int prec = 64;
   size_t esz = 8;
@@ -96,6 +118,7 @@ struct Slot {
 struct Ctx {
   std::vector<Slot> slots;
   hipStream_t stream = nullptr;
+  DevPool pool;
   std::string err;
   void* arena = nullptr;
   size_t arena_size = 0, arena_off = 0;
