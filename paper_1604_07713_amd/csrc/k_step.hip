@@ -1036,7 +1036,11 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRankPer = 4;
 constexpr uint32_t kRankChunk = 256;
-constexpr int kRankBlocks = 256;   // workgroups per instance of the ranking kernel
+#ifndef PIC_RANK_BLOCKS
+#define PIC_RANK_BLOCKS 1024
+#endif
+constexpr int kRankBlocks = 256;   // workgroups per instance of the batched ranking kernel
+constexpr int kRankBlocksPlain = PIC_RANK_BLOCKS;   // workgroups of the single-instance ranking kernel
 constexpr int kWriteBlocks = 64;   // workgroups per instance of the writing kernel
 
 template <class T>
@@ -1313,7 +1317,7 @@ hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uin
 template <class T>
 hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid) {
   (void)grid;
-  hipLaunchKernelGGL(k_birth_rank<T>, dim3(kRankBlocks), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_birth_rank<T>, dim3(kRankBlocksPlain), dim3(kBlock), 0, s, I);
   hipLaunchKernelGGL(k_birth_write<T>, dim3(kWriteBlocks), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
