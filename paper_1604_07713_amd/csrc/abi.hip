@@ -714,14 +714,19 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   const Mesh2D m = mesh_of(sl);
   const uint32_t n = sl.nleaves;
   if (!sl.stencil_ok) {
-    for (void* p : {(void*)sl.st.nbr, (void*)sl.st.coef, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
+    for (void* p : {(void*)sl.st.nbr, (void*)sl.st.code, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
       sl.release(p);
     sl.st.nbr = (uint32_t*)sl.alloc(4 * 8 * (size_t)n);
-    sl.st.coef = (double*)sl.alloc(8 * 8 * (size_t)n);
+    sl.st.code = (uint32_t*)sl.alloc(4 * ((size_t)n + 1));
     sl.st.diag = (double*)sl.alloc(8 * (size_t)n);
     sl.st.bnd = (double*)sl.alloc(8 * (size_t)n);
     sl.cg_ws = (double*)sl.alloc(8 * (size_t)cg_ws_doubles(n));
+    hip_check(hipMemsetAsync(sl.st.code + n, 0, 4, c->stream), "memset");
     hip_check(launch_build_stencil(m, sl.st, c->stream), "stencil");
+    uint32_t bad = 0;
+    hip_check(hipMemcpyAsync(&bad, sl.st.code + n, 4, hipMemcpyDeviceToHost, c->stream), "read");
+    c->sync();
+    if (bad) throw Err(PIC_E_STATE, "the tree is not 2:1 balanced across faces");
     sl.stencil_ok = true;
   }
   if (phi_init) hip_check(hipMemcpy(sl.phi64, phi_init, 8 * (size_t)n, hipMemcpyHostToDevice), "upload");

@@ -385,7 +385,7 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   hip_check(launch_build_lut(sl.key, sl.lv, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut");
   // per-leaf field and deposit arrays
   for (void* p : {(void*)sl.E, (void*)sl.e64, (void*)sl.cphi, (void*)sl.grad, (void*)sl.Q, (void*)sl.off,
-                  (void*)sl.st.nbr, (void*)sl.st.coef, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
+                  (void*)sl.st.nbr, (void*)sl.st.code, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
     sl.release(p);
   sl.st = Stencil2D{nullptr, nullptr, nullptr, nullptr};
   sl.cg_ws = nullptr;

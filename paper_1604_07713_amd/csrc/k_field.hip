@@ -278,6 +278,18 @@ hipError_t launch_round_table(const double* src, T* dst, int64_t n, hipStream_t 
 // ---------------------------------------------------------------------------
 // 2D finite-volume operator on the leaves
 // ---------------------------------------------------------------------------
+// Face coefficient min(h_a, h_b) / ((h_a + h_b) / 2) of a 2:1 tree: 1 between
+// leaves of one level, the double nearest 2/3 between leaves one level apart
+// (the quotient of exact binary fractions, whatever the levels).
+constexpr double kFaceTwoThirds = 2.0 / 3.0;
+__device__ __forceinline__ uint32_t face_code(double c, uint32_t* bad) {
+  if (c == 1.0) return 1u;
+  if (c == kFaceTwoThirds) return 2u;
+  *bad = 1u;
+  return 0u;
+}
+__device__ __forceinline__ double face_coef(uint32_t k) { return k == 1u ? 1.0 : (k == 2u ? kFaceTwoThirds : 0.0); }
+
 __global__ void k_build_stencil(Mesh2D m, Stencil2D st) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= m.nleaves) return;
@@ -285,7 +297,7 @@ __global__ void k_build_stencil(Mesh2D m, Stencil2D st) {
   const int la = m.lv[l];
   const double ha = ldexp(1.0, -la);
   uint32_t* nb = st.nbr + (size_t)l * 8u;
-  double* cf = st.coef + (size_t)l * 8u;
+  uint32_t code = 0u;
   int k = 0;
   double diag = 0.0, bnd = 0.0;
   const uint32_t half = b.size >> 1;
@@ -311,7 +323,7 @@ __global__ void k_build_stencil(Mesh2D m, Stencil2D st) {
     const double h1 = ldexp(1.0, -l1);
     const double c1 = fmin(ha, h1) / ((ha + h1) / 2.0);
     nb[k] = n1;
-    cf[k] = c1;
+    code |= face_code(c1, st.code + m.nleaves) << (2 * k);
     ++k;
     diag = diag + c1;
     if (l1 > la) {   // two finer neighbours share this side
@@ -319,15 +331,13 @@ __global__ void k_build_stencil(Mesh2D m, Stencil2D st) {
       const double h2 = ldexp(1.0, -(int)m.lv[n2]);
       const double c2 = fmin(ha, h2) / ((ha + h2) / 2.0);
       nb[k] = n2;
-      cf[k] = c2;
+      code |= face_code(c2, st.code + m.nleaves) << (2 * k);
       ++k;
       diag = diag + c2;
     }
   }
-  for (; k < 8; ++k) {
-    nb[k] = l;
-    cf[k] = 0.0;
-  }
+  for (; k < 8; ++k) nb[k] = l;
+  st.code[l] = code;
   st.diag[l] = diag;
   st.bnd[l] = bnd;
 }
@@ -410,9 +420,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, con
     b = b + st.bnd[i];
     double ax = st.diag[i] * x[i];
     const uint32_t* nb = st.nbr + (size_t)i * 8u;
-    const double* cf = st.coef + (size_t)i * 8u;
+    const uint32_t code = st.code[i];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) ax = ax - cf[k] * x[nb[k]];
+    for (int k = 0; k < 8; ++k) {
+      ax = ax - face_coef((code >> (2 * k)) & 3u) * x[nb[k]];
+    }
     const double ri = b - ax;
     const double zi = ri / st.diag[i];
     w.r[i] = ri;
@@ -473,11 +485,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(Mesh2D m, Stencil2D st, doubl
     const double pi = fma(beta, po[i], z[i]);
     double y = st.diag[i] * pi;
     const uint32_t* nb = st.nbr + (size_t)i * 8u;
-    const double* cf = st.coef + (size_t)i * 8u;
+    const uint32_t code = st.code[i];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const uint32_t j = nb[c];
-      y = y - cf[c] * fma(beta, po[j], z[j]);
+      y = y - face_coef((code >> (2 * c)) & 3u) * fma(beta, po[j], z[j]);
     }
     pn[i] = pi;
     w.q[i] = y;

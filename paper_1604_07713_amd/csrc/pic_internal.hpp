@@ -133,8 +133,12 @@ template <class T> hipError_t launch_corner_field(const Mesh2D& m, const double*
 hipError_t launch_cell_to_corner_phi(const Mesh2D& m, const double* cell_phi, double* corner_phi, hipStream_t s);
 template <class T> hipError_t launch_round_table(const double* src, T* dst, int64_t n, hipStream_t s);
 struct Stencil2D {
-  uint32_t* nbr;     // [nleaves][8], kNoKey-free: unused entries point at the leaf itself with coef 0
-  double* coef;      // [nleaves][8]
+  uint32_t* nbr;     // [nleaves][8]; unused entries point at the leaf itself
+  // [nleaves + 1]: 2 bits per neighbour entry k (bits 2k, 2k+1): 0 unused,
+  // 1 face coefficient 1 (same level), 2 coefficient 2/3 (levels one apart);
+  // the last word is set when a face between leaves more than one level
+  // apart was found (not a 2:1 tree)
+  uint32_t* code;
   double* diag;      // [nleaves]
   double* bnd;       // [nleaves] Dirichlet contribution to the right-hand side
 };
