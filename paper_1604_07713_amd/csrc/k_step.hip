@@ -910,9 +910,10 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
       else process_batch<T, MCC, DIM, K, DIRECT, false>(I, H, P, sp, base + threadIdx.x, nxt, cur, end, step, Qpar, D, st, Q);
     }
   } else {
-    // collision kernels: one batch per trip; the candidate queue is drained
-    // at the top of a trip once it holds kQDrain entries, and at the end.
-    // The single drain site keeps the collision code in the kernel once.
+    // collision kernels: one batch per trip; the queue of ionizations and
+    // charge exchanges is drained at the top of a trip once it holds kQDrain
+    // entries, and at the end.  The single drain site keeps that code in the
+    // kernel once.
     bool in_cur = true;
     for (;;) {
       const bool done = base >= end;

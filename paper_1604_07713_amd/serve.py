@@ -30,8 +30,9 @@ GIB = 1 << 30
 
 
 class Job:
-    def __init__(self, spec):
+    def __init__(self, spec, precision=32):
         self.spec = spec
+        self.precision = precision
         self.kind = spec["kind"]
         self.arrival = spec["arrival"]
         self.steps_total = int(spec["steps"])
@@ -45,23 +46,25 @@ class Job:
         self.result = None
         if self.kind == "ccp":
             self.desc = I.ccp_desc(ncells=spec["ncells"], ppc=spec["ppc"], voltage=spec["voltage"],
-                                   pressure_mtorr=spec["pressure"], precision=32, seed=5,
+                                   pressure_mtorr=spec["pressure"], precision=precision, seed=5,
                                    instance_key=spec["key"])
             self.nparticles = 2 * spec["ncells"] * spec["ppc"]
         else:
-            self.desc = I.streamer_desc(side=spec["side"], precision=32, seed=5, instance_key=spec["key"])
+            self.desc = I.streamer_desc(side=spec["side"], precision=precision, seed=5, instance_key=spec["key"])
             self.nparticles = 2 * spec["npairs"]
 
     def projected_bytes(self, growth_ccp=3.0, growth_streamer=32.0):
         """Device footprint if the population grows by the given factor:
-        particle slots (two buffers of s, v, w, id, cell in FP32) with the
-        library's births/sort headroom, births staging, and the mesh."""
+        particle slots (two buffers of s, v, w, id, cell in the particle
+        precision) with the library's births/sort headroom, births staging,
+        and the mesh."""
+        e = self.precision // 8
         if self.kind == "ccp":
-            per_slot = 2 * (4 * 4 + 12) + 44
+            per_slot = 2 * (4 * e + 12) + 11 * e
             slots = 2.0 * growth_ccp * self.nparticles + 8192
             mesh = 8 * 40 * (self.spec["ncells"] + 1)
         else:
-            per_slot = 2 * (5 * 4 + 12) + 48
+            per_slot = 2 * (5 * e + 12) + 12 * e
             slots = 2.0 * growth_streamer * self.nparticles + 8192
             leaves = max(1024.0, growth_streamer * self.nparticles / 16.0)
             mesh = leaves * 400 + 4 * (1 << 18)
@@ -70,7 +73,7 @@ class Job:
 
 class Server:
     def __init__(self, budget_bytes=None, tick_steps=25, field_every=10, adapt_every=10, max_slots=512,
-                 keep_results=False, stream=None):
+                 keep_results=False, stream=None, batched=True):
         self.ctx = B.Context([], stream=stream)
         if budget_bytes is None:
             import torch
@@ -82,6 +85,7 @@ class Server:
         self.adapt_every = adapt_every
         self.max_slots = max_slots
         self.keep_results = keep_results
+        self.batched = batched   # False: every job steps with its own launches (the plain method)
         self.pending = []
         self.running = {}
         self.done = []
@@ -127,13 +131,16 @@ class Server:
         full = [j for j in jobs if j.steps_total - j.steps_done >= K]
         rest = [j for j in jobs if j.steps_total - j.steps_done < K]
         upd = 0
-        groups = ([(full, K)] if full else []) + [([j], j.steps_total - j.steps_done) for j in rest]
+        if self.batched:
+            groups = ([(full, K)] if full else []) + [([j], j.steps_total - j.steps_done) for j in rest]
+        else:
+            groups = [([j], min(K, j.steps_total - j.steps_done)) for j in jobs]
         for group, n in groups:
             if n <= 0:
                 continue
             vn = np.stack([I.drive_voltage(j.desc, np.arange(j.steps_done + 1, j.steps_done + n + 1))
                            for j in group], axis=1)
-            st = self.ctx.step(-1, n, vn, solve_field=True, sort_every=20, batched=1,
+            st = self.ctx.step(-1, n, vn, solve_field=True, sort_every=20, batched=1 if self.batched else 0,
                                slots=[j.slot for j in group])
             u = st["alive_start"][0] + st["alive_start"][1]
             upd += u
@@ -226,7 +233,7 @@ class Server:
         self.ctx.close()
 
 
-def make_jobs(rate=20.0, duration=60.0, seed=5, scale=1.0, max_jobs=None):
+def make_jobs(rate=20.0, duration=60.0, seed=5, scale=1.0, max_jobs=None, precision=32):
     specs = I.job_stream(rate=rate, duration=duration, seed=seed)
     jobs = []
     for s in specs:
@@ -234,7 +241,7 @@ def make_jobs(rate=20.0, duration=60.0, seed=5, scale=1.0, max_jobs=None):
             s = dict(s, steps=max(1, int(s["steps"] * scale)))
         else:
             s = dict(s, steps=max(10, int(s["steps"] * scale)))
-        jobs.append(Job(s))
+        jobs.append(Job(s, precision=precision))
         if max_jobs and len(jobs) >= max_jobs:
             break
     return jobs
@@ -247,16 +254,19 @@ def main():
     ap.add_argument("--max-wall", type=float, default=None, help="stop serving after this many seconds")
     ap.add_argument("--steps-scale", type=float, default=1.0, help="scale every job's step count")
     ap.add_argument("--tick-steps", type=int, default=25)
+    ap.add_argument("--plain", action="store_true",
+                    help="the plain method: FP64 particles, every job stepped with its own launches")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    jobs = make_jobs(args.rate, args.duration, scale=args.steps_scale)
-    srv = Server(tick_steps=args.tick_steps)
+    jobs = make_jobs(args.rate, args.duration, scale=args.steps_scale, precision=64 if args.plain else 32)
+    srv = Server(tick_steps=args.tick_steps, batched=not args.plain)
     m = srv.run(jobs, max_wall=args.max_wall)
     offered = sum(j.nparticles * j.steps_total for j in jobs) / max(args.duration, 1e-9)
     m["offered_updates_per_s_lower_bound"] = offered
     m["ccp_jobs"] = sum(1 for j in jobs if j.kind == "ccp")
     m["streamer_jobs"] = sum(1 for j in jobs if j.kind == "streamer")
+    m["method"] = "plain FP64, per-job launches" if args.plain else "batched FP32, one launch for all 1D jobs"
     print(json.dumps(m), flush=True)
     srv.close()
 
