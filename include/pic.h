@@ -183,6 +183,12 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats);
  * units: w_units * 2^F (F = 24 FP32, 32 FP64); 2D: w_units. */
 int pic_deposit(pic_ctx c, int slot, uint64_t* q_out);
 
+/* Copy the latest per-species integer charge sums to q_out[2][nq] without
+ * depositing again: after pic_step, the sums the last step's particle loop
+ * accumulated (its survivors and births); after pic_deposit or pic_adapt,
+ * theirs.  Units as pic_deposit.  PIC_E_ARG if q_out is NULL. */
+int pic_deposit_read(pic_ctx c, int slot, uint64_t* q_out);
+
 /* Poisson from the latest deposit.  1D: Thomas with phi(0) = phi_left,
  * phi(L) = 0; outputs phi_out/e_out[ncells+1] (nullable).  2D: FV +
  * Jacobi CG from phi_init (nullable) to rtol, at most maxit iterations;

@@ -90,6 +90,7 @@ EXPORTS = {
     "pic_leapfrog_start": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_step": (C.c_int, [C.c_void_p, C.POINTER(StepArgs), C.POINTER(StepStats)]),
     "pic_deposit": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "pic_deposit_read": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "pic_field_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                                   C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "pic_adapt": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(AdaptArgs), C.POINTER(AdaptStats)]),
@@ -246,6 +247,12 @@ class Context:
         n = self.nq(slot)
         q = np.zeros((2, n), dtype=np.uint64)
         self._check(lib().pic_deposit(self.h, slot, _p(q)))
+        return q
+
+    def deposit_read(self, slot=0):
+        n = self.nq(slot)
+        q = np.zeros((2, n), dtype=np.uint64)
+        self._check(lib().pic_deposit_read(self.h, slot, _p(q)))
         return q
 
     def adapt(self, slot=0, n_lo=16, n_hi=64):

@@ -692,6 +692,17 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out) {
   PIC_GUARD_END(c)
 }
 
+int pic_deposit_read(pic_ctx c, int slot, uint64_t* q_out) {
+  PIC_GUARD_BEGIN
+  if (!q_out) throw Err(PIC_E_ARG, "null output");
+  Slot& sl = get_slot(c, slot);
+  Counters cn = read_counters(*c, sl);
+  const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
+  hip_check(hipMemcpy(q_out, latest, 8 * 2 * (size_t)sl.nq, hipMemcpyDeviceToHost), "read");
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
 int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init, double rtol, int maxit,
                     double* phi_out, double* e_out, int* iters, double* relres) {
   PIC_GUARD_BEGIN
