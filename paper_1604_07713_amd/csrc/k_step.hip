@@ -502,8 +502,12 @@ struct CollIn {
 // lanes of a wave that do not take part do not pay for the long draws of the
 // few that do.  The queue is drained once it holds kQDrain entries after a
 // batch, and at the end of the range; a batch adds at most K x kBlock.
-constexpr uint32_t kQCap = 320;
 constexpr uint32_t kQDrain = 64;
+// capacity for K particles per lane: what is left below kQDrain plus a batch
+template <int K>
+constexpr uint32_t q_cap() {
+  return kQDrain + (uint32_t)K * kBlock;
+}
 
 template <class T, int DIM>
 struct CollQueue {
@@ -511,8 +515,9 @@ struct CollQueue {
   uint32_t *kind, *i, *id, *r1, *wa, *wb, *w, *leaf;
   T *s0, *s1, *v0, *v1, *v2;
 };
-template <class T, int DIM>
+template <class T, int DIM, int K>
 __device__ __forceinline__ CollQueue<T, DIM> coll_queue() {
+  constexpr uint32_t kQCap = q_cap<K>();
   __shared__ uint32_t qn;
   __shared__ uint32_t qkind[kQCap], qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
   __shared__ T qs0[kQCap], qv0[kQCap], qv1[kQCap], qv2[kQCap];
@@ -852,8 +857,7 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
   const bool mcc = MCC && H.k.mcc != PIC_MCC_NONE;   // uniform over the workgroup
   CollQueue<T, DIM> Q{};
   if constexpr (MCC) {
-    static_assert(kQDrain - 1u + (uint32_t)K * kBlock <= kQCap, "collision queue too small for a batch");
-    Q = coll_queue<T, DIM>();
+    Q = coll_queue<T, DIM, K>();
     if (threadIdx.x == 0) *Q.n = 0u;
   }
   DepCache D{win, hkey, hval, 0u};
@@ -949,12 +953,15 @@ __device__ __forceinline__ void run_range(const InstDev<T>& I, int sp, uint32_t 
 #ifndef PIC_BATCH_1D
 #define PIC_BATCH_1D 2
 #endif
-#ifndef PIC_BATCH_MCC
-#define PIC_BATCH_MCC 1
+#ifndef PIC_BATCH_MCC1D
+#define PIC_BATCH_MCC1D 2
 #endif
-template <int DIM, bool MCC>
+#ifndef PIC_BATCH_MCC2D
+#define PIC_BATCH_MCC2D 1
+#endif
+template <class T, int DIM, bool MCC>
 constexpr int batch_k() {
-  return MCC ? PIC_BATCH_MCC : DIM == 2 ? PIC_BATCH_2D : PIC_BATCH_1D;
+  return MCC ? (DIM == 2 ? PIC_BATCH_MCC2D : PIC_BATCH_MCC1D) : DIM == 2 ? PIC_BATCH_2D : PIC_BATCH_1D;
 }
 
 // Plain launch over one instance: workgroups [0, gs) own consecutive chunks
@@ -971,7 +978,7 @@ constexpr int batch_k() {
 #endif
 template <class T, bool MCC, int DIM, bool DIRECT>
 __global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int commit) {
-  constexpr int K = batch_k<DIM, MCC>();
+  constexpr int K = batch_k<T, DIM, MCC>();
   const uint32_t step = I.ctr->step;
   const uint32_t n0 = I.ctr->count[0];
   const uint32_t n1 = I.nspecies == 2 ? I.ctr->count[1] : 0u;
@@ -986,7 +993,7 @@ __global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int
   const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - gs;
   const uint32_t nb = sp == 0 ? gs : grid - gs;
   const uint32_t count = sp == 0 ? n0 : n1;
-  constexpr int KU = K > batch_k<DIM, false>() ? K : batch_k<DIM, false>();
+  constexpr int KU = K > batch_k<T, DIM, false>() ? K : batch_k<T, DIM, false>();
   const uint32_t unit = (uint32_t)KU * kBlock;
   const uint32_t chunk = ((count + nb - 1u) / nb + unit - 1u) / unit * unit;
   unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
@@ -997,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int
   unsigned long long* row = I.part + (size_t)blockIdx.x * kNStat;
   if constexpr (MCC) {
     // a species without collisions takes the collisionless loop (uniform)
-    if (I.sk[sp].mcc == PIC_MCC_NONE) run_range<T, false, DIM, batch_k<DIM, false>(), DIRECT>(I, sp, begin, end, step, Qpar, row);
+    if (I.sk[sp].mcc == PIC_MCC_NONE) run_range<T, false, DIM, batch_k<T, DIM, false>(), DIRECT>(I, sp, begin, end, step, Qpar, row);
     else run_range<T, true, DIM, K, DIRECT>(I, sp, begin, end, step, Qpar, row);
   } else {
     run_range<T, false, DIM, K, DIRECT>(I, sp, begin, end, step, Qpar, row);
@@ -1020,7 +1027,7 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
     const uint32_t end = wi.end < count ? wi.end : count;
     unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
     if (wi.begin == 0 && sp == 0) zero_other_parity(I.Q, I.nq, step, I.nspecies, threadIdx.x, kBlock);
-    run_range<T, MCC, 1, batch_k<1, MCC>(), false>(I, sp, wi.begin, end, step, Qpar, bpart + (size_t)it * kNStat);
+    run_range<T, MCC, 1, batch_k<T, 1, MCC>(), false>(I, sp, wi.begin, end, step, Qpar, bpart + (size_t)it * kNStat);
   }
 }
 
