@@ -207,21 +207,24 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
     hip_check(launch_split_commit(sl.ctr, np, ns, C.stream), "split commit");
     st.split_parents += (int64_t)tot;
   }
-  // ---- merge rounds (leaves at the finest level over the upper bound) ----
-  for (int sp = 0; sp < ns; ++sp) {
-    for (;;) {
-      Scratch S(C);
-      uint32_t* cnt = count_all<T>(C, sl, S);
-      const uint32_t n = sl.nleaves;
-      uint32_t* groups = S.get<uint32_t>(n);
-      uint32_t* ng = S.get<uint32_t>(1);
+  // ---- merge (leaves at the finest level over the upper bound) ----
+  // One count serves both species (merging one leaves the other's counts as
+  // they are); the merge kernel runs every round of a leaf, so one launch
+  // per species finishes it.
+  {
+    Scratch S(C);
+    uint32_t* cnt = count_all<T>(C, sl, S);
+    const uint32_t n = sl.nleaves;
+    uint32_t* groups = S.get<uint32_t>(n);
+    uint32_t* ng = S.get<uint32_t>(1);
+    uint32_t* flags = S.get<uint32_t>(1);
+    uint32_t* npairs = S.get<uint32_t>(1);
+    double* energy = S.get<double>(1);
+    for (int sp = 0; sp < ns; ++sp) {
       hip_check(hipMemsetAsync(ng, 0, 4, C.stream), "memset");
       hip_check(launch_merge_groups(cnt, n, sp, n_hi, groups, ng, C.stream), "merge groups");
       const uint32_t ngroups = read1(C, ng);
-      if (!ngroups) break;
-      uint32_t* flags = S.get<uint32_t>(1);
-      uint32_t* npairs = S.get<uint32_t>(1);
-      double* energy = S.get<double>(1);
+      if (!ngroups) continue;
       hip_check(hipMemsetAsync(flags, 0, 4, C.stream), "memset");
       hip_check(hipMemsetAsync(npairs, 0, 4, C.stream), "memset");
       hip_check(hipMemsetAsync(energy, 0, 8, C.stream), "memset");
@@ -238,14 +241,13 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
       upload_dev(C, sl);
       {
         const InstDev<T> I = make_dev<T>(sl);
-        hip_check(launch_merge<T>(I, sp, groups, ngroups, cnt, sl.off, flags, energy, npairs, C.stream), "merge");
+        hip_check(launch_merge<T>(I, sp, groups, ngroups, cnt, sl.off, n_hi, flags, energy, npairs, C.stream), "merge");
       }
-      uint32_t fl = read1(C, flags);
+      const uint32_t fl = read1(C, flags);
       const uint32_t pairs = read1(C, npairs);
       st.merge_energy_change += read1(C, energy);
       if (fl) throw Err(PIC_E_CAPACITY, "a leaf holds more particles than a merge round can sort");
       st.merged_pairs += pairs;
-      if (!pairs) break;
     }
   }
   // ---- drop merged-away particles, order by leaf, fresh deposit ----

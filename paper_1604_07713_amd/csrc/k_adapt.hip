@@ -418,14 +418,21 @@ __device__ __forceinline__ bool merge_less(uint32_t oa, T va, uint32_t ia, uint3
   return ia < ib;
 }
 
+// One workgroup per leaf runs the merge rounds of that leaf one after the
+// other (sort the survivors, merge the pairs) until it holds at most n_hi
+// particles or a round merges nothing: the rounds of different leaves are
+// independent, so this equals rounds taken over all leaves at once.  A round
+// pairs at most kMergeMax / 2 = blockDim particles, one pair per thread.
 template <class T>
 __global__ __launch_bounds__(1024) void k_merge(InstDev<T> I, int sp, const uint32_t* groups, const uint32_t* cnt,
-                                                const uint32_t* end_off, uint32_t* flags, double* energy,
+                                                const uint32_t* end_off, int n_hi, uint32_t* flags, double* energy,
                                                 uint32_t* npairs) {
   __shared__ uint32_t soct[kMergeMax];
   __shared__ T sv2[kMergeMax];
   __shared__ uint32_t sid[kMergeMax];
   __shared__ uint32_t sidx[kMergeMax];
+  __shared__ uint32_t skipped;
+  static_assert(kMergeMax == 2 * 1024, "one pair per thread");
   const uint32_t leaf = groups[blockIdx.x];
   const uint32_t n = cnt[(size_t)sp * I.nleaves + leaf];
   if (n > kMergeMax) {
@@ -433,42 +440,13 @@ __global__ __launch_bounds__(1024) void k_merge(InstDev<T> I, int sp, const uint
     return;
   }
   const uint32_t first = end_off[leaf] - n;
-  uint32_t np2 = 1;
-  while (np2 < n) np2 <<= 1;
-  for (uint32_t t = threadIdx.x; t < np2; t += blockDim.x) {
-    if (t < n) {
-      const uint32_t i = first + t;
-      const T vx = G(I.v[sp][0])[i], vy = G(I.v[sp][1])[i], vz = G(I.v[sp][2])[i];
-      soct[t] = (vx < (T)0 ? 1u : 0u) | (vy < (T)0 ? 2u : 0u) | (vz < (T)0 ? 4u : 0u);
-      sv2[t] = (vx * vx + vy * vy) + vz * vz;
-      sid[t] = G(I.id[sp])[i];
-      sidx[t] = i;
-    } else {
-      soct[t] = 0xFFFFFFFFu;   // padding sorts last
-      sv2[t] = (T)0;
-      sid[t] = 0xFFFFFFFFu;
-      sidx[t] = 0xFFFFFFFFu;
-    }
-  }
-  __syncthreads();
-  // bitonic sort on (oct, v2, id)
-  for (uint32_t k = 2; k <= np2; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < np2; t += blockDim.x) {
-        const uint32_t p = t ^ j;
-        if (p > t) {
-          const bool up = (t & k) == 0;
-          const bool lt = merge_less<T>(soct[p], sv2[p], sid[p], soct[t], sv2[t], sid[t]);
-          if (lt == up) {
-            uint32_t a = soct[t]; soct[t] = soct[p]; soct[p] = a;
-            T b = sv2[t]; sv2[t] = sv2[p]; sv2[p] = b;
-            a = sid[t]; sid[t] = sid[p]; sid[p] = a;
-            a = sidx[t]; sidx[t] = sidx[p]; sidx[p] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+    const uint32_t i = first + t;
+    const T vx = G(I.v[sp][0])[i], vy = G(I.v[sp][1])[i], vz = G(I.v[sp][2])[i];
+    soct[t] = (vx < (T)0 ? 1u : 0u) | (vy < (T)0 ? 2u : 0u) | (vz < (T)0 ? 4u : 0u);
+    sv2[t] = (vx * vx + vy * vy) + vz * vz;
+    sid[t] = G(I.id[sp])[i];
+    sidx[t] = i;
   }
   // leaf box for the clamp
   const uint32_t xy = G(I.leaf_xy)[leaf];
@@ -477,32 +455,101 @@ __global__ __launch_bounds__(1024) void k_merge(InstDev<T> I, int sp, const uint
   const T hi[2] = {(T)((xy >> 16) + S) * (T)1.52587890625e-05, (T)((xy & 0xFFFFu) + S) * (T)1.52587890625e-05};
   double de = 0.0;
   uint32_t pairs = 0;
-  for (uint32_t t = threadIdx.x; 2u * t + 1u < n; t += blockDim.x) {
-    const uint32_t ia = sidx[2 * t], ib = sidx[2 * t + 1];
-    const uint32_t wa_u = G(I.w[sp])[ia], wb_u = G(I.w[sp])[ib];
-    const uint64_t ws = (uint64_t)wa_u + (uint64_t)wb_u;
-    if (ws > 0xFFFFFFFFull) continue;
-    const double wa = (double)wa_u, wb = (double)wb_u, wt = (double)ws;
-    const bool a_keeps = G(I.id[sp])[ia] < G(I.id[sp])[ib];
-    const uint32_t keep = a_keeps ? ia : ib, gone = a_keeps ? ib : ia;
-    T ns[2], nv[3];
-    for (int c = 0; c < 2; ++c) {
-      T x = (T)((wa * (double)G(I.s[sp][c])[ia] + wb * (double)G(I.s[sp][c])[ib]) / wt);
-      if (x < lo[c]) x = lo[c];
-      if (x >= hi[c]) x = prev_toward_zero(hi[c]);
-      ns[c] = x;
+  uint32_t m = n;   // survivors of the leaf, in sid/soct/sv2/sidx[0, m)
+  for (;;) {
+    uint32_t np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    for (uint32_t t = m + threadIdx.x; t < np2; t += blockDim.x) {
+      soct[t] = 0xFFFFFFFFu;   // padding sorts last
+      sv2[t] = (T)0;
+      sid[t] = 0xFFFFFFFFu;
+      sidx[t] = 0xFFFFFFFFu;
     }
-    for (int c = 0; c < 3; ++c) nv[c] = (T)((wa * (double)G(I.v[sp][c])[ia] + wb * (double)G(I.v[sp][c])[ib]) / wt);
-    const T va2 = sv2[2 * t], vb2 = sv2[2 * t + 1];
-    const double e_before = wa * (double)va2 + wb * (double)vb2;
-    G(I.s[sp][0])[keep] = ns[0];
-    G(I.s[sp][1])[keep] = ns[1];
-    for (int c = 0; c < 3; ++c) G(I.v[sp][c])[keep] = nv[c];
-    G(I.w[sp])[keep] = (uint32_t)ws;
-    G(I.w[sp])[gone] = 0u;
-    const T nv2 = (nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2];
-    de += wt * (double)nv2 - e_before;
-    ++pairs;
+    if (threadIdx.x == 0) skipped = 0u;
+    __syncthreads();
+    // bitonic sort on (oct, v2, id)
+    for (uint32_t k = 2; k <= np2; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = threadIdx.x; t < np2; t += blockDim.x) {
+          const uint32_t p = t ^ j;
+          if (p > t) {
+            const bool up = (t & k) == 0;
+            const bool lt = merge_less<T>(soct[p], sv2[p], sid[p], soct[t], sv2[t], sid[t]);
+            if (lt == up) {
+              uint32_t a = soct[t]; soct[t] = soct[p]; soct[p] = a;
+              T b = sv2[t]; sv2[t] = sv2[p]; sv2[p] = b;
+              a = sid[t]; sid[t] = sid[p]; sid[p] = a;
+              a = sidx[t]; sidx[t] = sidx[p]; sidx[p] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // merge pair (2t, 2t+1) in thread t; the survivors' sort keys are kept
+    // in registers until every thread has read its pair
+    const uint32_t np = m / 2u, t = threadIdx.x;
+    bool has = t < np, merged = false;
+    uint32_t o1 = 0u, i1 = 0u, x1 = 0u, o2 = 0u, i2 = 0u, x2 = 0u;
+    T e1 = (T)0, e2 = (T)0;
+    if (has) {
+      const uint32_t ia = sidx[2 * t], ib = sidx[2 * t + 1];
+      o1 = soct[2 * t]; e1 = sv2[2 * t]; i1 = sid[2 * t]; x1 = ia;
+      o2 = soct[2 * t + 1]; e2 = sv2[2 * t + 1]; i2 = sid[2 * t + 1]; x2 = ib;
+      const uint32_t wa_u = G(I.w[sp])[ia], wb_u = G(I.w[sp])[ib];
+      const uint64_t ws = (uint64_t)wa_u + (uint64_t)wb_u;
+      if (ws <= 0xFFFFFFFFull) {
+        const double wa = (double)wa_u, wb = (double)wb_u, wt = (double)ws;
+        const bool a_keeps = i1 < i2;
+        const uint32_t keep = a_keeps ? ia : ib, gone = a_keeps ? ib : ia;
+        T ns[2], nv[3];
+        for (int c = 0; c < 2; ++c) {
+          T x = (T)((wa * (double)G(I.s[sp][c])[ia] + wb * (double)G(I.s[sp][c])[ib]) / wt);
+          if (x < lo[c]) x = lo[c];
+          if (x >= hi[c]) x = prev_toward_zero(hi[c]);
+          ns[c] = x;
+        }
+        for (int c = 0; c < 3; ++c) nv[c] = (T)((wa * (double)G(I.v[sp][c])[ia] + wb * (double)G(I.v[sp][c])[ib]) / wt);
+        const double e_before = wa * (double)e1 + wb * (double)e2;
+        G(I.s[sp][0])[keep] = ns[0];
+        G(I.s[sp][1])[keep] = ns[1];
+        for (int c = 0; c < 3; ++c) G(I.v[sp][c])[keep] = nv[c];
+        G(I.w[sp])[keep] = (uint32_t)ws;
+        G(I.w[sp])[gone] = 0u;
+        const T nv2 = (nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2];
+        de += wt * (double)nv2 - e_before;
+        ++pairs;
+        merged = true;
+        o1 = (nv[0] < (T)0 ? 1u : 0u) | (nv[1] < (T)0 ? 2u : 0u) | (nv[2] < (T)0 ? 4u : 0u);
+        e1 = nv2;
+        i1 = a_keeps ? i1 : i2;
+        x1 = keep;
+      }
+    }
+    // the odd particle left over keeps its place after the pairs
+    const bool odd = (m & 1u) != 0u;
+    uint32_t lo_o = 0u, lo_i = 0u, lo_x = 0u;
+    T lo_e = (T)0;
+    if (odd && t == 0u) {
+      lo_o = soct[m - 1u]; lo_e = sv2[m - 1u]; lo_i = sid[m - 1u]; lo_x = sidx[m - 1u];
+    }
+    __syncthreads();
+    if (has) {
+      soct[t] = o1; sv2[t] = e1; sid[t] = i1; sidx[t] = x1;
+      if (!merged) {
+        const uint32_t q = np + (odd ? 1u : 0u) + atomicAdd(&skipped, 1u);
+        soct[q] = o2; sv2[q] = e2; sid[q] = i2; sidx[q] = x2;
+      }
+    }
+    if (odd && t == 0u) {
+      soct[np] = lo_o; sv2[np] = lo_e; sid[np] = lo_i; sidx[np] = lo_x;
+    }
+    __syncthreads();
+    const uint32_t sk = skipped;
+    const uint32_t m2 = np + (odd ? 1u : 0u) + sk;
+    __syncthreads();   // every thread has read 'skipped' before the next round resets it
+    if (sk == np || m2 <= (uint32_t)n_hi) break;   // nothing merged, or the leaf is within bounds
+    m = m2;
   }
   if (pairs) {
     atomicAdd(energy, de);
@@ -512,8 +559,10 @@ __global__ __launch_bounds__(1024) void k_merge(InstDev<T> I, int sp, const uint
 
 template <class T>
 hipError_t launch_merge(const InstDev<T>& I, int sp, const uint32_t* groups, uint32_t ngroups, const uint32_t* cnt,
-                        const uint32_t* end_off, uint32_t* flags, double* energy, uint32_t* npairs, hipStream_t s) {
-  hipLaunchKernelGGL(k_merge<T>, dim3(ngroups), dim3(1024), 0, s, I, sp, groups, cnt, end_off, flags, energy, npairs);
+                        const uint32_t* end_off, int n_hi, uint32_t* flags, double* energy, uint32_t* npairs,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_merge<T>, dim3(ngroups), dim3(1024), 0, s, I, sp, groups, cnt, end_off, n_hi, flags, energy,
+                     npairs);
   return hipGetLastError();
 }
 hipError_t launch_merge_groups(const uint32_t* cnt, uint32_t nleaves, int sp, int n_hi, uint32_t* groups,
@@ -530,7 +579,7 @@ hipError_t launch_merge_groups(const uint32_t* cnt, uint32_t nleaves, int sp, in
   template hipError_t launch_split_emit<T>(const InstDev<T>&, int, const uint32_t*, int, const uint32_t*,       \
                                            const uint32_t*, uint32_t*, int, hipStream_t);                       \
   template hipError_t launch_merge<T>(const InstDev<T>&, int, const uint32_t*, uint32_t, const uint32_t*,       \
-                                      const uint32_t*, uint32_t*, double*, uint32_t*, hipStream_t);
+                                      const uint32_t*, int, uint32_t*, double*, uint32_t*, hipStream_t);
 PIC_ADAPT_INST(float)
 PIC_ADAPT_INST(double)
 

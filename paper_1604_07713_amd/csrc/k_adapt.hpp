@@ -43,7 +43,7 @@ hipError_t launch_split_commit(Counters* ctr, const uint32_t* nparents, int nspe
 hipError_t launch_merge_groups(const uint32_t* cnt, uint32_t nleaves, int sp, int n_hi, uint32_t* groups,
                                uint32_t* ngroups, hipStream_t s);
 template <class T> hipError_t launch_merge(const InstDev<T>& I, int sp, const uint32_t* groups, uint32_t ngroups,
-                                           const uint32_t* cnt, const uint32_t* end_off, uint32_t* flags,
+                                           const uint32_t* cnt, const uint32_t* end_off, int n_hi, uint32_t* flags,
                                            double* energy, uint32_t* npairs, hipStream_t s);
 
 }  // namespace pic
