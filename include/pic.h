@@ -116,8 +116,9 @@ typedef struct {
   int64_t elastic, ionization, cx, births;
   int64_t numax_violations[2];  /* speed above the null-collision bound (should be 0) */
   int64_t lost_reflect;         /* reflected but still outside: removed        */
-  double loop_ms;               /* summed duration of the particle-loop kernels (timing != 0) */
+  double loop_ms;               /* summed duration of the timed particle-loop launches (timing != 0) */
   double step_ms;               /* wall duration of the call on the stream (timing != 0) */
+  int64_t loop_launches;        /* particle-loop launches timed in loop_ms               */
 } pic_step_stats;
 
 typedef struct {
@@ -138,7 +139,10 @@ typedef struct {
                         /* and replay it (0 = no graph)                            */
   const int* slots;     /* selected slots (NULL = all live slots)                 */
   int nslots;
-  int timing;           /* record HIP events around the particle-loop kernels     */
+  int timing;           /* 0: no events; n > 0: record HIP events around the      */
+                        /* particle-loop kernel of every n-th step of the call      */
+                        /* (per-slot launches; batched launches: every step), and   */
+                        /* around the whole call.  PIC_E_ARG if negative.           */
 } pic_step_args;
 
 typedef struct {

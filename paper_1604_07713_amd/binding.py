@@ -50,13 +50,13 @@ class StepStats(C.Structure):
     _fields_ = [("alive_start", C.c_int64 * 2), ("absorbed", C.c_int64 * 2), ("elastic", C.c_int64),
                 ("ionization", C.c_int64), ("cx", C.c_int64), ("births", C.c_int64),
                 ("numax_violations", C.c_int64 * 2), ("lost_reflect", C.c_int64), ("loop_ms", C.c_double),
-                ("step_ms", C.c_double)]
+                ("step_ms", C.c_double), ("loop_launches", C.c_int64)]
 
     def as_dict(self):
         return dict(alive_start=list(self.alive_start), absorbed=list(self.absorbed), elastic=self.elastic,
                     ionization=self.ionization, cx=self.cx, births=self.births,
                     numax_violations=list(self.numax_violations), lost_reflect=self.lost_reflect,
-                    loop_ms=self.loop_ms, step_ms=self.step_ms)
+                    loop_ms=self.loop_ms, step_ms=self.step_ms, loop_launches=self.loop_launches)
 
 
 class StepArgs(C.Structure):
@@ -238,7 +238,7 @@ class Context:
             sl = np.ascontiguousarray(slots, dtype=np.int32)
             a.slots = sl.ctypes.data
             a.nslots = len(sl)
-        a.timing = int(bool(timing))
+        a.timing = int(timing)   # True = 1: every launch; n: every n-th step
         st = StepStats()
         self._check(lib().pic_step(self.h, C.byref(a), C.byref(st)))
         return st.as_dict()

@@ -181,9 +181,11 @@ void finish_stats(Ctx& C, std::vector<Slot*>& sel, std::vector<Counters>& before
   }
   if (st) {
     const double lm = st->loop_ms, sm = st->step_ms;
+    const int64_t ll = st->loop_launches;
     *st = out;
     st->loop_ms = lm;
     st->step_ms = sm;
+    st->loop_launches = ll;
   }
   if (!err.empty()) throw Err(PIC_E_CAPACITY, err);
 }
@@ -788,7 +790,9 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
   if (stats) {
     stats->loop_ms = 0;
     stats->step_ms = 0;
+    stats->loop_launches = 0;
   }
+  if (a->timing < 0) throw Err(PIC_E_ARG, "timing must be >= 0");
   std::vector<Counters> before(nsel);
   bool any_ionizing = false;
   for (Slot* s : sel) any_ionizing = any_ionizing || s->ionizing;
@@ -799,6 +803,7 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     t1 = get_event(*c, 1);
   }
   double loop_ms = 0;
+  int64_t launches = 0;
   bool started = false;
   for (int64_t kb = 0; kb < a->nsteps; kb += chunk) {
     const int64_t ke = std::min<int64_t>(a->nsteps, kb + chunk);
@@ -824,13 +829,14 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
       if (sel[0]->prec == 32) batched_steps<float>(*c, sel, &sub, 0, sub.nsteps, a->timing ? &lm : nullptr);
       else batched_steps<double>(*c, sel, &sub, 0, sub.nsteps, a->timing ? &lm : nullptr);
       loop_ms += lm;
+      if (a->timing) launches += sub.nsteps;
     } else {
       std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
       for (int64_t k = 0; k < sub.nsteps; ++k) {
         for (int j = 0; j < nsel; ++j) {
           Slot& sl = *sel[j];
           hipEvent_t e0 = nullptr, e1 = nullptr;
-          if (a->timing) {
+          if (a->timing > 0 && (kb + k) % a->timing == 0) {
             e0 = get_event(*c, 2 + 2 * evs.size());
             e1 = get_event(*c, 3 + 2 * evs.size());
             evs.push_back({e0, e1});
@@ -853,6 +859,7 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
           hip_check(hipEventElapsedTime(&ms, p.first, p.second), "elapsed");
           loop_ms += ms;
         }
+        launches += (int64_t)evs.size();
       }
     }
   }
@@ -863,7 +870,10 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     hip_check(hipEventElapsedTime(&ms, t0, t1), "elapsed");
     if (stats) stats->step_ms = ms;
   }
-  if (stats) stats->loop_ms = loop_ms;
+  if (stats) {
+    stats->loop_ms = loop_ms;
+    stats->loop_launches = launches;
+  }
   finish_stats(*c, sel, before, stats);
   return PIC_OK;
   PIC_GUARD_END(c)
