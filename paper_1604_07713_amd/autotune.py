@@ -44,26 +44,35 @@ def save_cache(c):
         pass
 
 
-def tune(make_ctx, descs, v_next, steps=8, tiles=TILES, grids=GRIDS, use_cache=True):
+def tune(make_ctx, descs, v_next, steps=6, tiles=TILES, grids=GRIDS, use_cache=True):
     """make_ctx(): a fresh, loaded and started context of the ensemble.
-    v_next: [steps][nslots] drive table.  Returns dict(tile=, grid=, ms=)."""
+    v_next: [steps][nslots] drive table.  Returns dict(tile=, grid=, ns_per_update=)."""
     key = f"{arch()}/{size_class(descs)}"
     cache = load_cache() if use_cache else {}
     if key in cache:
         return dict(cache[key], cached=True)
     g = make_ctx()
-    results = []
+    cands = [(t, gr) for t in tiles for gr in grids]
+    score = {c: 0.0 for c in cands}
     step0 = 0
-    g.step(step0, 2, v_next[:2], solve_field=True, batched=4096)     # warm up
+    # Warm up.  Every run ends with a sort, so each candidate starts from
+    # particles in cell order; candidates are scored by kernel time per
+    # particle-update, and two passes in opposite orders cancel the drift of
+    # the ensemble (it grows and heats while it is tuned).
+    g.step(step0, 2, v_next[:2], solve_field=True, batched=4096, sort_every=2)
     step0 += 2
-    for t in tiles:
-        for gr in grids:
-            st = g.step(step0, steps, v_next[step0:step0 + steps], solve_field=True, batched=t, grid=gr, timing=True)
+    for order in (cands, cands[::-1]):
+        for t, gr in order:
+            st = g.step(step0, steps, v_next[step0:step0 + steps], solve_field=True, batched=t, grid=gr,
+                        timing=True, sort_every=steps)
             step0 += steps
-            results.append((st["loop_ms"] / steps, t, gr))
+            upd = max(st["alive_start"][0] + st["alive_start"][1], 1)
+            score[(t, gr)] += 0.5 * st["loop_ms"] / upd
     g.close()
-    ms, t, gr = min(results)
-    best = dict(tile=t, grid=gr, ms=ms, table=[dict(tile=x, grid=y, ms=m) for m, x, y in sorted(results)])
+    results = [(m, t, gr) for (t, gr), m in score.items()]
+    ns, t, gr = min(results)
+    best = dict(tile=t, grid=gr, ns_per_update=ns * 1e6,
+                table=[dict(tile=x, grid=y, ns_per_update=m * 1e6) for m, x, y in sorted(results)])
     cache[key] = best
     if use_cache:
         save_cache(cache)
