@@ -60,9 +60,10 @@ void* DevPool::get(size_t cls) {
 
 void DevPool::put(void* p, size_t cls) { pending_.emplace_back(cls, p); }
 
-void DevPool::synced() {
+void DevPool::synced(size_t held) {
+  const size_t limit = std::min(kMaxFree, std::max(kMinFree, held / 4));
   for (auto& e : pending_) {
-    if (free_bytes + e.first > kMaxFree) {
+    if (free_bytes + e.first > limit) {
       (void)hipFree(e.second);
     } else {
       free_.emplace(e.first, e.second);
@@ -70,6 +71,13 @@ void DevPool::synced() {
     }
   }
   pending_.clear();
+  // the limit may have dropped (slots retired): free the largest blocks first
+  while (free_bytes > limit && !free_.empty()) {
+    auto it = std::prev(free_.end());
+    (void)hipFree(it->second);
+    free_bytes -= it->first;
+    free_.erase(it);
+  }
 }
 
 void DevPool::clear() {
@@ -338,7 +346,9 @@ std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel) 
 void Ctx::sync() {
   hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
   arena_off = 0;
-  pool.synced();
+  size_t held = 0;
+  for (const Slot& s : slots) held += s.bytes_held;
+  pool.synced(held);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,7 +656,10 @@ void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
     int64_t need = c.count[sp];
     if (sl.ionizing) need += (int64_t)c.count[0] * std::max<int64_t>(1, std::min<int64_t>(steps_ahead, 4)) / 4 + 1024;
     if (need > sl.cap[sp]) {
-      grow(C, sl, sp, 2 * need + 1024, c.count[sp]);
+      // twice the need, clamped to what 32-bit byte offsets address (the
+      // need itself above that is refused by alloc_particles)
+      const int64_t limit = std::min<int64_t>((int64_t)(((1ull << 32) - 1) / sl.esz), 0x7FFFFFFF);
+      grow(C, sl, sp, std::max(need, std::min(2 * need + 1024, limit)), c.count[sp]);
       changed = true;
     }
   }

@@ -49,7 +49,10 @@ struct PBuf {
 // synchronization, when no queued work can still read or write it.
 struct DevPool {
   static constexpr size_t kMaxBlock = size_t(256) << 20;
-  static constexpr size_t kMaxFree = size_t(4) << 30;   // cached bytes beyond this are freed
+  // cached bytes beyond a quarter of what the context's slots hold (at least
+  // 64 MiB, at most 4 GiB) are freed: many small contexts do not hoard memory
+  static constexpr size_t kMinFree = size_t(64) << 20;
+  static constexpr size_t kMaxFree = size_t(4) << 30;
   std::multimap<size_t, void*> free_;
   std::vector<std::pair<size_t, void*>> pending_;
   size_t free_bytes = 0;
@@ -57,7 +60,7 @@ struct DevPool {
   static bool pooled(size_t cls) { return cls <= kMaxBlock; }
   void* get(size_t cls);   // cls from class_of; throws PIC_E_NOMEM
   void put(void* p, size_t cls);
-  void synced();
+  void synced(size_t held);   // held: bytes the context's slots hold
   void clear();
 };
 

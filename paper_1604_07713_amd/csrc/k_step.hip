@@ -9,6 +9,8 @@
 // global memory once per workgroup.  The deposit is integer (64-bit fixed
 // point), hence exact and independent of the order in which lanes and
 // workgroups add.
+#include <atomic>
+
 #include "device_util.hpp"
 #include "pic_internal.hpp"
 
@@ -1295,11 +1297,13 @@ hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, i
   return hipGetLastError();
 }
 // Workgroups of the step kernel variant that fit on the device at once
-// (occupancy per compute unit x compute units), cached per variant.
+// (occupancy per compute unit x compute units), cached per variant (contexts
+// driven from several threads may fill the cache at once: same value).
 template <class T>
 int step_resident_grid(int dim, bool mcc, bool direct) {
-  static int cache[2][2][2] = {};
-  int& c = cache[dim == 2 ? 1 : 0][mcc ? 1 : 0][direct ? 1 : 0];
+  static std::atomic<int> cache[2][2][2] = {};
+  std::atomic<int>& slot = cache[dim == 2 ? 1 : 0][mcc ? 1 : 0][direct ? 1 : 0];
+  int c = slot.load(std::memory_order_relaxed);
   if (c == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     const void* fn;
@@ -1311,6 +1315,7 @@ int step_resident_grid(int dim, bool mcc, bool direct) {
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess)
       return 2048;
     c = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    slot.store(c, std::memory_order_relaxed);
   }
   return c;
 }

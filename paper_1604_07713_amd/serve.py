@@ -1,25 +1,36 @@
 """Serving loop: continuous batching of ES-PIC jobs on one GPU.
 
 Jobs (1D capacitively coupled discharges and 2D avalanches of different
-sizes) arrive over time.  Each admitted job owns a slot of one library
-context; its particle and mesh state stay resident on the GPU until it
-finishes.  Admission is by projected device memory: ionization makes
-particle counts grow, so a job is admitted when the sum of the projected
-footprints of the resident jobs and the new one fits the budget.  Every tick
-all resident 1D jobs advance together in one persistent batched launch per
-step (each at its own step index), and the resident 2D jobs advance with
-periodic adaptation and field solves.  Jobs that arrive while others run are
-admitted as soon as memory and slots allow, so their work joins the device
-stream of the running ones.
+sizes) arrive over time.  Each admitted job owns a library slot; its
+particle and mesh state stay resident on the GPU until it finishes.  The 1D
+jobs share one context; each 2D job has a context of its own on one of a few
+HIP streams, and worker threads drive the 2D jobs of a tick concurrently, so
+their small, latency-bound adaptation and CG launches overlap on the GPU.
+
+Admission is by projected device memory.  Ionization makes an avalanche's
+population grow exponentially, so its footprint is projected to its peak:
+the population now times exp(lambda x the steps it has left), with lambda
+the largest of a prior and the mean growth of the avalanches finished so far.  A job
+is admitted when the projected peaks of the resident jobs and the new one fit
+the budget.  Every tick all resident 1D jobs advance together in one
+persistent batched launch per step (each at its own step index), and the
+resident 2D jobs advance with periodic adaptation and field solves.  Jobs
+that arrive while others run are admitted as soon as memory and slots allow,
+so their work joins the device work of the running ones.  A job that still
+runs out of device memory (or outgrows the library's per-array limit) fails
+and is reported; the others continue.
 
 CLI: python -m paper_1604_07713_amd.serve --duration 60 --rate 20
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
+import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -27,6 +38,9 @@ from . import binding as B
 from . import inputs as I
 
 GIB = 1 << 30
+# Growth of an avalanche per step (log) assumed before any is observed: about
+# a factor 3000 over 2000 steps, above what the 30 kV/cm workload shows.
+LAMBDA_PRIOR = 0.004
 
 
 class Job:
@@ -37,6 +51,8 @@ class Job:
         self.arrival = spec["arrival"]
         self.steps_total = int(spec["steps"])
         self.key = spec["key"]
+        self.ctx = None    # the library context holding the job's slot
+        self.own_ctx = False
         self.slot = None
         self.steps_done = 0
         self.t_submit = None
@@ -44,6 +60,8 @@ class Job:
         self.t_done = None
         self.updates = 0
         self.result = None
+        self.failed = False
+        self.n_now = 0     # live particles after the last tick
         if self.kind == "ccp":
             self.desc = I.ccp_desc(ncells=spec["ncells"], ppc=spec["ppc"], voltage=spec["voltage"],
                                    pressure_mtorr=spec["pressure"], precision=precision, seed=5,
@@ -52,29 +70,52 @@ class Job:
         else:
             self.desc = I.streamer_desc(side=spec["side"], precision=precision, seed=5, instance_key=spec["key"])
             self.nparticles = 2 * spec["npairs"]
+        self.n_now = self.nparticles
 
-    def projected_bytes(self, growth_ccp=3.0, growth_streamer=32.0):
-        """Device footprint if the population grows by the given factor:
-        particle slots (two buffers of s, v, w, id, cell in the particle
-        precision) with the library's births/sort headroom, births staging,
-        and the mesh."""
+    def growth_rate(self):
+        """Mean growth of the population per step (log) over the steps done,
+        or None before 50 steps."""
+        if self.steps_done < 50 or self.n_now <= 0:
+            return None
+        return math.log(self.n_now / self.nparticles) / self.steps_done
+
+    def projected_bytes(self, lam_streamer=0.004, growth_ccp=3.0):
+        """Device footprint at the job's projected peak population: particle
+        slots (two buffers of s, v, w, id, cell in the particle precision,
+        capacity up to twice the population) with births staging, and the
+        mesh.  An avalanche grows exponentially: its population now, times
+        exp(lam_streamer x the steps it has left); a discharge by at most
+        growth_ccp over its start."""
         e = self.precision // 8
         if self.kind == "ccp":
             per_slot = 2 * (4 * e + 12) + 11 * e
-            slots = 2.0 * growth_ccp * self.nparticles + 8192
+            peak = max(growth_ccp * self.nparticles, self.n_now)
+            slots = 2.0 * peak + 8192
             mesh = 8 * 40 * (self.spec["ncells"] + 1)
         else:
             per_slot = 2 * (5 * e + 12) + 12 * e
-            slots = 2.0 * growth_streamer * self.nparticles + 8192
-            leaves = max(1024.0, growth_streamer * self.nparticles / 16.0)
+            left = self.steps_total - self.steps_done
+            peak = max(self.n_now, 1) * math.exp(max(lam_streamer, 0.0) * left)
+            slots = 2.0 * peak + 8192
+            leaves = max(1024.0, peak / 16.0)
             mesh = leaves * 400 + 4 * (1 << 18)
         return int(per_slot * slots + mesh)
 
 
 class Server:
     def __init__(self, budget_bytes=None, tick_steps=25, field_every=10, adapt_every=10, max_slots=512,
-                 keep_results=False, stream=None, batched=True):
+                 keep_results=False, stream=None, batched=True, workers=4):
         self.ctx = B.Context([], stream=stream)
+        # 2D jobs: own contexts on `workers` streams (default priority), driven by
+        # as many threads; workers = 0 keeps them in the shared context
+        self.workers = workers
+        self.streams = []
+        self.pool = None
+        if workers > 0:
+            import torch
+            self.streams = [torch.cuda.Stream() for _ in range(workers)]
+            self.pool = ThreadPoolExecutor(max_workers=workers)
+        self.n_started = 0
         if budget_bytes is None:
             import torch
             free, total = torch.cuda.mem_get_info()
@@ -87,9 +128,9 @@ class Server:
         self.keep_results = keep_results
         self.batched = batched   # False: every job steps with its own launches (the plain method)
         self.pending = []
-        self.running = {}
+        self.running = []
         self.done = []
-        self.committed = 0
+        self.lam = LAMBDA_PRIOR   # growth per step assumed for avalanches (log), raised by observation
         self.t0 = time.perf_counter()
 
     # ---- admission ----
@@ -98,7 +139,15 @@ class Server:
         self.pending.append(job)
 
     def _start(self, job):
-        g = self.ctx
+        if job.kind == "streamer" and self.workers > 0:
+            job.stream_index = self.n_started % self.workers
+            st = self.streams[job.stream_index]
+            job.ctx = B.Context([], stream=ctypes.c_void_p(st.cuda_stream))
+            job.own_ctx = True
+        else:
+            job.ctx = self.ctx
+        self.n_started += 1
+        g = job.ctx
         slot = g.admit(job.desc)
         job.slot = slot
         job.t_admit = time.perf_counter()
@@ -119,12 +168,12 @@ class Server:
         # the library's own step counter starts at 0 for a new slot
 
     def _solve2d(self, job):
-        phi, it, rr, rc = self.ctx.field_solve_2d(job.slot, rtol=1e-8, maxit=4000)
+        phi, it, rr, rc = job.ctx.field_solve_2d(job.slot, rtol=1e-8, maxit=4000)
         return it
 
     # ---- stepping ----
     def _step_ccp(self):
-        jobs = [j for j in self.running.values() if j.kind == "ccp"]
+        jobs = [j for j in self.running if j.kind == "ccp"]
         if not jobs:
             return 0
         K = self.tick_steps
@@ -151,44 +200,76 @@ class Server:
                 j.updates += u / len(group)
         return upd
 
-    def _step_streamers(self):
+    def _tick_streamer(self, j):
+        """One tick of a 2D job: steps with adaptation and a field solve every
+        few steps.  Touches only the job's own context.  A job that runs out
+        of device memory fails and is retired."""
         upd = 0
-        for j in [j for j in self.running.values() if j.kind == "streamer"]:
-            n = min(self.tick_steps, j.steps_total - j.steps_done)
+        n = min(self.tick_steps, j.steps_total - j.steps_done)
+        try:
             while n > 0:
                 chunk = min(n, self.field_every - (j.steps_done % self.field_every))
-                st = self.ctx.step(-1, chunk, slots=[j.slot], sort_every=0)
+                st = j.ctx.step(-1, chunk, slots=[j.slot], sort_every=0)
                 u = st["alive_start"][0] + st["alive_start"][1]
                 upd += u
                 j.updates += u
                 j.steps_done += chunk
                 n -= chunk
                 if j.steps_done % self.adapt_every == 0 and j.steps_done < j.steps_total:
-                    self.ctx.adapt(j.slot)
+                    j.ctx.adapt(j.slot)
                 if j.steps_done % self.field_every == 0 and j.steps_done < j.steps_total:
                     self._solve2d(j)
+            j.n_now = j.ctx.count(j.slot, 0) + j.ctx.count(j.slot, 1)
+        except B.PicError as e:
+            # out of device memory, or past the library's per-array limit
+            if e.code not in (B.PIC_E_NOMEM, B.PIC_E_CAPACITY):
+                raise
+            j.failed = True
+            j.steps_done = j.steps_total
         return upd
+
+    def _step_streamers(self):
+        jobs = [j for j in self.running if j.kind == "streamer"]
+        if self.pool is None:
+            return sum(self._tick_streamer(j) for j in jobs)
+        # jobs on one stream run in one worker, in order; the streams run concurrently
+        lanes = [[j for j in jobs if j.ctx is not None and j.stream_index == w] for w in range(self.workers)]
+
+        def run(lane):
+            return sum(self._tick_streamer(j) for j in lane)
+        return sum(self.pool.map(run, [ln for ln in lanes if ln]))
 
     def _retire(self):
         now = time.perf_counter()
-        for slot, j in list(self.running.items()):
+        for j in list(self.running):
             if j.steps_done >= j.steps_total:
-                if self.keep_results:
-                    j.result = [self.ctx.read(slot, sp) for sp in range(2)]
-                j.final_counts = [self.ctx.count(slot, sp) for sp in range(2)]
-                self.ctx.retire(slot)
-                self.committed -= j.projected
+                g = j.ctx
+                if not j.failed:
+                    if self.keep_results:
+                        j.result = [g.read(j.slot, sp) for sp in range(2)]
+                    j.final_counts = [g.count(j.slot, sp) for sp in range(2)]
+                if j.kind == "streamer" and not j.failed:
+                    r = j.growth_rate()
+                    if r is not None:
+                        self.lam = max(self.lam, r)
+                if j.own_ctx:
+                    g.close()
+                else:
+                    g.retire(j.slot)
+                j.ctx = None
                 j.t_done = now
                 self.done.append(j)
-                del self.running[slot]
+                self.running.remove(j)
 
-    def run(self, jobs, max_wall=None, clock="wall"):
+    def run(self, jobs, max_wall=None, clock="wall", progress_every=None):
         """Serve jobs until all are done (or max_wall seconds).  clock='wall':
         a job is submitted when the wall clock passes its arrival time;
         clock='tick': when the tick counter does (deterministic tests).
-        Returns TTR percentiles and the aggregate particle-update rate."""
+        Returns TTR percentiles and the aggregate particle-update rate.
+        progress_every: seconds between status lines on stderr (None: none)."""
         jobs = sorted(jobs, key=lambda j: j.arrival)
         t_start = time.perf_counter()
+        t_print = t_start
         i = 0
         total_upd = 0
         ticks = 0
@@ -201,6 +282,11 @@ class Server:
             total_upd += self._step_ccp() + self._step_streamers()
             self._retire()
             ticks += 1
+            if progress_every and time.perf_counter() - t_print >= progress_every:
+                t_print = time.perf_counter()
+                print(json.dumps(dict(t_s=round(t_print - t_start, 1), submitted=i, done=len(self.done),
+                                      running=len(self.running), pending=len(self.pending),
+                                      updates=int(total_upd))), file=sys.stderr, flush=True)
             if i >= len(jobs) and not self.pending and not self.running:
                 break
             if max_wall is not None and time.perf_counter() - t_start > max_wall:
@@ -208,8 +294,10 @@ class Server:
             if not self.running and not self.pending and i < len(jobs) and clock == "wall":
                 time.sleep(max(0.0, min(0.01, jobs[i].arrival - (time.perf_counter() - t_start))))
         wall = time.perf_counter() - t_start
-        ttr = np.array([j.t_done - j.t_submit for j in self.done]) if self.done else np.zeros(0)
-        return dict(jobs_done=len(self.done), jobs_submitted=i, jobs_pending=len(self.pending),
+        ok = [j for j in self.done if not j.failed]
+        ttr = np.array([j.t_done - j.t_submit for j in ok]) if ok else np.zeros(0)
+        return dict(jobs_done=len(ok), jobs_failed=len(self.done) - len(ok), jobs_submitted=i,
+                    jobs_pending=len(self.pending),
                     jobs_running=len(self.running), wall_s=wall, ticks=ticks,
                     updates=total_upd, updates_per_s=total_upd / wall if wall > 0 else 0.0,
                     ttr_p50_s=float(np.percentile(ttr, 50)) if len(ttr) else None,
@@ -217,19 +305,28 @@ class Server:
                     budget_gib=self.budget / GIB)
 
     def _admit(self):
-        """Admit pending jobs in arrival order while the projected footprint fits."""
+        """Admit pending jobs in arrival order while the projected peak
+        footprints of the running jobs and the new one fit the budget.  The
+        avalanche growth rate is the largest of the prior and the mean rates
+        of finished avalanches (a running one's early rate overstates its
+        whole run: the avalanche's own space charge slows it later)."""
+        committed = sum(j.projected_bytes(self.lam) for j in self.running)
         while self.pending and len(self.running) < self.max_slots:
             job = self.pending[0]
-            need = job.projected_bytes()
-            if self.committed + need > self.budget and self.running:
+            need = job.projected_bytes(self.lam)
+            if committed + need > self.budget and self.running:
                 break
             self.pending.pop(0)
             self._start(job)
-            job.projected = need
-            self.committed += need
-            self.running[job.slot] = job
+            committed += need
+            self.running.append(job)
 
     def close(self):
+        for j in self.running:
+            if j.own_ctx and j.ctx is not None:
+                j.ctx.close()
+        if self.pool is not None:
+            self.pool.shutdown()
         self.ctx.close()
 
 
@@ -254,19 +351,21 @@ def main():
     ap.add_argument("--max-wall", type=float, default=None, help="stop serving after this many seconds")
     ap.add_argument("--steps-scale", type=float, default=1.0, help="scale every job's step count")
     ap.add_argument("--tick-steps", type=int, default=25)
+    ap.add_argument("--workers", type=int, default=4, help="streams / threads driving the 2D jobs (0: none)")
     ap.add_argument("--plain", action="store_true",
                     help="the plain method: FP64 particles, every job stepped with its own launches")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     jobs = make_jobs(args.rate, args.duration, scale=args.steps_scale, precision=64 if args.plain else 32)
-    srv = Server(tick_steps=args.tick_steps, batched=not args.plain)
-    m = srv.run(jobs, max_wall=args.max_wall)
+    srv = Server(tick_steps=args.tick_steps, batched=not args.plain, workers=args.workers)
+    m = srv.run(jobs, max_wall=args.max_wall, progress_every=10.0)
     offered = sum(j.nparticles * j.steps_total for j in jobs) / max(args.duration, 1e-9)
     m["offered_updates_per_s_lower_bound"] = offered
     m["ccp_jobs"] = sum(1 for j in jobs if j.kind == "ccp")
     m["streamer_jobs"] = sum(1 for j in jobs if j.kind == "streamer")
     m["method"] = "plain FP64, per-job launches" if args.plain else "batched FP32, one launch for all 1D jobs"
+    m["workers_2d"] = args.workers
     print(json.dumps(m), flush=True)
     srv.close()
 
