@@ -187,6 +187,14 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats);
  * units: w_units * 2^F (F = 24 FP32, 32 FP64); 2D: w_units. */
 int pic_deposit(pic_ctx c, int slot, uint64_t* q_out);
 
+/* How a slot ranks the staged births of a step by parent id (Sec. 4.3
+ * births; the ranks fix the newborn ids): 0 (default) pairwise while recent
+ * steps had up to 16384 births each, binned above; 1 always pairwise
+ * (work ~ births^2); 2 always binned (parent ids grouped in 4096 id bins,
+ * work ~ births x births per bin).  Both give the same ranks.  PIC_E_ARG for
+ * another method. */
+int pic_set_births_ranking(pic_ctx c, int slot, int method);
+
 /* Copy the latest per-species integer charge sums to q_out[2][nq] without
  * depositing again: after pic_step, the sums the last step's particle loop
  * accumulated (its survivors and births); after pic_deposit or pic_adapt,

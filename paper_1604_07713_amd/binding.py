@@ -91,6 +91,7 @@ EXPORTS = {
     "pic_step": (C.c_int, [C.c_void_p, C.POINTER(StepArgs), C.POINTER(StepStats)]),
     "pic_deposit": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "pic_deposit_read": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "pic_set_births_ranking": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "pic_field_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                                   C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "pic_adapt": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(AdaptArgs), C.POINTER(AdaptStats)]),
@@ -248,6 +249,10 @@ class Context:
         q = np.zeros((2, n), dtype=np.uint64)
         self._check(lib().pic_deposit(self.h, slot, _p(q)))
         return q
+
+    def set_births_ranking(self, slot, method):
+        """0: by the births of recent steps, 1: pairwise, 2: binned."""
+        self._check(lib().pic_set_births_ranking(self.h, slot, int(method)))
 
     def deposit_read(self, slot=0):
         n = self.nq(slot)

@@ -109,6 +109,8 @@ bool slot_has_mcc(const Slot& sl) {
   return false;
 }
 
+constexpr double kBinnedBirthsPerStep = 16384.0;
+
 template <class T>
 void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e1) {
   InstDev<T> I = make_dev<T>(sl);
@@ -116,7 +118,11 @@ void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e
   const int commit = (!sl.ionizing && !field) ? 1 : 0;
   if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
   hip_check(launch_step<T>(I, C.stream, g, slot_has_mcc(sl), commit), "step");
-  if (sl.ionizing) hip_check(launch_births<T>(I, C.stream, 256), "births");
+  if (sl.ionizing) {
+    // binned ranking once births per step are many (pairwise work grows as their square)
+    const bool binned = sl.births_method == 2 || (sl.births_method == 0 && sl.births_rate > kBinnedBirthsPerStep);
+    hip_check(launch_births<T>(I, C.stream, binned), "births");
+  }
   if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
   if (field)
     hip_check(launch_field1d<T>((const InstDev<T>*)sl.devI, 1, sl.d.ncells, 1, nullptr, C.stream), "field1d");
@@ -134,6 +140,13 @@ void reduce_plain_stats(Ctx& C, Slot& sl, int g) {
 void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead, Counters cn) {
   if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
+  if (sl.ionizing) {   // births per step since the previous chunk picks the ranking method
+    const uint64_t b = cn.stats[kStBirths];
+    if (cn.step > sl.rate_step_mark && b >= sl.rate_births_mark)
+      sl.births_rate = (double)(b - sl.rate_births_mark) / (double)(cn.step - sl.rate_step_mark);
+    sl.rate_births_mark = b;
+    sl.rate_step_mark = cn.step;
+  }
   if (a->step0 >= 0) cn.step = (uint32_t)a->step0;   // else: continue from the slot's own step index
   cn.vstep0 = cn.step + 1u;
   if (sl.d.dim == 1 && a->solve_field) {
@@ -690,6 +703,14 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out) {
     const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
     hip_check(hipMemcpy(q_out, latest, 8 * 2 * (size_t)sl.nq, hipMemcpyDeviceToHost), "read");
   }
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_set_births_ranking(pic_ctx c, int slot, int method) {
+  PIC_GUARD_BEGIN
+  if (method < 0 || method > 2) throw Err(PIC_E_ARG, "births ranking method must be 0, 1 or 2");
+  get_slot(c, slot).births_method = method;
   return PIC_OK;
   PIC_GUARD_END(c)
 }

@@ -514,7 +514,7 @@ void alloc_births(Ctx& C, Slot& sl, int64_t cap) {
   sl.birth_cap = 0;
   if (!sl.ionizing) return;
   const size_t e = sl.esz, c = (size_t)cap;
-  char* p = (char*)sl.alloc((16 + 8 * e) * c + 16 * 256);
+  char* p = (char*)sl.alloc((20 + 8 * e) * c + 4 * (3 * kBirthBins + 1) + 20 * 256);
   sl.birth_base = p;
   size_t o = 0;
   auto carve = [&](size_t n) {
@@ -530,6 +530,11 @@ void alloc_births(Ctx& C, Slot& sl, int64_t cap) {
   for (int k = 0; k < 2; ++k) sl.br_s[k] = carve(e * c);
   for (int k = 0; k < 3; ++k) sl.br_ve[k] = carve(e * c);
   for (int k = 0; k < 3; ++k) sl.br_vi[k] = carve(e * c);
+  sl.br_sorted = (uint32_t*)carve(4 * c);
+  sl.br_bin = (uint32_t*)carve(4 * kBirthBins);
+  hip_check(hipMemsetAsync(sl.br_bin, 0, 4 * kBirthBins, C.stream), "memset");   // kept zero as br_rank
+  sl.br_bin_off = (uint32_t*)carve(4 * (kBirthBins + 1));
+  sl.br_cursor = (uint32_t*)carve(4 * kBirthBins);
   sl.birth_cap = (uint32_t)cap;
 }
 
@@ -567,6 +572,10 @@ InstDev<T> make_dev(const Slot& sl) {
   I.nq = sl.nq;
   I.br.parent = sl.br_parent;
   I.br.rank = sl.br_rank;
+  I.br.bin = sl.br_bin;
+  I.br.bin_off = sl.br_bin_off;
+  I.br.cursor = sl.br_cursor;
+  I.br.sorted = sl.br_sorted;
   I.br.cell = sl.br_cell;
   I.br.w = sl.br_w;
   for (int k = 0; k < 2; ++k) I.br.s[k] = (T*)sl.br_s[k];

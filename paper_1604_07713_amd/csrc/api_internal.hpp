@@ -82,6 +82,12 @@ struct Slot {
   void* birth_base = nullptr;
   uint32_t* scan_tmp = nullptr;   // 2D: scratch of the sort's multi-block scan (after off)
   uint32_t *br_parent = nullptr, *br_rank = nullptr, *br_cell = nullptr, *br_w = nullptr;
+  uint32_t *br_bin = nullptr, *br_bin_off = nullptr, *br_cursor = nullptr, *br_sorted = nullptr;
+  // births ranking: 0 by the births of recent steps, 1 pairwise, 2 binned
+  int births_method = 0;
+  double births_rate = 0.0;           // births per step over the previous chunk of steps
+  uint64_t rate_births_mark = 0;
+  uint32_t rate_step_mark = 0;
   void* br_s[2] = {nullptr, nullptr};
   void* br_ve[3] = {nullptr, nullptr, nullptr};
   void* br_vi[3] = {nullptr, nullptr, nullptr};

@@ -320,7 +320,9 @@ __device__ __forceinline__ HotK<T> hot_constants(const InstDev<T>& I, int sp) {
 //   2. stage A of batch t+1: weight, leaf (2D) or position (1D), id;
 //   3. push and wall rule of batch t;
 //   4. point location of the particles that left their leaf (lookup table);
-//   5. collision candidate test; velocity components of the candidates;
+//   5. collision candidate test; the velocity components the push does not
+//      use, for the candidates (1D; the 2D collision loop takes v_z with
+//      stage B);
 //   6. stage B of batch t+1: the rest of the particle state;
 //   7. collisions, births, stores and deposit of batch t.
 // Stage B of batch t+1 thus overlaps the locate and collision round trips of
@@ -1130,6 +1132,95 @@ __device__ void birth_write_body(const InstDev<T>& I, uint32_t first, uint32_t n
   }
 }
 
+// Binned ranking.  Parent ids below next_id fall into kBirthBins bins of
+// 2^shift consecutive ids; a birth's rank is the number of staged parents in
+// lower bins (the bin offset) plus those in its own bin with a smaller id, so
+// each birth compares only with the members of its bin.
+__device__ __forceinline__ uint32_t birth_bin_shift(uint32_t next_id) {
+  const uint32_t top = next_id > 0u ? next_id - 1u : 0u;
+  uint32_t sh = 0u;
+  while (sh < 31u && (top >> sh) >= kBirthBins) ++sh;
+  return sh;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_bin(InstDev<T> I) {
+  __shared__ uint32_t hist[kBirthBins];
+  const uint32_t nb = I.ctr->nbirths;
+  bool cap_ok, id_ok;
+  if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
+  const uint32_t sh = birth_bin_shift(I.ctr->next_id);
+  for (uint32_t b = threadIdx.x; b < kBirthBins; b += kBlock) hist[b] = 0u;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock)
+    atomicAdd(&hist[I.br.parent[i] >> sh], 1u);
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < kBirthBins; b += kBlock)
+    if (hist[b]) gadd32(I.br.bin + b, hist[b]);
+}
+
+// one workgroup of 1024 threads: offsets and cursors of the bins; clears the counts
+template <class T>
+__global__ __launch_bounds__(1024) void k_birth_binscan(InstDev<T> I) {
+  __shared__ uint32_t part[1024];
+  const uint32_t nb = I.ctr->nbirths;
+  bool cap_ok, id_ok;
+  if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
+  constexpr uint32_t per = kBirthBins / 1024u;
+  uint32_t c[per], sum = 0u;
+#pragma unroll
+  for (uint32_t q = 0; q < per; ++q) {
+    c[q] = I.br.bin[threadIdx.x * per + q];
+    sum += c[q];
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024u; d <<= 1) {   // inclusive scan of the thread sums
+    const uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+#pragma unroll
+  for (uint32_t q = 0; q < per; ++q) {
+    const uint32_t b = threadIdx.x * per + q;
+    I.br.bin_off[b] = run;
+    I.br.cursor[b] = run;
+    I.br.bin[b] = 0u;
+    run += c[q];
+  }
+  if (threadIdx.x == 1023u) I.br.bin_off[kBirthBins] = run;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_scatter(InstDev<T> I) {
+  const uint32_t nb = I.ctr->nbirths;
+  bool cap_ok, id_ok;
+  if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
+  const uint32_t sh = birth_bin_shift(I.ctr->next_id);
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) {
+    const uint32_t pid = I.br.parent[i];
+    I.br.sorted[gadd32(I.br.cursor + (pid >> sh), 1u)] = pid;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_rank_binned(InstDev<T> I) {
+  const uint32_t nb = I.ctr->nbirths;
+  bool cap_ok, id_ok;
+  if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
+  const uint32_t sh = birth_bin_shift(I.ctr->next_id);
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) {
+    const uint32_t pid = I.br.parent[i];
+    const uint32_t b = pid >> sh;
+    const uint32_t lo = I.br.bin_off[b], hi = I.br.bin_off[b + 1u];
+    uint32_t r = lo;
+    for (uint32_t j = lo; j < hi; ++j) r += I.br.sorted[j] < pid ? 1u : 0u;
+    I.br.rank[i] = r;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_birth_rank(InstDev<T> I) { birth_rank_body<T>(I, blockIdx.x, gridDim.x); }
 template <class T>
@@ -1328,9 +1419,15 @@ hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uin
   return hipGetLastError();
 }
 template <class T>
-hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid) {
-  (void)grid;
-  hipLaunchKernelGGL(k_birth_rank<T>, dim3(kRankBlocksPlain), dim3(kBlock), 0, s, I);
+hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned) {
+  if (binned) {
+    hipLaunchKernelGGL(k_birth_bin<T>, dim3(256), dim3(kBlock), 0, s, I);
+    hipLaunchKernelGGL(k_birth_binscan<T>, dim3(1), dim3(1024), 0, s, I);
+    hipLaunchKernelGGL(k_birth_scatter<T>, dim3(512), dim3(kBlock), 0, s, I);
+    hipLaunchKernelGGL(k_birth_rank_binned<T>, dim3(1024), dim3(kBlock), 0, s, I);
+  } else {
+    hipLaunchKernelGGL(k_birth_rank<T>, dim3(kRankBlocksPlain), dim3(kBlock), 0, s, I);
+  }
   hipLaunchKernelGGL(k_birth_write<T>, dim3(kWriteBlocks), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
@@ -1377,7 +1474,7 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
   template int step_resident_grid<T>(int, bool, bool);                      \
   template hipError_t launch_step1d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
                                                unsigned long long*, hipStream_t, int, bool);               \
-  template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, int);                               \
+  template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, bool);                              \
   template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
   template hipError_t launch_commit<T>(const InstDev<T>&, hipStream_t);                                    \
   template hipError_t launch_commit_batched<T>(const InstDev<T>*, int, hipStream_t);                       \

@@ -43,6 +43,10 @@ template <class T>
 struct Births {          // staging of one step's ionization births (SoA)
   uint32_t* parent;
   uint32_t* rank;        // rank of the parent id among the staged ones (kept zero between steps)
+  uint32_t* bin;         // [kBirthBins] staged parents per id bin (kept zero between steps)
+  uint32_t* bin_off;     // [kBirthBins + 1] first position of each bin in 'sorted'
+  uint32_t* cursor;      // [kBirthBins] fill positions
+  uint32_t* sorted;      // staged parent ids grouped by bin
   uint32_t* cell;
   uint32_t* w;
   T* s[2];
@@ -100,7 +104,11 @@ template <class T> hipError_t launch_step(const InstDev<T>& I, hipStream_t s, in
 template <class T> int step_resident_grid(int dim, bool mcc, bool direct);
 template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
                                                     unsigned long long* bpart, hipStream_t s, int grid, bool mcc);
-template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, int grid);
+// Births of one step: rank the staged births by parent id, append the pairs.
+// binned: rank through id bins (work ~ births x births per bin) instead of
+// comparing every pair (work ~ births^2); the host picks it for many births.
+constexpr uint32_t kBirthBins = 4096;
+template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned);
 template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s);
 template <class T> hipError_t launch_commit(const InstDev<T>& I, hipStream_t s);
 template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, int ninst, hipStream_t s);

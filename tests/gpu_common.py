@@ -36,9 +36,10 @@ def assert_same_particles(a, b, tol, what=""):
             assert err.max() <= tol, f"{what}: {k} max rel error {err.max()}"
 
 
-def ccp_run_both(desc, nsteps, sort_every=20, gpu_kwargs=None):
+def ccp_run_both(desc, nsteps, sort_every=20, gpu_kwargs=None, births_ranking=0):
     parts = I.ccp_particles(desc)
     o, g = load_both(desc, parts)
+    g.set_births_ranking(0, births_ranking)
     o.deposit()
     g.deposit(0)
     v0 = float(I.drive_voltage(desc, 0))

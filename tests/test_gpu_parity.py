@@ -121,6 +121,18 @@ def test_ccp_400_steps_free_running(precision):
     assert np.array_equal(o.field_table(), g.field_table(0))
 
 
+def test_ccp_binned_births_ranking():
+    """The CCP discharge for 200 steps with the births ranked through id bins
+    on the GPU: the same newborn ids, hence the same particles, as the
+    oracle's ranking by parent id."""
+    d = I.ccp_desc(precision=32)
+    o, g, so, sg = ccp_run_both(d, 200, sort_every=20, births_ranking=2)
+    assert so["births"] > 0 and so["births"] == sg["births"]
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), TOL[32], f"species {sp}")
+    assert o.next_id == g.next_id(0)
+
+
 def test_quadtree_static_steps_bitwise():
     """2D static quadtree (levels 6-9), FP32 particles, reflecting walls, 100 steps."""
     d = I.quadtree_static_desc()
