@@ -40,6 +40,7 @@
  */
 #ifndef PIC_H
 #define PIC_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -155,6 +156,23 @@ typedef struct {
   int64_t nleaves;
   double merge_energy_change;   /* sum over merges of w (|v'|^2) - (w1|v1|^2 + w2|v2|^2) */
 } pic_adapt_stats;
+
+/* Device memory from the caller (e.g. a framework's caching allocator):
+ * alloc(bytes, stream, user) returns device memory usable in stream order on
+ * 'stream' (the context's stream) or NULL; free(p, user) gives a block back.
+ * The library hands a block back only after its stream has finished every
+ * queued use of it. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* p, void* user);
+  void* user;
+} pic_allocator;
+
+/* Route the particle, mesh, field and adaptation-scratch memory of a context
+ * through 'a' (NULL: hipMalloc with the library's own block cache).  Only on
+ * a context that holds no instance yet (build with ninst = 0, then
+ * pic_admit): else PIC_E_STATE.  The allocator must outlive the context. */
+int pic_set_allocator(pic_ctx c, const pic_allocator* a);
 
 /* Build a context holding ninst >= 0 instances (slots 0..ninst-1; more can be
  * admitted later with pic_admit): uniform 1D mesh,

@@ -113,7 +113,37 @@ EXPORTS = {
     "pic_admit": (C.c_int, [C.c_void_p, C.POINTER(InstanceDesc), C.POINTER(C.c_int)]),
     "pic_retire": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_slot_bytes": (C.c_int64, [C.c_void_p, C.c_int]),
+    "pic_set_allocator": (C.c_int, [C.c_void_p, C.c_void_p]),
 }
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory of a context from torch's caching allocator, in stream
+    order on the context's stream (pic_set_allocator)."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device is None else device
+
+        def _alloc(nbytes, stream, user):
+            try:
+                return self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+            except Exception:
+                return None
+
+        def _free(p, user):
+            self._torch.cuda.caching_allocator_delete(p)
+        self._alloc = ALLOC_FN(_alloc)   # kept alive with this object
+        self._free = FREE_FN(_free)
+        self.struct = Allocator(self._alloc, self._free, None)
 
 
 def lib():
@@ -176,18 +206,26 @@ def default_stream():
 class Context:
     """A library context owning one or more instance slots on the GPU."""
 
-    def __init__(self, descs, stream=None):
+    def __init__(self, descs, stream=None, allocator=None):
+        """allocator: None (hipMalloc and the library's block cache), or e.g.
+        TorchAllocator() (device memory from torch's caching allocator)."""
         if isinstance(descs, dict):
             descs = [descs]
         self.descs = list(descs)
-        arr = (InstanceDesc * len(descs))(*[make_desc(d) for d in descs])
+        self._allocator = allocator
+        first = [] if allocator is not None else self.descs
+        arr = (InstanceDesc * max(len(first), 1))(*[make_desc(d) for d in first])
         h = C.c_void_p()
         L = lib()
-        rc = L.pic_mesh_build(arr, len(descs), stream if stream is not None else default_stream(), C.byref(h))
+        rc = L.pic_mesh_build(arr, len(first), stream if stream is not None else default_stream(), C.byref(h))
         if rc != PIC_OK:
             raise PicError(rc, L.pic_last_error(None).decode())
         self.h = h
-        self._slot_desc = {i: d for i, d in enumerate(descs)}
+        self._slot_desc = {i: d for i, d in enumerate(first)}
+        if allocator is not None:
+            self._check(L.pic_set_allocator(self.h, C.byref(allocator.struct)))
+            for d in self.descs:
+                self.admit(d)
 
     def close(self):
         if getattr(self, "h", None):

@@ -257,14 +257,16 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
                                   (uint32_t)std::min<int64_t>(b + tile, sl.cap[sp])});
     rb[nsel + 1 + j] = (uint32_t)issued.size();
   }
+  // launch tables from the context's device memory source; a replaced table
+  // is reusable after the next synchronization
   auto ensure = [&](void*& p, size_t& have, size_t need) {
     if (have >= need) return;
-    if (p) {
-      C.sync();
-      (void)hipFree(p);
-    }
-    hip_check(hipMalloc(&p, need), "hipMalloc batched");
-    have = need;
+    if (p) C.pool.put(p, have);
+    p = nullptr;
+    have = 0;
+    const size_t cls = DevPool::class_of(need);
+    p = C.pool.get(cls);
+    have = cls;
   };
   ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * issued.size());
   ensure(C.b_insts, C.b_insts_bytes, sizeof(InstDev<T>) * nsel);
@@ -439,13 +441,12 @@ void pic_destroy(pic_ctx c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (Slot& s : c->slots) s.release_all();
+  c->release_tables();
   c->pool.clear();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  for (void* p : {c->b_insts, c->b_items, (void*)c->b_part, (void*)c->b_rowbeg, c->b_jobs})
-    if (p) (void)hipFree(p);
   if (c->arena) (void)hipHostFree(c->arena);
   delete c;
 }
@@ -455,6 +456,23 @@ int pic_set_stream(pic_ctx c, void* stream) {
   if (!c) throw Err(PIC_E_ARG, "null context");
   c->sync();
   c->stream = (hipStream_t)stream;
+  c->pool.stream = c->stream;
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_set_allocator(pic_ctx c, const pic_allocator* a) {
+  PIC_GUARD_BEGIN
+  if (!c) throw Err(PIC_E_ARG, "null context");
+  if (a && (!a->alloc || !a->free)) throw Err(PIC_E_ARG, "allocator needs alloc and free");
+  for (const Slot& s : c->slots)
+    if (s.live || !s.allocs.empty()) throw Err(PIC_E_STATE, "the context already holds instances");
+  c->sync();
+  c->release_tables();
+  c->pool.clear();   // blocks of the previous source go back to it
+  c->pool.has_ext = a != nullptr;
+  c->pool.ext = a ? *a : pic_allocator{};
+  c->pool.stream = c->stream;
   return PIC_OK;
   PIC_GUARD_END(c)
 }

@@ -27,7 +27,7 @@ struct Scratch {
   T* get(size_t n) {
     const size_t cls = DevPool::class_of(std::max<size_t>(n, 1) * sizeof(T));
     void* p = nullptr;
-    if (DevPool::pooled(cls)) {
+    if (pool.pooled(cls)) {
       p = pool.get(cls);
     } else {
       hip_check(hipMalloc(&p, cls), "hipMalloc scratch");
@@ -37,7 +37,7 @@ struct Scratch {
   }
   ~Scratch() {
     for (auto& b : blocks) {
-      if (DevPool::pooled(b.first)) {
+      if (pool.pooled(b.first)) {
         pool.put(b.second, b.first);
       } else {
         (void)hipDeviceSynchronize();

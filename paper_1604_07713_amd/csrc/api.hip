@@ -36,6 +36,11 @@ size_t DevPool::class_of(size_t bytes) {
 }
 
 void* DevPool::get(size_t cls) {
+  if (has_ext) {
+    void* p = ext.alloc(cls, (void*)stream, ext.user);
+    if (!p) throw Err(PIC_E_NOMEM, "the caller's allocator refused " + std::to_string(cls) + " bytes");
+    return p;
+  }
   auto it = free_.find(cls);
   if (it != free_.end()) {
     void* p = it->second;
@@ -61,6 +66,11 @@ void* DevPool::get(size_t cls) {
 void DevPool::put(void* p, size_t cls) { pending_.emplace_back(cls, p); }
 
 void DevPool::synced(size_t held) {
+  if (has_ext) {
+    for (auto& e : pending_) ext.free(e.second, ext.user);
+    pending_.clear();
+    return;
+  }
   const size_t limit = std::min(kMaxFree, std::max(kMinFree, held / 4));
   for (auto& e : pending_) {
     if (free_bytes + e.first > limit) {
@@ -81,6 +91,11 @@ void DevPool::synced(size_t held) {
 }
 
 void DevPool::clear() {
+  if (has_ext) {
+    for (auto& e : pending_) ext.free(e.second, ext.user);
+    pending_.clear();
+    return;
+  }
   for (auto& e : pending_) (void)hipFree(e.second);
   pending_.clear();
   for (auto& kv : free_) (void)hipFree(kv.second);
@@ -88,12 +103,23 @@ void DevPool::clear() {
   free_bytes = 0;
 }
 
+void Ctx::release_tables() {
+  void** tab[] = {&b_insts, &b_items, (void**)&b_part, (void**)&b_rowbeg, &b_jobs};
+  size_t* have[] = {&b_insts_bytes, &b_items_bytes, &b_part_bytes, &b_rowbeg_bytes, &b_jobs_bytes};
+  for (int i = 0; i < 5; ++i) {
+    if (*tab[i]) pool.put(*tab[i], *have[i]);
+    *tab[i] = nullptr;
+    *have[i] = 0;
+  }
+}
+
 void* Slot::alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   const size_t cls = DevPool::class_of(bytes);
   void* p = nullptr;
   size_t held = bytes;
-  if (pool && DevPool::pooled(cls)) {
+  const bool from_pool = pool && pool->pooled(cls);
+  if (from_pool) {
     p = pool->get(cls);
     held = cls;
   } else if (hipMalloc(&p, bytes) != hipSuccess || !p) {
@@ -102,13 +128,13 @@ void* Slot::alloc(size_t bytes) {
   }
   allocs.push_back(p);
   alloc_bytes.push_back(held);
+  alloc_pooled.push_back(from_pool ? 1 : 0);
   bytes_held += held;
   return p;
 }
 
-// Blocks taken from the pool carry their class size in alloc_bytes.
-static void give_back(DevPool* pool, void* p, size_t held) {
-  if (pool && DevPool::pooled(held) && held == DevPool::class_of(held)) pool->put(p, held);
+static void give_back(DevPool* pool, void* p, size_t held, bool from_pool) {
+  if (from_pool && pool) pool->put(p, held);
   else (void)hipFree(p);
 }
 
@@ -116,18 +142,20 @@ void Slot::release(void* p) {
   if (!p) return;
   for (size_t i = 0; i < allocs.size(); ++i)
     if (allocs[i] == p) {
-      give_back(pool, p, alloc_bytes[i]);
+      give_back(pool, p, alloc_bytes[i], alloc_pooled[i] != 0);
       bytes_held -= alloc_bytes[i];
       allocs.erase(allocs.begin() + i);
       alloc_bytes.erase(alloc_bytes.begin() + i);
+      alloc_pooled.erase(alloc_pooled.begin() + i);
       return;
     }
 }
 
 void Slot::release_all() {
-  for (size_t i = 0; i < allocs.size(); ++i) give_back(pool, allocs[i], alloc_bytes[i]);
+  for (size_t i = 0; i < allocs.size(); ++i) give_back(pool, allocs[i], alloc_bytes[i], alloc_pooled[i] != 0);
   allocs.clear();
   alloc_bytes.clear();
+  alloc_pooled.clear();
   bytes_held = 0;
 }
 
@@ -445,6 +473,7 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
   sl = Slot();
   sl.live = true;
   sl.pool = &C.pool;
+  C.pool.stream = C.stream;
   sl.d = d;
   sl.prec = d.precision;
   sl.esz = d.precision == 32 ? 4 : 8;

@@ -56,8 +56,13 @@ struct DevPool {
   std::multimap<size_t, void*> free_;
   std::vector<std::pair<size_t, void*>> pending_;
   size_t free_bytes = 0;
+  // caller's allocator (pic_set_allocator): every block comes from it and
+  // goes back to it at the next synchronization; nothing is cached here
+  pic_allocator ext{};
+  bool has_ext = false;
+  hipStream_t stream = nullptr;
   static size_t class_of(size_t bytes);
-  static bool pooled(size_t cls) { return cls <= kMaxBlock; }
+  bool pooled(size_t cls) const { return has_ext || cls <= kMaxBlock; }
   void* get(size_t cls);   // cls from class_of; throws PIC_E_NOMEM
   void put(void* p, size_t cls);
   void synced(size_t held);   // held: bytes the context's slots hold
@@ -118,6 +123,7 @@ struct Slot {
   // allocations
   std::vector<void*> allocs;
   std::vector<size_t> alloc_bytes;
+  std::vector<char> alloc_pooled;   // the block came from (and goes back to) the pool
   size_t bytes_held = 0;
   void* alloc(size_t bytes);
   void release(void* p);
@@ -149,6 +155,7 @@ struct Ctx {
   void* stage(const void* src, size_t bytes);
   void* pinned(size_t bytes);   // pinned host scratch from the staging arena
   void sync();
+  void release_tables();        // batched launch tables back to the pool
 };
 
 void derive(Slot& sl);
