@@ -802,7 +802,7 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
     c->sync();
     if (sc.done) break;
     if (k > maxit_u) throw Err(PIC_E_STATE, "CG did not stop");
-    batch = std::min(batch * 2, 32);
+    batch = std::min(batch * 2, 64);
   }
   const int it = (int)sc.it;
   const double rr = sc.rr, bb = sc.bb;

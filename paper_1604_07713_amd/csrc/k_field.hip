@@ -347,39 +347,52 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
   return hipGetLastError();
 }
 
-// CG workspace (doubles): r, z, p[0], p[1], q [5 n], block partials of p.q,
-// r.z, r.r and b.b [4][grid], then the scalars (CgScal).  One iteration k is
-// two launches: the direction and its image under A (with the partials of
-// p.q), then the updates of x, r and z (with the partials of r.z and r.r).
-// Each launch begins by summing the partials the previous launch left, in
-// the same fixed order in every workgroup, so every workgroup holds the same
-// alpha, beta and stopping test without a reduction launch, a fence or an
-// atomic.  Once the stopping test holds every later launch returns at once,
-// so the host queues many iterations between reads of the scalars.
+// CG with one global reduction per iteration (the Chronopoulos-Gear form of
+// Jacobi-preconditioned CG: mathematically the same iterates as the textbook
+// form).  With u = r / diag and w = A u, iteration k forms
+//   s_k = w_k + beta_k s_{k-1},  p_k = u_k + beta_k p_{k-1},
+//   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k,
+//   w_{k+1} = A u_{k+1},
+// and the three dot products r.u, w.u and r.r of the new vectors in one
+// pass; beta_k = g_k / g_{k-1} and alpha_k = g_k / (d_k - beta_k g_k /
+// alpha_{k-1}) with g = r.u, d = w.u (alpha_0 = g_0 / d_0, beta_0 = 0).
+// The product A u_{k+1} needs the neighbours' u_{k+1}: each row forms them
+// on the fly from the neighbours' r_k, w_k and s_{k-1}, with the very
+// operation their owner uses, so r, w and s are double-buffered by iteration
+// parity.  One iteration is one launch that begins by summing the partials
+// the previous launch left, in the same fixed order in every workgroup, so
+// every workgroup holds the same alpha, beta and stopping test without a
+// reduction launch, a fence or an atomic.  Once the stopping test holds every
+// later launch returns at once, so the host queues many iterations between
+// reads of the scalars.
+//
+// Workspace (doubles): r[2], w[2], s[2], p [7 n], block partials of r.u,
+// w.u, r.r and b.b [4][grid], then the scalars (CgScal).
 int cg_grid(uint32_t n) {
   int g = (int)ceil_div(n, kBlock);
   return g < 1024 ? g : 1024;
 }
 int cg_ws_doubles(uint32_t n) {
-  return (int)(5u * n + 4u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
+  return (int)(7u * n + 4u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
 }
-size_t cg_scalars_offset(uint32_t n) { return 5u * (size_t)n + 4u * (size_t)cg_grid(n); }
+size_t cg_scalars_offset(uint32_t n) { return 7u * (size_t)n + 4u * (size_t)cg_grid(n); }
 
 struct CgView {
-  double *r, *z, *p0, *p1, *q;
-  double *ppq, *prz, *prr, *pbb;
+  double *r[2], *w[2], *s[2], *p;
+  double *pg, *pd, *prr, *pbb;
   CgScal* sc;
 };
 __device__ __forceinline__ CgView cg_view(double* ws, uint32_t n, int grid) {
   CgView v;
-  v.r = ws;
-  v.z = ws + n;
-  v.p0 = ws + 2u * (size_t)n;
-  v.p1 = ws + 3u * (size_t)n;
-  v.q = ws + 4u * (size_t)n;
-  v.ppq = ws + 5u * (size_t)n;
-  v.prz = v.ppq + grid;
-  v.prr = v.prz + grid;
+  for (int b = 0; b < 2; ++b) {
+    v.r[b] = ws + (size_t)b * n;
+    v.w[b] = ws + (size_t)(2 + b) * n;
+    v.s[b] = ws + (size_t)(4 + b) * n;
+  }
+  v.p = ws + 6u * (size_t)n;
+  v.pg = ws + 7u * (size_t)n;
+  v.pd = v.pg + grid;
+  v.prr = v.pd + grid;
   v.pbb = v.prr + grid;
   v.sc = (CgScal*)(v.pbb + grid);
   return v;
@@ -406,40 +419,69 @@ __device__ __forceinline__ double sum_partials(const double* part) {
   return block_sum_all(a);
 }
 
-// r = b - A x, z = r / diag, p[0] = 0 (the first direction is z); partials
-// of r.z, r.r and b.b
+// Three workgroup sums in one pass through LDS (one pair of barriers).
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red3[3][kBlock / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane_id() == 0) {
+    red3[0][threadIdx.x / 64] = a;
+    red3[1][threadIdx.x / 64] = b;
+    red3[2][threadIdx.x / 64] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    a = a + red3[0][w];
+    b = b + red3[1][w];
+    c = c + red3[2][w];
+  }
+  __syncthreads();
+}
+// The partials of three arrays summed together, each in the fixed order of
+// sum_partials.
+__device__ __forceinline__ void sum_partials3(const double* pa, const double* pb, const double* pc, double& a,
+                                              double& b, double& c) {
+  a = b = c = 0.0;
+  for (uint32_t j = threadIdx.x; j < gridDim.x; j += kBlock) {
+    a += pa[j];
+    b += pb[j];
+    c += pc[j];
+  }
+  block_sum3(a, b, c);
+}
+
+// (A v)_i for a vector given row by row through f(j); U neighbours are
+// fetched at a time
+template <int U = 8, class F>
+__device__ __forceinline__ double apply_row(const Stencil2D& st, uint32_t i, double vi, F f) {
+  double y = st.diag[i] * vi;
+  const uint32_t* nb = st.nbr + (size_t)i * 8u;
+  const uint32_t code = st.code[i];
+#pragma unroll U
+  for (int c = 0; c < 8; ++c) y = y - face_coef((code >> (2 * c)) & 3u) * f(nb[c]);
+  return y;
+}
+
+// r = b - A x; partials of b.b
 __global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, const unsigned long long* __restrict__ Q,
                                                      int nspecies, double k0, double k1, const double* __restrict__ x,
                                                      double* ws) {
   const uint32_t n = m.nleaves;
   const CgView w = cg_view(ws, n, (int)gridDim.x);
-  double srz = 0.0, srr = 0.0, sbb = 0.0;
+  double sbb = 0.0;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     double b = (double)(long long)Q[i] * k0;
     if (nspecies > 1) b = b + (double)(long long)Q[(size_t)n + i] * k1;
     b = b + st.bnd[i];
-    double ax = st.diag[i] * x[i];
-    const uint32_t* nb = st.nbr + (size_t)i * 8u;
-    const uint32_t code = st.code[i];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      ax = ax - face_coef((code >> (2 * k)) & 3u) * x[nb[k]];
-    }
-    const double ri = b - ax;
-    const double zi = ri / st.diag[i];
-    w.r[i] = ri;
-    w.z[i] = zi;
-    w.p0[i] = 0.0;
-    srz += ri * zi;
-    srr += ri * ri;
+    const double ax = apply_row(st, i, x[i], [&](uint32_t j) { return x[j]; });
+    w.r[0][i] = b - ax;
     sbb += b * b;
   }
-  srz = block_sum_all(srz);
-  srr = block_sum_all(srr);
   sbb = block_sum_all(sbb);
   if (threadIdx.x == 0) {
-    w.prz[blockIdx.x] = srz;
-    w.prr[blockIdx.x] = srr;
     w.pbb[blockIdx.x] = sbb;
     if (blockIdx.x == 0) {
       w.sc->done = 0u;
@@ -448,81 +490,101 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, con
   }
 }
 
-// Iteration k, first half: r.z and r.r after k updates and the stopping test
-// (rr <= rtol2 bb, or k = maxit); beta = r.z / previous r.z (0 at k = 0);
-// p_new = z + beta p_old and q = A p_new (the neighbours' directions are
-// formed on the fly from their z and p_old with the same operation);
-// partials of p.q.
-__global__ __launch_bounds__(kBlock) void k_cg_dir(Mesh2D m, Stencil2D st, double* ws, uint32_t k, double rtol2,
-                                                   uint32_t maxit) {
+// u_0 = r_0 / diag, w_0 = A u_0, s_{-1} = p_{-1} = 0; partials of r.u, w.u
+// and r.r
+__global__ __launch_bounds__(kBlock) void k_cg_start(Mesh2D m, Stencil2D st, double* ws) {
+  const uint32_t n = m.nleaves;
+  const CgView w = cg_view(ws, n, (int)gridDim.x);
+  const double* __restrict__ r = w.r[0];
+  double sg = 0.0, sd = 0.0, srr = 0.0;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double ri = r[i];
+    const double ui = ri / st.diag[i];
+    const double wi = apply_row(st, i, ui, [&](uint32_t j) { return r[j] / st.diag[j]; });
+    w.w[0][i] = wi;
+    w.s[0][i] = 0.0;
+    w.p[i] = 0.0;
+    sg += ri * ui;
+    sd += wi * ui;
+    srr += ri * ri;
+  }
+  block_sum3(sg, sd, srr);
+  if (threadIdx.x == 0) {
+    w.pg[blockIdx.x] = sg;
+    w.pd[blockIdx.x] = sd;
+    w.prr[blockIdx.x] = srr;
+  }
+}
+
+// s_k, r_{k+1} and u_{k+1} of one row from its r_k, w_k, s_{k-1}: the same
+// operations for the owner and for every neighbour that needs its u_{k+1}
+#ifndef PIC_CG_UNROLL
+#define PIC_CG_UNROLL 4
+#endif
+struct CgNext {
+  double s, r, u;
+};
+__device__ __forceinline__ CgNext cg_next(double rk, double wk, double sk1, double dg, double alpha, double beta) {
+  CgNext o;
+  o.s = fma(beta, sk1, wk);
+  o.r = fma(-alpha, o.s, rk);
+  o.u = o.r / dg;
+  return o;
+}
+
+// Iteration k: the stopping test on r_k.r_k (rr <= rtol2 bb, or k = maxit),
+// alpha_k and beta_k, then s_k, p_k, x_{k+1}, r_{k+1}, w_{k+1} = A u_{k+1}
+// and the partials of r.u, w.u and r.r after the update.
+__global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
+                                                    uint32_t k, double rtol2, uint32_t maxit) {
   const uint32_t n = m.nleaves;
   const CgView w = cg_view(ws, n, (int)gridDim.x);
   CgScal* S = w.sc;
   if (S->done) return;   // uniform over the launch
-  const double rz = sum_partials(w.prz);
-  const double rr = sum_partials(w.prr);
-  double bb;
-  if (k == 0u) {
-    bb = sum_partials(w.pbb);
-  } else {
-    bb = S->bb;
-  }
+  double g, d, rr;
+  sum_partials3(w.pg, w.pd, w.prr, g, d, rr);
+  const double bb = k == 0u ? sum_partials(w.pbb) : S->bb;
   const bool stop = rr <= rtol2 * bb || k >= maxit;
+  const double beta = k == 0u ? 0.0 : g / S->gam[(k - 1u) & 1u];
+  const double alpha = k == 0u ? g / d : g / (d - beta * g / S->alf[(k - 1u) & 1u]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    S->rz2[k & 1u] = rz;
+    S->gam[k & 1u] = g;
+    S->alf[k & 1u] = alpha;
     S->rr = rr;
     if (k == 0u) S->bb = bb;
     S->it = k;
     if (stop) S->done = 1u;
   }
   if (stop) return;
-  const double beta = k == 0u ? 0.0 : rz / S->rz2[(k - 1u) & 1u];
-  const double* __restrict__ po = (k & 1u) ? w.p1 : w.p0;
-  double* __restrict__ pn = (k & 1u) ? w.p0 : w.p1;
-  const double* __restrict__ z = w.z;
-  double s = 0.0;
+  const bool odd = (k & 1u) != 0u;   // selects, not an index: keeps the view in registers
+  const double* __restrict__ R = odd ? w.r[1] : w.r[0];
+  const double* __restrict__ W = odd ? w.w[1] : w.w[0];
+  const double* __restrict__ Sp = odd ? w.s[1] : w.s[0];
+  double* __restrict__ Rn = odd ? w.r[0] : w.r[1];
+  double* __restrict__ Wn = odd ? w.w[0] : w.w[1];
+  double* __restrict__ Sn = odd ? w.s[0] : w.s[1];
+  double sg = 0.0, sd = 0.0, srr = 0.0;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const double pi = fma(beta, po[i], z[i]);
-    double y = st.diag[i] * pi;
-    const uint32_t* nb = st.nbr + (size_t)i * 8u;
-    const uint32_t code = st.code[i];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const uint32_t j = nb[c];
-      y = y - face_coef((code >> (2 * c)) & 3u) * fma(beta, po[j], z[j]);
-    }
-    pn[i] = pi;
-    w.q[i] = y;
-    s += pi * y;
+    const double dg = st.diag[i];
+    const double ri = R[i];
+    const CgNext o = cg_next(ri, W[i], Sp[i], dg, alpha, beta);
+    const double pi = fma(beta, w.p[i], ri / dg);
+    x[i] = fma(alpha, pi, x[i]);
+    const double wi = apply_row<PIC_CG_UNROLL>(st, i, o.u, [&](uint32_t j) {
+      return cg_next(R[j], W[j], Sp[j], st.diag[j], alpha, beta).u;
+    });
+    w.p[i] = pi;
+    Sn[i] = o.s;
+    Rn[i] = o.r;
+    Wn[i] = wi;
+    sg += o.r * o.u;
+    sd += wi * o.u;
+    srr += o.r * o.r;
   }
-  s = block_sum_all(s);
-  if (threadIdx.x == 0) w.ppq[blockIdx.x] = s;
-}
-
-// Iteration k, second half: alpha = r.z / p.q; x += alpha p, r -= alpha q,
-// z = r / diag; partials of r.z and r.r.
-__global__ __launch_bounds__(kBlock) void k_cg_update(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
-                                                      uint32_t k) {
-  const uint32_t n = m.nleaves;
-  const CgView w = cg_view(ws, n, (int)gridDim.x);
-  if (w.sc->done) return;   // uniform over the launch
-  const double pq = sum_partials(w.ppq);
-  const double alpha = w.sc->rz2[k & 1u] / pq;
-  const double* __restrict__ p = (k & 1u) ? w.p0 : w.p1;
-  double srz = 0.0, srr = 0.0;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    x[i] = x[i] + alpha * p[i];
-    const double ri = w.r[i] - alpha * w.q[i];
-    const double zi = ri / st.diag[i];
-    w.r[i] = ri;
-    w.z[i] = zi;
-    srz += ri * zi;
-    srr += ri * ri;
-  }
-  srz = block_sum_all(srz);
-  srr = block_sum_all(srr);
+  block_sum3(sg, sd, srr);
   if (threadIdx.x == 0) {
-    w.prz[blockIdx.x] = srz;
+    w.pg[blockIdx.x] = sg;
+    w.pd[blockIdx.x] = sd;
     w.prr[blockIdx.x] = srr;
   }
 }
@@ -531,14 +593,14 @@ hipError_t launch_cg_setup(const Mesh2D& m, const Stencil2D& st, const unsigned 
                            const double* kappa, double* x, double* ws, hipStream_t s) {
   const int g = cg_grid(m.nleaves);
   hipLaunchKernelGGL(k_cg_setup, dim3(g), dim3(kBlock), 0, s, m, st, Q, nspecies, kappa[0], kappa[1], x, ws);
+  hipLaunchKernelGGL(k_cg_start, dim3(g), dim3(kBlock), 0, s, m, st, ws);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, double* ws, uint32_t k, double rtol2,
                           uint32_t maxit, hipStream_t s) {
   const int g = cg_grid(m.nleaves);
-  hipLaunchKernelGGL(k_cg_dir, dim3(g), dim3(kBlock), 0, s, m, st, ws, k, rtol2, maxit);
-  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, m, st, x, ws, k);
+  hipLaunchKernelGGL(k_cg_iter, dim3(g), dim3(kBlock), 0, s, m, st, x, ws, k, rtol2, maxit);
   return hipGetLastError();
 }
 

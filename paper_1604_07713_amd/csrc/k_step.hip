@@ -328,8 +328,13 @@ __device__ __forceinline__ HotK<T> hot_constants(const InstDev<T>& I, int sp) {
 // Stage B of batch t+1 thus overlaps the locate and collision round trips of
 // batch t, and stage A overlaps the push.
 // Compiler-only fence: loads issued above it stay above it (they are not sunk
-// into the branches that use them), without waiting for their data.
-__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+// into the branches that use them), without waiting for their data, and no
+// instruction is scheduled across it (arithmetic on a load's result hoisted
+// above later loads would make those loads wait for it).
+__device__ __forceinline__ void issue_fence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
 
 template <class T>
 struct PState {

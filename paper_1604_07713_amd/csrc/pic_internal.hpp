@@ -154,7 +154,8 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
 // CG work vectors, block partials and scalars live in 'ws' (layout in
 // k_field.hip); the scalars sit at cg_scalars_offset(nleaves) doubles.
 struct CgScal {
-  double rz2[2];   // r.z of the last two iterations (by parity)
+  double gam[2];   // r.u of the last two iterations (by parity)
+  double alf[2];   // alpha of the last two iterations (by parity)
   double rr, bb;   // r.r of the last iteration checked, b.b
   uint32_t it;     // iterations done when the stopping test was last checked
   uint32_t done;   // stopping test met: later launches return at once
