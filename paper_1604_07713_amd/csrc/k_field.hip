@@ -362,24 +362,26 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
 // parity.  One iteration is one launch that begins by summing the partials
 // the previous launch left, in the same fixed order in every workgroup, so
 // every workgroup holds the same alpha, beta and stopping test without a
-// reduction launch, a fence or an atomic.  Once the stopping test holds every
-// later launch returns at once, so the host queues many iterations between
-// reads of the scalars.
+// reduction launch, a fence or an atomic; the partials are double-buffered
+// by parity too, since a workgroup that finishes early writes its partials
+// while a late one may still be summing the previous set.  Once the stopping
+// test holds every later launch returns at once, so the host queues many
+// iterations between reads of the scalars.
 //
 // Workspace (doubles): r[2], w[2], s[2], p [7 n], block partials of r.u,
-// w.u, r.r and b.b [4][grid], then the scalars (CgScal).
+// w.u and r.r [2][3][grid] and of b.b [grid], then the scalars (CgScal).
 int cg_grid(uint32_t n) {
   int g = (int)ceil_div(n, kBlock);
   return g < 1024 ? g : 1024;
 }
 int cg_ws_doubles(uint32_t n) {
-  return (int)(7u * n + 4u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
+  return (int)(7u * n + 7u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
 }
-size_t cg_scalars_offset(uint32_t n) { return 7u * (size_t)n + 4u * (size_t)cg_grid(n); }
+size_t cg_scalars_offset(uint32_t n) { return 7u * (size_t)n + 7u * (size_t)cg_grid(n); }
 
 struct CgView {
   double *r[2], *w[2], *s[2], *p;
-  double *pg, *pd, *prr, *pbb;
+  double *pg[2], *pd[2], *prr[2], *pbb;
   CgScal* sc;
 };
 __device__ __forceinline__ CgView cg_view(double* ws, uint32_t n, int grid) {
@@ -390,10 +392,13 @@ __device__ __forceinline__ CgView cg_view(double* ws, uint32_t n, int grid) {
     v.s[b] = ws + (size_t)(4 + b) * n;
   }
   v.p = ws + 6u * (size_t)n;
-  v.pg = ws + 7u * (size_t)n;
-  v.pd = v.pg + grid;
-  v.prr = v.pd + grid;
-  v.pbb = v.prr + grid;
+  double* part = ws + 7u * (size_t)n;
+  for (int b = 0; b < 2; ++b) {
+    v.pg[b] = part + (size_t)(3 * b) * grid;
+    v.pd[b] = part + (size_t)(3 * b + 1) * grid;
+    v.prr[b] = part + (size_t)(3 * b + 2) * grid;
+  }
+  v.pbb = part + (size_t)6 * grid;
   v.sc = (CgScal*)(v.pbb + grid);
   return v;
 }
@@ -510,9 +515,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Mesh2D m, Stencil2D st, dou
   }
   block_sum3(sg, sd, srr);
   if (threadIdx.x == 0) {
-    w.pg[blockIdx.x] = sg;
-    w.pd[blockIdx.x] = sd;
-    w.prr[blockIdx.x] = srr;
+    w.pg[0][blockIdx.x] = sg;
+    w.pd[0][blockIdx.x] = sd;
+    w.prr[0][blockIdx.x] = srr;
   }
 }
 
@@ -541,8 +546,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, doub
   const CgView w = cg_view(ws, n, (int)gridDim.x);
   CgScal* S = w.sc;
   if (S->done) return;   // uniform over the launch
+  const bool odd = (k & 1u) != 0u;   // selects, not an index: keeps the view in registers
   double g, d, rr;
-  sum_partials3(w.pg, w.pd, w.prr, g, d, rr);
+  sum_partials3(odd ? w.pg[1] : w.pg[0], odd ? w.pd[1] : w.pd[0], odd ? w.prr[1] : w.prr[0], g, d, rr);
   const double bb = k == 0u ? sum_partials(w.pbb) : S->bb;
   const bool stop = rr <= rtol2 * bb || k >= maxit;
   const double beta = k == 0u ? 0.0 : g / S->gam[(k - 1u) & 1u];
@@ -556,7 +562,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, doub
     if (stop) S->done = 1u;
   }
   if (stop) return;
-  const bool odd = (k & 1u) != 0u;   // selects, not an index: keeps the view in registers
   const double* __restrict__ R = odd ? w.r[1] : w.r[0];
   const double* __restrict__ W = odd ? w.w[1] : w.w[0];
   const double* __restrict__ Sp = odd ? w.s[1] : w.s[0];
@@ -583,9 +588,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, doub
   }
   block_sum3(sg, sd, srr);
   if (threadIdx.x == 0) {
-    w.pg[blockIdx.x] = sg;
-    w.pd[blockIdx.x] = sd;
-    w.prr[blockIdx.x] = srr;
+    (odd ? w.pg[0] : w.pg[1])[blockIdx.x] = sg;
+    (odd ? w.pd[0] : w.pd[1])[blockIdx.x] = sd;
+    (odd ? w.prr[0] : w.prr[1])[blockIdx.x] = srr;
   }
 }
 

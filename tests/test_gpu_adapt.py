@@ -152,3 +152,28 @@ def test_cg_solve_matches_oracle_and_direct():
     Eo = o.field_table()
     Eg = g.field_table(0)
     assert np.max(np.abs(Eg - Eo)) <= 1e-6 * np.max(np.abs(Eo))
+
+
+def test_cg_large_grid_deterministic():
+    """A 512 x 512 uniform tree (262,144 unknowns, the largest CG launch of
+    1024 workgroups): two solves from the same start give the same bits and
+    iteration count (the block partials each launch sums are not overwritten
+    by workgroups that finish early), and the true residual of the result
+    meets the tolerance."""
+    import scipy.sparse
+    d = I.streamer_desc(precision=64, min_level=9, max_level=9)
+    pos, ve, vi = cluster(200000, 7, sigma=0.1)
+    parts = [(pos, ve, None, np.arange(200000, dtype=np.uint32)),
+             (pos[:150000], vi[:150000], None, np.arange(200000, 350000, dtype=np.uint32))]
+    o, g = load_both(d, parts)
+    assert g.nq(0) == 512 * 512
+    o.deposit()
+    g.deposit(0)
+    zero = np.zeros(g.nq(0))
+    p1, it1, rr1, rc1 = g.field_solve_2d(0, phi_init=zero, rtol=1e-10)
+    p2, it2, rr2, rc2 = g.field_solve_2d(0, phi_init=zero, rtol=1e-10)
+    assert rc1 == 0 and rc2 == 0 and it1 > 100
+    assert it1 == it2 and np.array_equal(p1, p2)
+    rows, cols, vals, rhs = o.assemble_2d()
+    A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(o.nq(), o.nq()))
+    assert np.linalg.norm(rhs - A @ p1) <= 1e-8 * np.linalg.norm(rhs)
