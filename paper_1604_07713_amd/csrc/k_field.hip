@@ -368,31 +368,35 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
 // test holds every later launch returns at once, so the host queues many
 // iterations between reads of the scalars.
 //
-// Workspace (doubles): r[2], w[2], s[2], p [7 n], block partials of r.u,
-// w.u and r.r [2][3][grid] and of b.b [grid], then the scalars (CgScal).
+// Workspace (doubles): two sets (by parity) of per-row records {r, w, s,
+// diag} [2][4 n] (a neighbour's operands are one 32-byte record, not four
+// scattered doubles), p [n], block partials of r.u, w.u and r.r
+// [2][3][grid] and of b.b [grid], then the scalars (CgScal).
 int cg_grid(uint32_t n) {
   int g = (int)ceil_div(n, kBlock);
   return g < 1024 ? g : 1024;
 }
 int cg_ws_doubles(uint32_t n) {
-  return (int)(7u * n + 7u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
+  return (int)(9u * n + 7u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
 }
-size_t cg_scalars_offset(uint32_t n) { return 7u * (size_t)n + 7u * (size_t)cg_grid(n); }
+size_t cg_scalars_offset(uint32_t n) { return 9u * (size_t)n + 7u * (size_t)cg_grid(n); }
+
+struct __attribute__((aligned(32))) CgRec {
+  double r, w, s, d;
+};
 
 struct CgView {
-  double *r[2], *w[2], *s[2], *p;
+  CgRec* rec[2];
+  double* p;
   double *pg[2], *pd[2], *prr[2], *pbb;
   CgScal* sc;
 };
 __device__ __forceinline__ CgView cg_view(double* ws, uint32_t n, int grid) {
   CgView v;
-  for (int b = 0; b < 2; ++b) {
-    v.r[b] = ws + (size_t)b * n;
-    v.w[b] = ws + (size_t)(2 + b) * n;
-    v.s[b] = ws + (size_t)(4 + b) * n;
-  }
-  v.p = ws + 6u * (size_t)n;
-  double* part = ws + 7u * (size_t)n;
+  v.rec[0] = (CgRec*)ws;
+  v.rec[1] = (CgRec*)(ws + 4u * (size_t)n);
+  v.p = ws + 8u * (size_t)n;
+  double* part = ws + 9u * (size_t)n;
   for (int b = 0; b < 2; ++b) {
     v.pg[b] = part + (size_t)(3 * b) * grid;
     v.pd[b] = part + (size_t)(3 * b + 1) * grid;
@@ -482,7 +486,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, con
     if (nspecies > 1) b = b + (double)(long long)Q[(size_t)n + i] * k1;
     b = b + st.bnd[i];
     const double ax = apply_row(st, i, x[i], [&](uint32_t j) { return x[j]; });
-    w.r[0][i] = b - ax;
+    const double dg = st.diag[i];
+    w.rec[0][i].r = b - ax;
+    w.rec[0][i].d = dg;
+    w.rec[1][i].d = dg;
     sbb += b * b;
   }
   sbb = block_sum_all(sbb);
@@ -500,14 +507,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(Mesh2D m, Stencil2D st, con
 __global__ __launch_bounds__(kBlock) void k_cg_start(Mesh2D m, Stencil2D st, double* ws) {
   const uint32_t n = m.nleaves;
   const CgView w = cg_view(ws, n, (int)gridDim.x);
-  const double* __restrict__ r = w.r[0];
+  CgRec* __restrict__ rc = w.rec[0];
   double sg = 0.0, sd = 0.0, srr = 0.0;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const double ri = r[i];
-    const double ui = ri / st.diag[i];
-    const double wi = apply_row(st, i, ui, [&](uint32_t j) { return r[j] / st.diag[j]; });
-    w.w[0][i] = wi;
-    w.s[0][i] = 0.0;
+    const double ri = rc[i].r;
+    const double ui = ri / rc[i].d;
+    const double wi = apply_row(st, i, ui, [&](uint32_t j) { return rc[j].r / rc[j].d; });
+    rc[i].w = wi;
+    rc[i].s = 0.0;
     w.p[i] = 0.0;
     sg += ri * ui;
     sd += wi * ui;
@@ -523,9 +530,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Mesh2D m, Stencil2D st, dou
 
 // s_k, r_{k+1} and u_{k+1} of one row from its r_k, w_k, s_{k-1}: the same
 // operations for the owner and for every neighbour that needs its u_{k+1}
-#ifndef PIC_CG_UNROLL
-#define PIC_CG_UNROLL 4
-#endif
 struct CgNext {
   double s, r, u;
 };
@@ -537,18 +541,96 @@ __device__ __forceinline__ CgNext cg_next(double rk, double wk, double sk1, doub
   return o;
 }
 
+// Operands of one row that do not depend on alpha and beta: its own r_k,
+// w_k, s_{k-1}, p_{k-1}, x_k, diagonal and face codes, and its neighbours'
+// r_k, w_k, s_{k-1} and diagonals.
+struct CgRow {
+  double dg, r, w, s, p, x;
+  uint32_t code;
+  double nr[8], nw[8], ns[8], nd[8];
+};
+__device__ __forceinline__ void cg_load_row(const Stencil2D& st, const CgRec* __restrict__ rc,
+                                            const double* __restrict__ P, const double* __restrict__ x, uint32_t i,
+                                            CgRow& a) {
+  const CgRec o = rc[i];
+  a.dg = o.d;
+  a.r = o.r;
+  a.w = o.w;
+  a.s = o.s;
+  a.p = P[i];
+  a.x = x[i];
+  a.code = st.code[i];
+  const uint32_t* nb = st.nbr + (size_t)i * 8u;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const CgRec q = rc[nb[c]];
+    a.nr[c] = q.r;
+    a.nw[c] = q.w;
+    a.ns[c] = q.s;
+    a.nd[c] = q.d;
+  }
+}
+// The row's update: s_k, p_k, x_{k+1}, r_{k+1}, u_{k+1} and w_{k+1} = (A u_{k+1})_i
+// (the diagonal term first, then the eight neighbours in stencil order).
+struct CgOut {
+  CgNext o;
+  double p, x, w;
+};
+__device__ __forceinline__ CgOut cg_row(const CgRow& a, double alpha, double beta) {
+  CgOut r;
+  r.o = cg_next(a.r, a.w, a.s, a.dg, alpha, beta);
+  r.p = fma(beta, a.p, a.r / a.dg);
+  r.x = fma(alpha, r.p, a.x);
+  double y = a.dg * r.o.u;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    y = y - face_coef((a.code >> (2 * c)) & 3u) * cg_next(a.nr[c], a.nw[c], a.ns[c], a.nd[c], alpha, beta).u;
+  r.w = y;
+  return r;
+}
+
 // Iteration k: the stopping test on r_k.r_k (rr <= rtol2 bb, or k = maxit),
 // alpha_k and beta_k, then s_k, p_k, x_{k+1}, r_{k+1}, w_{k+1} = A u_{k+1}
-// and the partials of r.u, w.u and r.r after the update.
+// and the partials of r.u, w.u and r.r after the update.  The loads of the
+// partials, of the thread's first row and of its neighbours are all issued
+// before the partials are reduced (none of them depends on alpha or beta),
+// so the launch waits about two memory latencies instead of four.
+constexpr int kCgPartLoads = 1024 / kBlock;   // cg_grid() <= 1024 workgroups
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
                                                     uint32_t k, double rtol2, uint32_t maxit) {
   const uint32_t n = m.nleaves;
   const CgView w = cg_view(ws, n, (int)gridDim.x);
   CgScal* S = w.sc;
-  if (S->done) return;   // uniform over the launch
   const bool odd = (k & 1u) != 0u;   // selects, not an index: keeps the view in registers
-  double g, d, rr;
-  sum_partials3(odd ? w.pg[1] : w.pg[0], odd ? w.pd[1] : w.pd[0], odd ? w.prr[1] : w.prr[0], g, d, rr);
+  const double* __restrict__ pg = odd ? w.pg[1] : w.pg[0];
+  const double* __restrict__ pd = odd ? w.pd[1] : w.pd[0];
+  const double* __restrict__ pr = odd ? w.prr[1] : w.prr[0];
+  // partials of the previous launch, in the order sum_partials takes them
+  double vg[kCgPartLoads], vd[kCgPartLoads], vr[kCgPartLoads];
+#pragma unroll
+  for (int q = 0; q < kCgPartLoads; ++q) {
+    const uint32_t j = threadIdx.x + (uint32_t)q * kBlock;
+    const uint32_t jj = j < gridDim.x ? j : 0u;
+    vg[q] = pg[jj];
+    vd[q] = pd[jj];
+    vr[q] = pr[jj];
+  }
+  const CgRec* __restrict__ rc = odd ? w.rec[1] : w.rec[0];
+  const uint32_t i0 = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t stride = gridDim.x * kBlock;
+  CgRow a;
+  if (i0 < n) cg_load_row(st, rc, w.p, x, i0, a);
+  if (S->done) return;   // uniform over the launch (nothing has been written)
+  double g = 0.0, d = 0.0, rr = 0.0;
+#pragma unroll
+  for (int q = 0; q < kCgPartLoads; ++q) {
+    if (threadIdx.x + (uint32_t)q * kBlock < gridDim.x) {
+      g += vg[q];
+      d += vd[q];
+      rr += vr[q];
+    }
+  }
+  block_sum3(g, d, rr);
   const double bb = k == 0u ? sum_partials(w.pbb) : S->bb;
   const bool stop = rr <= rtol2 * bb || k >= maxit;
   const double beta = k == 0u ? 0.0 : g / S->gam[(k - 1u) & 1u];
@@ -562,29 +644,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, doub
     if (stop) S->done = 1u;
   }
   if (stop) return;
-  const double* __restrict__ R = odd ? w.r[1] : w.r[0];
-  const double* __restrict__ W = odd ? w.w[1] : w.w[0];
-  const double* __restrict__ Sp = odd ? w.s[1] : w.s[0];
-  double* __restrict__ Rn = odd ? w.r[0] : w.r[1];
-  double* __restrict__ Wn = odd ? w.w[0] : w.w[1];
-  double* __restrict__ Sn = odd ? w.s[0] : w.s[1];
+  CgRec* __restrict__ rn = odd ? w.rec[0] : w.rec[1];
   double sg = 0.0, sd = 0.0, srr = 0.0;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const double dg = st.diag[i];
-    const double ri = R[i];
-    const CgNext o = cg_next(ri, W[i], Sp[i], dg, alpha, beta);
-    const double pi = fma(beta, w.p[i], ri / dg);
-    x[i] = fma(alpha, pi, x[i]);
-    const double wi = apply_row<PIC_CG_UNROLL>(st, i, o.u, [&](uint32_t j) {
-      return cg_next(R[j], W[j], Sp[j], st.diag[j], alpha, beta).u;
-    });
-    w.p[i] = pi;
-    Sn[i] = o.s;
-    Rn[i] = o.r;
-    Wn[i] = wi;
-    sg += o.r * o.u;
-    sd += wi * o.u;
-    srr += o.r * o.r;
+  for (uint32_t i = i0; i < n; i += stride) {
+    if (i != i0) cg_load_row(st, rc, w.p, x, i, a);
+    const CgOut u = cg_row(a, alpha, beta);
+    w.p[i] = u.p;
+    x[i] = u.x;
+    rn[i].r = u.o.r;   // the record's diagonal stays
+    rn[i].w = u.w;
+    rn[i].s = u.o.s;
+    sg += u.o.r * u.o.u;
+    sd += u.w * u.o.u;
+    srr += u.o.r * u.o.r;
   }
   block_sum3(sg, sd, srr);
   if (threadIdx.x == 0) {
