@@ -95,13 +95,15 @@ def test_adapt_coarsens_after_removal():
     compare_all(o2, g2, 64, "after removal")
 
 
-@pytest.mark.parametrize("precision,ranking", [(64, 0), (32, 0), (32, 2)])
-def test_streamer_steps_with_births_match(precision, ranking):
+@pytest.mark.parametrize("precision,ranking,max_level", [(64, 0, 11), (32, 0, 11), (32, 2, 11), (32, 0, 12)])
+def test_streamer_steps_with_births_match(precision, ranking, max_level):
     """2D electron avalanche: 1 atm N2-like gas, 30 kV/cm, Gaussian seed of
     electron-ion pairs, levels 5-11, adapt every 10 steps, MCC with
     ionization births; both sides step with the same field table.  ranking 2:
-    the GPU ranks the births through id bins instead of pairwise."""
-    d = I.streamer_desc(precision=precision)
+    the GPU ranks the births through id bins instead of pairwise.  Levels up
+    to 12 take the point location that ends in a binary search (the lookup
+    table stops at level 11)."""
+    d = I.streamer_desc(precision=precision, max_level=max_level)
     parts = I.streamer_particles(d, npairs=3000)
     o, g = load_both(d, parts)
     g.set_births_ranking(0, ranking)
