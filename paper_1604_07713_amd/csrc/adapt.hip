@@ -103,16 +103,34 @@ bool rebuild(Ctx& C, Slot& sl, Scratch& S, uint32_t* emit, const uint32_t* cflag
   return true;
 }
 
+// Per-leaf counts of the present tree and particles, kept until either
+// changes (a rebuild, a relocation or new particles), so a pass that finds
+// nothing to do leaves its counts to the next pass.
+template <class T>
+struct Counts {
+  Ctx& C;
+  Slot& sl;
+  Scratch keep;
+  uint32_t* cnt = nullptr;
+  Counts(Ctx& c, Slot& s) : C(c), sl(s), keep(c) {}
+  uint32_t* get() {
+    if (!cnt) cnt = count_all<T>(C, sl, keep);
+    return cnt;
+  }
+  void stale() { cnt = nullptr; }
+};
+
 template <class T>
 void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   pic_adapt_stats st;
   std::memset(&st, 0, sizeof(st));
   const int ns = sl.d.nspecies;
   relocate_all<T>(C, sl);
+  Counts<T> counts(C, sl);
   // ---- coarsen and refine decided on the current tree ----
   {
     Scratch S(C);
-    uint32_t* cnt = count_all<T>(C, sl, S);
+    uint32_t* cnt = counts.get();
     const uint32_t n = sl.nleaves;
     uint32_t* cflag = S.get<uint32_t>(n);
     uint32_t* emit = S.get<uint32_t>(n + 1);
@@ -128,12 +146,13 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
     if (h[0]) {
       rebuild(C, sl, S, emit, cflag);
       relocate_all<T>(C, sl);
+      counts.stale();
     }
   }
   // ---- refine again while a leaf is over the upper bound ----
   for (;;) {
     Scratch S(C);
-    uint32_t* cnt = count_all<T>(C, sl, S);
+    uint32_t* cnt = counts.get();
     const uint32_t n = sl.nleaves;
     uint32_t* emit = S.get<uint32_t>(n + 1);
     uint32_t* nch = S.get<uint32_t>(3);
@@ -146,8 +165,10 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
     st.refined += h[2];
     rebuild(C, sl, S, emit, nullptr);
     relocate_all<T>(C, sl);
+    counts.stale();
   }
   // ---- 2:1 balance by refinement ----
+  bool balanced = false;
   for (;;) {
     Scratch S(C);
     const uint32_t n = sl.nleaves;
@@ -164,12 +185,16 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
     hip_check(hipMemsetAsync(nch, 0, 12, C.stream), "memset");
     hip_check(launch_tree_flags(view(sl), nullptr, ns, n_hi, 2, mark, nullptr, emit, nch, C.stream), "flags");
     rebuild(C, sl, S, emit, nullptr);
+    balanced = true;
   }
-  relocate_all<T>(C, sl);
+  if (balanced) {
+    relocate_all<T>(C, sl);
+    counts.stale();
+  }
   // ---- split rounds ----
   for (;;) {
     Scratch S(C);
-    uint32_t* cnt = count_all<T>(C, sl, S);
+    uint32_t* cnt = counts.get();
     Counters cn = read_counters(C, sl);
     const uint32_t nw = cn.next_id / 32u + 1u;
     uint32_t* bitmap = S.get<uint32_t>(nw);
@@ -205,6 +230,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
                   "split emit");
     }
     hip_check(launch_split_commit(sl.ctr, np, ns, C.stream), "split commit");
+    counts.stale();
     st.split_parents += (int64_t)tot;
   }
   // ---- merge (leaves at the finest level over the upper bound) ----
@@ -213,7 +239,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   // per species finishes it.
   {
     Scratch S(C);
-    uint32_t* cnt = count_all<T>(C, sl, S);
+    uint32_t* cnt = counts.get();
     const uint32_t n = sl.nleaves;
     uint32_t* groups = S.get<uint32_t>(n);
     uint32_t* ng = S.get<uint32_t>(1);
