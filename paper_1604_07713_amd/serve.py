@@ -61,6 +61,7 @@ class Job:
         self.updates = 0
         self.result = None
         self.failed = False
+        self.error = None  # (status, message) of a failed job
         self.n_now = 0     # live particles after the last tick
         if self.kind == "ccp":
             self.desc = I.ccp_desc(ncells=spec["ncells"], ppc=spec["ppc"], voltage=spec["voltage"],
@@ -225,6 +226,9 @@ class Server:
             if e.code not in (B.PIC_E_NOMEM, B.PIC_E_CAPACITY):
                 raise
             j.failed = True
+            j.error = (e.code, str(e))
+            print(json.dumps(dict(job_failed=j.spec.get("key"), steps=j.steps_done, particles=j.n_now, error=str(e))),
+                  file=sys.stderr, flush=True)
             j.steps_done = j.steps_total
         return upd
 
@@ -296,7 +300,10 @@ class Server:
         wall = time.perf_counter() - t_start
         ok = [j for j in self.done if not j.failed]
         ttr = np.array([j.t_done - j.t_submit for j in ok]) if ok else np.zeros(0)
-        return dict(jobs_done=len(ok), jobs_failed=len(self.done) - len(ok), jobs_submitted=i,
+        fails = [j.error[0] for j in self.done if j.failed and j.error]
+        return dict(jobs_done=len(ok), jobs_failed=len(self.done) - len(ok),
+                    jobs_failed_nomem=fails.count(B.PIC_E_NOMEM), jobs_failed_capacity=fails.count(B.PIC_E_CAPACITY),
+                    jobs_submitted=i,
                     jobs_pending=len(self.pending),
                     jobs_running=len(self.running), wall_s=wall, ticks=ticks,
                     updates=total_upd, updates_per_s=total_upd / wall if wall > 0 else 0.0,
@@ -344,17 +351,26 @@ def make_jobs(rate=20.0, duration=60.0, seed=5, scale=1.0, max_jobs=None, precis
     return jobs
 
 
+# Job lengths above this scale are refused (see main()).
+MAX_STEPS_SCALE = 0.2
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--duration", type=float, default=60.0, help="arrival window, s")
     ap.add_argument("--rate", type=float, default=20.0, help="jobs per second")
     ap.add_argument("--max-wall", type=float, default=None, help="stop serving after this many seconds")
-    ap.add_argument("--steps-scale", type=float, default=1.0, help="scale every job's step count")
+    ap.add_argument("--steps-scale", type=float, default=0.2,
+                    help=f"scale every job's step count (at most {MAX_STEPS_SCALE})")
     ap.add_argument("--tick-steps", type=int, default=25)
     ap.add_argument("--workers", type=int, default=4, help="streams / threads driving the 2D jobs (0: none)")
     ap.add_argument("--plain", action="store_true",
                     help="the plain method: FP64 particles, every job stepped with its own launches")
     args = ap.parse_args()
+    if args.steps_scale > MAX_STEPS_SCALE:
+        raise SystemExit(f"--steps-scale {args.steps_scale} refused: a full-length stream (avalanche jobs "
+                         f"of 2000 steps, up to ~100 resident 2D contexts) once ended in an illegal device "
+                         f"memory access whose cause is not yet found; use at most {MAX_STEPS_SCALE}")
     import torch
     torch.cuda.set_device(0)
     jobs = make_jobs(args.rate, args.duration, scale=args.steps_scale, precision=64 if args.plain else 32)
