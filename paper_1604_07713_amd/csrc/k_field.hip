@@ -46,21 +46,41 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
   __syncthreads();
   if (threadIdx.x == 0) {
     // forward sweep: d'_i = (b_i + d'_{i-1}) / m_i with phi_0 folded into b_1
+    // and phi_N = 0 into b_{N-1}.  The operands of the next group of kSweep
+    // elements are read from LDS while the current group's chain runs.
+    constexpr int kSweep = 8;
     double prev = 0.0;
     int i = 1;
-    for (; i + 3 < N; i += 4) {
-      const double b0 = b[i], b1 = b[i + 1], b2 = b[i + 2], b3 = b[i + 3];
-      const double m0 = im[i], m1 = im[i + 1], m2 = im[i + 2], m3 = im[i + 3];
-      const double c0 = (i == 1) ? b0 + left : b0;
-      const double d0 = (c0 + prev) * m0;
-      const double d1 = (b1 + d0) * m1;
-      const double d2 = (b2 + d1) * m2;
-      const double d3 = (b3 + d2) * m3;
-      b[i] = d0;
-      b[i + 1] = d1;
-      b[i + 2] = d2;
-      b[i + 3] = d3;
-      prev = d3;
+    if (N - 1 >= 2 * kSweep) {
+      double bn[kSweep], mn[kSweep];
+#pragma unroll
+      for (int q = 0; q < kSweep; ++q) {
+        bn[q] = b[i + q];
+        mn[q] = im[i + q];
+      }
+      bn[0] = bn[0] + left;
+      for (; i + 2 * kSweep <= N - 1; i += kSweep) {
+        double bc[kSweep], mc[kSweep];
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) {
+          bc[q] = bn[q];
+          mc[q] = mn[q];
+          bn[q] = b[i + kSweep + q];
+          mn[q] = im[i + kSweep + q];
+        }
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) {
+          prev = (bc[q] + prev) * mc[q];
+          b[i + q] = prev;
+        }
+      }
+      // the group already read (i .. i + kSweep - 1 < N - 1)
+#pragma unroll
+      for (int q = 0; q < kSweep; ++q) {
+        prev = (bn[q] + prev) * mn[q];
+        b[i + q] = prev;
+      }
+      i += kSweep;
     }
     for (; i < N; ++i) {
       double c = (i == 1) ? b[i] + left : b[i];
@@ -72,18 +92,34 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
     // back substitution: phi_{N-1} = d'_{N-1}, phi_i = d'_i + phi_{i+1} / m_i
     double nxt = b[N - 1];
     int j = N - 2;
-    for (; j - 3 >= 1; j -= 4) {
-      const double a0 = b[j], a1 = b[j - 1], a2 = b[j - 2], a3 = b[j - 3];
-      const double m0 = im[j], m1 = im[j - 1], m2 = im[j - 2], m3 = im[j - 3];
-      const double p0 = a0 + m0 * nxt;
-      const double p1 = a1 + m1 * p0;
-      const double p2 = a2 + m2 * p1;
-      const double p3 = a3 + m3 * p2;
-      b[j] = p0;
-      b[j - 1] = p1;
-      b[j - 2] = p2;
-      b[j - 3] = p3;
-      nxt = p3;
+    if (j + 1 >= 2 * kSweep + 1) {
+      double an[kSweep], mn[kSweep];
+#pragma unroll
+      for (int q = 0; q < kSweep; ++q) {
+        an[q] = b[j - q];
+        mn[q] = im[j - q];
+      }
+      for (; j - 2 * kSweep + 1 >= 1; j -= kSweep) {
+        double ac[kSweep], mc[kSweep];
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) {
+          ac[q] = an[q];
+          mc[q] = mn[q];
+          an[q] = b[j - kSweep - q];
+          mn[q] = im[j - kSweep - q];
+        }
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) {
+          nxt = ac[q] + mc[q] * nxt;
+          b[j - q] = nxt;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kSweep; ++q) {
+        nxt = an[q] + mn[q] * nxt;
+        b[j - q] = nxt;
+      }
+      j -= kSweep;
     }
     for (; j >= 1; --j) {
       const double p = b[j] + im[j] * nxt;
