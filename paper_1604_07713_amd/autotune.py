@@ -44,7 +44,7 @@ def save_cache(c):
         pass
 
 
-def tune(make_ctx, descs, v_next, steps=6, tiles=TILES, grids=GRIDS, use_cache=True):
+def tune(make_ctx, descs, v_next, steps=8, tiles=TILES, grids=GRIDS, use_cache=True, passes=3):
     """make_ctx(): a fresh, loaded and started context of the ensemble.
     v_next: [steps][nslots] drive table.  Returns dict(tile=, grid=, ns_per_update=)."""
     key = f"{arch()}/{size_class(descs)}"
@@ -57,17 +57,18 @@ def tune(make_ctx, descs, v_next, steps=6, tiles=TILES, grids=GRIDS, use_cache=T
     step0 = 0
     # Warm up.  Every run ends with a sort, so each candidate starts from
     # particles in cell order; candidates are scored by kernel time per
-    # particle-update, and two passes in opposite orders cancel the drift of
-    # the ensemble (it grows and heats while it is tuned).
+    # particle-update summed over passes in alternating orders, which cancels
+    # the drift of the ensemble (it grows and heats while it is tuned) and
+    # averages out the noise of single short runs.
     g.step(step0, 2, v_next[:2], solve_field=True, batched=4096, sort_every=2)
     step0 += 2
-    for order in (cands, cands[::-1]):
+    for order in [cands if k % 2 == 0 else cands[::-1] for k in range(passes)]:
         for t, gr in order:
             st = g.step(step0, steps, v_next[step0:step0 + steps], solve_field=True, batched=t, grid=gr,
                         timing=True, sort_every=steps)
             step0 += steps
             upd = max(st["alive_start"][0] + st["alive_start"][1], 1)
-            score[(t, gr)] += 0.5 * st["loop_ms"] / upd
+            score[(t, gr)] += st["loop_ms"] / upd / passes
     g.close()
     results = [(m, t, gr) for (t, gr), m in score.items()]
     ns, t, gr = min(results)
