@@ -1,0 +1,86 @@
+"""Edge cases of the step loop against the oracle: particle counts below one
+wave and not a multiple of the batch (lanes past the end must neither load
+out of range nor contribute), a discharge of one particle per cell, and an
+instance whose particles all leave through the walls and which keeps
+stepping empty."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07713_amd import binding as B
+from paper_1604_07713_amd import inputs as I
+from tests.gpu_common import assert_same_particles, ccp_run_both, load_both
+
+pytestmark = pytest.mark.gpu
+TOL = {64: 1e-12, 32: 1e-5}
+
+
+@pytest.mark.parametrize("n", [1, 5, 63, 257, 513])
+def test_quadtree_ragged_counts(n):
+    """The static quadtree with n FP32 electrons (fewer than a wave, or a
+    ragged last batch), 60 steps with a sort every 10."""
+    d = I.quadtree_static_desc()
+    s, v, w, ids = I.quadtree_particles(n, seed=9)
+    o, g = load_both(d, [(s, v, w, ids)])
+    keys, lv = o.leaves()
+    cx, cy = I.leaf_corners(keys, lv)
+    phi = I.quadtree_phi(cx, cy)
+    o.field_set(oracle.CORNER_PHI_2D, phi)
+    g.field_set(0, B.CORNER_PHI_2D, phi)
+    o.leapfrog_start()
+    g.leapfrog_start(0)
+    so = o.step(0, 60)
+    sg = g.step(0, 60, sort_every=10)
+    assert so["alive_start"] == sg["alive_start"]
+    assert_same_particles(o.read(0), g.read(0, 0), TOL[32], f"n={n}")
+    assert np.array_equal(o.deposit(), g.deposit(0))
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_ccp_one_particle_per_cell(precision):
+    """A 16-cell discharge with one electron and one ion per cell (32
+    particles, collisions and births on), 200 steps."""
+    d = I.ccp_desc(ncells=16, ppc=1, precision=precision)
+    o, g, so, sg = ccp_run_both(d, 200, sort_every=20)
+    for k in ("alive_start", "absorbed", "elastic", "ionization", "cx", "births"):
+        assert so[k] == sg[k], (k, so[k], sg[k])
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), TOL[precision], f"species {sp}")
+    assert o.next_id == g.next_id(0)
+
+
+def test_ccp_all_particles_leave_then_empty_steps():
+    """Every particle starts next to the grounded wall moving out: after a
+    few steps the instance is empty on both sides, its deposit is zero, and
+    30 more steps of an empty instance change nothing."""
+    d = I.ccp_desc(ncells=64, ppc=4, precision=64)
+    rng = np.random.Generator(np.random.PCG64(13))
+    ne = 40
+    s = 0.999 + 0.0009 * rng.random((ne, 1))
+    ve = np.zeros((ne, 3))
+    ve[:, 0] = 1.0e7
+    vi = np.zeros((ne, 3))
+    vi[:, 0] = 1.0e7
+    parts = [(s, ve, None, np.arange(ne, dtype=np.uint32)),
+             (s.copy(), vi, None, np.arange(ne, 2 * ne, dtype=np.uint32))]
+    o, g = load_both(d, parts)
+    o.deposit()
+    g.deposit(0)
+    v0 = float(I.drive_voltage(d, 0))
+    o.field_solve_1d(v0)
+    g.field_solve_1d(0, v0)
+    o.leapfrog_start()
+    g.leapfrog_start(0)
+    vn = I.drive_voltage(d, np.arange(1, 41))
+    so = o.step(0, 10, vn[:10], True)
+    sg = g.step(0, 10, vn[:10], solve_field=True, sort_every=5)
+    assert so["absorbed"] == sg["absorbed"] and sg["absorbed"][0] == ne and sg["absorbed"][1] == ne
+    for sp in range(2):
+        assert len(g.read(0, sp)["id"]) == 0 and len(o.read(sp)["id"]) == 0
+    so = o.step(10, 30, vn[10:40], True)
+    sg = g.step(10, 30, vn[10:40], solve_field=True, sort_every=5)
+    assert sg["alive_start"] == [0, 0] and so["alive_start"] == sg["alive_start"]
+    q = g.deposit_read(0)
+    assert not np.any(q)
+    assert o.next_id == g.next_id(0)
+    assert np.array_equal(o.field_table(), g.field_table(0))
