@@ -205,7 +205,7 @@ def main():
                     help="instead of the benchmark, copy this many bytes 10 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (sharding across GPUs is designed, not built); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np

@@ -27,7 +27,8 @@
  *       elastic energy loss 2m/M, isotropy moments, ionization energy balance.
  *   Births / split / merge (Sec. 4.3): exact count, weight, charge identities.
  *   Adapt (Sec. 3.1, 4.3): 2:1 balance, area sum, level bounds, idempotence.
- * Readings of points the paper leaves open are listed in the design doc.
+ * Where the paper leaves a point open, the reading taken is stated at the
+ * function that implements it.
  */
 #include "oracle.h"
 
