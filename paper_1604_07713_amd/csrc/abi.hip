@@ -793,7 +793,9 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   const CgScal* scd = (const CgScal*)(sl.cg_ws + cg_scalars_offset(n));
   CgScal sc{};
   uint32_t k = 0;
-  int batch = 4;
+  // a warm-started solve takes about as many iterations as the last one:
+  // queue three quarters of that before the first read of the scalars
+  int batch = std::max(4, std::min(1024, (int)(sl.cg_iters_prev / 4u * 3u)));
   for (;;) {
     const uint32_t kend = (uint32_t)std::min<uint64_t>((uint64_t)k + (uint64_t)batch, (uint64_t)maxit_u + 1u);
     for (; k < kend; ++k)
@@ -805,6 +807,7 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
     batch = std::min(batch * 2, 64);
   }
   const int it = (int)sc.it;
+  sl.cg_iters_prev = sc.it;
   const double rr = sc.rr, bb = sc.bb;
   hip_check(launch_cell_to_corner_phi(m, sl.phi64, sl.cphi, c->stream), "cell_to_corner");
   if (sl.prec == 32) hip_check(launch_corner_field<float>(m, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner");

@@ -109,6 +109,7 @@ struct Slot {
   Stencil2D st{nullptr, nullptr, nullptr, nullptr};
   double* cg_ws = nullptr;
   bool stencil_ok = false;
+  uint32_t cg_iters_prev = 0;   // iterations of the slot's last CG solve
   // deposit, counters, stats rows, order scratch
   unsigned long long* Q = nullptr;
   uint32_t nq = 0;
