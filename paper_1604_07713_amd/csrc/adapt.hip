@@ -98,7 +98,9 @@ bool rebuild(Ctx& C, Slot& sl, Scratch& S, uint32_t* emit, const uint32_t* cflag
   uint32_t* nkey = (uint32_t*)sl.alloc(4 * (size_t)total);
   uint8_t* nlv = (uint8_t*)sl.alloc((size_t)total);
   hip_check(launch_tree_emit(view(sl), emit, cflag, nkey, nlv, maxlv, C.stream), "emit");
-  const uint32_t mx = read1(C, maxlv);
+  // the finest level present matters only when the tree may go below the
+  // point-location table; else the table is direct whatever it is
+  const uint32_t mx = sl.d.max_level <= kLutMaxLevel ? (uint32_t)sl.d.max_level : read1(C, maxlv);
   set_mesh2d_device(C, sl, nkey, nlv, total, (int)mx);
   return true;
 }

@@ -419,7 +419,7 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   // point-location table at the finest level up to 11 (4^11 + 1 entries,
   // 16 MiB): below it every lookup is one load; deeper trees finish with a
   // binary search inside the table cell
-  sl.lut_level = std::min(sl.d.max_level, 11);
+  sl.lut_level = std::min(sl.d.max_level, kLutMaxLevel);
   sl.lut_direct = maxlv <= sl.lut_level;
   sl.lut = (uint32_t*)sl.alloc(4 * ((size_t(1) << (2 * sl.lut_level)) + 1));
   hip_check(launch_leaf_xy(sl.key, sl.lv, sl.nleaves, sl.xy, C.stream), "leaf_xy");

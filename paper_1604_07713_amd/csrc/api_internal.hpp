@@ -12,6 +12,7 @@
 namespace pic {
 
 constexpr int kMaxGrid = 2048;       // default upper bound on helper-kernel grids
+constexpr int kLutMaxLevel = 11;   // finest level of the point-location table (4^11 + 1 entries)
 constexpr int kMaxStepGrid = 8192;   // upper bound on the per-slot step-kernel grid (stats rows)
 
 struct Err {
