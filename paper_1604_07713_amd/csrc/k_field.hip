@@ -408,9 +408,16 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
 // diag} [2][4 n] (a neighbour's operands are one 32-byte record, not four
 // scattered doubles), p [n], block partials of r.u, w.u and r.r
 // [2][3][grid] and of b.b [grid], then the scalars (CgScal).
+// Workgroups of a CG launch: more rows per thread on large trees, but fewer
+// partials for every workgroup to sum and fewer workgroups to dispatch
+// (avalanche solves: 12.8 us per iteration at 1024, 11.6 at 512, 12.4 at 256).
+#ifndef PIC_CG_GRID_MAX
+#define PIC_CG_GRID_MAX 512
+#endif
+static_assert(PIC_CG_GRID_MAX % kBlock == 0 && PIC_CG_GRID_MAX <= 1024, "partials are loaded kBlock at a time");
 int cg_grid(uint32_t n) {
   int g = (int)ceil_div(n, kBlock);
-  return g < 1024 ? g : 1024;
+  return g < PIC_CG_GRID_MAX ? g : PIC_CG_GRID_MAX;
 }
 int cg_ws_doubles(uint32_t n) {
   return (int)(9u * n + 7u * (uint32_t)cg_grid(n) + (uint32_t)((sizeof(CgScal) + 7) / 8));
@@ -631,7 +638,7 @@ __device__ __forceinline__ CgOut cg_row(const CgRow& a, double alpha, double bet
 // partials, of the thread's first row and of its neighbours are all issued
 // before the partials are reduced (none of them depends on alpha or beta),
 // so the launch waits about two memory latencies instead of four.
-constexpr int kCgPartLoads = 1024 / kBlock;   // cg_grid() <= 1024 workgroups
+constexpr int kCgPartLoads = PIC_CG_GRID_MAX / kBlock;   // cg_grid() <= PIC_CG_GRID_MAX workgroups
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
                                                     uint32_t k, double rtol2, uint32_t maxit) {
   const uint32_t n = m.nleaves;

@@ -157,9 +157,9 @@ def test_cg_solve_matches_oracle_and_direct():
 
 
 def test_cg_large_grid_deterministic():
-    """A 512 x 512 uniform tree (262,144 unknowns, the largest CG launch of
-    1024 workgroups): two solves from the same start give the same bits and
-    iteration count (the block partials each launch sums are not overwritten
+    """A 512 x 512 uniform tree (262,144 unknowns, a CG launch with the most
+    workgroups it takes and several rows per thread): two solves from the
+    same start give the same bits and iteration count (the block partials each launch sums are not overwritten
     by workgroups that finish early), and the true residual of the result
     meets the tolerance."""
     import scipy.sparse
