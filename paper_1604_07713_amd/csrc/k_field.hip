@@ -408,6 +408,7 @@ hipError_t launch_build_stencil(const Mesh2D& m, const Stencil2D& st, hipStream_
 // diag} [2][4 n] (a neighbour's operands are one 32-byte record, not four
 // scattered doubles), p [n], block partials of r.u, w.u and r.r
 // [2][3][grid] and of b.b [grid], then the scalars (CgScal).
+//
 // Workgroups of a CG launch: more rows per thread on large trees, but fewer
 // partials for every workgroup to sum and fewer workgroups to dispatch
 // (avalanche solves: 12.8 us per iteration at 1024, 11.6 at 512, 12.4 at 256).
@@ -636,8 +637,7 @@ __device__ __forceinline__ CgOut cg_row(const CgRow& a, double alpha, double bet
 // alpha_k and beta_k, then s_k, p_k, x_{k+1}, r_{k+1}, w_{k+1} = A u_{k+1}
 // and the partials of r.u, w.u and r.r after the update.  The loads of the
 // partials, of the thread's first row and of its neighbours are all issued
-// before the partials are reduced (none of them depends on alpha or beta),
-// so the launch waits about two memory latencies instead of four.
+// before the partials are reduced: none of them depends on alpha or beta.
 constexpr int kCgPartLoads = PIC_CG_GRID_MAX / kBlock;   // cg_grid() <= PIC_CG_GRID_MAX workgroups
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Mesh2D m, Stencil2D st, double* __restrict__ x, double* ws,
                                                     uint32_t k, double rtol2, uint32_t maxit) {
