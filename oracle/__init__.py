@@ -32,7 +32,7 @@ class Desc(C.Structure):
                 ("wall_phi", C.c_double * 4), ("particle_bc", C.c_int), ("depth_z", C.c_double),
                 ("gas_density", C.c_double), ("gas_temperature", C.c_double), ("gas_mass", C.c_double),
                 ("seed", C.c_uint64), ("instance_key", C.c_uint32), ("nspecies", C.c_int),
-                ("species", Species * 2)]
+                ("species", Species * 2), ("field_scheme", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -113,6 +113,7 @@ def make_desc(d):
         c.wall_phi[i] = float(d["wall_phi"][i])
     c.seed = int(d["seed"])
     c.instance_key = int(d["instance_key"])
+    c.field_scheme = int(d.get("field_scheme", 0))
     c.nspecies = len(d["species"])
     for i, sp in enumerate(d["species"]):
         for k in ("charge", "mass", "w0", "sigma_el", "sigma_iz", "eps_iz", "sigma_cx", "eps_max"):

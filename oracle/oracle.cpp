@@ -236,7 +236,8 @@ template <class T> struct Sim : SimBase {
   uint32_t next_id = 0;
   /* 1D */
   int N = 0;
-  std::vector<T> En;            /* node E in T (N+1) */
+  std::vector<T> En;            /* 1D: node E (momentum-conserving CIC) or cell E
+                                   (energy-conserving CIC, N values + an unused one), in T */
   std::vector<double> inv_m;    /* Thomas pivots 1/m_i, i = 1..N-1 */
   /* 2D */
   std::unique_ptr<QNode> root;
@@ -391,10 +392,31 @@ template <class T> struct Sim : SimBase {
   }
 
   /* ---------------- field gather ---------------- */
+  /* E table from the node potentials ph[0..N]: node E by centred differences
+     inside and second-order one-sided differences at the walls (momentum-
+     conserving CIC), or cell E = (ph[i] - ph[i+1]) / dx for the N cells
+     (energy-conserving CIC; e[N] unused, 0).  inv2dx = 1 / (2 dx). */
+  void node_or_cell_e(const double* ph, double inv2dx, double* e) const {
+    if (d.field_scheme == OR_FIELD_CIC_EC) {
+      const double inv_dx = 2.0 * inv2dx;
+      for (int i = 0; i < N; ++i) e[i] = (ph[i] - ph[i + 1]) * inv_dx;
+      e[N] = 0.0;
+      return;
+    }
+    e[0] = ((3.0 * ph[0] - 4.0 * ph[1]) + ph[2]) * inv2dx;
+    for (int i = 1; i < N; ++i) e[i] = (ph[i - 1] - ph[i + 1]) * inv2dx;
+    e[N] = ((-3.0 * ph[N] + 4.0 * ph[N - 1]) - ph[N - 2]) * inv2dx;
+  }
+
+  /* Momentum-conserving CIC: E interpolated linearly between the cell's two
+     nodes (the same weights that assign its charge).  Energy-conserving CIC:
+     the E of the particle's cell, the difference of its two node potentials
+     (the derivative of the linear assignment function), Sec. 3. */
   T gather1d(T s) const {
     T g = s * (T)N;
     int64_t i = (int64_t)std::floor(g);
     if (i > N - 1) i = N - 1;
+    if (d.field_scheme == OR_FIELD_CIC_EC) return En[i];
     T f = g - (T)i;
     return En[i] + f * (En[i + 1] - En[i]);
   }
@@ -611,9 +633,7 @@ template <class T> struct Sim : SimBase {
     for (int i = N - 2; i >= 1; --i) ph[i] = dp[i] + inv_m[i] * ph[i + 1];
     double inv2dx = 1.0 / (2.0 * (d.length / N));
     std::vector<double> e(N + 1);
-    e[0] = ((3.0 * ph[0] - 4.0 * ph[1]) + ph[2]) * inv2dx;
-    for (int i = 1; i < N; ++i) e[i] = (ph[i - 1] - ph[i + 1]) * inv2dx;
-    e[N] = ((-3.0 * ph[N] + 4.0 * ph[N - 1]) - ph[N - 2]) * inv2dx;
+    node_or_cell_e(ph.data(), inv2dx, e.data());
     for (int i = 0; i <= N; ++i) {
       En[i] = (T)e[i];
       if (phi) phi[i] = ph[i];
@@ -1014,7 +1034,9 @@ void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]
 
 void* or_create(const or_desc* d) {
   if (!d || (d->dim != 1 && d->dim != 2) || (d->precision != 32 && d->precision != 64) ||
-      d->nspecies < 1 || d->nspecies > 2 || !(d->length > 0) || !(d->dt > 0))
+      d->nspecies < 1 || d->nspecies > 2 || !(d->length > 0) || !(d->dt > 0) ||
+      (d->field_scheme != OR_FIELD_CIC_EM && d->field_scheme != OR_FIELD_CIC_EC) ||
+      (d->dim == 2 && d->field_scheme != OR_FIELD_CIC_EM))   /* CIC is for the uniform mesh */
     return nullptr;
   SimBase* b;
   bool ok;
@@ -1083,11 +1105,9 @@ int or_field_set(void* h, int kind, const double* data) {
       }
       if (kind == OR_NODE_PHI_1D) {
         double inv2dx = 1.0 / (2.0 * (S.d.length / S.N));
-        const double* ph = data;
-        int N = S.N;
-        S.En[0] = (T)(((3.0 * ph[0] - 4.0 * ph[1]) + ph[2]) * inv2dx);
-        for (int i = 1; i < N; ++i) S.En[i] = (T)((ph[i - 1] - ph[i + 1]) * inv2dx);
-        S.En[N] = (T)(((-3.0 * ph[N] + 4.0 * ph[N - 1]) - ph[N - 2]) * inv2dx);
+        std::vector<double> e(S.N + 1);
+        S.node_or_cell_e(data, inv2dx, e.data());
+        for (int i = 0; i <= S.N; ++i) S.En[i] = (T)e[i];
         return OR_OK;
       }
       return OR_E_ARG;

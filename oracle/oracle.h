@@ -35,6 +35,8 @@ enum { OR_OK = 0, OR_E_ARG = -1, OR_E_CAPACITY = -3, OR_E_STATE = -5 };
 enum { OR_MCC_NONE = 0, OR_MCC_ELECTRON = 1, OR_MCC_ION_CX = 2 };
 enum { OR_WALL_NEUMANN = 0, OR_WALL_DIRICHLET = 1 };
 enum { OR_ABSORB = 0, OR_REFLECT = 1 };
+/* 1D particle-field coupling, both with CIC charge assignment to nodes (Sec. 3) */
+enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1 };
 /* field kinds for or_field_set */
 enum { OR_NODE_E_1D = 0, OR_NODE_PHI_1D = 1, OR_CORNER_PHI_2D = 2, OR_CORNER_E_2D = 3, OR_CELL_PHI_2D = 4 };
 
@@ -63,6 +65,8 @@ typedef struct {
   uint64_t seed; uint32_t instance_key;
   int nspecies;      /* 1 or 2: [0] electrons, [1] ions */
   or_species species[2];
+  int field_scheme;  /* 1D: OR_FIELD_CIC_EM (node E, linear gather) or
+                        OR_FIELD_CIC_EC (cell E, the particle's cell value) */
 } or_desc;
 
 typedef struct {

@@ -30,6 +30,7 @@ TORR = 101325.0 / 760.0
 MCC_NONE, MCC_ELECTRON, MCC_ION_CX = 0, 1, 2
 WALL_NEUMANN, WALL_DIRICHLET = 0, 1
 ABSORB, REFLECT = 0, 1
+FIELD_CIC_EM, FIELD_CIC_EC = 0, 1   # 1D particle-field coupling (momentum- or energy-conserving CIC)
 
 
 def species(charge, mass, w0=1.0, mcc=MCC_NONE, sigma_el=0.0, sigma_iz=0.0, eps_iz=0.0,
@@ -44,7 +45,7 @@ def base_desc(**kw):
              base_level=0, refine_disk=0, disk_cx=0.5, disk_cy=0.5, disk_r=0.0, disk_level=0,
              field_bc=[WALL_NEUMANN] * 4, wall_phi=[0.0] * 4, particle_bc=ABSORB, depth_z=1.0,
              gas_density=0.0, gas_temperature=300.0, gas_mass=40.0 * AMU, seed=0, instance_key=0,
-             species=[])
+             species=[], field_scheme=FIELD_CIC_EM)
     d.update(kw)
     return d
 

@@ -149,3 +149,59 @@ def test_cold_plasma_oscillation():
     # the uncorrected plasma frequency is measurably off, so the grid factor matters
     assert abs(2.0 / dt * math.asin(wp * dt / 2) / w_expect - 1) > 2e-4
     assert abs(amp[0] - delta) < 1e-9
+
+
+def _closed_plasma_energy(scheme, nsteps=3000, ncells=32, ppc=64, dx_over_debye=5.0, wpdt=0.1, seed=3):
+    """Total energy (electron kinetic + field, per m^2) of a warm electron
+    plasma over fixed ions between grounded walls with reflecting particles,
+    sampled every nsteps / 10 steps.  The field energy is
+    eps0/2 sum_c (phi_c+1 - phi_c)^2 / dx, which equals rho.phi/2 for the
+    discrete Poisson problem with phi = 0 on both walls."""
+    eps0 = 8.8541878128e-12
+    L = 0.01
+    dx = L / ncells
+    n0 = 1e14
+    wp = np.sqrt(n0 * I.E_CHARGE ** 2 / (eps0 * I.M_ELECTRON))
+    kT = (dx / dx_over_debye) ** 2 * n0 * I.E_CHARGE ** 2 / eps0
+    npart = ncells * ppc
+    w0 = n0 * L / npart
+    e = I.species(-I.E_CHARGE, I.M_ELECTRON, w0, I.MCC_NONE)
+    ion = I.species(I.E_CHARGE, 1e12 * I.AMU, w0, I.MCC_NONE)   # immobile
+    d = I.base_desc(dim=1, precision=64, length=L, dt=wpdt / wp, ncells=ncells, particle_bc=I.REFLECT,
+                    species=[e, ion], field_scheme=scheme)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = ((np.arange(npart) + 0.5) / npart)[:, None]
+    v = rng.normal(0.0, np.sqrt(kT / I.M_ELECTRON), (npart, 3))
+    o = oracle.Oracle(d)
+    o.load(0, s, v, None, np.arange(npart, dtype=np.uint32))
+    o.load(1, s.copy(), np.zeros((npart, 3)), None, np.arange(npart, 2 * npart, dtype=np.uint32))
+    o.deposit()
+    o.field_solve_1d(0.0)
+    o.leapfrog_start()
+
+    def energy():
+        r = o.read(0)
+        ke = 0.5 * I.M_ELECTRON * np.sum(w0 * r["w"] / 65536.0 * np.sum(r["v"] ** 2, axis=1))
+        o.deposit()
+        phi, _ = o.field_solve_1d(0.0)
+        return ke + 0.5 * eps0 * np.sum(np.diff(phi) ** 2) / dx
+
+    out = [energy()]
+    chunk = nsteps // 10
+    for k in range(10):
+        o.step(k * chunk, chunk, np.zeros(chunk), True)
+        out.append(energy())
+    return np.array(out) / out[0]
+
+
+def test_energy_conserving_cic_holds_energy_where_momentum_conserving_heats():
+    """Grid heating (Sec. 3, CIC-EM / CIC-EC): with a cell five Debye lengths
+    wide, the momentum-conserving scheme (linear gather of node E) heats the
+    plasma steadily, while the energy-conserving scheme (the particle's cell
+    E, the derivative of its linear charge assignment) keeps the total energy
+    to the leapfrog's small oscillation.  A wrong sign, cell or interpolation
+    in the energy-conserving gather breaks the second bound."""
+    em = _closed_plasma_energy(I.FIELD_CIC_EM)
+    ec = _closed_plasma_energy(I.FIELD_CIC_EC)
+    assert em[-1] > 1.04 and np.all(np.diff(em) > 0)   # monotone heating, > 4 % over ~48 plasma periods
+    assert np.max(np.abs(ec - 1.0)) < 2e-3
