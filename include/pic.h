@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 
 typedef struct pic_ctx_s* pic_ctx;
 
@@ -64,6 +64,12 @@ enum pic_status {
 enum { PIC_MCC_NONE = 0, PIC_MCC_ELECTRON = 1, PIC_MCC_ION_CX = 2 };
 enum { PIC_WALL_NEUMANN = 0, PIC_WALL_DIRICHLET = 1 };
 enum { PIC_ABSORB = 0, PIC_REFLECT = 1 };
+/* Particle-field coupling on the uniform 1D mesh (Sec. 3), both with CIC
+ * charge assignment to the nodes: momentum-conserving (the particle's E is
+ * interpolated linearly between its cell's node E values) or energy-
+ * conserving (the particle takes its cell's E, the difference of the cell's
+ * two node potentials over dx; the field table then holds N cell values). */
+enum { PIC_FIELD_CIC_EM = 0, PIC_FIELD_CIC_EC = 1 };
 enum { PIC_FP32 = 32, PIC_FP64 = 64 };
 /* field kinds for pic_field_set */
 enum {
@@ -109,6 +115,8 @@ typedef struct {
   int64_t capacity[2];  /* particle slots per species; 0 = sized from the load
                            (3x the loaded count + 4096 when ionizing); grows to
                            2x the projected need between chunks of steps       */
+  int field_scheme;     /* 1D: PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC; 2D: must be
+                           PIC_FIELD_CIC_EM (NGP deposit, bilinear gather)      */
 } pic_instance_desc;
 
 typedef struct {

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 _LIB = None
 
 PIC_OK, PIC_E_ARG, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+FIELD_CIC_EM, FIELD_CIC_EC = 0, 1   # 1D particle-field coupling (include/pic.h)
+ABI_VERSION = 2                     # PIC_ABI_VERSION of include/pic.h
 NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D = 0, 1, 2, 3, 4
 
 
@@ -43,7 +45,7 @@ class InstanceDesc(C.Structure):
                 ("wall_phi", C.c_double * 4), ("particle_bc", C.c_int), ("depth_z", C.c_double),
                 ("gas_density", C.c_double), ("gas_temperature", C.c_double), ("gas_mass", C.c_double),
                 ("seed", C.c_uint64), ("instance_key", C.c_uint32), ("nspecies", C.c_int),
-                ("species", SpeciesDesc * 2), ("capacity", C.c_int64 * 2)]
+                ("species", SpeciesDesc * 2), ("capacity", C.c_int64 * 2), ("field_scheme", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -160,6 +162,8 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.pic_abi_version() != ABI_VERSION:   # the structures below must match the library's
+            raise LibraryMissing(f"{LIB_PATH} has ABI {L.pic_abi_version()}, this binding {ABI_VERSION}; rebuild")
         _LIB = L
     return _LIB
 
@@ -189,6 +193,7 @@ def make_desc(d, capacity=(0, 0)):
     cap = d.get("capacity", capacity)
     c.capacity[0] = int(cap[0])
     c.capacity[1] = int(cap[1])
+    c.field_scheme = int(d.get("field_scheme", FIELD_CIC_EM))
     return c
 
 

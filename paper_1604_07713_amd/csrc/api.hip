@@ -391,6 +391,10 @@ void validate(const pic_instance_desc& d) {
   if (d.dim == 2 && (d.min_level < 0 || d.max_level > 14 || d.min_level > d.max_level || d.base_level < d.min_level ||
                      d.base_level > d.max_level))
     throw Err(PIC_E_ARG, "2D levels must satisfy 0 <= min <= base <= max <= 14");
+  if (d.field_scheme != PIC_FIELD_CIC_EM && d.field_scheme != PIC_FIELD_CIC_EC)
+    throw Err(PIC_E_ARG, "field_scheme must be PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC");
+  if (d.dim == 2 && d.field_scheme != PIC_FIELD_CIC_EM)
+    throw Err(PIC_E_ARG, "the energy-conserving coupling is for the uniform 1D mesh");
   for (int s = 0; s < d.nspecies; ++s) {
     const pic_species_desc& sp = d.species[s];
     if (!(sp.mass > 0)) throw Err(PIC_E_ARG, "species mass must be positive");
@@ -625,6 +629,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.kappa[0] = sl.kappa[0];
   I.kappa[1] = sl.kappa[1];
   I.inv2dx = sl.inv2dx;
+  I.cell_e = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_CIC_EC ? 1 : 0;
   I.phi64 = sl.phi64;
   I.e64 = sl.e64;
   return I;

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
   const double h2 = I.inv2dx;
   for (int i = threadIdx.x; i <= N; i += blockDim.x) {
     double e;
-    if (i == 0) e = ((3.0 * b[0] - 4.0 * b[1]) + b[2]) * h2;
+    if (I.cell_e) e = i < N ? (b[i] - b[i + 1]) * (2.0 * h2) : 0.0;   // cell E (energy-conserving)
+    else if (i == 0) e = ((3.0 * b[0] - 4.0 * b[1]) + b[2]) * h2;
     else if (i == N) e = ((-3.0 * b[N] + 4.0 * b[N - 1]) - b[N - 2]) * h2;
     else e = (b[i - 1] - b[i + 1]) * h2;
     E[i] = (T)e;
@@ -164,14 +165,17 @@ hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mod
   return hipGetLastError();
 }
 
-// node E (or node potential -> E) given by the caller, rounded to T
+// node E (or node potential -> E) given by the caller, rounded to T; with
+// the energy-conserving coupling the table holds cell E (N values, then 0)
 template <class T>
-__global__ void k_node_e_1d(T* E, double* e64, const double* data, int is_phi, int N, double inv2dx) {
+__global__ void k_node_e_1d(T* E, double* e64, const double* data, int is_phi, int N, double inv2dx, int cell_e) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > N) return;
   double e;
   if (!is_phi) {
     e = data[i];
+  } else if (cell_e) {
+    e = i < N ? (data[i] - data[i + 1]) * (2.0 * inv2dx) : 0.0;
   } else if (i == 0) {
     e = ((3.0 * data[0] - 4.0 * data[1]) + data[2]) * inv2dx;
   } else if (i == N) {
@@ -186,7 +190,7 @@ __global__ void k_node_e_1d(T* E, double* e64, const double* data, int is_phi, i
 template <class T>
 hipError_t launch_node_e_1d(const InstDev<T>& I, const double* data, int is_phi, hipStream_t s) {
   hipLaunchKernelGGL(k_node_e_1d<T>, dim3(ceil_div(I.N + 1, kBlock)), dim3(kBlock), 0, s, const_cast<T*>(I.E),
-                     I.e64, data, is_phi, I.N, I.inv2dx);
+                     I.e64, data, is_phi, I.N, I.inv2dx, I.cell_e);
   return hipGetLastError();
 }
 

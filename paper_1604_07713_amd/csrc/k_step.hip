@@ -289,6 +289,7 @@ struct HotK {
   const uint32_t* lut;
   int N, lut_level;
   bool reflect;
+  bool cell_e;   // 1D energy-conserving coupling: the cell's E, no interpolation
   uint32_t nq, key0, key1;
   SpeciesK<T> k;
 };
@@ -302,6 +303,7 @@ __device__ __forceinline__ HotK<T> hot_constants(const InstDev<T>& I, int sp) {
   h.N = I.N;
   h.lut_level = I.lut_level;
   h.reflect = I.particle_bc == PIC_REFLECT;
+  h.cell_e = I.cell_e != 0;
   h.nq = I.nq;
   h.key0 = I.key0;
   h.key1 = I.key1;
@@ -464,7 +466,7 @@ __device__ __forceinline__ bool push_one(const HotK<T>& H, const SpPtr<T>& P, ui
     int ic = (int)floor(g);
     if (ic > H.N - 1) ic = H.N - 1;
     const T fr = g - (T)ic;
-    const T E = f.e0 + fr * (f.e1 - f.e0);
+    const T E = H.cell_e ? f.e0 : f.e0 + fr * (f.e1 - f.e0);   // uniform over the launch
     p.v0 = p.v0 + k.qm_dt * E;
     p.s0 = p.s0 + p.v0 * k.dt_L;
     ok = wall_rule<T>(H.reflect, p.s0, p.v0, lost);
@@ -1351,7 +1353,8 @@ __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
         int ic = (int)floor(g);
         if (ic > I.N - 1) ic = I.N - 1;
         const T f = g - (T)ic;
-        const T E = G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]);
+        // the step loop's gather: the cell's E (energy-conserving) or linear between nodes
+        const T E = I.cell_e ? G(I.E)[ic] : G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]);
         G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * E;
       } else {
         T ex, ey;

@@ -87,6 +87,7 @@ struct InstDev {
   const double* inv_m;           // 1D Thomas pivots 1/m_i (i = 1..N-1)
   double kappa[2];               // charge-sum -> Poisson right-hand side factor per species
   double inv2dx;                 // 1D: 1 / (2 dx)
+  int cell_e;                    // 1D energy-conserving coupling: E holds cell values, gathered without interpolation
   double* phi64;                 // 1D: node potential; 2D: cell potential
   double* e64;                   // 1D: node E; 2D: corner E [nleaves][8]
 };

@@ -43,7 +43,20 @@ def start(ctx_or_oracles, descs, gpu):
 
 @pytest.mark.parametrize("precision,graph", [(32, 0), (32, 10), (64, 0)])
 def test_batched_ensemble_matches_oracle(precision, graph):
+    check_against_oracle(small_ensemble(precision=precision), precision, graph)
+
+
+@pytest.mark.parametrize("precision,graph", [(32, 10), (64, 0)])
+def test_batched_mixed_field_schemes(precision, graph):
+    """Every other instance uses the energy-conserving coupling (cell E,
+    no interpolation): the batched launch honours each instance's scheme."""
     descs = small_ensemble(precision=precision)
+    for j in range(1, len(descs), 2):
+        descs[j]["field_scheme"] = I.FIELD_CIC_EC
+    check_against_oracle(descs, precision, graph)
+
+
+def check_against_oracle(descs, precision, graph):
     nsteps = 60
     vn = np.stack([I.drive_voltage(d, np.arange(1, nsteps + 1)) for d in descs], axis=1)   # [k][slot]
     g = B.Context(descs)

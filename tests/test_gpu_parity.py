@@ -121,6 +121,21 @@ def test_ccp_400_steps_free_running(precision):
     assert np.array_equal(o.field_table(), g.field_table(0))
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_ccp_energy_conserving_coupling(precision):
+    """The CCP discharge with the energy-conserving coupling (the particle
+    takes its cell's E): 400 steps free running against the oracle."""
+    d = I.ccp_desc(precision=precision)
+    d["field_scheme"] = I.FIELD_CIC_EC
+    o, g, so, sg = ccp_run_both(d, 400, sort_every=20)
+    for k in ("alive_start", "absorbed", "elastic", "ionization", "cx", "births"):
+        assert so[k] == sg[k], (k, so[k], sg[k])
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), TOL[precision], f"species {sp}")
+    assert o.next_id == g.next_id(0)
+    assert np.array_equal(o.field_table(), g.field_table(0))
+
+
 def test_ccp_binned_births_ranking():
     """The CCP discharge for 200 steps with the births ranked through id bins
     on the GPU: the same newborn ids, hence the same particles, as the
