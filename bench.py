@@ -133,15 +133,20 @@ def ensemble_bench(nsteps, ninst=96, tune=True):
     """Batched ensemble of 1D CCP instances (config-0 physics, 96 uneven
     meshes): the FP32 batched path (one persistent launch per step, graph
     replay, autotuned work items) vs the FP64 plain path (per-instance
-    launches), both with the on-device field solve."""
+    launches), both with the on-device field solve; and the batched path
+    again with the energy-conserving coupling (cell E, no interpolation)."""
     import numpy as np
     import torch
     from paper_1604_07713_amd import autotune
     from paper_1604_07713_amd import binding as B
     from paper_1604_07713_amd import inputs as I
     out = {}
-    for mode, prec in (("batched", 32), ("plain", 64)):
+    tuned_batched = None
+    for mode, prec in (("batched", 32), ("plain", 64), ("batched_energy_conserving", 32)):
         descs = I.ensemble_descs(count=ninst, precision=prec)
+        if mode == "batched_energy_conserving":
+            for d in descs:
+                d["field_scheme"] = I.FIELD_CIC_EC
         vtab = np.stack([I.drive_voltage(d, np.arange(1, 4000)) for d in descs], axis=1)
 
         def make():
@@ -158,11 +163,15 @@ def ensemble_bench(nsteps, ninst=96, tune=True):
         tuned = None
         if mode == "batched":
             tuned = autotune.tune(make, descs, vtab) if tune else dict(tile=4096, grid=2048)
+            tuned_batched = tuned
+        elif mode == "batched_energy_conserving":
+            tuned = tuned_batched   # same ensemble, same launch shape
+        if tuned:
             kw.update(batched=tuned["tile"], grid=tuned["grid"])
         g.step(0, 10, vtab[:10], **kw)          # warm-up
         st = g.step(10, nsteps, vtab[10:10 + nsteps], timing=True, **kw)
         kern = st["loop_ms"]
-        if mode == "batched":
+        if mode != "plain":
             kw["graph_steps"] = 25
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -173,7 +182,7 @@ def ensemble_bench(nsteps, ninst=96, tune=True):
         out[mode] = dict(precision=f"fp{prec}", updates_per_s=upd / dt, ms_per_step=dt * 1e3 / nsteps,
                          births_per_step=st2["births"] / nsteps,
                          loop_kernel_ms_per_step=kern / nsteps, particles=upd // nsteps,
-                         launch="one persistent launch per step, HIP graph of 25 steps" if mode == "batched"
+                         launch="one persistent launch per step, HIP graph of 25 steps" if mode != "plain"
                          else "per-instance launches")
         if tuned:
             out[mode]["tile"] = tuned["tile"]
