@@ -78,12 +78,15 @@ def test_quadtree_full_size_sampled():
     assert np.array_equal(host_locate(gkeys, gr["s"]), gr["cell"].astype(np.int64))
 
 
-def test_ensemble_full_size_sampled():
+@pytest.mark.parametrize("scheme", [I.FIELD_CIC_EM, I.FIELD_CIC_EC])
+def test_ensemble_full_size_sampled(scheme):
     """The 96-instance ensemble at full size, batched FP32 with graph replay
-    (work items of 4096 particles, 2048 workgroups): three whole instances
-    (smallest, median and largest) equal the oracle's run, and every instance
-    keeps its charge units."""
+    (work items of 4096 particles, 2048 workgroups), with either 1D coupling:
+    three whole instances (smallest, median and largest) equal the oracle's
+    run, and every instance keeps its charge units."""
     descs = I.ensemble_descs(count=96, precision=32)
+    for d in descs:
+        d["field_scheme"] = scheme
     nsteps = 20
     vn = np.stack([I.drive_voltage(d, np.arange(1, nsteps + 1)) for d in descs], axis=1)
     g = B.Context(descs)
