@@ -129,7 +129,7 @@ def cpu_baseline(nparticles, nsteps, seed=2):
                        f"FP32-mirror oracle, {dt:.1f} s")
 
 
-def ensemble_bench(nsteps, ninst=96, tune=True):
+def ensemble_bench(nsteps, ninst=96, tune=True, modes=("batched", "plain", "batched_energy_conserving"), shape=None):
     """Batched ensemble of 1D CCP instances (config-0 physics, 96 uneven
     meshes): the FP32 batched path (one persistent launch per step, graph
     replay, autotuned work items) vs the FP64 plain path (per-instance
@@ -142,7 +142,9 @@ def ensemble_bench(nsteps, ninst=96, tune=True):
     from paper_1604_07713_amd import inputs as I
     out = {}
     tuned_batched = None
-    for mode, prec in (("batched", 32), ("plain", 64), ("batched_energy_conserving", 32)):
+    precs = {"batched": 32, "plain": 64, "batched_energy_conserving": 32}
+    for mode in modes:
+        prec = precs[mode]
         descs = I.ensemble_descs(count=ninst, precision=prec)
         if mode == "batched_energy_conserving":
             for d in descs:
@@ -161,11 +163,14 @@ def ensemble_bench(nsteps, ninst=96, tune=True):
         g = make()
         kw = dict(solve_field=True, sort_every=20)
         tuned = None
-        if mode == "batched":
-            tuned = autotune.tune(make, descs, vtab) if tune else dict(tile=4096, grid=2048)
+        if mode != "plain":
+            if shape:
+                tuned = dict(tile=shape[0], grid=shape[1])
+            elif tuned_batched:
+                tuned = tuned_batched   # same ensemble, same launch shape
+            else:
+                tuned = autotune.tune(make, descs, vtab) if tune else dict(tile=4096, grid=2048)
             tuned_batched = tuned
-        elif mode == "batched_energy_conserving":
-            tuned = tuned_batched   # same ensemble, same launch shape
         if tuned:
             kw.update(batched=tuned["tile"], grid=tuned["grid"])
         g.step(0, 10, vtab[:10], **kw)          # warm-up
@@ -188,7 +193,8 @@ def ensemble_bench(nsteps, ninst=96, tune=True):
             out[mode]["tile"] = tuned["tile"]
             out[mode]["grid"] = tuned["grid"]
         g.close()
-    out["batched_over_plain"] = out["batched"]["updates_per_s"] / out["plain"]["updates_per_s"]
+    if "batched" in out and "plain" in out:
+        out["batched_over_plain"] = out["batched"]["updates_per_s"] / out["plain"]["updates_per_s"]
     return out
 
 
@@ -210,6 +216,10 @@ def main():
     ap.add_argument("--only-streamer", action="store_true", help="measure only the streamer (profiling)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--only-ensemble", action="store_true", help="measure only the ensemble (profiling)")
+    ap.add_argument("--ensemble-modes", default="batched,plain,batched_energy_conserving",
+                    help="comma-separated ensemble modes to run with --only-ensemble")
+    ap.add_argument("--tile", type=int, default=0, help="batched work-item size (with --grid: skip the autotuner)")
+    ap.add_argument("--grid", type=int, default=0, help="batched persistent grid (with --tile)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="instead of the benchmark, copy this many bytes 10 times (counter calibration)")
     args = ap.parse_args()
@@ -233,7 +243,10 @@ def main():
     from paper_1604_07713_amd import binding as B
     from paper_1604_07713_amd import inputs as I
     if args.only_ensemble:
-        print(json.dumps({"ensemble": ensemble_bench(args.ensemble_steps, tune=False)}), flush=True)
+        shape = (args.tile, args.grid) if args.tile and args.grid else None
+        print(json.dumps({"ensemble": ensemble_bench(args.ensemble_steps, tune=False,
+                                                     modes=tuple(args.ensemble_modes.split(",")),
+                                                     shape=shape)}), flush=True)
         return
     if args.only_streamer:
         print(json.dumps({"streamer": streamer_bench(args.streamer_steps)}), flush=True)

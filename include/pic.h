@@ -34,9 +34,20 @@
  *  - Particle storage order on the device is unspecified; results (ids,
  *    states, deposits) do not depend on it.  Reads return particles sorted by
  *    id.
- *  - A device-side capacity overflow (births or split copies beyond the
- *    reserved slots, or u32 id exhaustion) returns PIC_E_CAPACITY; the
- *    instance is then in an error state (PIC_E_STATE on further steps).
+ *  - Capacity (Sec. 4.3: ionization multiplies the particles
+ *    exponentially).  A step of an ionizing instance starts only with room
+ *    for its worst case of births (every electron alive ionizing once); a
+ *    step without that room is not run, so the instance stays at its last
+ *    committed step.  pic_step then grows the buffers on the host and goes
+ *    on from there: the draws depend only on (particle id, step), so the
+ *    result is bit-identical to a run that never stopped.  When the room
+ *    cannot be made (the slot's memory limit, the 4 GiB per-array limit,
+ *    device memory, u32 particle ids), pic_step returns PIC_E_CAPACITY (or
+ *    PIC_E_NOMEM) with every slot at its last committed step
+ *    (pic_step_index tells which); the caller may free memory or raise the
+ *    limit and call again with step0 = -1 for the remaining steps.
+ *    PIC_E_STATE marks a slot whose device-side overflow guard fired
+ *    anyway (not expected: the room check rules it out).
  */
 #ifndef PIC_H
 #define PIC_H
@@ -47,7 +58,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 2
+#define PIC_ABI_VERSION 3
 
 typedef struct pic_ctx_s* pic_ctx;
 
@@ -71,13 +82,15 @@ enum { PIC_ABSORB = 0, PIC_REFLECT = 1 };
  * two node potentials over dx; the field table then holds N cell values). */
 enum { PIC_FIELD_CIC_EM = 0, PIC_FIELD_CIC_EC = 1 };
 enum { PIC_FP32 = 32, PIC_FP64 = 64 };
-/* field kinds for pic_field_set */
+/* field kinds for pic_field_set (Sec. 3: potential at cell centres or nodes,
+ * E at the nodes for the gather) */
 enum {
-  PIC_NODE_E_1D = 0,     /* double[ncells+1]: E at the nodes, V/m            */
+  PIC_NODE_E_1D = 0,     /* double[ncells+1]: E at the nodes, V/m (momentum-conserving slots only) */
   PIC_NODE_PHI_1D = 1,   /* double[ncells+1]: potential at the nodes, V      */
   PIC_CORNER_PHI_2D = 2, /* double[nleaves][4]: potential at leaf corners     */
   PIC_CORNER_E_2D = 3,   /* double[nleaves][4][2]: nodal E at leaf corners    */
-  PIC_CELL_PHI_2D = 4    /* double[nleaves]: cell-centre potential            */
+  PIC_CELL_PHI_2D = 4,   /* double[nleaves]: cell-centre potential            */
+  PIC_CELL_E_1D = 5      /* double[ncells]: E of each cell, V/m (energy-conserving slots only) */
 };
 /* corner order of a leaf: 0 = (x0,y0), 1 = (x1,y0), 2 = (x0,y1), 3 = (x1,y1) */
 
@@ -112,11 +125,22 @@ typedef struct {
   uint32_t instance_key;
   int nspecies;         /* 1 or 2: [0] electrons, [1] ions (births need both)    */
   pic_species_desc species[2];
-  int64_t capacity[2];  /* particle slots per species; 0 = sized from the load
-                           (3x the loaded count + 4096 when ionizing); grows to
-                           2x the projected need between chunks of steps       */
+  int64_t capacity[2];  /* particle slots per species at load: this many (at
+                           least the loaded count, rounded up to 256), or 0 =
+                           3x the loaded count + 4096 when ionizing, else the
+                           count; pic_step grows them as births need room     */
   int field_scheme;     /* 1D: PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC; 2D: must be
                            PIC_FIELD_CIC_EM (NGP deposit, bilinear gather)      */
+  /* 2D explicit tree (Sec. 3.1: cell-based quadtree; nleaves > 0 selects it,
+     base_level and the disk refinement are then ignored): leaf_keys[nleaves]
+     the Morton code of each leaf's low corner in 16-bit units (x in the even
+     bits), leaf_levels[nleaves] its level, in Morton order.  The leaves must
+     tile the square, lie within [min_level, max_level] and be 2:1 balanced
+     across faces and corners (ghost cells at +-1 level, Sec. 3.1), else
+     PIC_E_ARG.  Host arrays, read only during the call that builds the slot. */
+  const uint32_t* leaf_keys;
+  const uint8_t* leaf_levels;
+  int64_t nleaves;
 } pic_instance_desc;
 
 typedef struct {
@@ -128,6 +152,7 @@ typedef struct {
   double loop_ms;               /* summed duration of the timed particle-loop launches (timing != 0) */
   double step_ms;               /* wall duration of the call on the stream (timing != 0) */
   int64_t loop_launches;        /* particle-loop launches timed in loop_ms               */
+  int64_t room_stops;           /* times a slot stopped for want of room and was grown   */
 } pic_step_stats;
 
 typedef struct {
@@ -176,42 +201,103 @@ typedef struct {
   void* user;
 } pic_allocator;
 
-/* Route the particle, mesh, field and adaptation-scratch memory of a context
- * through 'a' (NULL: hipMalloc with the library's own block cache).  Only on
- * a context that holds no instance yet (build with ninst = 0, then
- * pic_admit): else PIC_E_STATE.  The allocator must outlive the context. */
-int pic_set_allocator(pic_ctx c, const pic_allocator* a);
+/* ---- the five calls of the particle loop ---- */
 
 /* Build a context holding ninst >= 0 instances (slots 0..ninst-1; more can be
- * admitted later with pic_admit): uniform 1D mesh,
- * or quadtree (uniform at base_level, optional disk refinement, 2:1 balance
- * across faces and corners; Sec. 3.1).  'stream' is a hipStream_t (NULL =
- * default stream).  On success *out owns all device state. */
+ * admitted later with pic_admit).  Mesh (Sec. 3.1: one cell-based grid for
+ * particle movement, collisions and output): a uniform 1D mesh of ncells, or
+ * a quadtree uniform at base_level with optional disk refinement and 2:1
+ * balance across faces and corners (ghost cells at +-1 level for direct and
+ * diagonal neighbours, Sec. 3.1), or an explicit tree (leaf_keys).
+ * descs[ninst] are host structs, read during the call.  'stream' is a
+ * hipStream_t (NULL = default stream).  On success *out owns all device
+ * state (free it with pic_destroy).  Errors: PIC_E_ARG for an invalid
+ * descriptor (levels, explicit tree, species), PIC_E_NOMEM, PIC_E_HIP. */
 int pic_mesh_build(const pic_instance_desc* descs, int ninst, void* stream, pic_ctx* out);
 
-/* Replace the particles of one species of one slot with n host particles:
- * s[n*dim] normalised positions in [0,1), v[n*3] m/s, w[n] (NULL: 2^16 each),
- * id[n] (NULL: 0..n-1).  Values are rounded to the slot's precision.
- * PIC_E_ARG if a position is outside [0,1). */
+/* Replace the particles of one species of one slot (Sec. 3: super-particles
+ * of the species; Sec. 3.1: each is kept in the leaf that contains it) with
+ * n host particles: s[n*dim] normalised positions in [0,1), v[n*3] m/s, w[n]
+ * (NULL: 2^16 each, i.e. w0 real particles), id[n] (NULL: 0..n-1).  Values
+ * are rounded to the slot's precision; the arrays are copied.  PIC_E_ARG if
+ * a position is outside [0,1) or a weight is 0. */
 int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double* s, const double* v,
                        const uint32_t* w, const uint32_t* id);
 
-/* Set the field table the gather reads (see the PIC_*_1D/2D kinds).  2D nodal
- * E is the mean over the leaves having the node as a corner of their
- * corner gradients (Sec. 3, bilinear gather from nodal E). */
-int pic_field_set(pic_ctx c, int slot, int kind, const double* data);
-
-/* v <- v - (q dt / 2m) E(x): start the leapfrog from the current field. */
-int pic_leapfrog_start(pic_ctx c, int slot);
-
-/* Advance nsteps steps: gather, push, walls, locate, MCC with births, deposit
- * (Sec. 3, 3.1, 4.3) for the selected slots; stats are summed over slots. */
+/* Advance nsteps steps of the selected slots (Sec. 3 explicit PIC with MCC,
+ * Sec. 3.1 particle tracking on the tree, Sec. 4.3 ionization births): per
+ * particle gather E, leapfrog push, wall rule, locate the cell, null-
+ * collision MCC with births, deposit to the charge sums.  a (host struct,
+ * read during the call) selects slots, launch shape, field solve and
+ * timing; stats (nullable) receives counts summed over the slots.  Capacity
+ * as in the conventions above (PIC_E_CAPACITY / PIC_E_NOMEM leave every
+ * slot at its last committed step).  PIC_E_ARG for bad arguments,
+ * PIC_E_STATE for a slot without particles or in an error state. */
 int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats);
 
-/* Deposit the current particles (CIC to nodes in 1D, NGP to leaves in 2D) and
- * copy the per-species integer charge sums to q_out[2][nq] (may be NULL).  1D
- * units: w_units * 2^F (F = 24 FP32, 32 FP64); 2D: w_units. */
-int pic_deposit(pic_ctx c, int slot, uint64_t* q_out);
+/* Deposit the current particles (Sec. 3: CIC to the nodes of the uniform 1D
+ * mesh, NGP to the leaf cells of the quadtree; Sec. 3.1: no per-level volume
+ * weighting) and copy out, each nullable:
+ *   q_out[2][nq]  per-species integer charge sums, in weight units (2D:
+ *                 w_units; 1D: w_units * 2^F, F = 24 FP32, 32 FP64);
+ *   rho_out[nq]   charge density, C/m^3: sum over species of
+ *                 q w0 2^-16 (2^-F in 1D) sums over dx (1D, per unit area)
+ *                 or over h^2 depth_z (2D, h the leaf side).
+ * nq = pic_nq (nodes in 1D, leaves in 2D); host buffers of the caller. */
+int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out);
+
+/* Adapt the quadtree of a 2D slot to the particle count (Sec. 3.1: cells
+ * refined and coarsened, particles reassigned by position; Sec. 4.3: AMR
+ * keeps particles per cell steady, splitting 1 -> 4 and merging as the
+ * fallback): coarsen sibling groups holding at most n_hi with a child below
+ * n_lo (and no touching leaf two levels finer), refine leaves above n_hi
+ * (repeatedly), 2:1 balance, reassign particles, split particles 1 -> 4 in
+ * leaves below n_lo, merge pairs in leaves above n_hi at max_level.  Ends
+ * with a fresh deposit.  s (nullable) receives what was done.  PIC_E_ARG for
+ * a 1D slot; PIC_E_CAPACITY if split copies would exhaust the u32 ids or the
+ * per-array limit (the tree is then adapted, the particles not split). */
+int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s);
+
+/* ---- field feed (Sec. 3: Poisson for the potential, E at the nodes) ---- */
+
+/* Set the field table the gather reads, from host data of the given kind
+ * (PIC_* field kinds above; the sizes are stated there).  2D nodal E is the
+ * mean, over the leaves having the node as a corner, of their corner
+ * gradients (Sec. 3: bilinear gather from nodal E).  PIC_E_ARG for a kind
+ * that does not fit the slot (dimension or 1D coupling). */
+int pic_field_set(pic_ctx c, int slot, int kind, const double* data);
+
+/* Poisson from the latest deposit (Sec. 3, potential at cell centres; the
+ * paper's multigrid is replaced by direct / CG solves in FP64).  1D: Thomas
+ * with phi(0) = phi_left, phi(L) = 0; outputs phi_out/e_out[ncells+1]
+ * (nullable).  2D: cell-centred finite volumes, two-point fluxes, Jacobi CG
+ * from phi_init[nleaves] (nullable: the slot's last solution) to rtol, at
+ * most maxit iterations; phi_out[nleaves], e_out[nleaves*8] corner E
+ * (nullable); iters, relres nullable.  Either sets the gather table.
+ * PIC_E_NUMERIC if CG did not reach rtol; PIC_E_STATE if the tree is not
+ * 2:1 balanced. */
+int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init, double rtol, int maxit,
+                    double* phi_out, double* e_out, int* iters, double* relres);
+
+/* v <- v - (q dt / 2m) E(x) for every particle of the slot: start the
+ * leapfrog from the current field table (Sec. 3, explicit PIC). */
+int pic_leapfrog_start(pic_ctx c, int slot);
+
+/* Copy the latest per-species integer charge sums to q_out[2][nq] (host,
+ * not NULL) without depositing again (Sec. 3 charge assignment): after
+ * pic_step, the sums the last step's particle loop accumulated (its
+ * survivors and births); after pic_deposit or pic_adapt, theirs.  Units as
+ * pic_deposit.  PIC_E_ARG if q_out is NULL. */
+int pic_deposit_read(pic_ctx c, int slot, uint64_t* q_out);
+
+/* ---- configuration ---- */
+
+/* Route the particle, mesh, field and adaptation-scratch memory of a context
+ * through 'a' (NULL: hipMalloc with the library's own block cache).  Only on
+ * a context that holds no instance yet (build with ninst = 0, then
+ * pic_admit): else PIC_E_STATE.  The allocator must outlive the context.
+ * (Infrastructure; no passage of the paper.) */
+int pic_set_allocator(pic_ctx c, const pic_allocator* a);
 
 /* How a slot ranks the staged births of a step by parent id (Sec. 4.3
  * births; the ranks fix the newborn ids): 0 (default) pairwise while recent
@@ -221,50 +307,61 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out);
  * another method. */
 int pic_set_births_ranking(pic_ctx c, int slot, int method);
 
-/* Copy the latest per-species integer charge sums to q_out[2][nq] without
- * depositing again: after pic_step, the sums the last step's particle loop
- * accumulated (its survivors and births); after pic_deposit or pic_adapt,
- * theirs.  Units as pic_deposit.  PIC_E_ARG if q_out is NULL. */
-int pic_deposit_read(pic_ctx c, int slot, uint64_t* q_out);
+/* Device bytes the slot may hold once its particle and births buffers grow
+ * (Sec. 4.3: exponential growth of the particle count; serving admits jobs
+ * by projected memory).  0 = no limit.  Growth that would pass the limit
+ * returns PIC_E_CAPACITY from pic_step with the slot at its last committed
+ * step.  PIC_E_ARG if negative. */
+int pic_set_slot_limit(pic_ctx c, int slot, int64_t max_bytes);
 
-/* Poisson from the latest deposit.  1D: Thomas with phi(0) = phi_left,
- * phi(L) = 0; outputs phi_out/e_out[ncells+1] (nullable).  2D: FV +
- * Jacobi CG from phi_init (nullable) to rtol, at most maxit iterations;
- * phi_out[nleaves]; e_out[nleaves*8] corner E (nullable).  Either sets the
- * gather table.  PIC_E_NUMERIC if CG did not reach rtol. */
-int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init, double rtol, int maxit,
-                    double* phi_out, double* e_out, int* iters, double* relres);
-
-/* Adapt the quadtree of a 2D slot to the particle count (Sec. 3.1, 4.3):
- * coarsen sibling groups holding at most n_hi with a child below n_lo, refine
- * leaves above n_hi (repeatedly), 2:1 balance, reassign particles by
- * position, split particles 1 -> 4 in leaves below n_lo, merge pairs in
- * leaves above n_hi at max_level.  Ends with a fresh deposit. */
-int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s);
-
-/* ---- helpers ---- */
-int64_t pic_count(pic_ctx c, int slot, int species);          /* live particles, or < 0 on error */
-uint32_t pic_next_id(pic_ctx c, int slot);
-/* copy one species sorted by id: s[n*dim], v[n*3], w[n], id[n], cell[n] (all nullable) */
-int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, uint32_t* w, uint32_t* id,
-                       uint32_t* cell);
-int64_t pic_nleaves(pic_ctx c, int slot);
-int pic_leaves_read(pic_ctx c, int slot, uint32_t* keys, uint8_t* levels);   /* Morton order */
-int64_t pic_nq(pic_ctx c, int slot);                           /* nodes (1D) or leaves (2D) */
-int pic_field_read(pic_ctx c, int slot, double* out);          /* gather table, as double */
-int pic_sort(pic_ctx c, int slot);                             /* drop holes, order by cell */
-int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf);
-int pic_derived(pic_ctx c, int slot, int species, double* out12);
-int pic_philox(int64_t n, const uint32_t* ctr, const uint32_t key[2], uint32_t* out);  /* ctr[n*4] */
-int pic_set_stream(pic_ctx c, void* stream);
-int pic_sync(pic_ctx c);
-int pic_num_slots(pic_ctx c);
-/* Serving: put a new instance into a free slot (allocating its state), or
- * free a slot.  Slots are independent; pic_step over many slots batches them. */
+/* Serving: put a new instance into a free slot (allocating its state, as
+ * pic_mesh_build does for one descriptor), or free a slot.  Slots are
+ * independent; pic_step over many slots batches them.  *slot receives the
+ * slot index.  (Infrastructure around the method; no passage of the paper.) */
 int pic_admit(pic_ctx c, const pic_instance_desc* d, int* slot);
 int pic_retire(pic_ctx c, int slot);
+
+/* Make all later work of the context go to another hipStream_t (after
+ * finishing the queued work); pic_sync waits for the context's stream. */
+int pic_set_stream(pic_ctx c, void* stream);
+int pic_sync(pic_ctx c);
+
+/* ---- readers and helpers (host buffers of the caller, sizes as stated) ---- */
+
+/* live particles of a species (Sec. 3 super-particles), or < 0 on error */
+int64_t pic_count(pic_ctx c, int slot, int species);
+/* next particle id the slot hands to births and split copies (Sec. 4.3); 0 on error */
+uint32_t pic_next_id(pic_ctx c, int slot);
+/* global index of the slot's next step (its last committed step + 1), or < 0 */
+int64_t pic_step_index(pic_ctx c, int slot);
+/* one species sorted by id: s[n*dim], v[n*3], w[n], id[n], cell[n] (all
+ * nullable; n = pic_count); cell = leaf index (2D, Sec. 3.1) or 1D cell */
+int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, uint32_t* w, uint32_t* id,
+                       uint32_t* cell);
+/* quadtree leaves (Sec. 3.1): count, then keys[n] / levels[n] in Morton order */
+int64_t pic_nleaves(pic_ctx c, int slot);
+int pic_leaves_read(pic_ctx c, int slot, uint32_t* keys, uint8_t* levels);
+/* entries of the charge sums and densities: nodes (1D) or leaves (2D) */
+int64_t pic_nq(pic_ctx c, int slot);
+/* the gather table as double: 1D [ncells+1] node E (cell E for energy-
+ * conserving slots, last entry 0); 2D [nleaves][4][2] corner E (Sec. 3) */
+int pic_field_read(pic_ctx c, int slot, double* out);
+/* drop holes and order the particles by cell (Sec. 3.1 cell-based lists;
+ * the results of later steps do not depend on it) */
+int pic_sort(pic_ctx c, int slot);
+/* leaf[n] containing each point s[n*2] in [0,1)^2 (Sec. 3.1 location on the
+ * tree); PIC_E_ARG for a point outside */
+int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf);
+/* the slot's derived per-species constants out12[12], rounded to its
+ * precision: q dt/m, dt/L, candidate threshold, a_el, a_iz, v_iz^2, 2m/M,
+ * v_max^2, gas thermal speed, a_cx, g_max, q dt/2m (Sec. 3 MCC) */
+int pic_derived(pic_ctx c, int slot, int species, double* out12);
+/* Philox4x32-10 blocks (the counter-based generator behind the MCC draws):
+ * out[n*4] for counters ctr[n*4] under key[2] */
+int pic_philox(int64_t n, const uint32_t* ctr, const uint32_t key[2], uint32_t* out);
+int pic_num_slots(pic_ctx c);
 int64_t pic_slot_bytes(pic_ctx c, int slot);                   /* device bytes held by a slot */
-const char* pic_last_error(pic_ctx c);
+const char* pic_last_error(pic_ctx c);                         /* NULL ctx: this thread's last error */
 void pic_destroy(pic_ctx c);
 int pic_abi_version(void);
 

@@ -26,7 +26,19 @@
  *   MCC null-collision (Sec. 3): event rates vs n*sigma*v (binomial 5 sigma),
  *       elastic energy loss 2m/M, isotropy moments, ionization energy balance.
  *   Births / split / merge (Sec. 4.3): exact count, weight, charge identities.
- *   Adapt (Sec. 3.1, 4.3): 2:1 balance, area sum, level bounds, idempotence.
+ *   Adapt (Sec. 3.1, 4.3): 2:1 balance, area sum, level bounds, idempotence;
+ *       the coarsen rule on a hand-built explicit tree whose expected leaf
+ *       set is written down, one sibling group per condition.
+ *   Coarse-fine face coefficient of the FV operator: a linear potential
+ *       across faces between levels is annihilated, and a manufactured
+ *       solution converges at second order, on trees with such faces.
+ *   Cell-to-node potential at hanging nodes: exact for linear cell
+ *       potentials against the mean of the incident leaf centres.
+ *   Merge pairing by (velocity octant, |v|^2, id): one leaf whose pairs are
+ *       listed by hand.
+ *   Charge density: integrates to the total charge exactly (to rounding).
+ *   The tree pins are checked against planted mistakes (a copy of this file
+ *       with one rule changed must fail them: tests/test_oracle_mutants.py).
  * Where the paper leaves a point open, the reading taken is stated at the
  * function that implements it.
  */
@@ -244,6 +256,7 @@ template <class T> struct Sim : SimBase {
   std::vector<QNode*> leaves;
   std::vector<T> cornerE;       /* [leaf][corner][2] in T */
   std::vector<double> cornerE64;
+  std::vector<double> cornerPhi; /* [leaf][corner]: potentials behind cornerE (if given) */
   /* deposit */
   std::vector<uint64_t> Q[2];
 
@@ -304,6 +317,12 @@ template <class T> struct Sim : SimBase {
           d.base_level < d.min_level || d.base_level > d.max_level) return false;
       root.reset(new QNode());
       root->level = 0; root->ix = root->iy = 0; root->parent = nullptr; root->leaf_index = -1;
+      if (d.nleaves > 0) {
+        if (!explicit_tree()) return false;
+        relist();
+        for (int s = 0; s < 2; ++s) Q[s].assign(nq(), 0);
+        return true;
+      }
       refine_uniform(root.get(), d.base_level);
       if (d.refine_disk) {
         bool changed = true;
@@ -326,6 +345,46 @@ template <class T> struct Sim : SimBase {
     return true;
   }
 
+  /* Tree given leaf by leaf (Morton order).  Each leaf is an aligned Morton
+     range of 4^(16-level) keys; in Morton order they must follow each other
+     without gap or overlap from key 0 to 2^32.  The pointer tree is grown by
+     descending to each leaf.  An unbalanced tree is refused, not repaired. */
+  bool explicit_tree() {
+    if (!d.leaf_keys || !d.leaf_levels) return false;
+    uint64_t pos = 0;
+    for (int64_t i = 0; i < d.nleaves; ++i) {
+      const int L = d.leaf_levels[i];
+      if (L < d.min_level || L > d.max_level) return false;
+      const uint64_t span = (uint64_t)1 << (2 * (16 - L));
+      if ((uint64_t)d.leaf_keys[i] != pos) return false;
+      pos += span;
+      uint32_t X = 0, Y = 0;
+      for (int b = 0; b < 16; ++b) {
+        X |= ((d.leaf_keys[i] >> (2 * b)) & 1u) << b;
+        Y |= ((d.leaf_keys[i] >> (2 * b + 1)) & 1u) << b;
+      }
+      const uint32_t ix = X >> (16 - L), iy = Y >> (16 - L);
+      QNode* n = root.get();
+      for (int l = 0; l < L; ++l) {
+        if (n->is_leaf()) refine_node(n);
+        const int c = (int)(((ix >> (L - 1 - l)) & 1u) + 2u * ((iy >> (L - 1 - l)) & 1u));
+        n = n->kid[c].get();
+      }
+      if (!n->is_leaf()) return false;
+    }
+    if (pos != ((uint64_t)1 << 32)) return false;
+    std::vector<QNode*> lv;
+    collect_leaves(root.get(), lv);
+    if ((int64_t)lv.size() != d.nleaves) return false;
+    for (QNode* a : lv) {
+      std::vector<QNode*> t;
+      touching(root.get(), a->x0(), a->y0(), a->x1(), a->y1(), t);
+      for (QNode* b : t)
+        if (b->level > a->level + 1) return false;
+    }
+    return true;
+  }
+
   void refine_uniform(QNode* n, int L) {
     if (n->level >= L) return;
     refine_node(n);
@@ -337,6 +396,7 @@ template <class T> struct Sim : SimBase {
     collect_leaves(root.get(), leaves);
     cornerE.assign(leaves.size() * 8, (T)0);
     cornerE64.assign(leaves.size() * 8, 0.0);
+    cornerPhi.assign(leaves.size() * 4, 0.0);
     for (int s = 0; s < 2; ++s) Q[s].assign(leaves.size(), 0);
   }
 
@@ -610,6 +670,27 @@ template <class T> struct Sim : SimBase {
     return (((s.charge * s.w0) * std::ldexp(1.0, -16)) / d.depth_z) / EPS0;
   }
 
+  /* charge density of the latest deposit: the integer sums scaled to
+     coulombs (w_units = 2^16 carries w0 real particles; 1D shares carry F
+     more bits) over the cell volume per unit area (dx, 1D) or per leaf area
+     and depth (h^2 depth_z, 2D); no per-level weighting (Sec. 3.1) */
+  void rho(double* out) const {
+    for (int64_t i = 0; i < nq(); ++i) {
+      double r = 0.0;
+      for (int sp = 0; sp < d.nspecies; ++sp) {
+        const or_species& s = d.species[sp];
+        const double units = (double)(int64_t)Q[sp][i];
+        if (d.dim == 1)
+          r = r + ((units * std::ldexp(1.0, -(16 + F))) * (s.charge * s.w0)) / (d.length / N);
+        else {
+          const double h = d.length * std::ldexp(1.0, -leaves[i]->level);
+          r = r + ((units * std::ldexp(1.0, -16)) * (s.charge * s.w0)) / ((h * h) * d.depth_z);
+        }
+      }
+      out[i] = r;
+    }
+  }
+
   double rhs_cell(int64_t i) const {
     double b = 0.0;
     for (int sp = 0; sp < d.nspecies; ++sp) b = b + (double)(int64_t)Q[sp][i] * kappa(sp);
@@ -672,6 +753,7 @@ template <class T> struct Sim : SimBase {
   /* corner potentials per leaf -> corner gradients -> nodal E table */
   void corner_field_from_corner_phi(const std::vector<double>& cphi) {
     size_t nl = leaves.size();
+    cornerPhi = cphi;
     std::vector<double> g(nl * 8);
     for (size_t l = 0; l < nl; ++l) {
       double h = d.length * std::ldexp(1.0, -leaves[l]->level);
@@ -1099,8 +1181,16 @@ int or_field_set(void* h, int kind, const double* data) {
   return dispatch(h, [&](auto& S) {
     using T = typename std::remove_reference<decltype(S.En)>::type::value_type;
     if (S.d.dim == 1) {
-      if (kind == OR_NODE_E_1D) {
+      const bool ec = S.d.field_scheme == OR_FIELD_CIC_EC;
+      if (kind == OR_NODE_E_1D) {   /* node E: momentum-conserving coupling only */
+        if (ec) return OR_E_ARG;
         for (int i = 0; i <= S.N; ++i) S.En[i] = (T)data[i];
+        return OR_OK;
+      }
+      if (kind == OR_CELL_E_1D) {   /* cell E: energy-conserving coupling only */
+        if (!ec) return OR_E_ARG;
+        for (int i = 0; i < S.N; ++i) S.En[i] = (T)data[i];
+        S.En[S.N] = (T)0;
         return OR_OK;
       }
       if (kind == OR_NODE_PHI_1D) {
@@ -1127,6 +1217,31 @@ int or_field_set(void* h, int kind, const double* data) {
       return OR_OK;
     }
     return OR_E_ARG;
+  });
+}
+
+int or_rho(void* h, double* rho_out) {
+  return dispatch(h, [&](auto& S) {
+    S.rho(rho_out);
+    return OR_OK;
+  });
+}
+
+int or_corner_phi(void* h, double* out) {
+  return dispatch(h, [&](auto& S) {
+    if (S.d.dim != 2) return (int)OR_E_ARG;
+    for (size_t i = 0; i < S.cornerPhi.size(); ++i) out[i] = S.cornerPhi[i];
+    return (int)OR_OK;
+  });
+}
+
+int or_set_next_id(void* h, uint32_t next_id) {
+  return dispatch(h, [&](auto& S) {
+    for (int sp = 0; sp < S.d.nspecies; ++sp)
+      for (const auto& q : S.p[sp])
+        if (q.id >= next_id) return (int)OR_E_ARG;
+    S.next_id = next_id;
+    return (int)OR_OK;
   });
 }
 

@@ -37,8 +37,11 @@ enum { OR_WALL_NEUMANN = 0, OR_WALL_DIRICHLET = 1 };
 enum { OR_ABSORB = 0, OR_REFLECT = 1 };
 /* 1D particle-field coupling, both with CIC charge assignment to nodes (Sec. 3) */
 enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1 };
-/* field kinds for or_field_set */
-enum { OR_NODE_E_1D = 0, OR_NODE_PHI_1D = 1, OR_CORNER_PHI_2D = 2, OR_CORNER_E_2D = 3, OR_CELL_PHI_2D = 4 };
+/* field kinds for or_field_set.  OR_NODE_E_1D is for the momentum-conserving
+   1D coupling (N+1 node values), OR_CELL_E_1D for the energy-conserving one
+   (N cell values); each is refused on the other coupling. */
+enum { OR_NODE_E_1D = 0, OR_NODE_PHI_1D = 1, OR_CORNER_PHI_2D = 2, OR_CORNER_E_2D = 3, OR_CELL_PHI_2D = 4,
+       OR_CELL_E_1D = 5 };
 
 typedef struct {
   double charge;     /* C */
@@ -67,6 +70,14 @@ typedef struct {
   or_species species[2];
   int field_scheme;  /* 1D: OR_FIELD_CIC_EM (node E, linear gather) or
                         OR_FIELD_CIC_EC (cell E, the particle's cell value) */
+  /* 2D explicit tree (nleaves > 0): leaves in Morton order, key = Morton code
+     of the leaf's low corner in 16-bit units (x in the even bits), level per
+     leaf.  They must tile the square, lie within [min_level, max_level] and be
+     2:1 balanced across faces and corners, else or_create fails.  base_level
+     and the disk refinement are then ignored. */
+  const uint32_t* leaf_keys;
+  const uint8_t* leaf_levels;
+  int64_t nleaves;
 } or_desc;
 
 typedef struct {
@@ -95,6 +106,15 @@ int64_t or_nleaves(void* h);
 int or_leaves(void* h, uint32_t* keys, uint8_t* levels);
 int64_t or_nq(void* h);   /* nodes (1D) or leaves (2D) */
 int or_deposit(void* h, uint64_t* q_out);
+/* charge density of the latest deposit per node (1D, C/m^3: the node sum over
+   dx) or per leaf (2D, C/m^3: the leaf sum over h^2 depth_z) */
+int or_rho(void* h, double* rho_out);
+/* corner potentials [leaf][4] behind the current 2D field table (after a
+   CORNER_PHI / CELL_PHI field set or a 2D solve) */
+int or_corner_phi(void* h, double* out);
+/* set the next id handed to births and split copies; OR_E_ARG if an id in use
+   is not below it */
+int or_set_next_id(void* h, uint32_t next_id);
 int or_field_set(void* h, int kind, const double* data);
 int or_field_table(void* h, double* out);
 int or_field_solve_1d(void* h, double phi_left, double* phi_out, double* e_out);

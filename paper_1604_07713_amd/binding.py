@@ -17,8 +17,8 @@ _LIB = None
 
 PIC_OK, PIC_E_ARG, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 FIELD_CIC_EM, FIELD_CIC_EC = 0, 1   # 1D particle-field coupling (include/pic.h)
-ABI_VERSION = 2                     # PIC_ABI_VERSION of include/pic.h
-NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D = 0, 1, 2, 3, 4
+ABI_VERSION = 3                     # PIC_ABI_VERSION of include/pic.h
+NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D = 0, 1, 2, 3, 4, 5
 
 
 class LibraryMissing(RuntimeError):
@@ -45,20 +45,22 @@ class InstanceDesc(C.Structure):
                 ("wall_phi", C.c_double * 4), ("particle_bc", C.c_int), ("depth_z", C.c_double),
                 ("gas_density", C.c_double), ("gas_temperature", C.c_double), ("gas_mass", C.c_double),
                 ("seed", C.c_uint64), ("instance_key", C.c_uint32), ("nspecies", C.c_int),
-                ("species", SpeciesDesc * 2), ("capacity", C.c_int64 * 2), ("field_scheme", C.c_int)]
+                ("species", SpeciesDesc * 2), ("capacity", C.c_int64 * 2), ("field_scheme", C.c_int),
+                ("leaf_keys", C.c_void_p), ("leaf_levels", C.c_void_p), ("nleaves", C.c_int64)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("alive_start", C.c_int64 * 2), ("absorbed", C.c_int64 * 2), ("elastic", C.c_int64),
                 ("ionization", C.c_int64), ("cx", C.c_int64), ("births", C.c_int64),
                 ("numax_violations", C.c_int64 * 2), ("lost_reflect", C.c_int64), ("loop_ms", C.c_double),
-                ("step_ms", C.c_double), ("loop_launches", C.c_int64)]
+                ("step_ms", C.c_double), ("loop_launches", C.c_int64), ("room_stops", C.c_int64)]
 
     def as_dict(self):
         return dict(alive_start=list(self.alive_start), absorbed=list(self.absorbed), elastic=self.elastic,
                     ionization=self.ionization, cx=self.cx, births=self.births,
                     numax_violations=list(self.numax_violations), lost_reflect=self.lost_reflect,
-                    loop_ms=self.loop_ms, step_ms=self.step_ms, loop_launches=self.loop_launches)
+                    loop_ms=self.loop_ms, step_ms=self.step_ms, loop_launches=self.loop_launches,
+                    room_stops=self.room_stops)
 
 
 class StepArgs(C.Structure):
@@ -91,7 +93,9 @@ EXPORTS = {
     "pic_field_set": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "pic_leapfrog_start": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_step": (C.c_int, [C.c_void_p, C.POINTER(StepArgs), C.POINTER(StepStats)]),
-    "pic_deposit": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "pic_deposit": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "pic_step_index": (C.c_int64, [C.c_void_p, C.c_int]),
+    "pic_set_slot_limit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64]),
     "pic_deposit_read": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "pic_set_births_ranking": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "pic_field_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
@@ -194,6 +198,15 @@ def make_desc(d, capacity=(0, 0)):
     c.capacity[0] = int(cap[0])
     c.capacity[1] = int(cap[1])
     c.field_scheme = int(d.get("field_scheme", FIELD_CIC_EM))
+    keep = []
+    if d.get("leaf_keys") is not None:
+        keys = np.ascontiguousarray(d["leaf_keys"], dtype=np.uint32)
+        lv = np.ascontiguousarray(d["leaf_levels"], dtype=np.uint8)
+        keep = [keys, lv]
+        c.leaf_keys = keys.ctypes.data
+        c.leaf_levels = lv.ctypes.data
+        c.nleaves = len(keys)
+    c._keep = keep   # the arrays outlive the call that reads them
     return c
 
 
@@ -219,7 +232,8 @@ class Context:
         self.descs = list(descs)
         self._allocator = allocator
         first = [] if allocator is not None else self.descs
-        arr = (InstanceDesc * max(len(first), 1))(*[make_desc(d) for d in first])
+        made = [make_desc(d) for d in first]
+        arr = (InstanceDesc * max(len(first), 1))(*made)
         h = C.c_void_p()
         L = lib()
         rc = L.pic_mesh_build(arr, len(first), stream if stream is not None else default_stream(), C.byref(h))
@@ -287,11 +301,13 @@ class Context:
         self._check(lib().pic_step(self.h, C.byref(a), C.byref(st)))
         return st.as_dict()
 
-    def deposit(self, slot=0):
+    def deposit(self, slot=0, rho=False):
+        """Integer charge sums [2][nq]; with rho=True also the charge density [nq]."""
         n = self.nq(slot)
         q = np.zeros((2, n), dtype=np.uint64)
-        self._check(lib().pic_deposit(self.h, slot, _p(q)))
-        return q
+        r = np.zeros(n) if rho else None
+        self._check(lib().pic_deposit(self.h, slot, _p(q), _p(r)))
+        return (q, r) if rho else q
 
     def set_births_ranking(self, slot, method):
         """0: by the births of recent steps, 1: pairwise, 2: binned."""
@@ -353,6 +369,15 @@ class Context:
     def next_id(self, slot=0):
         return lib().pic_next_id(self.h, slot)
 
+    def step_index(self, slot=0):
+        n = lib().pic_step_index(self.h, slot)
+        if n < 0:
+            self._check(int(n))
+        return int(n)
+
+    def set_slot_limit(self, slot, max_bytes):
+        self._check(lib().pic_set_slot_limit(self.h, slot, int(max_bytes)))
+
     def read(self, slot, species):
         dim = self.dim(slot)
         n = self.count(slot, species)
@@ -395,7 +420,8 @@ class Context:
 
     def admit(self, desc):
         s = C.c_int(-1)
-        self._check(lib().pic_admit(self.h, C.byref(make_desc(desc)), C.byref(s)))
+        md = make_desc(desc)
+        self._check(lib().pic_admit(self.h, C.byref(md), C.byref(s)))
         self._slot_desc[s.value] = desc
         return s.value
 

@@ -137,7 +137,11 @@ void reduce_plain_stats(Ctx& C, Slot& sl, int g) {
             "stats_reduce");
 }
 
-void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int64_t steps_ahead, Counters cn) {
+// Before a run of 'nsteps' steps of one slot: births rate (ranking method),
+// drive table v_next[k * nsel + j] for k < nsteps, capacity, device view.
+// The slot continues from its own step index.
+void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, const double* v_next, int j, int nsel, int64_t nsteps,
+                  Counters cn) {
   if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
   if (sl.ionizing) {   // births per step since the previous chunk picks the ranking method
@@ -147,24 +151,25 @@ void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, int j, int nsel, int
     sl.rate_births_mark = b;
     sl.rate_step_mark = cn.step;
   }
-  if (a->step0 >= 0) cn.step = (uint32_t)a->step0;   // else: continue from the slot's own step index
   cn.vstep0 = cn.step + 1u;
+  cn.flags &= ~kFlagNeedRoom;
   if (sl.d.dim == 1 && a->solve_field) {
-    if (!a->v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
-    if (sl.v_cap < (uint32_t)a->nsteps) {
+    if (!v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
+    if (sl.v_cap < (uint32_t)nsteps) {
+      double* nt = (double*)sl.alloc(8 * (size_t)std::max<int64_t>(nsteps, 64));
       sl.release(sl.v_table);
-      sl.v_cap = (uint32_t)std::max(a->nsteps, 64);
-      sl.v_table = (double*)sl.alloc(8 * sl.v_cap);
+      sl.v_table = nt;
+      sl.v_cap = (uint32_t)std::max<int64_t>(nsteps, 64);
     }
-    std::vector<double> vt(a->nsteps);
-    for (int k = 0; k < a->nsteps; ++k) vt[k] = a->v_next[(size_t)k * nsel + j];
+    std::vector<double> vt(nsteps);
+    for (int64_t k = 0; k < nsteps; ++k) vt[k] = v_next[(size_t)k * nsel + j];
     hip_check(hipMemcpyAsync(sl.v_table, C.stage(vt.data(), 8 * vt.size()), 8 * vt.size(), hipMemcpyHostToDevice,
                              C.stream),
               "v table");
-    sl.v_len = (uint32_t)a->nsteps;
+    sl.v_len = (uint32_t)nsteps;
   }
+  ensure_capacity(C, sl, cn, nsteps);
   write_counters(C, sl, cn);
-  ensure_capacity(C, sl, cn, steps_ahead);
   upload_dev(C, sl);
 }
 
@@ -187,7 +192,7 @@ void finish_stats(Ctx& C, std::vector<Slot*>& sel, std::vector<Counters>& before
     out.numax_violations[0] += (int64_t)(c.stats[kStViol0] - b.stats[kStViol0]);
     out.numax_violations[1] += (int64_t)(c.stats[kStViol1] - b.stats[kStViol1]);
     out.lost_reflect += (int64_t)(c.stats[kStLostReflect] - b.stats[kStLostReflect]);
-    if (c.flags) {
+    if (c.flags & ~kFlagNeedRoom) {
       sel[j]->error_state = true;
       err = "capacity exceeded on the device (flags " + std::to_string(c.flags) + ")";
     }
@@ -496,7 +501,8 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
   const int dim = sl.d.dim;
   for (int64_t i = 0; i < n * dim; ++i)
     if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "position outside [0,1)");
-  int64_t cap = std::max<int64_t>(sl.d.capacity[species], sl.ionizing ? 3 * n + 4096 : n);
+  int64_t cap = sl.d.capacity[species] > 0 ? std::max<int64_t>(sl.d.capacity[species], n)
+                                            : (sl.ionizing ? 3 * n + 4096 : n);
   cap = std::max<int64_t>(cap, 256);
   cap = (cap + 255) & ~(int64_t)255;
   Counters cn = read_counters(*c, sl);
@@ -655,8 +661,18 @@ int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
   Slot& sl = get_slot(c, slot);
   if (!data) throw Err(PIC_E_ARG, "null data");
   if (sl.d.dim == 1) {
-    if (kind != PIC_NODE_E_1D && kind != PIC_NODE_PHI_1D) throw Err(PIC_E_ARG, "bad field kind for 1D");
-    hip_check(hipMemcpy(sl.phi64, data, 8 * (size_t)(sl.d.ncells + 1), hipMemcpyHostToDevice), "upload");
+    const bool ec = sl.d.field_scheme == PIC_FIELD_CIC_EC;
+    if (kind != PIC_NODE_E_1D && kind != PIC_NODE_PHI_1D && kind != PIC_CELL_E_1D)
+      throw Err(PIC_E_ARG, "bad field kind for 1D");
+    if (kind == PIC_NODE_E_1D && ec) throw Err(PIC_E_ARG, "node E is for the momentum-conserving coupling (use PIC_CELL_E_1D)");
+    if (kind == PIC_CELL_E_1D && !ec) throw Err(PIC_E_ARG, "cell E is for the energy-conserving coupling (use PIC_NODE_E_1D)");
+    if (kind == PIC_CELL_E_1D) {   // N cell values, the unused last entry 0
+      std::vector<double> e(data, data + sl.d.ncells);
+      e.push_back(0.0);
+      hip_check(hipMemcpy(sl.phi64, e.data(), 8 * e.size(), hipMemcpyHostToDevice), "upload");
+    } else {
+      hip_check(hipMemcpy(sl.phi64, data, 8 * (size_t)(sl.d.ncells + 1), hipMemcpyHostToDevice), "upload");
+    }
     // data staged in phi64 (node potential or node E) -> E table
     if (sl.prec == 32) hip_check(launch_node_e_1d<float>(make_dev<float>(sl), sl.phi64, kind == PIC_NODE_PHI_1D, c->stream), "node_e");
     else hip_check(launch_node_e_1d<double>(make_dev<double>(sl), sl.phi64, kind == PIC_NODE_PHI_1D, c->stream), "node_e");
@@ -709,7 +725,7 @@ int pic_leapfrog_start(pic_ctx c, int slot) {
   PIC_GUARD_END(c)
 }
 
-int pic_deposit(pic_ctx c, int slot, uint64_t* q_out) {
+int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out) {
   PIC_GUARD_BEGIN
   Slot& sl = get_slot(c, slot);
   hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, c->stream), "memset");
@@ -717,9 +733,21 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out) {
   if (sl.prec == 32) hip_check(launch_deposit<float>(make_dev<float>(sl), c->stream, g), "deposit");
   else hip_check(launch_deposit<double>(make_dev<double>(sl), c->stream, g), "deposit");
   Counters cn = read_counters(*c, sl);
-  if (q_out) {
-    const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
-    hip_check(hipMemcpy(q_out, latest, 8 * 2 * (size_t)sl.nq, hipMemcpyDeviceToHost), "read");
+  const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
+  if (q_out) hip_check(hipMemcpy(q_out, latest, 8 * 2 * (size_t)sl.nq, hipMemcpyDeviceToHost), "read");
+  if (rho_out) {
+    const int F = sl.prec == 32 ? 24 : 32;
+    double qw0[2] = {0.0, 0.0};
+    for (int sp = 0; sp < sl.d.nspecies; ++sp) qw0[sp] = sl.d.species[sp].charge * sl.d.species[sp].w0;
+    double* r = (double*)sl.alloc(8 * (size_t)sl.nq);
+    const bool two = sl.d.dim == 2;
+    hip_check(launch_rho(latest, sl.nq, sl.d.nspecies, qw0[0], qw0[1], two ? 16 : 16 + F,
+                         two ? 0.0 : sl.d.length / sl.d.ncells, two ? sl.lv : nullptr, sl.d.length, sl.d.depth_z, r,
+                         c->stream),
+              "rho");
+    hip_check(hipMemcpyAsync(rho_out, r, 8 * (size_t)sl.nq, hipMemcpyDeviceToHost, c->stream), "read");
+    c->sync();
+    sl.release(r);
   }
   return PIC_OK;
   PIC_GUARD_END(c)
@@ -835,50 +863,95 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     stats->loop_launches = 0;
   }
   if (a->timing < 0) throw Err(PIC_E_ARG, "timing must be >= 0");
-  std::vector<Counters> before(nsel);
+  if (a->batched)
+    for (Slot* s : sel)
+      if (s->d.dim != 1 || s->prec != sel[0]->prec) throw Err(PIC_E_ARG, "batched steps need 1D slots of one precision");
+  for (Slot* s : sel)
+    if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   bool any_ionizing = false;
   for (Slot* s : sel) any_ionizing = any_ionizing || s->ionizing;
   const int64_t chunk = any_ionizing ? 64 : std::max(a->nsteps, 1);
+  // The call's steps are k = 0 .. nsteps-1 of every selected slot; slot j
+  // runs its step k as global step start[j] + k.  Slots run in groups of
+  // equal progress: a slot whose step found no room for its births stops at
+  // its last committed step (the device leaves it untouched), is grown on
+  // the host and continues later from there, with the same draws (they
+  // depend on particle id and step only), so the result equals a run that
+  // never stopped.
+  std::vector<Counters> before = read_counters_many(*c, sel);
+  std::vector<uint32_t> start(nsel);
+  for (int j = 0; j < nsel; ++j) {
+    start[j] = a->step0 >= 0 ? (uint32_t)a->step0 : before[j].step;
+    if (before[j].step != start[j]) {
+      Counters cn = before[j];
+      cn.step = start[j];
+      write_counters(*c, *sel[j], cn);
+      before[j].step = start[j];
+    }
+  }
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (a->timing) {
     t0 = get_event(*c, 0);
     t1 = get_event(*c, 1);
   }
+  bool started = false;
   double loop_ms = 0;
   int64_t launches = 0;
-  bool started = false;
-  for (int64_t kb = 0; kb < a->nsteps; kb += chunk) {
-    const int64_t ke = std::min<int64_t>(a->nsteps, kb + chunk);
+  std::vector<int64_t> stalled(nsel, -1);   // progress at which a slot last stopped for room
+  int64_t room_stops = 0;
+  for (;;) {
+    const std::vector<Counters> cur = read_counters_many(*c, sel);
+    int64_t dmin = a->nsteps;
+    std::vector<int64_t> done(nsel);
+    for (int j = 0; j < nsel; ++j) {
+      done[j] = (int64_t)(uint32_t)(cur[j].step - start[j]);
+      if (cur[j].flags & kFlagNeedRoom) {
+        // stopped for room twice at the same step although grown in between
+        if (stalled[j] == done[j]) throw Err(PIC_E_CAPACITY, "no room for the next step after growing the slot");
+        stalled[j] = done[j];
+        ++room_stops;
+      }
+      if (done[j] < a->nsteps) dmin = std::min(dmin, done[j]);
+    }
+    if (dmin >= a->nsteps) break;
+    std::vector<Slot*> grp;
+    std::vector<int> gj;
+    for (int j = 0; j < nsel; ++j)
+      if (done[j] == dmin) {
+        grp.push_back(sel[j]);
+        gj.push_back(j);
+      }
+    const int64_t n = std::min<int64_t>(chunk, a->nsteps - dmin);
     pic_step_args sub = *a;
-    sub.step0 = a->step0 >= 0 ? a->step0 + kb : -1;
-    sub.nsteps = (int)(ke - kb);
+    sub.step0 = -1;
+    sub.nsteps = (int)n;
+    const int ng = (int)grp.size();
     std::vector<double> vn;
     if (a->solve_field && a->v_next) {
-      vn.assign(a->v_next + (size_t)kb * nsel, a->v_next + (size_t)ke * nsel);
+      vn.resize((size_t)n * ng);
+      for (int64_t k = 0; k < n; ++k)
+        for (int q = 0; q < ng; ++q) vn[(size_t)k * ng + q] = a->v_next[(size_t)(dmin + k) * nsel + gj[q]];
       sub.v_next = vn.data();
     }
-    const std::vector<Counters> cur = read_counters_many(*c, sel);
-    if (kb == 0) before = cur;
-    for (int j = 0; j < nsel; ++j) prepare_slot(*c, *sel[j], &sub, j, nsel, ke - kb, cur[j]);
-    if (a->timing && !started) {
+    for (int q = 0; q < ng; ++q)
+      prepare_slot(*c, *grp[q], &sub, sub.v_next, q, ng, n, cur[gj[q]]);
+    if (a->timing && !started) {   // the call's wall time starts after the first preparation
       hip_check(hipEventRecord(t0, c->stream), "event");
       started = true;
     }
     if (a->batched) {
-      for (Slot* s : sel)
-        if (s->d.dim != 1 || s->prec != sel[0]->prec) throw Err(PIC_E_ARG, "batched steps need 1D slots of one precision");
       double lm = 0;
-      if (sel[0]->prec == 32) batched_steps<float>(*c, sel, &sub, 0, sub.nsteps, a->timing ? &lm : nullptr);
-      else batched_steps<double>(*c, sel, &sub, 0, sub.nsteps, a->timing ? &lm : nullptr);
+      if (grp[0]->prec == 32) batched_steps<float>(*c, grp, &sub, 0, n, a->timing ? &lm : nullptr);
+      else batched_steps<double>(*c, grp, &sub, 0, n, a->timing ? &lm : nullptr);
       loop_ms += lm;
-      if (a->timing) launches += sub.nsteps;
+      if (a->timing) launches += n;
     } else {
       std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-      for (int64_t k = 0; k < sub.nsteps; ++k) {
-        for (int j = 0; j < nsel; ++j) {
-          Slot& sl = *sel[j];
+      for (int64_t k = 0; k < n; ++k) {
+        for (int q = 0; q < ng; ++q) {
+          Slot& sl = *grp[q];
           hipEvent_t e0 = nullptr, e1 = nullptr;
-          if (a->timing > 0 && (kb + k) % a->timing == 0) {
+          if (a->timing > 0 && (dmin + k) % a->timing == 0) {
             e0 = get_event(*c, 2 + 2 * evs.size());
             e1 = get_event(*c, 3 + 2 * evs.size());
             evs.push_back({e0, e1});
@@ -886,13 +959,13 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
           const int g = step_grid(sl, a->grid);
           if (sl.prec == 32) plain_step<float>(*c, sl, a->solve_field != 0, g, e0, e1);
           else plain_step<double>(*c, sl, a->solve_field != 0, g, e0, e1);
-          if (a->sort_every > 0 && (kb + k + 1) % a->sort_every == 0) sort_slot(*c, sl);
+          if (a->sort_every > 0 && (dmin + k + 1) % a->sort_every == 0) sort_slot(*c, sl);
         }
       }
-      for (int j = 0; j < nsel; ++j) {
-        const int g = step_grid(*sel[j], a->grid);
-        if (sel[j]->prec == 32) reduce_plain_stats<float>(*c, *sel[j], g);
-        else reduce_plain_stats<double>(*c, *sel[j], g);
+      for (int q = 0; q < ng; ++q) {
+        const int g = step_grid(*grp[q], a->grid);
+        if (grp[q]->prec == 32) reduce_plain_stats<float>(*c, *grp[q], g);
+        else reduce_plain_stats<double>(*c, *grp[q], g);
       }
       if (a->timing) {
         c->sync();
@@ -917,6 +990,23 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     stats->loop_launches = launches;
   }
   finish_stats(*c, sel, before, stats);
+  if (stats) stats->room_stops = room_stops;
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int64_t pic_step_index(pic_ctx c, int slot) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  return (int64_t)read_counters(*c, sl).step;
+  PIC_GUARD_END(c)
+}
+
+int pic_set_slot_limit(pic_ctx c, int slot, int64_t max_bytes) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  if (max_bytes < 0) throw Err(PIC_E_ARG, "the limit must be >= 0");
+  sl.byte_limit = (size_t)max_bytes;
   return PIC_OK;
   PIC_GUARD_END(c)
 }

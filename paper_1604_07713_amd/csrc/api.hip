@@ -268,38 +268,68 @@ std::vector<HostLeaf> host_refine(const std::vector<HostLeaf>& L, const std::vec
   return out;
 }
 
+// Leaves that a finer leaf two or more levels deeper touches (face or
+// corner).  Probes one unit outside each leaf's side midpoints and corners
+// find every coarser leaf that touches it.
+bool host_unbalanced(const std::vector<HostLeaf>& L, std::vector<char>& mark, int64_t* nmark) {
+  bool any = false;
+  for (size_t i = 0; i < L.size(); ++i) {
+    uint32_t X, Y;
+    unmorton_host(L[i].key, X, Y);
+    const uint32_t S = 1u << (16 - L[i].lv);
+    const int64_t px[8] = {(int64_t)X - 1, (int64_t)X + S, (int64_t)X + S / 2, (int64_t)X + S / 2,
+                           (int64_t)X - 1, (int64_t)X + S, (int64_t)X - 1, (int64_t)X + S};
+    const int64_t py[8] = {(int64_t)Y + S / 2, (int64_t)Y + S / 2, (int64_t)Y - 1, (int64_t)Y + S,
+                           (int64_t)Y - 1, (int64_t)Y - 1, (int64_t)Y + S, (int64_t)Y + S};
+    for (int k = 0; k < 8; ++k) {
+      if (px[k] < 0 || py[k] < 0 || px[k] >= 65536 || py[k] >= 65536) continue;
+      const size_t j = host_locate(L, (uint32_t)px[k], (uint32_t)py[k]);
+      if ((int)L[j].lv < (int)L[i].lv - 1) {
+        if (!mark[j] && nmark) ++*nmark;
+        mark[j] = 1;
+        any = true;
+      }
+    }
+  }
+  return any;
+}
+
 // 2:1 balance over faces and corners: refine a leaf while a leaf touching it
-// is two or more levels finer.  Probes one unit outside each leaf's side
-// midpoints and corners find every coarser leaf that touches it.
+// is two or more levels finer.
 int64_t host_balance(std::vector<HostLeaf>& L) {
   int64_t nref = 0;
   for (;;) {
     std::vector<char> mark(L.size(), 0);
-    bool any = false;
-    for (size_t i = 0; i < L.size(); ++i) {
-      uint32_t X, Y;
-      unmorton_host(L[i].key, X, Y);
-      const uint32_t S = 1u << (16 - L[i].lv);
-      const int64_t px[8] = {(int64_t)X - 1, (int64_t)X + S, (int64_t)X + S / 2, (int64_t)X + S / 2,
-                             (int64_t)X - 1, (int64_t)X + S, (int64_t)X - 1, (int64_t)X + S};
-      const int64_t py[8] = {(int64_t)Y + S / 2, (int64_t)Y + S / 2, (int64_t)Y - 1, (int64_t)Y + S,
-                             (int64_t)Y - 1, (int64_t)Y - 1, (int64_t)Y + S, (int64_t)Y + S};
-      for (int k = 0; k < 8; ++k) {
-        if (px[k] < 0 || py[k] < 0 || px[k] >= 65536 || py[k] >= 65536) continue;
-        const size_t j = host_locate(L, (uint32_t)px[k], (uint32_t)py[k]);
-        if ((int)L[j].lv < (int)L[i].lv - 1) {
-          if (!mark[j]) ++nref;
-          mark[j] = 1;
-          any = true;
-        }
-      }
-    }
-    if (!any) return nref;
+    if (!host_unbalanced(L, mark, &nref)) return nref;
     L = host_refine(L, mark);
   }
 }
 
+// A tree given leaf by leaf (Morton order): every leaf an aligned Morton
+// range of 4^(16 - level) keys, the ranges following each other from 0 to
+// 2^32 without gap or overlap, levels within bounds, 2:1 balanced across
+// faces and corners.  Anything else is refused (PIC_E_ARG), not repaired.
+std::vector<HostLeaf> host_explicit_tree(const pic_instance_desc& d) {
+  if (!d.leaf_keys || !d.leaf_levels || d.nleaves > (int64_t)1 << 28)
+    throw Err(PIC_E_ARG, "explicit tree needs leaf_keys and leaf_levels (at most 2^28 leaves)");
+  std::vector<HostLeaf> L((size_t)d.nleaves);
+  uint64_t pos = 0;
+  for (int64_t i = 0; i < d.nleaves; ++i) {
+    const int lv = d.leaf_levels[i];
+    if (lv < d.min_level || lv > d.max_level) throw Err(PIC_E_ARG, "explicit tree: leaf level outside [min, max]");
+    if ((uint64_t)d.leaf_keys[i] != pos)
+      throw Err(PIC_E_ARG, "explicit tree: leaves must tile the square in Morton order (gap, overlap or misaligned key)");
+    pos += (uint64_t)1 << (2 * (16 - lv));
+    L[i] = HostLeaf{d.leaf_keys[i], (uint8_t)lv};
+  }
+  if (pos != ((uint64_t)1 << 32)) throw Err(PIC_E_ARG, "explicit tree: leaves do not cover the square");
+  std::vector<char> mark(L.size(), 0);
+  if (host_unbalanced(L, mark, nullptr)) throw Err(PIC_E_ARG, "explicit tree: not 2:1 balanced across faces and corners");
+  return L;
+}
+
 std::vector<HostLeaf> host_build_tree(const pic_instance_desc& d) {
+  if (d.nleaves > 0) return host_explicit_tree(d);
   std::vector<HostLeaf> L;
   const int B = d.base_level;
   const uint32_t n = 1u << B;
@@ -395,6 +425,7 @@ void validate(const pic_instance_desc& d) {
     throw Err(PIC_E_ARG, "field_scheme must be PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC");
   if (d.dim == 2 && d.field_scheme != PIC_FIELD_CIC_EM)
     throw Err(PIC_E_ARG, "the energy-conserving coupling is for the uniform 1D mesh");
+  if (d.nleaves < 0 || (d.nleaves > 0 && d.dim != 2)) throw Err(PIC_E_ARG, "an explicit tree is for 2D slots");
   for (int s = 0; s < d.nspecies; ++s) {
     const pic_species_desc& sp = d.species[s];
     if (!(sp.mass > 0)) throw Err(PIC_E_ARG, "species mass must be positive");
@@ -513,22 +544,29 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
   } else {
     set_mesh2d(C, sl, host_build_tree(d));
   }
+  // the caller's leaf arrays are read only while building
+  sl.d.leaf_keys = nullptr;
+  sl.d.leaf_levels = nullptr;
   sl.ionizing = d.nspecies == 2 && d.species[0].mcc == PIC_MCC_ELECTRON;
 }
 
 // ---------------------------------------------------------------------------
 // particle buffers
 // ---------------------------------------------------------------------------
-void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
+size_t pbuf_bytes(const Slot& sl, int64_t cap) {
+  return (2 * sl.esz + 3 * sl.esz + 12) * (size_t)cap + 8 * 256;
+}
+
+// A fresh particle buffer of 'cap' slots (nothing of the slot changes if the
+// allocation fails).
+PBuf new_pbuf(Slot& sl, int64_t cap) {
   // kernels address each particle array with 32-bit byte offsets
   if ((uint64_t)cap * sl.esz >= (1ull << 32) || cap > 0x7FFFFFFF)
     throw Err(PIC_E_CAPACITY, "particle capacity exceeds the per-array limit of 4 GiB");
-  PBuf& b = sl.pb[sp][which];
-  if (b.base) sl.release(b.base);
+  PBuf b;
   const size_t e = sl.esz;
   const size_t c = (size_t)cap;
-  const size_t bytes = (2 * e + 3 * e + 12) * c + 8 * 256;
-  char* p = (char*)sl.alloc(bytes);
+  char* p = (char*)sl.alloc(pbuf_bytes(sl, cap));
   b.base = p;
   size_t o = 0;
   auto carve = [&](size_t n) {
@@ -542,15 +580,27 @@ void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
   b.w = (uint32_t*)carve(4 * c);
   b.id = (uint32_t*)carve(4 * c);
   b.cell = sl.d.dim == 2 ? (uint32_t*)carve(4 * c) : nullptr;
+  return b;
 }
 
+void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
+  PBuf nb = new_pbuf(sl, cap);
+  PBuf& b = sl.pb[sp][which];
+  if (b.base) sl.release(b.base);
+  b = nb;
+}
+
+size_t births_bytes(const Slot& sl, int64_t cap) {
+  return (20 + 8 * sl.esz) * (size_t)cap + 4 * (3 * kBirthBins + 1) + 20 * 256;
+}
+
+// Births staging of 'cap' entries.  The new block is allocated before the
+// old one is given back, so a failed allocation leaves the slot as it was.
 void alloc_births(Ctx& C, Slot& sl, int64_t cap) {
-  if (sl.birth_base) sl.release(sl.birth_base);
-  sl.birth_base = nullptr;
-  sl.birth_cap = 0;
   if (!sl.ionizing) return;
   const size_t e = sl.esz, c = (size_t)cap;
-  char* p = (char*)sl.alloc((20 + 8 * e) * c + 4 * (3 * kBirthBins + 1) + 20 * 256);
+  char* p = (char*)sl.alloc(births_bytes(sl, cap));
+  if (sl.birth_base) sl.release(sl.birth_base);
   sl.birth_base = p;
   size_t o = 0;
   auto carve = [&](size_t n) {
@@ -665,14 +715,20 @@ int grid_for(int64_t n) {
   return (int)g;
 }
 
-// grow particle capacity of a species (keeps contents; count from counters)
+// Grow the particle capacity of a species, keeping the first 'count' slots.
+// Both new buffers (live and sort target) are allocated before anything of
+// the slot changes, so a failed allocation leaves the slot as it was.
 void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count) {
-  const int cur = sl.cur[sp];
-  PBuf old = sl.pb[sp][cur];
-  const int64_t oldcap = sl.cap[sp];
-  sl.pb[sp][cur] = PBuf();
-  alloc_particles(sl, sp, newcap, cur);
-  PBuf& nb = sl.pb[sp][cur];
+  const int cur = sl.cur[sp], other = 1 - cur;
+  PBuf nb = new_pbuf(sl, newcap);
+  PBuf no;
+  try {
+    no = new_pbuf(sl, newcap);
+  } catch (...) {
+    sl.release(nb.base);
+    throw;
+  }
+  const PBuf old = sl.pb[sp][cur];
   const size_t e = sl.esz;
   if (count) {
     hip_check(hipMemcpyAsync(nb.s[0], old.s[0], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
@@ -687,27 +743,48 @@ void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count) {
   }
   C.sync();
   sl.release(old.base);
-  (void)oldcap;
-  // the sort buffer follows the new capacity
-  const int other = 1 - cur;
   if (sl.pb[sp][other].base) sl.release(sl.pb[sp][other].base);
-  sl.pb[sp][other] = PBuf();
-  alloc_particles(sl, sp, newcap, other);
+  sl.pb[sp][cur] = nb;
+  sl.pb[sp][other] = no;
   sl.cap[sp] = newcap;
 }
 
+// Capacity for the next steps.  A step of an ionizing slot is started only
+// with room for its worst case of births (every electron alive ionizes
+// once): 2 count[0] electron slots, count[1] + count[0] ion slots and
+// count[0] staged births.  Growth is to twice that need (less if the slot's
+// memory limit or the 32-bit array addressing says so, but never below the
+// need).  Throws PIC_E_CAPACITY (or PIC_E_NOMEM) with the slot unchanged
+// when the need cannot be met; the ids still needed are checked too.
 void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
-  bool changed = false;
+  (void)steps_ahead;
+  int64_t need[2] = {0, 0};
   for (int sp = 0; sp < sl.d.nspecies; ++sp) {
-    int64_t need = c.count[sp];
-    if (sl.ionizing) need += (int64_t)c.count[0] * std::max<int64_t>(1, std::min<int64_t>(steps_ahead, 4)) / 4 + 1024;
-    if (need > sl.cap[sp]) {
-      // twice the need, clamped to what 32-bit byte offsets address (the
-      // need itself above that is refused by alloc_particles)
-      const int64_t limit = std::min<int64_t>((int64_t)(((1ull << 32) - 1) / sl.esz), 0x7FFFFFFF);
-      grow(C, sl, sp, std::max(need, std::min(2 * need + 1024, limit)), c.count[sp]);
-      changed = true;
+    need[sp] = c.count[sp];
+    if (sl.ionizing) need[sp] += (int64_t)c.count[0] + 1024;
+  }
+  if (sl.ionizing && (uint64_t)c.next_id + 2ull * c.count[0] > 0xFFFFFFFFull)
+    throw Err(PIC_E_CAPACITY, "particle ids exhausted: the next step could need ids beyond 2^32 - 1");
+  bool changed = false;
+  const int64_t arr_limit = std::min<int64_t>((int64_t)(((1ull << 32) - 1) / sl.esz), 0x7FFFFFFF);
+  for (int sp = 0; sp < sl.d.nspecies; ++sp) {
+    if (need[sp] <= sl.cap[sp]) continue;
+    if (need[sp] > arr_limit) throw Err(PIC_E_CAPACITY, "particle capacity exceeds the per-array limit of 4 GiB");
+    int64_t want = std::max(need[sp], std::min(2 * need[sp] + 1024, arr_limit));
+    if (sl.byte_limit) {
+      // bytes after the growth: the two particle buffers of this species are
+      // replaced (births staging follows species 0)
+      auto after = [&](int64_t cap) {
+        size_t b = sl.bytes_held - 2 * pbuf_bytes(sl, sl.cap[sp]) + 2 * pbuf_bytes(sl, cap);
+        if (sp == 0 && sl.ionizing) b = b - (sl.birth_base ? births_bytes(sl, sl.birth_cap) : 0) + births_bytes(sl, cap);
+        return b;
+      };
+      if (after(want) > sl.byte_limit) want = need[sp];
+      if (after(want) > sl.byte_limit)
+        throw Err(PIC_E_CAPACITY, "the slot's memory limit leaves no room for the next step");
     }
+    grow(C, sl, sp, want, c.count[sp]);
+    changed = true;
   }
   if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) {
     alloc_births(C, sl, sl.cap[0]);

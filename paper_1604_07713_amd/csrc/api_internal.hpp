@@ -122,6 +122,7 @@ struct Slot {
   void* devI = nullptr;    // device copy of InstDev<T>
   uint32_t max_id_loaded[2] = {0, 0};
   bool error_state = false;
+  size_t byte_limit = 0;   // device bytes the slot may hold after growth (0: no limit)
   // allocations
   std::vector<void*> allocs;
   std::vector<size_t> alloc_bytes;
@@ -166,6 +167,8 @@ void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L);
 void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n, int maxlv);
 void adapt_slot(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out);
 void alloc_particles(Slot& sl, int sp, int64_t cap, int which);
+size_t pbuf_bytes(const Slot& sl, int64_t cap);
+size_t births_bytes(const Slot& sl, int64_t cap);
 void alloc_births(Ctx& C, Slot& sl, int64_t cap);
 template <class T> InstDev<T> make_dev(const Slot& sl);
 void upload_dev(Ctx& C, Slot& sl);

@@ -24,6 +24,9 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
                                                     const double* __restrict__ phi_left) {
   extern __shared__ double lds[];
   const InstDev<T>& I = insts[blockIdx.x];
+  // after a step that was not run for want of room, neither solve nor commit
+  // (the table keeps the field of the last committed step)
+  if (mode == 1 && (I.ctr->flags & kFlagNeedRoom)) return;
   const int N = I.N;
   double* b = lds;              // [N+1] right-hand side, then forward-sweep values, then phi
   double* im = lds + (N + 1);   // [N+1] pivots
@@ -162,6 +165,36 @@ hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mod
                           hipStream_t s) {
   const size_t lds = (size_t)2 * (max_n + 1) * sizeof(double);
   hipLaunchKernelGGL(k_field1d<T>, dim3(ninst), dim3(kBlock), lds, s, insts, mode, phi_left);
+  return hipGetLastError();
+}
+
+// Charge density of an integer deposit (Sec. 3: charge at the nodes of the
+// uniform mesh or the centres of the leaves; Sec. 3.1: no per-level volume
+// weighting): the sums scaled to coulombs (w_units = 2^16 carries w0 real
+// particles, 1D shares carry F more bits), over dx (1D, per unit area) or
+// over h^2 depth_z (2D), species added in order.
+__global__ void k_rho(const unsigned long long* Q, uint32_t nq, int nspecies, double qw0_0, double qw0_1, int shift,
+                      double dx, const uint8_t* lv, double length, double depth_z, double* rho) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  double r = 0.0;
+  for (int sp = 0; sp < nspecies; ++sp) {
+    const double units = (double)(long long)Q[(size_t)sp * nq + i];
+    const double qw0 = sp == 0 ? qw0_0 : qw0_1;
+    if (!lv) {
+      r = r + ((units * ldexp(1.0, -shift)) * qw0) / dx;
+    } else {
+      const double h = length * ldexp(1.0, -(int)lv[i]);
+      r = r + ((units * ldexp(1.0, -shift)) * qw0) / ((h * h) * depth_z);
+    }
+  }
+  rho[i] = r;
+}
+
+hipError_t launch_rho(const unsigned long long* Q, uint32_t nq, int nspecies, double qw0_0, double qw0_1, int shift,
+                      double dx, const uint8_t* lv, double length, double depth_z, double* rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho, dim3(ceil_div(nq, kBlock)), dim3(kBlock), 0, s, Q, nq, nspecies, qw0_0, qw0_1, shift, dx,
+                     lv, length, depth_z, rho);
   return hipGetLastError();
 }
 

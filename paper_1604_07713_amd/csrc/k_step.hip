@@ -990,6 +990,10 @@ constexpr int batch_k() {
 template <class T, bool MCC, int DIM, bool DIRECT>
 __global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int commit) {
   constexpr int K = batch_k<T, DIM, MCC>();
+  if (step_blocked<T>(I)) {   // uniform over the launch: no room for this step's births
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&I.ctr->flags, kFlagNeedRoom);
+    return;
+  }
   const uint32_t step = I.ctr->step;
   const uint32_t n0 = I.ctr->count[0];
   const uint32_t n1 = I.nspecies == 2 ? I.ctr->count[1] : 0u;
@@ -1033,6 +1037,10 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
     const WorkItem wi = items[it];
     const InstDev<T>& I = insts[wi.inst];
     const int sp = (int)wi.species;
+    if (step_blocked<T>(I)) {   // the same decision for every item of the instance
+      if (wi.begin == 0 && sp == 0 && threadIdx.x == 0) atomicOr(&I.ctr->flags, kFlagNeedRoom);
+      continue;
+    }
     const uint32_t step = I.ctr->step;
     const uint32_t count = I.ctr->count[sp];
     const uint32_t end = wi.end < count ? wi.end : count;
@@ -1064,6 +1072,8 @@ constexpr int kWriteBlocks = 64;   // workgroups per instance of the writing ker
 
 template <class T>
 __device__ __forceinline__ bool births_fit(const InstDev<T>& I, uint32_t nb, bool& cap_ok, bool& id_ok) {
+  cap_ok = id_ok = true;
+  if (I.ctr->flags & kFlagNeedRoom) return false;   // the step was not run
   const uint32_t c0 = I.ctr->count[0], c1 = I.ctr->count[1], nid = I.ctr->next_id;
   cap_ok = (uint64_t)c0 + nb <= I.cap[0] && (uint64_t)c1 + nb <= I.cap[1] && nb <= I.birth_cap;
   id_ok = (uint64_t)nid + 2ull * nb <= 0xFFFFFFFFull;
@@ -1110,7 +1120,7 @@ __device__ void birth_write_body(const InstDev<T>& I, uint32_t first, uint32_t n
   if (nb == 0u) return;
   bool cap_ok, id_ok;
   if (!births_fit(I, nb, cap_ok, id_ok)) {
-    if (threadIdx.x == 0 && first == 0)
+    if (threadIdx.x == 0 && first == 0 && !(cap_ok && id_ok))
       atomicOr(&I.ctr->flags, (!cap_ok ? kFlagBirthOverflow : 0u) | (!id_ok ? kFlagIdOverflow : 0u));
     return;
   }
@@ -1250,6 +1260,7 @@ template <class T>
 __device__ void commit_body(const InstDev<T>& I) {
   if (threadIdx.x == 0) {
     Counters* c = I.ctr;
+    if (c->flags & kFlagNeedRoom) return;   // the step was not run: no commit
     const uint32_t nb = c->nbirths;
     if (nb && !(c->flags & (kFlagBirthOverflow | kFlagIdOverflow))) {
       c->count[0] += nb;

@@ -25,7 +25,11 @@ struct Counters {
   uint32_t done;         // workgroups finished in the current launch
   unsigned long long stats[12];
 };
-enum : uint32_t { kFlagBirthOverflow = 1u, kFlagIdOverflow = 2u, kFlagSplitOverflow = 4u };
+// kFlagNeedRoom: a step found less room than its worst case of births needs
+// and was not run (nor any later one, until the host clears the flag): the
+// instance stays at its last committed step.  The other flags mark overflows
+// that this check rules out; they remain as a guard.
+enum : uint32_t { kFlagBirthOverflow = 1u, kFlagIdOverflow = 2u, kFlagSplitOverflow = 4u, kFlagNeedRoom = 8u };
 enum StatIdx {
   kStAlive0 = 0, kStAlive1, kStAbs0, kStAbs1, kStElastic, kStIonization, kStCx, kStBirths,
   kStViol0, kStViol1, kStLostReflect, kStUnused
@@ -93,6 +97,25 @@ struct InstDev {
 };
 constexpr int kNStat = 12;
 
+// Room for one step of an ionizing instance: every electron alive at the
+// start of the step can ionize at most once, so a step appends at most
+// count[0] electrons and as many ions, stages as many births and uses twice
+// as many ids.  A step without that room is not started (every workgroup of
+// every launch of the step sees the same counters and decides alike), so
+// the instance is never left part-way through a step.
+__host__ __device__ inline bool room_for_step(uint32_t count0, uint32_t count1, uint32_t next_id, uint64_t cap0,
+                                              uint64_t cap1, uint64_t birth_cap) {
+  const uint64_t c0 = count0, c1 = count1;
+  return 2u * c0 <= cap0 && c1 + c0 <= cap1 && c0 <= birth_cap && (uint64_t)next_id + 2u * c0 <= 0xFFFFFFFFull;
+}
+template <class T>
+__device__ __forceinline__ bool step_blocked(const InstDev<T>& I) {
+  const Counters* c = I.ctr;
+  if (c->flags & kFlagNeedRoom) return true;
+  if (I.nspecies < 2 || I.sk[0].mcc != PIC_MCC_ELECTRON) return false;   // no births
+  return !room_for_step(c->count[0], c->count[1], c->next_id, I.cap[0], I.cap[1], I.birth_cap);
+}
+
 // Work item of the batched (persistent) 1D launch.
 struct WorkItem {
   uint32_t inst, species, begin, end;
@@ -126,6 +149,10 @@ template <class T> hipError_t launch_relocate(const InstDev<T>& I, int species, 
 template <class T> hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mode,
                                              const double* phi_left, hipStream_t s);
 template <class T> hipError_t launch_node_e_1d(const InstDev<T>& I, const double* data, int is_phi, hipStream_t s);
+// charge density per node (1D, lv = NULL) or leaf (2D) from Q[species][nq];
+// shift = 16 (+ F in 1D)
+hipError_t launch_rho(const unsigned long long* Q, uint32_t nq, int nspecies, double qw0_0, double qw0_1, int shift,
+                      double dx, const uint8_t* lv, double length, double depth_z, double* rho, hipStream_t s);
 struct Mesh2D {
   const uint32_t* key;
   const uint32_t* xy;

@@ -73,6 +73,8 @@ def test_adapt_split_and_merge_match():
 
 
 def test_adapt_coarsens_after_removal():
+    """The tree of a dense cluster, given explicitly, with most particles
+    removed: both sides coarsen it the same way."""
     d = I.streamer_desc(min_level=2, max_level=6, precision=64)
     d["base_level"] = 2
     pos, ve, vi = cluster(20000, 11, sigma=0.05)
@@ -80,18 +82,16 @@ def test_adapt_coarsens_after_removal():
                          (pos[:0], vi[:0], None, np.zeros(0, dtype=np.uint32))])
     adapt_both(o, g)
     compare_all(o, g, 64, "first")
-    # drop most particles (same subset on both sides) and adapt again: coarsening
+    # the adapted tree, with a sparse subset of the particles (same on both sides)
+    keys, lv = o.leaves()
+    d2 = dict(d, leaf_keys=keys, leaf_levels=lv)
     r = o.read(0)
     keep = np.arange(0, len(r["id"]), 40)
-    o2 = oracle.Oracle(d)
-    g2 = B.Context(d)
-    for ctx in (o2, ):
-        ctx.load(0, r["s"][keep], r["v"][keep], r["w"][keep], r["id"][keep])
-        ctx.load(1, r["s"][:0], r["v"][:0], None, np.zeros(0, dtype=np.uint32))
-    g2.load(0, 0, r["s"][keep], r["v"][keep], r["w"][keep], r["id"][keep])
-    g2.load(0, 1, r["s"][:0], r["v"][:0], None, np.zeros(0, dtype=np.uint32))
-    adapt_both(o2, g2)
+    o2, g2 = load_both(d2, [(r["s"][keep], r["v"][keep], r["w"][keep], r["id"][keep]),
+                            (r["s"][:0], r["v"][:0], None, np.zeros(0, dtype=np.uint32))])
+    assert np.array_equal(g2.leaves(0)[0], keys)
     st = adapt_both(o2, g2)
+    assert st["coarsened"] > 0
     compare_all(o2, g2, 64, "after removal")
 
 

@@ -1,0 +1,178 @@
+"""The boundary's contract on the GPU, through the C ABI.
+
+  - capacity (paper Sec. 4.3: ionization multiplies the particles): a step
+    without room for its worst case of births is not run; the library grows
+    the buffers and goes on, bit-identical to a run that never stopped; when
+    the slot's memory limit forbids the growth, PIC_E_CAPACITY leaves the slot
+    at its last committed step, equal to a reference stopped there, and a
+    retry after raising the limit ends equal to the reference;
+  - explicit trees (Sec. 3.1 cell-based quadtree) match the oracle, and the
+    coarsen rule acts on the GPU as written;
+  - the charge density output (Sec. 3 charge at nodes / cell centres;
+    Sec. 3.1 no per-level weighting) matches the oracle;
+  - the energy-conserving 1D coupling takes cell E (Sec. 3) and refuses node E.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07713_amd import binding as B
+from paper_1604_07713_amd import inputs as I
+from tests.gpu_common import assert_same_particles, load_both
+from tests.test_oracle_tree_pins import coarsen_case, explicit, points_in
+
+pytestmark = pytest.mark.gpu
+
+
+def same_state(a, b, slot_a=0, slot_b=0, what=""):
+    for sp in range(2):
+        assert_same_particles(a.read(slot_a, sp), b.read(slot_b, sp), 0, f"{what} species {sp}")
+    assert a.next_id(slot_a) == b.next_id(slot_b), what
+    assert a.step_index(slot_a) == b.step_index(slot_b), what
+    assert np.array_equal(a.deposit_read(slot_a), b.deposit_read(slot_b)), f"{what}: deposits differ"
+
+
+def streamer_start(capacity=None, npairs=5000):
+    d = I.streamer_desc(precision=32, max_level=8)
+    if capacity:
+        d["capacity"] = capacity
+    g = B.Context(d)
+    for sp, (s, v, w, ids) in enumerate(I.streamer_particles(d, npairs=npairs)):
+        g.load(0, sp, s, v, w, ids)
+    g.field_solve_2d(0, rtol=1e-10)
+    g.leapfrog_start(0)
+    return d, g
+
+
+# capacities just above one step's worst case at the start (2 n + 1024
+# electron slots, 2 n + 1024 ion slots, rounded to 256): the first steps run,
+# and the room runs out within a few dozen steps as births accumulate
+TIGHT_5000 = (11264, 11264)
+TIGHT_8192 = (17664, 17664)
+
+
+def test_room_stops_are_bit_identical_2d():
+    _, ref = streamer_start(capacity=(2_000_000, 2_000_000))
+    _, run = streamer_start(capacity=TIGHT_5000)
+    sr = ref.step(0, 192)
+    st = run.step(0, 192)
+    assert sr["room_stops"] == 0 and st["room_stops"] > 0, (sr["room_stops"], st["room_stops"])
+    assert sr["births"] == st["births"] > 0
+    same_state(ref, run, what="after 192 steps")
+
+
+def test_capacity_error_keeps_last_committed_step_2d():
+    _, ref = streamer_start(capacity=(2_000_000, 2_000_000))
+    _, run = streamer_start(capacity=TIGHT_5000)
+    run.set_slot_limit(0, run.slot_bytes(0) + 200_000)
+    with pytest.raises(B.PicError) as e:
+        run.step(0, 256)
+    assert e.value.code == B.PIC_E_CAPACITY
+    k = run.step_index(0)
+    assert 0 < k < 256
+    ref.step(0, k)
+    same_state(ref, run, what=f"stopped at step {k}")
+    run.set_slot_limit(0, 0)
+    run.step(-1, 256 - k)
+    ref.step(-1, 256 - k)
+    same_state(ref, run, what="after the retry")
+
+
+@pytest.mark.parametrize("batched", [0, 4096])
+def test_room_stops_are_bit_identical_1d(batched):
+    descs = [dict(I.ccp_desc(ncells=128, ppc=64, precision=32, instance_key=k, voltage=450.0 + 50 * k),
+                  capacity=TIGHT_8192) for k in range(3)]
+    big = [dict(d, capacity=(1_000_000, 1_000_000)) for d in descs]
+    ctx = {}
+    for name, dd in (("ref", big), ("run", descs)):
+        g = B.Context(dd)
+        for j, d in enumerate(dd):
+            for sp, (s, v, w, ids) in enumerate(I.ccp_particles(d)):
+                g.load(j, sp, s, v, w, ids)
+            g.deposit(j)
+            g.field_solve_1d(j, float(I.drive_voltage(d, 0)))
+            g.leapfrog_start(j)
+        ctx[name] = g
+    vn = np.stack([I.drive_voltage(d, np.arange(1, 401)) for d in descs], axis=1)
+    sr = ctx["ref"].step(0, 400, vn, solve_field=True, sort_every=20, batched=batched)
+    st = ctx["run"].step(0, 400, vn, solve_field=True, sort_every=20, batched=batched)
+    assert sr["room_stops"] == 0 and st["room_stops"] > 0
+    assert sr["births"] == st["births"] > 0
+    for j in range(3):
+        same_state(ctx["ref"], ctx["run"], j, j, f"instance {j}")
+
+
+# ---------------------------------------------------------------------------
+# explicit trees
+# ---------------------------------------------------------------------------
+def test_explicit_tree_coarsen_matches_oracle():
+    leaves, ce, ci = coarsen_case()
+    d = I.streamer_desc(min_level=2, max_level=4, precision=64)
+    d["base_level"] = 2
+    d, leaves = explicit(d, leaves)
+    rng = np.random.Generator(np.random.PCG64(31))
+    pe = np.concatenate([points_in(rng, *t, ce[t]) for t in leaves])
+    pi = np.concatenate([points_in(rng, *t, ci[t]) for t in leaves if t in ci])
+    parts = [(pe, np.zeros((len(pe), 3)), None, np.arange(len(pe), dtype=np.uint32)),
+             (pi, np.zeros((len(pi), 3)), None, np.arange(len(pe), len(pe) + len(pi), dtype=np.uint32))]
+    o, g = load_both(d, parts)
+    assert np.array_equal(o.leaves()[0], g.leaves(0)[0]) and np.array_equal(o.leaves()[1], g.leaves(0)[1])
+    so, sg = o.adapt(16, 64), g.adapt(0, 16, 64)
+    assert sg["coarsened"] == so["coarsened"] == 1 and sg["refined"] == 0
+    ko, lo = o.leaves()
+    kg, lg = g.leaves(0)
+    assert np.array_equal(ko, kg) and np.array_equal(lo, lg)
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), 0, f"species {sp}")
+
+
+def test_explicit_tree_rejected_when_unbalanced():
+    d = I.streamer_desc(min_level=1, max_level=3, precision=64)
+    d["base_level"] = 1
+    unbal = [(1, 1, 0), (1, 0, 1), (1, 1, 1), (2, 0, 0), (2, 1, 0), (2, 0, 1)]
+    unbal += [(3, 2 + i, 2 + j) for i in range(2) for j in range(2)]
+    with pytest.raises(B.PicError) as e:
+        B.Context(explicit(d, unbal)[0])
+    assert e.value.code == B.PIC_E_ARG
+
+
+# ---------------------------------------------------------------------------
+# charge density, cell E
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [64, 32])
+def test_rho_matches_oracle(precision):
+    d = I.streamer_desc(min_level=2, max_level=6, precision=precision)
+    d.update(base_level=2, refine_disk=1, disk_cx=0.37, disk_cy=0.61, disk_r=0.2, disk_level=6)
+    rng = np.random.Generator(np.random.PCG64(6))
+    n = 5000
+    parts = [(rng.random((n, 2)), np.zeros((n, 3)), rng.integers(1, 1 << 17, n).astype(np.uint32),
+              np.arange(n, dtype=np.uint32)),
+             (rng.random((n, 2)), np.zeros((n, 3)), None, np.arange(n, 2 * n, dtype=np.uint32))]
+    o, g = load_both(d, parts)
+    qo = o.deposit()
+    qg, rg = g.deposit(0, rho=True)
+    assert np.array_equal(qo, qg)
+    assert np.array_equal(o.rho(), rg)
+    d1 = I.ccp_desc(ncells=97, ppc=16, precision=precision)
+    o1, g1 = load_both(d1, I.ccp_particles(d1))
+    o1.deposit()
+    assert np.array_equal(o1.rho(), g1.deposit(0, rho=True)[1])
+
+
+def test_cell_e_on_energy_conserving_slot():
+    d = I.ccp_desc(ncells=64, ppc=16, precision=64)
+    d["field_scheme"] = I.FIELD_CIC_EC
+    o, g = load_both(d, I.ccp_particles(d))
+    with pytest.raises(B.PicError):
+        g.field_set(0, B.NODE_E_1D, np.zeros(65))
+    e = np.random.Generator(np.random.PCG64(3)).normal(0, 2e3, 64)
+    o.field_set(oracle.CELL_E_1D, e)
+    g.field_set(0, B.CELL_E_1D, e)
+    assert np.array_equal(o.field_table(), g.field_table(0))
+    o.leapfrog_start()
+    g.leapfrog_start(0)
+    so = o.step(0, 20)
+    sg = g.step(0, 20)
+    assert so["births"] == sg["births"] and so["elastic"] == sg["elastic"]
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), 0, f"species {sp}")

@@ -140,20 +140,20 @@ def test_adapt_idempotent_without_split_or_coarsen():
 
 
 def test_coarsen_after_particles_leave():
+    """The adapted tree of a dense cluster, given explicitly, with most of the
+    particles removed: sibling groups coarsen and the tree stays balanced."""
     d = cluster_desc(lmin=2, lmax=6)
     o = oracle.Oracle(d)
     load_cluster(o, n=20000, sigma=0.05)
     o.adapt(16, 64)
     k1, l1 = o.leaves()
-    # remove most particles: keep a sparse subset, the tree should coarsen
     r = o.read(0)
     keep = np.arange(0, len(r["id"]), 50)
-    o2 = oracle.Oracle(d)
+    o2 = oracle.Oracle(dict(d, leaf_keys=k1, leaf_levels=l1))
     o2.load(0, r["s"][keep], r["v"][keep], w=r["w"][keep], ids=r["id"][keep])
     o2.load(1, r["s"][:0], r["v"][:0], ids=np.zeros(0, dtype=np.uint32))
-    o2.adapt(16, 64)      # builds up from the uniform base
-    n_before = len(o2.leaves()[0])
+    assert np.array_equal(o2.leaves()[0], k1)
     st = o2.adapt(16, 64)
     keys, lv = o2.leaves()
     check_balanced(keys, lv)
-    assert len(keys) <= n_before
+    assert st["coarsened"] > 0 and len(keys) < len(k1)
