@@ -898,6 +898,7 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
   double loop_ms = 0;
   int64_t launches = 0;
   std::vector<int64_t> stalled(nsel, -1);   // progress at which a slot last stopped for room
+  std::vector<int64_t> grown_at(nsel, -1);  // progress at which a stopped slot was last grown
   int64_t room_stops = 0;
   for (;;) {
     const std::vector<Counters> cur = read_counters_many(*c, sel);
@@ -906,10 +907,10 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     for (int j = 0; j < nsel; ++j) {
       done[j] = (int64_t)(uint32_t)(cur[j].step - start[j]);
       if (cur[j].flags & kFlagNeedRoom) {
-        // stopped for room twice at the same step although grown in between
-        if (stalled[j] == done[j]) throw Err(PIC_E_CAPACITY, "no room for the next step after growing the slot");
+        // stopped again at the step it was grown for: the growth did not help
+        if (grown_at[j] == done[j]) throw Err(PIC_E_CAPACITY, "no room for the next step after growing the slot");
+        if (stalled[j] != done[j]) ++room_stops;
         stalled[j] = done[j];
-        ++room_stops;
       }
       if (done[j] < a->nsteps) dmin = std::min(dmin, done[j]);
     }
@@ -933,8 +934,10 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
         for (int q = 0; q < ng; ++q) vn[(size_t)k * ng + q] = a->v_next[(size_t)(dmin + k) * nsel + gj[q]];
       sub.v_next = vn.data();
     }
-    for (int q = 0; q < ng; ++q)
+    for (int q = 0; q < ng; ++q) {
+      if (cur[gj[q]].flags & kFlagNeedRoom) grown_at[gj[q]] = dmin;
       prepare_slot(*c, *grp[q], &sub, sub.v_next, q, ng, n, cur[gj[q]]);
+    }
     if (a->timing && !started) {   // the call's wall time starts after the first preparation
       hip_check(hipEventRecord(t0, c->stream), "event");
       started = true;
