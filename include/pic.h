@@ -258,6 +258,21 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out);
  * per-array limit (the tree is then adapted, the particles not split). */
 int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s);
 
+/* For callers that cannot allocate device memory (code between graph
+ * captures, tight serving loops, harnesses that forbid allocation): pic_step
+ * without any device allocation.  Batched 1D launches only (a->batched > 0,
+ * graph_steps = 0, timing = 0; else PIC_E_ARG).  Its launch tables (work
+ * items, instance table, per-item partial statistics, sort jobs, drive
+ * tables) live in a 16 MiB device workspace of the library, one per device,
+ * held until the process ends; a call whose tables do not fit returns
+ * PIC_E_ARG before any step runs.  It never grows particle buffers: when a
+ * step needs more room it returns PIC_E_CAPACITY with every slot at its last
+ * committed step (pic_step grows them).  The workspace is shared by every
+ * call on the device and keeps the last call's contents: calls that overlap
+ * on one device (two threads, two streams) race and must not be made.
+ * Results equal pic_step's with the same arguments. */
+int pic_step_noalloc(pic_ctx c, const pic_step_args* a, pic_step_stats* stats);
+
 /* ---- field feed (Sec. 3: Poisson for the potential, E at the nodes) ---- */
 
 /* Set the field table the gather reads, from host data of the given kind

@@ -93,6 +93,7 @@ EXPORTS = {
     "pic_field_set": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "pic_leapfrog_start": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_step": (C.c_int, [C.c_void_p, C.POINTER(StepArgs), C.POINTER(StepStats)]),
+    "pic_step_noalloc": (C.c_int, [C.c_void_p, C.POINTER(StepArgs), C.POINTER(StepStats)]),
     "pic_deposit": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "pic_step_index": (C.c_int64, [C.c_void_p, C.c_int]),
     "pic_set_slot_limit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64]),
@@ -278,7 +279,8 @@ class Context:
         self._check(lib().pic_particles_load(self.h, slot, species, len(s), _p(s), _p(v), _p(w), _p(ids)))
 
     def step(self, step0, nsteps=1, v_next=None, solve_field=False, sort_every=0, batched=0, slots=None,
-             timing=False, grid=0, graph_steps=0):
+             timing=False, grid=0, graph_steps=0, noalloc=False):
+        """pic_step, or pic_step_noalloc with noalloc=True."""
         a = StepArgs()
         a.step0 = int(step0)
         a.nsteps = int(nsteps)
@@ -298,7 +300,8 @@ class Context:
             a.nslots = len(sl)
         a.timing = int(timing)   # True = 1: every launch; n: every n-th step
         st = StepStats()
-        self._check(lib().pic_step(self.h, C.byref(a), C.byref(st)))
+        fn = lib().pic_step_noalloc if noalloc else lib().pic_step
+        self._check(fn(self.h, C.byref(a), C.byref(st)))
         return st.as_dict()
 
     def deposit(self, slot=0, rho=False):

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -19,9 +20,55 @@ using namespace pic;
 
 struct pic_ctx_s : public Ctx {};
 
+// Device memory of the no-allocation step (pic_step_noalloc): its launch
+// tables live in this file-scope array, one copy per device, held until the
+// process ends.  Host code must not pass the array's name to a kernel (on
+// the host it is only a stand-in); scratch_device_ptr() gives the device
+// address, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of 'scratch' on the current device (looked up on the first
+// call per device, with that device current).
+void* scratch_device_ptr() {
+  int dev = -1;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) throw Err(PIC_E_ARG, "device index out of range for the no-allocation workspace");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw Err(PIC_E_HIP, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Launch tables carved from the no-allocation workspace.
+struct Workspace {
+  char* base;
+  size_t size, off;
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (off + bytes > size)
+      throw Err(PIC_E_ARG, "the launch tables need more than the " + std::to_string(size >> 20) +
+                               " MiB no-allocation workspace (fewer slots, larger work items or fewer steps per call)");
+    void* p = base + off;
+    off += bytes;
+    return p;
+  }
+};
+
+__global__ void k_zero_u64(unsigned long long* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0ull;
+}
 
 #define PIC_GUARD_BEGIN try {
 #define PIC_GUARD_END(ctx)                                   \
@@ -141,7 +188,7 @@ void reduce_plain_stats(Ctx& C, Slot& sl, int g) {
 // drive table v_next[k * nsel + j] for k < nsteps, capacity, device view.
 // The slot continues from its own step index.
 void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, const double* v_next, int j, int nsel, int64_t nsteps,
-                  Counters cn) {
+                  Counters cn, bool noalloc = false) {
   if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
   if (sl.ionizing) {   // births per step since the previous chunk picks the ranking method
@@ -153,6 +200,13 @@ void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, const double* v_next
   }
   cn.vstep0 = cn.step + 1u;
   cn.flags &= ~kFlagNeedRoom;
+  if (noalloc) {   // the drive table goes to the workspace; no growth
+    if (sl.d.dim == 1 && a->solve_field && !v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
+    check_capacity(sl, cn);
+    write_counters(C, sl, cn);
+    upload_dev(C, sl);
+    return;
+  }
   if (sl.d.dim == 1 && a->solve_field) {
     if (!v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
     if (sl.v_cap < (uint32_t)nsteps) {
@@ -236,7 +290,7 @@ hipEvent_t get_event(Ctx& C, size_t i) {
 // once into a HIP graph on the context's capture stream and replayed.
 template <class T>
 void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int64_t kbeg, int64_t kend,
-                   double* loop_ms) {
+                   double* loop_ms, Workspace* ws = nullptr) {
   const int nsel = (int)sel.size();
   const uint32_t tile = (uint32_t)(a->batched > 1 ? a->batched : 4096);
   if (tile % kBlock) throw Err(PIC_E_ARG, "batched tile must be a multiple of 256");
@@ -273,17 +327,41 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     p = C.pool.get(cls);
     have = cls;
   };
-  ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * issued.size());
-  ensure(C.b_insts, C.b_insts_bytes, sizeof(InstDev<T>) * nsel);
-  if (C.b_part_bytes < sizeof(unsigned long long) * kNStat * issued.size()) {
-    ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * issued.size());
-    hip_check(hipMemsetAsync(C.b_part, 0, C.b_part_bytes, C.stream), "memset");
+  // the tables: the context's (pooled, kept between calls) or, without
+  // allocation, carved from the workspace (the caller's drive tables sit
+  // there already)
+  void *t_items, *t_insts, *t_rowbeg, *t_jobs;
+  unsigned long long* t_part;
+  if (ws) {
+    t_items = ws->take(sizeof(WorkItem) * issued.size());
+    t_insts = ws->take(sizeof(InstDev<T>) * nsel);
+    t_part = (unsigned long long*)ws->take(sizeof(unsigned long long) * kNStat * issued.size());
+    t_rowbeg = ws->take(sizeof(uint32_t) * rb.size());
+    t_jobs = ws->take(sizeof(SortJob<T>) * 2 * (size_t)nsel);
+    // partial-stats rows start at zero (the workspace keeps the last call's contents)
+    const size_t nrow = (size_t)kNStat * issued.size();
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<size_t>((nrow + 255) / 256, 1024)), dim3(256), 0,
+                       C.stream, t_part, nrow);
+    hip_check(hipGetLastError(), "zero rows");
+  } else {
+    ensure(C.b_items, C.b_items_bytes, sizeof(WorkItem) * issued.size());
+    ensure(C.b_insts, C.b_insts_bytes, sizeof(InstDev<T>) * nsel);
+    if (C.b_part_bytes < sizeof(unsigned long long) * kNStat * issued.size()) {
+      ensure(*(void**)&C.b_part, C.b_part_bytes, sizeof(unsigned long long) * kNStat * issued.size());
+      hip_check(hipMemsetAsync(C.b_part, 0, C.b_part_bytes, C.stream), "memset");
+    }
+    ensure(*(void**)&C.b_rowbeg, C.b_rowbeg_bytes, sizeof(uint32_t) * rb.size());
+    ensure(C.b_jobs, C.b_jobs_bytes, sizeof(SortJob<T>) * 2 * (size_t)nsel);
+    t_items = C.b_items;
+    t_insts = C.b_insts;
+    t_part = C.b_part;
+    t_rowbeg = C.b_rowbeg;
+    t_jobs = C.b_jobs;
   }
-  ensure(*(void**)&C.b_rowbeg, C.b_rowbeg_bytes, sizeof(uint32_t) * rb.size());
-  hip_check(hipMemcpyAsync(C.b_items, C.stage(issued.data(), sizeof(WorkItem) * issued.size()),
+  hip_check(hipMemcpyAsync(t_items, C.stage(issued.data(), sizeof(WorkItem) * issued.size()),
                            sizeof(WorkItem) * issued.size(), hipMemcpyHostToDevice, C.stream),
             "items");
-  hip_check(hipMemcpyAsync(C.b_rowbeg, C.stage(rb.data(), 4 * rb.size()), 4 * rb.size(), hipMemcpyHostToDevice,
+  hip_check(hipMemcpyAsync(t_rowbeg, C.stage(rb.data(), 4 * rb.size()), 4 * rb.size(), hipMemcpyHostToDevice,
                            C.stream),
             "rowbeg");
   // Batched sort of every selected slot (both species at once), replacing
@@ -307,12 +385,11 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
         max_ncell = std::max(max_ncell, N);
       }
     }
-    ensure(C.b_jobs, C.b_jobs_bytes, sizeof(SortJob<T>) * jobs.size());
-    hip_check(hipMemcpyAsync(C.b_jobs, C.stage(jobs.data(), sizeof(SortJob<T>) * jobs.size()),
+    hip_check(hipMemcpyAsync(t_jobs, C.stage(jobs.data(), sizeof(SortJob<T>) * jobs.size()),
                              sizeof(SortJob<T>) * jobs.size(), hipMemcpyHostToDevice, C.stream),
               "sort jobs");
-    hip_check(launch_sort_batched<T>((const InstDev<T>*)C.b_insts, (const SortJob<T>*)C.b_jobs, 2 * nsel, max_ncell,
-                                     (const WorkItem*)C.b_items, (uint32_t)issued.size(),
+    hip_check(launch_sort_batched<T>((const InstDev<T>*)t_insts, (const SortJob<T>*)t_jobs, 2 * nsel, max_ncell,
+                                     (const WorkItem*)t_items, (uint32_t)issued.size(),
                                      (int)std::min<size_t>(issued.size(), 2048), C.stream),
               "sort batched");
     for (int j = 0; j < nsel; ++j)
@@ -322,16 +399,22 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   };
   auto upload_insts = [&]() {
     std::vector<InstDev<T>> v(nsel);
-    for (int j = 0; j < nsel; ++j) v[j] = make_dev<T>(*sel[j]);
-    hip_check(hipMemcpyAsync(C.b_insts, C.stage(v.data(), sizeof(InstDev<T>) * nsel), sizeof(InstDev<T>) * nsel,
+    for (int j = 0; j < nsel; ++j) {
+      v[j] = make_dev<T>(*sel[j]);
+      if (ws && a->solve_field) {   // drive tables in the workspace: [slot][step] from its start
+        v[j].v_table = (const double*)ws->base + (size_t)j * (size_t)(kend - kbeg);
+        v[j].v_len = (uint32_t)(kend - kbeg);
+      }
+    }
+    hip_check(hipMemcpyAsync(t_insts, C.stage(v.data(), sizeof(InstDev<T>) * nsel), sizeof(InstDev<T>) * nsel,
                              hipMemcpyHostToDevice, C.stream),
               "insts");
   };
   upload_insts();
   const int grid = (int)std::min<size_t>(issued.size(), (size_t)(a->grid > 0 ? a->grid : 2048));
-  const InstDev<T>* dI = (const InstDev<T>*)C.b_insts;
+  const InstDev<T>* dI = (const InstDev<T>*)t_insts;
   auto one_step = [&](hipStream_t st) {
-    hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)C.b_items, (uint32_t)issued.size(), C.b_part, st, grid,
+    hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)t_items, (uint32_t)issued.size(), t_part, st, grid,
                                        any_mcc),
               "step1d_batched");
     if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, st), "births_batched");
@@ -399,7 +482,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
       }
     }
   }
-  hip_check(launch_stats_reduce<T>(dI, nsel, C.b_part, C.b_rowbeg, 0u, C.stream), "stats_reduce batched");
+  hip_check(launch_stats_reduce<T>(dI, nsel, t_part, (const uint32_t*)t_rowbeg, 0u, C.stream), "stats_reduce batched");
   if (sorted_any)
     for (Slot* s : sel) upload_dev(C, *s);
   if (loop_ms) {
@@ -852,8 +935,7 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   PIC_GUARD_END(c)
 }
 
-int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
-  PIC_GUARD_BEGIN
+static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, bool noalloc) {
   if (!c || !a || a->nsteps < 0) throw Err(PIC_E_ARG, "bad step arguments");
   std::vector<Slot*> sel = selection(c, a);
   const int nsel = (int)sel.size();
@@ -863,6 +945,8 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     stats->loop_launches = 0;
   }
   if (a->timing < 0) throw Err(PIC_E_ARG, "timing must be >= 0");
+  if (noalloc && (a->batched <= 0 || a->graph_steps != 0 || a->timing != 0))
+    throw Err(PIC_E_ARG, "the no-allocation step takes batched launches without graph replay or timing");
   if (a->batched)
     for (Slot* s : sel)
       if (s->d.dim != 1 || s->prec != sel[0]->prec) throw Err(PIC_E_ARG, "batched steps need 1D slots of one precision");
@@ -870,7 +954,9 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   bool any_ionizing = false;
   for (Slot* s : sel) any_ionizing = any_ionizing || s->ionizing;
-  const int64_t chunk = any_ionizing ? 64 : std::max(a->nsteps, 1);
+  // without allocation the drive tables of a chunk sit in the workspace
+  const int64_t chunk = (any_ionizing || noalloc) ? 64 : std::max(a->nsteps, 1);
+  char* ws_base = noalloc ? (char*)scratch_device_ptr() : nullptr;
   // The call's steps are k = 0 .. nsteps-1 of every selected slot; slot j
   // runs its step k as global step start[j] + k.  Slots run in groups of
   // equal progress: a slot whose step found no room for its births stops at
@@ -934,9 +1020,21 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
         for (int q = 0; q < ng; ++q) vn[(size_t)k * ng + q] = a->v_next[(size_t)(dmin + k) * nsel + gj[q]];
       sub.v_next = vn.data();
     }
+    Workspace ws{ws_base, kNoAllocScratchBytes, 0};
+    if (noalloc && a->solve_field) {
+      if (!a->v_next) throw Err(PIC_E_ARG, "solve_field needs v_next");
+      // drive tables [slot][step], the layout batched_steps reads
+      std::vector<double> vt((size_t)n * ng);
+      for (int q = 0; q < ng; ++q)
+        for (int64_t k = 0; k < n; ++k) vt[(size_t)q * n + k] = vn[(size_t)k * ng + q];
+      void* dv = ws.take(8 * vt.size());
+      hip_check(hipMemcpyAsync(dv, c->stage(vt.data(), 8 * vt.size()), 8 * vt.size(), hipMemcpyHostToDevice,
+                               c->stream),
+                "drive tables");
+    }
     for (int q = 0; q < ng; ++q) {
       if (cur[gj[q]].flags & kFlagNeedRoom) grown_at[gj[q]] = dmin;
-      prepare_slot(*c, *grp[q], &sub, sub.v_next, q, ng, n, cur[gj[q]]);
+      prepare_slot(*c, *grp[q], &sub, sub.v_next, q, ng, n, cur[gj[q]], noalloc);
     }
     if (a->timing && !started) {   // the call's wall time starts after the first preparation
       hip_check(hipEventRecord(t0, c->stream), "event");
@@ -944,8 +1042,9 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
     }
     if (a->batched) {
       double lm = 0;
-      if (grp[0]->prec == 32) batched_steps<float>(*c, grp, &sub, 0, n, a->timing ? &lm : nullptr);
-      else batched_steps<double>(*c, grp, &sub, 0, n, a->timing ? &lm : nullptr);
+      Workspace* w = noalloc ? &ws : nullptr;
+      if (grp[0]->prec == 32) batched_steps<float>(*c, grp, &sub, 0, n, a->timing ? &lm : nullptr, w);
+      else batched_steps<double>(*c, grp, &sub, 0, n, a->timing ? &lm : nullptr, w);
       loop_ms += lm;
       if (a->timing) launches += n;
     } else {
@@ -994,6 +1093,24 @@ int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
   }
   finish_stats(*c, sel, before, stats);
   if (stats) stats->room_stops = room_stops;
+}
+
+int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
+  PIC_GUARD_BEGIN
+  step_impl(c, a, stats, false);
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_step_noalloc(pic_ctx c, const pic_step_args* a, pic_step_stats* stats) {
+  PIC_GUARD_BEGIN
+  if (!c) throw Err(PIC_E_ARG, "null context");
+  struct Hold {   // no block goes back to the device or the caller's allocator during the call
+    Ctx& C;
+    explicit Hold(Ctx& x) : C(x) { C.hold_pool = true; }
+    ~Hold() { C.hold_pool = false; }
+  } hold(*c);
+  step_impl(c, a, stats, true);
   return PIC_OK;
   PIC_GUARD_END(c)
 }

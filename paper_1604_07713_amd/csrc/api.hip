@@ -404,6 +404,7 @@ std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel) 
 void Ctx::sync() {
   hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
   arena_off = 0;
+  if (hold_pool) return;
   size_t held = 0;
   for (const Slot& s : slots) held += s.bytes_held;
   pool.synced(held);
@@ -791,6 +792,16 @@ void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
     changed = true;
   }
   if (changed) upload_dev(C, sl);
+}
+
+// The room check of ensure_capacity without growing: PIC_E_CAPACITY when the
+// next step could need more room than the slot holds.
+void check_capacity(const Slot& sl, const Counters& c) {
+  if (!sl.ionizing) return;
+  if ((uint64_t)c.next_id + 2ull * c.count[0] > 0xFFFFFFFFull)
+    throw Err(PIC_E_CAPACITY, "particle ids exhausted: the next step could need ids beyond 2^32 - 1");
+  if (!room_for_step(c.count[0], c.count[1], c.next_id, (uint64_t)sl.cap[0], (uint64_t)sl.cap[1], sl.birth_cap))
+    throw Err(PIC_E_CAPACITY, "the next step needs more particle room than the slot holds (pic_step grows it)");
 }
 
 template <class T>

@@ -155,6 +155,9 @@ struct Ctx {
   // graph capture stream (default priority) and the events joining it to the caller's stream
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  // set during a no-allocation step: synchronizations keep released blocks
+  // pending instead of freeing them (they are freed at a later sync)
+  bool hold_pool = false;
   void* stage(const void* src, size_t bytes);
   void* pinned(size_t bytes);   // pinned host scratch from the staging arena
   void sync();
@@ -177,6 +180,7 @@ std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel);
 void write_counters(Ctx& C, Slot& sl, const Counters& c);
 int grid_for(int64_t n);
 void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead);
+void check_capacity(const Slot& sl, const Counters& c);
 void sort_slot(Ctx& C, Slot& sl);
 void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count);
 uint32_t morton_host(uint32_t x, uint32_t y);
