@@ -157,3 +157,56 @@ def test_streamer_full_config_properties():
     allids = np.concatenate(allids)
     assert len(np.unique(allids)) == len(allids)
     assert allids.max() < g.next_id(0)
+
+
+def test_streamer_resynced_at_full_size():
+    """The avalanche workload (1e4 seed pairs, 1 cm, levels 5-11, adapt and
+    CG every 10 steps) run on the GPU to steps 1000 and 1300, where it holds
+    about a million particles and more; at each point the GPU's state (tree,
+    particles, field table, next id) is loaded into the oracle and both sides
+    take 3 more steps, the second time with the binned births ranking.  Ids,
+    weights, cells, births, event counts and deposits must match exactly,
+    positions and velocities to 1e-5 relative (in practice bitwise)."""
+    d = I.streamer_desc(side=0.01, precision=32)
+    g = B.Context(d)
+    for sp, (s, v, w, ids) in enumerate(I.streamer_particles(d, npairs=10000)):
+        g.load(0, sp, s, v, w, ids)
+    g.adapt(0)
+    g.field_solve_2d(0, rtol=1e-8, maxit=4000)
+    g.leapfrog_start(0)
+    step = 0
+    for stop, ranking in ((1000, 1), (1300, 2)):
+        while step < stop:
+            g.step(-1, 10, sort_every=0)
+            step += 10
+            g.adapt(0)
+            g.field_solve_2d(0, rtol=1e-8, maxit=4000)
+        g.set_births_ranking(0, ranking)
+        keys, lv = g.leaves(0)
+        E = g.field_table(0)
+        parts = [g.read(0, sp) for sp in range(2)]
+        n = sum(len(p["id"]) for p in parts)
+        o = oracle.Oracle(dict(d, leaf_keys=keys, leaf_levels=lv))
+        for sp, p in enumerate(parts):
+            o.load(sp, p["s"], p["v"], p["w"], p["id"])
+        o.set_next_id(g.next_id(0))
+        o.field_set(oracle.CORNER_E_2D, E)
+        for sp in range(2):
+            assert np.array_equal(o.read(sp)["cell"], parts[sp]["cell"]), f"step {step}: cells on load"
+        so = o.step(step, 3)
+        sg = g.step(-1, 3, sort_every=0)
+        step += 3
+        print(f"resync at step {stop}: {n} particles, {so['births']} births in 3 steps", flush=True)
+        assert n > 500_000
+        for k in ("alive_start", "absorbed", "elastic", "ionization", "births", "numax_violations"):
+            assert so[k] == sg[k], (stop, k, so[k], sg[k])
+        assert so["births"] > 0
+        for sp in range(2):
+            assert_same_particles(o.read(sp), g.read(0, sp), 1e-5, f"step {step} species {sp}")
+        assert o.next_id == g.next_id(0)
+        assert np.array_equal(o.deposit(), g.deposit_read(0)), f"step {step}: deposits differ"
+        if step < 1300:
+            g.adapt(0)
+            g.field_solve_2d(0, rtol=1e-8, maxit=4000)
+        g.set_births_ranking(0, 0)
+        del o
