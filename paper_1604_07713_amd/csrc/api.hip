@@ -753,16 +753,20 @@ void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count) {
 // Capacity for the next steps.  A step of an ionizing slot is started only
 // with room for its worst case of births (every electron alive ionizes
 // once): 2 count[0] electron slots, count[1] + count[0] ion slots and
-// count[0] staged births.  Growth is to twice that need (less if the slot's
-// memory limit or the 32-bit array addressing says so, but never below the
-// need).  Throws PIC_E_CAPACITY (or PIC_E_NOMEM) with the slot unchanged
+// count[0] staged births; the need adds the births expected over the coming
+// steps.  Growth is to twice that need (less if the slot's memory limit or
+// the 32-bit array addressing says so, but never below the need).  Throws PIC_E_CAPACITY (or PIC_E_NOMEM) with the slot unchanged
 // when the need cannot be met; the ids still needed are checked too.
 void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
-  (void)steps_ahead;
+  // births expected over the coming steps (the rate of the previous steps,
+  // with a margin): room for them too, so that steps rarely stop for room
+  // (a stop only costs time: the slot then waits for the others and is
+  // grown before it goes on)
+  const int64_t expect = sl.ionizing ? (int64_t)(sl.births_rate * 2.0 * (double)std::max<int64_t>(steps_ahead, 1)) : 0;
   int64_t need[2] = {0, 0};
   for (int sp = 0; sp < sl.d.nspecies; ++sp) {
     need[sp] = c.count[sp];
-    if (sl.ionizing) need[sp] += (int64_t)c.count[0] + 1024;
+    if (sl.ionizing) need[sp] += (int64_t)c.count[0] + 2 * expect + 1024;
   }
   if (sl.ionizing && (uint64_t)c.next_id + 2ull * c.count[0] > 0xFFFFFFFFull)
     throw Err(PIC_E_CAPACITY, "particle ids exhausted: the next step could need ids beyond 2^32 - 1");
