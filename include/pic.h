@@ -15,7 +15,9 @@
  *     uniform mesh; no per-level volume weighting, Sec. 3.1),
  *   quadtree adaptation to the particle count with particle split/merge
  *     (Sec. 3.1 reassignment on refine/coarsen; Sec. 4.3 splitting 1 -> 4).
- * The Poisson solves (FP64 Thomas in 1D; FP64 cell-centred finite volumes
+ * The Poisson solves (1D: the exact solution of the node system by the
+ * closed-form inverse of the tridiagonal operator, integer prefix sums
+ * rounded once; 2D: FP64 cell-centred finite volumes
  * with Jacobi-preconditioned CG in 2D, standing in for the paper's multigrid
  * of Sec. 3) also run in kernels of this library.
  *
@@ -283,8 +285,8 @@ int pic_step_noalloc(pic_ctx c, const pic_step_args* a, pic_step_stats* stats);
 int pic_field_set(pic_ctx c, int slot, int kind, const double* data);
 
 /* Poisson from the latest deposit (Sec. 3, potential at cell centres; the
- * paper's multigrid is replaced by direct / CG solves in FP64).  1D: Thomas
- * with phi(0) = phi_left, phi(L) = 0; outputs phi_out/e_out[ncells+1]
+ * paper's multigrid is replaced by direct / CG solves in FP64).  1D: exact
+ * solution of the node system with phi(0) = phi_left, phi(L) = 0; outputs phi_out/e_out[ncells+1]
  * (nullable).  2D: cell-centred finite volumes, two-point fluxes, Jacobi CG
  * from phi_init[nleaves] (nullable: the slot's last solution) to rtol, at
  * most maxit iterations; phi_out[nleaves], e_out[nleaves*8] corner E

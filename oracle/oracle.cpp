@@ -18,7 +18,8 @@
  *   CIC / NGP deposit (Sec. 3; no volume weighting, Sec. 3.1):
  *       exact charge sums, first moment, brute-force counts.
  *   Locate on the quadtree (Sec. 3.1): brute force over all leaves.
- *   1D Poisson (Thomas): closed-form parabola, scipy banded solver.
+ *   1D Poisson (exact inverse of the tridiagonal operator, integer sums):
+ *       closed-form parabola, scipy banded solver, exact rational arithmetic.
  *   2D cell-centred Poisson (FV + Jacobi CG): scipy sparse direct solve,
  *       manufactured-solution convergence.
  *   Nodal E from cell/corner potentials: exact for linear potentials on any
@@ -250,7 +251,6 @@ template <class T> struct Sim : SimBase {
   int N = 0;
   std::vector<T> En;            /* 1D: node E (momentum-conserving CIC) or cell E
                                    (energy-conserving CIC, N values + an unused one), in T */
-  std::vector<double> inv_m;    /* Thomas pivots 1/m_i, i = 1..N-1 */
   /* 2D */
   std::unique_ptr<QNode> root;
   std::vector<QNode*> leaves;
@@ -304,14 +304,6 @@ template <class T> struct Sim : SimBase {
       N = d.ncells;
       if (N < 2) return false;
       En.assign(N + 1, (T)0);
-      inv_m.assign(N, 0.0);
-      /* Thomas for tridiag(-1, 2, -1): pivot m_1 = 2, m_i = 2 - 1/m_{i-1};
-         the pivots depend only on N and are inverted once */
-      double m = 2.0;
-      for (int i = 1; i < N; ++i) {
-        if (i > 1) m = 2.0 - inv_m[i - 1];
-        inv_m[i] = 1.0 / m;
-      }
     } else {
       if (d.min_level < 0 || d.max_level > 14 || d.min_level > d.max_level ||
           d.base_level < d.min_level || d.base_level > d.max_level) return false;
@@ -697,21 +689,45 @@ template <class T> struct Sim : SimBase {
     return b;
   }
 
+  /* 1D Poisson on the nodes (Sec. 3; potential phi_0 = V(t) on the powered
+     wall, phi_N = 0 on the grounded one):
+       2 phi_i - phi_{i-1} - phi_{i+1} = c_i,   c_i = sum_s kappa_s Q_s,i,
+     for i = 1 .. N-1.  Its exact solution, from the inverse of
+     tridiag(-1, 2, -1), (A^-1)_ij = min(i, j) (N - max(i, j)) / N, is
+       phi_i = V (N - i) / N
+             + sum_s (kappa_s / N) [ (N - i) sum_{j <= i} j Q_s,j
+                                     + i sum_{j > i} (N - j) Q_s,j ].
+     The Q are integer charge sums, so each bracket is an exact integer
+     (formed here in 128-bit arithmetic with running sums) and is rounded to
+     double once; the rest is a fixed short sequence of double operations.
+     The charge at the wall nodes does not enter (Dirichlet nodes). */
   void solve1d(double phi_left, double* phi, double* E) {
-    /* phi_0 = V(t), phi_N = 0; (2 phi_i - phi_{i-1} - phi_{i+1}) = b_i */
-    std::vector<double> ph(N + 1, 0.0), dp(N, 0.0);
+    typedef unsigned __int128 u128;
+    std::vector<double> ph(N + 1, 0.0);
     ph[0] = phi_left;
     ph[N] = 0.0;
-    double prev = 0.0;
-    for (int i = 1; i < N; ++i) {
-      double b = rhs_cell(i);
-      if (i == 1) b = b + ph[0];
-      if (i == N - 1) b = b + ph[N];
-      dp[i] = (b + prev) * inv_m[i];
-      prev = dp[i];
+    std::vector<u128> P1[2], P2[2];
+    u128 T2[2] = {0, 0};
+    for (int sp = 0; sp < d.nspecies; ++sp) {
+      P1[sp].assign(N, 0);
+      P2[sp].assign(N, 0);
+      u128 a = 0, b = 0;
+      for (int j = 1; j < N; ++j) {
+        a += (u128)(uint64_t)j * (u128)Q[sp][j];
+        b += (u128)(uint64_t)(N - j) * (u128)Q[sp][j];
+        P1[sp][j] = a;
+        P2[sp][j] = b;
+      }
+      T2[sp] = b;
     }
-    ph[N - 1] = dp[N - 1];
-    for (int i = N - 2; i >= 1; --i) ph[i] = dp[i] + inv_m[i] * ph[i + 1];
+    for (int i = 1; i < N; ++i) {
+      double v = (phi_left * (double)(N - i)) / (double)N;
+      for (int sp = 0; sp < d.nspecies; ++sp) {
+        const u128 D = (u128)(uint64_t)(N - i) * P1[sp][i] + (u128)(uint64_t)i * (T2[sp] - P2[sp][i]);
+        v = v + ((double)D * kappa(sp)) / (double)N;
+      }
+      ph[i] = v;
+    }
     double inv2dx = 1.0 / (2.0 * (d.length / N));
     std::vector<double> e(N + 1);
     node_or_cell_e(ph.data(), inv2dx, e.data());

@@ -525,14 +525,6 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
   if (d.dim == 1) {
     const int N = d.ncells;
     sl.nq = N + 1;
-    std::vector<double> im(N + 1, 0.0);
-    double m = 2.0;
-    for (int i = 1; i < N; ++i) {
-      if (i > 1) m = 2.0 - im[i - 1];
-      im[i] = 1.0 / m;
-    }
-    sl.inv_m = (double*)sl.alloc(8 * (N + 1));
-    hip_check(hipMemcpy(sl.inv_m, im.data(), 8 * (N + 1), hipMemcpyHostToDevice), "upload pivots");
     sl.E = sl.alloc(sl.esz * (N + 1));
     sl.e64 = (double*)sl.alloc(8 * (N + 1));
     sl.phi64 = (double*)sl.alloc(8 * (N + 1));
@@ -676,7 +668,6 @@ InstDev<T> make_dev(const Slot& sl) {
   I.v_len = sl.v_len;
   I.part = sl.part;
   I.nparts = (uint32_t)grid_for(sl.cap[0] + sl.cap[1]);
-  I.inv_m = sl.inv_m;
   I.kappa[0] = sl.kappa[0];
   I.kappa[1] = sl.kappa[1];
   I.inv2dx = sl.inv2dx;

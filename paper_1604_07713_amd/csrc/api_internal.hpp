@@ -100,7 +100,7 @@ struct Slot {
   uint32_t birth_cap = 0;
   // field tables
   void* E = nullptr;
-  double *e64 = nullptr, *phi64 = nullptr, *inv_m = nullptr, *cphi = nullptr, *grad = nullptr;
+  double *e64 = nullptr, *phi64 = nullptr, *cphi = nullptr, *grad = nullptr;
   // 2D mesh
   uint32_t *key = nullptr, *xy = nullptr, *lut = nullptr;
   uint8_t* lv = nullptr;

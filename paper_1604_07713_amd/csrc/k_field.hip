@@ -2,10 +2,10 @@
 // the particle gather reads (arXiv:1604.07713, Sec. 3: potential at cell
 // centres, E at cell nodes/corners, bilinear gather).
 //
-//  1D: one workgroup per instance.  The right-hand side is built in parallel
-//      from the integer charge sums; the Thomas sweeps (tridiag(-1,2,-1) with
-//      the pivots inverted once per mesh) run in one lane over LDS; node E by
-//      centred differences inside, second-order one-sided at the walls.
+//  1D: one workgroup per instance: the exact solution of the node system
+//      through the closed-form inverse of tridiag(-1,2,-1), with 128-bit
+//      integer prefix sums of the charge sums (no sequential sweep); node E
+//      by centred differences inside, second-order one-sided at the walls.
 //  2D: cell-centred finite volumes on the leaves with two-point fluxes,
 //      solved by Jacobi-preconditioned CG; node potentials are the mean of
 //      the cell potentials of the leaves having the node as a corner
@@ -19,26 +19,40 @@ namespace pic {
 // ---------------------------------------------------------------------------
 // 1D
 // ---------------------------------------------------------------------------
+// The exact solution of the 1D node system 2 phi_i - phi_{i-1} - phi_{i+1} =
+// c_i (i = 1..N-1, phi_0 = V, phi_N = 0, c_i = sum_s kappa_s Q_s,i) through
+// the inverse of tridiag(-1, 2, -1), (A^-1)_ij = min(i,j) (N - max(i,j)) / N:
+//   phi_i = V (N - i) / N + sum_s (kappa_s / N) D_s,i,
+//   D_s,i = (N - i) sum_{j<=i} j Q_s,j + i sum_{j>i} (N - j) Q_s,j.
+// D is an exact integer (the Q are integer charge sums): each thread sums its
+// run of nodes in 128-bit integers, a workgroup scan gives every node its
+// prefix sums, and D is rounded to double once.  The result does not depend
+// on how the nodes are split between threads, so it is the same for every
+// launch shape, and it is the exact solution rounded (a few ulps of its
+// terms) instead of a sequential sweep's rounding.
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 shfl_up_u128(u128 v, unsigned off) {
+  const unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
+  const unsigned long long l2 = __shfl_up(lo, off), h2 = __shfl_up(hi, off);
+  return ((u128)h2 << 64) | (u128)l2;
+}
+
+constexpr int kField1dThreads = 1024;
+
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict__ insts, int mode,
-                                                    const double* __restrict__ phi_left) {
-  extern __shared__ double lds[];
+__global__ __launch_bounds__(kField1dThreads) void k_field1d(const InstDev<T>* __restrict__ insts, int mode,
+                                                             const double* __restrict__ phi_left) {
+  extern __shared__ double ph[];   // [N + 1] node potentials
+  __shared__ u128 wtot[kField1dThreads / 64][4];
   const InstDev<T>& I = insts[blockIdx.x];
   // after a step that was not run for want of room, neither solve nor commit
   // (the table keeps the field of the last committed step)
   if (mode == 1 && (I.ctr->flags & kFlagNeedRoom)) return;
   const int N = I.N;
-  double* b = lds;              // [N+1] right-hand side, then forward-sweep values, then phi
-  double* im = lds + (N + 1);   // [N+1] pivots
   const uint32_t step = I.ctr->step;
   const uint32_t par = mode == 1 ? (step & 1u) : ((step + 1u) & 1u);
   const unsigned long long* Q = I.Q + (size_t)par * 2u * I.nq;
-  for (int i = threadIdx.x; i <= N; i += blockDim.x) {
-    double v = 0.0;
-    for (int sp = 0; sp < I.nspecies; ++sp) v = v + (double)(long long)Q[(size_t)sp * I.nq + i] * I.kappa[sp];
-    b[i] = v;
-    im[i] = I.inv_m[i];
-  }
   double left;
   if (mode == 1) {
     const uint32_t k = step + 1u - I.ctr->vstep0;
@@ -46,104 +60,75 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
   } else {
     left = phi_left ? phi_left[blockIdx.x] : 0.0;
   }
+  // interior nodes [j0, j1) of this thread
+  const int per = (N - 1 + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int j0 = 1 + (int)threadIdx.x * per;
+  const int j1 = j0 + per < N ? j0 + per : N;
+  const int ns = I.nspecies;
+  // q[0..1]: sum j Q_s,j and sum (N - j) Q_s,j of species 0; q[2..3] of species 1
+  u128 q[4] = {0, 0, 0, 0};
+  for (int sp = 0; sp < ns; ++sp)
+    for (int j = j0; j < j1; ++j) {
+      const u128 v = (u128)Q[(size_t)sp * I.nq + j];
+      q[2 * sp] += (u128)(unsigned)j * v;
+      q[2 * sp + 1] += (u128)(unsigned)(N - j) * v;
+    }
+  // workgroup exclusive scan of the four sums (inclusive within the wave by
+  // shuffles, then the totals of the lower waves)
+  const int lane = lane_id(), wv = threadIdx.x / 64, nw = blockDim.x / 64;
+  u128 inc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    inc[k] = q[k];
+#pragma unroll
+    for (unsigned off = 1; off < 64; off <<= 1) {
+      const u128 o = shfl_up_u128(inc[k], off);
+      if (lane >= (int)off) inc[k] += o;
+    }
+  }
+  if (lane == 63)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wtot[wv][k] = inc[k];
   __syncthreads();
+  u128 base[4] = {0, 0, 0, 0}, total[4] = {0, 0, 0, 0};
+  for (int w = 0; w < nw; ++w)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (w < wv) base[k] += wtot[w][k];
+      total[k] += wtot[w][k];
+    }
+  // the thread's nodes: prefix sums through node j, then D and phi
+  u128 P[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) P[k] = base[k] + inc[k] - q[k];
+  const double dN = (double)N;
+  for (int j = j0; j < j1; ++j) {
+    double v = (left * (double)(N - j)) / dN;
+    for (int sp = 0; sp < ns; ++sp) {
+      const u128 qq = (u128)Q[(size_t)sp * I.nq + j];
+      P[2 * sp] += (u128)(unsigned)j * qq;
+      P[2 * sp + 1] += (u128)(unsigned)(N - j) * qq;
+      const u128 D = (u128)(unsigned)(N - j) * P[2 * sp] + (u128)(unsigned)j * (total[2 * sp + 1] - P[2 * sp + 1]);
+      v = v + ((double)D * I.kappa[sp]) / dN;
+    }
+    ph[j] = v;
+  }
   if (threadIdx.x == 0) {
-    // forward sweep: d'_i = (b_i + d'_{i-1}) / m_i with phi_0 folded into b_1
-    // and phi_N = 0 into b_{N-1}.  The operands of the next group of kSweep
-    // elements are read from LDS while the current group's chain runs.
-    constexpr int kSweep = 8;
-    double prev = 0.0;
-    int i = 1;
-    if (N - 1 >= 2 * kSweep) {
-      double bn[kSweep], mn[kSweep];
-#pragma unroll
-      for (int q = 0; q < kSweep; ++q) {
-        bn[q] = b[i + q];
-        mn[q] = im[i + q];
-      }
-      bn[0] = bn[0] + left;
-      for (; i + 2 * kSweep <= N - 1; i += kSweep) {
-        double bc[kSweep], mc[kSweep];
-#pragma unroll
-        for (int q = 0; q < kSweep; ++q) {
-          bc[q] = bn[q];
-          mc[q] = mn[q];
-          bn[q] = b[i + kSweep + q];
-          mn[q] = im[i + kSweep + q];
-        }
-#pragma unroll
-        for (int q = 0; q < kSweep; ++q) {
-          prev = (bc[q] + prev) * mc[q];
-          b[i + q] = prev;
-        }
-      }
-      // the group already read (i .. i + kSweep - 1 < N - 1)
-#pragma unroll
-      for (int q = 0; q < kSweep; ++q) {
-        prev = (bn[q] + prev) * mn[q];
-        b[i + q] = prev;
-      }
-      i += kSweep;
-    }
-    for (; i < N; ++i) {
-      double c = (i == 1) ? b[i] + left : b[i];
-      if (i == N - 1) c = c + 0.0;   // phi_N = 0 folded into b_{N-1}
-      const double d = (c + prev) * im[i];
-      b[i] = d;
-      prev = d;
-    }
-    // back substitution: phi_{N-1} = d'_{N-1}, phi_i = d'_i + phi_{i+1} / m_i
-    double nxt = b[N - 1];
-    int j = N - 2;
-    if (j + 1 >= 2 * kSweep + 1) {
-      double an[kSweep], mn[kSweep];
-#pragma unroll
-      for (int q = 0; q < kSweep; ++q) {
-        an[q] = b[j - q];
-        mn[q] = im[j - q];
-      }
-      for (; j - 2 * kSweep + 1 >= 1; j -= kSweep) {
-        double ac[kSweep], mc[kSweep];
-#pragma unroll
-        for (int q = 0; q < kSweep; ++q) {
-          ac[q] = an[q];
-          mc[q] = mn[q];
-          an[q] = b[j - kSweep - q];
-          mn[q] = im[j - kSweep - q];
-        }
-#pragma unroll
-        for (int q = 0; q < kSweep; ++q) {
-          nxt = ac[q] + mc[q] * nxt;
-          b[j - q] = nxt;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kSweep; ++q) {
-        nxt = an[q] + mn[q] * nxt;
-        b[j - q] = nxt;
-      }
-      j -= kSweep;
-    }
-    for (; j >= 1; --j) {
-      const double p = b[j] + im[j] * nxt;
-      b[j] = p;
-      nxt = p;
-    }
-    b[0] = left;
-    b[N] = 0.0;
+    ph[0] = left;
+    ph[N] = 0.0;
   }
   __syncthreads();
   T* E = const_cast<T*>(I.E);
   const double h2 = I.inv2dx;
   for (int i = threadIdx.x; i <= N; i += blockDim.x) {
     double e;
-    if (I.cell_e) e = i < N ? (b[i] - b[i + 1]) * (2.0 * h2) : 0.0;   // cell E (energy-conserving)
-    else if (i == 0) e = ((3.0 * b[0] - 4.0 * b[1]) + b[2]) * h2;
-    else if (i == N) e = ((-3.0 * b[N] + 4.0 * b[N - 1]) - b[N - 2]) * h2;
-    else e = (b[i - 1] - b[i + 1]) * h2;
+    if (I.cell_e) e = i < N ? (ph[i] - ph[i + 1]) * (2.0 * h2) : 0.0;   // cell E (energy-conserving)
+    else if (i == 0) e = ((3.0 * ph[0] - 4.0 * ph[1]) + ph[2]) * h2;
+    else if (i == N) e = ((-3.0 * ph[N] + 4.0 * ph[N - 1]) - ph[N - 2]) * h2;
+    else e = (ph[i - 1] - ph[i + 1]) * h2;
     E[i] = (T)e;
     if (I.e64) I.e64[i] = e;
-    if (I.phi64) I.phi64[i] = b[i];
+    if (I.phi64) I.phi64[i] = ph[i];
   }
   if (mode == 1 && threadIdx.x == 0) {
     // commit the step: births join the counts, the step index advances
@@ -163,8 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_field1d(const InstDev<T>* __restrict
 template <class T>
 hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mode, const double* phi_left,
                           hipStream_t s) {
-  const size_t lds = (size_t)2 * (max_n + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_field1d<T>, dim3(ninst), dim3(kBlock), lds, s, insts, mode, phi_left);
+  const size_t lds = (size_t)(max_n + 1) * sizeof(double);
+  hipLaunchKernelGGL(k_field1d<T>, dim3(ninst), dim3(kField1dThreads), lds, s, insts, mode, phi_left);
   return hipGetLastError();
 }
 

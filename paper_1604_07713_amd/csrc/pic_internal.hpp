@@ -88,7 +88,6 @@ struct InstDev {
   unsigned long long* part;      // per-block partial stats [nparts][kNStat]
   uint32_t nparts;
   // FP64 field data
-  const double* inv_m;           // 1D Thomas pivots 1/m_i (i = 1..N-1)
   double kappa[2];               // charge-sum -> Poisson right-hand side factor per species
   double inv2dx;                 // 1D: 1 / (2 dx)
   int cell_e;                    // 1D energy-conserving coupling: E holds cell values, gathered without interpolation

@@ -94,11 +94,19 @@ def test_deposit_matches_1d_and_2d(precision):
     assert np.array_equal(o2.deposit(), g2.deposit(0))
 
 
-def test_thomas_matches_bitwise():
-    d = I.ccp_desc(ncells=300, ppc=20)
-    o, g = load_both(d, I.ccp_particles(d))
-    o.deposit()
-    g.deposit(0)
+@pytest.mark.parametrize("ncells,heavy", [(300, False), (4096, False), (8192, True), (2, False)])
+def test_poisson1d_matches_bitwise(ncells, heavy):
+    """The exact 1D solve (128-bit integer prefix sums rounded once) on the
+    GPU equals the oracle's bit for bit, from a few nodes to the largest mesh,
+    also with weights near 2^32 (charge sums near 2^64 per node)."""
+    d = I.ccp_desc(ncells=ncells, ppc=20)
+    parts = I.ccp_particles(d)
+    if heavy:
+        rng = np.random.Generator(np.random.PCG64(4))
+        parts = [(s, v, rng.integers(1 << 31, 1 << 32, len(w), dtype=np.uint64).astype(np.uint32), ids)
+                 for (s, v, w, ids) in parts]
+    o, g = load_both(d, parts)
+    assert np.array_equal(o.deposit(), g.deposit(0))
     po, eo = o.field_solve_1d(321.5)
     pg, eg = g.field_solve_1d(0, 321.5)
     assert np.array_equal(po, pg) and np.array_equal(eo, eg)

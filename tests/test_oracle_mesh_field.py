@@ -117,15 +117,15 @@ def test_ngp_deposit_counts_brute_force():
     assert np.array_equal(q, np.bincount(idx, weights=w, minlength=len(keys)).astype(np.uint64))
 
 
-def _thomas_case(N=64, L=0.05, V=123.0):
+def _poisson1d_case(N=64, L=0.05, V=123.0):
     d = I.ccp_desc(ncells=N, ppc=8, length=L)
     o = oracle.Oracle(d)
     return d, o
 
 
-def test_thomas_uniform_charge_gives_parabola():
+def test_poisson1d_uniform_charge_gives_parabola():
     N, L, V = 64, 0.05, 123.0
-    d, o = _thomas_case(N, L, V)
+    d, o = _poisson1d_case(N, L, V)
     # uniform ion charge on every node: one ion per node, exactly on the node
     pos = np.arange(N + 1) / N
     pos = pos[pos < 1.0]
@@ -142,9 +142,9 @@ def test_thomas_uniform_charge_gives_parabola():
     assert np.allclose(E, Eex, rtol=1e-9, atol=1e-9 * np.max(np.abs(Eex)))
 
 
-def test_thomas_matches_banded_solver():
+def test_poisson1d_matches_banded_solver():
     N, L, V = 97, 0.067, -37.5
-    d, o = _thomas_case(N, L, V)
+    d, o = _poisson1d_case(N, L, V)
     rng = np.random.Generator(np.random.PCG64(8))
     n = 5000
     o.load(0, rng.random((n, 1)), np.zeros((n, 3)), ids=np.arange(n, dtype=np.uint32))
@@ -264,3 +264,45 @@ def test_fv_manufactured_solution_converges():
         phi, *_ = o.field_solve_2d(rtol=1e-13)
         errs.append(np.max(np.abs(phi - np.sin(np.pi * xc) * np.sin(np.pi * yc))))
     assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+
+
+def test_poisson1d_exact_against_rational_elimination():
+    """The 1D solve against Gaussian elimination in exact rational arithmetic
+    (fractions) of the same tridiagonal system: the oracle's result is the
+    exact solution rounded, within a few units in the last place."""
+    from fractions import Fraction as Fr
+    N, L, V = 13, 0.05, 77.25
+    d = I.ccp_desc(ncells=N, ppc=4, length=L)
+    o = oracle.Oracle(d)
+    rng = np.random.Generator(np.random.PCG64(21))
+    for sp in range(2):
+        n = 300
+        o.load(sp, rng.random((n, 1)), np.zeros((n, 3)), w=rng.integers(1, 1 << 17, n).astype(np.uint32),
+               ids=np.arange(sp * n, (sp + 1) * n, dtype=np.uint32))
+    q = o.deposit()
+    phi, _ = o.field_solve_1d(V)
+    dx = L / N
+    kap = [Fr(((sp["charge"] * sp["w0"]) * 2.0 ** -48) * dx / 8.8541878128e-12) for sp in d["species"]]
+    # exact right-hand side and elimination on tridiag(-1, 2, -1), phi_0 = V, phi_N = 0
+    c = [sum(kap[s] * int(q[s][i]) for s in range(2)) for i in range(N + 1)]
+    m = N - 1
+    diag = [Fr(2)] * m
+    rhs = [c[i + 1] for i in range(m)]
+    rhs[0] += Fr(V)
+    for k in range(1, m):
+        f = Fr(-1) / diag[k - 1]
+        diag[k] -= f * Fr(-1)
+        rhs[k] -= f * rhs[k - 1]
+    x = [Fr(0)] * m
+    x[m - 1] = rhs[m - 1] / diag[m - 1]
+    for k in range(m - 2, -1, -1):
+        x[k] = (rhs[k] + x[k + 1]) / diag[k]
+    exact = np.array([float(v) for v in x])
+    assert phi[0] == V and phi[N] == 0.0
+    # a few roundings of terms of either sign: the bound scales with the
+    # magnitude of the terms (the species' potentials nearly cancel)
+    scale = np.array([abs(float(V * (N - i) / N)) + sum(
+        abs(float(kap[s] * sum(min(i, j) * (N - max(i, j)) * int(q[s][j]) for j in range(1, N)) / N))
+        for s in range(2)) for i in range(1, N)])
+    err = np.abs(phi[1:N] - exact) / scale
+    assert err.max() <= 8 * 2.0 ** -52, err.max()
