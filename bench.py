@@ -222,7 +222,7 @@ def cpu_baseline(nparticles, nsteps, seed=2, extra=True):
 
 
 def ensemble_bench(nsteps, ninst=96, tune=True,
-                   modes=("batched", "plain_fp32", "plain", "batched_energy_conserving"), shape=None):
+                   modes=("batched", "plain_fp32", "plain", "batched_energy_conserving"), shape=None, sort_every=50):
     """Batched ensemble of 1D CCP instances (config-0 physics, 96 uneven
     meshes), with the on-device field solve: the FP32 batched path (one
     persistent launch per step, graph replay, autotuned work items), the
@@ -257,7 +257,7 @@ def ensemble_bench(nsteps, ninst=96, tune=True,
                 g.leapfrog_start(j)
             return g
         g = make()
-        kw = dict(solve_field=True, sort_every=20)
+        kw = dict(solve_field=True, sort_every=sort_every)
         tuned = None
         if batched:
             if shape:
@@ -356,6 +356,7 @@ def main():
     ap.add_argument("--only-quadtree", action="store_true", help="measure only the quadtree workload (profiling)")
     ap.add_argument("--ensemble-modes", default="batched,plain_fp32,plain,batched_energy_conserving",
                     help="comma-separated ensemble modes to run with --only-ensemble")
+    ap.add_argument("--ensemble-sort-every", type=int, default=50)
     ap.add_argument("--tile", type=int, default=0, help="batched work-item size (with --grid: skip the autotuner)")
     ap.add_argument("--grid", type=int, default=0, help="batched persistent grid (with --tile)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -388,7 +389,8 @@ def main():
     if args.only_ensemble:
         print(json.dumps({"ensemble": ensemble_bench(args.ensemble_steps, tune=False,
                                                      modes=tuple(args.ensemble_modes.split(",")),
-                                                     shape=shape)}), flush=True)
+                                                     shape=shape, sort_every=args.ensemble_sort_every)}),
+              flush=True)
         return
     if args.only_streamer:
         print(json.dumps({"streamer": streamer_bench(args.streamer_steps)}), flush=True)
@@ -441,7 +443,7 @@ def main():
                                    traffic_from_profile("k_step<float,false,2,true>", f"quadtree {n} electrons")),
                           per="k_step<float,false,2,true> launch, 44 B per particle-update"))
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_bench(args.ensemble_steps, shape=shape)
+        out["ensemble"] = ensemble_bench(args.ensemble_steps, shape=shape, sort_every=args.ensemble_sort_every)
     if not args.no_streamer:
         out["streamer"] = streamer_bench(args.streamer_steps)
     if cpu is not None:

@@ -296,6 +296,8 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   if (tile % kBlock) throw Err(PIC_E_ARG, "batched tile must be a multiple of 256");
   bool ionizing = false, any_mcc = false;
   int maxn = 0;
+  double max_births_rate = 0.0;
+  for (Slot* s : sel) max_births_rate = std::max(max_births_rate, s->births_rate);
   std::vector<int> order(nsel);
   for (int j = 0; j < nsel; ++j) order[j] = j;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -417,7 +419,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)t_items, (uint32_t)issued.size(), t_part, st, grid,
                                        any_mcc),
               "step1d_batched");
-    if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, st), "births_batched");
+    if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, st, 2.0 * max_births_rate), "births_batched");
   };
   auto one_commit = [&](hipStream_t st) {
     if (a->solve_field) hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, st), "field1d batched");

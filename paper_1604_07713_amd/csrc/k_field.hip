@@ -66,13 +66,17 @@ __global__ __launch_bounds__(kField1dThreads) void k_field1d(const InstDev<T>* _
   const int j1 = j0 + per < N ? j0 + per : N;
   const int ns = I.nspecies;
   // q[0..1]: sum j Q_s,j and sum (N - j) Q_s,j of species 0; q[2..3] of species 1
+  // (species loops unrolled with constant indices: the arrays stay in registers)
   u128 q[4] = {0, 0, 0, 0};
-  for (int sp = 0; sp < ns; ++sp)
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+    if (sp >= ns) break;
     for (int j = j0; j < j1; ++j) {
       const u128 v = (u128)Q[(size_t)sp * I.nq + j];
       q[2 * sp] += (u128)(unsigned)j * v;
       q[2 * sp + 1] += (u128)(unsigned)(N - j) * v;
     }
+  }
   // workgroup exclusive scan of the four sums (inclusive within the wave by
   // shuffles, then the totals of the lower waves)
   const int lane = lane_id(), wv = threadIdx.x / 64, nw = blockDim.x / 64;
@@ -91,12 +95,15 @@ __global__ __launch_bounds__(kField1dThreads) void k_field1d(const InstDev<T>* _
     for (int k = 0; k < 4; ++k) wtot[wv][k] = inc[k];
   __syncthreads();
   u128 base[4] = {0, 0, 0, 0}, total[4] = {0, 0, 0, 0};
-  for (int w = 0; w < nw; ++w)
+  for (int w = 0; w < nw; ++w) {
+    const bool lower = w < wv;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (w < wv) base[k] += wtot[w][k];
-      total[k] += wtot[w][k];
+      const u128 t = wtot[w][k];
+      base[k] += lower ? t : (u128)0;
+      total[k] += t;
     }
+  }
   // the thread's nodes: prefix sums through node j, then D and phi
   u128 P[4];
 #pragma unroll
@@ -104,7 +111,9 @@ __global__ __launch_bounds__(kField1dThreads) void k_field1d(const InstDev<T>* _
   const double dN = (double)N;
   for (int j = j0; j < j1; ++j) {
     double v = (left * (double)(N - j)) / dN;
-    for (int sp = 0; sp < ns; ++sp) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      if (sp >= ns) break;
       const u128 qq = (u128)Q[(size_t)sp * I.nq + j];
       P[2 * sp] += (u128)(unsigned)j * qq;
       P[2 * sp + 1] += (u128)(unsigned)(N - j) * qq;

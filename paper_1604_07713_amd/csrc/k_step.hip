@@ -9,6 +9,7 @@
 // global memory once per workgroup.  The deposit is integer (64-bit fixed
 // point), hence exact and independent of the order in which lanes and
 // workgroups add.
+#include <algorithm>
 #include <atomic>
 
 #include "device_util.hpp"
@@ -1451,9 +1452,16 @@ hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned) {
   return hipGetLastError();
 }
 template <class T>
-hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s) {
-  hipLaunchKernelGGL(k_birth_rank_batched<T>, dim3(kRankBlocks, ninst), dim3(kBlock), 0, s, I);
-  hipLaunchKernelGGL(k_birth_write_batched<T>, dim3(kWriteBlocks, ninst), dim3(kBlock), 0, s, I);
+hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s, double births_per_step) {
+  // workgroups per instance from the births expected per step (the kernels
+  // loop over their work, so any count is correct; idle workgroups only cost
+  // dispatch time): ranking work items are (births / 1024) x (births / 256)
+  const double nb = births_per_step > 0 ? births_per_step : 0.0;
+  const double items = (nb / (kRankPer * kBlock) + 1.0) * (nb / kRankChunk + 1.0);
+  const int rank_blocks = (int)std::min<double>(kRankBlocks, std::max(4.0, items / 2.0));
+  const int write_blocks = (int)std::min<double>(kWriteBlocks, std::max(1.0, nb / kBlock + 1.0));
+  hipLaunchKernelGGL(k_birth_rank_batched<T>, dim3(rank_blocks, ninst), dim3(kBlock), 0, s, I);
+  hipLaunchKernelGGL(k_birth_write_batched<T>, dim3(write_blocks, ninst), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
 template <class T>
@@ -1494,7 +1502,7 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
   template hipError_t launch_step1d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
                                                unsigned long long*, hipStream_t, int, bool);               \
   template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, bool);                              \
-  template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
+  template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t, double);               \
   template hipError_t launch_commit<T>(const InstDev<T>&, hipStream_t);                                    \
   template hipError_t launch_commit_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
   template hipError_t launch_stats_reduce<T>(const InstDev<T>*, int, unsigned long long*, const uint32_t*, \

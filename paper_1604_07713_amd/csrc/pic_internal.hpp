@@ -132,7 +132,9 @@ template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const W
 // comparing every pair (work ~ births^2); the host picks it for many births.
 constexpr uint32_t kBirthBins = 4096;
 template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned);
-template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s);
+// births_per_step: the most births per step expected of an instance (sizes the grids)
+template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s,
+                                                    double births_per_step);
 template <class T> hipError_t launch_commit(const InstDev<T>& I, hipStream_t s);
 template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, int ninst, hipStream_t s);
 template <class T> hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long long* rows,
