@@ -102,6 +102,7 @@ def load_lib(path):
     L.or_rho.argtypes = [P, P]
     L.or_corner_phi.argtypes = [P, P]
     L.or_set_next_id.argtypes = [P, C.c_uint32]
+    L.or_gather.argtypes = [P, C.c_int64, P, P]
     return L
 
 
@@ -241,10 +242,21 @@ class Oracle:
         _check(self.L.or_field_set(self.h, kind, _ptr(data)), "or_field_set")
 
     def field_table(self):
-        n = self.nq() if self.dim == 1 else self.nq() * 8
+        if self.dim == 1:
+            n = self.nq()
+        else:
+            n = self.nq() * (2 if self.desc.get("field_scheme", 0) == FIELD_CIC_AMR else 8)
         out = np.zeros(n)
         self.L.or_field_table(self.h, _ptr(out))
-        return out if self.dim == 1 else out.reshape(-1, 4, 2)
+        if self.dim == 1:
+            return out
+        return out.reshape(-1, 2) if self.desc.get("field_scheme", 0) == FIELD_CIC_AMR else out.reshape(-1, 4, 2)
+
+    def gather(self, s):
+        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1, self.dim)
+        out = np.zeros(s.shape)
+        _check(self.L.or_gather(self.h, len(s), _ptr(s), _ptr(out)), "or_gather")
+        return out
 
     def field_solve_1d(self, phi_left):
         n = self.nq()
@@ -300,4 +312,5 @@ class Oracle:
 
 
 # field kinds
-NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D = 0, 1, 2, 3, 4, 5
+NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D, CELL_E_2D = 0, 1, 2, 3, 4, 5, 6
+FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR = 0, 1, 2

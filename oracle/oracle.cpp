@@ -257,6 +257,8 @@ template <class T> struct Sim : SimBase {
   std::vector<T> cornerE;       /* [leaf][corner][2] in T */
   std::vector<double> cornerE64;
   std::vector<double> cornerPhi; /* [leaf][corner]: potentials behind cornerE (if given) */
+  std::vector<T> cellE;          /* [leaf][2]: cell-centred E (cloud-in-cell coupling), in T */
+  std::vector<double> cellE64;
   /* deposit */
   std::vector<uint64_t> Q[2];
 
@@ -389,6 +391,8 @@ template <class T> struct Sim : SimBase {
     cornerE.assign(leaves.size() * 8, (T)0);
     cornerE64.assign(leaves.size() * 8, 0.0);
     cornerPhi.assign(leaves.size() * 4, 0.0);
+    cellE.assign(leaves.size() * 2, (T)0);
+    cellE64.assign(leaves.size() * 2, 0.0);
     for (int s = 0; s < 2; ++s) Q[s].assign(leaves.size(), 0);
   }
 
@@ -473,7 +477,105 @@ template <class T> struct Sim : SimBase {
     return En[i] + f * (En[i + 1] - En[i]);
   }
 
+  /* ---- cloud-in-cell on the quadtree (Sec. 3.1, Fig. 2) ----
+     A particle in leaf l (level L, side h) is a square cloud of side h
+     centred on it.  The cloud covers l and up to three level-L cells beside
+     it: the direct neighbours on the particle's side of l's centre in x and
+     in y, and the diagonal one; its bilinear area fractions, in fixed point
+     with H = F/2 bits per axis, weight them.  Where the tree is not uniform
+     those level-L cells are ghost cells (ghost cells at +-1 level in direct
+     and diagonal neighbours, Sec. 3.1): one that lies inside a coarser leaf
+     belongs to that leaf; one over finer leaves is shared equally among its
+     four quadrants (again where a quadrant is finer still).  A ghost cell
+     outside the domain is folded back across the wall onto the cell inside.
+     The same fractions scatter the charge and gather the cell-centred field
+     (the same shape function both ways, Sec. 3.1). */
+  static const int H = F / 2;
+
+  struct Cloud {
+    uint32_t cx[4], cy[4];   /* centres of own, x-, y-, diagonal cell (16-bit units) */
+    uint64_t share[4];       /* in units of 2^-F of the particle */
+    T wt[4];                 /* the same fractions in T */
+    int level;
+  };
+
+  Cloud cloud(const T s[2], int64_t cell) const {
+    const QNode* lf = leaves[cell];
+    const int L = lf->level;
+    const uint32_t S = 1u << (16 - L);
+    const T sc = (T)std::ldexp(1.0, L);
+    const T gx = (s[0] * sc - (T)lf->ix) - (T)0.5, gy = (s[1] * sc - (T)lf->iy) - (T)0.5;
+    const T ax = gx < (T)0 ? -gx : gx, ay = gy < (T)0 ? -gy : gy;
+    const T one = (T)std::ldexp(1.0, H);
+    const uint64_t rx = (uint64_t)std::rint(ax * one), ry = (uint64_t)std::rint(ay * one);
+    const uint64_t o = (uint64_t)1 << H;
+    Cloud c;
+    c.level = L;
+    const int64_t X = (int64_t)lf->ix * S + S / 2, Y = (int64_t)lf->iy * S + S / 2;
+    const int64_t Xn = X + (gx >= (T)0 ? (int64_t)S : -(int64_t)S);
+    const int64_t Yn = Y + (gy >= (T)0 ? (int64_t)S : -(int64_t)S);
+    const bool xin = Xn >= 0 && Xn < 65536, yin = Yn >= 0 && Yn < 65536;
+    const int64_t xs = xin ? Xn : X, ys = yin ? Yn : Y;   /* folded back at the walls */
+    c.cx[0] = (uint32_t)X;  c.cy[0] = (uint32_t)Y;
+    c.cx[1] = (uint32_t)xs; c.cy[1] = (uint32_t)Y;
+    c.cx[2] = (uint32_t)X;  c.cy[2] = (uint32_t)ys;
+    c.cx[3] = (uint32_t)xs; c.cy[3] = (uint32_t)ys;
+    c.share[0] = (o - rx) * (o - ry);
+    c.share[1] = rx * (o - ry);
+    c.share[2] = (o - rx) * ry;
+    c.share[3] = rx * ry;
+    const T fx = (T)rx / one, fy = (T)ry / one;
+    c.wt[0] = ((T)1 - fx) * ((T)1 - fy);
+    c.wt[1] = fx * ((T)1 - fy);
+    c.wt[2] = ((T)1 - fx) * fy;
+    c.wt[3] = fx * fy;
+    return c;
+  }
+
+  /* units of charge into the level-L cell centred at (X, Y): to the leaf
+     holding it, or split equally (remainder to the first quadrants in Z
+     order) among its quadrants when finer leaves cover it */
+  void scatter_cell(uint32_t X, uint32_t Y, int L, uint64_t units, std::vector<uint64_t>& Qs) const {
+    const QNode* n = locate_node(root.get(), X / 65536.0, Y / 65536.0);
+    if (n->level <= L) {
+      Qs[n->leaf_index] += units;
+      return;
+    }
+    const uint32_t q = 1u << (16 - L - 2);
+    const uint64_t base = units >> 2, rem = units & 3u;
+    for (uint32_t k = 0; k < 4; ++k)
+      scatter_cell((k & 1) ? X + q : X - q, (k >> 1) ? Y + q : Y - q, L + 1, base + (k < rem ? 1u : 0u), Qs);
+  }
+
+  /* cell-centred field of the level-L cell centred at (X, Y): its leaf's, or
+     the mean of its quadrants' (Z order) */
+  void gather_cell(uint32_t X, uint32_t Y, int L, T E[2]) const {
+    const QNode* n = locate_node(root.get(), X / 65536.0, Y / 65536.0);
+    if (n->level <= L) {
+      E[0] = cellE[n->leaf_index * 2];
+      E[1] = cellE[n->leaf_index * 2 + 1];
+      return;
+    }
+    const uint32_t q = 1u << (16 - L - 2);
+    T e[4][2];
+    for (uint32_t k = 0; k < 4; ++k)
+      gather_cell((k & 1) ? X + q : X - q, (k >> 1) ? Y + q : Y - q, L + 1, e[k]);
+    for (int c = 0; c < 2; ++c) E[c] = ((e[0][c] + e[1][c]) + (e[2][c] + e[3][c])) * (T)0.25;
+  }
+
+  void gather_cic_amr(const T s[2], int64_t cell, T E[2]) const {
+    const Cloud c = cloud(s, cell);
+    T e[4][2];
+    for (int k = 0; k < 4; ++k) gather_cell(c.cx[k], c.cy[k], c.level, e[k]);
+    for (int m = 0; m < 2; ++m)
+      E[m] = ((c.wt[0] * e[0][m] + c.wt[1] * e[1][m]) + c.wt[2] * e[2][m]) + c.wt[3] * e[3][m];
+  }
+
   void gather2d(const Particle<T>& q, T E[2]) const {
+    if (d.field_scheme == OR_FIELD_CIC_AMR) {
+      gather_cic_amr(q.s, q.cell, E);
+      return;
+    }
     const QNode* lf = leaves[q.cell];
     T sc = (T)std::ldexp(1.0, lf->level);
     T xi = q.s[0] * sc - (T)lf->ix;
@@ -575,6 +677,10 @@ template <class T> struct Sim : SimBase {
           uint64_t r = (uint64_t)(int64_t)std::rint(f * (T)std::ldexp(1.0, F));
           Q[sp][i] += (uint64_t)q.w * (one - r);
           Q[sp][i + 1] += (uint64_t)q.w * r;
+        } else if (d.field_scheme == OR_FIELD_CIC_AMR) {
+          const Cloud c = cloud(q.s, q.cell);
+          for (int k = 0; k < 4; ++k)
+            if (c.share[k]) scatter_cell(c.cx[k], c.cy[k], c.level, (uint64_t)q.w * c.share[k], Q[sp]);
         } else {
           Q[sp][q.cell] += (uint64_t)q.w;
         }
@@ -659,7 +765,8 @@ template <class T> struct Sim : SimBase {
       double dx = d.length / N;
       return (((s.charge * s.w0) * std::ldexp(1.0, -(16 + F))) * dx) / EPS0;
     }
-    return (((s.charge * s.w0) * std::ldexp(1.0, -16)) / d.depth_z) / EPS0;
+    const int f2 = d.field_scheme == OR_FIELD_CIC_AMR ? F : 0;   /* cloud shares carry F more bits */
+    return (((s.charge * s.w0) * std::ldexp(1.0, -(16 + f2))) / d.depth_z) / EPS0;
   }
 
   /* charge density of the latest deposit: the integer sums scaled to
@@ -676,7 +783,8 @@ template <class T> struct Sim : SimBase {
           r = r + ((units * std::ldexp(1.0, -(16 + F))) * (s.charge * s.w0)) / (d.length / N);
         else {
           const double h = d.length * std::ldexp(1.0, -leaves[i]->level);
-          r = r + ((units * std::ldexp(1.0, -16)) * (s.charge * s.w0)) / ((h * h) * d.depth_z);
+          const int f2 = d.field_scheme == OR_FIELD_CIC_AMR ? F : 0;
+          r = r + ((units * std::ldexp(1.0, -(16 + f2))) * (s.charge * s.w0)) / ((h * h) * d.depth_z);
         }
       }
       out[i] = r;
@@ -797,6 +905,19 @@ template <class T> struct Sim : SimBase {
       }
     }
     for (size_t i = 0; i < cornerE64.size(); ++i) cornerE[i] = (T)cornerE64[i];
+    cell_e_from_corners();
+  }
+
+  /* cell-centred E of each leaf: the mean of its four nodal E values (the
+     gradient of its bilinear potential at the centre when the nodal E come
+     from that potential) */
+  void cell_e_from_corners() {
+    for (size_t l = 0; l < leaves.size(); ++l)
+      for (int k = 0; k < 2; ++k) {
+        const double* c = &cornerE64[l * 8];
+        cellE64[l * 2 + k] = 0.25 * ((c[0 + k] + c[2 + k]) + (c[4 + k] + c[6 + k]));
+        cellE[l * 2 + k] = (T)cellE64[l * 2 + k];
+      }
   }
 
   void corner_field_from_cell_phi(const double* phi) {
@@ -1133,8 +1254,10 @@ void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]
 void* or_create(const or_desc* d) {
   if (!d || (d->dim != 1 && d->dim != 2) || (d->precision != 32 && d->precision != 64) ||
       d->nspecies < 1 || d->nspecies > 2 || !(d->length > 0) || !(d->dt > 0) ||
-      (d->field_scheme != OR_FIELD_CIC_EM && d->field_scheme != OR_FIELD_CIC_EC) ||
-      (d->dim == 2 && d->field_scheme != OR_FIELD_CIC_EM))   /* CIC is for the uniform mesh */
+      (d->field_scheme != OR_FIELD_CIC_EM && d->field_scheme != OR_FIELD_CIC_EC &&
+       d->field_scheme != OR_FIELD_CIC_AMR) ||
+      (d->dim == 2 && d->field_scheme == OR_FIELD_CIC_EC) ||    /* energy-conserving: uniform 1D mesh */
+      (d->dim == 1 && d->field_scheme == OR_FIELD_CIC_AMR))     /* cloud on the tree: 2D */
     return nullptr;
   SimBase* b;
   bool ok;
@@ -1226,6 +1349,12 @@ int or_field_set(void* h, int kind, const double* data) {
     }
     if (kind == OR_CORNER_E_2D) {
       for (size_t i = 0; i < nl * 8; ++i) { S.cornerE64[i] = data[i]; S.cornerE[i] = (T)data[i]; }
+      S.cell_e_from_corners();
+      return OR_OK;
+    }
+    if (kind == OR_CELL_E_2D) {   /* the cloud-in-cell gather table, given directly */
+      if (S.d.field_scheme != OR_FIELD_CIC_AMR) return OR_E_ARG;
+      for (size_t i = 0; i < nl * 2; ++i) { S.cellE64[i] = data[i]; S.cellE[i] = (T)data[i]; }
       return OR_OK;
     }
     if (kind == OR_CELL_PHI_2D) {
@@ -1265,9 +1394,35 @@ int or_field_table(void* h, double* out) {
   return dispatch(h, [&](auto& S) {
     if (S.d.dim == 1)
       for (int i = 0; i <= S.N; ++i) out[i] = (double)S.En[i];
+    else if (S.d.field_scheme == OR_FIELD_CIC_AMR)
+      for (size_t i = 0; i < S.cellE.size(); ++i) out[i] = (double)S.cellE[i];
     else
       for (size_t i = 0; i < S.cornerE.size(); ++i) out[i] = (double)S.cornerE[i];
     return OR_OK;
+  });
+}
+
+int or_gather(void* h, int64_t n, const double* s, double* out) {
+  return dispatch(h, [&](auto& S) {
+    using T = typename std::remove_reference<decltype(S.En)>::type::value_type;
+    for (int64_t i = 0; i < n; ++i) {
+      if (S.d.dim == 1) {
+        const T x = (T)s[i];
+        if (!(x >= (T)0 && x < (T)1)) return (int)OR_E_ARG;
+        out[i] = (double)S.gather1d(x);
+      } else {
+        Particle<T> q;
+        q.s[0] = (T)s[2 * i];
+        q.s[1] = (T)s[2 * i + 1];
+        if (!(q.s[0] >= (T)0 && q.s[0] < (T)1 && q.s[1] >= (T)0 && q.s[1] < (T)1)) return (int)OR_E_ARG;
+        q.cell = S.locate_cell(q.s);
+        T E[2];
+        S.gather2d(q, E);
+        out[2 * i] = (double)E[0];
+        out[2 * i + 1] = (double)E[1];
+      }
+    }
+    return (int)OR_OK;
   });
 }
 

@@ -35,13 +35,17 @@ enum { OR_OK = 0, OR_E_ARG = -1, OR_E_CAPACITY = -3, OR_E_STATE = -5 };
 enum { OR_MCC_NONE = 0, OR_MCC_ELECTRON = 1, OR_MCC_ION_CX = 2 };
 enum { OR_WALL_NEUMANN = 0, OR_WALL_DIRICHLET = 1 };
 enum { OR_ABSORB = 0, OR_REFLECT = 1 };
-/* 1D particle-field coupling, both with CIC charge assignment to nodes (Sec. 3) */
-enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1 };
+/* particle-field coupling: 1D CIC to nodes, momentum- or energy-conserving
+   (Sec. 3); 2D NGP scatter with bilinear gather of nodal E (OR_FIELD_CIC_EM,
+   Sec. 3) or the cloud-in-cell on the quadtree with ghost cells at +-1 level
+   and the same shape function for scatter and gather (OR_FIELD_CIC_AMR,
+   Sec. 3.1) */
+enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1, OR_FIELD_CIC_AMR = 2 };
 /* field kinds for or_field_set.  OR_NODE_E_1D is for the momentum-conserving
    1D coupling (N+1 node values), OR_CELL_E_1D for the energy-conserving one
    (N cell values); each is refused on the other coupling. */
 enum { OR_NODE_E_1D = 0, OR_NODE_PHI_1D = 1, OR_CORNER_PHI_2D = 2, OR_CORNER_E_2D = 3, OR_CELL_PHI_2D = 4,
-       OR_CELL_E_1D = 5 };
+       OR_CELL_E_1D = 5, OR_CELL_E_2D = 6 /* [leaf][2], cloud-in-cell slots only */ };
 
 typedef struct {
   double charge;     /* C */
@@ -125,6 +129,9 @@ int or_leapfrog_start(void* h);
 int or_step(void* h, int64_t step0, int nsteps, const double* v_next, int solve_1d, or_stats* st);
 int or_adapt(void* h, int n_lo, int n_hi, or_adapt_stats* st);
 int or_locate(void* h, int64_t n, const double* s, uint32_t* leaf);
+/* the field the step's gather gives at n positions s[n*dim] (the current
+   table, the slot's coupling): out[n*dim] (test helper) */
+int or_gather(void* h, int64_t n, const double* s, double* out);
 void or_derived(void* h, int species, double* out);
 void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

@@ -31,6 +31,7 @@ MCC_NONE, MCC_ELECTRON, MCC_ION_CX = 0, 1, 2
 WALL_NEUMANN, WALL_DIRICHLET = 0, 1
 ABSORB, REFLECT = 0, 1
 FIELD_CIC_EM, FIELD_CIC_EC = 0, 1   # 1D particle-field coupling (momentum- or energy-conserving CIC)
+FIELD_CIC_AMR = 2                   # 2D: cloud-in-cell on the quadtree (ghost cells at +-1 level)
 
 
 def species(charge, mass, w0=1.0, mcc=MCC_NONE, sigma_el=0.0, sigma_iz=0.0, eps_iz=0.0,

@@ -13,6 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 import pytest
 
 import oracle
+from tests import test_oracle_cic_amr as C
 from tests import test_oracle_tree_pins as P
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.cpp")
@@ -43,6 +44,14 @@ MUTANTS = {
         "if (ox != oy) return ox < oy;",
         "(void)ox; (void)oy;",
         P.check_merge_pairs),
+    "cloud reaches to the wrong side": (
+        "const int64_t Xn = X + (gx >= (T)0 ? (int64_t)S : -(int64_t)S);",
+        "const int64_t Xn = X + (gx >= (T)0 ? -(int64_t)S : (int64_t)S);",
+        lambda L: C.check_area_overlaps(1, L)),
+    "ghost over finer leaves goes to one of them": (
+        "    if (n->level <= L) {\n      Qs[n->leaf_index] += units;",
+        "    if (true) {\n      Qs[n->leaf_index] += units;",
+        lambda L: C.check_area_overlaps(1, L)),
     "merge breaks ties by the larger id": (
         "return P[x].id < P[y].id;",
         "return P[x].id > P[y].id;",
