@@ -83,6 +83,17 @@ enum { PIC_ABSORB = 0, PIC_REFLECT = 1 };
  * conserving (the particle takes its cell's E, the difference of the cell's
  * two node potentials over dx; the field table then holds N cell values). */
 enum { PIC_FIELD_CIC_EM = 0, PIC_FIELD_CIC_EC = 1 };
+/* On the quadtree: NGP scatter to the leaves with bilinear gather of nodal E
+ * (PIC_FIELD_CIC_EM, the default, Sec. 3), or the cloud-in-cell on the
+ * quadtree (Sec. 3.1, Fig. 2): a particle's square cloud of its leaf's size
+ * covers its leaf and the direct and diagonal neighbours on its side, through
+ * ghost cells at +-1 level where the neighbours differ in level (a ghost cell
+ * inside a coarser leaf belongs to it, one over finer leaves is shared by
+ * area, one outside the domain folds back), with the same shape function for
+ * the scatter (charge in fixed point, F/2 bits per axis: exactly conserved)
+ * and for the gather of the cell-centred E (the mean of each leaf's nodal E,
+ * or PIC_CELL_E_2D). */
+enum { PIC_FIELD_CIC_AMR = 2 };
 enum { PIC_FP32 = 32, PIC_FP64 = 64 };
 /* field kinds for pic_field_set (Sec. 3: potential at cell centres or nodes,
  * E at the nodes for the gather) */
@@ -92,7 +103,8 @@ enum {
   PIC_CORNER_PHI_2D = 2, /* double[nleaves][4]: potential at leaf corners     */
   PIC_CORNER_E_2D = 3,   /* double[nleaves][4][2]: nodal E at leaf corners    */
   PIC_CELL_PHI_2D = 4,   /* double[nleaves]: cell-centre potential            */
-  PIC_CELL_E_1D = 5      /* double[ncells]: E of each cell, V/m (energy-conserving slots only) */
+  PIC_CELL_E_1D = 5,     /* double[ncells]: E of each cell, V/m (energy-conserving slots only) */
+  PIC_CELL_E_2D = 6      /* double[nleaves][2]: cell-centred E, V/m (cloud-in-cell slots only) */
 };
 /* corner order of a leaf: 0 = (x0,y0), 1 = (x1,y0), 2 = (x0,y1), 3 = (x1,y1) */
 
@@ -131,8 +143,9 @@ typedef struct {
                            least the loaded count, rounded up to 256), or 0 =
                            3x the loaded count + 4096 when ionizing, else the
                            count; pic_step grows them as births need room     */
-  int field_scheme;     /* 1D: PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC; 2D: must be
-                           PIC_FIELD_CIC_EM (NGP deposit, bilinear gather)      */
+  int field_scheme;     /* 1D: PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC; 2D:
+                           PIC_FIELD_CIC_EM (NGP deposit, bilinear gather) or
+                           PIC_FIELD_CIC_AMR (cloud-in-cell on the tree)       */
   /* 2D explicit tree (Sec. 3.1: cell-based quadtree; nleaves > 0 selects it,
      base_level and the disk refinement are then ignored): leaf_keys[nleaves]
      the Morton code of each leaf's low corner in 16-bit units (x in the even
@@ -238,13 +251,15 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
 int pic_step(pic_ctx c, const pic_step_args* a, pic_step_stats* stats);
 
 /* Deposit the current particles (Sec. 3: CIC to the nodes of the uniform 1D
- * mesh, NGP to the leaf cells of the quadtree; Sec. 3.1: no per-level volume
- * weighting) and copy out, each nullable:
- *   q_out[2][nq]  per-species integer charge sums, in weight units (2D:
- *                 w_units; 1D: w_units * 2^F, F = 24 FP32, 32 FP64);
+ * mesh, NGP to the leaf cells of the quadtree; Sec. 3.1: the cloud-in-cell on
+ * the quadtree, and no per-level volume weighting) and copy out, each
+ * nullable:
+ *   q_out[2][nq]  per-species integer charge sums, in weight units (NGP:
+ *                 w_units; 1D and the 2D cloud: w_units * 2^F, F = 24 FP32,
+ *                 32 FP64);
  *   rho_out[nq]   charge density, C/m^3: sum over species of
- *                 q w0 2^-16 (2^-F in 1D) sums over dx (1D, per unit area)
- *                 or over h^2 depth_z (2D, h the leaf side).
+ *                 q w0 2^-16 (2^-F with a cloud) sums over dx (1D, per unit
+ *                 area) or over h^2 depth_z (2D, h the leaf side).
  * nq = pic_nq (nodes in 1D, leaves in 2D); host buffers of the caller. */
 int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out);
 
@@ -361,8 +376,12 @@ int pic_leaves_read(pic_ctx c, int slot, uint32_t* keys, uint8_t* levels);
 /* entries of the charge sums and densities: nodes (1D) or leaves (2D) */
 int64_t pic_nq(pic_ctx c, int slot);
 /* the gather table as double: 1D [ncells+1] node E (cell E for energy-
- * conserving slots, last entry 0); 2D [nleaves][4][2] corner E (Sec. 3) */
+ * conserving slots, last entry 0); 2D [nleaves][4][2] corner E (Sec. 3), or
+ * [nleaves][2] cell E for cloud-in-cell slots (Sec. 3.1) */
 int pic_field_read(pic_ctx c, int slot, double* out);
+/* the field E the step's gather gives at n points s[n*dim] (normalised, in
+ * [0,1)): out[n*dim], V/m (Sec. 3 / 3.1 gather); PIC_E_ARG for a point outside */
+int pic_gather(pic_ctx c, int slot, int64_t n, const double* s, double* out);
 /* drop holes and order the particles by cell (Sec. 3.1 cell-based lists;
  * the results of later steps do not depend on it) */
 int pic_sort(pic_ctx c, int slot);

@@ -485,8 +485,8 @@ template <class T> struct Sim : SimBase {
      with H = F/2 bits per axis, weight them.  Where the tree is not uniform
      those level-L cells are ghost cells (ghost cells at +-1 level in direct
      and diagonal neighbours, Sec. 3.1): one that lies inside a coarser leaf
-     belongs to that leaf; one over finer leaves is shared equally among its
-     four quadrants (again where a quadrant is finer still).  A ghost cell
+     belongs to that leaf; one over finer leaves is shared among them in
+     proportion to their area.  A ghost cell
      outside the domain is folded back across the wall onto the cell inside.
      The same fractions scatter the charge and gather the cell-centred field
      (the same shape function both ways, Sec. 3.1). */
@@ -532,35 +532,55 @@ template <class T> struct Sim : SimBase {
     return c;
   }
 
-  /* units of charge into the level-L cell centred at (X, Y): to the leaf
-     holding it, or split equally (remainder to the first quadrants in Z
-     order) among its quadrants when finer leaves cover it */
-  void scatter_cell(uint32_t X, uint32_t Y, int L, uint64_t units, std::vector<uint64_t>& Qs) const {
-    const QNode* n = locate_node(root.get(), X / 65536.0, Y / 65536.0);
+  /* The leaves that make up the level-L cell centred at (X, Y) (16-bit
+     units): the one leaf holding it (at level L or coarser), or the finer
+     leaves tiling it, which follow each other in Morton order.  Returns the
+     index of the first and the count; level differences in 'dl'. */
+  int64_t cell_leaves(uint32_t X, uint32_t Y, int L, std::vector<int>& dl) const {
+    const uint32_t S = 1u << (16 - L);
+    const uint32_t X0 = X - S / 2, Y0 = Y - S / 2;
+    const QNode* n = locate_node(root.get(), X0 / 65536.0, Y0 / 65536.0);
+    dl.clear();
     if (n->level <= L) {
-      Qs[n->leaf_index] += units;
-      return;
+      dl.push_back(0);
+      return n->leaf_index;
     }
-    const uint32_t q = 1u << (16 - L - 2);
-    const uint64_t base = units >> 2, rem = units & 3u;
-    for (uint32_t k = 0; k < 4; ++k)
-      scatter_cell((k & 1) ? X + q : X - q, (k >> 1) ? Y + q : Y - q, L + 1, base + (k < rem ? 1u : 0u), Qs);
+    const double x0 = X0 / 65536.0, y0 = Y0 / 65536.0, x1 = (X0 + S) / 65536.0, y1 = (Y0 + S) / 65536.0;
+    for (size_t l = (size_t)n->leaf_index; l < leaves.size(); ++l) {
+      const QNode* m = leaves[l];
+      if (!(m->x0() >= x0 && m->x1() <= x1 && m->y0() >= y0 && m->y1() <= y1)) break;
+      dl.push_back(m->level - L);
+    }
+    return n->leaf_index;
+  }
+
+  /* units of charge into the level-L cell centred at (X, Y): all to the leaf
+     holding it, or to the finer leaves tiling it in proportion to their area
+     (units / 4^(level difference), rounded down; what the rounding leaves
+     goes to the first of them) */
+  void scatter_cell(uint32_t X, uint32_t Y, int L, uint64_t units, std::vector<uint64_t>& Qs) const {
+    std::vector<int> dl;
+    const int64_t first = cell_leaves(X, Y, L, dl);
+    uint64_t given = 0;
+    for (size_t k = 0; k < dl.size(); ++k) {
+      const uint64_t part = units >> (2 * dl[k]);
+      Qs[first + (int64_t)k] += part;
+      given += part;
+    }
+    Qs[first] += units - given;
   }
 
   /* cell-centred field of the level-L cell centred at (X, Y): its leaf's, or
-     the mean of its quadrants' (Z order) */
+     the area-weighted mean of the finer leaves tiling it, summed in Morton
+     order */
   void gather_cell(uint32_t X, uint32_t Y, int L, T E[2]) const {
-    const QNode* n = locate_node(root.get(), X / 65536.0, Y / 65536.0);
-    if (n->level <= L) {
-      E[0] = cellE[n->leaf_index * 2];
-      E[1] = cellE[n->leaf_index * 2 + 1];
-      return;
+    std::vector<int> dl;
+    const int64_t first = cell_leaves(X, Y, L, dl);
+    E[0] = E[1] = (T)0;
+    for (size_t k = 0; k < dl.size(); ++k) {
+      const T f = (T)std::ldexp(1.0, -2 * dl[k]);
+      for (int c = 0; c < 2; ++c) E[c] = E[c] + cellE[(first + (int64_t)k) * 2 + c] * f;
     }
-    const uint32_t q = 1u << (16 - L - 2);
-    T e[4][2];
-    for (uint32_t k = 0; k < 4; ++k)
-      gather_cell((k & 1) ? X + q : X - q, (k >> 1) ? Y + q : Y - q, L + 1, e[k]);
-    for (int c = 0; c < 2; ++c) E[c] = ((e[0][c] + e[1][c]) + (e[2][c] + e[3][c])) * (T)0.25;
   }
 
   void gather_cic_amr(const T s[2], int64_t cell, T E[2]) const {

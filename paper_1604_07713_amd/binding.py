@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 _LIB = None
 
 PIC_OK, PIC_E_ARG, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
-FIELD_CIC_EM, FIELD_CIC_EC = 0, 1   # 1D particle-field coupling (include/pic.h)
+FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR = 0, 1, 2   # particle-field couplings (include/pic.h)
 ABI_VERSION = 3                     # PIC_ABI_VERSION of include/pic.h
-NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D = 0, 1, 2, 3, 4, 5
+NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D, CELL_E_2D = 0, 1, 2, 3, 4, 5, 6
 
 
 class LibraryMissing(RuntimeError):
@@ -112,6 +112,7 @@ EXPORTS = {
     "pic_field_read": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "pic_sort": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_locate": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
+    "pic_gather": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
     "pic_derived": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "pic_philox": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pic_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -334,10 +335,20 @@ class Context:
         self._check(lib().pic_field_set(self.h, slot, kind, _p(data)))
 
     def field_table(self, slot=0):
-        n = self.nq(slot) if self.dim(slot) == 1 else self.nq(slot) * 8
+        cic = self.dim(slot) == 2 and self._slot_desc[slot].get("field_scheme", 0) == FIELD_CIC_AMR
+        n = self.nq(slot) if self.dim(slot) == 1 else self.nq(slot) * (2 if cic else 8)
         out = np.zeros(n)
         self._check(lib().pic_field_read(self.h, slot, _p(out)))
-        return out if self.dim(slot) == 1 else out.reshape(-1, 4, 2)
+        if self.dim(slot) == 1:
+            return out
+        return out.reshape(-1, 2) if cic else out.reshape(-1, 4, 2)
+
+    def gather(self, slot, s):
+        dim = self.dim(slot)
+        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1, dim)
+        out = np.zeros(s.shape)
+        self._check(lib().pic_gather(self.h, slot, len(s), _p(s), _p(out)))
+        return out
 
     def field_solve_1d(self, slot, phi_left):
         n = self.nq(slot)

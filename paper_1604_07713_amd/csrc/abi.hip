@@ -106,6 +106,14 @@ Mesh2D mesh_of(const Slot& sl) {
   return m;
 }
 
+// The cell-centred E table of a cloud-in-cell slot from its FP64 corner
+// table (after every change of the corner table).
+void refresh_cell_e(Ctx& C, Slot& sl) {
+  if (sl.d.dim != 2 || sl.d.field_scheme != PIC_FIELD_CIC_AMR || !sl.cellE) return;
+  if (sl.prec == 32) hip_check(launch_cell_e<float>(sl.e64, sl.nleaves, (float*)sl.cellE, C.stream), "cell_e");
+  else hip_check(launch_cell_e<double>(sl.e64, sl.nleaves, (double*)sl.cellE, C.stream), "cell_e");
+}
+
 void* dev_upload(Ctx& C, Slot& sl, const void* host, size_t bytes) {
   void* d = sl.alloc(bytes);
   hip_check(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, C.stream), "upload");
@@ -775,13 +783,24 @@ int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
     hip_check(hipMemcpy(sl.e64, data, 8 * 8 * n, hipMemcpyHostToDevice), "upload");
     if (sl.prec == 32) hip_check(launch_round_table<float>(sl.e64, (float*)sl.E, (int64_t)(8 * n), c->stream), "round");
     else hip_check(launch_round_table<double>(sl.e64, (double*)sl.E, (int64_t)(8 * n), c->stream), "round");
+    refresh_cell_e(*c, sl);
     c->sync();
+    return PIC_OK;
+  } else if (kind == PIC_CELL_E_2D) {   // the cloud's gather table, given directly
+    if (sl.d.field_scheme != PIC_FIELD_CIC_AMR) throw Err(PIC_E_ARG, "cell E is for cloud-in-cell slots");
+    double* tmp = (double*)sl.alloc(8 * 2 * n);
+    hip_check(hipMemcpy(tmp, data, 8 * 2 * n, hipMemcpyHostToDevice), "upload");
+    if (sl.prec == 32) hip_check(launch_round_table<float>(tmp, (float*)sl.cellE, (int64_t)(2 * n), c->stream), "round");
+    else hip_check(launch_round_table<double>(tmp, (double*)sl.cellE, (int64_t)(2 * n), c->stream), "round");
+    c->sync();
+    sl.release(tmp);
     return PIC_OK;
   } else {
     throw Err(PIC_E_ARG, "bad field kind for 2D");
   }
   if (sl.prec == 32) hip_check(launch_corner_field<float>(m, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner");
   else hip_check(launch_corner_field<double>(m, sl.cphi, sl.grad, sl.e64, (double*)sl.E, c->stream), "corner");
+  refresh_cell_e(*c, sl);
   c->sync();
   return PIC_OK;
   PIC_GUARD_END(c)
@@ -790,10 +809,11 @@ int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
 int pic_field_read(pic_ctx c, int slot, double* out) {
   PIC_GUARD_BEGIN
   Slot& sl = get_slot(c, slot);
-  const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1 : (size_t)sl.nleaves * 8;
+  const bool cic = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR;
+  const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1 : (size_t)sl.nleaves * (cic ? 2 : 8);
   std::vector<char> tmp(sl.esz * n);
   c->sync();
-  hip_check(hipMemcpy(tmp.data(), sl.E, sl.esz * n, hipMemcpyDeviceToHost), "read");
+  hip_check(hipMemcpy(tmp.data(), cic ? sl.cellE : sl.E, sl.esz * n, hipMemcpyDeviceToHost), "read");
   for (size_t i = 0; i < n; ++i) out[i] = sl.esz == 4 ? (double)((float*)tmp.data())[i] : ((double*)tmp.data())[i];
   return PIC_OK;
   PIC_GUARD_END(c)
@@ -826,7 +846,8 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out) {
     for (int sp = 0; sp < sl.d.nspecies; ++sp) qw0[sp] = sl.d.species[sp].charge * sl.d.species[sp].w0;
     double* r = (double*)sl.alloc(8 * (size_t)sl.nq);
     const bool two = sl.d.dim == 2;
-    hip_check(launch_rho(latest, sl.nq, sl.d.nspecies, qw0[0], qw0[1], two ? 16 : 16 + F,
+    const bool cloud = !two || sl.d.field_scheme == PIC_FIELD_CIC_AMR;   // shares carry F more bits
+    hip_check(launch_rho(latest, sl.nq, sl.d.nspecies, qw0[0], qw0[1], cloud ? 16 + F : 16,
                          two ? 0.0 : sl.d.length / sl.d.ncells, two ? sl.lv : nullptr, sl.d.length, sl.d.depth_z, r,
                          c->stream),
               "rho");
@@ -925,6 +946,7 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   hip_check(launch_cell_to_corner_phi(m, sl.phi64, sl.cphi, c->stream), "cell_to_corner");
   if (sl.prec == 32) hip_check(launch_corner_field<float>(m, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner");
   else hip_check(launch_corner_field<double>(m, sl.cphi, sl.grad, sl.e64, (double*)sl.E, c->stream), "corner");
+  refresh_cell_e(*c, sl);
   c->sync();
   if (phi_out) hip_check(hipMemcpy(phi_out, sl.phi64, 8 * (size_t)n, hipMemcpyDeviceToHost), "read");
   if (e_out) hip_check(hipMemcpy(e_out, sl.e64, 8 * 8 * (size_t)n, hipMemcpyDeviceToHost), "read");
@@ -1160,6 +1182,27 @@ int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf) 
   hip_check(hipMemcpy(leaf, dl, 4 * (size_t)n, hipMemcpyDeviceToHost), "read");
   (void)hipFree(ds);
   (void)hipFree(dl);
+  return PIC_OK;
+  PIC_GUARD_END(c)
+}
+
+int pic_gather(pic_ctx c, int slot, int64_t n, const double* s, double* out) {
+  PIC_GUARD_BEGIN
+  Slot& sl = get_slot(c, slot);
+  const int dim = sl.d.dim;
+  if (n < 0 || (n > 0 && (!s || !out))) throw Err(PIC_E_ARG, "bad arguments");
+  for (int64_t i = 0; i < n * dim; ++i)
+    if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "point outside [0,1)");
+  if (n == 0) return PIC_OK;
+  double* ds = (double*)sl.alloc(8 * (size_t)(n * dim));
+  double* dout = (double*)sl.alloc(8 * (size_t)(n * dim));
+  hip_check(hipMemcpy(ds, s, 8 * (size_t)(n * dim), hipMemcpyHostToDevice), "upload");
+  if (sl.prec == 32) hip_check(launch_gather_points<float>(make_dev<float>(sl), ds, n, dout, c->stream), "gather");
+  else hip_check(launch_gather_points<double>(make_dev<double>(sl), ds, n, dout, c->stream), "gather");
+  c->sync();
+  hip_check(hipMemcpy(out, dout, 8 * (size_t)(n * dim), hipMemcpyDeviceToHost), "read");
+  sl.release(ds);
+  sl.release(dout);
   return PIC_OK;
   PIC_GUARD_END(c)
 }

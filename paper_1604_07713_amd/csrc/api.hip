@@ -197,7 +197,8 @@ void derive(Slot& sl) {
       const double dx = d.length / d.ncells;
       sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -(16 + F))) * dx) / kEPS0;
     } else {
-      sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -16)) / d.depth_z) / kEPS0;
+      const int f2 = d.field_scheme == PIC_FIELD_CIC_AMR ? F : 0;   // cloud shares carry F more bits
+      sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -(16 + f2))) / d.depth_z) / kEPS0;
     }
   }
   if (d.dim == 1) sl.inv2dx = 1.0 / (2.0 * (d.length / d.ncells));
@@ -422,10 +423,13 @@ void validate(const pic_instance_desc& d) {
   if (d.dim == 2 && (d.min_level < 0 || d.max_level > 14 || d.min_level > d.max_level || d.base_level < d.min_level ||
                      d.base_level > d.max_level))
     throw Err(PIC_E_ARG, "2D levels must satisfy 0 <= min <= base <= max <= 14");
-  if (d.field_scheme != PIC_FIELD_CIC_EM && d.field_scheme != PIC_FIELD_CIC_EC)
-    throw Err(PIC_E_ARG, "field_scheme must be PIC_FIELD_CIC_EM or PIC_FIELD_CIC_EC");
-  if (d.dim == 2 && d.field_scheme != PIC_FIELD_CIC_EM)
+  if (d.field_scheme != PIC_FIELD_CIC_EM && d.field_scheme != PIC_FIELD_CIC_EC &&
+      d.field_scheme != PIC_FIELD_CIC_AMR)
+    throw Err(PIC_E_ARG, "unknown field_scheme");
+  if (d.dim == 2 && d.field_scheme == PIC_FIELD_CIC_EC)
     throw Err(PIC_E_ARG, "the energy-conserving coupling is for the uniform 1D mesh");
+  if (d.dim == 1 && d.field_scheme == PIC_FIELD_CIC_AMR)
+    throw Err(PIC_E_ARG, "the cloud-in-cell on the tree is for 2D slots");
   if (d.nleaves < 0 || (d.nleaves > 0 && d.dim != 2)) throw Err(PIC_E_ARG, "an explicit tree is for 2D slots");
   for (int s = 0; s < d.nspecies; ++s) {
     const pic_species_desc& sp = d.species[s];
@@ -462,8 +466,10 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   hip_check(launch_build_lut(sl.key, sl.lv, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut");
   // per-leaf field and deposit arrays
   for (void* p : {(void*)sl.E, (void*)sl.e64, (void*)sl.cphi, (void*)sl.grad, (void*)sl.Q, (void*)sl.off,
-                  (void*)sl.st.nbr, (void*)sl.st.code, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
+                  (void*)sl.st.nbr, (void*)sl.st.code, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws,
+                  sl.cellE})
     sl.release(p);
+  sl.cellE = nullptr;
   sl.st = Stencil2D{nullptr, nullptr, nullptr, nullptr};
   sl.cg_ws = nullptr;
   sl.stencil_ok = false;
@@ -477,6 +483,10 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   sl.off = (uint32_t*)sl.alloc(4 * ((size_t)sl.nq + 1 + scan_tmp_words((uint32_t)sl.nq)));
   sl.scan_tmp = sl.off + sl.nq + 1;   // scratch of the multi-block scan of the sort
   hip_check(hipMemsetAsync(sl.E, 0, sl.esz * 8 * sl.nleaves, C.stream), "memset");
+  if (sl.d.field_scheme == PIC_FIELD_CIC_AMR) {   // the cloud's cell-centred E table
+    sl.cellE = sl.alloc(sl.esz * 2 * sl.nleaves);
+    hip_check(hipMemsetAsync(sl.cellE, 0, sl.esz * 2 * sl.nleaves, C.stream), "memset");
+  }
   hip_check(hipMemsetAsync(sl.e64, 0, 64 * (size_t)sl.nleaves, C.stream), "memset");
   hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
   // the next 2D solve starts from the potential of the old tree
@@ -672,6 +682,8 @@ InstDev<T> make_dev(const Slot& sl) {
   I.kappa[1] = sl.kappa[1];
   I.inv2dx = sl.inv2dx;
   I.cell_e = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_CIC_EC ? 1 : 0;
+  I.cic_amr = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR ? 1 : 0;
+  I.cellE = (const T*)sl.cellE;
   I.phi64 = sl.phi64;
   I.e64 = sl.e64;
   return I;

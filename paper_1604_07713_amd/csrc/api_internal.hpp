@@ -100,6 +100,7 @@ struct Slot {
   uint32_t birth_cap = 0;
   // field tables
   void* E = nullptr;
+  void* cellE = nullptr;   // 2D cloud-in-cell: cell-centred E [nleaves][2] in the particle precision
   double *e64 = nullptr, *phi64 = nullptr, *cphi = nullptr, *grad = nullptr;
   // 2D mesh
   uint32_t *key = nullptr, *xy = nullptr, *lut = nullptr;

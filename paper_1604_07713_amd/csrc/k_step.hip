@@ -169,6 +169,10 @@ struct FixedPoint<double> {
   static constexpr int F = 32;
 };
 
+// the cloud-in-cell gather on the quadtree (defined with its scatter below)
+template <class T>
+__device__ __forceinline__ void gather_cic(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T& ex, T& ey);
+
 // ---------------------------------------------------------------------------
 // Deposit pre-aggregation: each workgroup owns a window of kWin consecutive
 // cells in LDS (its particles are a contiguous, cell-ordered range, so their
@@ -1370,7 +1374,8 @@ __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
         G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * E;
       } else {
         T ex, ey;
-        gather2d<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], ex, ey);
+        if (I.cic_amr) gather_cic<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], ex, ey);
+        else gather2d<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], ex, ey);
         G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * ex;
         G(I.v[sp][1])[i] = G(I.v[sp][1])[i] - h * ey;
       }
@@ -1390,12 +1395,321 @@ __global__ __launch_bounds__(kBlock) void k_relocate(InstDev<T> I, int sp) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cloud-in-cell on the quadtree (Sec. 3.1, Fig. 2).  A particle in leaf l
+// (level L, side h) is a square cloud of side h centred on it, covering l and
+// up to three level-L cells beside it (the direct neighbours on the
+// particle's side of l's centre in x and in y, and the diagonal one), with
+// the bilinear area fractions in fixed point, F/2 bits per axis.  Where the
+// tree is not uniform those cells are ghost cells (ghost cells at +-1 level
+// in direct and diagonal neighbours, Sec. 3.1): inside a coarser leaf a ghost
+// cell belongs to it; over finer leaves (which follow each other in Morton
+// order) it is shared among them by area.  A ghost cell outside the domain is
+// folded back across the wall.  The same fractions scatter the charge and
+// gather the cell-centred field (the same shape function both ways).
+// ---------------------------------------------------------------------------
+template <class T>
+struct Cloud {
+  int32_t cx[4], cy[4];        // centres of own, x-, y- and diagonal cells (16-bit units)
+  unsigned long long share[4]; // in units of 2^-F of the particle
+  T wt[4];                     // the same fractions in T
+  int level;
+};
+
+template <class T>
+__device__ __forceinline__ Cloud<T> cloud_at(const InstDev<T>& I, uint32_t leaf, T sx, T sy) {
+  constexpr int H = FixedPoint<T>::F / 2;
+  const uint32_t xy = G(I.leaf_xy)[leaf];
+  const int L = (int)G(I.leaf_lv)[leaf];
+  const int32_t S = 1 << (16 - L);
+  const uint32_t X0 = xy >> 16, Y0 = xy & 0xFFFFu;
+  const T sc = (T)(1u << L);
+  const T gx = (sx * sc - (T)(X0 >> (16 - L))) - (T)0.5;
+  const T gy = (sy * sc - (T)(Y0 >> (16 - L))) - (T)0.5;
+  const T ax = gx < (T)0 ? -gx : gx, ay = gy < (T)0 ? -gy : gy;
+  const T one = (T)(1u << H);
+  const unsigned long long rx = (unsigned long long)rint(ax * one), ry = (unsigned long long)rint(ay * one);
+  const unsigned long long o = 1ull << H;
+  Cloud<T> c;
+  c.level = L;
+  const int32_t X = (int32_t)X0 + S / 2, Y = (int32_t)Y0 + S / 2;
+  const int32_t Xn = X + (gx >= (T)0 ? S : -S), Yn = Y + (gy >= (T)0 ? S : -S);
+  const int32_t xs = (Xn >= 0 && Xn < 65536) ? Xn : X;   // folded back at the walls
+  const int32_t ys = (Yn >= 0 && Yn < 65536) ? Yn : Y;
+  c.cx[0] = X;  c.cy[0] = Y;
+  c.cx[1] = xs; c.cy[1] = Y;
+  c.cx[2] = X;  c.cy[2] = ys;
+  c.cx[3] = xs; c.cy[3] = ys;
+  c.share[0] = (o - rx) * (o - ry);
+  c.share[1] = rx * (o - ry);
+  c.share[2] = (o - rx) * ry;
+  c.share[3] = rx * ry;
+  const T fx = (T)rx / one, fy = (T)ry / one;
+  c.wt[0] = ((T)1 - fx) * ((T)1 - fy);
+  c.wt[1] = fx * ((T)1 - fy);
+  c.wt[2] = ((T)1 - fx) * fy;
+  c.wt[3] = fx * fy;
+  return c;
+}
+
+// First leaf of the level-L cell centred at (X, Y): the leaf holding its low
+// corner.  If that leaf is at level L or coarser it holds the whole cell
+// (coarse = true); else the cell is tiled by it and the leaves after it
+// whose keys stay below the cell's end.
+template <class T>
+__device__ __forceinline__ uint32_t cell_first(const InstDev<T>& I, int32_t X, int32_t Y, int L, bool& coarse,
+                                               uint64_t& key_end) {
+  const uint32_t S = 1u << (16 - L);
+  const uint32_t X0 = (uint32_t)X - S / 2, Y0 = (uint32_t)Y - S / 2;
+  const uint32_t f = locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, X0, Y0, I.lut_direct != 0);
+  coarse = (int)G(I.leaf_lv)[f] <= L;
+  key_end = (uint64_t)morton2(X0, Y0) + ((uint64_t)S * (uint64_t)S);
+  return f;
+}
+
+template <class T>
+__device__ __forceinline__ void gather_cell(const InstDev<T>& I, int32_t X, int32_t Y, int L, T& ex, T& ey) {
+  bool coarse;
+  uint64_t kend;
+  uint32_t l = cell_first(I, X, Y, L, coarse, kend);
+  ex = (T)0;
+  ey = (T)0;
+  if (coarse) {
+    ex = ex + G(I.cellE)[2 * l];
+    ey = ey + G(I.cellE)[2 * l + 1];
+    return;
+  }
+  for (; l < I.nleaves && (uint64_t)G(I.leaf_key)[l] < kend; ++l) {
+    const T f = (T)ldexp(1.0, -2 * ((int)G(I.leaf_lv)[l] - L));
+    ex = ex + G(I.cellE)[2 * l] * f;
+    ey = ey + G(I.cellE)[2 * l + 1] * f;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void gather_cic(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T& ex, T& ey) {
+  const Cloud<T> c = cloud_at<T>(I, leaf, sx, sy);
+  T e0[4], e1[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gather_cell<T>(I, c.cx[k], c.cy[k], c.level, e0[k], e1[k]);
+  ex = ((c.wt[0] * e0[0] + c.wt[1] * e0[1]) + c.wt[2] * e0[2]) + c.wt[3] * e0[3];
+  ey = ((c.wt[0] * e1[0] + c.wt[1] * e1[1]) + c.wt[2] * e1[2]) + c.wt[3] * e1[3];
+}
+
+// units of charge into the level-L cell centred at (X, Y): to its leaf, or by
+// area to the finer leaves tiling it (rounded down; the rest to the first)
+template <class T, class Add>
+__device__ __forceinline__ void scatter_cell(const InstDev<T>& I, int32_t X, int32_t Y, int L,
+                                             unsigned long long units, Add add) {
+  bool coarse;
+  uint64_t kend;
+  const uint32_t f = cell_first(I, X, Y, L, coarse, kend);
+  if (coarse) {
+    add(f, units);
+    return;
+  }
+  unsigned long long given = 0ull;
+  for (uint32_t l = f; l < I.nleaves && (uint64_t)G(I.leaf_key)[l] < kend; ++l) {
+    const unsigned long long part = units >> (2 * ((int)G(I.leaf_lv)[l] - L));
+    add(l, part);
+    given += part;
+  }
+  add(f, units - given);
+}
+
+template <class T, class Add>
+__device__ __forceinline__ void scatter_cic(const InstDev<T>& I, uint32_t leaf, T sx, T sy, uint32_t w, Add add) {
+  const Cloud<T> c = cloud_at<T>(I, leaf, sx, sy);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (c.share[k]) scatter_cell<T>(I, c.cx[k], c.cy[k], c.level, (unsigned long long)w * c.share[k], add);
+}
+
+// The particle loop of a quadtree slot with the cloud-in-cell coupling: one
+// particle per lane, in place (gather from the cell-centred field table,
+// push, walls, locate, MCC with births, deposit of the cloud).  Workgroups
+// take contiguous ranges of a species as k_step does.
+template <class T, bool MCC>
+__global__ __launch_bounds__(kBlock) void k_step2d_cic(InstDev<T> I, int commit) {
+  if (step_blocked<T>(I)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&I.ctr->flags, kFlagNeedRoom);
+    return;
+  }
+  const uint32_t step = I.ctr->step;
+  const uint32_t n0 = I.ctr->count[0];
+  const uint32_t n1 = I.nspecies == 2 ? I.ctr->count[1] : 0u;
+  const uint32_t grid = gridDim.x;
+  uint32_t gs = grid;
+  if (I.nspecies == 2) {
+    gs = (uint32_t)(((uint64_t)grid * n0 + ((uint64_t)n0 + n1) / 2u) / ((uint64_t)n0 + n1 + 1u));
+    if (gs < 1u) gs = 1u;
+    if (gs > grid - 1u) gs = grid - 1u;
+  }
+  const int sp = blockIdx.x >= gs ? 1 : 0;
+  const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - gs;
+  const uint32_t nb = sp == 0 ? gs : grid - gs;
+  const uint32_t count = sp == 0 ? n0 : n1;
+  const uint32_t chunk = ((count + nb - 1u) / nb + kBlock - 1u) / kBlock * kBlock;
+  unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
+  zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
+  const uint64_t begin64 = (uint64_t)b * chunk;
+  const uint32_t begin = begin64 < count ? (uint32_t)begin64 : count;
+  const uint32_t end = (uint64_t)begin + chunk < count ? begin + chunk : count;
+  unsigned long long* row = I.part + (size_t)blockIdx.x * kNStat;
+  unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
+  unsigned long long* Qi = Qpar + I.nq;
+  const DepLds Ld = dep_lds();
+  DepCache D{Ld.win, Ld.hkey, Ld.hval, 0u};
+  dep_zero(D);
+  if (threadIdx.x == 0) {
+    const uint32_t c0 = begin < end && G(I.w[sp])[begin] ? G(I.cell[sp])[begin] : 0u;
+    *Ld.wbase = c0 > kWin / 2u ? c0 - kWin / 2u : 0u;
+  }
+  __syncthreads();
+  D.base = *Ld.wbase;
+  const SpeciesK<T> k = I.sk[sp];
+  const bool mcc = MCC && k.mcc != PIC_MCC_NONE;
+  const bool reflect = I.particle_bc == PIC_REFLECT;
+  LStat st = {0, 0, 0, 0, 0, 0, 0};
+  auto add_own = [&](uint32_t l, unsigned long long v) { dep_add(D, Qs, l, v); };
+  auto add_ion = [&](uint32_t l, unsigned long long v) {
+    if (v) gadd(Qi + l, v);
+  };
+  for (uint32_t base = begin; base < end; base += kBlock) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t w = i < end ? G(I.w[sp])[i] : 0u;
+    bool live = w != 0u;
+    T sx = (T)0, sy = (T)0, vx = (T)0, vy = (T)0, vz = (T)0;
+    uint32_t id = 0u, leaf = 0u;
+    bool birth = false;
+    BirthRec<T> rec;
+    if (live) {
+      sx = G(I.s[sp][0])[i];
+      sy = G(I.s[sp][1])[i];
+      vx = G(I.v[sp][0])[i];
+      vy = G(I.v[sp][1])[i];
+      vz = G(I.v[sp][2])[i];
+      id = G(I.id[sp])[i];
+      leaf = G(I.cell[sp])[i];
+      st.alive++;
+      T ex, ey;
+      gather_cic<T>(I, leaf, sx, sy, ex, ey);
+      vx = vx + k.qm_dt * ex;
+      vy = vy + k.qm_dt * ey;
+      sx = sx + vx * k.dt_L;
+      sy = sy + vy * k.dt_L;
+      bool lost = false;
+      const bool okx = wall_rule<T>(reflect, sx, vx, lost);
+      const bool oky = okx && wall_rule<T>(reflect, sy, vy, lost);
+      if (!(okx && oky)) {
+        live = false;
+        st.absorbed++;
+        st.lost += lost ? 1u : 0u;
+        G(I.w[sp])[i] = 0u;
+      } else {
+        leaf = locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, (uint32_t)(sx * (T)65536),
+                           (uint32_t)(sy * (T)65536), I.lut_direct != 0);
+        if (mcc) {
+          WordStream ws(I.key0, I.key1, id, step);
+          const uint32_t r0 = ws.next();
+          const uint32_t r1 = ws.next();
+          if ((r0 >> 8) < k.tcand) {
+            const uint32_t kind = collision_kind<T>(k, r1, vx, vy, vz, st);
+            if (kind == kCollElastic) {
+              collide_elastic<T>(k, ws, vx, vy, vz);
+              st.elastic++;
+            } else if (kind == kCollIonize) {
+              collide_ionize<T>(k, ws, vx, vy, vz, rec);
+              birth = true;
+              st.ionization++;
+            } else if (kind == kCollCx) {
+              st.cx += collide_cx<T>(k, r1, ws, vx, vy, vz, st) ? 1u : 0u;
+            }
+          }
+        }
+        G(I.s[sp][0])[i] = sx;
+        G(I.s[sp][1])[i] = sy;
+        G(I.v[sp][0])[i] = vx;
+        G(I.v[sp][1])[i] = vy;
+        G(I.v[sp][2])[i] = vz;
+        G(I.cell[sp])[i] = leaf;
+      }
+    }
+    stage_birth<T>(I, birth, id, leaf, w, sx, sy, rec);
+    if (live) scatter_cic<T>(I, leaf, sx, sy, w, add_own);
+    if (birth) {   // the newborn electron and ion sit on the parent
+      scatter_cic<T>(I, leaf, sx, sy, w, add_own);
+      scatter_cic<T>(I, leaf, sx, sy, w, add_ion);
+    }
+  }
+  __syncthreads();
+  dep_flush(D, Qs, I.nq);
+  add_stats_row(row, st, sp);
+  if (commit) last_block_commit(I.ctr, step);
+}
+
+// Standalone cloud deposit of the current particles into Q[(step + 1) & 1].
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_deposit_cic(InstDev<T> I) {
+  const uint32_t step = I.ctr->step;
+  unsigned long long* Qpar = I.Q + (size_t)((step + 1u) & 1u) * 2u * I.nq;
+  for (int sp = 0; sp < I.nspecies; ++sp) {
+    unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
+    const uint32_t count = I.ctr->count[sp];
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
+      const uint32_t w = G(I.w[sp])[i];
+      if (!w) continue;
+      scatter_cic<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], w,
+                     [&](uint32_t l, unsigned long long v) {
+                       if (v) gadd(Qs + l, v);
+                     });
+    }
+  }
+}
+
+// Cell-centred E of each leaf: the mean of its four nodal E values.
+template <class T>
+__global__ void k_cell_e(const double* corner_e64, uint32_t nleaves, T* cellE) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nleaves) return;
+  const double* c = corner_e64 + (size_t)8 * l;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) cellE[2 * l + k] = (T)(0.25 * ((c[0 + k] + c[2 + k]) + (c[4 + k] + c[6 + k])));
+}
+
+// The field the step's gather gives at n points (test helper).
+template <class T>
+__global__ void k_gather_points(InstDev<T> I, const double* s, int64_t n, double* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (I.dim == 1) {
+    const T x = (T)s[j];
+    const T g = x * (T)I.N;
+    int ic = (int)floor(g);
+    if (ic > I.N - 1) ic = I.N - 1;
+    const T f = g - (T)ic;
+    out[j] = (double)(I.cell_e ? G(I.E)[ic] : G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]));
+    return;
+  }
+  const T sx = (T)s[2 * j], sy = (T)s[2 * j + 1];
+  const uint32_t leaf = locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, (uint32_t)(sx * (T)65536),
+                                    (uint32_t)(sy * (T)65536), I.lut_direct != 0);
+  T ex, ey;
+  if (I.cic_amr) gather_cic<T>(I, leaf, sx, sy, ex, ey);
+  else gather2d<T>(I, leaf, sx, sy, ex, ey);
+  out[2 * j] = (double)ex;
+  out[2 * j + 1] = (double)ey;
+}
+
 // ---- launchers ----
 template <class T>
 hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit) {
   if (I.nspecies == 2 && grid < 2) return hipErrorInvalidValue;   // the species split needs two workgroups
   const dim3 g(grid), b(kBlock);
-  if (I.dim == 1) {
+  if (I.cic_amr) {
+    if (mcc) hipLaunchKernelGGL((k_step2d_cic<T, true>), g, b, 0, s, I, commit);
+    else hipLaunchKernelGGL((k_step2d_cic<T, false>), g, b, 0, s, I, commit);
+  } else if (I.dim == 1) {
     if (mcc) hipLaunchKernelGGL((k_step<T, true, 1, false>), g, b, 0, s, I, commit);
     else hipLaunchKernelGGL((k_step<T, false, 1, false>), g, b, 0, s, I, commit);
   } else if (I.lut_direct) {
@@ -1482,7 +1796,18 @@ hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long lon
 }
 template <class T>
 hipError_t launch_deposit(const InstDev<T>& I, hipStream_t s, int grid) {
-  hipLaunchKernelGGL(k_deposit<T>, dim3(grid), dim3(kBlock), 0, s, I);
+  if (I.cic_amr) hipLaunchKernelGGL(k_deposit_cic<T>, dim3(grid), dim3(kBlock), 0, s, I);
+  else hipLaunchKernelGGL(k_deposit<T>, dim3(grid), dim3(kBlock), 0, s, I);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t launch_cell_e(const double* corner_e64, uint32_t nleaves, T* cellE, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_e<T>, dim3(ceil_div(nleaves, kBlock)), dim3(kBlock), 0, s, corner_e64, nleaves, cellE);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t launch_gather_points(const InstDev<T>& I, const double* pts, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_points<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, I, pts, n, out);
   return hipGetLastError();
 }
 template <class T>
@@ -1508,6 +1833,8 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
   template hipError_t launch_stats_reduce<T>(const InstDev<T>*, int, unsigned long long*, const uint32_t*, \
                                              uint32_t, hipStream_t);                                       \
   template hipError_t launch_deposit<T>(const InstDev<T>&, hipStream_t, int);                              \
+  template hipError_t launch_cell_e<T>(const double*, uint32_t, T*, hipStream_t);                          \
+  template hipError_t launch_gather_points<T>(const InstDev<T>&, const double*, int64_t, double*, hipStream_t); \
   template hipError_t launch_leapfrog_start<T>(const InstDev<T>&, hipStream_t, int);                       \
   template hipError_t launch_relocate<T>(const InstDev<T>&, int, hipStream_t, int);
 PIC_INSTANTIATE(float)

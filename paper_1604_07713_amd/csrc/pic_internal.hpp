@@ -91,6 +91,8 @@ struct InstDev {
   double kappa[2];               // charge-sum -> Poisson right-hand side factor per species
   double inv2dx;                 // 1D: 1 / (2 dx)
   int cell_e;                    // 1D energy-conserving coupling: E holds cell values, gathered without interpolation
+  int cic_amr;                   // 2D cloud-in-cell coupling: deposit and gather through the particle's cloud
+  const T* cellE;                // 2D cloud-in-cell: cell-centred E [nleaves][2]
   double* phi64;                 // 1D: node potential; 2D: cell potential
   double* e64;                   // 1D: node E; 2D: corner E [nleaves][8]
 };
@@ -140,6 +142,12 @@ template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, int nin
 template <class T> hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long long* rows,
                                                   const uint32_t* row_begin, uint32_t nrows_plain, hipStream_t s);
 template <class T> hipError_t launch_deposit(const InstDev<T>& I, hipStream_t s, int grid);
+// cell-centred E table [nleaves][2] of the cloud-in-cell coupling from the
+// FP64 corner table [nleaves][8]
+template <class T> hipError_t launch_cell_e(const double* corner_e64, uint32_t nleaves, T* cellE, hipStream_t s);
+// the field the step's gather gives at n device points pts[n*dim] -> out[n*dim]
+template <class T> hipError_t launch_gather_points(const InstDev<T>& I, const double* pts, int64_t n, double* out,
+                                                   hipStream_t s);
 template <class T> hipError_t launch_leapfrog_start(const InstDev<T>& I, hipStream_t s, int grid);
 template <class T> hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int grid);
 

@@ -83,8 +83,8 @@ def check_area_overlaps(seed, library=None):
         q = o.deposit()[0].astype(np.float64)
         want = brute_shares(o, x, y, w, H64)
         assert int(o.deposit()[0].astype(object).sum()) == w << (2 * H64)     # exact total
-        # equal up to the remainders of the integer split among quadrants
-        assert np.max(np.abs(q - want)) <= 8.0, (x, y, np.max(np.abs(q - want)))
+        # equal up to the remainder of the integer split among finer leaves
+        assert np.max(np.abs(q - want)) <= 64.0, (x, y, np.max(np.abs(q - want)))
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -142,8 +142,8 @@ def test_gather_is_the_deposit_weights_applied_to_the_field():
     pts = rng.random((80, 2))
     got = o.gather(pts)
     for k, (x, y) in enumerate(pts):
-        # a heavy particle: the integer split of its shares among quadrants
-        # then rounds at 2^-48 of a share
+        # a heavy particle: the integer split of its shares among finer
+        # leaves then rounds at 2^-48 of a share
         o.load(0, np.array([[x, y]]), np.zeros((1, 3)), w=np.array([65536], dtype=np.uint32))
         wts = o.deposit()[0].astype(np.float64) / 2.0 ** (2 * H64 + 16)
         want = wts @ E

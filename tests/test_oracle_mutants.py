@@ -48,9 +48,9 @@ MUTANTS = {
         "const int64_t Xn = X + (gx >= (T)0 ? (int64_t)S : -(int64_t)S);",
         "const int64_t Xn = X + (gx >= (T)0 ? -(int64_t)S : (int64_t)S);",
         lambda L: C.check_area_overlaps(1, L)),
-    "ghost over finer leaves goes to one of them": (
-        "    if (n->level <= L) {\n      Qs[n->leaf_index] += units;",
-        "    if (true) {\n      Qs[n->leaf_index] += units;",
+    "ghost over finer leaves shared equally whatever their size": (
+        "const uint64_t part = units >> (2 * dl[k]);",
+        "const uint64_t part = units / dl.size();",
         lambda L: C.check_area_overlaps(1, L)),
     "merge breaks ties by the larger id": (
         "return P[x].id < P[y].id;",
