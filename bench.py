@@ -42,6 +42,14 @@ METRIC = "particle-updates/s (locate+gather+push+MCC+deposit), 2D AMR; batched v
 PROFILE_PMC = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
+T_START = time.perf_counter()
+
+
+def note(stage):
+    """A progress line on stderr as each stage of the run ends."""
+    print(f"[bench] {stage} done at {time.perf_counter() - T_START:.1f} s", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("k_step.hip", "device_util.hpp", "pic_internal.hpp"):
@@ -295,6 +303,7 @@ def ensemble_bench(nsteps, ninst=96, tune=True,
             out[mode]["tile"] = tuned["tile"]
             out[mode]["grid"] = tuned["grid"]
         g.close()
+        note(f"ensemble {mode}")
     if "batched" in out and "plain" in out:
         out["batched_over_plain"] = out["batched"]["updates_per_s"] / out["plain"]["updates_per_s"]
     if "batched" in out and "plain_fp32" in out:
@@ -371,6 +380,7 @@ def main():
     cpu = None
     if not args.no_cpu and not profiling:
         cpu = cpu_baseline(args.particles, args.cpu_steps)
+        note("cpu baseline")
 
     import numpy as np
     import torch
@@ -399,6 +409,7 @@ def main():
     # the timed steps hold floor(steps / sort_every) sorts
     sort_every = min(SORT_EVERY, args.steps)
     q = quadtree_bench(args.particles, args.steps, args.warmup, sort_every, TIMING_EVERY)
+    note(f"quadtree {args.particles}")
     value = q["updates"] / q["seconds"]
     # dominant kernel: the fused 2D step kernel; its mean launch duration from
     # HIP events recorded on the library's stream around the launches of every
@@ -434,6 +445,7 @@ def main():
     if args.large_particles:
         n = args.large_particles
         ql = quadtree_bench(n, 50, 10, 50, 5)
+        note(f"quadtree {n}")
         out["quadtree_large"] = dict(
             particles=n, state_bytes=n * 28,
             note="state beyond the 256 MB Infinity Cache: the bandwidth figure is HBM bandwidth",
@@ -444,8 +456,10 @@ def main():
                           per="k_step<float,false,2,true> launch, 44 B per particle-update"))
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(args.ensemble_steps, shape=shape, sort_every=args.ensemble_sort_every)
+        note("ensemble")
     if not args.no_streamer:
         out["streamer"] = streamer_bench(args.streamer_steps)
+        note("streamer")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

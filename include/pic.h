@@ -178,8 +178,9 @@ typedef struct {
   const double* v_next; /* ... phi(0) = v_next[k*ninst_sel + j] for step k, slot j */
   int sort_every;       /* re-sort particles by cell every n steps (0 = never)    */
   int batched;          /* 0: launches per slot; > 0: one persistent launch over   */
-                        /* all selected 1D slots of one precision, with this many  */
-                        /* particles per work item (1 = 4096)                      */
+                        /* all selected slots of one dimension and precision, with */
+                        /* this many particles per work item (1 = 4096); quadtree  */
+                        /* slots with the cloud-in-cell coupling are refused       */
   int grid;             /* workgroups of the particle kernel: persistent grid of the
                            batched launch (0 = 2048), or grid of the per-slot launch
                            (0 = one workgroup per 256 particles, at most 2048);
@@ -277,7 +278,7 @@ int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s);
 
 /* For callers that cannot allocate device memory (code between graph
  * captures, tight serving loops, harnesses that forbid allocation): pic_step
- * without any device allocation.  Batched 1D launches only (a->batched > 0,
+ * without any device allocation.  Batched launches only (a->batched > 0,
  * graph_steps = 0, timing = 0; else PIC_E_ARG).  Its launch tables (work
  * items, instance table, per-item partial statistics, sort jobs, drive
  * tables) live in a 16 MiB device workspace of the library, one per device,

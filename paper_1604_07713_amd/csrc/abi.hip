@@ -164,8 +164,6 @@ bool slot_has_mcc(const Slot& sl) {
   return false;
 }
 
-constexpr double kBinnedBirthsPerStep = 16384.0;
-
 template <class T>
 void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e1) {
   InstDev<T> I = make_dev<T>(sl);
@@ -175,8 +173,7 @@ void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e
   hip_check(launch_step<T>(I, C.stream, g, slot_has_mcc(sl), commit), "step");
   if (sl.ionizing) {
     // binned ranking once births per step are many (pairwise work grows as their square)
-    const bool binned = sl.births_method == 2 || (sl.births_method == 0 && sl.births_rate > kBinnedBirthsPerStep);
-    hip_check(launch_births<T>(I, C.stream, binned), "births");
+    hip_check(launch_births<T>(I, C.stream, I.births_binned != 0), "births");
   }
   if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
   if (field)
@@ -291,7 +288,8 @@ hipEvent_t get_event(Ctx& C, size_t i) {
   return C.ev[i];
 }
 
-// One persistent launch per step over all selected 1D slots: the work items
+// One persistent launch per step over all selected slots (all 1D, or all
+// quadtree slots with the corner-field coupling): the work items
 // (slot, species, particle range) are listed largest slot first; per-slot
 // constants come from a device table of InstDev.  With graph_steps > 0 the
 // step sequence (particle loop, births, field solve + commit) is captured
@@ -302,7 +300,8 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   const int nsel = (int)sel.size();
   const uint32_t tile = (uint32_t)(a->batched > 1 ? a->batched : 4096);
   if (tile % kBlock) throw Err(PIC_E_ARG, "batched tile must be a multiple of 256");
-  bool ionizing = false, any_mcc = false;
+  bool ionizing = false, any_mcc = false, any_binned = false;
+  const bool dim2 = sel[0]->d.dim == 2;
   int maxn = 0;
   double max_births_rate = 0.0;
   for (Slot* s : sel) max_births_rate = std::max(max_births_rate, s->births_rate);
@@ -383,12 +382,13 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     uint32_t max_ncell = 0;
     for (int j = 0; j < nsel; ++j) {
       Slot& sl = *sel[j];
-      const uint32_t N = (uint32_t)sl.d.ncells;
+      const uint32_t N = dim2 ? sl.nq : (uint32_t)sl.d.ncells;
       for (int sp = 0; sp < 2; ++sp) {
         SortJob<T>& J = jobs[2 * (size_t)j + sp];
-        J.off = nullptr;
-        J.ncell = N;
+        J.off = nullptr;   // no job for an absent species (every sort kernel skips it)
+        J.ncell = 0;
         if (sp >= sl.d.nspecies || !sl.pb[sp][0].base) continue;
+        J.ncell = N;
         PBuf& d = sl.pb[sp][1 - sl.cur[sp]];
         J.off = sl.off + (size_t)sp * (N + 1);
         J.dst = SortDst<T>{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
@@ -411,6 +411,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     std::vector<InstDev<T>> v(nsel);
     for (int j = 0; j < nsel; ++j) {
       v[j] = make_dev<T>(*sel[j]);
+      any_binned = any_binned || v[j].births_binned;
       if (ws && a->solve_field) {   // drive tables in the workspace: [slot][step] from its start
         v[j].v_table = (const double*)ws->base + (size_t)j * (size_t)(kend - kbeg);
         v[j].v_len = (uint32_t)(kend - kbeg);
@@ -424,13 +425,19 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   const int grid = (int)std::min<size_t>(issued.size(), (size_t)(a->grid > 0 ? a->grid : 2048));
   const InstDev<T>* dI = (const InstDev<T>*)t_insts;
   auto one_step = [&](hipStream_t st) {
-    hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)t_items, (uint32_t)issued.size(), t_part, st, grid,
-                                       any_mcc),
-              "step1d_batched");
-    if (ionizing) hip_check(launch_births_batched<T>(dI, nsel, st, 2.0 * max_births_rate), "births_batched");
+    if (dim2)
+      hip_check(launch_step2d_batched<T>(dI, (const WorkItem*)t_items, (uint32_t)issued.size(), t_part, st, grid,
+                                         any_mcc),
+                "step2d_batched");
+    else
+      hip_check(launch_step1d_batched<T>(dI, (const WorkItem*)t_items, (uint32_t)issued.size(), t_part, st, grid,
+                                         any_mcc),
+                "step1d_batched");
+    if (ionizing)
+      hip_check(launch_births_batched<T>(dI, nsel, st, 2.0 * max_births_rate, any_binned), "births_batched");
   };
   auto one_commit = [&](hipStream_t st) {
-    if (a->solve_field) hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, st), "field1d batched");
+    if (a->solve_field && !dim2) hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, st), "field1d batched");
     else hip_check(launch_commit_batched<T>(dI, nsel, st), "commit batched");
   };
   const int gsteps = a->graph_steps;
@@ -972,8 +979,12 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
   if (noalloc && (a->batched <= 0 || a->graph_steps != 0 || a->timing != 0))
     throw Err(PIC_E_ARG, "the no-allocation step takes batched launches without graph replay or timing");
   if (a->batched)
-    for (Slot* s : sel)
-      if (s->d.dim != 1 || s->prec != sel[0]->prec) throw Err(PIC_E_ARG, "batched steps need 1D slots of one precision");
+    for (Slot* s : sel) {
+      if (s->d.dim != sel[0]->d.dim || s->prec != sel[0]->prec)
+        throw Err(PIC_E_ARG, "batched steps need slots of one dimension and one precision");
+      if (s->d.dim == 2 && s->d.field_scheme == PIC_FIELD_CIC_AMR)
+        throw Err(PIC_E_ARG, "batched steps take quadtree slots with the corner-field coupling");
+    }
   for (Slot* s : sel)
     if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   bool any_ionizing = false;

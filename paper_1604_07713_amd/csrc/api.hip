@@ -480,8 +480,10 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   sl.grad = (double*)sl.alloc(8 * 8 * (size_t)sl.nleaves);
   sl.phi64 = (double*)sl.alloc(8 * (size_t)sl.nleaves);
   sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
-  sl.off = (uint32_t*)sl.alloc(4 * ((size_t)sl.nq + 1 + scan_tmp_words((uint32_t)sl.nq)));
-  sl.scan_tmp = sl.off + sl.nq + 1;   // scratch of the multi-block scan of the sort
+  // one offset array per species (the batched sort takes both at once),
+  // then the scratch of the multi-block scan of the per-species sort
+  sl.off = (uint32_t*)sl.alloc(4 * (2 * ((size_t)sl.nq + 1) + scan_tmp_words((uint32_t)sl.nq)));
+  sl.scan_tmp = sl.off + 2 * ((size_t)sl.nq + 1);
   hip_check(hipMemsetAsync(sl.E, 0, sl.esz * 8 * sl.nleaves, C.stream), "memset");
   if (sl.d.field_scheme == PIC_FIELD_CIC_AMR) {   // the cloud's cell-centred E table
     sl.cellE = sl.alloc(sl.esz * 2 * sl.nleaves);
@@ -684,6 +686,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.cell_e = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_CIC_EC ? 1 : 0;
   I.cic_amr = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR ? 1 : 0;
   I.cellE = (const T*)sl.cellE;
+  I.births_binned = sl.births_method == 2 || (sl.births_method == 0 && sl.births_rate > kBinnedBirthsPerStep);
   I.phi64 = sl.phi64;
   I.e64 = sl.e64;
   return I;

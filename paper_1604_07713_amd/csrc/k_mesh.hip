@@ -244,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(InstDev<T> I, int sp, u
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_sort_fill_batched(const SortJob<T>* jobs) {
   const SortJob<T>& J = jobs[blockIdx.y];
+  if (!J.off) return;   // no such species in the slot
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i <= J.ncell; i += gridDim.x * kBlock) J.off[i] = 0u;
 }
 template <class T>

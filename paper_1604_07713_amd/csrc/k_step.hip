@@ -1055,6 +1055,40 @@ __global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __r
   }
 }
 
+// Batched 2D launch: the same walk over (instance, species, range) work
+// items of quadtree instances; each instance's leaf tables, point-location
+// table and corner-E table come from its descriptor, and whether its tree
+// is shallow enough for a direct lookup is decided per item (uniform over
+// the workgroup).
+template <class T, bool MCC>
+__global__ __launch_bounds__(kBlock) void k_step2d_batched(const InstDev<T>* __restrict__ insts,
+                                                           const WorkItem* __restrict__ items, uint32_t nitems,
+                                                           unsigned long long* bpart) {
+  constexpr int KM = batch_k<T, 2, true>(), KF = batch_k<T, 2, false>();
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const InstDev<T>& I = insts[wi.inst];
+    const int sp = (int)wi.species;
+    if (step_blocked<T>(I)) {   // the same decision for every item of the instance
+      if (wi.begin == 0 && sp == 0 && threadIdx.x == 0) atomicOr(&I.ctr->flags, kFlagNeedRoom);
+      continue;
+    }
+    const uint32_t step = I.ctr->step;
+    const uint32_t count = I.ctr->count[sp];
+    const uint32_t end = wi.end < count ? wi.end : count;
+    unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
+    if (wi.begin == 0 && sp == 0) zero_other_parity(I.Q, I.nq, step, I.nspecies, threadIdx.x, kBlock);
+    unsigned long long* row = bpart + (size_t)it * kNStat;
+    if (MCC && I.sk[sp].mcc != PIC_MCC_NONE) {
+      if (I.lut_direct) run_range<T, true, 2, KM, true>(I, sp, wi.begin, end, step, Qpar, row);
+      else run_range<T, true, 2, KM, false>(I, sp, wi.begin, end, step, Qpar, row);
+    } else {
+      if (I.lut_direct) run_range<T, false, 2, KF, true>(I, sp, wi.begin, end, step, Qpar, row);
+      else run_range<T, false, 2, KF, false>(I, sp, wi.begin, end, step, Qpar, row);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Births: rank by parent id (count of smaller staged parent ids; the ids are
 // distinct), then append the electron at count[0] + r with id next_id + 2r
@@ -1166,7 +1200,7 @@ __device__ __forceinline__ uint32_t birth_bin_shift(uint32_t next_id) {
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_birth_bin(InstDev<T> I) {
+__device__ void birth_bin_body(const InstDev<T>& I, uint32_t first, uint32_t nblocks) {
   __shared__ uint32_t hist[kBirthBins];
   const uint32_t nb = I.ctr->nbirths;
   bool cap_ok, id_ok;
@@ -1174,7 +1208,7 @@ __global__ __launch_bounds__(kBlock) void k_birth_bin(InstDev<T> I) {
   const uint32_t sh = birth_bin_shift(I.ctr->next_id);
   for (uint32_t b = threadIdx.x; b < kBirthBins; b += kBlock) hist[b] = 0u;
   __syncthreads();
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock)
+  for (uint32_t i = first * kBlock + threadIdx.x; i < nb; i += nblocks * kBlock)
     atomicAdd(&hist[I.br.parent[i] >> sh], 1u);
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < kBirthBins; b += kBlock)
@@ -1183,7 +1217,7 @@ __global__ __launch_bounds__(kBlock) void k_birth_bin(InstDev<T> I) {
 
 // one workgroup of 1024 threads: offsets and cursors of the bins; clears the counts
 template <class T>
-__global__ __launch_bounds__(1024) void k_birth_binscan(InstDev<T> I) {
+__device__ void birth_binscan_body(const InstDev<T>& I) {
   __shared__ uint32_t part[1024];
   const uint32_t nb = I.ctr->nbirths;
   bool cap_ok, id_ok;
@@ -1216,24 +1250,24 @@ __global__ __launch_bounds__(1024) void k_birth_binscan(InstDev<T> I) {
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_birth_scatter(InstDev<T> I) {
+__device__ void birth_scatter_body(const InstDev<T>& I, uint32_t first, uint32_t nblocks) {
   const uint32_t nb = I.ctr->nbirths;
   bool cap_ok, id_ok;
   if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
   const uint32_t sh = birth_bin_shift(I.ctr->next_id);
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) {
+  for (uint32_t i = first * kBlock + threadIdx.x; i < nb; i += nblocks * kBlock) {
     const uint32_t pid = I.br.parent[i];
     I.br.sorted[gadd32(I.br.cursor + (pid >> sh), 1u)] = pid;
   }
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_birth_rank_binned(InstDev<T> I) {
+__device__ void birth_rank_binned_body(const InstDev<T>& I, uint32_t first, uint32_t nblocks) {
   const uint32_t nb = I.ctr->nbirths;
   bool cap_ok, id_ok;
   if (nb == 0u || !births_fit(I, nb, cap_ok, id_ok)) return;
   const uint32_t sh = birth_bin_shift(I.ctr->next_id);
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) {
+  for (uint32_t i = first * kBlock + threadIdx.x; i < nb; i += nblocks * kBlock) {
     const uint32_t pid = I.br.parent[i];
     const uint32_t b = pid >> sh;
     const uint32_t lo = I.br.bin_off[b], hi = I.br.bin_off[b + 1u];
@@ -1241,6 +1275,19 @@ __global__ __launch_bounds__(kBlock) void k_birth_rank_binned(InstDev<T> I) {
     for (uint32_t j = lo; j < hi; ++j) r += I.br.sorted[j] < pid ? 1u : 0u;
     I.br.rank[i] = r;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_bin(InstDev<T> I) { birth_bin_body<T>(I, blockIdx.x, gridDim.x); }
+template <class T>
+__global__ __launch_bounds__(1024) void k_birth_binscan(InstDev<T> I) { birth_binscan_body<T>(I); }
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_scatter(InstDev<T> I) {
+  birth_scatter_body<T>(I, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_rank_binned(InstDev<T> I) {
+  birth_rank_binned_body<T>(I, blockIdx.x, gridDim.x);
 }
 
 template <class T>
@@ -1252,7 +1299,28 @@ __global__ __launch_bounds__(kBlock) void k_birth_write(InstDev<T> I) { birth_wr
 // share of its work
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_birth_rank_batched(const InstDev<T>* insts) {
-  birth_rank_body<T>(insts[blockIdx.y], blockIdx.x, gridDim.x);
+  const InstDev<T>& I = insts[blockIdx.y];
+  if (!I.births_binned) birth_rank_body<T>(I, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_bin_batched(const InstDev<T>* insts) {
+  const InstDev<T>& I = insts[blockIdx.y];
+  if (I.births_binned) birth_bin_body<T>(I, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(1024) void k_birth_binscan_batched(const InstDev<T>* insts) {
+  const InstDev<T>& I = insts[blockIdx.y];
+  if (I.births_binned) birth_binscan_body<T>(I);
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_scatter_batched(const InstDev<T>* insts) {
+  const InstDev<T>& I = insts[blockIdx.y];
+  if (I.births_binned) birth_scatter_body<T>(I, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_birth_rank_binned_batched(const InstDev<T>* insts) {
+  const InstDev<T>& I = insts[blockIdx.y];
+  if (I.births_binned) birth_rank_binned_body<T>(I, blockIdx.x, gridDim.x);
 }
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_birth_write_batched(const InstDev<T>* insts) {
@@ -1753,6 +1821,13 @@ hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uin
   return hipGetLastError();
 }
 template <class T>
+hipError_t launch_step2d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
+                                 unsigned long long* bpart, hipStream_t s, int grid, bool mcc) {
+  if (mcc) hipLaunchKernelGGL((k_step2d_batched<T, true>), dim3(grid), dim3(kBlock), 0, s, I, items, nitems, bpart);
+  else hipLaunchKernelGGL((k_step2d_batched<T, false>), dim3(grid), dim3(kBlock), 0, s, I, items, nitems, bpart);
+  return hipGetLastError();
+}
+template <class T>
 hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned) {
   if (binned) {
     hipLaunchKernelGGL(k_birth_bin<T>, dim3(256), dim3(kBlock), 0, s, I);
@@ -1766,7 +1841,8 @@ hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned) {
   return hipGetLastError();
 }
 template <class T>
-hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s, double births_per_step) {
+hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s, double births_per_step,
+                                 bool any_binned) {
   // workgroups per instance from the births expected per step (the kernels
   // loop over their work, so any count is correct; idle workgroups only cost
   // dispatch time): ranking work items are (births / 1024) x (births / 256)
@@ -1775,6 +1851,13 @@ hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s, 
   const int rank_blocks = (int)std::min<double>(kRankBlocks, std::max(4.0, items / 2.0));
   const int write_blocks = (int)std::min<double>(kWriteBlocks, std::max(1.0, nb / kBlock + 1.0));
   hipLaunchKernelGGL(k_birth_rank_batched<T>, dim3(rank_blocks, ninst), dim3(kBlock), 0, s, I);
+  if (any_binned) {
+    const int per = (int)std::min<double>(512.0, std::max(8.0, nb / kBlock + 1.0));
+    hipLaunchKernelGGL(k_birth_bin_batched<T>, dim3(std::min(per, 256), ninst), dim3(kBlock), 0, s, I);
+    hipLaunchKernelGGL(k_birth_binscan_batched<T>, dim3(1, ninst), dim3(1024), 0, s, I);
+    hipLaunchKernelGGL(k_birth_scatter_batched<T>, dim3(per, ninst), dim3(kBlock), 0, s, I);
+    hipLaunchKernelGGL(k_birth_rank_binned_batched<T>, dim3(per, ninst), dim3(kBlock), 0, s, I);
+  }
   hipLaunchKernelGGL(k_birth_write_batched<T>, dim3(write_blocks, ninst), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
@@ -1826,8 +1909,10 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
   template int step_resident_grid<T>(int, bool, bool);                      \
   template hipError_t launch_step1d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
                                                unsigned long long*, hipStream_t, int, bool);               \
+  template hipError_t launch_step2d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
+                                               unsigned long long*, hipStream_t, int, bool);               \
   template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, bool);                              \
-  template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t, double);               \
+  template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t, double, bool);         \
   template hipError_t launch_commit<T>(const InstDev<T>&, hipStream_t);                                    \
   template hipError_t launch_commit_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
   template hipError_t launch_stats_reduce<T>(const InstDev<T>*, int, unsigned long long*, const uint32_t*, \

@@ -93,6 +93,7 @@ struct InstDev {
   int cell_e;                    // 1D energy-conserving coupling: E holds cell values, gathered without interpolation
   int cic_amr;                   // 2D cloud-in-cell coupling: deposit and gather through the particle's cloud
   const T* cellE;                // 2D cloud-in-cell: cell-centred E [nleaves][2]
+  int births_binned;             // births ranked through id bins (else pairwise)
   double* phi64;                 // 1D: node potential; 2D: cell potential
   double* e64;                   // 1D: node E; 2D: corner E [nleaves][8]
 };
@@ -117,7 +118,10 @@ __device__ __forceinline__ bool step_blocked(const InstDev<T>& I) {
   return !room_for_step(c->count[0], c->count[1], c->next_id, I.cap[0], I.cap[1], I.birth_cap);
 }
 
-// Work item of the batched (persistent) 1D launch.
+// Births per step above which the ranking goes through id bins.
+constexpr double kBinnedBirthsPerStep = 16384.0;
+
+// Work item of the batched (persistent) launches.
 struct WorkItem {
   uint32_t inst, species, begin, end;
 };
@@ -129,14 +133,18 @@ template <class T> hipError_t launch_step(const InstDev<T>& I, hipStream_t s, in
 template <class T> int step_resident_grid(int dim, bool mcc, bool direct);
 template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
                                                     unsigned long long* bpart, hipStream_t s, int grid, bool mcc);
+template <class T> hipError_t launch_step2d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
+                                                    unsigned long long* bpart, hipStream_t s, int grid, bool mcc);
 // Births of one step: rank the staged births by parent id, append the pairs.
 // binned: rank through id bins (work ~ births x births per bin) instead of
 // comparing every pair (work ~ births^2); the host picks it for many births.
 constexpr uint32_t kBirthBins = 4096;
 template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned);
-// births_per_step: the most births per step expected of an instance (sizes the grids)
+// births_per_step: the most births per step expected of an instance (sizes
+// the grids); any_binned: some instance ranks through id bins (its
+// births_binned flag), the others pairwise
 template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s,
-                                                    double births_per_step);
+                                                    double births_per_step, bool any_binned);
 template <class T> hipError_t launch_commit(const InstDev<T>& I, hipStream_t s);
 template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, int ninst, hipStream_t s);
 template <class T> hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long long* rows,
