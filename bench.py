@@ -9,6 +9,13 @@ particle (no collisions in this workload), plus the periodic re-sort of the
 particles by leaf.  Inputs are synthetic and seeded; they are resident in
 HBM before the timed region starts.
 
+Beside it (same line, own keys): the same quadtree at 16,777,216 electrons
+(state beyond the Infinity Cache), the batched-vs-plain comparisons the
+metric names -- 96 uneven 1D discharges and 32 uneven 2D avalanches on
+dynamic quadtrees, each stepped by one persistent launch per step over all
+instances and by per-instance launches (FP32 and FP64) -- and the 2D
+avalanche breakdown run.
+
 Prints ONE JSON line (metric/value/unit/... plus "roofline" for the
 dominant kernel and "cpu_baseline" for the oracle on a bounded sample).
 
@@ -313,6 +320,100 @@ def ensemble_bench(nsteps, ninst=96, tune=True,
     return out
 
 
+TILES_2D = (512, 1024, 2048, 4096)
+GRIDS_2D = (256, 512, 1024, 2048)
+
+
+def avalanche_bench(nsteps=200, ninst=32, field_every=10, tune=True, shape=None,
+                    modes=("batched", "plain_fp32", "plain")):
+    """Batched ensemble of 2D avalanches on dynamic quadtrees, shaped like
+    the served stream's 2D jobs (32 instances, sides 0.25-1 cm, 1e3-1e4
+    seed pairs, levels 5-11, 30 kV/cm).  Every field_every steps each slot
+    adapts its tree (split / merge) and re-solves its field with the FP64 CG
+    (per-slot calls, the same in every mode); the particle-loop calls in
+    between (locate, gather, push, MCC with births, deposit) are timed: one
+    persistent launch per step over all slots (batched, FP32), per-slot
+    launches of the same FP32 kernels (plain_fp32: the batching gain alone),
+    and per-slot FP64 launches (plain: the paper's method at the oracle's
+    precision)."""
+    import torch
+    from paper_1604_07713_amd import autotune
+    from paper_1604_07713_amd import binding as B
+    from paper_1604_07713_amd import inputs as I
+    out = {}
+    tuned = None
+    for mode in modes:
+        prec = 64 if mode == "plain" else 32
+        ens = I.avalanche_ensemble(count=ninst, precision=prec)
+        descs = [d for d, _ in ens]
+
+        def make():
+            g = B.Context(descs)
+            for j, (d, parts) in enumerate(ens):
+                for sp, (s, v, w, ids) in enumerate(parts):
+                    g.load(j, sp, s, v, w, ids)
+                g.adapt(j)
+                g.field_solve_2d(j, rtol=1e-8, maxit=4000)
+                g.leapfrog_start(j)
+            return g
+        kw = {}
+        if mode == "batched":
+            if shape:
+                tuned = dict(tile=shape[0], grid=shape[1])
+            elif tune:
+                npart = sum(len(p[0][0]) * 2 for _, p in ens)
+                tuned = autotune.tune(make, descs, None, tiles=TILES_2D, grids=GRIDS_2D, nparticles=npart)
+            else:
+                tuned = dict(tile=1024, grid=1024)
+            kw = dict(batched=tuned["tile"], grid=tuned["grid"])
+        g = make()
+        t_loop = t_field = 0.0
+        upd = births = 0
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(0, nsteps, field_every):
+            t0 = time.perf_counter()
+            st = g.step(-1, field_every, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for j in range(ninst):
+                g.adapt(j)
+                g.field_solve_2d(j, rtol=1e-8, maxit=4000)
+            torch.cuda.synchronize()
+            t_loop += t1 - t0
+            t_field += time.perf_counter() - t1
+            upd += int(st["alive_start"][0] + st["alive_start"][1])
+            births += int(st["births"])
+        wall = time.perf_counter() - t_start
+        r = dict(precision=f"fp{prec}", particle_loop_updates_per_s=upd / t_loop,
+                 updates_per_s_with_adapt_and_field=upd / wall, particle_loop_ms_per_step=t_loop * 1e3 / nsteps,
+                 adapt_and_field_s=t_field, births=births,
+                 particles_end=int(sum(g.count(j, 0) + g.count(j, 1) for j in range(ninst))),
+                 launch=("one persistent launch per step over all slots" if mode == "batched"
+                         else "per-slot launches"))
+        if mode == "batched":
+            r.update(tile=tuned["tile"], grid=tuned["grid"])
+            # one more chunk with events around every step's particle-loop
+            # launches (the batched step kernel and the births kernels)
+            st = g.step(-1, field_every, timing=1, **kw)
+            n_upd = int(st["alive_start"][0] + st["alive_start"][1])
+            r["roofline"] = roofline(BYTES_PER_UPDATE_2D_MCC * n_upd / field_every, st["loop_ms"] / field_every)
+            r["roofline"]["per"] = "batched particle-loop launch (k_step2d_batched + births), 56 B per particle-update"
+        out[mode] = r
+        g.close()
+        note(f"avalanche ensemble {mode}")
+    rate = {m: out[m]["particle_loop_updates_per_s"] for m in out}
+    if "batched" in rate and "plain_fp32" in rate:
+        out["batched_over_plain_fp32"] = rate["batched"] / rate["plain_fp32"]
+    if "batched" in rate and "plain" in rate:
+        out["batched_over_plain"] = rate["batched"] / rate["plain"]
+    if "plain_fp32" in rate and "plain" in rate:
+        out["plain_fp32_over_plain_fp64"] = rate["plain_fp32"] / rate["plain"]
+    out["workload"] = (f"{ninst} avalanches (sides 0.25-1 cm, 1e3-1e4 seed pairs, N2-like gas at 1 atm, "
+                       f"30 kV/cm, levels 5-11), {nsteps} steps, adapt + FP64 CG every {field_every} steps")
+    return out
+
+
 def quadtree_bench(n, steps, warmup, sort_every, timing_every):
     """The static quadtree workload with n electrons: whole step loop rate
     (timed steps include floor(steps / sort_every) sorts) and the mean
@@ -363,6 +464,10 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--only-ensemble", action="store_true", help="measure only the ensemble (profiling)")
     ap.add_argument("--only-quadtree", action="store_true", help="measure only the quadtree workload (profiling)")
+    ap.add_argument("--no-avalanche", action="store_true", help="skip the batched-vs-plain 2D avalanche ensemble")
+    ap.add_argument("--only-avalanche", action="store_true", help="measure only the 2D avalanche ensemble")
+    ap.add_argument("--avalanche-steps", type=int, default=200)
+    ap.add_argument("--avalanche-modes", default="batched,plain_fp32,plain")
     ap.add_argument("--ensemble-modes", default="batched,plain_fp32,plain,batched_energy_conserving",
                     help="comma-separated ensemble modes to run with --only-ensemble")
     ap.add_argument("--ensemble-sort-every", type=int, default=50)
@@ -374,7 +479,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU (sharding across GPUs is designed, not built); --gpus must be 1"}))
         sys.exit(2)
-    profiling = args.only_ensemble or args.only_streamer or args.only_quadtree or args.copy_probe
+    profiling = (args.only_ensemble or args.only_streamer or args.only_quadtree or args.only_avalanche
+                 or args.copy_probe)
     # the oracle's host timing runs first, before this process touches the GPU
     # (its ensemble sample forks worker processes)
     cpu = None
@@ -404,6 +510,11 @@ def main():
         return
     if args.only_streamer:
         print(json.dumps({"streamer": streamer_bench(args.streamer_steps)}), flush=True)
+        return
+    if args.only_avalanche:
+        print(json.dumps({"avalanche_ensemble": avalanche_bench(args.avalanche_steps, shape=shape,
+                                                                modes=tuple(args.avalanche_modes.split(",")))}),
+              flush=True)
         return
 
     # the timed steps hold floor(steps / sort_every) sorts
@@ -460,6 +571,10 @@ def main():
     if not args.no_streamer:
         out["streamer"] = streamer_bench(args.streamer_steps)
         note("streamer")
+    if not args.no_avalanche:
+        out["avalanche_ensemble"] = avalanche_bench(args.avalanche_steps, shape=shape,
+                                                    modes=tuple(args.avalanche_modes.split(",")))
+        note("avalanche ensemble")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -1,7 +1,7 @@
-"""Autotuner for the batched (persistent) 1D launch: particles per work item
-and grid size, chosen by timing the step kernels on a scratch copy of the
-ensemble.  Results are cached as JSON keyed by GPU architecture and a size
-class of the ensemble."""
+"""Autotuner for the batched (persistent) launches, 1D and 2D: particles per
+work item and grid size, chosen by timing the step kernels on a scratch copy
+of the ensemble.  Results are cached as JSON keyed by GPU architecture and a
+size class of the ensemble."""
 from __future__ import annotations
 
 import json
@@ -13,10 +13,10 @@ TILES = (1024, 2048, 4096, 8192)
 GRIDS = (512, 1024, 2048, 4096)
 
 
-def size_class(descs):
-    tot = sum(d["extra"]["npart"] * 2 for d in descs)
+def size_class(descs, nparticles=None):
+    tot = nparticles if nparticles is not None else sum(d["extra"]["npart"] * 2 for d in descs)
     prec = {d["precision"] for d in descs}
-    return f"1d-fp{min(prec)}-n{len(descs)}-p2e{int(round(math.log2(max(tot, 1))))}"
+    return f"{descs[0]['dim']}d-fp{min(prec)}-n{len(descs)}-p2e{int(round(math.log2(max(tot, 1))))}"
 
 
 def arch():
@@ -44,10 +44,13 @@ def save_cache(c):
         pass
 
 
-def tune(make_ctx, descs, v_next, steps=8, tiles=TILES, grids=GRIDS, use_cache=True, passes=3):
+def tune(make_ctx, descs, v_next=None, steps=8, tiles=TILES, grids=GRIDS, use_cache=True, passes=3,
+         nparticles=None):
     """make_ctx(): a fresh, loaded and started context of the ensemble.
-    v_next: [steps][nslots] drive table.  Returns dict(tile=, grid=, ns_per_update=)."""
-    key = f"{arch()}/{size_class(descs)}"
+    v_next: [steps][nslots] drive table of 1D slots (the field is solved on
+    the device every step); None for quadtree slots (the field stays as set).
+    Returns dict(tile=, grid=, ns_per_update=)."""
+    key = f"{arch()}/{size_class(descs, nparticles)}"
     cache = load_cache() if use_cache else {}
     if key in cache:
         return dict(cache[key], cached=True)
@@ -60,12 +63,15 @@ def tune(make_ctx, descs, v_next, steps=8, tiles=TILES, grids=GRIDS, use_cache=T
     # particle-update summed over passes in alternating orders, which cancels
     # the drift of the ensemble (it grows and heats while it is tuned) and
     # averages out the noise of single short runs.
-    g.step(step0, 2, v_next[:2], solve_field=True, batched=4096, sort_every=2)
+    def run(n, **kw):
+        if v_next is None:
+            return g.step(-1, n, **kw)
+        return g.step(step0, n, v_next[step0:step0 + n], solve_field=True, **kw)
+    run(2, batched=4096, sort_every=2)
     step0 += 2
     for order in [cands if k % 2 == 0 else cands[::-1] for k in range(passes)]:
         for t, gr in order:
-            st = g.step(step0, steps, v_next[step0:step0 + steps], solve_field=True, batched=t, grid=gr,
-                        timing=True, sort_every=steps)
+            st = run(steps, batched=t, grid=gr, timing=True, sort_every=steps)
             step0 += steps
             upd = max(st["alive_start"][0] + st["alive_start"][1], 1)
             score[(t, gr)] += st["loop_ms"] / upd / passes

@@ -195,6 +195,21 @@ def streamer_particles(desc, npairs=10000, sigma=5e-4, rng_seed=None):
             (pos.copy(), vi, w.copy(), np.arange(npairs, 2 * npairs, dtype=np.uint32))]
 
 
+def avalanche_ensemble(count=32, seed=6, precision=32):
+    """Batched ensemble of 2D avalanches shaped like the served stream's 2D
+    jobs: domain side uniform in 0.25-1 cm, seed pairs uniform in 1e3-1e4,
+    the avalanche physics above (levels 5-11, 30 kV/cm), a Philox key and a
+    seed draw of its own per instance.  Returns [(desc, particles)]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = rng.uniform(0.0025, 0.01, count)
+    npairs = rng.integers(1000, 10001, count)
+    out = []
+    for k in range(count):
+        d = streamer_desc(side=float(sides[k]), precision=precision, seed=seed, instance_key=k)
+        out.append((d, streamer_particles(d, npairs=int(npairs[k]), rng_seed=[seed, k])))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Served request stream
 # --------------------------------------------------------------------------
