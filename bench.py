@@ -34,9 +34,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, GB/s
 # Algorithmic bytes per particle-update (what the step must move; the field,
 # leaf and charge tables are cache resident and not counted):
-#  2D FP32 without collisions: read sx, sy, vx, vy, w, leaf (24 B), write
-#  sx, sy, vx, vy (16 B), plus the per-particle weight this layout carries
-#  (counted twice over: read with the state and kept for the deposit) -> 44 B.
+#  2D FP32 without collisions: read sx, sy, vx, vy, leaf (20 B) and the
+#  per-particle weight this layout carries (4 B), write sx, sy, vx, vy, leaf
+#  (20 B; the leaf is counted although it is stored only when it changes)
+#  -> 44 B.
 BYTES_PER_UPDATE_2D = 44
 #  1D FP32 with MCC: read s, vx, w, id (16 B), write s, vx (8 B); a particle
 #  that collides also moves vy, vz in and out (16 B per collision).
@@ -238,9 +239,10 @@ def cpu_baseline(nparticles, nsteps, seed=2, extra=True):
 
 def ensemble_bench(nsteps, ninst=96, tune=True,
                    modes=("batched", "plain_fp32", "plain", "batched_energy_conserving"), shape=None, sort_every=50):
-    """Batched ensemble of 1D CCP instances (config-0 physics, 96 uneven
-    meshes), with the on-device field solve: the FP32 batched path (one
-    persistent launch per step, graph replay, autotuned work items), the
+    """Batched ensemble of 1D CCP instances (the 1D discharge's physics, 96
+    uneven meshes), with the on-device field solve: the FP32 batched path
+    (one persistent launch per step, autotuned work items; the same steps
+    replayed from captured HIP graphs are timed beside it), the
     same FP32 arithmetic with per-instance launches (plain_fp32: the
     batching gain alone), the FP64 plain path (per-instance launches; its
     ratio to plain_fp32 is the precision gain alone), and the batched path
@@ -286,21 +288,29 @@ def ensemble_bench(nsteps, ninst=96, tune=True,
         g.step(0, 10, vtab[:10], **kw)          # warm-up
         st = g.step(10, nsteps, vtab[10:10 + nsteps], timing=1, **kw)
         kern = st["loop_ms"]
-        if batched:
-            kw["graph_steps"] = 25
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st2 = g.step(10 + nsteps, nsteps, vtab[10 + nsteps:10 + 2 * nsteps], **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        graph_rate = None
+        if batched:
+            # the same steps replayed from a captured HIP graph of 25 steps
+            k0 = 10 + 2 * nsteps
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st3 = g.step(k0, nsteps, vtab[k0:k0 + nsteps], graph_steps=25, **kw)
+            torch.cuda.synchronize()
+            graph_rate = (st3["alive_start"][0] + st3["alive_start"][1]) / (time.perf_counter() - t1)
         upd = st2["alive_start"][0] + st2["alive_start"][1]
         upd_t = st["alive_start"][0] + st["alive_start"][1]
         coll_t = st["elastic"] + st["ionization"] + st["cx"]
         out[mode] = dict(precision=f"fp{prec}", updates_per_s=upd / dt, ms_per_step=dt * 1e3 / nsteps,
                          births_per_step=st2["births"] / nsteps, room_stops=st["room_stops"] + st2["room_stops"],
                          loop_kernel_ms_per_step=kern / nsteps, particles=upd // nsteps,
-                         launch=("one persistent launch per step, HIP graph of 25 steps" if batched
-                                 else "per-instance launches"))
+                         launch=("one persistent launch per step" if batched else "per-instance launches"))
+        if graph_rate is not None:
+            out[mode]["graph_replay_updates_per_s"] = graph_rate
         if batched and prec == 32:
             # the persistent particle-loop launch: 24 B per update + 16 B per collision
             per = (BYTES_PER_UPDATE_1D_MCC * upd_t + BYTES_PER_COLLISION_1D * coll_t) / nsteps

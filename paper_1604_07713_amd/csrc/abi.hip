@@ -232,11 +232,12 @@ void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, const double* v_next
   upload_dev(C, sl);
 }
 
-void finish_stats(Ctx& C, std::vector<Slot*>& sel, std::vector<Counters>& before, pic_step_stats* st) {
+// now: the counters after the last launch of the call (read after it).
+void finish_stats(Ctx& C, std::vector<Slot*>& sel, std::vector<Counters>& before, const std::vector<Counters>& now,
+                  pic_step_stats* st) {
   pic_step_stats out;
   std::memset(&out, 0, sizeof(out));
   std::string err;
-  const std::vector<Counters> now = read_counters_many(C, sel);
   for (size_t j = 0; j < sel.size(); ++j) {
     const Counters& c = now[j];
     const Counters& b = before[j];
@@ -300,11 +301,16 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
   const int nsel = (int)sel.size();
   const uint32_t tile = (uint32_t)(a->batched > 1 ? a->batched : 4096);
   if (tile % kBlock) throw Err(PIC_E_ARG, "batched tile must be a multiple of 256");
-  bool ionizing = false, any_mcc = false, any_binned = false;
+  bool ionizing = false, any_mcc = false;
   const bool dim2 = sel[0]->d.dim == 2;
   int maxn = 0;
-  double max_births_rate = 0.0;
-  for (Slot* s : sel) max_births_rate = std::max(max_births_rate, s->births_rate);
+  // the busiest ionizing slot of each ranking method (-1: none ranks that way)
+  double pair_rate = -1.0, bin_rate = -1.0;
+  for (Slot* s : sel) {
+    if (!s->ionizing) continue;
+    double& r = slot_births_binned(*s) ? bin_rate : pair_rate;
+    r = std::max(r, s->births_rate);
+  }
   std::vector<int> order(nsel);
   for (int j = 0; j < nsel; ++j) order[j] = j;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -411,7 +417,6 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     std::vector<InstDev<T>> v(nsel);
     for (int j = 0; j < nsel; ++j) {
       v[j] = make_dev<T>(*sel[j]);
-      any_binned = any_binned || v[j].births_binned;
       if (ws && a->solve_field) {   // drive tables in the workspace: [slot][step] from its start
         v[j].v_table = (const double*)ws->base + (size_t)j * (size_t)(kend - kbeg);
         v[j].v_len = (uint32_t)(kend - kbeg);
@@ -434,7 +439,9 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
                                          any_mcc),
                 "step1d_batched");
     if (ionizing)
-      hip_check(launch_births_batched<T>(dI, nsel, st, 2.0 * max_births_rate, any_binned), "births_batched");
+      hip_check(launch_births_batched<T>(dI, nsel, st, pair_rate < 0 ? -1.0 : 2.0 * pair_rate,
+                                         bin_rate < 0 ? -1.0 : 2.0 * bin_rate),
+                "births_batched");
   };
   auto one_commit = [&](hipStream_t st) {
     if (a->solve_field && !dim2) hip_check(launch_field1d<T>(dI, nsel, maxn, 1, nullptr, st), "field1d batched");
@@ -1021,8 +1028,14 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
   std::vector<int64_t> stalled(nsel, -1);   // progress at which a slot last stopped for room
   std::vector<int64_t> grown_at(nsel, -1);  // progress at which a stopped slot was last grown
   int64_t room_stops = 0;
+  // the counters at the top of each round: those just read for the first,
+  // then a fresh read after the round's launches (the last one also gives
+  // the call's statistics)
+  std::vector<Counters> cur = before;
+  bool fresh = true;
   for (;;) {
-    const std::vector<Counters> cur = read_counters_many(*c, sel);
+    if (!fresh) cur = read_counters_many(*c, sel);
+    fresh = false;
     int64_t dmin = a->nsteps;
     std::vector<int64_t> done(nsel);
     for (int j = 0; j < nsel; ++j) {
@@ -1067,9 +1080,26 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
                                c->stream),
                 "drive tables");
     }
-    for (int q = 0; q < ng; ++q) {
-      if (cur[gj[q]].flags & kFlagNeedRoom) grown_at[gj[q]] = dmin;
-      prepare_slot(*c, *grp[q], &sub, sub.v_next, q, ng, n, cur[gj[q]], noalloc);
+    {
+      // the counters and device views of the group go out in one gathered
+      // upload (a no-allocation step uploads them one by one)
+      struct Defer {
+        Ctx& c;
+        Defer(Ctx& c_, bool on) : c(c_) { c.defer_uploads = on; }
+        ~Defer() {
+          c.defer_uploads = false;
+          try {
+            c.flush_uploads();
+          } catch (...) {
+          }
+        }
+      } defer(*c, !noalloc);
+      for (int q = 0; q < ng; ++q) {
+        if (cur[gj[q]].flags & kFlagNeedRoom) grown_at[gj[q]] = dmin;
+        prepare_slot(*c, *grp[q], &sub, sub.v_next, q, ng, n, cur[gj[q]], noalloc);
+      }
+      c->defer_uploads = false;
+      c->flush_uploads();
     }
     if (a->timing && !started) {   // the call's wall time starts after the first preparation
       hip_check(hipEventRecord(t0, c->stream), "event");
@@ -1126,7 +1156,7 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
     stats->loop_ms = loop_ms;
     stats->loop_launches = launches;
   }
-  finish_stats(*c, sel, before, stats);
+  finish_stats(*c, sel, before, cur, stats);
   if (stats) stats->room_stops = room_stops;
 }
 

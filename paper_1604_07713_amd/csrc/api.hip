@@ -104,9 +104,9 @@ void DevPool::clear() {
 }
 
 void Ctx::release_tables() {
-  void** tab[] = {&b_insts, &b_items, (void**)&b_part, (void**)&b_rowbeg, &b_jobs};
-  size_t* have[] = {&b_insts_bytes, &b_items_bytes, &b_part_bytes, &b_rowbeg_bytes, &b_jobs_bytes};
-  for (int i = 0; i < 5; ++i) {
+  void** tab[] = {&b_insts, &b_items, (void**)&b_part, (void**)&b_rowbeg, &b_jobs, &b_blob};
+  size_t* have[] = {&b_insts_bytes, &b_items_bytes, &b_part_bytes, &b_rowbeg_bytes, &b_jobs_bytes, &b_blob_bytes};
+  for (int i = 0; i < 6; ++i) {
     if (*tab[i]) pool.put(*tab[i], *have[i]);
     *tab[i] = nullptr;
     *have[i] = 0;
@@ -391,18 +391,91 @@ void* Ctx::pinned(size_t bytes) {
   return p;
 }
 
+__global__ void k_copy_blobs(const Blob* b) {
+  const Blob x = b[blockIdx.x];
+  const uint32_t* s = (const uint32_t*)x.src;
+  uint32_t* d = (uint32_t*)x.dst;
+  for (uint32_t i = threadIdx.x; i < x.bytes / 4u; i += blockDim.x) d[i] = s[i];
+}
+
+// Device buffer of a gathered batch.  A replaced buffer goes back to the
+// pool, which reuses it only after the next synchronization.
+void* Ctx::blob_buffer(size_t bytes) {
+  if (b_blob_bytes < bytes) {
+    if (b_blob) pool.put(b_blob, b_blob_bytes);
+    b_blob = nullptr;
+    b_blob_bytes = 0;
+    const size_t cls = DevPool::class_of(bytes);
+    b_blob = pool.get(cls);
+    b_blob_bytes = cls;
+  }
+  return b_blob;
+}
+
+void Ctx::upload(void* dst, const void* src, size_t bytes) {
+  if (!defer_uploads) {
+    hip_check(hipMemcpyAsync(dst, stage(src, bytes), bytes, hipMemcpyHostToDevice, stream), "upload");
+    return;
+  }
+  if (bytes % 4) throw Err(PIC_E_ARG, "gathered uploads take whole 32-bit words");
+  pend.push_back(Blob{dst, (const void*)(uintptr_t)pend_data.size(), (uint32_t)bytes, 0u});
+  pend_data.insert(pend_data.end(), (const char*)src, (const char*)src + bytes);
+  pend_data.resize((pend_data.size() + 15) & ~(size_t)15);
+}
+
+void Ctx::flush_uploads() {
+  if (pend.empty()) return;
+  const size_t n = pend.size();
+  const size_t tab = (n * sizeof(Blob) + 255) & ~(size_t)255;
+  const size_t total = tab + pend_data.size();
+  char* D = (char*)blob_buffer(total);
+  std::vector<char> host(total);
+  for (size_t j = 0; j < n; ++j) {
+    Blob b = pend[j];
+    b.src = D + tab + (size_t)(uintptr_t)b.src;
+    std::memcpy(host.data() + j * sizeof(Blob), &b, sizeof(Blob));
+  }
+  std::memcpy(host.data() + tab, pend_data.data(), pend_data.size());
+  pend.clear();
+  pend_data.clear();
+  hip_check(hipMemcpyAsync(D, stage(host.data(), total), total, hipMemcpyHostToDevice, stream), "gathered upload");
+  hipLaunchKernelGGL(k_copy_blobs, dim3((unsigned)n), dim3(64), 0, stream, (const Blob*)D);
+  hip_check(hipGetLastError(), "copy blobs");
+}
+
+// Counters of many slots: one table upload, one gather kernel and one
+// download (or per-slot downloads for a few slots and in no-allocation
+// steps, which take no device buffer).
 std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel) {
-  Counters* h = (Counters*)C.pinned(sizeof(Counters) * sel.size());
-  for (size_t j = 0; j < sel.size(); ++j)
-    hip_check(hipMemcpyAsync(h + j, sel[j]->ctr, sizeof(Counters), hipMemcpyDeviceToHost, C.stream), "read counters");
-  std::vector<Counters> out(sel.size());
+  C.flush_uploads();
+  const size_t n = sel.size();
+  std::vector<Counters> out(n);
+  Counters* h = (Counters*)C.pinned(sizeof(Counters) * n);
+  if (n >= 4 && !C.hold_pool) {
+    const size_t tab = (n * sizeof(Blob) + 255) & ~(size_t)255;
+    char* D = (char*)C.blob_buffer(tab + sizeof(Counters) * n);
+    std::vector<Blob> t(n);
+    for (size_t j = 0; j < n; ++j)
+      t[j] = Blob{D + tab + j * sizeof(Counters), sel[j]->ctr, (uint32_t)sizeof(Counters), 0u};
+    hip_check(hipMemcpyAsync(D, C.stage(t.data(), n * sizeof(Blob)), n * sizeof(Blob), hipMemcpyHostToDevice,
+                             C.stream),
+              "counters table");
+    hipLaunchKernelGGL(k_copy_blobs, dim3((unsigned)n), dim3(64), 0, C.stream, (const Blob*)D);
+    hip_check(hipGetLastError(), "gather counters");
+    hip_check(hipMemcpyAsync(h, D + tab, sizeof(Counters) * n, hipMemcpyDeviceToHost, C.stream), "read counters");
+  } else {
+    for (size_t j = 0; j < n; ++j)
+      hip_check(hipMemcpyAsync(h + j, sel[j]->ctr, sizeof(Counters), hipMemcpyDeviceToHost, C.stream),
+                "read counters");
+  }
   hip_check(hipStreamSynchronize(C.stream), "hipStreamSynchronize");
-  std::memcpy(out.data(), h, sizeof(Counters) * sel.size());
+  std::memcpy(out.data(), h, sizeof(Counters) * n);
   C.sync();
   return out;
 }
 
 void Ctx::sync() {
+  flush_uploads();
   hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
   arena_off = 0;
   if (hold_pool) return;
@@ -686,7 +759,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.cell_e = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_CIC_EC ? 1 : 0;
   I.cic_amr = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR ? 1 : 0;
   I.cellE = (const T*)sl.cellE;
-  I.births_binned = sl.births_method == 2 || (sl.births_method == 0 && sl.births_rate > kBinnedBirthsPerStep);
+  I.births_binned = slot_births_binned(sl) ? 1 : 0;
   I.phi64 = sl.phi64;
   I.e64 = sl.e64;
   return I;
@@ -696,24 +769,22 @@ InstDev<T> make_dev(const Slot& sl) {
 void upload_dev(Ctx& C, Slot& sl) {
   if (sl.prec == 32) {
     InstDev<float> I = make_dev<float>(sl);
-    hip_check(hipMemcpyAsync(sl.devI, C.stage(&I, sizeof(I)), sizeof(I), hipMemcpyHostToDevice, C.stream), "upload");
+    C.upload(sl.devI, &I, sizeof(I));
   } else {
     InstDev<double> I = make_dev<double>(sl);
-    hip_check(hipMemcpyAsync(sl.devI, C.stage(&I, sizeof(I)), sizeof(I), hipMemcpyHostToDevice, C.stream), "upload");
+    C.upload(sl.devI, &I, sizeof(I));
   }
 }
 
 Counters read_counters(Ctx& C, Slot& sl) {
+  C.flush_uploads();
   Counters c;
   hip_check(hipMemcpyAsync(&c, sl.ctr, sizeof(c), hipMemcpyDeviceToHost, C.stream), "read counters");
   C.sync();
   return c;
 }
 
-void write_counters(Ctx& C, Slot& sl, const Counters& c) {
-  hip_check(hipMemcpyAsync(sl.ctr, C.stage(&c, sizeof(c)), sizeof(c), hipMemcpyHostToDevice, C.stream),
-            "write counters");
-}
+void write_counters(Ctx& C, Slot& sl, const Counters& c) { C.upload(sl.ctr, &c, sizeof(c)); }
 
 int grid_for(int64_t n) {
   int64_t g = (n + kBlock - 1) / kBlock;

@@ -134,6 +134,20 @@ struct Slot {
   void release_all();
 };
 
+// Births of the slot ranked through id bins (else pairwise): by request, or
+// once its births per step are many.
+inline bool slot_births_binned(const Slot& sl) {
+  return sl.births_method == 2 || (sl.births_method == 0 && sl.births_rate > kBinnedBirthsPerStep);
+}
+
+// One small host -> device (or device -> device) copy of a gathered batch:
+// a copy kernel moves 'bytes' (a multiple of 4) from src to dst.
+struct Blob {
+  void* dst;
+  const void* src;
+  uint32_t bytes, pad;
+};
+
 struct Ctx {
   std::vector<Slot> slots;
   hipStream_t stream = nullptr;
@@ -159,6 +173,17 @@ struct Ctx {
   // set during a no-allocation step: synchronizations keep released blocks
   // pending instead of freeing them (they are freed at a later sync)
   bool hold_pool = false;
+  // Small uploads (counters, instance views) of many slots gathered into one
+  // transfer and one copy kernel while defer_uploads is set; flushed by
+  // flush_uploads (and before any read of counters).
+  bool defer_uploads = false;
+  std::vector<Blob> pend;        // src holds the offset into pend_data
+  std::vector<char> pend_data;
+  void* b_blob = nullptr;        // device side of a gathered batch: table, then payload
+  size_t b_blob_bytes = 0;
+  void upload(void* dst, const void* src, size_t bytes);
+  void flush_uploads();
+  void* blob_buffer(size_t bytes);
   void* stage(const void* src, size_t bytes);
   void* pinned(size_t bytes);   // pinned host scratch from the staging arena
   void sync();

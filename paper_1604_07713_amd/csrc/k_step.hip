@@ -1841,23 +1841,29 @@ hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned) {
   return hipGetLastError();
 }
 template <class T>
-hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s, double births_per_step,
-                                 bool any_binned) {
+hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s, double pair_births,
+                                 double bin_births) {
   // workgroups per instance from the births expected per step (the kernels
   // loop over their work, so any count is correct; idle workgroups only cost
-  // dispatch time): ranking work items are (births / 1024) x (births / 256)
-  const double nb = births_per_step > 0 ? births_per_step : 0.0;
-  const double items = (nb / (kRankPer * kBlock) + 1.0) * (nb / kRankChunk + 1.0);
-  const int rank_blocks = (int)std::min<double>(kRankBlocks, std::max(4.0, items / 2.0));
-  const int write_blocks = (int)std::min<double>(kWriteBlocks, std::max(1.0, nb / kBlock + 1.0));
-  hipLaunchKernelGGL(k_birth_rank_batched<T>, dim3(rank_blocks, ninst), dim3(kBlock), 0, s, I);
-  if (any_binned) {
+  // dispatch time): pairwise ranking work items are (births / 1024) x
+  // (births / 256)
+  if (pair_births >= 0.0) {
+    const double nb = pair_births;
+    const double items = (nb / (kRankPer * kBlock) + 1.0) * (nb / kRankChunk + 1.0);
+    const int rank_blocks = (int)std::min<double>(kRankBlocks, std::max(4.0, items / 2.0));
+    hipLaunchKernelGGL(k_birth_rank_batched<T>, dim3(rank_blocks, ninst), dim3(kBlock), 0, s, I);
+  }
+  if (bin_births >= 0.0) {
+    const double nb = bin_births;
+    const int hist_blocks = (int)std::min<double>(64.0, nb / 4096.0 + 1.0);   // LDS histogram per 4096 births
     const int per = (int)std::min<double>(512.0, std::max(8.0, nb / kBlock + 1.0));
-    hipLaunchKernelGGL(k_birth_bin_batched<T>, dim3(std::min(per, 256), ninst), dim3(kBlock), 0, s, I);
+    hipLaunchKernelGGL(k_birth_bin_batched<T>, dim3(hist_blocks, ninst), dim3(kBlock), 0, s, I);
     hipLaunchKernelGGL(k_birth_binscan_batched<T>, dim3(1, ninst), dim3(1024), 0, s, I);
     hipLaunchKernelGGL(k_birth_scatter_batched<T>, dim3(per, ninst), dim3(kBlock), 0, s, I);
     hipLaunchKernelGGL(k_birth_rank_binned_batched<T>, dim3(per, ninst), dim3(kBlock), 0, s, I);
   }
+  const double nb = std::max(pair_births, bin_births);
+  const int write_blocks = (int)std::min<double>(kWriteBlocks, std::max(1.0, nb / kBlock + 1.0));
   hipLaunchKernelGGL(k_birth_write_batched<T>, dim3(write_blocks, ninst), dim3(kBlock), 0, s, I);
   return hipGetLastError();
 }
@@ -1912,7 +1918,7 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
   template hipError_t launch_step2d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
                                                unsigned long long*, hipStream_t, int, bool);               \
   template hipError_t launch_births<T>(const InstDev<T>&, hipStream_t, bool);                              \
-  template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t, double, bool);         \
+  template hipError_t launch_births_batched<T>(const InstDev<T>*, int, hipStream_t, double, double);       \
   template hipError_t launch_commit<T>(const InstDev<T>&, hipStream_t);                                    \
   template hipError_t launch_commit_batched<T>(const InstDev<T>*, int, hipStream_t);                       \
   template hipError_t launch_stats_reduce<T>(const InstDev<T>*, int, unsigned long long*, const uint32_t*, \

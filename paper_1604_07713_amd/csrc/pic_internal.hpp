@@ -118,8 +118,9 @@ __device__ __forceinline__ bool step_blocked(const InstDev<T>& I) {
   return !room_for_step(c->count[0], c->count[1], c->next_id, I.cap[0], I.cap[1], I.birth_cap);
 }
 
-// Births per step above which the ranking goes through id bins.
-constexpr double kBinnedBirthsPerStep = 16384.0;
+// Births per step above which the ranking goes through id bins (pairwise
+// ranking work grows as the square of the births).
+constexpr double kBinnedBirthsPerStep = 2048.0;
 
 // Work item of the batched (persistent) launches.
 struct WorkItem {
@@ -140,11 +141,11 @@ template <class T> hipError_t launch_step2d_batched(const InstDev<T>* I, const W
 // comparing every pair (work ~ births^2); the host picks it for many births.
 constexpr uint32_t kBirthBins = 4096;
 template <class T> hipError_t launch_births(const InstDev<T>& I, hipStream_t s, bool binned);
-// births_per_step: the most births per step expected of an instance (sizes
-// the grids); any_binned: some instance ranks through id bins (its
-// births_binned flag), the others pairwise
+// pair_births / bin_births: the most births per step expected of an
+// instance ranked pairwise / through id bins (its births_binned flag); they
+// size the grids, and a negative value means no instance ranks that way
 template <class T> hipError_t launch_births_batched(const InstDev<T>* I, int ninst, hipStream_t s,
-                                                    double births_per_step, bool any_binned);
+                                                    double pair_births, double bin_births);
 template <class T> hipError_t launch_commit(const InstDev<T>& I, hipStream_t s);
 template <class T> hipError_t launch_commit_batched(const InstDev<T>* I, int ninst, hipStream_t s);
 template <class T> hipError_t launch_stats_reduce(const InstDev<T>* I, int ninst, unsigned long long* rows,

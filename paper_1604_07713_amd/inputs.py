@@ -102,7 +102,7 @@ def drive_voltage(desc, n):
 
 
 def ensemble_descs(count=96, seed=4, precision=32):
-    """Batched ensemble: config-0 physics with per-instance mesh, ppc, voltage and
+    """Batched ensemble: the 1D discharge's physics with per-instance mesh, ppc, voltage and
     pressure drawn from PCG64(seed): 'count' draws each of cells, ppc, V, p."""
     rng = np.random.Generator(np.random.PCG64(seed))
     cells = np.exp(rng.uniform(math.log(128), math.log(4096), count))
