@@ -3,9 +3,11 @@
 Jobs (1D capacitively coupled discharges and 2D avalanches of different
 sizes) arrive over time.  Each admitted job owns a library slot; its
 particle and mesh state stay resident on the GPU until it finishes.  The 1D
-jobs share one context; each 2D job has a context of its own on one of a few
-HIP streams, and worker threads drive the 2D jobs of a tick concurrently, so
-their small, latency-bound adaptation and CG launches overlap on the GPU.
+jobs share one context.  The 2D jobs are spread over a few lanes, each a
+context on a HIP stream of its own (default priority) driven by a thread of
+its own, so the small, latency-bound adaptation and CG launches of jobs in
+different lanes overlap on the GPU while the jobs of a lane share batched
+particle-loop launches.
 
 Admission is by projected device memory.  Ionization makes an avalanche's
 population grow exponentially, so its footprint is projected to its peak:
@@ -13,8 +15,10 @@ the population now times exp(lambda x the steps it has left), with lambda
 the largest of a prior and the mean growth of the avalanches finished so far.  A job
 is admitted when the projected peaks of the resident jobs and the new one fit
 the budget.  Every tick all resident 1D jobs advance together in one
-persistent batched launch per step (each at its own step index), and the
-resident 2D jobs advance with periodic adaptation and field solves.  Jobs
+persistent batched launch per step (each at its own step index), and so do
+the resident 2D jobs that stand at the same point of their cycle of
+adaptation and field solve (each adapts its tree and re-solves its field at
+its own cycle boundaries, with per-slot calls).  Jobs
 that arrive while others run are admitted as soon as memory and slots allow,
 so their work joins the device work of the running ones.  A job that still
 runs out of device memory (or outgrows the library's per-array limit) fails
@@ -30,6 +34,7 @@ import json
 import math
 import sys
 import time
+
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -52,7 +57,6 @@ class Job:
         self.steps_total = int(spec["steps"])
         self.key = spec["key"]
         self.ctx = None    # the library context holding the job's slot
-        self.own_ctx = False
         self.slot = None
         self.steps_done = 0
         self.t_submit = None
@@ -103,19 +107,24 @@ class Job:
         return int(per_slot * slots + mesh)
 
 
+# work-item size and persistent grid of the batched 2D launch (the
+# autotuner's choice for the avalanche ensemble)
+TILE_2D, GRID_2D = 2048, 2048
+
+
 class Server:
     def __init__(self, budget_bytes=None, tick_steps=25, field_every=10, adapt_every=10, max_slots=512,
-                 keep_results=False, stream=None, batched=True, workers=4):
+                 keep_results=False, stream=None, batched=True, lanes=4):
         self.ctx = B.Context([], stream=stream)
-        # 2D jobs: own contexts on `workers` streams (default priority), driven by
-        # as many threads; workers = 0 keeps them in the shared context
-        self.workers = workers
-        self.streams = []
+        # 2D jobs: `lanes` contexts, each on its own stream and driven by its
+        # own thread; lanes = 0 keeps them in the 1D jobs' context
+        self.lanes = []
         self.pool = None
-        if workers > 0:
+        if lanes > 0:
             import torch
-            self.streams = [torch.cuda.Stream() for _ in range(workers)]
-            self.pool = ThreadPoolExecutor(max_workers=workers)
+            self.streams = [torch.cuda.Stream() for _ in range(lanes)]
+            self.lanes = [B.Context([], stream=ctypes.c_void_p(st.cuda_stream)) for st in self.streams]
+            self.pool = ThreadPoolExecutor(max_workers=lanes)
         self.n_started = 0
         if budget_bytes is None:
             import torch
@@ -140,14 +149,11 @@ class Server:
         self.pending.append(job)
 
     def _start(self, job):
-        if job.kind == "streamer" and self.workers > 0:
-            job.stream_index = self.n_started % self.workers
-            st = self.streams[job.stream_index]
-            job.ctx = B.Context([], stream=ctypes.c_void_p(st.cuda_stream))
-            job.own_ctx = True
-        else:
-            job.ctx = self.ctx
-        self.n_started += 1
+        job.ctx = self.ctx
+        if job.kind == "streamer" and self.lanes:
+            job.lane = self.n_started % len(self.lanes)
+            job.ctx = self.lanes[job.lane]
+            self.n_started += 1
         g = job.ctx
         slot = g.admit(job.desc)
         job.slot = slot
@@ -201,47 +207,95 @@ class Server:
                 j.updates += u / len(group)
         return upd
 
-    def _tick_streamer(self, j):
-        """One tick of a 2D job: steps with adaptation and a field solve every
-        few steps.  Touches only the job's own context.  A job that runs out
-        of device memory fails and is retired."""
-        upd = 0
-        n = min(self.tick_steps, j.steps_total - j.steps_done)
+    def _fail(self, j, e):
+        """A job that ran out of device memory (or past the library's
+        per-array limit) fails and is retired; the others go on."""
+        if e.code not in (B.PIC_E_NOMEM, B.PIC_E_CAPACITY):
+            raise e
+        j.failed = True
+        j.error = (e.code, str(e))
+        print(json.dumps(dict(job_failed=j.spec.get("key"), steps=j.steps_done, particles=j.n_now, error=str(e))),
+              file=sys.stderr, flush=True)
+        j.steps_done = j.steps_total
+
+    def _cycle(self, j):
+        """Adaptation and field solve of a 2D job at its cycle boundaries."""
         try:
-            while n > 0:
-                chunk = min(n, self.field_every - (j.steps_done % self.field_every))
-                st = j.ctx.step(-1, chunk, slots=[j.slot], sort_every=0)
-                u = st["alive_start"][0] + st["alive_start"][1]
-                upd += u
-                j.updates += u
-                j.steps_done += chunk
-                n -= chunk
-                if j.steps_done % self.adapt_every == 0 and j.steps_done < j.steps_total:
-                    j.ctx.adapt(j.slot)
-                if j.steps_done % self.field_every == 0 and j.steps_done < j.steps_total:
-                    self._solve2d(j)
-            j.n_now = j.ctx.count(j.slot, 0) + j.ctx.count(j.slot, 1)
+            if j.steps_done % self.adapt_every == 0 and j.steps_done < j.steps_total:
+                j.ctx.adapt(j.slot)
+            if j.steps_done % self.field_every == 0 and j.steps_done < j.steps_total:
+                self._solve2d(j)
         except B.PicError as e:
-            # out of device memory, or past the library's per-array limit
+            self._fail(j, e)
+
+    def _step_group(self, grp, n):
+        """n steps of a group of 2D jobs at the same point of their cycle:
+        one persistent launch per step over all of them (batched), or per-job
+        launches (plain).  If the call fails for memory, each job's progress
+        is read back from the library and the jobs go on one by one, so only
+        the ones that cannot grow fail."""
+        kw = dict(batched=TILE_2D, grid=GRID_2D) if self.batched else {}
+        ctx = grp[0].ctx
+        try:
+            st = ctx.step(-1, n, slots=[j.slot for j in grp], sort_every=0, **kw)
+        except B.PicError as e:
             if e.code not in (B.PIC_E_NOMEM, B.PIC_E_CAPACITY):
                 raise
-            j.failed = True
-            j.error = (e.code, str(e))
-            print(json.dumps(dict(job_failed=j.spec.get("key"), steps=j.steps_done, particles=j.n_now, error=str(e))),
-                  file=sys.stderr, flush=True)
-            j.steps_done = j.steps_total
-        return upd
+            upd = 0
+            for j in grp:
+                target = j.steps_done + n
+                j.steps_done = ctx.step_index(j.slot)
+                try:
+                    if j.steps_done < target:
+                        st = ctx.step(-1, target - j.steps_done, slots=[j.slot], sort_every=0)
+                        u = st["alive_start"][0] + st["alive_start"][1]
+                        upd += u
+                        j.updates += u
+                        j.steps_done = target
+                except B.PicError as e2:
+                    j.steps_done = ctx.step_index(j.slot)
+                    self._fail(j, e2)
+            return upd
+        u = st["alive_start"][0] + st["alive_start"][1]
+        for j in grp:
+            j.steps_done += n
+            j.updates += u / len(grp)   # attributed by share (reporting only)
+        return u
 
     def _step_streamers(self):
-        jobs = [j for j in self.running if j.kind == "streamer"]
-        if self.pool is None:
-            return sum(self._tick_streamer(j) for j in jobs)
-        # jobs on one stream run in one worker, in order; the streams run concurrently
-        lanes = [[j for j in jobs if j.ctx is not None and j.stream_index == w] for w in range(self.workers)]
+        """Advance every resident 2D job by up to tick_steps steps, the lanes
+        concurrently."""
+        jobs = [j for j in self.running if j.kind == "streamer" and j.steps_done < j.steps_total]
+        if not self.lanes:
+            return self._step_lane(jobs)
+        per = [[j for j in jobs if j.lane == k] for k in range(len(self.lanes))]
+        return sum(self.pool.map(self._step_lane, [p for p in per if p]))
 
-        def run(lane):
-            return sum(self._tick_streamer(j) for j in lane)
-        return sum(self.pool.map(run, [ln for ln in lanes if ln]))
+    def _step_lane(self, jobs):
+        """Advance the 2D jobs of one context by up to tick_steps steps.  Jobs
+        whose next cycle boundary is equally far step together; after the
+        first boundary every job is aligned with the others."""
+        left = {id(j): min(self.tick_steps, j.steps_total - j.steps_done) for j in jobs}
+        upd = 0
+        while True:
+            active = [j for j in jobs if left[id(j)] > 0 and not j.failed]
+            if not active:
+                break
+            groups = {}
+            for j in active:
+                n = min(left[id(j)], self.field_every - j.steps_done % self.field_every)
+                groups.setdefault(n, []).append(j)
+            for n in sorted(groups):
+                grp = groups[n]
+                upd += self._step_group(grp, n)
+                for j in grp:
+                    if not j.failed:
+                        left[id(j)] -= n
+                        self._cycle(j)
+        for j in jobs:
+            if not j.failed:
+                j.n_now = j.ctx.count(j.slot, 0) + j.ctx.count(j.slot, 1)
+        return upd
 
     def _retire(self):
         now = time.perf_counter()
@@ -256,10 +310,7 @@ class Server:
                     r = j.growth_rate()
                     if r is not None:
                         self.lam = max(self.lam, r)
-                if j.own_ctx:
-                    g.close()
-                else:
-                    g.retire(j.slot)
+                g.retire(j.slot)
                 j.ctx = None
                 j.t_done = now
                 self.done.append(j)
@@ -329,11 +380,10 @@ class Server:
             self.running.append(job)
 
     def close(self):
-        for j in self.running:
-            if j.own_ctx and j.ctx is not None:
-                j.ctx.close()
         if self.pool is not None:
             self.pool.shutdown()
+        for g in self.lanes:
+            g.close()
         self.ctx.close()
 
 
@@ -363,25 +413,27 @@ def main():
     ap.add_argument("--steps-scale", type=float, default=0.2,
                     help=f"scale every job's step count (at most {MAX_STEPS_SCALE})")
     ap.add_argument("--tick-steps", type=int, default=25)
-    ap.add_argument("--workers", type=int, default=4, help="streams / threads driving the 2D jobs (0: none)")
+    ap.add_argument("--lanes", type=int, default=4, help="contexts / streams / threads of the 2D jobs (0: none)")
     ap.add_argument("--plain", action="store_true",
                     help="the plain method: FP64 particles, every job stepped with its own launches")
     args = ap.parse_args()
     if args.steps_scale > MAX_STEPS_SCALE:
         raise SystemExit(f"--steps-scale {args.steps_scale} refused: a full-length stream (avalanche jobs "
-                         f"of 2000 steps, up to ~100 resident 2D contexts) once ended in an illegal device "
-                         f"memory access whose cause is not yet found; use at most {MAX_STEPS_SCALE}")
+                         f"of 2000 steps, then served with one context per 2D job) once ended in an illegal "
+                         f"device memory access whose cause is not yet found; use at most {MAX_STEPS_SCALE}")
     import torch
     torch.cuda.set_device(0)
     jobs = make_jobs(args.rate, args.duration, scale=args.steps_scale, precision=64 if args.plain else 32)
-    srv = Server(tick_steps=args.tick_steps, batched=not args.plain, workers=args.workers)
+    srv = Server(tick_steps=args.tick_steps, batched=not args.plain, lanes=args.lanes)
     m = srv.run(jobs, max_wall=args.max_wall, progress_every=10.0)
     offered = sum(j.nparticles * j.steps_total for j in jobs) / max(args.duration, 1e-9)
     m["offered_updates_per_s_lower_bound"] = offered
     m["ccp_jobs"] = sum(1 for j in jobs if j.kind == "ccp")
     m["streamer_jobs"] = sum(1 for j in jobs if j.kind == "streamer")
-    m["method"] = "plain FP64, per-job launches" if args.plain else "batched FP32, one launch for all 1D jobs"
-    m["workers_2d"] = args.workers
+    m["method"] = ("plain FP64, per-job launches" if args.plain
+                   else "batched FP32, one launch per step for all 1D jobs and one per lane for its 2D jobs "
+                        "at one cycle point")
+    m["lanes_2d"] = args.lanes
     print(json.dumps(m), flush=True)
     srv.close()
 
