@@ -33,7 +33,8 @@ class Desc(C.Structure):
                 ("gas_density", C.c_double), ("gas_temperature", C.c_double), ("gas_mass", C.c_double),
                 ("seed", C.c_uint64), ("instance_key", C.c_uint32), ("nspecies", C.c_int),
                 ("species", Species * 2), ("field_scheme", C.c_int),
-                ("leaf_keys", C.c_void_p), ("leaf_levels", C.c_void_p), ("nleaves", C.c_int64)]
+                ("leaf_keys", C.c_void_p), ("leaf_levels", C.c_void_p), ("nleaves", C.c_int64),
+                ("disk_cz", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -121,6 +122,7 @@ def make_desc(d):
     for i in range(4):
         c.field_bc[i] = int(d["field_bc"][i])
         c.wall_phi[i] = float(d["wall_phi"][i])
+    c.disk_cz = float(d.get("disk_cz", 0.5))
     c.seed = int(d["seed"])
     c.instance_key = int(d["instance_key"])
     c.field_scheme = int(d.get("field_scheme", 0))
@@ -244,12 +246,16 @@ class Oracle:
     def field_table(self):
         if self.dim == 1:
             n = self.nq()
+        elif self.dim == 3:
+            n = self.nq() * 24
         else:
             n = self.nq() * (2 if self.desc.get("field_scheme", 0) == FIELD_CIC_AMR else 8)
         out = np.zeros(n)
         self.L.or_field_table(self.h, _ptr(out))
         if self.dim == 1:
             return out
+        if self.dim == 3:
+            return out.reshape(-1, 8, 3)
         return out.reshape(-1, 2) if self.desc.get("field_scheme", 0) == FIELD_CIC_AMR else out.reshape(-1, 4, 2)
 
     def gather(self, s):
@@ -298,7 +304,7 @@ class Oracle:
         return st.as_dict()
 
     def locate(self, s):
-        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1, 2)
+        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1, self.dim)
         out = np.zeros(len(s), dtype=np.uint32)
         _check(self.L.or_locate(self.h, len(s), _ptr(s), _ptr(out)), "or_locate")
         return out
@@ -313,4 +319,5 @@ class Oracle:
 
 # field kinds
 NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D, CELL_E_2D = 0, 1, 2, 3, 4, 5, 6
+CORNER_PHI_3D, CORNER_E_3D = 7, 8
 FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR = 0, 1, 2

@@ -218,6 +218,67 @@ uint32_t morton16(uint32_t x, uint32_t y) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Octree (pointer form): cubic cells (Sec. 3.1 quad/octree), children    */
+/* in Morton order (x fastest, then y, then z)                           */
+/* ------------------------------------------------------------------ */
+struct ONode {
+  int level;
+  uint32_t i[3];
+  std::unique_ptr<ONode> kid[8];
+  int64_t leaf_index;
+  bool is_leaf() const { return !kid[0]; }
+  double h() const { return std::ldexp(1.0, -level); }
+  double lo(int a) const { return i[a] * h(); }
+  double hi(int a) const { return (i[a] + 1) * h(); }
+};
+
+void refine8(ONode* n) {
+  for (int c = 0; c < 8; ++c) {
+    n->kid[c].reset(new ONode());
+    ONode* k = n->kid[c].get();
+    k->level = n->level + 1;
+    for (int a = 0; a < 3; ++a) k->i[a] = 2 * n->i[a] + ((c >> a) & 1);
+    k->leaf_index = -1;
+  }
+}
+
+void collect8(ONode* n, std::vector<ONode*>& out) {
+  if (n->is_leaf()) { n->leaf_index = (int64_t)out.size(); out.push_back(n); return; }
+  for (int c = 0; c < 8; ++c) collect8(n->kid[c].get(), out);
+}
+
+/* leaves whose closed box meets the closed box [lo, hi] */
+void touching3(ONode* n, const double lo[3], const double hi[3], std::vector<ONode*>& out) {
+  for (int a = 0; a < 3; ++a)
+    if (n->lo(a) > hi[a] || lo[a] > n->hi(a)) return;
+  if (n->is_leaf()) { out.push_back(n); return; }
+  for (int c = 0; c < 8; ++c) touching3(n->kid[c].get(), lo, hi, out);
+}
+
+ONode* locate3(ONode* root, const double s[3]) {
+  ONode* n = root;
+  while (!n->is_leaf()) {
+    const double hh = std::ldexp(1.0, -(n->level + 1));
+    int c = 0;
+    for (int a = 0; a < 3; ++a)
+      if (s[a] >= (2 * n->i[a] + 1) * hh) c |= 1 << a;
+    n = n->kid[c].get();
+  }
+  return n;
+}
+
+/* Morton code of three 10-bit coordinates (x in bits 0, 3, 6, ...) */
+uint32_t morton10(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t k = 0;
+  for (int b = 0; b < 10; ++b) {
+    k |= ((x >> b) & 1u) << (3 * b);
+    k |= ((y >> b) & 1u) << (3 * b + 1);
+    k |= ((z >> b) & 1u) << (3 * b + 2);
+  }
+  return k;
+}
+
+/* ------------------------------------------------------------------ */
 /* Simulation state                                                    */
 /* ------------------------------------------------------------------ */
 struct SimBase {
@@ -226,7 +287,7 @@ struct SimBase {
 };
 
 template <class T> struct Particle {
-  T s[2];
+  T s[3];
   T v[3];
   uint32_t w;
   uint32_t id;
@@ -259,6 +320,11 @@ template <class T> struct Sim : SimBase {
   std::vector<double> cornerPhi; /* [leaf][corner]: potentials behind cornerE (if given) */
   std::vector<T> cellE;          /* [leaf][2]: cell-centred E (cloud-in-cell coupling), in T */
   std::vector<double> cellE64;
+  /* 3D */
+  std::unique_ptr<ONode> root3;
+  std::vector<ONode*> leaves3;
+  std::vector<T> cornerE3;       /* [leaf][corner][3] in T */
+  std::vector<double> cornerE3_64;
   /* deposit */
   std::vector<uint64_t> Q[2];
 
@@ -297,11 +363,157 @@ template <class T> struct Sim : SimBase {
     }
   }
 
-  int64_t nq() const { return d.dim == 1 ? (int64_t)N + 1 : (int64_t)leaves.size(); }
+  int64_t nq() const {
+    return d.dim == 1 ? (int64_t)N + 1 : d.dim == 3 ? (int64_t)leaves3.size() : (int64_t)leaves.size();
+  }
+
+  /* ---------------- 3D mesh: static octree ---------------- */
+  /* base level everywhere, then every leaf whose closed box meets the
+     closed ball (centre disk_cx, disk_cy, disk_cz, radius disk_r) refined
+     until disk_level, then 2:1 balance across faces, edges and corners */
+  bool build3() {
+    if (d.min_level < 0 || d.max_level > 10 || d.min_level > d.max_level || d.base_level < d.min_level ||
+        d.base_level > d.max_level)
+      return false;
+    if (d.nleaves > 0 || d.field_scheme != OR_FIELD_CIC_EM) return false;
+    root3.reset(new ONode());
+    root3->level = 0;
+    root3->i[0] = root3->i[1] = root3->i[2] = 0;
+    root3->leaf_index = -1;
+    refine_uniform3(root3.get(), d.base_level);
+    if (d.refine_disk) {
+      const double c[3] = {d.disk_cx, d.disk_cy, d.disk_cz};
+      bool changed = true;
+      while (changed) {
+        changed = false;
+        std::vector<ONode*> lv;
+        collect8(root3.get(), lv);
+        for (ONode* n : lv) {
+          if (n->level >= d.disk_level || n->level >= d.max_level) continue;
+          double r2 = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            const double g = std::max(std::max(n->lo(a) - c[a], 0.0), c[a] - n->hi(a));
+            r2 = r2 + g * g;
+          }
+          if (r2 <= d.disk_r * d.disk_r) { refine8(n); changed = true; }
+        }
+      }
+    }
+    balance3();
+    leaves3.clear();
+    collect8(root3.get(), leaves3);
+    cornerE3.assign(leaves3.size() * 24, (T)0);
+    cornerE3_64.assign(leaves3.size() * 24, 0.0);
+    for (int s = 0; s < 2; ++s) Q[s].assign(leaves3.size(), 0);
+    return true;
+  }
+
+  void refine_uniform3(ONode* n, int L) {
+    if (n->level >= L) return;
+    refine8(n);
+    for (int c = 0; c < 8; ++c) refine_uniform3(n->kid[c].get(), L);
+  }
+
+  int64_t balance3() {
+    int64_t nref = 0;
+    bool changed = true;
+    while (changed) {
+      changed = false;
+      std::vector<ONode*> lv;
+      collect8(root3.get(), lv);
+      std::vector<ONode*> mark;
+      for (ONode* a : lv) {
+        const double lo[3] = {a->lo(0), a->lo(1), a->lo(2)}, hi[3] = {a->hi(0), a->hi(1), a->hi(2)};
+        std::vector<ONode*> t;
+        touching3(root3.get(), lo, hi, t);
+        for (ONode* b : t)
+          if (b->level > a->level + 1) { mark.push_back(a); break; }
+      }
+      for (ONode* a : mark) { refine8(a); ++nref; changed = true; }
+    }
+    return nref;
+  }
+
+  /* Nodal E on the octree from the potentials at each leaf's corners
+     (corner c = a + 2b + 4e along x, y, z): each leaf's E = -grad of its
+     trilinear potential at the corner -- x-component (f(0,b,e) - f(1,b,e))/h
+     and likewise in y and z -- then at every node the mean over the leaves
+     having the node as a corner (Sec. 3: nodal E), taken in octant order
+     (the octant below the node in x first, then y, then z).  The leaf of an
+     octant is the one holding the point half a finest cell from the node
+     into it; the node is one of its corners when its coordinates are
+     multiples of the leaf's size. */
+  void corner_field3(const double* cphi) {
+    const size_t nl = leaves3.size();
+    std::vector<double> g(nl * 24);
+    for (size_t l = 0; l < nl; ++l) {
+      const double h = d.length * std::ldexp(1.0, -leaves3[l]->level);
+      const double* f = &cphi[l * 8];
+      for (int c = 0; c < 8; ++c) {
+        const int a = c & 1, b = (c >> 1) & 1, e = c >> 2;
+        g[l * 24 + c * 3 + 0] = (f[0 + 2 * b + 4 * e] - f[1 + 2 * b + 4 * e]) / h;
+        g[l * 24 + c * 3 + 1] = (f[a + 0 + 4 * e] - f[a + 2 + 4 * e]) / h;
+        g[l * 24 + c * 3 + 2] = (f[a + 2 * b + 0] - f[a + 2 * b + 4]) / h;
+      }
+    }
+    for (size_t l = 0; l < nl; ++l) {
+      const ONode* lf = leaves3[l];
+      const uint32_t size = 1u << (10 - lf->level);
+      for (int c = 0; c < 8; ++c) {
+        uint32_t X[3];
+        for (int a = 0; a < 3; ++a) X[a] = lf->i[a] * size + (((c >> a) & 1) ? size : 0u);
+        double sum[3] = {0.0, 0.0, 0.0};
+        int k = 0;
+        for (int q = 0; q < 8; ++q) {
+          bool inside = true;
+          double pt[3];
+          for (int a = 0; a < 3; ++a) {
+            const int up = (q >> a) & 1;
+            if ((up == 0 && X[a] == 0u) || (up == 1 && X[a] >= 1024u)) inside = false;
+            pt[a] = ((double)X[a] + (up ? 0.5 : -0.5)) / 1024.0;
+          }
+          if (!inside) continue;
+          const ONode* m = locate3(root3.get(), pt);
+          const uint32_t ms = 1u << (10 - m->level);
+          if (X[0] % ms || X[1] % ms || X[2] % ms) continue;   /* on an edge or face of m, not a corner */
+          int mc = 0;
+          for (int a = 0; a < 3; ++a)
+            if (!((q >> a) & 1)) mc |= 1 << a;   /* m lies below the node along a: the node is its upper side */
+          for (int a = 0; a < 3; ++a) sum[a] = sum[a] + g[(size_t)m->leaf_index * 24 + mc * 3 + a];
+          ++k;
+        }
+        for (int a = 0; a < 3; ++a) {
+          const double e = sum[a] / (double)k;
+          cornerE3_64[l * 24 + c * 3 + a] = e;
+          cornerE3[l * 24 + c * 3 + a] = (T)e;
+        }
+      }
+    }
+  }
+
+  /* trilinear interpolation of the leaf's corner E at the particle (Sec. 3:
+     gather from nodal E), weights ((x factor) (y factor)) (z factor),
+     summed over the corners in order */
+  void gather3d(const Particle<T>& q, T E[3]) const {
+    const ONode* lf = leaves3[q.cell];
+    const T sc = (T)std::ldexp(1.0, lf->level);
+    T f[3];
+    for (int a = 0; a < 3; ++a) f[a] = q.s[a] * sc - (T)lf->i[a];
+    const T* ce = &cornerE3[q.cell * 24];
+    for (int k = 0; k < 3; ++k) E[k] = (T)0;
+    for (int c = 0; c < 8; ++c) {
+      const T wx = (c & 1) ? f[0] : (T)1 - f[0];
+      const T wy = ((c >> 1) & 1) ? f[1] : (T)1 - f[1];
+      const T wz = (c >> 2) ? f[2] : (T)1 - f[2];
+      const T w = (wx * wy) * wz;
+      for (int k = 0; k < 3; ++k) E[k] = E[k] + w * ce[c * 3 + k];
+    }
+  }
 
   /* ---------------- mesh ---------------- */
   bool build() {
     derive();
+    if (d.dim == 3) return build3();
     if (d.dim == 1) {
       N = d.ncells;
       if (N < 2) return false;
@@ -416,8 +628,12 @@ template <class T> struct Sim : SimBase {
     return nref;
   }
 
-  int64_t locate_cell(const T s[2]) {
+  int64_t locate_cell(const T s[3]) {
     if (d.dim == 1) return -1;
+    if (d.dim == 3) {
+      const double x[3] = {(double)s[0], (double)s[1], (double)s[2]};
+      return locate3(root3.get(), x)->leaf_index;
+    }
     return locate_node(root.get(), (double)s[0], (double)s[1])->leaf_index;
   }
 
@@ -429,7 +645,8 @@ template <class T> struct Sim : SimBase {
     for (int64_t i = 0; i < n; ++i) {
       Particle<T> q;
       q.s[0] = (T)s[i * d.dim];
-      q.s[1] = d.dim == 2 ? (T)s[i * d.dim + 1] : (T)0;
+      q.s[1] = d.dim >= 2 ? (T)s[i * d.dim + 1] : (T)0;
+      q.s[2] = d.dim == 3 ? (T)s[i * d.dim + 2] : (T)0;
       for (int c = 0; c < 3; ++c) q.v[c] = (T)v[i * 3 + c];
       q.w = w ? w[i] : 65536u;
       q.id = id ? id[i] : (uint32_t)i;
@@ -627,7 +844,7 @@ template <class T> struct Sim : SimBase {
   }
 
   /* ---------------- MCC (null collision) ---------------- */
-  struct Birth { uint32_t parent; T s[2]; int64_t cell; T ve[3]; T vi[3]; uint32_t w; };
+  struct Birth { uint32_t parent; T s[3]; int64_t cell; T ve[3]; T vi[3]; uint32_t w; };
 
   void mcc(int sp, Particle<T>& q, uint32_t step, std::vector<Birth>& births, or_stats* st) {
     const SpeciesK<T>& k = K[sp];
@@ -663,7 +880,7 @@ template <class T> struct Sim : SimBase {
         T va = std::sqrt(v2a), vb = std::sqrt(v2b);
         Birth b;
         b.parent = q.id;
-        b.s[0] = q.s[0]; b.s[1] = q.s[1]; b.cell = q.cell; b.w = q.w;
+        b.s[0] = q.s[0]; b.s[1] = q.s[1]; b.s[2] = q.s[2]; b.cell = q.cell; b.w = q.w;
         for (int c = 0; c < 3; ++c) { v[c] = va * d1[c]; b.ve[c] = vb * d2[c]; }
         for (int c = 0; c < 3; ++c) b.vi[c] = k.v_thgT * gauss12<T>(rs);
         births.push_back(b);
@@ -727,6 +944,20 @@ template <class T> struct Sim : SimBase {
             if (lost_r) st->lost_reflect++;
             continue;
           }
+        } else if (d.dim == 3) {
+          T E[3];
+          gather3d(q, E);
+          for (int a = 0; a < 3; ++a) q.v[a] = q.v[a] + k.qm_dtT * E[a];
+          for (int a = 0; a < 3; ++a) q.s[a] = q.s[a] + q.v[a] * k.dt_LT;
+          bool ok = true;
+          for (int a = 0; a < 3 && ok; ++a) ok = wall(q.s[a], q.v[a], lost_r);
+          if (!ok) {
+            q.alive = false;
+            st->absorbed[sp]++;
+            if (lost_r) st->lost_reflect++;
+            continue;
+          }
+          q.cell = locate_cell(q.s);
         } else {
           T E[2];
           gather2d(q, E);
@@ -758,6 +989,7 @@ template <class T> struct Sim : SimBase {
         Particle<T> e, i;
         e.s[0] = i.s[0] = b.s[0];
         e.s[1] = i.s[1] = b.s[1];
+        e.s[2] = i.s[2] = b.s[2];
         e.cell = i.cell = b.cell;
         e.w = i.w = b.w;
         e.alive = i.alive = true;
@@ -801,7 +1033,10 @@ template <class T> struct Sim : SimBase {
         const double units = (double)(int64_t)Q[sp][i];
         if (d.dim == 1)
           r = r + ((units * std::ldexp(1.0, -(16 + F))) * (s.charge * s.w0)) / (d.length / N);
-        else {
+        else if (d.dim == 3) {
+          const double h = d.length * std::ldexp(1.0, -leaves3[i]->level);
+          r = r + ((units * std::ldexp(1.0, -16)) * (s.charge * s.w0)) / ((h * h) * h);
+        } else {
           const double h = d.length * std::ldexp(1.0, -leaves[i]->level);
           const int f2 = d.field_scheme == OR_FIELD_CIC_AMR ? F : 0;
           r = r + ((units * std::ldexp(1.0, -(16 + f2))) * (s.charge * s.w0)) / ((h * h) * d.depth_z);
@@ -1246,6 +1481,10 @@ template <class T> struct Sim : SimBase {
         if (d.dim == 1) {
           T E = gather1d(q.s[0]);
           q.v[0] = q.v[0] - k.hqm_dtT * E;
+        } else if (d.dim == 3) {
+          T E[3];
+          gather3d(q, E);
+          for (int a = 0; a < 3; ++a) q.v[a] = q.v[a] - k.hqm_dtT * E[a];
         } else {
           T E[2];
           gather2d(q, E);
@@ -1272,11 +1511,11 @@ void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]
 void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) { philox10<uint64_t>(ctr, key, out); }
 
 void* or_create(const or_desc* d) {
-  if (!d || (d->dim != 1 && d->dim != 2) || (d->precision != 32 && d->precision != 64) ||
+  if (!d || d->dim < 1 || d->dim > 3 || (d->precision != 32 && d->precision != 64) ||
       d->nspecies < 1 || d->nspecies > 2 || !(d->length > 0) || !(d->dt > 0) ||
       (d->field_scheme != OR_FIELD_CIC_EM && d->field_scheme != OR_FIELD_CIC_EC &&
        d->field_scheme != OR_FIELD_CIC_AMR) ||
-      (d->dim == 2 && d->field_scheme == OR_FIELD_CIC_EC) ||    /* energy-conserving: uniform 1D mesh */
+      (d->dim >= 2 && d->field_scheme == OR_FIELD_CIC_EC) ||    /* energy-conserving: uniform 1D mesh */
       (d->dim == 1 && d->field_scheme == OR_FIELD_CIC_AMR))     /* cloud on the tree: 2D */
     return nullptr;
   SimBase* b;
@@ -1309,10 +1548,21 @@ int or_read(void* h, int species, double* s, double* v, uint32_t* w, uint32_t* i
   return dispatch(h, [&](auto& S) { return S.read(species, s, v, w, id, cell); });
 }
 
-int64_t or_nleaves(void* h) { return dispatch(h, [&](auto& S) { return (int64_t)S.leaves.size(); }); }
+int64_t or_nleaves(void* h) {
+  return dispatch(h, [&](auto& S) { return S.d.dim == 3 ? (int64_t)S.leaves3.size() : (int64_t)S.leaves.size(); });
+}
 
 int or_leaves(void* h, uint32_t* keys, uint8_t* levels) {
   return dispatch(h, [&](auto& S) {
+    if (S.d.dim == 3) {   /* keys: Morton codes of the 10-bit corner coordinates */
+      for (size_t l = 0; l < S.leaves3.size(); ++l) {
+        const ONode* n = S.leaves3[l];
+        const uint32_t sh = 10 - n->level;
+        keys[l] = morton10(n->i[0] << sh, n->i[1] << sh, n->i[2] << sh);
+        levels[l] = (uint8_t)n->level;
+      }
+      return OR_OK;
+    }
     for (size_t l = 0; l < S.leaves.size(); ++l) {
       const QNode* n = S.leaves[l];
       uint32_t sh = 16 - n->level;
@@ -1357,6 +1607,18 @@ int or_field_set(void* h, int kind, const double* data) {
         std::vector<double> e(S.N + 1);
         S.node_or_cell_e(data, inv2dx, e.data());
         for (int i = 0; i <= S.N; ++i) S.En[i] = (T)e[i];
+        return OR_OK;
+      }
+      return OR_E_ARG;
+    }
+    if (S.d.dim == 3) {
+      const size_t n3 = S.leaves3.size();
+      if (kind == OR_CORNER_PHI_3D) {
+        S.corner_field3(data);
+        return OR_OK;
+      }
+      if (kind == OR_CORNER_E_3D) {
+        for (size_t i = 0; i < n3 * 24; ++i) { S.cornerE3_64[i] = data[i]; S.cornerE3[i] = (T)data[i]; }
         return OR_OK;
       }
       return OR_E_ARG;
@@ -1414,6 +1676,8 @@ int or_field_table(void* h, double* out) {
   return dispatch(h, [&](auto& S) {
     if (S.d.dim == 1)
       for (int i = 0; i <= S.N; ++i) out[i] = (double)S.En[i];
+    else if (S.d.dim == 3)
+      for (size_t i = 0; i < S.cornerE3.size(); ++i) out[i] = (double)S.cornerE3[i];
     else if (S.d.field_scheme == OR_FIELD_CIC_AMR)
       for (size_t i = 0; i < S.cellE.size(); ++i) out[i] = (double)S.cellE[i];
     else
@@ -1430,6 +1694,16 @@ int or_gather(void* h, int64_t n, const double* s, double* out) {
         const T x = (T)s[i];
         if (!(x >= (T)0 && x < (T)1)) return (int)OR_E_ARG;
         out[i] = (double)S.gather1d(x);
+      } else if (S.d.dim == 3) {
+        Particle<T> q;
+        for (int a = 0; a < 3; ++a) {
+          q.s[a] = (T)s[3 * i + a];
+          if (!(q.s[a] >= (T)0 && q.s[a] < (T)1)) return (int)OR_E_ARG;
+        }
+        q.cell = S.locate_cell(q.s);
+        T E[3];
+        S.gather3d(q, E);
+        for (int a = 0; a < 3; ++a) out[3 * i + a] = (double)E[a];
       } else {
         Particle<T> q;
         q.s[0] = (T)s[2 * i];
@@ -1506,6 +1780,10 @@ int or_adapt(void* h, int n_lo, int n_hi, or_adapt_stats* st) {
 
 int or_locate(void* h, int64_t n, const double* s, uint32_t* leaf) {
   return dispatch(h, [&](auto& S) {
+    if (S.d.dim == 3) {
+      for (int64_t i = 0; i < n; ++i) leaf[i] = (uint32_t)locate3(S.root3.get(), &s[3 * i])->leaf_index;
+      return (int)OR_OK;
+    }
     if (S.d.dim != 2) return (int)OR_E_ARG;
     for (int64_t i = 0; i < n; ++i) leaf[i] = (uint32_t)locate_node(S.root.get(), s[2 * i], s[2 * i + 1])->leaf_index;
     return (int)OR_OK;

@@ -45,7 +45,11 @@ enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1, OR_FIELD_CIC_AMR = 2 };
    1D coupling (N+1 node values), OR_CELL_E_1D for the energy-conserving one
    (N cell values); each is refused on the other coupling. */
 enum { OR_NODE_E_1D = 0, OR_NODE_PHI_1D = 1, OR_CORNER_PHI_2D = 2, OR_CORNER_E_2D = 3, OR_CELL_PHI_2D = 4,
-       OR_CELL_E_1D = 5, OR_CELL_E_2D = 6 /* [leaf][2], cloud-in-cell slots only */ };
+       OR_CELL_E_1D = 5, OR_CELL_E_2D = 6 /* [leaf][2], cloud-in-cell slots only */,
+       /* 3D octree: potentials at each leaf's 8 corners [leaf][8], or E at
+          them [leaf][8][3]; corner c = a + 2b + 4e with a, b, e in {0, 1}
+          the sides along x, y, z */
+       OR_CORNER_PHI_3D = 7, OR_CORNER_E_3D = 8 };
 
 typedef struct {
   double charge;     /* C */
@@ -58,13 +62,13 @@ typedef struct {
 } or_species;
 
 typedef struct {
-  int dim;           /* 1 or 2 */
+  int dim;           /* 1, 2 or 3 (3: static octree, field given at the nodes) */
   int precision;     /* 32 or 64 (particle arithmetic); field solve is FP64 */
   double length;     /* 1D gap / 2D square side, m */
   double dt;         /* s */
   int ncells;        /* 1D uniform cells */
-  int min_level, max_level, base_level;        /* 2D */
-  int refine_disk; double disk_cx, disk_cy, disk_r; int disk_level;  /* 2D initial refinement */
+  int min_level, max_level, base_level;        /* 2D (levels <= 14), 3D (levels <= 10) */
+  int refine_disk; double disk_cx, disk_cy, disk_r; int disk_level;  /* 2D disk / 3D ball refinement */
   int field_bc[4]; double wall_phi[4];        /* 2D walls x0,x1,y0,y1 */
   int particle_bc;   /* OR_ABSORB / OR_REFLECT */
   double depth_z;    /* 2D out-of-plane length, m */
@@ -82,6 +86,7 @@ typedef struct {
   const uint32_t* leaf_keys;
   const uint8_t* leaf_levels;
   int64_t nleaves;
+  double disk_cz;    /* 3D: z of the refined ball's centre (x, y: disk_cx, disk_cy) */
 } or_desc;
 
 typedef struct {

@@ -43,7 +43,7 @@ def species(charge, mass, w0=1.0, mcc=MCC_NONE, sigma_el=0.0, sigma_iz=0.0, eps_
 
 def base_desc(**kw):
     d = dict(dim=1, precision=64, length=1.0, dt=1e-12, ncells=0, min_level=0, max_level=0,
-             base_level=0, refine_disk=0, disk_cx=0.5, disk_cy=0.5, disk_r=0.0, disk_level=0,
+             base_level=0, refine_disk=0, disk_cx=0.5, disk_cy=0.5, disk_cz=0.5, disk_r=0.0, disk_level=0,
              field_bc=[WALL_NEUMANN] * 4, wall_phi=[0.0] * 4, particle_bc=ABSORB, depth_z=1.0,
              gas_density=0.0, gas_temperature=300.0, gas_mass=40.0 * AMU, seed=0, instance_key=0,
              species=[], field_scheme=FIELD_CIC_EM)
@@ -158,6 +158,83 @@ def leaf_corners(keys, levels):
 def quadtree_phi(x, y):
     """The static potential of the quadtree workload, V (x, y in m)."""
     return x * x + 0.3 * np.sin(2.0 * math.pi * y)
+
+
+# --------------------------------------------------------------------------
+# 3D static octree: base level 4 refined to level 7 inside a centred ball
+# --------------------------------------------------------------------------
+def octree_static_desc(precision=32, seed=7, base=4, top=7, r=0.15):
+    e = species(-E_CHARGE, M_ELECTRON, 1.0, MCC_NONE)
+    return base_desc(dim=3, precision=precision, length=1.0, dt=1e-9, min_level=base, max_level=top,
+                     base_level=base, refine_disk=1, disk_cx=0.5, disk_cy=0.5, disk_cz=0.5, disk_r=r,
+                     disk_level=top, particle_bc=REFLECT, seed=seed, species=[e], gas_mass=40.0 * AMU)
+
+
+def octree_particles(n, seed=7, t_ev=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = rng.random((n, 3))
+    v = maxwellian(rng, n, t_ev, M_ELECTRON)
+    return s, v, np.full(n, 65536, dtype=np.uint32), np.arange(n, dtype=np.uint32)
+
+
+def leaf_corners3(keys, levels):
+    """Physical-unit corner coordinates of octree leaves given (Morton key of
+    the 10-bit corner coordinates, level): x, y, z arrays of shape
+    (nleaves, 8), corner c = a + 2b + 4e along x, y, z."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    lv = np.asarray(levels, dtype=np.int64)
+    xyz = [np.zeros(len(keys), dtype=np.uint64) for _ in range(3)]
+    for b in range(10):
+        for a in range(3):
+            xyz[a] |= ((keys >> np.uint64(3 * b + a)) & np.uint64(1)) << np.uint64(b)
+    h = 2.0 ** (-lv.astype(np.float64))
+    base = [x.astype(np.float64) / 1024.0 for x in xyz]
+    out = []
+    for a in range(3):
+        side = np.array([(c >> a) & 1 for c in range(8)], dtype=np.float64)
+        out.append(base[a][:, None] + side[None, :] * h[:, None])
+    return out
+
+
+def octree_phi(x, y, z):
+    """The static potential of the octree workload, V (x, y, z in m)."""
+    return x * x + 0.3 * np.sin(2.0 * math.pi * y) + 0.5 * z * z
+
+
+def octree_avalanche_desc(precision=32, seed=8, side=0.005, e0=3e6, top=7):
+    """Electron avalanche on a static octree in a uniform field along z
+    (the avalanche physics above, 1 atm, 30 kV/cm), absorbing walls, levels
+    4 to 7 refined around the seed."""
+    n_g = 101325.0 / (K_BOLTZMANN * 300.0)
+    m_i = 28.0 * AMU
+    e = species(-E_CHARGE, M_ELECTRON, 1.0, MCC_ELECTRON, sigma_el=1e-19, sigma_iz=2e-20, eps_iz=15.6,
+                eps_max=200.0)
+    i = species(E_CHARGE, m_i, 1.0, MCC_NONE)
+    d = base_desc(dim=3, precision=precision, length=side, dt=1e-13, min_level=4, max_level=top, base_level=4,
+                  refine_disk=1, disk_cx=0.5, disk_cy=0.5, disk_cz=0.5, disk_r=0.2, disk_level=top,
+                  particle_bc=ABSORB, gas_density=n_g, gas_temperature=300.0, gas_mass=m_i, seed=seed,
+                  species=[e, i])
+    d["extra"] = dict(e0=e0)
+    return d
+
+
+def octree_avalanche_phi(desc, x, y, z):
+    """Potential of the uniform field along z: 0 at z = 0, E0 L at z = L."""
+    return desc["extra"]["e0"] * z
+
+
+def octree_avalanche_particles(desc, npairs=3000, sigma=0.1):
+    rng = np.random.Generator(np.random.PCG64(desc["seed"]))
+    pos = np.empty((0, 3))
+    while len(pos) < npairs:
+        p = rng.normal(0.5, sigma, size=(npairs, 3))
+        p = p[np.all((p >= 0.0) & (p < 1.0), axis=1)]
+        pos = np.concatenate([pos, p])[:npairs]
+    ve = maxwellian(rng, npairs, 1.0, M_ELECTRON)
+    vi = maxwellian(rng, npairs, K_BOLTZMANN * 300.0 / E_CHARGE, desc["species"][1]["mass"])
+    w = np.full(npairs, 65536, dtype=np.uint32)
+    return [(pos.copy(), ve, w.copy(), np.arange(npairs, dtype=np.uint32)),
+            (pos.copy(), vi, w.copy(), np.arange(npairs, 2 * npairs, dtype=np.uint32))]
 
 
 # --------------------------------------------------------------------------

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_cic_amr as C
+from tests import test_oracle_octree as O3
 from tests import test_oracle_tree_pins as P
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.cpp")
@@ -56,6 +57,26 @@ MUTANTS = {
         "return P[x].id < P[y].id;",
         "return P[x].id > P[y].id;",
         P.check_merge_pairs),
+    "trilinear weight takes the wrong side in z": (
+        "const T wz = (c >> 2) ? f[2] : (T)1 - f[2];",
+        "const T wz = (c >> 2) ? (T)1 - f[2] : f[2];",
+        O3.check_trilinear),
+    "octree balance allows two levels": (
+        "if (b->level > a->level + 1) { mark.push_back(a); break; }\n      }\n      for (ONode* a : mark)",
+        "if (b->level > a->level + 2) { mark.push_back(a); break; }\n      }\n      for (ONode* a : mark)",
+        O3.check_mesh),
+    "octree locate sends points on a mid-plane down": (
+        "if (s[a] >= (2 * n->i[a] + 1) * hh) c |= 1 << a;",
+        "if (s[a] > (2 * n->i[a] + 1) * hh) c |= 1 << a;",
+        O3.check_locate),
+    "ball refinement stops a level early": (
+        "if (n->level >= d.disk_level || n->level >= d.max_level) continue;\n          double r2",
+        "if (n->level + 1 >= d.disk_level || n->level >= d.max_level) continue;\n          double r2",
+        O3.check_mesh),
+    "octree nodal E divides by eight always": (
+        "const double e = sum[a] / (double)k;",
+        "const double e = sum[a] / 8.0;",
+        O3.check_nodal_e),
 }
 
 
