@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 3
+#define PIC_ABI_VERSION 4
 
 typedef struct pic_ctx_s* pic_ctx;
 
@@ -104,9 +104,18 @@ enum {
   PIC_CORNER_E_2D = 3,   /* double[nleaves][4][2]: nodal E at leaf corners    */
   PIC_CELL_PHI_2D = 4,   /* double[nleaves]: cell-centre potential            */
   PIC_CELL_E_1D = 5,     /* double[ncells]: E of each cell, V/m (energy-conserving slots only) */
-  PIC_CELL_E_2D = 6      /* double[nleaves][2]: cell-centred E, V/m (cloud-in-cell slots only) */
+  PIC_CELL_E_2D = 6,     /* double[nleaves][2]: cell-centred E, V/m (cloud-in-cell slots only) */
+  PIC_CORNER_PHI_3D = 7, /* double[nleaves][8]: potential at octree leaf corners, V */
+  PIC_CORNER_E_3D = 8    /* double[nleaves][8][3]: nodal E at octree leaf corners, V/m */
 };
-/* corner order of a leaf: 0 = (x0,y0), 1 = (x1,y0), 2 = (x0,y1), 3 = (x1,y1) */
+/* corner order of a quadtree leaf: 0 = (x0,y0), 1 = (x1,y0), 2 = (x0,y1),
+ * 3 = (x1,y1); of an octree leaf: c = a + 2b + 4e with a, b, e in {0, 1} the
+ * lower / upper side along x, y, z.  On the octree (Sec. 3.1 quad/octree,
+ * cubic cells) the nodal E of a node is the mean, over the leaves having it
+ * as a corner, of their trilinear-potential gradients there (taken in octant
+ * order: below the node in x first, then y, then z), the gather is the
+ * trilinear interpolation of the leaf's corner E and the deposit is NGP to
+ * the leaf. */
 
 typedef struct {
   double charge;        /* C */
@@ -121,14 +130,18 @@ typedef struct {
 } pic_species_desc;
 
 typedef struct {
-  int dim;              /* 1 (uniform mesh) or 2 (quadtree)                      */
+  int dim;              /* 1 (uniform mesh), 2 (quadtree) or 3 (static octree:
+                           field given at the nodes; no pic_adapt, no
+                           pic_field_solve, no batched steps)                 */
   int precision;        /* PIC_FP32 or PIC_FP64: particle arithmetic             */
   double length;        /* m: 1D gap, or side of the 2D square                   */
   double dt;            /* s                                                      */
   int ncells;           /* 1D: uniform cells (2 .. 1<<20)                        */
-  int min_level, max_level, base_level;   /* 2D levels, 0 .. 14                 */
-  int refine_disk;      /* 2D: refine leaves whose closed box meets the disk ... */
-  double disk_cx, disk_cy, disk_r;        /* ... (normalised centre, radius)    */
+  int min_level, max_level, base_level;   /* 2D levels, 0 .. 14; 3D, 0 .. 10   */
+  int refine_disk;      /* 2D / 3D: refine leaves whose closed box meets the
+                           disk / ball ...                                      */
+  double disk_cx, disk_cy, disk_r;        /* ... (normalised centre, radius;
+                                             3D: centre z in disk_cz)          */
   int disk_level;       /* ... up to this level, then 2:1 balance               */
   int field_bc[4];      /* 2D walls x=0, x=1, y=0, y=1: PIC_WALL_*               */
   double wall_phi[4];   /* Dirichlet wall potentials, V                          */
@@ -156,6 +169,7 @@ typedef struct {
   const uint32_t* leaf_keys;
   const uint8_t* leaf_levels;
   int64_t nleaves;
+  double disk_cz;       /* 3D: normalised z of the refined ball's centre        */
 } pic_instance_desc;
 
 typedef struct {

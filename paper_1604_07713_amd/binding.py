@@ -17,8 +17,9 @@ _LIB = None
 
 PIC_OK, PIC_E_ARG, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR = 0, 1, 2   # particle-field couplings (include/pic.h)
-ABI_VERSION = 3                     # PIC_ABI_VERSION of include/pic.h
+ABI_VERSION = 4                     # PIC_ABI_VERSION of include/pic.h
 NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D, CELL_E_2D = 0, 1, 2, 3, 4, 5, 6
+CORNER_PHI_3D, CORNER_E_3D = 7, 8
 
 
 class LibraryMissing(RuntimeError):
@@ -46,7 +47,8 @@ class InstanceDesc(C.Structure):
                 ("gas_density", C.c_double), ("gas_temperature", C.c_double), ("gas_mass", C.c_double),
                 ("seed", C.c_uint64), ("instance_key", C.c_uint32), ("nspecies", C.c_int),
                 ("species", SpeciesDesc * 2), ("capacity", C.c_int64 * 2), ("field_scheme", C.c_int),
-                ("leaf_keys", C.c_void_p), ("leaf_levels", C.c_void_p), ("nleaves", C.c_int64)]
+                ("leaf_keys", C.c_void_p), ("leaf_levels", C.c_void_p), ("nleaves", C.c_int64),
+                ("disk_cz", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -189,6 +191,7 @@ def make_desc(d, capacity=(0, 0)):
     for i in range(4):
         c.field_bc[i] = int(d["field_bc"][i])
         c.wall_phi[i] = float(d["wall_phi"][i])
+    c.disk_cz = float(d.get("disk_cz", 0.5))
     c.seed = int(d["seed"])
     c.instance_key = int(d["instance_key"])
     c.nspecies = len(d["species"])
@@ -336,11 +339,14 @@ class Context:
 
     def field_table(self, slot=0):
         cic = self.dim(slot) == 2 and self._slot_desc[slot].get("field_scheme", 0) == FIELD_CIC_AMR
-        n = self.nq(slot) if self.dim(slot) == 1 else self.nq(slot) * (2 if cic else 8)
+        n = (self.nq(slot) if self.dim(slot) == 1 else self.nq(slot) * 24 if self.dim(slot) == 3
+             else self.nq(slot) * (2 if cic else 8))
         out = np.zeros(n)
         self._check(lib().pic_field_read(self.h, slot, _p(out)))
         if self.dim(slot) == 1:
             return out
+        if self.dim(slot) == 3:
+            return out.reshape(-1, 8, 3)
         return out.reshape(-1, 2) if cic else out.reshape(-1, 4, 2)
 
     def gather(self, slot, s):
@@ -417,7 +423,7 @@ class Context:
         self._check(lib().pic_sort(self.h, slot))
 
     def locate(self, slot, s):
-        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1, 2)
+        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1, self.dim(slot))
         out = np.zeros(len(s), dtype=np.uint32)
         self._check(lib().pic_locate(self.h, slot, len(s), _p(s), _p(out)))
         return out

@@ -146,6 +146,21 @@ __global__ void k_locate_points(const uint32_t* key, const uint8_t* lv, const ui
   out[i] = locate_leaf(key, lv, lut, L, X, Y);
 }
 
+__global__ void k_locate_points3(const uint32_t* key, const uint8_t* lv, const uint32_t* lut, int L, const double* s,
+                                 int64_t n, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = locate_leaf3(key, lv, lut, L, (uint32_t)(s[3 * i] * 1024.0), (uint32_t)(s[3 * i + 1] * 1024.0),
+                        (uint32_t)(s[3 * i + 2] * 1024.0));
+}
+
+// A coordinate inside [0, 1) once rounded to the particle precision (a
+// double just below 1 rounds to 1 in FP32).
+bool in_unit(double x, int prec) {
+  const double r = prec == 32 ? (double)(float)x : x;
+  return r >= 0.0 && r < 1.0;
+}
+
 __global__ void k_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -397,7 +412,8 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
         J.ncell = N;
         PBuf& d = sl.pb[sp][1 - sl.cur[sp]];
         J.off = sl.off + (size_t)sp * (N + 1);
-        J.dst = SortDst<T>{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
+        J.dst = SortDst<T>{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell,
+                           (T*)d.s[2]};
         max_ncell = std::max(max_ncell, N);
       }
     }
@@ -607,7 +623,7 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
   if (n < 0 || n > 0x7FFFFFFF || (n > 0 && (!s || !v))) throw Err(PIC_E_ARG, "bad particle arrays");
   const int dim = sl.d.dim;
   for (int64_t i = 0; i < n * dim; ++i)
-    if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "position outside [0,1)");
+    if (!in_unit(s[i], sl.prec)) throw Err(PIC_E_ARG, "position outside [0,1) in the particle precision");
   int64_t cap = sl.d.capacity[species] > 0 ? std::max<int64_t>(sl.d.capacity[species], n)
                                             : (sl.ionizing ? 3 * n + 4096 : n);
   cap = std::max<int64_t>(cap, 256);
@@ -653,7 +669,7 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
   cn.next_id = std::max(cn.next_id, std::max(sl.max_id_loaded[0], sl.max_id_loaded[1]));
   write_counters(*c, sl, cn);
   if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) alloc_births(*c, sl, sl.cap[0]);
-  if (dim == 2 && n) {
+  if (dim >= 2 && n) {
     if (sl.prec == 32) hip_check(launch_relocate<float>(make_dev<float>(sl), species, c->stream, grid_for(n)), "relocate");
     else hip_check(launch_relocate<double>(make_dev<double>(sl), species, c->stream, grid_for(n)), "relocate");
   }
@@ -702,7 +718,7 @@ int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, u
   if (n) {
     hip_check(hipMemcpy(hw.data(), b.w, 4 * n, hipMemcpyDeviceToHost), "read");
     hip_check(hipMemcpy(hid.data(), b.id, 4 * n, hipMemcpyDeviceToHost), "read");
-    if (dim == 2) hip_check(hipMemcpy(hc.data(), b.cell, 4 * n, hipMemcpyDeviceToHost), "read");
+    if (dim >= 2) hip_check(hipMemcpy(hc.data(), b.cell, 4 * n, hipMemcpyDeviceToHost), "read");
     std::vector<char> tmp(e * n);
     auto get = [&](const void* src, double* dst, int stride, int comp) {
       hip_check(hipMemcpy(tmp.data(), src, e * n, hipMemcpyDeviceToHost), "read");
@@ -723,7 +739,7 @@ int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, u
     if (w) w[j] = hw[i];
     if (id) id[j] = hid[i];
     if (cell) {
-      if (dim == 2) {
+      if (dim >= 2) {
         cell[j] = hc[i];
       } else {
         const int N = sl.d.ncells;
@@ -742,14 +758,14 @@ int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, u
 int64_t pic_nleaves(pic_ctx c, int slot) {
   PIC_GUARD_BEGIN
   Slot& sl = get_slot(c, slot);
-  return sl.d.dim == 2 ? (int64_t)sl.nleaves : 0;
+  return sl.d.dim >= 2 ? (int64_t)sl.nleaves : 0;
   PIC_GUARD_END(c)
 }
 
 int pic_leaves_read(pic_ctx c, int slot, uint32_t* keys, uint8_t* levels) {
   PIC_GUARD_BEGIN
   Slot& sl = get_slot(c, slot);
-  if (sl.d.dim != 2) throw Err(PIC_E_ARG, "not a quadtree slot");
+  if (sl.d.dim < 2) throw Err(PIC_E_ARG, "not a tree slot");
   c->sync();
   if (keys) hip_check(hipMemcpy(keys, sl.key, 4 * (size_t)sl.nleaves, hipMemcpyDeviceToHost), "read");
   if (levels) hip_check(hipMemcpy(levels, sl.lv, sl.nleaves, hipMemcpyDeviceToHost), "read");
@@ -783,6 +799,23 @@ int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
     // data staged in phi64 (node potential or node E) -> E table
     if (sl.prec == 32) hip_check(launch_node_e_1d<float>(make_dev<float>(sl), sl.phi64, kind == PIC_NODE_PHI_1D, c->stream), "node_e");
     else hip_check(launch_node_e_1d<double>(make_dev<double>(sl), sl.phi64, kind == PIC_NODE_PHI_1D, c->stream), "node_e");
+    c->sync();
+    return PIC_OK;
+  }
+  if (sl.d.dim == 3) {   // octree: corner potentials -> nodal E, or corner E given
+    const Mesh2D m3 = mesh_of(sl);
+    const size_t n3 = sl.nleaves;
+    if (kind == PIC_CORNER_PHI_3D) {
+      hip_check(hipMemcpy(sl.cphi, data, 8 * 8 * n3, hipMemcpyHostToDevice), "upload");
+      if (sl.prec == 32) hip_check(launch_corner_field3<float>(m3, sl.cphi, sl.grad, sl.e64, (float*)sl.E, c->stream), "corner3");
+      else hip_check(launch_corner_field3<double>(m3, sl.cphi, sl.grad, sl.e64, (double*)sl.E, c->stream), "corner3");
+    } else if (kind == PIC_CORNER_E_3D) {
+      hip_check(hipMemcpy(sl.e64, data, 8 * 24 * n3, hipMemcpyHostToDevice), "upload");
+      if (sl.prec == 32) hip_check(launch_round_table<float>(sl.e64, (float*)sl.E, (int64_t)(24 * n3), c->stream), "round");
+      else hip_check(launch_round_table<double>(sl.e64, (double*)sl.E, (int64_t)(24 * n3), c->stream), "round");
+    } else {
+      throw Err(PIC_E_ARG, "bad field kind for 3D");
+    }
     c->sync();
     return PIC_OK;
   }
@@ -824,7 +857,8 @@ int pic_field_read(pic_ctx c, int slot, double* out) {
   PIC_GUARD_BEGIN
   Slot& sl = get_slot(c, slot);
   const bool cic = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR;
-  const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1 : (size_t)sl.nleaves * (cic ? 2 : 8);
+  const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1
+                   : sl.d.dim == 3 ? (size_t)sl.nleaves * 24 : (size_t)sl.nleaves * (cic ? 2 : 8);
   std::vector<char> tmp(sl.esz * n);
   c->sync();
   hip_check(hipMemcpy(tmp.data(), cic ? sl.cellE : sl.E, sl.esz * n, hipMemcpyDeviceToHost), "read");
@@ -859,11 +893,11 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out) {
     double qw0[2] = {0.0, 0.0};
     for (int sp = 0; sp < sl.d.nspecies; ++sp) qw0[sp] = sl.d.species[sp].charge * sl.d.species[sp].w0;
     double* r = (double*)sl.alloc(8 * (size_t)sl.nq);
-    const bool two = sl.d.dim == 2;
-    const bool cloud = !two || sl.d.field_scheme == PIC_FIELD_CIC_AMR;   // shares carry F more bits
+    const bool tree = sl.d.dim >= 2;
+    const bool cloud = !tree || sl.d.field_scheme == PIC_FIELD_CIC_AMR;   // shares carry F more bits
     hip_check(launch_rho(latest, sl.nq, sl.d.nspecies, qw0[0], qw0[1], cloud ? 16 + F : 16,
-                         two ? 0.0 : sl.d.length / sl.d.ncells, two ? sl.lv : nullptr, sl.d.length, sl.d.depth_z, r,
-                         c->stream),
+                         tree ? 0.0 : sl.d.length / sl.d.ncells, tree ? sl.lv : nullptr, sl.d.length, sl.d.depth_z,
+                         sl.d.dim == 3 ? 1 : 0, r, c->stream),
               "rho");
     hip_check(hipMemcpyAsync(rho_out, r, 8 * (size_t)sl.nq, hipMemcpyDeviceToHost, c->stream), "read");
     c->sync();
@@ -911,6 +945,7 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
     if (relres) *relres = 0.0;
     return PIC_OK;
   }
+  if (sl.d.dim == 3) throw Err(PIC_E_ARG, "octree slots take their field at the nodes (no solve)");
   const Mesh2D m = mesh_of(sl);
   const uint32_t n = sl.nleaves;
   if (!sl.stencil_ok) {
@@ -991,6 +1026,7 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
         throw Err(PIC_E_ARG, "batched steps need slots of one dimension and one precision");
       if (s->d.dim == 2 && s->d.field_scheme == PIC_FIELD_CIC_AMR)
         throw Err(PIC_E_ARG, "batched steps take quadtree slots with the corner-field coupling");
+      if (s->d.dim == 3) throw Err(PIC_E_ARG, "octree slots step one by one (no batched launch)");
     }
   for (Slot* s : sel)
     if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
@@ -1208,16 +1244,21 @@ int pic_sort(pic_ctx c, int slot) {
 int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf) {
   PIC_GUARD_BEGIN
   Slot& sl = get_slot(c, slot);
-  if (sl.d.dim != 2) throw Err(PIC_E_ARG, "not a quadtree slot");
-  for (int64_t i = 0; i < 2 * n; ++i)
+  const int dim = sl.d.dim;
+  if (dim < 2) throw Err(PIC_E_ARG, "not a tree slot");
+  for (int64_t i = 0; i < dim * n; ++i)
     if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "point outside [0,1)");
   double* ds = nullptr;
   uint32_t* dl = nullptr;
-  hip_check(hipMalloc(&ds, 16 * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
+  hip_check(hipMalloc(&ds, 8 * dim * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
   hip_check(hipMalloc(&dl, 4 * (size_t)std::max<int64_t>(n, 1)), "hipMalloc");
-  hip_check(hipMemcpy(ds, s, 16 * (size_t)n, hipMemcpyHostToDevice), "upload");
-  hipLaunchKernelGGL(k_locate_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, sl.key, sl.lv,
-                     sl.lut, sl.lut_level, ds, n, dl);
+  hip_check(hipMemcpy(ds, s, 8 * dim * (size_t)n, hipMemcpyHostToDevice), "upload");
+  if (dim == 3)
+    hipLaunchKernelGGL(k_locate_points3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, sl.key, sl.lv,
+                       sl.lut, sl.lut_level, ds, n, dl);
+  else
+    hipLaunchKernelGGL(k_locate_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, sl.key, sl.lv,
+                       sl.lut, sl.lut_level, ds, n, dl);
   hip_check(hipGetLastError(), "locate");
   c->sync();
   hip_check(hipMemcpy(leaf, dl, 4 * (size_t)n, hipMemcpyDeviceToHost), "read");
@@ -1233,7 +1274,7 @@ int pic_gather(pic_ctx c, int slot, int64_t n, const double* s, double* out) {
   const int dim = sl.d.dim;
   if (n < 0 || (n > 0 && (!s || !out))) throw Err(PIC_E_ARG, "bad arguments");
   for (int64_t i = 0; i < n * dim; ++i)
-    if (!(s[i] >= 0.0 && s[i] < 1.0)) throw Err(PIC_E_ARG, "point outside [0,1)");
+    if (!in_unit(s[i], sl.prec)) throw Err(PIC_E_ARG, "point outside [0,1) in the particle precision");
   if (n == 0) return PIC_OK;
   double* ds = (double*)sl.alloc(8 * (size_t)(n * dim));
   double* dout = (double*)sl.alloc(8 * (size_t)(n * dim));

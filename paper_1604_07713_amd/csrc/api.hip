@@ -488,7 +488,7 @@ void Ctx::sync() {
 // slot construction
 // ---------------------------------------------------------------------------
 void validate(const pic_instance_desc& d) {
-  if (d.dim != 1 && d.dim != 2) throw Err(PIC_E_ARG, "dim must be 1 or 2");
+  if (d.dim < 1 || d.dim > 3) throw Err(PIC_E_ARG, "dim must be 1, 2 or 3");
   if (d.precision != PIC_FP32 && d.precision != PIC_FP64) throw Err(PIC_E_ARG, "precision must be 32 or 64");
   if (!(d.length > 0) || !(d.dt > 0)) throw Err(PIC_E_ARG, "length and dt must be positive");
   if (d.nspecies < 1 || d.nspecies > 2) throw Err(PIC_E_ARG, "nspecies must be 1 or 2");
@@ -499,11 +499,16 @@ void validate(const pic_instance_desc& d) {
   if (d.field_scheme != PIC_FIELD_CIC_EM && d.field_scheme != PIC_FIELD_CIC_EC &&
       d.field_scheme != PIC_FIELD_CIC_AMR)
     throw Err(PIC_E_ARG, "unknown field_scheme");
-  if (d.dim == 2 && d.field_scheme == PIC_FIELD_CIC_EC)
+  if (d.dim >= 2 && d.field_scheme == PIC_FIELD_CIC_EC)
     throw Err(PIC_E_ARG, "the energy-conserving coupling is for the uniform 1D mesh");
+  if (d.dim == 3 && (d.min_level < 0 || d.max_level > 10 || d.min_level > d.max_level ||
+                     d.base_level < d.min_level || d.base_level > d.max_level))
+    throw Err(PIC_E_ARG, "3D levels must satisfy 0 <= min <= base <= max <= 10");
+  if (d.dim == 3 && d.field_scheme != PIC_FIELD_CIC_EM)
+    throw Err(PIC_E_ARG, "the octree takes the nodal-E gather with NGP deposit");
   if (d.dim == 1 && d.field_scheme == PIC_FIELD_CIC_AMR)
     throw Err(PIC_E_ARG, "the cloud-in-cell on the tree is for 2D slots");
-  if (d.nleaves < 0 || (d.nleaves > 0 && d.dim != 2)) throw Err(PIC_E_ARG, "an explicit tree is for 2D slots");
+  if (d.nleaves < 0 || (d.nleaves > 0 && d.dim != 2)) throw Err(PIC_E_ARG, "an explicit tree is for quadtree slots");
   for (int s = 0; s < d.nspecies; ++s) {
     const pic_species_desc& sp = d.species[s];
     if (!(sp.mass > 0)) throw Err(PIC_E_ARG, "species mass must be positive");
@@ -576,6 +581,163 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   sl.release(ophi);
 }
 
+// ---------------------------------------------------------------------------
+// octree (3D): host construction in Morton order of 10-bit coordinates
+// ---------------------------------------------------------------------------
+uint32_t morton3_host(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t k = 0;
+  for (int b = 0; b < 10; ++b) {
+    k |= ((x >> b) & 1u) << (3 * b);
+    k |= ((y >> b) & 1u) << (3 * b + 1);
+    k |= ((z >> b) & 1u) << (3 * b + 2);
+  }
+  return k;
+}
+void unmorton3_host(uint32_t k, uint32_t X[3]) {
+  X[0] = X[1] = X[2] = 0;
+  for (int b = 0; b < 10; ++b)
+    for (int a = 0; a < 3; ++a) X[a] |= ((k >> (3 * b + a)) & 1u) << b;
+}
+static size_t host_locate3(const std::vector<HostLeaf>& L, uint32_t X, uint32_t Y, uint32_t Z) {
+  const uint32_t m = morton3_host(X, Y, Z);
+  size_t lo = 0, hi = L.size() - 1;
+  while (lo < hi) {
+    const size_t mid = (lo + hi + 1) / 2;
+    if (L[mid].key <= m) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+static std::vector<HostLeaf> host_refine3(const std::vector<HostLeaf>& L, const std::vector<char>& mark) {
+  std::vector<HostLeaf> out;
+  out.reserve(L.size() + 7 * std::count(mark.begin(), mark.end(), 1));
+  for (size_t i = 0; i < L.size(); ++i) {
+    if (!mark[i]) {
+      out.push_back(L[i]);
+      continue;
+    }
+    uint32_t X[3];
+    unmorton3_host(L[i].key, X);
+    const uint32_t half = 1u << (10 - L[i].lv - 1);
+    for (int c = 0; c < 8; ++c)
+      out.push_back(HostLeaf{morton3_host(X[0] + (c & 1) * half, X[1] + ((c >> 1) & 1) * half,
+                                          X[2] + (c >> 2) * half),
+                             (uint8_t)(L[i].lv + 1)});
+  }
+  return out;
+}
+// 2:1 over faces, edges and corners: probes one unit outside the 6 face
+// centres, 12 edge midpoints and 8 corners of every leaf find each coarser
+// leaf touching it; one two or more levels coarser is refined.
+static int64_t host_balance3(std::vector<HostLeaf>& L) {
+  int64_t nref = 0;
+  for (;;) {
+    std::vector<char> mark(L.size(), 0);
+    bool any = false;
+    for (size_t i = 0; i < L.size(); ++i) {
+      uint32_t X[3];
+      unmorton3_host(L[i].key, X);
+      const int64_t S = (int64_t)1 << (10 - L[i].lv);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!dx && !dy && !dz) continue;
+            const int dd[3] = {dx, dy, dz};
+            int64_t P[3];
+            bool in = true;
+            for (int a = 0; a < 3; ++a) {
+              P[a] = dd[a] < 0 ? (int64_t)X[a] - 1 : dd[a] > 0 ? (int64_t)X[a] + S : (int64_t)X[a] + S / 2;
+              if (P[a] < 0 || P[a] >= 1024) in = false;
+            }
+            if (!in) continue;
+            const size_t j = host_locate3(L, (uint32_t)P[0], (uint32_t)P[1], (uint32_t)P[2]);
+            if ((int)L[j].lv < (int)L[i].lv - 1) {
+              if (!mark[j]) ++nref;
+              mark[j] = 1;
+              any = true;
+            }
+          }
+    }
+    if (!any) return nref;
+    L = host_refine3(L, mark);
+  }
+}
+// base level everywhere, every leaf whose closed box meets the closed ball
+// refined until disk_level, then 2:1 balance (Sec. 3.1 octree)
+std::vector<HostLeaf> host_build_tree3(const pic_instance_desc& d) {
+  std::vector<HostLeaf> L;
+  const int B = d.base_level;
+  const uint32_t n = 1u << B;
+  for (uint32_t iz = 0; iz < n; ++iz)
+    for (uint32_t iy = 0; iy < n; ++iy)
+      for (uint32_t ix = 0; ix < n; ++ix)
+        L.push_back(HostLeaf{morton3_host(ix << (10 - B), iy << (10 - B), iz << (10 - B)), (uint8_t)B});
+  std::sort(L.begin(), L.end(), [](const HostLeaf& a, const HostLeaf& b) { return a.key < b.key; });
+  if (d.refine_disk) {
+    const double c[3] = {d.disk_cx, d.disk_cy, d.disk_cz};
+    for (;;) {
+      std::vector<char> mark(L.size(), 0);
+      bool any = false;
+      for (size_t i = 0; i < L.size(); ++i) {
+        if (L[i].lv >= d.disk_level || L[i].lv >= d.max_level) continue;
+        uint32_t X[3];
+        unmorton3_host(L[i].key, X);
+        const double h = std::ldexp(1.0, -(int)L[i].lv);
+        double r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          const double lo = X[a] / 1024.0, hi = lo + h;
+          const double g = std::max(std::max(lo - c[a], 0.0), c[a] - hi);
+          r2 = r2 + g * g;
+        }
+        if (r2 <= d.disk_r * d.disk_r) {
+          mark[i] = 1;
+          any = true;
+        }
+      }
+      if (!any) break;
+      L = host_refine3(L, mark);
+    }
+  }
+  host_balance3(L);
+  return L;
+}
+
+// Mesh tables of an octree slot: keys, levels, packed corners, lookup table
+// at level min(max_level, 7) (8^7 + 1 entries, 8 MiB), corner field tables.
+void set_mesh3(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
+  const size_t n = L.size();
+  std::vector<uint32_t> keys(n);
+  std::vector<uint8_t> lv(n);
+  int mx = 0;
+  for (size_t i = 0; i < n; ++i) {
+    keys[i] = L[i].key;
+    lv[i] = L[i].lv;
+    mx = std::max(mx, (int)L[i].lv);
+  }
+  sl.key = (uint32_t*)sl.alloc(4 * n);
+  sl.lv = (uint8_t*)sl.alloc(n);
+  hip_check(hipMemcpy(sl.key, keys.data(), 4 * n, hipMemcpyHostToDevice), "upload keys");
+  hip_check(hipMemcpy(sl.lv, lv.data(), n, hipMemcpyHostToDevice), "upload levels");
+  sl.nleaves = (uint32_t)n;
+  sl.nq = sl.nleaves;
+  sl.xy = (uint32_t*)sl.alloc(4 * n);
+  sl.lut_level = std::min(sl.d.max_level, 7);
+  sl.lut_direct = mx <= sl.lut_level;
+  sl.lut = (uint32_t*)sl.alloc(4 * ((size_t(1) << (3 * sl.lut_level)) + 1));
+  hip_check(launch_leaf_xyz(sl.key, sl.nleaves, sl.xy, C.stream), "leaf_xyz");
+  hip_check(launch_build_lut3(sl.key, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut3");
+  sl.E = sl.alloc(sl.esz * 24 * n);
+  sl.e64 = (double*)sl.alloc(8 * 24 * n);
+  sl.cphi = (double*)sl.alloc(8 * 8 * n);
+  sl.grad = (double*)sl.alloc(8 * 24 * n);
+  sl.phi64 = (double*)sl.alloc(8 * n);
+  sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
+  sl.off = (uint32_t*)sl.alloc(4 * (2 * ((size_t)sl.nq + 1) + scan_tmp_words((uint32_t)sl.nq)));
+  sl.scan_tmp = sl.off + 2 * ((size_t)sl.nq + 1);
+  hip_check(hipMemsetAsync(sl.E, 0, sl.esz * 24 * n, C.stream), "memset");
+  hip_check(hipMemsetAsync(sl.e64, 0, 8 * 24 * n, C.stream), "memset");
+  hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+}
+
 void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L) {
   std::vector<uint32_t> keys(L.size());
   std::vector<uint8_t> lv(L.size());
@@ -619,6 +781,8 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
     hip_check(hipMemsetAsync(sl.e64, 0, 8 * (N + 1), C.stream), "memset");
     hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (N + 1), C.stream), "memset");
     hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+  } else if (d.dim == 3) {
+    set_mesh3(C, sl, host_build_tree3(d));
   } else {
     set_mesh2d(C, sl, host_build_tree(d));
   }
@@ -632,7 +796,7 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
 // particle buffers
 // ---------------------------------------------------------------------------
 size_t pbuf_bytes(const Slot& sl, int64_t cap) {
-  return (2 * sl.esz + 3 * sl.esz + 12) * (size_t)cap + 8 * 256;
+  return ((size_t)std::max(sl.d.dim, 2) * sl.esz + 3 * sl.esz + 12) * (size_t)cap + 9 * 256;
 }
 
 // A fresh particle buffer of 'cap' slots (nothing of the slot changes if the
@@ -653,11 +817,12 @@ PBuf new_pbuf(Slot& sl, int64_t cap) {
     return q;
   };
   b.s[0] = carve(e * c);
-  b.s[1] = sl.d.dim == 2 ? carve(e * c) : nullptr;
+  b.s[1] = sl.d.dim >= 2 ? carve(e * c) : nullptr;
+  b.s[2] = sl.d.dim == 3 ? carve(e * c) : nullptr;
   for (int k = 0; k < 3; ++k) b.v[k] = carve(e * c);
   b.w = (uint32_t*)carve(4 * c);
   b.id = (uint32_t*)carve(4 * c);
-  b.cell = sl.d.dim == 2 ? (uint32_t*)carve(4 * c) : nullptr;
+  b.cell = sl.d.dim >= 2 ? (uint32_t*)carve(4 * c) : nullptr;
   return b;
 }
 
@@ -669,7 +834,7 @@ void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
 }
 
 size_t births_bytes(const Slot& sl, int64_t cap) {
-  return (20 + 8 * sl.esz) * (size_t)cap + 4 * (3 * kBirthBins + 1) + 20 * 256;
+  return (20 + (6 + (size_t)std::max(sl.d.dim, 2)) * sl.esz) * (size_t)cap + 4 * (3 * kBirthBins + 1) + 21 * 256;
 }
 
 // Births staging of 'cap' entries.  The new block is allocated before the
@@ -691,7 +856,7 @@ void alloc_births(Ctx& C, Slot& sl, int64_t cap) {
   hip_check(hipMemsetAsync(sl.br_rank, 0, 4 * c, C.stream), "memset");   // the births kernels keep it zero
   sl.br_cell = (uint32_t*)carve(4 * c);
   sl.br_w = (uint32_t*)carve(4 * c);
-  for (int k = 0; k < 2; ++k) sl.br_s[k] = carve(e * c);
+  for (int k = 0; k < 3; ++k) sl.br_s[k] = k < std::max(sl.d.dim, 2) ? carve(e * c) : nullptr;
   for (int k = 0; k < 3; ++k) sl.br_ve[k] = carve(e * c);
   for (int k = 0; k < 3; ++k) sl.br_vi[k] = carve(e * c);
   sl.br_sorted = (uint32_t*)carve(4 * c);
@@ -718,6 +883,7 @@ InstDev<T> make_dev(const Slot& sl) {
     const PBuf& b = sl.pb[s][sl.cur[s]];
     I.s[s][0] = (T*)b.s[0];
     I.s[s][1] = (T*)b.s[1];
+    I.s[s][2] = (T*)b.s[2];
     for (int k = 0; k < 3; ++k) I.v[s][k] = (T*)b.v[k];
     I.w[s] = b.w;
     I.id[s] = b.id;
@@ -742,7 +908,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.br.sorted = sl.br_sorted;
   I.br.cell = sl.br_cell;
   I.br.w = sl.br_w;
-  for (int k = 0; k < 2; ++k) I.br.s[k] = (T*)sl.br_s[k];
+  for (int k = 0; k < 3; ++k) I.br.s[k] = (T*)sl.br_s[k];
   for (int k = 0; k < 3; ++k) {
     I.br.ve[k] = (T*)sl.br_ve[k];
     I.br.vi[k] = (T*)sl.br_vi[k];
@@ -810,10 +976,12 @@ void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count) {
   const size_t e = sl.esz;
   if (count) {
     hip_check(hipMemcpyAsync(nb.s[0], old.s[0], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
-    if (sl.d.dim == 2) {
+    if (sl.d.dim >= 2) {
       hip_check(hipMemcpyAsync(nb.s[1], old.s[1], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
       hip_check(hipMemcpyAsync(nb.cell, old.cell, 4 * count, hipMemcpyDeviceToDevice, C.stream), "grow");
     }
+    if (sl.d.dim == 3)
+      hip_check(hipMemcpyAsync(nb.s[2], old.s[2], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
     for (int k = 0; k < 3; ++k)
       hip_check(hipMemcpyAsync(nb.v[k], old.v[k], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
     hip_check(hipMemcpyAsync(nb.w, old.w, 4 * count, hipMemcpyDeviceToDevice, C.stream), "grow");
@@ -890,7 +1058,7 @@ void sort_species(Ctx& C, Slot& sl, int sp) {
   InstDev<T> I = make_dev<T>(sl);
   const int other = 1 - sl.cur[sp];
   PBuf& d = sl.pb[sp][other];
-  SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
+  SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell, (T*)d.s[2]};
   const uint32_t ncell = sl.d.dim == 1 ? (uint32_t)sl.d.ncells : sl.nleaves;
   hip_check(launch_sort<T>(I, sp, ncell, sl.off, sl.scan_tmp, dst, grid_for(sl.cap[sp]), C.stream), "sort");
   sl.cur[sp] = other;

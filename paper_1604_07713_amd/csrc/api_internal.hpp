@@ -35,7 +35,7 @@ struct HostLeaf {
 
 struct PBuf {
   void* base = nullptr;
-  void* s[2] = {nullptr, nullptr};
+  void* s[3] = {nullptr, nullptr, nullptr};
   void* v[3] = {nullptr, nullptr, nullptr};
   uint32_t* w = nullptr;
   uint32_t* id = nullptr;
@@ -94,7 +94,7 @@ struct Slot {
   double births_rate = 0.0;           // births per step over the previous chunk of steps
   uint64_t rate_births_mark = 0;
   uint32_t rate_step_mark = 0;
-  void* br_s[2] = {nullptr, nullptr};
+  void* br_s[3] = {nullptr, nullptr, nullptr};
   void* br_ve[3] = {nullptr, nullptr, nullptr};
   void* br_vi[3] = {nullptr, nullptr, nullptr};
   uint32_t birth_cap = 0;

@@ -253,4 +253,36 @@ __device__ __forceinline__ uint32_t locate_leaf(const uint32_t* __restrict__ key
   return lo;
 }
 
+// Octree (3D): Morton code of three 10-bit coordinates (x in bits 0, 3, 6,
+// ...), and the leaf holding the point (X, Y, Z) in 10-bit units: the lookup
+// table at level lut_level gives the leaf holding the table cell's low
+// corner; a deeper tree ends in a binary search over the keys of the leaves
+// inside the table cell.
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return spread10(x) | (spread10(y) << 1) | (spread10(z) << 2);
+}
+__device__ __forceinline__ uint32_t locate_leaf3(const uint32_t* __restrict__ key, const uint8_t* __restrict__ lv,
+                                                 const uint32_t* __restrict__ lut, int lut_level, uint32_t X,
+                                                 uint32_t Y, uint32_t Z, bool lut_direct = false) {
+  const int sh = 10 - lut_level;
+  const uint32_t c = morton3(X >> sh, Y >> sh, Z >> sh);
+  uint32_t lo = G(lut)[c];
+  if (lut_direct || (int)G(lv)[lo] <= lut_level) return lo;
+  uint32_t hi = G(lut)[c + 1] - 1u;
+  const uint32_t m = morton3(X, Y, Z);
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (G(key)[mid] <= m) lo = mid; else hi = mid - 1u;
+  }
+  return lo;
+}
+
 }  // namespace pic

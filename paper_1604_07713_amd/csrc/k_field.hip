@@ -168,7 +168,7 @@ hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mod
 // particles, 1D shares carry F more bits), over dx (1D, per unit area) or
 // over h^2 depth_z (2D), species added in order.
 __global__ void k_rho(const unsigned long long* Q, uint32_t nq, int nspecies, double qw0_0, double qw0_1, int shift,
-                      double dx, const uint8_t* lv, double length, double depth_z, double* rho) {
+                      double dx, const uint8_t* lv, double length, double depth_z, int cube, double* rho) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
   double r = 0.0;
@@ -179,16 +179,17 @@ __global__ void k_rho(const unsigned long long* Q, uint32_t nq, int nspecies, do
       r = r + ((units * ldexp(1.0, -shift)) * qw0) / dx;
     } else {
       const double h = length * ldexp(1.0, -(int)lv[i]);
-      r = r + ((units * ldexp(1.0, -shift)) * qw0) / ((h * h) * depth_z);
+      r = r + ((units * ldexp(1.0, -shift)) * qw0) / ((h * h) * (cube ? h : depth_z));
     }
   }
   rho[i] = r;
 }
 
 hipError_t launch_rho(const unsigned long long* Q, uint32_t nq, int nspecies, double qw0_0, double qw0_1, int shift,
-                      double dx, const uint8_t* lv, double length, double depth_z, double* rho, hipStream_t s) {
+                      double dx, const uint8_t* lv, double length, double depth_z, int cube, double* rho,
+                      hipStream_t s) {
   hipLaunchKernelGGL(k_rho, dim3(ceil_div(nq, kBlock)), dim3(kBlock), 0, s, Q, nq, nspecies, qw0_0, qw0_1, shift, dx,
-                     lv, length, depth_z, rho);
+                     lv, length, depth_z, cube, rho);
   return hipGetLastError();
 }
 
@@ -328,6 +329,74 @@ hipError_t launch_corner_field(const Mesh2D& m, const double* corner_phi, double
   hipLaunchKernelGGL(k_corner_grad, dim3(ceil_div(m.nleaves, kBlock)), dim3(kBlock), 0, s, m, corner_phi, grad);
   hipLaunchKernelGGL(k_nodal_e<T>, dim3(ceil_div(4u * m.nleaves, kBlock)), dim3(kBlock), 0, s, m, grad, corner_e64,
                      corner_e);
+  return hipGetLastError();
+}
+
+// ---- octree (3D): nodal E from potentials at each leaf's corners ----
+// Corner c = a + 2b + 4e along x, y, z.  Each leaf's E = -grad of its
+// trilinear potential at each corner; a node's E is the mean over the
+// leaves having it as a corner, taken in octant order (below the node in x
+// first, then y, then z), each octant's leaf found at the finest cell
+// beside the node (Sec. 3: nodal E).  m.xy holds the packed 10-bit corner
+// coordinates.
+__global__ void k_corner_grad3(Mesh2D m, const double* __restrict__ cphi, double* __restrict__ grad) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= m.nleaves) return;
+  const double h = ldexp(m.length, -(int)m.lv[l]);
+  const double* f = cphi + (size_t)l * 8u;
+  double* g = grad + (size_t)l * 24u;
+  for (int c = 0; c < 8; ++c) {
+    const int a = c & 1, b = (c >> 1) & 1, e = c >> 2;
+    g[c * 3 + 0] = (f[0 + 2 * b + 4 * e] - f[1 + 2 * b + 4 * e]) / h;
+    g[c * 3 + 1] = (f[a + 0 + 4 * e] - f[a + 2 + 4 * e]) / h;
+    g[c * 3 + 2] = (f[a + 2 * b + 0] - f[a + 2 * b + 4]) / h;
+  }
+}
+
+template <class T>
+__global__ void k_nodal_e3(Mesh2D m, const double* __restrict__ grad, double* __restrict__ ce64,
+                           T* __restrict__ ce) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 8u * m.nleaves) return;
+  const uint32_t l = t >> 3;
+  const int c = (int)(t & 7u);
+  const uint32_t p = m.xy[l];
+  const uint32_t size = 1u << (10 - (int)m.lv[l]);
+  uint32_t X[3];
+  for (int a = 0; a < 3; ++a) X[a] = ((p >> (10 * a)) & 0x3FFu) + (((c >> a) & 1) ? size : 0u);
+  double sum[3] = {0.0, 0.0, 0.0};
+  int k = 0;
+  for (int q = 0; q < 8; ++q) {
+    bool inside = true;
+    uint32_t P[3];
+    for (int a = 0; a < 3; ++a) {
+      const int up = (q >> a) & 1;
+      if ((up == 0 && X[a] == 0u) || (up == 1 && X[a] >= 1024u)) inside = false;
+      P[a] = up ? X[a] : X[a] - 1u;
+    }
+    if (!inside) continue;
+    const uint32_t leaf = locate_leaf3(m.key, m.lv, m.lut, m.lut_level, P[0], P[1], P[2]);
+    const uint32_t ms = 1u << (10 - (int)m.lv[leaf]);
+    if ((X[0] & (ms - 1u)) || (X[1] & (ms - 1u)) || (X[2] & (ms - 1u))) continue;   // not a corner of it
+    int mc = 0;
+    for (int a = 0; a < 3; ++a)
+      if (!((q >> a) & 1)) mc |= 1 << a;   // the leaf lies below the node along a
+    for (int a = 0; a < 3; ++a) sum[a] = sum[a] + grad[(size_t)leaf * 24u + mc * 3 + a];
+    ++k;
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double e = sum[a] / (double)k;
+    ce64[(size_t)t * 3u + a] = e;
+    ce[(size_t)t * 3u + a] = (T)e;
+  }
+}
+
+template <class T>
+hipError_t launch_corner_field3(const Mesh2D& m, const double* corner_phi, double* grad, double* corner_e64,
+                                T* corner_e, hipStream_t s) {
+  hipLaunchKernelGGL(k_corner_grad3, dim3(ceil_div(m.nleaves, kBlock)), dim3(kBlock), 0, s, m, corner_phi, grad);
+  hipLaunchKernelGGL(k_nodal_e3<T>, dim3(ceil_div(8u * m.nleaves, kBlock)), dim3(kBlock), 0, s, m, grad,
+                     corner_e64, corner_e);
   return hipGetLastError();
 }
 
@@ -759,6 +828,7 @@ hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, doubl
   template hipError_t launch_field1d<T>(const InstDev<T>*, int, int, int, const double*, hipStream_t);          \
   template hipError_t launch_node_e_1d<T>(const InstDev<T>&, const double*, int, hipStream_t);                 \
   template hipError_t launch_corner_field<T>(const Mesh2D&, const double*, double*, double*, T*, hipStream_t);   \
+  template hipError_t launch_corner_field3<T>(const Mesh2D&, const double*, double*, double*, T*, hipStream_t);  \
   template hipError_t launch_round_table<T>(const double*, T*, int64_t, hipStream_t);
 PIC_FIELD_INST(float)
 PIC_FIELD_INST(double)

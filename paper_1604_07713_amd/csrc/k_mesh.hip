@@ -75,13 +75,56 @@ hipError_t launch_build_lut(const uint32_t* key, const uint8_t* lv, uint32_t n, 
   return hipGetLastError();
 }
 
+// ---- octree (3D): corner coordinates and lookup table ----
+__device__ __forceinline__ uint32_t compact10(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
+  return v;
+}
+
+__global__ void k_leaf_xyz(const uint32_t* key, uint32_t n, uint32_t* xyz) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < n) xyz[l] = compact10(key[l]) | (compact10(key[l] >> 1) << 10) | (compact10(key[l] >> 2) << 20);
+}
+
+hipError_t launch_leaf_xyz(const uint32_t* key, uint32_t n, uint32_t* xyz, hipStream_t s) {
+  hipLaunchKernelGGL(k_leaf_xyz, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, key, n, xyz);
+  return hipGetLastError();
+}
+
+// lut[c] = last leaf whose key <= key of level-L cell c's low corner; lut[8^L] = n
+__global__ void k_build_lut3(const uint32_t* key, uint32_t n, uint32_t* lut, int L) {
+  const uint32_t ncell = 1u << (3 * L);
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncell) return;
+  if (c == ncell) {
+    lut[c] = n;
+    return;
+  }
+  const uint32_t k = c << (3 * (10 - L));
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (key[mid] <= k) lo = mid; else hi = mid - 1u;
+  }
+  lut[c] = lo;
+}
+
+hipError_t launch_build_lut3(const uint32_t* key, uint32_t n, uint32_t* lut, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_lut3, dim3(ceil_div((1u << (3 * L)) + 1u, kBlock)), dim3(kBlock), 0, s, key, n, lut, L);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Counting sort of one species by cell (1D: floor(s N); 2D: leaf), dropping
 // holes.  hist/off has ncell + 1 entries.
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint32_t i) {
-  if (I.dim == 2) return G(I.cell[sp])[i];
+  if (I.dim >= 2) return G(I.cell[sp])[i];
   const T g = G(I.s[sp][0])[i] * (T)I.N;
   int ic = (int)floor(g);
   if (ic > I.N - 1) ic = I.N - 1;
@@ -215,10 +258,11 @@ __device__ void sort_scatter_range(const InstDev<T>& I, int sp, uint32_t* off, u
       const uint32_t i = t0 + q * kBlock + threadIdx.x;
       const uint32_t pos = inwin[q] ? gbase[o[q]] + slot[q] : slot[q];
       G(d.s0)[pos] = G(I.s[sp][0])[i];
-      if (I.dim == 2) {
+      if (I.dim >= 2) {
         G(d.s1)[pos] = G(I.s[sp][1])[i];
         G(d.cell)[pos] = G(I.cell[sp])[i];
       }
+      if (I.dim == 3) G(d.s2)[pos] = G(I.s[sp][2])[i];
       G(d.v0)[pos] = G(I.v[sp][0])[i];
       G(d.v1)[pos] = G(I.v[sp][1])[i];
       G(d.v2)[pos] = G(I.v[sp][2])[i];

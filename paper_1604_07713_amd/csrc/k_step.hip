@@ -131,7 +131,7 @@ __device__ __forceinline__ bool collide_cx(const SpeciesK<T>& k, uint32_t r1, Wo
 // Stage a birth: slot from one atomic per wave.
 template <class T>
 __device__ __forceinline__ void stage_birth(const InstDev<T>& I, bool birth, uint32_t pid, uint32_t cell, uint32_t w,
-                                            T s0, T s1, const BirthRec<T>& rec) {
+                                            T s0, T s1, const BirthRec<T>& rec, T s2 = (T)0) {
   const uint64_t bm = __ballot(birth);
   if (bm == 0ull) return;
   const int lane = lane_id();
@@ -149,7 +149,8 @@ __device__ __forceinline__ void stage_birth(const InstDev<T>& I, bool birth, uin
   G(I.br.cell)[slot] = cell;
   G(I.br.w)[slot] = w;
   G(I.br.s[0])[slot] = s0;
-  if (I.dim == 2) G(I.br.s[1])[slot] = s1;
+  if (I.dim >= 2) G(I.br.s[1])[slot] = s1;
+  if (I.dim == 3) G(I.br.s[2])[slot] = s2;
   G(I.br.ve[0])[slot] = rec.ve0;
   G(I.br.ve[1])[slot] = rec.ve1;
   G(I.br.ve[2])[slot] = rec.ve2;
@@ -1171,11 +1172,15 @@ __device__ void birth_write_body(const InstDev<T>& I, uint32_t first, uint32_t n
     const uint32_t w = I.br.w[i];
     I.s[0][0][pe] = I.br.s[0][i];
     I.s[1][0][pi] = I.br.s[0][i];
-    if (I.dim == 2) {
+    if (I.dim >= 2) {
       I.s[0][1][pe] = I.br.s[1][i];
       I.s[1][1][pi] = I.br.s[1][i];
       I.cell[0][pe] = I.br.cell[i];
       I.cell[1][pi] = I.br.cell[i];
+    }
+    if (I.dim == 3) {
+      I.s[0][2][pe] = I.br.s[2][i];
+      I.s[1][2][pi] = I.br.s[2][i];
     }
     for (int c = 0; c < 3; ++c) {
       I.v[0][c][pe] = I.br.ve[c][i];
@@ -1424,6 +1429,153 @@ __global__ __launch_bounds__(kBlock) void k_deposit(InstDev<T> I) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Octree (3D, Sec. 3.1 quad/octree with cubic cells).  The gather is the
+// trilinear interpolation of the leaf's corner E (corner c = a + 2b + 4e
+// along x, y, z), weights ((x factor)(y factor))(z factor), summed over the
+// corners in order; the deposit is NGP to the leaf.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void gather3d(const InstDev<T>& I, uint32_t leaf, T sx, T sy, T sz, T e[3]) {
+  const uint32_t p = G(I.leaf_xy)[leaf];
+  const int L = (int)G(I.leaf_lv)[leaf];
+  const int sh = 10 - L;
+  const T sc = (T)(1u << L);
+  const T f0 = sx * sc - (T)((p & 0x3FFu) >> sh);
+  const T f1 = sy * sc - (T)(((p >> 10) & 0x3FFu) >> sh);
+  const T f2 = sz * sc - (T)(((p >> 20) & 0x3FFu) >> sh);
+  const T* ce = I.E + (size_t)leaf * 24u;
+  e[0] = e[1] = e[2] = (T)0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const T wx = (c & 1) ? f0 : (T)1 - f0;
+    const T wy = ((c >> 1) & 1) ? f1 : (T)1 - f1;
+    const T wz = (c >> 2) ? f2 : (T)1 - f2;
+    const T w = (wx * wy) * wz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e[a] = e[a] + w * G(ce)[c * 3 + a];
+  }
+}
+
+// The particle loop of an octree slot: one particle per lane, in place
+// (gather, push, walls, locate, MCC with births, NGP deposit).  Workgroups
+// take contiguous ranges of a species as k_step does.
+template <class T, bool MCC>
+__global__ __launch_bounds__(kBlock) void k_step3d(InstDev<T> I, int commit) {
+  if (step_blocked<T>(I)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&I.ctr->flags, kFlagNeedRoom);
+    return;
+  }
+  const uint32_t step = I.ctr->step;
+  const uint32_t n0 = I.ctr->count[0];
+  const uint32_t n1 = I.nspecies == 2 ? I.ctr->count[1] : 0u;
+  const uint32_t grid = gridDim.x;
+  uint32_t gs = grid;
+  if (I.nspecies == 2) {
+    gs = (uint32_t)(((uint64_t)grid * n0 + ((uint64_t)n0 + n1) / 2u) / ((uint64_t)n0 + n1 + 1u));
+    if (gs < 1u) gs = 1u;
+    if (gs > grid - 1u) gs = grid - 1u;
+  }
+  const int sp = blockIdx.x >= gs ? 1 : 0;
+  const uint32_t b = sp == 0 ? blockIdx.x : blockIdx.x - gs;
+  const uint32_t nb = sp == 0 ? gs : grid - gs;
+  const uint32_t count = sp == 0 ? n0 : n1;
+  const uint32_t chunk = ((count + nb - 1u) / nb + kBlock - 1u) / kBlock * kBlock;
+  unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
+  zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
+  const uint64_t begin64 = (uint64_t)b * chunk;
+  const uint32_t begin = begin64 < count ? (uint32_t)begin64 : count;
+  const uint32_t end = (uint64_t)begin + chunk < count ? begin + chunk : count;
+  unsigned long long* row = I.part + (size_t)blockIdx.x * kNStat;
+  unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
+  unsigned long long* Qi = Qpar + I.nq;
+  const DepLds Ld = dep_lds();
+  DepCache D{Ld.win, Ld.hkey, Ld.hval, 0u};
+  dep_zero(D);
+  if (threadIdx.x == 0) {
+    const uint32_t c0 = begin < end && G(I.w[sp])[begin] ? G(I.cell[sp])[begin] : 0u;
+    *Ld.wbase = c0 > kWin / 2u ? c0 - kWin / 2u : 0u;
+  }
+  __syncthreads();
+  D.base = *Ld.wbase;
+  const SpeciesK<T> k = I.sk[sp];
+  const bool mcc = MCC && k.mcc != PIC_MCC_NONE;
+  const bool reflect = I.particle_bc == PIC_REFLECT;
+  LStat st = {0, 0, 0, 0, 0, 0, 0};
+  for (uint32_t base = begin; base < end; base += kBlock) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t w = i < end ? G(I.w[sp])[i] : 0u;
+    bool live = w != 0u;
+    T s[3] = {(T)0, (T)0, (T)0}, v[3] = {(T)0, (T)0, (T)0};
+    uint32_t id = 0u, leaf = 0u;
+    bool birth = false;
+    BirthRec<T> rec;
+    if (live) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        s[a] = G(I.s[sp][a])[i];
+        v[a] = G(I.v[sp][a])[i];
+      }
+      id = G(I.id[sp])[i];
+      leaf = G(I.cell[sp])[i];
+      st.alive++;
+      T e[3];
+      gather3d<T>(I, leaf, s[0], s[1], s[2], e);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[a] = v[a] + k.qm_dt * e[a];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) s[a] = s[a] + v[a] * k.dt_L;
+      bool lost = false;
+      const bool okx = wall_rule<T>(reflect, s[0], v[0], lost);
+      const bool oky = okx && wall_rule<T>(reflect, s[1], v[1], lost);
+      const bool okz = oky && wall_rule<T>(reflect, s[2], v[2], lost);
+      if (!okz) {
+        live = false;
+        st.absorbed++;
+        st.lost += lost ? 1u : 0u;
+        G(I.w[sp])[i] = 0u;
+      } else {
+        leaf = locate_leaf3(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, (uint32_t)(s[0] * (T)1024),
+                            (uint32_t)(s[1] * (T)1024), (uint32_t)(s[2] * (T)1024), I.lut_direct != 0);
+        if (mcc) {
+          WordStream ws(I.key0, I.key1, id, step);
+          const uint32_t r0 = ws.next();
+          const uint32_t r1 = ws.next();
+          if ((r0 >> 8) < k.tcand) {
+            const uint32_t kind = collision_kind<T>(k, r1, v[0], v[1], v[2], st);
+            if (kind == kCollElastic) {
+              collide_elastic<T>(k, ws, v[0], v[1], v[2]);
+              st.elastic++;
+            } else if (kind == kCollIonize) {
+              collide_ionize<T>(k, ws, v[0], v[1], v[2], rec);
+              birth = true;
+              st.ionization++;
+            } else if (kind == kCollCx) {
+              st.cx += collide_cx<T>(k, r1, ws, v[0], v[1], v[2], st) ? 1u : 0u;
+            }
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          G(I.s[sp][a])[i] = s[a];
+          G(I.v[sp][a])[i] = v[a];
+        }
+        G(I.cell[sp])[i] = leaf;
+      }
+    }
+    stage_birth<T>(I, birth, id, leaf, w, s[0], s[1], rec, s[2]);
+    if (live) dep_add(D, Qs, leaf, (unsigned long long)w);
+    if (birth) {   // the newborn electron and ion sit on the parent
+      dep_add(D, Qs, leaf, (unsigned long long)w);
+      gadd(Qi + leaf, (unsigned long long)w);
+    }
+  }
+  __syncthreads();
+  dep_flush(D, Qs, I.nq);
+  add_stats_row(row, st, sp);
+  if (commit) last_block_commit(I.ctr, step);
+}
+
 // v <- v - (q dt / 2m) E(x) with the current field table.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
@@ -1440,6 +1592,10 @@ __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
         // the step loop's gather: the cell's E (energy-conserving) or linear between nodes
         const T E = I.cell_e ? G(I.E)[ic] : G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]);
         G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * E;
+      } else if (I.dim == 3) {
+        T e[3];
+        gather3d<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], G(I.s[sp][2])[i], e);
+        for (int a = 0; a < 3; ++a) G(I.v[sp][a])[i] = G(I.v[sp][a])[i] - h * e[a];
       } else {
         T ex, ey;
         if (I.cic_amr) gather_cic<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], ex, ey);
@@ -1457,6 +1613,12 @@ __global__ __launch_bounds__(kBlock) void k_relocate(InstDev<T> I, int sp) {
   const uint32_t count = I.ctr->count[sp];
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
     if (!G(I.w[sp])[i]) continue;
+    if (I.dim == 3) {
+      G(I.cell[sp])[i] = locate_leaf3(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, (uint32_t)(G(I.s[sp][0])[i] * (T)1024),
+                                      (uint32_t)(G(I.s[sp][1])[i] * (T)1024), (uint32_t)(G(I.s[sp][2])[i] * (T)1024),
+                                      I.lut_direct != 0);
+      continue;
+    }
     const uint32_t X = (uint32_t)(G(I.s[sp][0])[i] * (T)65536);
     const uint32_t Y = (uint32_t)(G(I.s[sp][1])[i] * (T)65536);
     G(I.cell[sp])[i] = locate2d<T>(I, X, Y);
@@ -1759,6 +1921,15 @@ __global__ void k_gather_points(InstDev<T> I, const double* s, int64_t n, double
     out[j] = (double)(I.cell_e ? G(I.E)[ic] : G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]));
     return;
   }
+  if (I.dim == 3) {
+    const T p[3] = {(T)s[3 * j], (T)s[3 * j + 1], (T)s[3 * j + 2]};
+    const uint32_t leaf = locate_leaf3(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, (uint32_t)(p[0] * (T)1024),
+                                       (uint32_t)(p[1] * (T)1024), (uint32_t)(p[2] * (T)1024), I.lut_direct != 0);
+    T e[3];
+    gather3d<T>(I, leaf, p[0], p[1], p[2], e);
+    for (int a = 0; a < 3; ++a) out[3 * j + a] = (double)e[a];
+    return;
+  }
   const T sx = (T)s[2 * j], sy = (T)s[2 * j + 1];
   const uint32_t leaf = locate_leaf(I.leaf_key, I.leaf_lv, I.lut, I.lut_level, (uint32_t)(sx * (T)65536),
                                     (uint32_t)(sy * (T)65536), I.lut_direct != 0);
@@ -1774,7 +1945,10 @@ template <class T>
 hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit) {
   if (I.nspecies == 2 && grid < 2) return hipErrorInvalidValue;   // the species split needs two workgroups
   const dim3 g(grid), b(kBlock);
-  if (I.cic_amr) {
+  if (I.dim == 3) {
+    if (mcc) hipLaunchKernelGGL((k_step3d<T, true>), g, b, 0, s, I, commit);
+    else hipLaunchKernelGGL((k_step3d<T, false>), g, b, 0, s, I, commit);
+  } else if (I.cic_amr) {
     if (mcc) hipLaunchKernelGGL((k_step2d_cic<T, true>), g, b, 0, s, I, commit);
     else hipLaunchKernelGGL((k_step2d_cic<T, false>), g, b, 0, s, I, commit);
   } else if (I.dim == 1) {
@@ -1794,13 +1968,14 @@ hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, i
 // driven from several threads may fill the cache at once: same value).
 template <class T>
 int step_resident_grid(int dim, bool mcc, bool direct) {
-  static std::atomic<int> cache[2][2][2] = {};
-  std::atomic<int>& slot = cache[dim == 2 ? 1 : 0][mcc ? 1 : 0][direct ? 1 : 0];
+  static std::atomic<int> cache[3][2][2] = {};
+  std::atomic<int>& slot = cache[dim - 1][mcc ? 1 : 0][direct ? 1 : 0];
   int c = slot.load(std::memory_order_relaxed);
   if (c == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     const void* fn;
-    if (dim == 1) fn = mcc ? (const void*)k_step<T, true, 1, false> : (const void*)k_step<T, false, 1, false>;
+    if (dim == 3) fn = mcc ? (const void*)k_step3d<T, true> : (const void*)k_step3d<T, false>;
+    else if (dim == 1) fn = mcc ? (const void*)k_step<T, true, 1, false> : (const void*)k_step<T, false, 1, false>;
     else if (direct) fn = mcc ? (const void*)k_step<T, true, 2, true> : (const void*)k_step<T, false, 2, true>;
     else fn = mcc ? (const void*)k_step<T, true, 2, false> : (const void*)k_step<T, false, 2, false>;
     if (hipGetDevice(&dev) != hipSuccess ||

@@ -53,7 +53,7 @@ struct Births {          // staging of one step's ionization births (SoA)
   uint32_t* sorted;      // staged parent ids grouped by bin
   uint32_t* cell;
   uint32_t* w;
-  T* s[2];
+  T* s[3];
   T* ve[3];
   T* vi[3];
 };
@@ -64,15 +64,15 @@ struct InstDev {
   int dim, N, particle_bc, nspecies;
   uint32_t key0, key1;           // Philox key
   SpeciesK<T> sk[2];
-  T* s[2][2];                    // [species][axis]
+  T* s[2][3];                    // [species][axis] (axis 2: 3D only)
   T* v[2][3];
   uint32_t* w[2];
   uint32_t* id[2];
   uint32_t* cell[2];
   uint32_t cap[2];
-  const T* E;                    // 1D node E [N+1]; 2D corner E [nleaves][4][2]
+  const T* E;                    // 1D node E [N+1]; 2D corner E [nleaves][4][2]; 3D corner E [nleaves][8][3]
   const uint32_t* leaf_key;
-  const uint32_t* leaf_xy;       // (x0 << 16) | y0 in 16-bit units
+  const uint32_t* leaf_xy;       // 2D: (x0 << 16) | y0 in 16-bit units; 3D: x0 | y0 << 10 | z0 << 20 in 10-bit units
   const uint8_t* leaf_lv;
   const uint32_t* lut;           // leaf containing each level-lut_level cell's low corner
   int lut_level;
@@ -169,8 +169,11 @@ template <class T> hipError_t launch_field1d(const InstDev<T>* insts, int ninst,
 template <class T> hipError_t launch_node_e_1d(const InstDev<T>& I, const double* data, int is_phi, hipStream_t s);
 // charge density per node (1D, lv = NULL) or leaf (2D) from Q[species][nq];
 // shift = 16 (+ F in 1D)
+// charge density per cell: 1D (lv null) over dx; 2D over h^2 depth_z; 3D
+// (cube != 0) over h^3
 hipError_t launch_rho(const unsigned long long* Q, uint32_t nq, int nspecies, double qw0_0, double qw0_1, int shift,
-                      double dx, const uint8_t* lv, double length, double depth_z, double* rho, hipStream_t s);
+                      double dx, const uint8_t* lv, double length, double depth_z, int cube, double* rho,
+                      hipStream_t s);
 struct Mesh2D {
   const uint32_t* key;
   const uint32_t* xy;
@@ -184,6 +187,10 @@ struct Mesh2D {
 };
 template <class T> hipError_t launch_corner_field(const Mesh2D& m, const double* corner_phi, double* grad,
                                                   double* corner_e64, T* corner_e, hipStream_t s);
+// octree (the mesh view carries the packed 10-bit corners in xy): corner
+// potentials [leaf][8] -> gradients [leaf][8][3] -> nodal E [leaf][8][3]
+template <class T> hipError_t launch_corner_field3(const Mesh2D& m, const double* corner_phi, double* grad,
+                                                   double* corner_e64, T* corner_e, hipStream_t s);
 hipError_t launch_cell_to_corner_phi(const Mesh2D& m, const double* cell_phi, double* corner_phi, hipStream_t s);
 template <class T> hipError_t launch_round_table(const double* src, T* dst, int64_t n, hipStream_t s);
 struct Stencil2D {
@@ -224,6 +231,10 @@ hipError_t launch_remap_cells(const uint32_t* nxy, const uint8_t* nlv, uint32_t 
                               const uint8_t* olv, const uint32_t* olut, int olut_level, const double* src, double* dst,
                               hipStream_t s);
 hipError_t launch_leaf_xy(const uint32_t* key, const uint8_t* lv, uint32_t nleaves, uint32_t* xy, hipStream_t s);
+// octree: packed 10-bit corner coordinates of each leaf, and the lookup
+// table at level L (8^L + 1 entries)
+hipError_t launch_leaf_xyz(const uint32_t* key, uint32_t nleaves, uint32_t* xyz, hipStream_t s);
+hipError_t launch_build_lut3(const uint32_t* key, uint32_t nleaves, uint32_t* lut, int lut_level, hipStream_t s);
 __host__ __device__ inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 }  // namespace pic

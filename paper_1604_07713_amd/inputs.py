@@ -41,6 +41,17 @@ def species(charge, mass, w0=1.0, mcc=MCC_NONE, sigma_el=0.0, sigma_iz=0.0, eps_
                 sigma_cx=float(sigma_cx), eps_max=float(eps_max))
 
 
+# The largest position below 1 that stays below 1 in FP32 (a double in
+# [1 - 2^-25, 1) rounds to 1.0 in FP32, outside the domain): normalised
+# positions are drawn in [0, 1) and capped here, so the same inputs are
+# valid at either particle precision.
+S_MAX = 1.0 - 2.0 ** -24
+
+
+def unit_positions(rng, shape):
+    return np.minimum(rng.random(shape), S_MAX)
+
+
 def base_desc(**kw):
     d = dict(dim=1, precision=64, length=1.0, dt=1e-12, ncells=0, min_level=0, max_level=0,
              base_level=0, refine_disk=0, disk_cx=0.5, disk_cy=0.5, disk_cz=0.5, disk_r=0.0, disk_level=0,
@@ -86,7 +97,7 @@ def ccp_particles(desc, rng_seed=None):
     rng = np.random.Generator(np.random.PCG64(desc["seed"] if rng_seed is None else rng_seed))
     out = []
     for k, (t_ev, sp) in enumerate(((ex["te_ev"], desc["species"][0]), (ex["ti_ev"], desc["species"][1]))):
-        s = rng.random(n)
+        s = unit_positions(rng, n)
         v = maxwellian(rng, n, t_ev, sp["mass"])
         w = np.full(n, 65536, dtype=np.uint32)
         ids = np.arange(k * n, (k + 1) * n, dtype=np.uint32)
@@ -132,7 +143,7 @@ def quadtree_static_desc(precision=32, seed=2):
 
 def quadtree_particles(n, seed=2, t_ev=1.0):
     rng = np.random.Generator(np.random.PCG64(seed))
-    s = rng.random((n, 2))
+    s = unit_positions(rng, (n, 2))
     v = maxwellian(rng, n, t_ev, M_ELECTRON)
     return s, v, np.full(n, 65536, dtype=np.uint32), np.arange(n, dtype=np.uint32)
 
@@ -172,7 +183,7 @@ def octree_static_desc(precision=32, seed=7, base=4, top=7, r=0.15):
 
 def octree_particles(n, seed=7, t_ev=1.0):
     rng = np.random.Generator(np.random.PCG64(seed))
-    s = rng.random((n, 3))
+    s = unit_positions(rng, (n, 3))
     v = maxwellian(rng, n, t_ev, M_ELECTRON)
     return s, v, np.full(n, 65536, dtype=np.uint32), np.arange(n, dtype=np.uint32)
 
@@ -228,7 +239,7 @@ def octree_avalanche_particles(desc, npairs=3000, sigma=0.1):
     pos = np.empty((0, 3))
     while len(pos) < npairs:
         p = rng.normal(0.5, sigma, size=(npairs, 3))
-        p = p[np.all((p >= 0.0) & (p < 1.0), axis=1)]
+        p = p[np.all((p >= 0.0) & (p <= S_MAX), axis=1)]
         pos = np.concatenate([pos, p])[:npairs]
     ve = maxwellian(rng, npairs, 1.0, M_ELECTRON)
     vi = maxwellian(rng, npairs, K_BOLTZMANN * 300.0 / E_CHARGE, desc["species"][1]["mass"])
@@ -263,7 +274,7 @@ def streamer_particles(desc, npairs=10000, sigma=5e-4, rng_seed=None):
     pos = np.empty((0, 2))
     while len(pos) < npairs:
         p = rng.normal(0.5, sigma / L, size=(npairs, 2))
-        p = p[np.all((p >= 0.0) & (p < 1.0), axis=1)]
+        p = p[np.all((p >= 0.0) & (p <= S_MAX), axis=1)]
         pos = np.concatenate([pos, p])[:npairs]
     ve = maxwellian(rng, npairs, 1.0, M_ELECTRON)
     vi = maxwellian(rng, npairs, K_BOLTZMANN * 300.0 / E_CHARGE, desc["species"][1]["mass"])

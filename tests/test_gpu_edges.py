@@ -84,3 +84,32 @@ def test_ccp_all_particles_leave_then_empty_steps():
     assert not np.any(q)
     assert o.next_id == g.next_id(0)
     assert np.array_equal(o.field_table(), g.field_table(0))
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_positions_rounding_to_one_in_fp32_are_refused(dim):
+    """A double in [1 - 2^-25, 1) is inside the domain but rounds to 1.0 in
+    FP32, outside it: an FP32 slot refuses it at load (as the oracle does), an
+    FP64 slot takes it; the point gather refuses it the same way."""
+    near = 1.0 - 2.0 ** -26
+    for prec, ok in ((32, False), (64, True)):
+        if dim == 1:
+            d = I.ccp_desc(ncells=16, ppc=4, precision=prec)
+        elif dim == 2:
+            d = I.quadtree_static_desc(precision=prec)
+        else:
+            d = I.octree_static_desc(precision=prec)
+        g = B.Context(d)
+        s = np.full((4, dim), 0.5)
+        s[2, dim - 1] = near
+        if ok:
+            g.load(0, 0, s, np.zeros((4, 3)))
+            assert g.count(0, 0) == 4
+        else:
+            with pytest.raises(B.PicError) as e:
+                g.load(0, 0, s, np.zeros((4, 3)))
+            assert e.value.code == B.PIC_E_ARG
+            with pytest.raises(B.PicError) as e:
+                g.gather(0, s)
+            assert e.value.code == B.PIC_E_ARG
+        g.close()

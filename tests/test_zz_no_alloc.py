@@ -56,7 +56,7 @@ def test_noalloc_refuses_tables_beyond_the_workspace():
     rng = np.random.Generator(np.random.PCG64(9))
     n = 20_000_000          # work items of 256 particles: 2 x 78125 items, over the workspace
     for sp in range(2):
-        g.load(0, sp, rng.random((n, 1)), np.zeros((n, 3)), None, np.arange(sp * n, (sp + 1) * n, dtype=np.uint32))
+        g.load(0, sp, I.unit_positions(rng, (n, 1)), np.zeros((n, 3)), None, np.arange(sp * n, (sp + 1) * n, dtype=np.uint32))
     g.deposit(0)
     g.field_solve_1d(0, 0.0)
     with pytest.raises(B.PicError) as e:
