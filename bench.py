@@ -13,8 +13,9 @@ Beside it (same line, own keys): the same quadtree at 16,777,216 electrons
 (state beyond the Infinity Cache), the batched-vs-plain comparisons the
 metric names -- 96 uneven 1D discharges and 32 uneven 2D avalanches on
 dynamic quadtrees, each stepped by one persistent launch per step over all
-instances and by per-instance launches (FP32 and FP64) -- and the 2D
-avalanche breakdown run.
+instances and by per-instance launches (FP32 and FP64) -- the 2D
+avalanche breakdown run, and the 3D octree counterpart of the quadtree
+workload (4,194,304 electrons, 46,488 leaves).
 
 Prints ONE JSON line (metric/value/unit/... plus "roofline" for the
 dominant kernel and "cpu_baseline" for the oracle on a bounded sample).
@@ -46,6 +47,9 @@ BYTES_PER_COLLISION_1D = 16
 #  2D FP32 with MCC (avalanche): read s (8), v (12), leaf, id, w (12); write
 #  s, v, leaf (24) -> 56 B.
 BYTES_PER_UPDATE_2D_MCC = 56
+#  3D FP32 without collisions: read sx, sy, sz, vx, vy, vz, leaf, w (32 B),
+#  write sx, sy, sz, vx, vy, vz, leaf (28 B) -> 60 B.
+BYTES_PER_UPDATE_3D = 60
 METRIC = "particle-updates/s (locate+gather+push+MCC+deposit), 2D AMR; batched vs plain"
 PROFILE_PMC = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
@@ -453,6 +457,40 @@ def quadtree_bench(n, steps, warmup, sort_every, timing_every):
     return dict(updates=updates, seconds=dt, kernel_ms=kern_ms, leaves=int(len(keys)))
 
 
+def octree_bench(n, steps, warmup, sort_every, timing_every):
+    """The static octree workload (unit cube, level 4 refined to level 7
+    inside a centred ball of radius 0.15: 46,488 leaves) with n electrons,
+    timed like the quadtree workload."""
+    import torch
+    from paper_1604_07713_amd import binding as B
+    from paper_1604_07713_amd import inputs as I
+    d = I.octree_static_desc()
+    g = B.Context(d)
+    s, v, w, ids = I.octree_particles(n)
+    g.load(0, 0, s, v, w, ids)
+    keys, lv = g.leaves(0)
+    x, y, z = I.leaf_corners3(keys, lv)
+    g.field_set(0, B.CORNER_PHI_3D, I.octree_phi(x, y, z))
+    g.leapfrog_start(0)
+    if warmup:
+        g.step(0, warmup, sort_every=sort_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.step(warmup, steps, sort_every=sort_every, timing=timing_every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    updates = st["alive_start"][0]
+    kern_ms = st["loop_ms"] / max(st["loop_launches"], 1)
+    out = dict(particles=n, leaves=int(len(keys)), steps=steps, updates_per_s=updates / dt,
+               ms_per_step=dt * 1e3 / steps, kernel_ms_per_step=kern_ms,
+               workload=(f"3D static octree (levels 4-7, {len(keys)} leaves), {n} electrons, trilinear gather + "
+                         f"push + reflect + locate + NGP deposit, sort every {sort_every} steps"))
+    out["roofline"] = roofline((updates / steps) * BYTES_PER_UPDATE_3D, kern_ms)
+    out["roofline"]["per"] = "k_step3d<float,false> launch, 60 B per particle-update"
+    return out
+
+
 TIMING_EVERY = 10   # steps between timed launches of the dominant kernel
 SORT_EVERY = 50     # re-sort the quadtree particles by leaf every this many steps
 
@@ -475,6 +513,8 @@ def main():
     ap.add_argument("--only-ensemble", action="store_true", help="measure only the ensemble (profiling)")
     ap.add_argument("--only-quadtree", action="store_true", help="measure only the quadtree workload (profiling)")
     ap.add_argument("--no-avalanche", action="store_true", help="skip the batched-vs-plain 2D avalanche ensemble")
+    ap.add_argument("--no-octree", action="store_true", help="skip the 3D octree workload")
+    ap.add_argument("--only-octree", action="store_true", help="measure only the 3D octree workload (profiling)")
     ap.add_argument("--only-avalanche", action="store_true", help="measure only the 2D avalanche ensemble")
     ap.add_argument("--avalanche-steps", type=int, default=200)
     ap.add_argument("--avalanche-modes", default="batched,plain_fp32,plain")
@@ -490,7 +530,7 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU (sharding across GPUs is designed, not built); --gpus must be 1"}))
         sys.exit(2)
     profiling = (args.only_ensemble or args.only_streamer or args.only_quadtree or args.only_avalanche
-                 or args.copy_probe)
+                 or args.only_octree or args.copy_probe)
     # the oracle's host timing runs first, before this process touches the GPU
     # (its ensemble sample forks worker processes)
     cpu = None
@@ -520,6 +560,10 @@ def main():
         return
     if args.only_streamer:
         print(json.dumps({"streamer": streamer_bench(args.streamer_steps)}), flush=True)
+        return
+    if args.only_octree:
+        print(json.dumps({"octree": octree_bench(args.particles, args.steps, args.warmup, min(SORT_EVERY, args.steps),
+                                                 TIMING_EVERY)}), flush=True)
         return
     if args.only_avalanche:
         print(json.dumps({"avalanche_ensemble": avalanche_bench(args.avalanche_steps, shape=shape,
@@ -575,6 +619,9 @@ def main():
             roofline=dict(roofline((ql["updates"] / 50) * BYTES_PER_UPDATE_2D, ql["kernel_ms"],
                                    traffic_from_profile("k_step<float,false,2,true>", f"quadtree {n} electrons")),
                           per="k_step<float,false,2,true> launch, 44 B per particle-update"))
+    if not args.no_octree:
+        out["octree"] = octree_bench(args.particles, args.steps, args.warmup, sort_every, TIMING_EVERY)
+        note("octree")
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(args.ensemble_steps, shape=shape, sort_every=args.ensemble_sort_every)
         note("ensemble")
