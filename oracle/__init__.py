@@ -104,6 +104,7 @@ def load_lib(path):
     L.or_corner_phi.argtypes = [P, P]
     L.or_set_next_id.argtypes = [P, C.c_uint32]
     L.or_gather.argtypes = [P, C.c_int64, P, P]
+    L.or_dipic_field.argtypes = [P, C.c_double, P, P]
     return L
 
 
@@ -271,6 +272,13 @@ class Oracle:
         _check(self.L.or_field_solve_1d(self.h, float(phi_left), _ptr(phi), _ptr(e)), "or_field_solve_1d")
         return phi, e
 
+    def dipic_field(self, phi_left):
+        n = self.nq()
+        phi = np.zeros(n)
+        chi = np.zeros(n)
+        _check(self.L.or_dipic_field(self.h, float(phi_left), _ptr(phi), _ptr(chi)), "or_dipic_field")
+        return phi, chi
+
     def field_solve_2d(self, phi_init=None, rtol=1e-12, maxit=10000):
         n = self.nq()
         out = np.zeros(n)
@@ -320,4 +328,4 @@ class Oracle:
 # field kinds
 NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D, CELL_E_2D = 0, 1, 2, 3, 4, 5, 6
 CORNER_PHI_3D, CORNER_E_3D = 7, 8
-FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR = 0, 1, 2
+FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR, FIELD_DIPIC = 0, 1, 2, 3

@@ -289,6 +289,7 @@ struct SimBase {
 template <class T> struct Particle {
   T s[3];
   T v[3];
+  T b;            /* direct implicit: (dt/2) times the filtered acceleration, m/s */
   uint32_t w;
   uint32_t id;
   int64_t cell;   /* located leaf (2D) */
@@ -650,6 +651,7 @@ template <class T> struct Sim : SimBase {
       for (int c = 0; c < 3; ++c) q.v[c] = (T)v[i * 3 + c];
       q.w = w ? w[i] : 65536u;
       q.id = id ? id[i] : (uint32_t)i;
+      q.b = (T)0;
       for (int c = 0; c < d.dim; ++c)
         if (!(q.s[c] >= (T)0 && q.s[c] < (T)1)) return OR_E_ARG;
       q.alive = true;
@@ -978,6 +980,11 @@ template <class T> struct Sim : SimBase {
         if (d.species[sp].mcc != OR_MCC_NONE) mcc(sp, q, n, births, st);
       }
     }
+    return finish_step(births, st);
+  }
+
+  /* births appended, the absorbed removed, the deposit of the step */
+  int finish_step(std::vector<Birth>& births, or_stats* st) {
     /* births: sorted by parent id; rank r -> electron next_id+2r, ion +2r+1 */
     std::sort(births.begin(), births.end(), [](const Birth& a, const Birth& b) { return a.parent < b.parent; });
     if (!births.empty()) {
@@ -992,6 +999,7 @@ template <class T> struct Sim : SimBase {
         e.s[2] = i.s[2] = b.s[2];
         e.cell = i.cell = b.cell;
         e.w = i.w = b.w;
+        e.b = i.b = (T)0;
         e.alive = i.alive = true;
         for (int c = 0; c < 3; ++c) { e.v[c] = b.ve[c]; i.v[c] = b.vi[c]; }
         e.id = next_id + 2u * (uint32_t)r;
@@ -1008,6 +1016,109 @@ template <class T> struct Sim : SimBase {
                   p[sp].end());
     deposit();
     return OR_OK;
+  }
+
+  /* ---------------- 1D direct implicit step (Sec. 3: DIPIC) ----------------
+     The D1 scheme of direct implicit PIC, with the particle velocity v at
+     half steps and b = (dt/2) abar, abar the filtered acceleration:
+       predictor   v~ = v + b,   x~ = x + dt v~                (walls apply)
+       field       -d/dx[(1 + chi) dphi/dx] = rho~ / eps0 at t_{n+1}, rho~
+                   and chi from the charge at the predicted positions,
+                   chi = sum_s (q_s / m_s) (dt^2 / 2) rho~_s / eps0
+       corrector   a = (q/m) E_{n+1}(x~),  v = v~ + (dt/2) a,
+                   x = x~ + dt (dt/2) a,   b = (b + (dt/2) a) / 2  (walls apply)
+     then collisions and births (a newborn has b = 0) and the deposit.
+     Readings: chi at the nodes from the CIC charge sums of each species
+     over the node's cell (a wall node's half cell: twice its sum over dx,
+     the density there; over a whole cell the wall face of a uniform
+     plasma would see a quarter less susceptibility than the interior, and
+     at large w_p dt the sheets beside the walls grow); the face
+     coefficient 1 + (chi_i + chi_{i+1}) / 2; the variable-coefficient
+     system solved by the Thomas algorithm in FP64 (forward elimination
+     from node 1, back substitution from node N-1). */
+  double chi_coef(int sp) const {
+    const or_species& s = d.species[sp];
+    const double dx = d.length / N;
+    return (((s.charge / s.mass) * ((d.dt * d.dt) * 0.5)) * (((s.charge * s.w0) * std::ldexp(1.0, -(16 + F))) / dx)) /
+           EPS0;
+  }
+
+  void solve1d_implicit(double phi_left, double* phi_out = nullptr, double* chi_out = nullptr) {
+    std::vector<double> chi(N + 1, 0.0), f(N), ph(N + 1, 0.0);
+    for (int i = 0; i <= N; ++i) {
+      double c = 0.0;
+      for (int sp = 0; sp < d.nspecies; ++sp) c = c + chi_coef(sp) * (double)(int64_t)Q[sp][i];
+      chi[i] = (i == 0 || i == N) ? 2.0 * c : c;   /* a wall node's charge fills half a cell */
+    }
+    for (int i = 0; i < N; ++i) f[i] = 1.0 + (chi[i] + chi[i + 1]) * 0.5;   /* face i + 1/2 */
+    /* interior nodes 1 .. N-1: -f[i-1] ph[i-1] + (f[i-1] + f[i]) ph[i] - f[i] ph[i+1] = rhs[i] */
+    std::vector<double> cp(N, 0.0), dp(N, 0.0);
+    for (int i = 1; i < N; ++i) {
+      double r = 0.0;
+      for (int sp = 0; sp < d.nspecies; ++sp) r = r + (double)(int64_t)Q[sp][i] * kappa(sp);
+      if (i == 1) r = r + f[0] * phi_left;
+      const double a = -f[i - 1], bb = f[i - 1] + f[i], c = -f[i];
+      if (i == 1) {
+        cp[i] = c / bb;
+        dp[i] = r / bb;
+      } else {
+        const double m = bb - a * cp[i - 1];
+        cp[i] = c / m;
+        dp[i] = (r - a * dp[i - 1]) / m;
+      }
+    }
+    ph[0] = phi_left;
+    ph[N] = 0.0;
+    ph[N - 1] = dp[N - 1];
+    for (int i = N - 2; i >= 1; --i) ph[i] = dp[i] - cp[i] * ph[i + 1];
+    const double inv2dx = 1.0 / (2.0 * (d.length / N));
+    std::vector<double> e(N + 1);
+    node_or_cell_e(ph.data(), inv2dx, e.data());
+    for (int i = 0; i <= N; ++i) {
+      En[i] = (T)e[i];
+      if (phi_out) phi_out[i] = ph[i];
+      if (chi_out) chi_out[i] = chi[i];
+    }
+  }
+
+  int step_dipic(uint32_t n, double phi_left, or_stats* st) {
+    std::vector<Birth> births;
+    for (int sp = 0; sp < d.nspecies; ++sp) {
+      const SpeciesK<T>& k = K[sp];
+      for (Particle<T>& q : p[sp]) {
+        if (!q.alive) continue;
+        st->alive_start[sp]++;
+        q.v[0] = q.v[0] + q.b;
+        q.s[0] = q.s[0] + q.v[0] * k.dt_LT;
+        bool lost_r = false;
+        if (!wall(q.s[0], q.v[0], lost_r)) {
+          q.alive = false;
+          st->absorbed[sp]++;
+          if (lost_r) st->lost_reflect++;
+        }
+      }
+    }
+    deposit();                    /* charge at the predicted positions */
+    solve1d_implicit(phi_left);   /* E at t_{n+1} */
+    for (int sp = 0; sp < d.nspecies; ++sp) {
+      const SpeciesK<T>& k = K[sp];
+      for (Particle<T>& q : p[sp]) {
+        if (!q.alive) continue;
+        const T dv = k.hqm_dtT * gather1d(q.s[0]);
+        q.v[0] = q.v[0] + dv;
+        q.s[0] = q.s[0] + dv * k.dt_LT;
+        q.b = (q.b + dv) * (T)0.5;
+        bool lost_r = false;
+        if (!wall(q.s[0], q.v[0], lost_r)) {
+          q.alive = false;
+          st->absorbed[sp]++;
+          if (lost_r) st->lost_reflect++;
+          continue;
+        }
+        if (d.species[sp].mcc != OR_MCC_NONE) mcc(sp, q, n, births, st);
+      }
+    }
+    return finish_step(births, st);
   }
 
   /* ---------------- 1D Poisson (Thomas) ---------------- */
@@ -1481,6 +1592,7 @@ template <class T> struct Sim : SimBase {
         if (d.dim == 1) {
           T E = gather1d(q.s[0]);
           q.v[0] = q.v[0] - k.hqm_dtT * E;
+          q.b = d.field_scheme == OR_FIELD_DIPIC ? k.hqm_dtT * E : (T)0;   /* filtered acceleration a(x_0) */
         } else if (d.dim == 3) {
           T E[3];
           gather3d(q, E);
@@ -1514,9 +1626,10 @@ void* or_create(const or_desc* d) {
   if (!d || d->dim < 1 || d->dim > 3 || (d->precision != 32 && d->precision != 64) ||
       d->nspecies < 1 || d->nspecies > 2 || !(d->length > 0) || !(d->dt > 0) ||
       (d->field_scheme != OR_FIELD_CIC_EM && d->field_scheme != OR_FIELD_CIC_EC &&
-       d->field_scheme != OR_FIELD_CIC_AMR) ||
+       d->field_scheme != OR_FIELD_CIC_AMR && d->field_scheme != OR_FIELD_DIPIC) ||
       (d->dim >= 2 && d->field_scheme == OR_FIELD_CIC_EC) ||    /* energy-conserving: uniform 1D mesh */
-      (d->dim == 1 && d->field_scheme == OR_FIELD_CIC_AMR))     /* cloud on the tree: 2D */
+      (d->dim == 1 && d->field_scheme == OR_FIELD_CIC_AMR) ||   /* cloud on the tree: 2D */
+      (d->dim != 1 && d->field_scheme == OR_FIELD_DIPIC))       /* direct implicit: 1D */
     return nullptr;
   SimBase* b;
   bool ok;
@@ -1728,6 +1841,15 @@ int or_field_solve_1d(void* h, double phi_left, double* phi_out, double* e_out) 
   });
 }
 
+int or_dipic_field(void* h, double phi_left, double* phi_out, double* chi_out) {
+  return dispatch(h, [&](auto& S) {
+    if (S.d.dim != 1 || S.d.field_scheme != OR_FIELD_DIPIC) return (int)OR_E_ARG;
+    S.deposit();
+    S.solve1d_implicit(phi_left, phi_out, chi_out);
+    return (int)OR_OK;
+  });
+}
+
 int or_field_solve_2d(void* h, const double* phi_init, double rtol, int maxit, double* phi_out, int* iters,
                       double* relres) {
   return dispatch(h, [&](auto& S) {
@@ -1762,7 +1884,13 @@ int or_leapfrog_start(void* h) {
 int or_step(void* h, int64_t step0, int nsteps, const double* v_next, int solve_1d, or_stats* st) {
   std::memset(st, 0, sizeof(*st));
   return dispatch(h, [&](auto& S) {
+    if (S.d.field_scheme == OR_FIELD_DIPIC && !solve_1d) return (int)OR_E_ARG;   /* the field is part of the step */
     for (int k = 0; k < nsteps; ++k) {
+      if (S.d.field_scheme == OR_FIELD_DIPIC) {
+        int rc = S.step_dipic((uint32_t)(step0 + k), v_next[k], st);
+        if (rc != OR_OK) return rc;
+        continue;
+      }
       int rc = S.step((uint32_t)(step0 + k), st);
       if (rc != OR_OK) return rc;
       if (solve_1d && S.d.dim == 1) S.solve1d(v_next[k], nullptr, nullptr);

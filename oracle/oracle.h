@@ -40,7 +40,11 @@ enum { OR_ABSORB = 0, OR_REFLECT = 1 };
    Sec. 3) or the cloud-in-cell on the quadtree with ghost cells at +-1 level
    and the same shape function for scatter and gather (OR_FIELD_CIC_AMR,
    Sec. 3.1) */
-enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1, OR_FIELD_CIC_AMR = 2 };
+enum { OR_FIELD_CIC_EM = 0, OR_FIELD_CIC_EC = 1, OR_FIELD_CIC_AMR = 2,
+       /* 1D direct implicit PIC (Sec. 3: DIPIC, the Poisson solve extended
+          with the implicit susceptibility), D1 time integration; CIC to the
+          nodes with the linear gather; steps only with the field solve */
+       OR_FIELD_DIPIC = 3 };
 /* field kinds for or_field_set.  OR_NODE_E_1D is for the momentum-conserving
    1D coupling (N+1 node values), OR_CELL_E_1D for the energy-conserving one
    (N cell values); each is refused on the other coupling. */
@@ -127,6 +131,11 @@ int or_set_next_id(void* h, uint32_t next_id);
 int or_field_set(void* h, int kind, const double* data);
 int or_field_table(void* h, double* out);
 int or_field_solve_1d(void* h, double phi_left, double* phi_out, double* e_out);
+/* direct implicit slots (test hook): deposit the particles as they are and
+   solve the implicit Poisson equation with phi(0) = phi_left, phi(L) = 0;
+   phi_out[N+1] the node potentials, chi_out[N+1] the node susceptibility;
+   the E table is set from them */
+int or_dipic_field(void* h, double phi_left, double* phi_out, double* chi_out);
 int or_field_solve_2d(void* h, const double* phi_init, double rtol, int maxit,
                       double* phi_out, int* iters, double* relres);
 int64_t or_assemble_2d(void* h, int32_t* rows, int32_t* cols, double* vals, double* rhs);

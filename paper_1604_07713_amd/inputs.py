@@ -31,6 +31,7 @@ MCC_NONE, MCC_ELECTRON, MCC_ION_CX = 0, 1, 2
 WALL_NEUMANN, WALL_DIRICHLET = 0, 1
 ABSORB, REFLECT = 0, 1
 FIELD_CIC_EM, FIELD_CIC_EC = 0, 1   # 1D particle-field coupling (momentum- or energy-conserving CIC)
+FIELD_DIPIC = 3                     # 1D: direct implicit PIC (D1 scheme, susceptibility in the Poisson solve)
 FIELD_CIC_AMR = 2                   # 2D: cloud-in-cell on the quadtree (ghost cells at +-1 level)
 
 

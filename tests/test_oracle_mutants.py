@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_cic_amr as C
+from tests import test_oracle_dipic as DI
 from tests import test_oracle_octree as O3
 from tests import test_oracle_tree_pins as P
 
@@ -73,6 +74,22 @@ MUTANTS = {
         "if (n->level >= d.disk_level || n->level >= d.max_level) continue;\n          double r2",
         "if (n->level + 1 >= d.disk_level || n->level >= d.max_level) continue;\n          double r2",
         O3.check_mesh),
+    "implicit susceptibility without the half": (
+        "return (((s.charge / s.mass) * ((d.dt * d.dt) * 0.5))",
+        "return (((s.charge / s.mass) * ((d.dt * d.dt) * 1.0))",
+        lambda L: DI.check_cold_plasma(L, wdts=(4.0,))),
+    "filtered acceleration not averaged": (
+        "q.b = (q.b + dv) * (T)0.5;",
+        "q.b = dv;",
+        lambda L: DI.check_cold_plasma(L, wdts=(1.5,))),
+    "implicit Thomas elimination with the wrong sign": (
+        "dp[i] = (r - a * dp[i - 1]) / m;",
+        "dp[i] = (r + a * dp[i - 1]) / m;",
+        DI.check_implicit_solve),
+    "wall susceptibility over a whole cell": (
+        "chi[i] = (i == 0 || i == N) ? 2.0 * c : c;",
+        "chi[i] = c;",
+        DI.check_implicit_solve),
     "octree nodal E divides by eight always": (
         "const double e = sum[a] / (double)k;",
         "const double e = sum[a] / 8.0;",
