@@ -94,6 +94,24 @@ enum { PIC_FIELD_CIC_EM = 0, PIC_FIELD_CIC_EC = 1 };
  * and for the gather of the cell-centred E (the mean of each leaf's nodal E,
  * or PIC_CELL_E_2D). */
 enum { PIC_FIELD_CIC_AMR = 2 };
+/* 1D only: the direct implicit step (Sec. 3, the D1 scheme; the Poisson
+ * solve carries the implicit susceptibility).  Each particle keeps b =
+ * (dt/2) abar, abar its time-filtered acceleration (set by
+ * pic_leapfrog_start to (dt/2) a(x_0), zero at load and at birth).  A step:
+ *   predictor  v~ = v + b, x~ = x + dt v~ (wall rule);
+ *   field      -d/dx[(1 + chi) dphi/dx] = rho~/eps0 with phi(0) = the next
+ *              drive value, phi(L) = 0; rho~ and chi = sum_s (q_s/m_s)
+ *              (dt^2/2) rho~_s/eps0 from the CIC charge of the predicted
+ *              positions (a wall node's charge over its half cell), face
+ *              coefficients 1 + (chi_i + chi_i+1)/2, solved by forward
+ *              elimination and back substitution in FP64; node E as for
+ *              PIC_FIELD_CIC_EM;
+ *   corrector  dv = (q dt / 2m) E_n+1(x~): v = v~ + dv, x = x~ + dt dv,
+ *              b = (b + dv)/2 (wall rule), then collisions, births and
+ *              the deposit.
+ * Such a slot steps only with solve_field set (the field is part of the
+ * step) and not in batched or no-allocation calls. */
+enum { PIC_FIELD_DIPIC = 3 };
 enum { PIC_FP32 = 32, PIC_FP64 = 64 };
 /* field kinds for pic_field_set (Sec. 3: potential at cell centres or nodes,
  * E at the nodes for the gather) */

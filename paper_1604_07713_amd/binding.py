@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 _LIB = None
 
 PIC_OK, PIC_E_ARG, PIC_E_NOMEM, PIC_E_CAPACITY, PIC_E_HIP, PIC_E_STATE, PIC_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
-FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR = 0, 1, 2   # particle-field couplings (include/pic.h)
+FIELD_CIC_EM, FIELD_CIC_EC, FIELD_CIC_AMR, FIELD_DIPIC = 0, 1, 2, 3   # particle-field couplings (include/pic.h)
 ABI_VERSION = 4                     # PIC_ABI_VERSION of include/pic.h
 NODE_E_1D, NODE_PHI_1D, CORNER_PHI_2D, CORNER_E_2D, CELL_PHI_2D, CELL_E_1D, CELL_E_2D = 0, 1, 2, 3, 4, 5, 6
 CORNER_PHI_3D, CORNER_E_3D = 7, 8

@@ -182,6 +182,16 @@ bool slot_has_mcc(const Slot& sl) {
 template <class T>
 void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e1) {
   InstDev<T> I = make_dev<T>(sl);
+  if (I.dipic) {   // predictor, implicit field, corrector; then births and the commit
+    if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
+    hip_check(launch_dipic_predict<T>(I, C.stream, g), "dipic predict");
+    hip_check(launch_dipic_field<T>(I, C.stream), "dipic field");
+    hip_check(launch_dipic_correct<T>(I, C.stream, g, slot_has_mcc(sl)), "dipic correct");
+    if (sl.ionizing) hip_check(launch_births<T>(I, C.stream, I.births_binned != 0), "births");
+    if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
+    hip_check(launch_commit<T>(I, C.stream), "commit");
+    return;
+  }
   const bool field = sl.d.dim == 1 && solve;
   const int commit = (!sl.ionizing && !field) ? 1 : 0;
   if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
@@ -413,7 +423,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
         PBuf& d = sl.pb[sp][1 - sl.cur[sp]];
         J.off = sl.off + (size_t)sp * (N + 1);
         J.dst = SortDst<T>{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell,
-                           (T*)d.s[2]};
+                           (T*)d.s[2], (T*)d.acc};
         max_ncell = std::max(max_ncell, N);
       }
     }
@@ -661,6 +671,7 @@ int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double
     }
     hip_check(hipMemcpy(b.w, ww.data(), 4 * n, hipMemcpyHostToDevice), "load");
     hip_check(hipMemcpy(b.id, ii.data(), 4 * n, hipMemcpyHostToDevice), "load");
+    if (b.acc) hip_check(hipMemset(b.acc, 0, e * n), "load");   // no filtered acceleration before the start
     sl.max_id_loaded[species] = mx + 1u;
   } else {
     sl.max_id_loaded[species] = 0;
@@ -1027,7 +1038,11 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
       if (s->d.dim == 2 && s->d.field_scheme == PIC_FIELD_CIC_AMR)
         throw Err(PIC_E_ARG, "batched steps take quadtree slots with the corner-field coupling");
       if (s->d.dim == 3) throw Err(PIC_E_ARG, "octree slots step one by one (no batched launch)");
+      if (s->d.field_scheme == PIC_FIELD_DIPIC) throw Err(PIC_E_ARG, "direct implicit slots step one by one");
     }
+  for (Slot* s : sel)
+    if (s->d.field_scheme == PIC_FIELD_DIPIC && !a->solve_field)
+      throw Err(PIC_E_ARG, "a direct implicit step solves the field (set solve_field and v_next)");
   for (Slot* s : sel)
     if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
   bool any_ionizing = false;

@@ -196,6 +196,9 @@ void derive(Slot& sl) {
     if (d.dim == 1) {
       const double dx = d.length / d.ncells;
       sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -(16 + F))) * dx) / kEPS0;
+      // direct implicit: (q/m)(dt^2/2) rho_s / eps0 per unit charge sum (rho over a cell)
+      sl.chi[s] = (((sp.charge / sp.mass) * ((d.dt * d.dt) * 0.5)) * (((sp.charge * sp.w0) * std::ldexp(1.0, -(16 + F))) / dx)) /
+                  kEPS0;
     } else {
       const int f2 = d.field_scheme == PIC_FIELD_CIC_AMR ? F : 0;   // cloud shares carry F more bits
       sl.kappa[s] = (((sp.charge * sp.w0) * std::ldexp(1.0, -(16 + f2))) / d.depth_z) / kEPS0;
@@ -497,7 +500,7 @@ void validate(const pic_instance_desc& d) {
                      d.base_level > d.max_level))
     throw Err(PIC_E_ARG, "2D levels must satisfy 0 <= min <= base <= max <= 14");
   if (d.field_scheme != PIC_FIELD_CIC_EM && d.field_scheme != PIC_FIELD_CIC_EC &&
-      d.field_scheme != PIC_FIELD_CIC_AMR)
+      d.field_scheme != PIC_FIELD_CIC_AMR && d.field_scheme != PIC_FIELD_DIPIC)
     throw Err(PIC_E_ARG, "unknown field_scheme");
   if (d.dim >= 2 && d.field_scheme == PIC_FIELD_CIC_EC)
     throw Err(PIC_E_ARG, "the energy-conserving coupling is for the uniform 1D mesh");
@@ -508,6 +511,8 @@ void validate(const pic_instance_desc& d) {
     throw Err(PIC_E_ARG, "the octree takes the nodal-E gather with NGP deposit");
   if (d.dim == 1 && d.field_scheme == PIC_FIELD_CIC_AMR)
     throw Err(PIC_E_ARG, "the cloud-in-cell on the tree is for 2D slots");
+  if (d.dim != 1 && d.field_scheme == PIC_FIELD_DIPIC)
+    throw Err(PIC_E_ARG, "the direct implicit step is for the uniform 1D mesh");
   if (d.nleaves < 0 || (d.nleaves > 0 && d.dim != 2)) throw Err(PIC_E_ARG, "an explicit tree is for quadtree slots");
   for (int s = 0; s < d.nspecies; ++s) {
     const pic_species_desc& sp = d.species[s];
@@ -781,6 +786,11 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
     hip_check(hipMemsetAsync(sl.e64, 0, 8 * (N + 1), C.stream), "memset");
     hip_check(hipMemsetAsync(sl.phi64, 0, 8 * (N + 1), C.stream), "memset");
     hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
+    if (d.field_scheme == PIC_FIELD_DIPIC) {
+      sl.Qp = (unsigned long long*)sl.alloc(8 * 2 * (size_t)sl.nq);
+      sl.dws = (double*)sl.alloc(8 * 4 * (size_t)sl.nq);
+      hip_check(hipMemsetAsync(sl.Qp, 0, 16 * (size_t)sl.nq, C.stream), "memset");
+    }
   } else if (d.dim == 3) {
     set_mesh3(C, sl, host_build_tree3(d));
   } else {
@@ -796,7 +806,8 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
 // particle buffers
 // ---------------------------------------------------------------------------
 size_t pbuf_bytes(const Slot& sl, int64_t cap) {
-  return ((size_t)std::max(sl.d.dim, 2) * sl.esz + 3 * sl.esz + 12) * (size_t)cap + 9 * 256;
+  const size_t acc = sl.d.field_scheme == PIC_FIELD_DIPIC ? sl.esz : 0;
+  return ((size_t)std::max(sl.d.dim, 2) * sl.esz + 3 * sl.esz + acc + 12) * (size_t)cap + 10 * 256;
 }
 
 // A fresh particle buffer of 'cap' slots (nothing of the slot changes if the
@@ -823,6 +834,7 @@ PBuf new_pbuf(Slot& sl, int64_t cap) {
   b.w = (uint32_t*)carve(4 * c);
   b.id = (uint32_t*)carve(4 * c);
   b.cell = sl.d.dim >= 2 ? (uint32_t*)carve(4 * c) : nullptr;
+  b.acc = sl.d.field_scheme == PIC_FIELD_DIPIC ? carve(e * c) : nullptr;
   return b;
 }
 
@@ -884,6 +896,7 @@ InstDev<T> make_dev(const Slot& sl) {
     I.s[s][0] = (T*)b.s[0];
     I.s[s][1] = (T*)b.s[1];
     I.s[s][2] = (T*)b.s[2];
+    I.acc[s] = (T*)b.acc;
     for (int k = 0; k < 3; ++k) I.v[s][k] = (T*)b.v[k];
     I.w[s] = b.w;
     I.id[s] = b.id;
@@ -924,6 +937,11 @@ InstDev<T> make_dev(const Slot& sl) {
   I.inv2dx = sl.inv2dx;
   I.cell_e = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_CIC_EC ? 1 : 0;
   I.cic_amr = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR ? 1 : 0;
+  I.dipic = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_DIPIC ? 1 : 0;
+  I.chi[0] = sl.chi[0];
+  I.chi[1] = sl.chi[1];
+  I.Qp = sl.Qp;
+  I.dws = sl.dws;
   I.cellE = (const T*)sl.cellE;
   I.births_binned = slot_births_binned(sl) ? 1 : 0;
   I.phi64 = sl.phi64;
@@ -982,6 +1000,7 @@ void grow(Ctx& C, Slot& sl, int sp, int64_t newcap, uint32_t count) {
     }
     if (sl.d.dim == 3)
       hip_check(hipMemcpyAsync(nb.s[2], old.s[2], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
+    if (old.acc) hip_check(hipMemcpyAsync(nb.acc, old.acc, e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
     for (int k = 0; k < 3; ++k)
       hip_check(hipMemcpyAsync(nb.v[k], old.v[k], e * count, hipMemcpyDeviceToDevice, C.stream), "grow");
     hip_check(hipMemcpyAsync(nb.w, old.w, 4 * count, hipMemcpyDeviceToDevice, C.stream), "grow");
@@ -1058,7 +1077,8 @@ void sort_species(Ctx& C, Slot& sl, int sp) {
   InstDev<T> I = make_dev<T>(sl);
   const int other = 1 - sl.cur[sp];
   PBuf& d = sl.pb[sp][other];
-  SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell, (T*)d.s[2]};
+  SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell, (T*)d.s[2],
+                 (T*)d.acc};
   const uint32_t ncell = sl.d.dim == 1 ? (uint32_t)sl.d.ncells : sl.nleaves;
   hip_check(launch_sort<T>(I, sp, ncell, sl.off, sl.scan_tmp, dst, grid_for(sl.cap[sp]), C.stream), "sort");
   sl.cur[sp] = other;

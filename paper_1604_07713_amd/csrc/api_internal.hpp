@@ -40,6 +40,7 @@ struct PBuf {
   uint32_t* w = nullptr;
   uint32_t* id = nullptr;
   uint32_t* cell = nullptr;
+  void* acc = nullptr;   // direct implicit: (dt/2) x the filtered acceleration per particle
 };
 
 // Device memory cache of a context.  Blocks of up to kMaxBlock bytes are
@@ -80,6 +81,9 @@ struct Slot {
   HostK hk[2];
   double kappa[2] = {0, 0};
   double inv2dx = 0;
+  double chi[2] = {0, 0};                  // direct implicit: charge sum -> susceptibility per species
+  unsigned long long* Qp = nullptr;        // direct implicit: charge at the predicted positions [2][N+1]
+  double* dws = nullptr;                   // direct implicit solve scratch [4][N+1]
   // particles: [species][buffer]; cur = live buffer, the other is the sort target
   PBuf pb[2][2];
   int cur[2] = {0, 0};

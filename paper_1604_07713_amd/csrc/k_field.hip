@@ -162,6 +162,122 @@ hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mod
   return hipGetLastError();
 }
 
+// Direct implicit field (Sec. 3, D1 scheme): one workgroup.  The charge of
+// the predicted positions (Qp) gives the susceptibility at the nodes, chi_i
+// = sum_s chi_s Qp_s,i (a wall node's charge fills half a cell: twice
+// that), and the right-hand side c_i = sum_s kappa_s Qp_s,i; the node system
+//   -f_i-1 phi_i-1 + (f_i-1 + f_i) phi_i - f_i phi_i+1 = c_i  (i = 1..N-1),
+//   f_i = 1 + (chi_i + chi_i+1)/2,  phi_0 = V (the next drive value), phi_N = 0,
+// is solved by forward elimination and back substitution.  The recurrences
+// are sequential (one lane, FP64 divisions), their operands staged through
+// LDS a chunk at a time by the whole workgroup; node E as in the explicit
+// solve.  Qp is cleared for the next step.  Scratch dws [4][N+1]: chi then
+// the elimination's c' (chi is dead by then), f, the right-hand side then
+// phi, and the elimination's d'.
+constexpr int kDipicThreads = 1024;
+constexpr int kDipicChunk = 2048;
+
+template <class T>
+__global__ __launch_bounds__(kDipicThreads) void k_dipic_field(InstDev<T> I) {
+  __shared__ double sa[kDipicChunk + 1], sb[kDipicChunk];
+  if (I.ctr->flags & kFlagNeedRoom) return;   // the predictor did not run this step
+  const int N = I.N;
+  const uint32_t nq = I.nq;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t kk = I.ctr->step + 1u - I.ctr->vstep0;
+  const double left = (I.v_table && kk < I.v_len) ? I.v_table[kk] : 0.0;
+  double* chi = I.dws;
+  double* cp = I.dws;
+  double* f = I.dws + nq;
+  double* rhs = I.dws + 2u * nq;
+  double* ph = I.dws + 2u * nq;
+  double* dp = I.dws + 3u * nq;
+  unsigned long long* Qp = I.Qp;
+  const int ns = I.nspecies;
+  for (int i = tid; i <= N; i += nt) {
+    double c = 0.0;
+    for (int sp = 0; sp < ns; ++sp) c = c + I.chi[sp] * (double)(long long)Qp[(size_t)sp * nq + i];
+    chi[i] = (i == 0 || i == N) ? 2.0 * c : c;
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += nt) f[i] = 1.0 + (chi[i] + chi[i + 1]) * 0.5;
+  for (int i = 1 + tid; i < N; i += nt) {
+    double r = 0.0;
+    for (int sp = 0; sp < ns; ++sp) r = r + (double)(long long)Qp[(size_t)sp * nq + i] * I.kappa[sp];
+    if (i == 1) r = r + (1.0 + (chi[0] + chi[1]) * 0.5) * left;
+    rhs[i] = r;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < (uint32_t)ns * nq; j += nt) Qp[j] = 0ull;
+  // forward elimination over nodes [c0, c0 + n): f[c0-1 .. c0+n-1] and the
+  // right-hand sides go to LDS; lane 0 carries c', d' of the previous node
+  double cprev = 0.0, dprev = 0.0;
+  for (int c0 = 1; c0 < N; c0 += kDipicChunk) {
+    const int n = N - c0 < kDipicChunk ? N - c0 : kDipicChunk;
+    for (int t = tid; t <= n; t += nt) sa[t] = f[c0 - 1 + t];
+    for (int t = tid; t < n; t += nt) sb[t] = rhs[c0 + t];
+    __syncthreads();
+    if (tid == 0) {
+      for (int t = 0; t < n; ++t) {
+        const double a = -sa[t], bb = sa[t] + sa[t + 1], c = -sa[t + 1];
+        double cpi, dpi;
+        if (c0 + t == 1) {
+          cpi = c / bb;
+          dpi = sb[t] / bb;
+        } else {
+          const double m = bb - a * cprev;
+          cpi = c / m;
+          dpi = (sb[t] - a * dprev) / m;
+        }
+        cp[c0 + t] = cpi;
+        dp[c0 + t] = dpi;
+        cprev = cpi;
+        dprev = dpi;
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution over nodes [lo, hi), from the top
+  double next = 0.0;
+  for (int hi = N; hi > 1; hi -= kDipicChunk) {
+    const int lo = hi - kDipicChunk > 1 ? hi - kDipicChunk : 1;
+    for (int t = tid; t < hi - lo; t += nt) {
+      sa[t] = cp[lo + t];
+      sb[t] = dp[lo + t];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = hi - 1; i >= lo; --i) {
+        next = i == N - 1 ? sb[i - lo] : sb[i - lo] - sa[i - lo] * next;
+        ph[i] = next;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ph[0] = left;
+    ph[N] = 0.0;
+  }
+  __syncthreads();
+  T* E = const_cast<T*>(I.E);
+  const double h2 = I.inv2dx;
+  for (int i = tid; i <= N; i += nt) {
+    double e;
+    if (i == 0) e = ((3.0 * ph[0] - 4.0 * ph[1]) + ph[2]) * h2;
+    else if (i == N) e = ((-3.0 * ph[N] + 4.0 * ph[N - 1]) - ph[N - 2]) * h2;
+    else e = (ph[i - 1] - ph[i + 1]) * h2;
+    E[i] = (T)e;
+    if (I.e64) I.e64[i] = e;
+    if (I.phi64) I.phi64[i] = ph[i];
+  }
+}
+
+template <class T>
+hipError_t launch_dipic_field(const InstDev<T>& I, hipStream_t s) {
+  hipLaunchKernelGGL(k_dipic_field<T>, dim3(1), dim3(kDipicThreads), 0, s, I);
+  return hipGetLastError();
+}
+
 // Charge density of an integer deposit (Sec. 3: charge at the nodes of the
 // uniform mesh or the centres of the leaves; Sec. 3.1: no per-level volume
 // weighting): the sums scaled to coulombs (w_units = 2^16 carries w0 real
@@ -826,6 +942,7 @@ hipError_t launch_cg_iter(const Mesh2D& m, const Stencil2D& st, double* x, doubl
 
 #define PIC_FIELD_INST(T)                                                                                        \
   template hipError_t launch_field1d<T>(const InstDev<T>*, int, int, int, const double*, hipStream_t);          \
+  template hipError_t launch_dipic_field<T>(const InstDev<T>&, hipStream_t);                                   \
   template hipError_t launch_node_e_1d<T>(const InstDev<T>&, const double*, int, hipStream_t);                 \
   template hipError_t launch_corner_field<T>(const Mesh2D&, const double*, double*, double*, T*, hipStream_t);   \
   template hipError_t launch_corner_field3<T>(const Mesh2D&, const double*, double*, double*, T*, hipStream_t);  \

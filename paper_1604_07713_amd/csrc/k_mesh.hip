@@ -263,6 +263,7 @@ __device__ void sort_scatter_range(const InstDev<T>& I, int sp, uint32_t* off, u
         G(d.cell)[pos] = G(I.cell[sp])[i];
       }
       if (I.dim == 3) G(d.s2)[pos] = G(I.s[sp][2])[i];
+      if (I.dipic) G(d.acc)[pos] = G(I.acc[sp])[i];
       G(d.v0)[pos] = G(I.v[sp][0])[i];
       G(d.v1)[pos] = G(I.v[sp][1])[i];
       G(d.v2)[pos] = G(I.v[sp][2])[i];

@@ -8,7 +8,8 @@ template <class T>
 struct SortDst {
   T *s0, *s1, *v0, *v1, *v2;
   uint32_t *w, *id, *cell;
-  T* s2;   // 3D only
+  T* s2;    // 3D only
+  T* acc;   // direct implicit only
 };
 
 // One (slot, species) of a batched sort: its offsets (ncell + 1 words, or

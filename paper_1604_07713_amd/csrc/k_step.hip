@@ -1188,6 +1188,10 @@ __device__ void birth_write_body(const InstDev<T>& I, uint32_t first, uint32_t n
     }
     I.w[0][pe] = w;
     I.w[1][pi] = w;
+    if (I.dipic) {   // a newborn has no filtered acceleration yet
+      I.acc[0][pe] = (T)0;
+      I.acc[1][pi] = (T)0;
+    }
     I.id[0][pe] = nid + 2u * r;
     I.id[1][pi] = nid + 2u * r + 1u;
   }
@@ -1576,6 +1580,202 @@ __global__ __launch_bounds__(kBlock) void k_step3d(InstDev<T> I, int commit) {
   if (commit) last_block_commit(I.ctr, step);
 }
 
+// ---------------------------------------------------------------------------
+// 1D direct implicit step (Sec. 3, the D1 scheme).  acc holds b = (dt/2)
+// abar, abar the time-filtered acceleration.  The predictor moves every
+// particle with v~ = v + b, x~ = x + dt v~ (wall rule) and deposits the CIC
+// charge of x~ into Qp; the field kernel then solves the Poisson equation
+// with the implicit susceptibility of that charge for E_n+1; the corrector
+// adds dv = (q dt / 2m) E_n+1(x~) to v and dt dv to x, sets b = (b + dv)/2,
+// applies the wall rule, the collisions and births, and deposits the step's
+// charge.  One lane per particle; the species split of the workgroups is
+// the explicit step's, so both kernels add their counts to the same
+// partial-stats rows.
+struct BlockRange {
+  int sp;
+  uint32_t begin, end;
+};
+template <class T>
+__device__ __forceinline__ BlockRange dipic_range(const InstDev<T>& I) {
+  const uint32_t n0 = I.ctr->count[0];
+  const uint32_t n1 = I.nspecies == 2 ? I.ctr->count[1] : 0u;
+  const uint32_t grid = gridDim.x;
+  uint32_t gs = grid;
+  if (I.nspecies == 2) {
+    gs = (uint32_t)(((uint64_t)grid * n0 + ((uint64_t)n0 + n1) / 2u) / ((uint64_t)n0 + n1 + 1u));
+    if (gs < 1u) gs = 1u;
+    if (gs > grid - 1u) gs = grid - 1u;
+  }
+  BlockRange r;
+  r.sp = blockIdx.x >= gs ? 1 : 0;
+  const uint32_t b = r.sp == 0 ? blockIdx.x : blockIdx.x - gs;
+  const uint32_t nb = r.sp == 0 ? gs : grid - gs;
+  const uint32_t count = r.sp == 0 ? n0 : n1;
+  const uint32_t chunk = ((count + nb - 1u) / nb + kBlock - 1u) / kBlock * kBlock;
+  const uint64_t begin64 = (uint64_t)b * chunk;
+  r.begin = begin64 < count ? (uint32_t)begin64 : count;
+  r.end = (uint64_t)r.begin + chunk < count ? r.begin + chunk : count;
+  return r;
+}
+
+// CIC shares of a 1D position in 64-bit fixed point: node ic gets w (1 - f),
+// node ic + 1 gets w f.
+template <class T>
+__device__ __forceinline__ void cic1d_shares(int N, T s, uint32_t w, uint32_t& ic_out, unsigned long long& q0,
+                                             unsigned long long& q1) {
+  const T g = s * (T)N;
+  int ic = (int)floor(g);
+  if (ic > N - 1) ic = N - 1;
+  const T fr = g - (T)ic;
+  const unsigned long long one = 1ull << FixedPoint<T>::F;
+  const unsigned long long r = (unsigned long long)(long long)rint(fr * (T)(1ull << FixedPoint<T>::F));
+  ic_out = (uint32_t)ic;
+  q0 = (unsigned long long)w * (one - r);
+  q1 = (unsigned long long)w * r;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dipic_predict(InstDev<T> I) {
+  if (step_blocked<T>(I)) {   // uniform over the launch: no room for this step's births
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&I.ctr->flags, kFlagNeedRoom);
+    return;
+  }
+  const BlockRange R = dipic_range<T>(I);
+  const int sp = R.sp;
+  const T dt_L = I.sk[sp].dt_L;
+  const bool reflect = I.particle_bc == PIC_REFLECT;
+  T* S = I.s[sp][0];
+  T* V = I.v[sp][0];
+  const T* A = I.acc[sp];
+  uint32_t* W = I.w[sp];
+  unsigned long long* Qs = I.Qp + (size_t)sp * I.nq;
+  LStat st = {0, 0, 0, 0, 0, 0, 0};
+  // the trip count is uniform over the workgroup (the atomic adds shuffle
+  // across the wave)
+  for (uint32_t t = R.begin; t < R.end; t += kBlock) {
+    const uint32_t i = t + threadIdx.x;
+    const uint32_t w = i < R.end ? W[i] : 0u;
+    uint32_t key = kNoKey;
+    unsigned long long q0 = 0ull, q1 = 0ull;
+    if (w) {
+      T v = V[i] + A[i];
+      T s = S[i] + v * dt_L;
+      bool lost = false;
+      const bool ok = wall_rule<T>(reflect, s, v, lost);
+      st.alive++;
+      if (!ok) {
+        st.absorbed++;
+        st.lost += lost ? 1u : 0u;
+        W[i] = 0u;
+      } else {
+        S[i] = s;
+        V[i] = v;
+        cic1d_shares<T>(I.N, s, w, key, q0, q1);
+      }
+    }
+    seg_atomic_add(Qs, key, q0);
+    seg_atomic_add(Qs, key == kNoKey ? kNoKey : key + 1u, q1);
+  }
+  add_stats_row(I.part + (size_t)blockIdx.x * kNStat, st, sp);
+}
+
+template <class T, bool MCC>
+__global__ __launch_bounds__(kBlock) void k_dipic_correct(InstDev<T> I) {
+  if (I.ctr->flags & kFlagNeedRoom) return;   // the predictor did not run this step
+  const uint32_t step = I.ctr->step;
+  zero_other_parity(I.Q, I.nq, step, I.nspecies, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
+  const BlockRange R = dipic_range<T>(I);
+  const int sp = R.sp;
+  const SpeciesK<T> k = I.sk[sp];
+  const bool mcc = MCC && k.mcc != PIC_MCC_NONE;          // uniform
+  const bool births = mcc && k.mcc == PIC_MCC_ELECTRON;   // uniform: newborns only from electron impact
+  const bool reflect = I.particle_bc == PIC_REFLECT;
+  const int N = I.N;
+  const T* E = I.E;
+  T* S = I.s[sp][0];
+  T* V0 = I.v[sp][0];
+  T* V1 = I.v[sp][1];
+  T* V2 = I.v[sp][2];
+  T* A = I.acc[sp];
+  uint32_t* W = I.w[sp];
+  const uint32_t* ID = I.id[sp];
+  unsigned long long* Qpar = I.Q + (size_t)(step & 1u) * 2u * I.nq;
+  unsigned long long* Qs = Qpar + (size_t)sp * I.nq;
+  LStat st = {0, 0, 0, 0, 0, 0, 0};
+  for (uint32_t t = R.begin; t < R.end; t += kBlock) {
+    const uint32_t i = t + threadIdx.x;
+    uint32_t w = i < R.end ? W[i] : 0u;
+    bool birth = false;
+    BirthRec<T> rec = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+    uint32_t id = 0u;
+    T s = (T)0;
+    uint32_t key = kNoKey;
+    unsigned long long q0 = 0ull, q1 = 0ull;
+    if (w) {
+      s = S[i];
+      T v = V0[i];
+      // E_n+1 at the predicted position, linear between the cell's nodes
+      const T g = s * (T)N;
+      int ic = (int)floor(g);
+      if (ic > N - 1) ic = N - 1;
+      const T fr = g - (T)ic;
+      const T e0 = E[ic], e1 = E[ic + 1];
+      const T dv = k.hqm_dt * (e0 + fr * (e1 - e0));
+      v = v + dv;
+      s = s + dv * k.dt_L;
+      A[i] = (A[i] + dv) * (T)0.5;
+      bool lost = false;
+      if (!wall_rule<T>(reflect, s, v, lost)) {
+        st.absorbed++;
+        st.lost += lost ? 1u : 0u;
+        W[i] = 0u;
+        w = 0u;
+      } else {
+        if (mcc) {
+          id = ID[i];
+          WordStream ws(I.key0, I.key1, id, step);
+          const uint32_t r0 = ws.next();
+          const uint32_t r1 = ws.next();
+          if ((r0 >> 8) < k.tcand) {
+            T vy = V1[i], vz = V2[i];
+            const uint32_t kind = collision_kind<T>(k, r1, v, vy, vz, st);
+            if (kind == kCollElastic) {
+              st.elastic++;
+              collide_elastic<T>(k, ws, v, vy, vz);
+            } else if (kind == kCollIonize) {
+              st.ionization++;
+              collide_ionize<T>(k, ws, v, vy, vz, rec);
+              birth = true;
+            } else if (kind == kCollCx) {
+              st.cx += collide_cx<T>(k, r1, ws, v, vy, vz, st) ? 1u : 0u;
+            }
+            if (kind != kCollNone) {
+              V1[i] = vy;
+              V2[i] = vz;
+            }
+          }
+        }
+        S[i] = s;
+        V0[i] = v;
+        cic1d_shares<T>(N, s, w, key, q0, q1);
+      }
+    }
+    if (births) stage_birth<T>(I, birth, id, 0u, w, s, (T)0, rec);
+    seg_atomic_add(Qs, key, q0);
+    seg_atomic_add(Qs, key == kNoKey ? kNoKey : key + 1u, q1);
+    // a newborn pair sits on its parent with the parent's weight
+    if (births && __ballot(birth) != 0ull) {
+      const uint32_t kb = birth ? key : kNoKey;
+      const uint32_t kb1 = birth ? key + 1u : kNoKey;
+      seg_atomic_add(Qpar, kb, q0);
+      seg_atomic_add(Qpar, kb1, q1);
+      seg_atomic_add(Qpar + I.nq, kb, q0);
+      seg_atomic_add(Qpar + I.nq, kb1, q1);
+    }
+  }
+  add_stats_row(I.part + (size_t)blockIdx.x * kNStat, st, sp);
+}
+
 // v <- v - (q dt / 2m) E(x) with the current field table.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
@@ -1592,6 +1792,7 @@ __global__ __launch_bounds__(kBlock) void k_leapfrog_start(InstDev<T> I) {
         // the step loop's gather: the cell's E (energy-conserving) or linear between nodes
         const T E = I.cell_e ? G(I.E)[ic] : G(I.E)[ic] + f * (G(I.E)[ic + 1] - G(I.E)[ic]);
         G(I.v[sp][0])[i] = G(I.v[sp][0])[i] - h * E;
+        if (I.dipic) G(I.acc[sp])[i] = h * E;   // b = (dt/2) a(x_0)
       } else if (I.dim == 3) {
         T e[3];
         gather3d<T>(I, G(I.cell[sp])[i], G(I.s[sp][0])[i], G(I.s[sp][1])[i], G(I.s[sp][2])[i], e);
@@ -2080,6 +2281,17 @@ hipError_t launch_leapfrog_start(const InstDev<T>& I, hipStream_t s, int grid) {
   return hipGetLastError();
 }
 template <class T>
+hipError_t launch_dipic_predict(const InstDev<T>& I, hipStream_t s, int grid) {
+  hipLaunchKernelGGL(k_dipic_predict<T>, dim3(grid), dim3(kBlock), 0, s, I);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t launch_dipic_correct(const InstDev<T>& I, hipStream_t s, int grid, bool mcc) {
+  if (mcc) hipLaunchKernelGGL((k_dipic_correct<T, true>), dim3(grid), dim3(kBlock), 0, s, I);
+  else hipLaunchKernelGGL((k_dipic_correct<T, false>), dim3(grid), dim3(kBlock), 0, s, I);
+  return hipGetLastError();
+}
+template <class T>
 hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int grid) {
   hipLaunchKernelGGL(k_relocate<T>, dim3(grid), dim3(kBlock), 0, s, I, species);
   return hipGetLastError();
@@ -2102,7 +2314,9 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
   template hipError_t launch_cell_e<T>(const double*, uint32_t, T*, hipStream_t);                          \
   template hipError_t launch_gather_points<T>(const InstDev<T>&, const double*, int64_t, double*, hipStream_t); \
   template hipError_t launch_leapfrog_start<T>(const InstDev<T>&, hipStream_t, int);                       \
-  template hipError_t launch_relocate<T>(const InstDev<T>&, int, hipStream_t, int);
+  template hipError_t launch_relocate<T>(const InstDev<T>&, int, hipStream_t, int);                        \
+  template hipError_t launch_dipic_predict<T>(const InstDev<T>&, hipStream_t, int);                        \
+  template hipError_t launch_dipic_correct<T>(const InstDev<T>&, hipStream_t, int, bool);
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)
 

@@ -69,6 +69,7 @@ struct InstDev {
   uint32_t* w[2];
   uint32_t* id[2];
   uint32_t* cell[2];
+  T* acc[2];                     // direct implicit: (dt/2) x filtered acceleration (else null)
   uint32_t cap[2];
   const T* E;                    // 1D node E [N+1]; 2D corner E [nleaves][4][2]; 3D corner E [nleaves][8][3]
   const uint32_t* leaf_key;
@@ -90,6 +91,10 @@ struct InstDev {
   // FP64 field data
   double kappa[2];               // charge-sum -> Poisson right-hand side factor per species
   double inv2dx;                 // 1D: 1 / (2 dx)
+  int dipic;                     // 1D direct implicit step (D1 scheme)
+  double chi[2];                 // direct implicit: charge-sum -> susceptibility factor per species
+  unsigned long long* Qp;        // direct implicit: charge at the predicted positions [2][N+1]
+  double* dws;                   // direct implicit solve scratch [4][N+1]
   int cell_e;                    // 1D energy-conserving coupling: E holds cell values, gathered without interpolation
   int cic_amr;                   // 2D cloud-in-cell coupling: deposit and gather through the particle's cloud
   const T* cellE;                // 2D cloud-in-cell: cell-centred E [nleaves][2]
@@ -159,6 +164,11 @@ template <class T> hipError_t launch_gather_points(const InstDev<T>& I, const do
                                                    hipStream_t s);
 template <class T> hipError_t launch_leapfrog_start(const InstDev<T>& I, hipStream_t s, int grid);
 template <class T> hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int grid);
+// 1D direct implicit step: predictor (grid workgroups), field (one
+// workgroup), corrector (grid workgroups); births and commit follow.
+template <class T> hipError_t launch_dipic_predict(const InstDev<T>& I, hipStream_t s, int grid);
+template <class T> hipError_t launch_dipic_field(const InstDev<T>& I, hipStream_t s);
+template <class T> hipError_t launch_dipic_correct(const InstDev<T>& I, hipStream_t s, int grid, bool mcc);
 
 // ---- field (k_field.hip) ----
 // mode 0: solve from the latest deposit with phi(0) = phi_left[inst];

@@ -85,6 +85,17 @@ def ccp_desc(ncells=128, ppc=64, voltage=450.0, pressure_mtorr=30.0, precision=6
     return d
 
 
+def dipic_ccp_desc(precision=64, n0=1e16, steps_per_period=200, **kw):
+    """The 1D discharge at a hundred times the plasma density (n0 = 1e16
+    m^-3) and twice the time step (200 steps per RF period): w_p dt = 2.08,
+    where the explicit leapfrog is unstable, and dx = 4.4 Debye lengths at
+    2.5 eV, beyond the explicit rule of about 3; stepped by the direct
+    implicit scheme."""
+    d = ccp_desc(precision=precision, n0=n0, steps_per_period=steps_per_period, **kw)
+    d["field_scheme"] = FIELD_DIPIC
+    return d
+
+
 def maxwellian(rng, n, t_ev, mass):
     vth = math.sqrt(t_ev * E_CHARGE / mass)
     return rng.standard_normal((n, 3)) * vth

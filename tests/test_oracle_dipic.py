@@ -190,3 +190,29 @@ def test_dipic_needs_the_field_solve():
         o.load(sp, s, v, w, ids)
     with pytest.raises(RuntimeError):
         o.step(0, 1)
+
+
+def run_discharge(d, nsteps):
+    o = oracle.Oracle(d)
+    for sp, (s, v, w, ids) in enumerate(I.ccp_particles(d)):
+        o.load(sp, s, v, w, ids)
+    o.deposit()
+    o.field_solve_1d(float(I.drive_voltage(d, 0)))
+    o.leapfrog_start()
+    return o, o.step(0, nsteps, I.drive_voltage(d, np.arange(1, nsteps + 1)), True)
+
+
+def test_discharge_beyond_the_explicit_limits():
+    """The discharge at w_p dt = 2.08 with dx = 4.4 Debye lengths: the direct
+    implicit step keeps its electrons (within 5% after 200 steps, none beyond
+    the velocity bound of the collision tables), while the explicit step at
+    the same time step loses all of them (leapfrog is unstable beyond w_p dt
+    = 2)."""
+    d = I.dipic_ccp_desc()
+    n = d["extra"]["npart"]
+    o, st = run_discharge(d, 200)
+    assert abs(o.count(0) - n) < 0.05 * n
+    assert st["numax_violations"][0] == 0 and st["births"] > 0
+    e = dict(d, field_scheme=I.FIELD_CIC_EM)
+    o2, st2 = run_discharge(e, 200)
+    assert o2.count(0) == 0 and st2["numax_violations"][0] > 0
