@@ -14,8 +14,9 @@ Beside it (same line, own keys): the same quadtree at 16,777,216 electrons
 metric names -- 96 uneven 1D discharges and 32 uneven 2D avalanches on
 dynamic quadtrees, each stepped by one persistent launch per step over all
 instances and by per-instance launches (FP32 and FP64) -- the 2D
-avalanche breakdown run, and the 3D octree counterpart of the quadtree
-workload (4,194,304 electrons, 46,488 leaves).
+avalanche breakdown run, the 3D octree counterpart of the quadtree
+workload (4,194,304 electrons, 46,488 leaves), and the 1D discharge at
+w_p dt = 2.08 stepped by the direct implicit scheme.
 
 Prints ONE JSON line (metric/value/unit/... plus "roofline" for the
 dominant kernel and "cpu_baseline" for the oracle on a bounded sample).
@@ -219,6 +220,10 @@ def cpu_baseline(nparticles, nsteps, seed=2, extra=True):
     # 1D discharge in full: 16,384 particles, 400 steps, FP64
     u, t = _ccp_oracle_run((I.ccp_desc(precision=64), 400))
     out["ccp_full"] = dict(updates_per_s=u / t, cores=1, sample=f"the whole 1D discharge run, 400 steps, FP64, {t:.2f} s")
+    # the direct implicit discharge in full: 16,384 particles, 400 steps, FP64
+    u, t = _ccp_oracle_run((I.dipic_ccp_desc(precision=64), 400))
+    out["dipic_full"] = dict(updates_per_s=u / t, cores=1,
+                             sample=f"the whole direct implicit 1D discharge, 400 steps, FP64, {t:.2f} s")
     # ensemble: 8 of the 96 instances, one process each, a bounded number of steps
     from concurrent.futures import ProcessPoolExecutor
     descs = I.ensemble_descs(count=96, precision=64)
@@ -491,6 +496,45 @@ def octree_bench(n, steps, warmup, sort_every, timing_every):
     return out
 
 
+def dipic_bench(ppc=64, nsteps=400, precision=64, sort_every=20, timing_every=10):
+    """The 1D discharge at w_p dt = 2.08 (n0 = 1e16 m^-3, 200 steps per RF
+    period, 128 cells, 450 V, 30 mTorr argon with collisions and ionization
+    births), stepped by the direct implicit scheme: predictor, implicit field
+    solve and corrector every step, re-sorted every sort_every steps."""
+    import numpy as np
+    import torch
+    from paper_1604_07713_amd import binding as B
+    from paper_1604_07713_amd import inputs as I
+    d = I.dipic_ccp_desc(precision=precision, ppc=ppc)
+    g = B.Context(d)
+    for sp, (s, v, w, ids) in enumerate(I.ccp_particles(d)):
+        g.load(0, sp, s, v, w, ids)
+    g.deposit(0)
+    g.field_solve_1d(0, float(I.drive_voltage(d, 0)))
+    g.leapfrog_start(0)
+    vn = I.drive_voltage(d, np.arange(1, nsteps + 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.step(0, nsteps, vn, solve_field=True, sort_every=sort_every, timing=timing_every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    updates = st["alive_start"][0] + st["alive_start"][1]
+    return dict(particles_start=2 * d["extra"]["npart"], steps=nsteps, precision=f"fp{precision}",
+                updates_per_s=updates / dt, ms_per_step=dt * 1e3 / nsteps,
+                step_kernels_ms=st["loop_ms"] / max(st["loop_launches"], 1), births=st["births"],
+                workload=(f"1D discharge, direct implicit (w_p dt 2.08, dx 4.4 Debye lengths), 128 cells x {ppc} "
+                          f"per cell per species, {nsteps} steps, sort every {sort_every}"),
+                note="step_kernels_ms: predictor + implicit field + corrector + births of one step (HIP events "
+                     f"around every {timing_every}th step)")
+
+
+def dipic_runs():
+    """The discharge as the tests run it (FP64, 16,384 particles) and at
+    2048 per cell per species in FP32 (524,288 particles)."""
+    return dict(discharge_fp64=dipic_bench(), discharge_large_fp32=dipic_bench(ppc=2048, nsteps=200, precision=32))
+
+
 TIMING_EVERY = 10   # steps between timed launches of the dominant kernel
 SORT_EVERY = 50     # re-sort the quadtree particles by leaf every this many steps
 
@@ -516,6 +560,8 @@ def main():
     ap.add_argument("--no-octree", action="store_true", help="skip the 3D octree workload")
     ap.add_argument("--only-octree", action="store_true", help="measure only the 3D octree workload (profiling)")
     ap.add_argument("--only-avalanche", action="store_true", help="measure only the 2D avalanche ensemble")
+    ap.add_argument("--no-dipic", action="store_true", help="skip the direct implicit 1D discharge")
+    ap.add_argument("--only-dipic", action="store_true", help="measure only the direct implicit 1D discharge")
     ap.add_argument("--avalanche-steps", type=int, default=200)
     ap.add_argument("--avalanche-modes", default="batched,plain_fp32,plain")
     ap.add_argument("--ensemble-modes", default="batched,plain_fp32,plain,batched_energy_conserving",
@@ -530,7 +576,7 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU (sharding across GPUs is designed, not built); --gpus must be 1"}))
         sys.exit(2)
     profiling = (args.only_ensemble or args.only_streamer or args.only_quadtree or args.only_avalanche
-                 or args.only_octree or args.copy_probe)
+                 or args.only_octree or args.only_dipic or args.copy_probe)
     # the oracle's host timing runs first, before this process touches the GPU
     # (its ensemble sample forks worker processes)
     cpu = None
@@ -564,6 +610,9 @@ def main():
     if args.only_octree:
         print(json.dumps({"octree": octree_bench(args.particles, args.steps, args.warmup, min(SORT_EVERY, args.steps),
                                                  TIMING_EVERY)}), flush=True)
+        return
+    if args.only_dipic:
+        print(json.dumps({"dipic": dipic_runs()}), flush=True)
         return
     if args.only_avalanche:
         print(json.dumps({"avalanche_ensemble": avalanche_bench(args.avalanche_steps, shape=shape,
@@ -632,6 +681,9 @@ def main():
         out["avalanche_ensemble"] = avalanche_bench(args.avalanche_steps, shape=shape,
                                                     modes=tuple(args.avalanche_modes.split(",")))
         note("avalanche ensemble")
+    if not args.no_dipic:
+        out["dipic"] = dipic_runs()
+        note("dipic")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

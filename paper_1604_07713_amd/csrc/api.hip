@@ -788,7 +788,7 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
     hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, C.stream), "memset");
     if (d.field_scheme == PIC_FIELD_DIPIC) {
       sl.Qp = (unsigned long long*)sl.alloc(8 * 2 * (size_t)sl.nq);
-      sl.dws = (double*)sl.alloc(8 * 4 * (size_t)sl.nq);
+      sl.dws = (double*)sl.alloc(8 * 3 * (size_t)sl.nq);
       hip_check(hipMemsetAsync(sl.Qp, 0, 16 * (size_t)sl.nq, C.stream), "memset");
     }
   } else if (d.dim == 3) {

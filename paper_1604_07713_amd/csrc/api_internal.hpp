@@ -83,7 +83,7 @@ struct Slot {
   double inv2dx = 0;
   double chi[2] = {0, 0};                  // direct implicit: charge sum -> susceptibility per species
   unsigned long long* Qp = nullptr;        // direct implicit: charge at the predicted positions [2][N+1]
-  double* dws = nullptr;                   // direct implicit solve scratch [4][N+1]
+  double* dws = nullptr;                   // direct implicit solve scratch [3][N+1]
   // particles: [species][buffer]; cur = live buffer, the other is the sort target
   PBuf pb[2][2];
   int cur[2] = {0, 0};

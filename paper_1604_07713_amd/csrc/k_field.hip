@@ -169,66 +169,76 @@ hipError_t launch_field1d(const InstDev<T>* insts, int ninst, int max_n, int mod
 //   -f_i-1 phi_i-1 + (f_i-1 + f_i) phi_i - f_i phi_i+1 = c_i  (i = 1..N-1),
 //   f_i = 1 + (chi_i + chi_i+1)/2,  phi_0 = V (the next drive value), phi_N = 0,
 // is solved by forward elimination and back substitution.  The recurrences
-// are sequential (one lane, FP64 divisions), their operands staged through
-// LDS a chunk at a time by the whole workgroup; node E as in the explicit
-// solve.  Qp is cleared for the next step.  Scratch dws [4][N+1]: chi then
-// the elimination's c' (chi is dead by then), f, the right-hand side then
-// phi, and the elimination's d'.
+// are sequential (one lane, FP64 divisions); the workgroup forms the face
+// coefficients and right-hand sides of a chunk of nodes straight from Qp
+// into LDS ahead of the lane's sweep, which also stores c', d' to the
+// scratch dws [3][N+1] (read back only by meshes beyond one chunk).  With
+// N <= kDipicChunk phi stays in LDS, else it goes to dws too.  Node E as in the explicit solve; Qp is cleared for the next
+// step.
 constexpr int kDipicThreads = 1024;
-constexpr int kDipicChunk = 2048;
+constexpr int kDipicChunk = 1920;
+
+template <class T>
+__device__ __forceinline__ double dipic_chi(const InstDev<T>& I, const unsigned long long* Qp, int i) {
+  double c = 0.0;
+  for (int sp = 0; sp < I.nspecies; ++sp) c = c + I.chi[sp] * (double)(long long)Qp[(size_t)sp * I.nq + i];
+  return (i == 0 || i == I.N) ? 2.0 * c : c;   // a wall node's charge fills half a cell
+}
+template <class T>
+__device__ __forceinline__ double dipic_face(const InstDev<T>& I, const unsigned long long* Qp, int i) {
+  return 1.0 + (dipic_chi<T>(I, Qp, i) + dipic_chi<T>(I, Qp, i + 1)) * 0.5;   // face i + 1/2
+}
 
 template <class T>
 __global__ __launch_bounds__(kDipicThreads) void k_dipic_field(InstDev<T> I) {
-  __shared__ double sa[kDipicChunk + 1], sb[kDipicChunk];
+  __shared__ double sf[kDipicChunk + 1], sr[kDipicChunk], scp[kDipicChunk], sdp[kDipicChunk];
   if (I.ctr->flags & kFlagNeedRoom) return;   // the predictor did not run this step
   const int N = I.N;
   const uint32_t nq = I.nq;
   const int tid = threadIdx.x, nt = blockDim.x;
   const uint32_t kk = I.ctr->step + 1u - I.ctr->vstep0;
   const double left = (I.v_table && kk < I.v_len) ? I.v_table[kk] : 0.0;
-  double* chi = I.dws;
+  const bool single = N <= kDipicChunk;
   double* cp = I.dws;
-  double* f = I.dws + nq;
-  double* rhs = I.dws + 2u * nq;
-  double* ph = I.dws + 2u * nq;
-  double* dp = I.dws + 3u * nq;
+  double* dp = I.dws + nq;
+  double* ph = single ? sf : I.dws + 2u * nq;   // sf is free once the sweep is done
   unsigned long long* Qp = I.Qp;
-  const int ns = I.nspecies;
-  for (int i = tid; i <= N; i += nt) {
-    double c = 0.0;
-    for (int sp = 0; sp < ns; ++sp) c = c + I.chi[sp] * (double)(long long)Qp[(size_t)sp * nq + i];
-    chi[i] = (i == 0 || i == N) ? 2.0 * c : c;
-  }
-  __syncthreads();
-  for (int i = tid; i < N; i += nt) f[i] = 1.0 + (chi[i] + chi[i + 1]) * 0.5;
-  for (int i = 1 + tid; i < N; i += nt) {
-    double r = 0.0;
-    for (int sp = 0; sp < ns; ++sp) r = r + (double)(long long)Qp[(size_t)sp * nq + i] * I.kappa[sp];
-    if (i == 1) r = r + (1.0 + (chi[0] + chi[1]) * 0.5) * left;
-    rhs[i] = r;
-  }
-  __syncthreads();
-  for (uint32_t j = tid; j < (uint32_t)ns * nq; j += nt) Qp[j] = 0ull;
-  // forward elimination over nodes [c0, c0 + n): f[c0-1 .. c0+n-1] and the
-  // right-hand sides go to LDS; lane 0 carries c', d' of the previous node
+  // forward elimination over chunks of nodes [c0, c0 + n); lane 0 carries
+  // c', d' of the previous node
   double cprev = 0.0, dprev = 0.0;
   for (int c0 = 1; c0 < N; c0 += kDipicChunk) {
     const int n = N - c0 < kDipicChunk ? N - c0 : kDipicChunk;
-    for (int t = tid; t <= n; t += nt) sa[t] = f[c0 - 1 + t];
-    for (int t = tid; t < n; t += nt) sb[t] = rhs[c0 + t];
+    for (int t = tid; t <= n; t += nt) sf[t] = dipic_face<T>(I, Qp, c0 - 1 + t);
+    for (int t = tid; t < n; t += nt) {
+      const int i = c0 + t;
+      double r = 0.0;
+      for (int sp = 0; sp < I.nspecies; ++sp) r = r + (double)(long long)Qp[(size_t)sp * nq + i] * I.kappa[sp];
+      if (i == 1) r = r + dipic_face<T>(I, Qp, 0) * left;
+      sr[t] = r;
+    }
     __syncthreads();
     if (tid == 0) {
-      for (int t = 0; t < n; ++t) {
-        const double a = -sa[t], bb = sa[t] + sa[t + 1], c = -sa[t + 1];
-        double cpi, dpi;
-        if (c0 + t == 1) {
-          cpi = c / bb;
-          dpi = sb[t] / bb;
-        } else {
-          const double m = bb - a * cprev;
-          cpi = c / m;
-          dpi = (sb[t] - a * dprev) / m;
-        }
+      int t = 0;
+      if (c0 == 1) {   // node 1 starts the elimination
+        const double bb = sf[0] + sf[1], c = -sf[1];
+        cprev = c / bb;
+        dprev = sr[0] / bb;
+        scp[0] = cprev;
+        sdp[0] = dprev;
+        cp[1] = cprev;
+        dp[1] = dprev;
+        t = 1;
+      }
+      // branch-free body: the LDS operands of later nodes load ahead, the
+      // two divisions of a node are independent
+#pragma unroll 4
+      for (; t < n; ++t) {
+        const double a = -sf[t], bb = sf[t] + sf[t + 1], c = -sf[t + 1], r = sr[t];
+        const double m = bb - a * cprev;
+        const double cpi = c / m;
+        const double dpi = (r - a * dprev) / m;
+        scp[t] = cpi;
+        sdp[t] = dpi;
         cp[c0 + t] = cpi;
         dp[c0 + t] = dpi;
         cprev = cpi;
@@ -237,19 +247,32 @@ __global__ __launch_bounds__(kDipicThreads) void k_dipic_field(InstDev<T> I) {
     }
     __syncthreads();
   }
-  // back substitution over nodes [lo, hi), from the top
+  // the charge of the predicted positions is consumed
+  for (uint32_t j = tid; j < (uint32_t)I.nspecies * nq; j += nt) Qp[j] = 0ull;
+  // back substitution over the same chunks from the top; the last chunk's
+  // c', d' are still in LDS
+  const int last = 1 + ((N - 2) / kDipicChunk) * kDipicChunk;
   double next = 0.0;
-  for (int hi = N; hi > 1; hi -= kDipicChunk) {
-    const int lo = hi - kDipicChunk > 1 ? hi - kDipicChunk : 1;
-    for (int t = tid; t < hi - lo; t += nt) {
-      sa[t] = cp[lo + t];
-      sb[t] = dp[lo + t];
+  for (int c0 = last; c0 >= 1; c0 -= kDipicChunk) {
+    const int n = N - c0 < kDipicChunk ? N - c0 : kDipicChunk;
+    if (c0 != last) {
+      for (int t = tid; t < n; t += nt) {
+        scp[t] = cp[c0 + t];
+        sdp[t] = dp[c0 + t];
+      }
     }
     __syncthreads();
     if (tid == 0) {
-      for (int i = hi - 1; i >= lo; --i) {
-        next = i == N - 1 ? sb[i - lo] : sb[i - lo] - sa[i - lo] * next;
-        ph[i] = next;
+      int t = n - 1;
+      if (c0 == last) {   // node N - 1
+        next = sdp[t];
+        ph[c0 + t] = next;
+        --t;
+      }
+#pragma unroll 4
+      for (; t >= 0; --t) {
+        next = sdp[t] - scp[t] * next;
+        ph[c0 + t] = next;
       }
     }
     __syncthreads();

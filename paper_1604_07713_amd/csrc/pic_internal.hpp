@@ -94,7 +94,7 @@ struct InstDev {
   int dipic;                     // 1D direct implicit step (D1 scheme)
   double chi[2];                 // direct implicit: charge-sum -> susceptibility factor per species
   unsigned long long* Qp;        // direct implicit: charge at the predicted positions [2][N+1]
-  double* dws;                   // direct implicit solve scratch [4][N+1]
+  double* dws;                   // direct implicit solve scratch [3][N+1] (meshes beyond one LDS chunk)
   int cell_e;                    // 1D energy-conserving coupling: E holds cell values, gathered without interpolation
   int cic_amr;                   // 2D cloud-in-cell coupling: deposit and gather through the particle's cloud
   const T* cellE;                // 2D cloud-in-cell: cell-centred E [nleaves][2]

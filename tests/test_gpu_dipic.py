@@ -100,6 +100,30 @@ def test_two_species_between_reflecting_walls(precision):
     assert np.array_equal(o.deposit(), g.deposit_read(0))
 
 
+@pytest.mark.parametrize("ncells", [1920, 1921, 4100])
+def test_meshes_beyond_one_lds_chunk(ncells):
+    """Node counts at and beyond the field kernel's LDS chunk (1920 interior
+    nodes): the sweeps carry c', d' across chunks through global memory."""
+    d, xe, we, xi, wi = random_plasma(seed=5, N=ncells)
+    d = dict(d, particle_bc=I.REFLECT)
+    rng = np.random.Generator(np.random.PCG64(12))
+    dx, dt = d["length"] / d["ncells"], d["dt"]
+    parts = [(xe[:, None], rng.standard_normal((len(xe), 3)) * (0.5 * dx / dt), we, np.arange(len(xe), dtype=np.uint32)),
+             (xi[:, None], np.zeros((len(xi), 3)), wi, np.arange(len(xe), len(xe) + len(xi), dtype=np.uint32))]
+    o, g = load_both(d, parts)
+    o.deposit()
+    g.deposit(0)
+    o.field_solve_1d(-3.0)
+    g.field_solve_1d(0, -3.0)
+    o.leapfrog_start()
+    g.leapfrog_start(0)
+    vn = -3.0 * np.ones(12)
+    same_stats(o.step(0, 12, vn, True), g.step(0, 12, vn, solve_field=True, sort_every=5))
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), TOL[64], f"species {sp}")
+    same_field(o, g, 64)
+
+
 @pytest.mark.parametrize("precision,ranking", [(64, 0), (32, 0), (32, 2)])
 def test_discharge_with_collisions_and_births(precision, ranking):
     """The discharge at w_p dt = 2.08 (100x the density of the explicit
