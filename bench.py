@@ -491,7 +491,8 @@ def octree_bench(n, steps, warmup, sort_every, timing_every):
                ms_per_step=dt * 1e3 / steps, kernel_ms_per_step=kern_ms,
                workload=(f"3D static octree (levels 4-7, {len(keys)} leaves), {n} electrons, trilinear gather + "
                          f"push + reflect + locate + NGP deposit, sort every {sort_every} steps"))
-    out["roofline"] = roofline((updates / steps) * BYTES_PER_UPDATE_3D, kern_ms)
+    out["roofline"] = roofline((updates / steps) * BYTES_PER_UPDATE_3D, kern_ms,
+                               traffic_from_profile("k_step3d<float,false>", f"octree {n} electrons"))
     out["roofline"]["per"] = "k_step3d<float,false> launch, 60 B per particle-update"
     return out
 
