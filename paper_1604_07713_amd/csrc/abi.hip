@@ -194,13 +194,14 @@ void plain_step(Ctx& C, Slot& sl, bool solve, int g, hipEvent_t e0, hipEvent_t e
   }
   const bool field = sl.d.dim == 1 && solve;
   const int commit = (!sl.ionizing && !field) ? 1 : 0;
-  if (e0) hip_check(hipEventRecord(e0, C.stream), "event");
-  hip_check(launch_step<T>(I, C.stream, g, slot_has_mcc(sl), commit), "step");
+  // a timed step: from the step kernel's own start to its end, or to after
+  // the births kernels
+  hip_check(launch_step<T>(I, C.stream, g, slot_has_mcc(sl), commit, e0, sl.ionizing ? nullptr : e1), "step");
   if (sl.ionizing) {
     // binned ranking once births per step are many (pairwise work grows as their square)
     hip_check(launch_births<T>(I, C.stream, I.births_binned != 0), "births");
+    if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
   }
-  if (e1) hip_check(hipEventRecord(e1, C.stream), "event");
   if (field)
     hip_check(launch_field1d<T>((const InstDev<T>*)sl.devI, 1, sl.d.ncells, 1, nullptr, C.stream), "field1d");
   else if (!commit)

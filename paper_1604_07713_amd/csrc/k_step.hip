@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <atomic>
 
+#include <hip/hip_ext.h>
+
 #include "device_util.hpp"
 #include "pic_internal.hpp"
 
@@ -2239,25 +2241,34 @@ __global__ void k_gather_points(InstDev<T> I, const double* s, int64_t n, double
 }
 
 // ---- launchers ----
+// A launch whose start and end the runtime writes into t0 / t1 (the
+// dispatch's own timestamps) when they are given.
+template <typename F, typename... A>
+void launch_timed(F kernel, dim3 g, dim3 b, hipStream_t s, hipEvent_t t0, hipEvent_t t1, A... args) {
+  if (t0 || t1) hipExtLaunchKernelGGL(kernel, g, b, 0, s, t0, t1, 0, args...);
+  else hipLaunchKernelGGL(kernel, g, b, 0, s, args...);
+}
+
 template <class T>
-hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit) {
+hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit, hipEvent_t t0,
+                       hipEvent_t t1) {
   if (I.nspecies == 2 && grid < 2) return hipErrorInvalidValue;   // the species split needs two workgroups
   const dim3 g(grid), b(kBlock);
   if (I.dim == 3) {
-    if (mcc) hipLaunchKernelGGL((k_step3d<T, true>), g, b, 0, s, I, commit);
-    else hipLaunchKernelGGL((k_step3d<T, false>), g, b, 0, s, I, commit);
+    if (mcc) launch_timed(k_step3d<T, true>, g, b, s, t0, t1, I, commit);
+    else launch_timed(k_step3d<T, false>, g, b, s, t0, t1, I, commit);
   } else if (I.cic_amr) {
-    if (mcc) hipLaunchKernelGGL((k_step2d_cic<T, true>), g, b, 0, s, I, commit);
-    else hipLaunchKernelGGL((k_step2d_cic<T, false>), g, b, 0, s, I, commit);
+    if (mcc) launch_timed(k_step2d_cic<T, true>, g, b, s, t0, t1, I, commit);
+    else launch_timed(k_step2d_cic<T, false>, g, b, s, t0, t1, I, commit);
   } else if (I.dim == 1) {
-    if (mcc) hipLaunchKernelGGL((k_step<T, true, 1, false>), g, b, 0, s, I, commit);
-    else hipLaunchKernelGGL((k_step<T, false, 1, false>), g, b, 0, s, I, commit);
+    if (mcc) launch_timed(k_step<T, true, 1, false>, g, b, s, t0, t1, I, commit);
+    else launch_timed(k_step<T, false, 1, false>, g, b, s, t0, t1, I, commit);
   } else if (I.lut_direct) {
-    if (mcc) hipLaunchKernelGGL((k_step<T, true, 2, true>), g, b, 0, s, I, commit);
-    else hipLaunchKernelGGL((k_step<T, false, 2, true>), g, b, 0, s, I, commit);
+    if (mcc) launch_timed(k_step<T, true, 2, true>, g, b, s, t0, t1, I, commit);
+    else launch_timed(k_step<T, false, 2, true>, g, b, s, t0, t1, I, commit);
   } else {
-    if (mcc) hipLaunchKernelGGL((k_step<T, true, 2, false>), g, b, 0, s, I, commit);
-    else hipLaunchKernelGGL((k_step<T, false, 2, false>), g, b, 0, s, I, commit);
+    if (mcc) launch_timed(k_step<T, true, 2, false>, g, b, s, t0, t1, I, commit);
+    else launch_timed(k_step<T, false, 2, false>, g, b, s, t0, t1, I, commit);
   }
   return hipGetLastError();
 }
@@ -2395,7 +2406,7 @@ hipError_t launch_relocate(const InstDev<T>& I, int species, hipStream_t s, int 
 }
 
 #define PIC_INSTANTIATE(T)                                                                                 \
-  template hipError_t launch_step<T>(const InstDev<T>&, hipStream_t, int, bool, int);                                                     \
+  template hipError_t launch_step<T>(const InstDev<T>&, hipStream_t, int, bool, int, hipEvent_t, hipEvent_t);                                                     \
   template int step_resident_grid<T>(int, bool, bool);                      \
   template hipError_t launch_step1d_batched<T>(const InstDev<T>*, const WorkItem*, uint32_t,               \
                                                unsigned long long*, hipStream_t, int, bool);               \

@@ -135,7 +135,9 @@ struct WorkItem {
 // ---- launchers (k_step.hip) ----
 // commit != 0: the last workgroup advances the step index (no births kernel
 // or field solve follows in this step).
-template <class T> hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit);
+// t0 / t1, when given, receive the step kernel's own start and end (timing).
+template <class T> hipError_t launch_step(const InstDev<T>& I, hipStream_t s, int grid, bool mcc, int commit,
+                                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 template <class T> int step_resident_grid(int dim, bool mcc, bool direct);
 template <class T> hipError_t launch_step1d_batched(const InstDev<T>* I, const WorkItem* items, uint32_t nitems,
                                                     unsigned long long* bpart, hipStream_t s, int grid, bool mcc);
