@@ -51,6 +51,10 @@ BYTES_PER_UPDATE_2D_MCC = 56
 #  3D FP32 without collisions: read sx, sy, sz, vx, vy, vz, leaf, w (32 B),
 #  write sx, sy, sz, vx, vy, vz, leaf (28 B) -> 60 B.
 BYTES_PER_UPDATE_3D = 60
+#  1D direct implicit step: the predictor reads s, v_x, b, w and writes s,
+#  v_x; the corrector reads s, v_x, b, w, id and writes s, v_x, b -> 56 B
+#  (FP32), 100 B (FP64).
+BYTES_PER_UPDATE_DIPIC = {32: 56, 64: 100}
 METRIC = "particle-updates/s (locate+gather+push+MCC+deposit), 2D AMR; batched vs plain"
 PROFILE_PMC = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
@@ -521,9 +525,14 @@ def dipic_bench(ppc=64, nsteps=400, precision=64, sort_every=20, timing_every=10
     dt = time.perf_counter() - t0
     g.close()
     updates = st["alive_start"][0] + st["alive_start"][1]
+    kern_ms = st["loop_ms"] / max(st["loop_launches"], 1)
+    per_update = BYTES_PER_UPDATE_DIPIC[precision]
+    roof = roofline((updates / nsteps) * per_update, kern_ms)
+    roof["per"] = (f"the step's kernels (predictor, implicit field, corrector, births), {per_update} B per "
+                   "particle-update (predictor and corrector traffic; collisions' extra bytes left out)")
     return dict(particles_start=2 * d["extra"]["npart"], steps=nsteps, precision=f"fp{precision}",
-                updates_per_s=updates / dt, ms_per_step=dt * 1e3 / nsteps,
-                step_kernels_ms=st["loop_ms"] / max(st["loop_launches"], 1), births=st["births"],
+                updates_per_s=updates / dt, ms_per_step=dt * 1e3 / nsteps, roofline=roof,
+                step_kernels_ms=kern_ms, births=st["births"],
                 workload=(f"1D discharge, direct implicit (w_p dt 2.08, dx 4.4 Debye lengths), 128 cells x {ppc} "
                           f"per cell per species, {nsteps} steps, sort every {sort_every}"),
                 note="step_kernels_ms: predictor + implicit field + corrector + births of one step (HIP events "
