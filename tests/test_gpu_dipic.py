@@ -140,6 +140,22 @@ def test_discharge_with_collisions_and_births(precision, ranking):
     assert np.array_equal(o.deposit(), g.deposit_read(0))
 
 
+def test_discharge_at_the_benchmarks_large_size():
+    """The discharge at 2048 particles per cell per species in FP32 (524,288
+    particles), as the benchmark times it: 200 steps, sort every 20, default
+    launch grid, against the oracle stepping every particle."""
+    d = I.dipic_ccp_desc(precision=32, ppc=2048)
+    o, g, so, sg = ccp_run_both(d, 200, sort_every=20)
+    same_stats(so, sg)
+    print("births", so["births"], "elastic", so["elastic"], "cx", so["cx"], flush=True)
+    assert so["births"] > 0
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), TOL[32], f"species {sp}")
+    assert o.next_id == g.next_id(0)
+    same_field(o, g, 32)
+    assert np.array_equal(o.deposit(), g.deposit_read(0))
+
+
 def test_room_stops_are_bit_identical():
     d = fast_ionizing(I.dipic_ccp_desc(precision=32))
     ctx = {}

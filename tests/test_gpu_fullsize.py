@@ -43,13 +43,14 @@ def host_locate(keys, s):
     return (np.searchsorted(keys.astype(np.uint64), m, side="right") - 1).astype(np.int64)
 
 
-def test_quadtree_full_size_sampled():
+@pytest.mark.parametrize("n", [4194304, 16777216])
+def test_quadtree_full_size_sampled(n):
     """4,194,304 electrons on the static quadtree (the benchmark's particles),
-    default launch grid, 60 steps with the order kept by a sort every 50 steps:
+    and the 16,777,216 of its variant beyond the Infinity Cache, default
+    launch grid, 60 steps with the order kept by a sort every 50 steps:
     20,000 particles sampled by id equal the oracle's, and the step loop's
     deposit equals the particles' NGP charge."""
     d = I.quadtree_static_desc()
-    n = 4194304
     s, v, w, ids = I.quadtree_particles(n)
     g = B.Context(d)
     g.load(0, 0, s, v, w, ids)
