@@ -1612,8 +1612,6 @@ __global__ __launch_bounds__(kBlock) void k_step3d(InstDev<T> I, int commit) {
 // charge.  One lane per particle; the species split of the workgroups is
 // the explicit step's, so both kernels add their counts to the same
 // partial-stats rows.
-constexpr int kDipicK = 1;   // particles per lane per trip of the direct implicit kernels
-
 struct BlockRange {
   int sp;
   uint32_t begin, end;
@@ -1634,8 +1632,7 @@ __device__ __forceinline__ BlockRange dipic_range(const InstDev<T>& I) {
   const uint32_t b = r.sp == 0 ? blockIdx.x : blockIdx.x - gs;
   const uint32_t nb = r.sp == 0 ? gs : grid - gs;
   const uint32_t count = r.sp == 0 ? n0 : n1;
-  const uint32_t unit = kDipicK * kBlock;
-  const uint32_t chunk = ((count + nb - 1u) / nb + unit - 1u) / unit * unit;
+  const uint32_t chunk = ((count + nb - 1u) / nb + kBlock - 1u) / kBlock * kBlock;
   const uint64_t begin64 = (uint64_t)b * chunk;
   r.begin = begin64 < count ? (uint32_t)begin64 : count;
   r.end = (uint64_t)r.begin + chunk < count ? r.begin + chunk : count;
@@ -1715,47 +1712,34 @@ __global__ __launch_bounds__(kBlock) void k_dipic_predict(InstDev<T> I) {
   __syncthreads();
   D.base = *L.wbase;
   LStat st = {0, 0, 0, 0, 0, 0, 0};
-  // kDipicK particles per lane per trip, all their loads issued first (a
-  // lane past the end reads the range's first particle and drops it); the
-  // trip count is uniform over the workgroup (the deposit shuffles across
-  // the wave)
-  for (uint32_t t = R.begin; t < R.end; t += kDipicK * kBlock) {
-    uint32_t w[kDipicK];
-    T v[kDipicK], s[kDipicK], b[kDipicK];
-#pragma unroll
-    for (int j = 0; j < kDipicK; ++j) {
-      const uint32_t i = t + (uint32_t)j * kBlock + threadIdx.x;
-      const uint32_t ii = i < R.end ? i : R.begin;
-      w[j] = W[ii];
-      v[j] = V[ii];
-      s[j] = S[ii];
-      b[j] = A[ii];
-      w[j] = i < R.end ? w[j] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < kDipicK; ++j) {
-      const uint32_t i = t + (uint32_t)j * kBlock + threadIdx.x;
-      uint32_t key = kNoKey;
-      unsigned long long q0 = 0ull, q1 = 0ull;
-      if (w[j]) {
-        T vv = v[j] + b[j];
-        T ss = s[j] + vv * dt_L;
-        bool lost = false;
-        const bool ok = wall_rule<T>(reflect, ss, vv, lost);
-        st.alive++;
-        if (!ok) {
-          st.absorbed++;
-          st.lost += lost ? 1u : 0u;
-          W[i] = 0u;
-        } else {
-          S[i] = ss;
-          V[i] = vv;
-          cic1d_shares<T>(I.N, ss, w[j], key, q0, q1);
-        }
+  // one particle per lane and trip, its loads issued together (a lane past
+  // the end reads the range's first particle and drops it); the trip count
+  // is uniform over the workgroup (the deposit shuffles across the wave)
+  for (uint32_t t = R.begin; t < R.end; t += kBlock) {
+    const uint32_t i = t + threadIdx.x;
+    const uint32_t ii = i < R.end ? i : R.begin;
+    const uint32_t w = i < R.end ? W[ii] : 0u;
+    const T v0 = V[ii], s0 = S[ii], b = A[ii];
+    uint32_t key = kNoKey;
+    unsigned long long q0 = 0ull, q1 = 0ull;
+    if (w) {
+      T v = v0 + b;
+      T s = s0 + v * dt_L;
+      bool lost = false;
+      const bool ok = wall_rule<T>(reflect, s, v, lost);
+      st.alive++;
+      if (!ok) {
+        st.absorbed++;
+        st.lost += lost ? 1u : 0u;
+        W[i] = 0u;
+      } else {
+        S[i] = s;
+        V[i] = v;
+        cic1d_shares<T>(I.N, s, w, key, q0, q1);
       }
-      seg_dep_add(D, Qs, key, q0);
-      seg_dep_add(D, Qs, key == kNoKey ? kNoKey : key + 1u, q1);
     }
+    seg_dep_add(D, Qs, key, q0);
+    seg_dep_add(D, Qs, key == kNoKey ? kNoKey : key + 1u, q1);
   }
   __syncthreads();
   dep_flush(D, Qs, I.nq);
@@ -1791,102 +1775,81 @@ __global__ __launch_bounds__(kBlock) void k_dipic_correct(InstDev<T> I) {
   __syncthreads();
   D.base = *L.wbase;
   LStat st = {0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t t = R.begin; t < R.end; t += kDipicK * kBlock) {
-    // loads of kDipicK particles first (as in the predictor), then the
-    // field at each (the E table is cache resident)
-    uint32_t wk[kDipicK], idk[kDipicK];
-    T sk[kDipicK], vk[kDipicK], bk[kDipicK], e0k[kDipicK], e1k[kDipicK];
-#pragma unroll
-    for (int j = 0; j < kDipicK; ++j) {
-      const uint32_t i = t + (uint32_t)j * kBlock + threadIdx.x;
-      const uint32_t ii = i < R.end ? i : R.begin;
-      wk[j] = W[ii];
-      sk[j] = S[ii];
-      vk[j] = V0[ii];
-      bk[j] = A[ii];
-      idk[j] = mcc ? ID[ii] : 0u;
-      wk[j] = i < R.end ? wk[j] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < kDipicK; ++j) {
-      const T g = (wk[j] ? sk[j] : (T)0) * (T)N;
-      int ic = (int)floor(g);
-      if (ic > N - 1) ic = N - 1;
-      e0k[j] = E[ic];
-      e1k[j] = E[ic + 1];
-    }
-#pragma unroll
-    for (int j = 0; j < kDipicK; ++j) {
-      const uint32_t i = t + (uint32_t)j * kBlock + threadIdx.x;
-      uint32_t w = wk[j];
-      bool birth = false;
-      BirthRec<T> rec = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-      uint32_t id = 0u;
-      T s = (T)0;
-      uint32_t key = kNoKey;
-      unsigned long long q0 = 0ull, q1 = 0ull;
-      if (w) {
-        s = sk[j];
-        T v = vk[j];
-        // E_n+1 at the predicted position, linear between the cell's nodes
-        const T g = s * (T)N;
-        int ic = (int)floor(g);
-        if (ic > N - 1) ic = N - 1;
-        const T fr = g - (T)ic;
-        const T e0 = e0k[j], e1 = e1k[j];
-        const T dv = k.hqm_dt * (e0 + fr * (e1 - e0));
-        v = v + dv;
-        s = s + dv * k.dt_L;
-        A[i] = (bk[j] + dv) * (T)0.5;
-        bool lost = false;
-        if (!wall_rule<T>(reflect, s, v, lost)) {
-          st.absorbed++;
-          st.lost += lost ? 1u : 0u;
-          W[i] = 0u;
-          w = 0u;
-        } else {
-          if (mcc) {
-            id = idk[j];
-            WordStream ws(I.key0, I.key1, id, step);
-            const uint32_t r0 = ws.next();
-            const uint32_t r1 = ws.next();
-            if ((r0 >> 8) < k.tcand) {
-              T vy = V1[i], vz = V2[i];
-              const uint32_t kind = collision_kind<T>(k, r1, v, vy, vz, st);
-              if (kind == kCollElastic) {
-                st.elastic++;
-                collide_elastic<T>(k, ws, v, vy, vz);
-              } else if (kind == kCollIonize) {
-                st.ionization++;
-                collide_ionize<T>(k, ws, v, vy, vz, rec);
-                birth = true;
-              } else if (kind == kCollCx) {
-                st.cx += collide_cx<T>(k, r1, ws, v, vy, vz, st) ? 1u : 0u;
-              }
-              if (kind != kCollNone) {
-                V1[i] = vy;
-                V2[i] = vz;
-              }
+  for (uint32_t t = R.begin; t < R.end; t += kBlock) {
+    // the particle's loads together (as in the predictor), then the field
+    // at its predicted position (the E table is cache resident)
+    const uint32_t i = t + threadIdx.x;
+    const uint32_t ii = i < R.end ? i : R.begin;
+    uint32_t w = i < R.end ? W[ii] : 0u;
+    const T s0 = S[ii], v0 = V0[ii], b = A[ii];
+    const uint32_t pid = mcc ? ID[ii] : 0u;
+    const T g = (w ? s0 : (T)0) * (T)N;
+    int ic = (int)floor(g);
+    if (ic > N - 1) ic = N - 1;
+    const T e0 = E[ic], e1 = E[ic + 1];
+    bool birth = false;
+    BirthRec<T> rec = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+    uint32_t id = 0u;
+    T s = (T)0;
+    uint32_t key = kNoKey;
+    unsigned long long q0 = 0ull, q1 = 0ull;
+    if (w) {
+      s = s0;
+      T v = v0;
+      // E_n+1 at the predicted position, linear between the cell's nodes
+      const T fr = g - (T)ic;
+      const T dv = k.hqm_dt * (e0 + fr * (e1 - e0));
+      v = v + dv;
+      s = s + dv * k.dt_L;
+      A[i] = (b + dv) * (T)0.5;
+      bool lost = false;
+      if (!wall_rule<T>(reflect, s, v, lost)) {
+        st.absorbed++;
+        st.lost += lost ? 1u : 0u;
+        W[i] = 0u;
+        w = 0u;
+      } else {
+        if (mcc) {
+          id = pid;
+          WordStream ws(I.key0, I.key1, id, step);
+          const uint32_t r0 = ws.next();
+          const uint32_t r1 = ws.next();
+          if ((r0 >> 8) < k.tcand) {
+            T vy = V1[i], vz = V2[i];
+            const uint32_t kind = collision_kind<T>(k, r1, v, vy, vz, st);
+            if (kind == kCollElastic) {
+              st.elastic++;
+              collide_elastic<T>(k, ws, v, vy, vz);
+            } else if (kind == kCollIonize) {
+              st.ionization++;
+              collide_ionize<T>(k, ws, v, vy, vz, rec);
+              birth = true;
+            } else if (kind == kCollCx) {
+              st.cx += collide_cx<T>(k, r1, ws, v, vy, vz, st) ? 1u : 0u;
+            }
+            if (kind != kCollNone) {
+              V1[i] = vy;
+              V2[i] = vz;
             }
           }
-          S[i] = s;
-          V0[i] = v;
-          cic1d_shares<T>(N, s, w, key, q0, q1);
         }
+        S[i] = s;
+        V0[i] = v;
+        cic1d_shares<T>(N, s, w, key, q0, q1);
       }
-      if (births) stage_birth<T>(I, birth, id, 0u, w, s, (T)0, rec);
-      seg_dep_add(D, Qs, key, q0);
-      seg_dep_add(D, Qs, key == kNoKey ? kNoKey : key + 1u, q1);
-      // a newborn pair sits on its parent with the parent's weight (rare:
-      // straight to global memory)
-      if (births && __ballot(birth) != 0ull) {
-        const uint32_t kb = birth ? key : kNoKey;
-        const uint32_t kb1 = birth ? key + 1u : kNoKey;
-        seg_atomic_add(Qpar, kb, q0);
-        seg_atomic_add(Qpar, kb1, q1);
-        seg_atomic_add(Qpar + I.nq, kb, q0);
-        seg_atomic_add(Qpar + I.nq, kb1, q1);
-      }
+    }
+    if (births) stage_birth<T>(I, birth, id, 0u, w, s, (T)0, rec);
+    seg_dep_add(D, Qs, key, q0);
+    seg_dep_add(D, Qs, key == kNoKey ? kNoKey : key + 1u, q1);
+    // a newborn pair sits on its parent with the parent's weight (rare:
+    // straight to global memory)
+    if (births && __ballot(birth) != 0ull) {
+      const uint32_t kb = birth ? key : kNoKey;
+      const uint32_t kb1 = birth ? key + 1u : kNoKey;
+      seg_atomic_add(Qpar, kb, q0);
+      seg_atomic_add(Qpar, kb1, q1);
+      seg_atomic_add(Qpar + I.nq, kb, q0);
+      seg_atomic_add(Qpar + I.nq, kb1, q1);
     }
   }
   __syncthreads();
