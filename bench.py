@@ -546,7 +546,7 @@ def dipic_runs():
 
 
 TIMING_EVERY = 10   # steps between timed launches of the dominant kernel
-SORT_EVERY = 50     # re-sort the quadtree particles by leaf every this many steps
+SORT_EVERY = 50     # re-sort the quadtree and octree particles by leaf every this many steps
 
 
 def main():
@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--no-octree", action="store_true", help="skip the 3D octree workload")
     ap.add_argument("--only-octree", action="store_true", help="measure only the 3D octree workload (profiling)")
     ap.add_argument("--only-avalanche", action="store_true", help="measure only the 2D avalanche ensemble")
+    ap.add_argument("--sort-every", type=int, default=SORT_EVERY,
+                    help="steps between re-sorts of the quadtree and octree particles by leaf")
     ap.add_argument("--no-dipic", action="store_true", help="skip the direct implicit 1D discharge")
     ap.add_argument("--only-dipic", action="store_true", help="measure only the direct implicit 1D discharge")
     ap.add_argument("--avalanche-steps", type=int, default=200)
@@ -618,7 +620,7 @@ def main():
         print(json.dumps({"streamer": streamer_bench(args.streamer_steps)}), flush=True)
         return
     if args.only_octree:
-        print(json.dumps({"octree": octree_bench(args.particles, args.steps, args.warmup, min(SORT_EVERY, args.steps),
+        print(json.dumps({"octree": octree_bench(args.particles, args.steps, args.warmup, min(args.sort_every, args.steps),
                                                  TIMING_EVERY)}), flush=True)
         return
     if args.only_dipic:
@@ -631,7 +633,7 @@ def main():
         return
 
     # the timed steps hold floor(steps / sort_every) sorts
-    sort_every = min(SORT_EVERY, args.steps)
+    sort_every = min(args.sort_every, args.steps)
     q = quadtree_bench(args.particles, args.steps, args.warmup, sort_every, TIMING_EVERY)
     note(f"quadtree {args.particles}")
     value = q["updates"] / q["seconds"]
@@ -668,7 +670,7 @@ def main():
         return
     if args.large_particles:
         n = args.large_particles
-        ql = quadtree_bench(n, 50, 10, 50, 5)
+        ql = quadtree_bench(n, 50, 10, min(args.sort_every, 50), 5)
         note(f"quadtree {n}")
         out["quadtree_large"] = dict(
             particles=n, state_bytes=n * 28,
