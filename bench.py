@@ -221,6 +221,46 @@ def cpu_baseline(nparticles, nsteps, seed=2, extra=True):
                cpu_model=model, host_threads=avail)
     if not extra:
         return out
+    # the octree workload on all its particles for a few steps
+    d3 = I.octree_static_desc()
+    o3 = oracle.Oracle(d3)
+    s3, v3, w3, ids3 = I.octree_particles(nparticles)
+    o3.load(0, s3, v3, w3, ids3)
+    k3, l3 = o3.leaves()
+    x3, y3, z3 = I.leaf_corners3(k3, l3)
+    o3.field_set(oracle.CORNER_PHI_3D, I.octree_phi(x3, y3, z3))
+    o3.leapfrog_start()
+    steps3 = 8
+    t0 = time.perf_counter()
+    st3 = o3.step(0, steps3)
+    t3 = time.perf_counter() - t0
+    del o3
+    out["octree_sample"] = dict(updates_per_s=st3["alive_start"][0] / t3, cores=1,
+                                sample=f"{nparticles} particles x {steps3} steps of the octree workload, "
+                                       f"single-threaded FP32-mirror oracle, {t3:.1f} s")
+    # the streamer's first 200 of its 2000 steps (adapt and CG every 10)
+    ds = I.streamer_desc(side=0.01, precision=32)
+    os_ = oracle.Oracle(ds)
+    for sp, (s_, v_, w_, i_) in enumerate(I.streamer_particles(ds, npairs=10000)):
+        os_.load(sp, s_, v_, w_, i_)
+    os_.adapt()
+    os_.field_solve_2d(rtol=1e-8, maxit=4000)
+    os_.leapfrog_start()
+    t_loop = t_all = 0.0
+    upd_s = 0
+    for k in range(0, 200, 10):
+        t0 = time.perf_counter()
+        st_s = os_.step(k, 10)
+        t1 = time.perf_counter()
+        os_.adapt()
+        os_.field_solve_2d(rtol=1e-8, maxit=4000)
+        t_loop += t1 - t0
+        t_all += time.perf_counter() - t0
+        upd_s += st_s["alive_start"][0] + st_s["alive_start"][1]
+    out["streamer_sample"] = dict(particle_loop_updates_per_s=upd_s / t_loop, updates_per_s_with_adapt_and_field=upd_s / t_all,
+                                  cores=1, sample=f"the 2D streamer's first 200 of its 2000 steps (2e4 -> {os_.count(0) + os_.count(1)} "
+                                                  f"particles; the full run reaches 3e7), FP32-mirror oracle, {t_all:.1f} s")
+    del os_
     # 1D discharge in full: 16,384 particles, 400 steps, FP64
     u, t = _ccp_oracle_run((I.ccp_desc(precision=64), 400))
     out["ccp_full"] = dict(updates_per_s=u / t, cores=1, sample=f"the whole 1D discharge run, 400 steps, FP64, {t:.2f} s")
