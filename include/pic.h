@@ -208,11 +208,14 @@ typedef struct {
   int nsteps;
   int solve_field;      /* 1D: after each step solve Poisson on the device with   */
   const double* v_next; /* ... phi(0) = v_next[k*ninst_sel + j] for step k, slot j */
+                        /* (a direct implicit slot solves within the step, at the */
+                        /* same drive value, and needs both)                        */
   int sort_every;       /* re-sort particles by cell every n steps (0 = never)    */
   int batched;          /* 0: launches per slot; > 0: one persistent launch over   */
                         /* all selected slots of one dimension and precision, with */
                         /* this many particles per work item (1 = 4096); quadtree  */
-                        /* slots with the cloud-in-cell coupling are refused       */
+                        /* slots with the cloud-in-cell coupling, octree slots and */
+                        /* direct implicit slots are refused (PIC_E_ARG)           */
   int grid;             /* workgroups of the particle kernel: persistent grid of the
                            batched launch (0 = 2048), or grid of the per-slot launch
                            (0 = one workgroup per 256 particles, at most 2048);
@@ -221,10 +224,13 @@ typedef struct {
                         /* and replay it (0 = no graph)                            */
   const int* slots;     /* selected slots (NULL = all live slots)                 */
   int nslots;
-  int timing;           /* 0: no events; n > 0: record HIP events around the      */
-                        /* particle-loop kernel of every n-th step of the call      */
-                        /* (per-slot launches; batched launches: every step), and   */
-                        /* around the whole call.  PIC_E_ARG if negative.           */
+  int timing;           /* 0: no events; n > 0: time the particle loop of every    */
+                        /* n-th step of the call (per-slot launches: the step       */
+                        /* kernel's own start and end, or to after the births      */
+                        /* kernels when they follow; direct implicit: predictor to */
+                        /* births; batched launches: every step, around the launch */
+                        /* and its births kernels), and the whole call.  PIC_E_ARG */
+                        /* if negative.                                             */
 } pic_step_args;
 
 typedef struct {
