@@ -50,6 +50,19 @@
  *    limit and call again with step0 = -1 for the remaining steps.
  *    PIC_E_STATE marks a slot whose device-side overflow guard fired
  *    anyway (not expected: the room check rules it out).
+ *  - Failed slots.  A call that fails part-way through changing a slot's
+ *    device tables (pic_adapt for lack of device memory, or any runtime
+ *    error in pic_adapt or pic_particles_load) marks the slot failed; so
+ *    does the overflow guard above.  Every later call on a failed slot
+ *    returns PIC_E_STATE, except pic_count, pic_next_id, pic_step_index,
+ *    pic_nleaves, pic_nq, pic_slot_bytes and pic_retire; the context's other
+ *    slots are unaffected.  Device memory running out in pic_step or
+ *    pic_particles_load leaves the slot usable (see above and below).
+ *  - Launch checks: with PIC_CHECK_LAUNCHES=1 in the environment, every
+ *    kernel-side view of a slot is checked on the host against the slot's
+ *    live device blocks before it is used (each array inside one block with
+ *    the extent its count implies; particle arrays below 4 GiB); a failed
+ *    check returns PIC_E_STATE instead of launching.
  */
 #ifndef PIC_H
 #define PIC_H
@@ -274,7 +287,9 @@ int pic_mesh_build(const pic_instance_desc* descs, int ninst, void* stream, pic_
  * n host particles: s[n*dim] normalised positions in [0,1), v[n*3] m/s, w[n]
  * (NULL: 2^16 each, i.e. w0 real particles), id[n] (NULL: 0..n-1).  Values
  * are rounded to the slot's precision; the arrays are copied.  PIC_E_ARG if
- * a position is outside [0,1) or a weight is 0. */
+ * a position is outside [0,1) or a weight is 0.  PIC_E_NOMEM (the room is
+ * allocated before the old particles are touched) leaves the slot as it
+ * was. */
 int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double* s, const double* v,
                        const uint32_t* w, const uint32_t* id);
 
@@ -310,8 +325,11 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out);
  * (repeatedly), 2:1 balance, reassign particles, split particles 1 -> 4 in
  * leaves below n_lo, merge pairs in leaves above n_hi at max_level.  Ends
  * with a fresh deposit.  s (nullable) receives what was done.  PIC_E_ARG for
- * a 1D slot; PIC_E_CAPACITY if split copies would exhaust the u32 ids or the
- * per-array limit (the tree is then adapted, the particles not split). */
+ * a 1D slot; PIC_E_CAPACITY, after a complete adaptation, if split copies
+ * would exhaust the u32 ids or the per-array limit (the particles are then
+ * not split) or a leaf at max_level holds more particles than one merge
+ * round sorts (that leaf is not merged); PIC_E_NOMEM marks the slot failed
+ * (the conventions above). */
 int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s);
 
 /* For callers that cannot allocate device memory (code between graph

@@ -90,7 +90,17 @@ Slot& get_slot(pic_ctx c, int slot) {
   return c->slots[slot];
 }
 
+// A slot whose device data may be used: not marked failed (a device-side
+// overflow, or a call that failed part-way through changing its tables).
+// A failed slot answers only the counter reads and pic_retire.
+Slot& usable_slot(pic_ctx c, int slot) {
+  Slot& sl = get_slot(c, slot);
+  if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state (retire it)");
+  return sl;
+}
+
 Mesh2D mesh_of(const Slot& sl) {
+  if (launch_checks()) check_tables(sl);
   Mesh2D m;
   m.key = sl.key;
   m.xy = sl.xy;
@@ -220,7 +230,7 @@ void reduce_plain_stats(Ctx& C, Slot& sl, int g) {
 // The slot continues from its own step index.
 void prepare_slot(Ctx& C, Slot& sl, const pic_step_args* a, const double* v_next, int j, int nsel, int64_t nsteps,
                   Counters cn, bool noalloc = false) {
-  if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
+  if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state (retire it)");
   if (!sl.pb[0][sl.cur[0]].base) throw Err(PIC_E_STATE, "no particles loaded");
   if (sl.ionizing) {   // births per step since the previous chunk picks the ranking method
     const uint64_t b = cn.stats[kStBirths];
@@ -421,6 +431,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
         J.ncell = 0;
         if (sp >= sl.d.nspecies || !sl.pb[sp][0].base) continue;
         J.ncell = N;
+        check_sort_target(sl, sp);
         PBuf& d = sl.pb[sp][1 - sl.cur[sp]];
         J.off = sl.off + (size_t)sp * (N + 1);
         J.dst = SortDst<T>{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell,
@@ -629,66 +640,72 @@ int pic_num_slots(pic_ctx c) { return c ? (int)c->slots.size() : 0; }
 int pic_particles_load(pic_ctx c, int slot, int species, int64_t n, const double* s, const double* v,
                        const uint32_t* w, const uint32_t* id) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (species < 0 || species >= sl.d.nspecies) throw Err(PIC_E_ARG, "bad species");
   if (n < 0 || n > 0x7FFFFFFF || (n > 0 && (!s || !v))) throw Err(PIC_E_ARG, "bad particle arrays");
   const int dim = sl.d.dim;
   for (int64_t i = 0; i < n * dim; ++i)
     if (!in_unit(s[i], sl.prec)) throw Err(PIC_E_ARG, "position outside [0,1) in the particle precision");
+  std::vector<uint32_t> ww(n), ii(n);
+  uint32_t mx = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    ww[i] = w ? w[i] : 65536u;
+    ii[i] = id ? id[i] : (uint32_t)i;
+    if (ww[i] == 0u) throw Err(PIC_E_ARG, "particle weight must be positive");
+    mx = std::max(mx, ii[i]);
+  }
   int64_t cap = sl.d.capacity[species] > 0 ? std::max<int64_t>(sl.d.capacity[species], n)
                                             : (sl.ionizing ? 3 * n + 4096 : n);
   cap = std::max<int64_t>(cap, 256);
   cap = (cap + 255) & ~(int64_t)255;
   Counters cn = read_counters(*c, sl);
-  if (cap > sl.cap[species] || !sl.pb[species][0].base) {
-    alloc_particles(sl, species, cap, 0);
-    alloc_particles(sl, species, cap, 1);
-    sl.cap[species] = cap;
-  }
-  sl.cur[species] = 0;
-  const PBuf& b = sl.pb[species][0];
-  const size_t e = sl.esz;
-  std::vector<char> tmp(e * (size_t)std::max<int64_t>(n, 1));
-  auto put = [&](void* dst, const double* src, int stride, int comp) {
-    if (e == 4) {
-      float* f = (float*)tmp.data();
-      for (int64_t i = 0; i < n; ++i) f[i] = (float)src[i * stride + comp];
+  // Room first: births staging, then the particle buffers, each whole or not
+  // done, so a failed allocation leaves the slot as it was.  A failure after
+  // the old particles are overwritten marks the slot failed.
+  const bool fresh = cap > sl.cap[species] || !sl.pb[species][0].base;
+  const int64_t cap0 = species == 0 && fresh ? cap : sl.cap[0];
+  if (sl.ionizing && sl.birth_cap < (uint64_t)cap0) alloc_births(*c, sl, cap0);
+  if (fresh) alloc_particles(sl, species, cap);
+  try {
+    sl.cur[species] = 0;
+    const PBuf& b = sl.pb[species][0];
+    const size_t e = sl.esz;
+    std::vector<char> tmp(e * (size_t)std::max<int64_t>(n, 1));
+    auto put = [&](void* dst, const double* src, int stride, int comp) {
+      if (e == 4) {
+        float* f = (float*)tmp.data();
+        for (int64_t i = 0; i < n; ++i) f[i] = (float)src[i * stride + comp];
+      } else {
+        double* f = (double*)tmp.data();
+        for (int64_t i = 0; i < n; ++i) f[i] = src[i * stride + comp];
+      }
+      hip_check(hipMemcpy(dst, tmp.data(), e * n, hipMemcpyHostToDevice), "load");
+    };
+    if (n) {
+      for (int k = 0; k < dim; ++k) put(b.s[k], s, dim, k);
+      for (int k = 0; k < 3; ++k) put(b.v[k], v, 3, k);
+      hip_check(hipMemcpy(b.w, ww.data(), 4 * n, hipMemcpyHostToDevice), "load");
+      hip_check(hipMemcpy(b.id, ii.data(), 4 * n, hipMemcpyHostToDevice), "load");
+      if (b.acc) hip_check(hipMemset(b.acc, 0, e * n), "load");   // no filtered acceleration before the start
+      sl.max_id_loaded[species] = mx + 1u;
     } else {
-      double* f = (double*)tmp.data();
-      for (int64_t i = 0; i < n; ++i) f[i] = src[i * stride + comp];
+      sl.max_id_loaded[species] = 0;
     }
-    hip_check(hipMemcpy(dst, tmp.data(), e * n, hipMemcpyHostToDevice), "load");
-  };
-  if (n) {
-    for (int k = 0; k < dim; ++k) put(b.s[k], s, dim, k);
-    for (int k = 0; k < 3; ++k) put(b.v[k], v, 3, k);
-    std::vector<uint32_t> ww(n), ii(n);
-    uint32_t mx = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      ww[i] = w ? w[i] : 65536u;
-      ii[i] = id ? id[i] : (uint32_t)i;
-      if (ww[i] == 0u) throw Err(PIC_E_ARG, "particle weight must be positive");
-      mx = std::max(mx, ii[i]);
+    cn.count[species] = (uint32_t)n;
+    cn.next_id = std::max(cn.next_id, std::max(sl.max_id_loaded[0], sl.max_id_loaded[1]));
+    write_counters(*c, sl, cn);
+    if (dim >= 2 && n) {
+      if (sl.prec == 32) hip_check(launch_relocate<float>(make_dev<float>(sl), species, c->stream, grid_for(n)), "relocate");
+      else hip_check(launch_relocate<double>(make_dev<double>(sl), species, c->stream, grid_for(n)), "relocate");
     }
-    hip_check(hipMemcpy(b.w, ww.data(), 4 * n, hipMemcpyHostToDevice), "load");
-    hip_check(hipMemcpy(b.id, ii.data(), 4 * n, hipMemcpyHostToDevice), "load");
-    if (b.acc) hip_check(hipMemset(b.acc, 0, e * n), "load");   // no filtered acceleration before the start
-    sl.max_id_loaded[species] = mx + 1u;
-  } else {
-    sl.max_id_loaded[species] = 0;
+    // start cell-ordered, so deposits and gathers of a workgroup cluster
+    if (n) sort_slot(*c, sl);
+    upload_dev(*c, sl);
+    c->sync();
+  } catch (...) {
+    sl.error_state = true;
+    throw;
   }
-  cn.count[species] = (uint32_t)n;
-  cn.next_id = std::max(cn.next_id, std::max(sl.max_id_loaded[0], sl.max_id_loaded[1]));
-  write_counters(*c, sl, cn);
-  if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) alloc_births(*c, sl, sl.cap[0]);
-  if (dim >= 2 && n) {
-    if (sl.prec == 32) hip_check(launch_relocate<float>(make_dev<float>(sl), species, c->stream, grid_for(n)), "relocate");
-    else hip_check(launch_relocate<double>(make_dev<double>(sl), species, c->stream, grid_for(n)), "relocate");
-  }
-  // start cell-ordered, so deposits and gathers of a workgroup cluster
-  if (n) sort_slot(*c, sl);
-  upload_dev(*c, sl);
-  c->sync();
   return PIC_OK;
   PIC_GUARD_END(c)
 }
@@ -718,7 +735,7 @@ uint32_t pic_next_id(pic_ctx c, int slot) {
 int pic_particles_read(pic_ctx c, int slot, int species, double* s, double* v, uint32_t* w, uint32_t* id,
                        uint32_t* cell) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (species < 0 || species >= sl.d.nspecies) throw Err(PIC_E_ARG, "bad species");
   Counters cn = read_counters(*c, sl);
   const size_t n = cn.count[species];
@@ -776,7 +793,7 @@ int64_t pic_nleaves(pic_ctx c, int slot) {
 
 int pic_leaves_read(pic_ctx c, int slot, uint32_t* keys, uint8_t* levels) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (sl.d.dim < 2) throw Err(PIC_E_ARG, "not a tree slot");
   c->sync();
   if (keys) hip_check(hipMemcpy(keys, sl.key, 4 * (size_t)sl.nleaves, hipMemcpyDeviceToHost), "read");
@@ -793,7 +810,7 @@ int64_t pic_nq(pic_ctx c, int slot) {
 
 int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (!data) throw Err(PIC_E_ARG, "null data");
   if (sl.d.dim == 1) {
     const bool ec = sl.d.field_scheme == PIC_FIELD_CIC_EC;
@@ -867,7 +884,7 @@ int pic_field_set(pic_ctx c, int slot, int kind, const double* data) {
 
 int pic_field_read(pic_ctx c, int slot, double* out) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   const bool cic = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR;
   const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1
                    : sl.d.dim == 3 ? (size_t)sl.nleaves * 24 : (size_t)sl.nleaves * (cic ? 2 : 8);
@@ -881,7 +898,7 @@ int pic_field_read(pic_ctx c, int slot, double* out) {
 
 int pic_leapfrog_start(pic_ctx c, int slot) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   const int g = grid_for(std::max(sl.cap[0], sl.cap[1]));
   if (sl.prec == 32) hip_check(launch_leapfrog_start<float>(make_dev<float>(sl), c->stream, g), "leapfrog");
   else hip_check(launch_leapfrog_start<double>(make_dev<double>(sl), c->stream, g), "leapfrog");
@@ -892,7 +909,7 @@ int pic_leapfrog_start(pic_ctx c, int slot) {
 
 int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   hip_check(hipMemsetAsync(sl.Q, 0, 32 * (size_t)sl.nq, c->stream), "memset");
   const int g = grid_for(std::max(sl.cap[0], sl.cap[1]));
   if (sl.prec == 32) hip_check(launch_deposit<float>(make_dev<float>(sl), c->stream, g), "deposit");
@@ -922,7 +939,7 @@ int pic_deposit(pic_ctx c, int slot, uint64_t* q_out, double* rho_out) {
 int pic_set_births_ranking(pic_ctx c, int slot, int method) {
   PIC_GUARD_BEGIN
   if (method < 0 || method > 2) throw Err(PIC_E_ARG, "births ranking method must be 0, 1 or 2");
-  get_slot(c, slot).births_method = method;
+  usable_slot(c, slot).births_method = method;
   return PIC_OK;
   PIC_GUARD_END(c)
 }
@@ -930,7 +947,7 @@ int pic_set_births_ranking(pic_ctx c, int slot, int method) {
 int pic_deposit_read(pic_ctx c, int slot, uint64_t* q_out) {
   PIC_GUARD_BEGIN
   if (!q_out) throw Err(PIC_E_ARG, "null output");
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   Counters cn = read_counters(*c, sl);
   const unsigned long long* latest = sl.Q + (size_t)((cn.step + 1u) & 1u) * 2u * sl.nq;
   hip_check(hipMemcpy(q_out, latest, 8 * 2 * (size_t)sl.nq, hipMemcpyDeviceToHost), "read");
@@ -941,7 +958,7 @@ int pic_deposit_read(pic_ctx c, int slot, uint64_t* q_out) {
 int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init, double rtol, int maxit,
                     double* phi_out, double* e_out, int* iters, double* relres) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (sl.d.dim == 1) {
     double* pl = (double*)c->stage(&phi_left, sizeof(double));
     upload_dev(*c, sl);
@@ -1045,7 +1062,7 @@ static void step_impl(pic_ctx c, const pic_step_args* a, pic_step_stats* stats, 
     if (s->d.field_scheme == PIC_FIELD_DIPIC && !a->solve_field)
       throw Err(PIC_E_ARG, "a direct implicit step solves the field (set solve_field and v_next)");
   for (Slot* s : sel)
-    if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state after a capacity overflow");
+    if (s->error_state) throw Err(PIC_E_STATE, "slot is in an error state (retire it)");
   bool any_ionizing = false;
   for (Slot* s : sel) any_ionizing = any_ionizing || s->ionizing;
   // without allocation the drive tables of a chunk sit in the workspace
@@ -1241,7 +1258,7 @@ int64_t pic_step_index(pic_ctx c, int slot) {
 
 int pic_set_slot_limit(pic_ctx c, int slot, int64_t max_bytes) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (max_bytes < 0) throw Err(PIC_E_ARG, "the limit must be >= 0");
   sl.byte_limit = (size_t)max_bytes;
   return PIC_OK;
@@ -1250,7 +1267,7 @@ int pic_set_slot_limit(pic_ctx c, int slot, int64_t max_bytes) {
 
 int pic_sort(pic_ctx c, int slot) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   sort_slot(*c, sl);
   c->sync();
   return PIC_OK;
@@ -1259,7 +1276,7 @@ int pic_sort(pic_ctx c, int slot) {
 
 int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   const int dim = sl.d.dim;
   if (dim < 2) throw Err(PIC_E_ARG, "not a tree slot");
   for (int64_t i = 0; i < dim * n; ++i)
@@ -1286,7 +1303,7 @@ int pic_locate(pic_ctx c, int slot, int64_t n, const double* s, uint32_t* leaf) 
 
 int pic_gather(pic_ctx c, int slot, int64_t n, const double* s, double* out) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   const int dim = sl.d.dim;
   if (n < 0 || (n > 0 && (!s || !out))) throw Err(PIC_E_ARG, "bad arguments");
   for (int64_t i = 0; i < n * dim; ++i)
@@ -1307,7 +1324,7 @@ int pic_gather(pic_ctx c, int slot, int64_t n, const double* s, double* out) {
 
 int pic_derived(pic_ctx c, int slot, int species, double* out) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (species < 0 || species > 1) throw Err(PIC_E_ARG, "bad species");
   if (sl.prec == 32) {
     SpeciesK<float> k = to_dev<float>(sl.hk[species]);
@@ -1385,7 +1402,7 @@ int64_t pic_slot_bytes(pic_ctx c, int slot) {
 
 int pic_adapt(pic_ctx c, int slot, const pic_adapt_args* a, pic_adapt_stats* s) {
   PIC_GUARD_BEGIN
-  Slot& sl = get_slot(c, slot);
+  Slot& sl = usable_slot(c, slot);
   if (!a) throw Err(PIC_E_ARG, "null adapt arguments");
   adapt_slot(*c, sl, a->n_lo, a->n_hi, s);
   return PIC_OK;

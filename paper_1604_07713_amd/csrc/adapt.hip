@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -50,6 +51,7 @@ struct Scratch {
 };
 
 TreeView view(const Slot& sl) {
+  if (launch_checks()) check_tables(sl);
   TreeView t;
   t.key = sl.key;
   t.lv = sl.lv;
@@ -127,6 +129,9 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   pic_adapt_stats st;
   std::memset(&st, 0, sizeof(st));
   const int ns = sl.d.nspecies;
+  // a capacity limit met while splitting or merging stops that part only;
+  // it is raised once the adaptation is complete
+  std::string deferred;
   relocate_all<T>(C, sl);
   Counts<T> counts(C, sl);
   // ---- coarsen and refine decided on the current tree ----
@@ -213,11 +218,23 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
     C.sync();
     const uint64_t tot = (uint64_t)h[0] + h[1];
     if (!tot) break;
-    if ((uint64_t)cn.next_id + 3ull * tot > 0xFFFFFFFFull) throw Err(PIC_E_CAPACITY, "particle ids exhausted by splitting");
-    for (int sp = 0; sp < ns; ++sp) {
-      const int64_t need = (int64_t)cn.count[sp] + 3 * (int64_t)h[sp];
-      if (need > sl.cap[sp]) grow(C, sl, sp, need + need / 2 + 1024, cn.count[sp]);
+    if ((uint64_t)cn.next_id + 3ull * tot > 0xFFFFFFFFull) {
+      deferred = "particle ids exhausted by splitting";
+      break;
     }
+    bool room = true;
+    for (int sp = 0; sp < ns && room; ++sp) {
+      const int64_t need = (int64_t)cn.count[sp] + 3 * (int64_t)h[sp];
+      if (need <= sl.cap[sp]) continue;
+      try {
+        grow(C, sl, sp, need + need / 2 + 1024, cn.count[sp]);
+      } catch (const Err& e) {   // the per-array limit: no split this round (growth leaves the slot whole)
+        if (e.code != PIC_E_CAPACITY) throw;
+        deferred = e.msg;
+        room = false;
+      }
+    }
+    if (!room) break;
     upload_dev(C, sl);
     uint32_t* prefix = S.get<uint32_t>(nw + 1);
     uint32_t* tmp = S.get<uint32_t>(scan_tmp_words(nw));
@@ -261,6 +278,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
       {
         const InstDev<T> I = make_dev<T>(sl);
         const int other = 1 - sl.cur[sp];
+        check_sort_target(sl, sp);
         PBuf& d = sl.pb[sp][other];
         SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell};
         hip_check(launch_sort<T>(I, sp, n, sl.off, sl.scan_tmp, dst, grid_for(sl.cap[sp]), C.stream), "sort");
@@ -274,7 +292,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
       const uint32_t fl = read1(C, flags);
       const uint32_t pairs = read1(C, npairs);
       st.merge_energy_change += read1(C, energy);
-      if (fl) throw Err(PIC_E_CAPACITY, "a leaf holds more particles than a merge round can sort");
+      if (fl) deferred = "a leaf holds more particles than a merge round can sort";   // such leaves are left as they are
       st.merged_pairs += pairs;
     }
   }
@@ -285,6 +303,7 @@ void adapt_impl(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   C.sync();
   st.nleaves = sl.nleaves;
   if (out) *out = st;
+  if (!deferred.empty()) throw Err(PIC_E_CAPACITY, deferred);
 }
 
 }  // namespace
@@ -293,8 +312,30 @@ void adapt_slot(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out) {
   if (sl.d.dim != 2) throw Err(PIC_E_ARG, "adapt needs a quadtree slot");
   if (sl.error_state) throw Err(PIC_E_STATE, "slot is in an error state");
   if (n_lo < 0 || n_hi < 1 || n_lo > n_hi) throw Err(PIC_E_ARG, "need 0 <= n_lo <= n_hi");
-  if (sl.prec == 32) adapt_impl<float>(C, sl, n_lo, n_hi, out);
-  else adapt_impl<double>(C, sl, n_lo, n_hi, out);
+  // An adaptation that fails part-way (device memory, a runtime error) leaves
+  // the tree and the particles in between two states: the slot is then
+  // marked failed, and every later call on it but pic_retire and the counter
+  // reads returns PIC_E_STATE.  A capacity limit leaves a complete
+  // adaptation (particles not split, or an over-full leaf not merged).
+  try {
+    if (sl.prec == 32) adapt_impl<float>(C, sl, n_lo, n_hi, out);
+    else adapt_impl<double>(C, sl, n_lo, n_hi, out);
+  } catch (const Err& e) {
+    if (e.code != PIC_E_CAPACITY) {
+      sl.error_state = true;
+      throw;
+    }
+    try {
+      upload_dev(C, sl);
+      C.sync();
+    } catch (...) {
+      sl.error_state = true;
+    }
+    throw;
+  } catch (...) {
+    sl.error_state = true;
+    throw;
+  }
   upload_dev(C, sl);
   C.sync();
 }

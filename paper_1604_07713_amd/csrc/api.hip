@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -534,7 +535,10 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   double* ophi = sl.phi64;
   const int olut_level = sl.lut_level;
   const bool carry = okey && olv && olut && ophi && sl.nleaves > 0;
+  // (a failed allocation below leaves released tables null; its caller marks
+  // the slot failed)
   sl.release(sl.xy);
+  sl.xy = nullptr;
   sl.key = key;
   sl.lv = lv;
   sl.nleaves = n;
@@ -544,6 +548,7 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   // binary search inside the table cell
   sl.lut_level = std::min(sl.d.max_level, kLutMaxLevel);
   sl.lut_direct = maxlv <= sl.lut_level;
+  sl.lut = nullptr;
   sl.lut = (uint32_t*)sl.alloc(4 * ((size_t(1) << (2 * sl.lut_level)) + 1));
   hip_check(launch_leaf_xy(sl.key, sl.lv, sl.nleaves, sl.xy, C.stream), "leaf_xy");
   hip_check(launch_build_lut(sl.key, sl.lv, sl.nleaves, sl.lut, sl.lut_level, C.stream), "build_lut");
@@ -552,6 +557,10 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
                   (void*)sl.st.nbr, (void*)sl.st.code, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws,
                   sl.cellE})
     sl.release(p);
+  sl.E = nullptr;
+  sl.e64 = sl.cphi = sl.grad = nullptr;
+  sl.Q = nullptr;
+  sl.off = sl.scan_tmp = nullptr;
   sl.cellE = nullptr;
   sl.st = Stencil2D{nullptr, nullptr, nullptr, nullptr};
   sl.cg_ws = nullptr;
@@ -561,6 +570,7 @@ void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n,
   sl.e64 = (double*)sl.alloc(8 * 8 * (size_t)sl.nleaves);
   sl.cphi = (double*)sl.alloc(8 * 4 * (size_t)sl.nleaves);
   sl.grad = (double*)sl.alloc(8 * 8 * (size_t)sl.nleaves);
+  sl.phi64 = nullptr;   // the old cell potential is held in ophi until it is carried over
   sl.phi64 = (double*)sl.alloc(8 * (size_t)sl.nleaves);
   sl.Q = (unsigned long long*)sl.alloc(8 * 4 * (size_t)sl.nq);
   // one offset array per species (the batched sort takes both at once),
@@ -838,11 +848,22 @@ PBuf new_pbuf(Slot& sl, int64_t cap) {
   return b;
 }
 
-void alloc_particles(Slot& sl, int sp, int64_t cap, int which) {
-  PBuf nb = new_pbuf(sl, cap);
-  PBuf& b = sl.pb[sp][which];
-  if (b.base) sl.release(b.base);
-  b = nb;
+// Both particle buffers (live and sort target) of a species for 'cap'
+// particles.  The new blocks are allocated before the old ones are given
+// back, so a failed allocation leaves the slot as it was.
+void alloc_particles(Slot& sl, int sp, int64_t cap) {
+  PBuf b0 = new_pbuf(sl, cap);
+  PBuf b1;
+  try {
+    b1 = new_pbuf(sl, cap);
+  } catch (...) {
+    sl.release(b0.base);
+    throw;
+  }
+  for (int k = 0; k < 2; ++k) sl.release(sl.pb[sp][k].base);
+  sl.pb[sp][0] = b0;
+  sl.pb[sp][1] = b1;
+  sl.cap[sp] = cap;
 }
 
 size_t births_bytes(const Slot& sl, int64_t cap) {
@@ -877,6 +898,115 @@ void alloc_births(Ctx& C, Slot& sl, int64_t cap) {
   sl.br_bin_off = (uint32_t*)carve(4 * (kBirthBins + 1));
   sl.br_cursor = (uint32_t*)carve(4 * kBirthBins);
   sl.birth_cap = (uint32_t)cap;
+}
+
+// ---------------------------------------------------------------------------
+// launch checks (PIC_CHECK_LAUNCHES=1 in the environment): every kernel-side
+// view of a slot is checked on the host, before it is used, against the
+// slot's live blocks: each array a kernel addresses lies inside one live
+// block with the extent its count implies, and particle arrays stay below
+// 4 GiB (the kernels' 32-bit byte offsets).  A failed check is PIC_E_STATE,
+// raised instead of the launch.
+// ---------------------------------------------------------------------------
+bool launch_checks() {
+  static const bool on = [] {
+    const char* e = std::getenv("PIC_CHECK_LAUNCHES");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
+}
+
+void check_block(const Slot& sl, const void* p, size_t bytes, const char* what) {
+  if (!bytes) return;
+  if (!p) throw Err(PIC_E_STATE, std::string("launch check: ") + what + " is null");
+  const char* q = (const char*)p;
+  for (size_t i = 0; i < sl.allocs.size(); ++i) {
+    const char* a = (const char*)sl.allocs[i];
+    if (q >= a && q + bytes <= a + sl.alloc_bytes[i]) return;
+  }
+  throw Err(PIC_E_STATE, std::string("launch check: ") + what + " (" + std::to_string(bytes) +
+                             " bytes) is not inside a live block of the slot");
+}
+
+// The particle arrays of one buffer for 'cap' particles.
+void check_pbuf(const Slot& sl, const PBuf& b, int64_t cap) {
+  const size_t c = (size_t)cap, e = sl.esz;
+  if ((uint64_t)c * e >= (1ull << 32)) throw Err(PIC_E_STATE, "launch check: a particle array reaches 4 GiB");
+  for (int k = 0; k < sl.d.dim; ++k) check_block(sl, b.s[k], c * e, "positions");
+  for (int k = 0; k < 3; ++k) check_block(sl, b.v[k], c * e, "velocities");
+  check_block(sl, b.w, 4 * c, "weights");
+  check_block(sl, b.id, 4 * c, "ids");
+  if (sl.d.dim >= 2) check_block(sl, b.cell, 4 * c, "leaf indices");
+  if (sl.d.field_scheme == PIC_FIELD_DIPIC) check_block(sl, b.acc, c * e, "filtered accelerations");
+}
+
+// Mesh, field and deposit tables.
+void check_tables(const Slot& sl) {
+  const size_t e = sl.esz, L = sl.nleaves, dim = (size_t)sl.d.dim;
+  const size_t n1 = (size_t)sl.d.ncells + 1;
+  check_block(sl, sl.ctr, sizeof(Counters), "counters");
+  check_block(sl, sl.part, 8 * (size_t)kNStat * kMaxStepGrid, "stats rows");
+  if (sl.nq != (dim == 1 ? n1 : L)) throw Err(PIC_E_STATE, "launch check: deposit length does not match the mesh");
+  check_block(sl, sl.Q, 32 * (size_t)sl.nq, "deposit");
+  if (dim == 1) {
+    check_block(sl, sl.E, n1 * e, "field table");
+    check_block(sl, sl.phi64, 8 * n1, "potential");
+    check_block(sl, sl.e64, 8 * n1, "FP64 field");
+    if (sl.d.field_scheme == PIC_FIELD_DIPIC) {
+      check_block(sl, sl.Qp, 16 * (size_t)sl.nq, "predicted deposit");
+      check_block(sl, sl.dws, 24 * (size_t)sl.nq, "implicit solve scratch");
+    }
+  } else {
+    const size_t corners = dim == 2 ? 4 : 8, lut = (size_t(1) << (dim * (size_t)sl.lut_level)) + 1;
+    if (L == 0) throw Err(PIC_E_STATE, "launch check: empty tree");
+    check_block(sl, sl.key, 4 * L, "leaf keys");
+    check_block(sl, sl.lv, L, "leaf levels");
+    check_block(sl, sl.xy, 4 * L, "leaf corners");
+    check_block(sl, sl.lut, 4 * lut, "point-location table");
+    check_block(sl, sl.E, corners * dim * L * e, "field table");
+    check_block(sl, sl.e64, 8 * corners * dim * L, "FP64 field");
+    check_block(sl, sl.cphi, 8 * corners * L, "corner potential");
+    check_block(sl, sl.grad, 8 * corners * dim * L, "corner gradients");
+    check_block(sl, sl.phi64, 8 * L, "cell potential");
+    check_block(sl, sl.off, 4 * 2 * (L + 1), "leaf offsets");
+    if (sl.d.field_scheme == PIC_FIELD_CIC_AMR) check_block(sl, sl.cellE, 2 * L * e, "cell-centred field");
+  }
+}
+
+template <class T>
+void check_view(const Slot& sl, const InstDev<T>& I) {
+  check_tables(sl);
+  for (int sp = 0; sp < sl.d.nspecies; ++sp) {
+    const PBuf& b = sl.pb[sp][sl.cur[sp]];
+    if (!b.base) continue;   // nothing loaded: the kernels see no particles of this species
+    if ((void*)I.s[sp][0] != b.s[0] || I.cap[sp] != (uint32_t)sl.cap[sp])
+      throw Err(PIC_E_STATE, "launch check: particle view does not match the live buffer");
+    check_pbuf(sl, b, sl.cap[sp]);
+  }
+  if (I.v_len) check_block(sl, I.v_table, 8 * (size_t)I.v_len, "drive table");
+  if (sl.ionizing && I.birth_cap) {
+    const size_t c = I.birth_cap, e = sizeof(T);
+    if ((uint64_t)c * e >= (1ull << 32)) throw Err(PIC_E_STATE, "launch check: births staging reaches 4 GiB");
+    for (const void* p : {(const void*)I.br.parent, (const void*)I.br.rank, (const void*)I.br.cell,
+                          (const void*)I.br.w, (const void*)I.br.sorted})
+      check_block(sl, p, 4 * c, "births staging");
+    for (int k = 0; k < std::max(sl.d.dim, 2); ++k) check_block(sl, I.br.s[k], c * e, "births staging");
+    for (int k = 0; k < 3; ++k) {
+      check_block(sl, I.br.ve[k], c * e, "births staging");
+      check_block(sl, I.br.vi[k], c * e, "births staging");
+    }
+    check_block(sl, I.br.bin, 4 * (size_t)kBirthBins, "births bins");
+    check_block(sl, I.br.cursor, 4 * (size_t)kBirthBins, "births bins");
+    check_block(sl, I.br.bin_off, 4 * ((size_t)kBirthBins + 1), "births bins");
+  }
+}
+
+// The sort target of a species and the per-cell offsets of the sort.
+void check_sort_target(const Slot& sl, int sp) {
+  if (!launch_checks()) return;
+  check_pbuf(sl, sl.pb[sp][1 - sl.cur[sp]], sl.cap[sp]);
+  const size_t n = sl.d.dim == 1 ? (size_t)sl.d.ncells + 1 : (size_t)sl.nleaves + 1;
+  check_block(sl, sl.off, 4 * 2 * n, "cell offsets");
 }
 
 template <class T>
@@ -946,6 +1076,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.births_binned = slot_births_binned(sl) ? 1 : 0;
   I.phi64 = sl.phi64;
   I.e64 = sl.e64;
+  if (launch_checks()) check_view(sl, I);
   return I;
 }
 
@@ -1036,28 +1167,41 @@ void ensure_capacity(Ctx& C, Slot& sl, const Counters& c, int64_t steps_ahead) {
     throw Err(PIC_E_CAPACITY, "particle ids exhausted: the next step could need ids beyond 2^32 - 1");
   bool changed = false;
   const int64_t arr_limit = std::min<int64_t>((int64_t)(((1ull << 32) - 1) / sl.esz), 0x7FFFFFFF);
-  for (int sp = 0; sp < sl.d.nspecies; ++sp) {
-    if (need[sp] <= sl.cap[sp]) continue;
-    if (need[sp] > arr_limit) throw Err(PIC_E_CAPACITY, "particle capacity exceeds the per-array limit of 4 GiB");
-    int64_t want = std::max(need[sp], std::min(2 * need[sp] + 1024, arr_limit));
-    if (sl.byte_limit) {
-      // bytes after the growth: the two particle buffers of this species are
-      // replaced (births staging follows species 0)
-      auto after = [&](int64_t cap) {
-        size_t b = sl.bytes_held - 2 * pbuf_bytes(sl, sl.cap[sp]) + 2 * pbuf_bytes(sl, cap);
-        if (sp == 0 && sl.ionizing) b = b - (sl.birth_base ? births_bytes(sl, sl.birth_cap) : 0) + births_bytes(sl, cap);
-        return b;
-      };
-      if (after(want) > sl.byte_limit) want = need[sp];
-      if (after(want) > sl.byte_limit)
-        throw Err(PIC_E_CAPACITY, "the slot's memory limit leaves no room for the next step");
+  // each growth is whole or not done; if a later one fails, the device view
+  // is brought up to the earlier ones before the error goes out
+  try {
+    for (int sp = 0; sp < sl.d.nspecies; ++sp) {
+      if (need[sp] <= sl.cap[sp]) continue;
+      if (need[sp] > arr_limit) throw Err(PIC_E_CAPACITY, "particle capacity exceeds the per-array limit of 4 GiB");
+      int64_t want = std::max(need[sp], std::min(2 * need[sp] + 1024, arr_limit));
+      if (sl.byte_limit) {
+        // bytes after the growth: the two particle buffers of this species are
+        // replaced (births staging follows species 0)
+        auto after = [&](int64_t cap) {
+          size_t b = sl.bytes_held - 2 * pbuf_bytes(sl, sl.cap[sp]) + 2 * pbuf_bytes(sl, cap);
+          if (sp == 0 && sl.ionizing) b = b - (sl.birth_base ? births_bytes(sl, sl.birth_cap) : 0) + births_bytes(sl, cap);
+          return b;
+        };
+        if (after(want) > sl.byte_limit) want = need[sp];
+        if (after(want) > sl.byte_limit)
+          throw Err(PIC_E_CAPACITY, "the slot's memory limit leaves no room for the next step");
+      }
+      grow(C, sl, sp, want, c.count[sp]);
+      changed = true;
     }
-    grow(C, sl, sp, want, c.count[sp]);
-    changed = true;
-  }
-  if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) {
-    alloc_births(C, sl, sl.cap[0]);
-    changed = true;
+    if (sl.ionizing && sl.birth_cap < (uint64_t)sl.cap[0]) {
+      alloc_births(C, sl, sl.cap[0]);
+      changed = true;
+    }
+  } catch (...) {
+    if (changed) {
+      try {
+        upload_dev(C, sl);
+      } catch (...) {
+        sl.error_state = true;
+      }
+    }
+    throw;
   }
   if (changed) upload_dev(C, sl);
 }
@@ -1075,6 +1219,7 @@ void check_capacity(const Slot& sl, const Counters& c) {
 template <class T>
 void sort_species(Ctx& C, Slot& sl, int sp) {
   InstDev<T> I = make_dev<T>(sl);
+  check_sort_target(sl, sp);
   const int other = 1 - sl.cur[sp];
   PBuf& d = sl.pb[sp][other];
   SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell, (T*)d.s[2],

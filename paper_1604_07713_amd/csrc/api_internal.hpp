@@ -199,11 +199,14 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d);
 void set_mesh2d(Ctx& C, Slot& sl, const std::vector<HostLeaf>& L);
 void set_mesh2d_device(Ctx& C, Slot& sl, uint32_t* key, uint8_t* lv, uint32_t n, int maxlv);
 void adapt_slot(Ctx& C, Slot& sl, int n_lo, int n_hi, pic_adapt_stats* out);
-void alloc_particles(Slot& sl, int sp, int64_t cap, int which);
+void alloc_particles(Slot& sl, int sp, int64_t cap);
 size_t pbuf_bytes(const Slot& sl, int64_t cap);
 size_t births_bytes(const Slot& sl, int64_t cap);
 void alloc_births(Ctx& C, Slot& sl, int64_t cap);
-template <class T> InstDev<T> make_dev(const Slot& sl);
+template <class T> InstDev<T> make_dev(const Slot& sl);   // checked when launch checks are on
+bool launch_checks();                        // PIC_CHECK_LAUNCHES set in the environment
+void check_tables(const Slot& sl);           // mesh, field and deposit tables against the slot's blocks
+void check_sort_target(const Slot& sl, int sp);   // no-op unless launch checks are on
 void upload_dev(Ctx& C, Slot& sl);
 Counters read_counters(Ctx& C, Slot& sl);
 std::vector<Counters> read_counters_many(Ctx& C, const std::vector<Slot*>& sel);

@@ -4,6 +4,9 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# every kernel-side view of a slot is checked against the slot's live device
+# blocks before it is used (a failed check is an error, not a launch)
+os.environ.setdefault("PIC_CHECK_LAUNCHES", "1")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
