@@ -424,7 +424,7 @@ void batched_steps(Ctx& C, std::vector<Slot*>& sel, const pic_step_args* a, int6
     uint32_t max_ncell = 0;
     for (int j = 0; j < nsel; ++j) {
       Slot& sl = *sel[j];
-      const uint32_t N = dim2 ? sl.nq : (uint32_t)sl.d.ncells;
+      const uint32_t N = dim2 ? sl.nq : sort_bins_1d(sl);
       for (int sp = 0; sp < 2; ++sp) {
         SortJob<T>& J = jobs[2 * (size_t)j + sp];
         J.off = nullptr;   // no job for an absent species (every sort kernel skips it)

@@ -787,6 +787,7 @@ void build_slot(Ctx& C, Slot& sl, const pic_instance_desc& d) {
   if (d.dim == 1) {
     const int N = d.ncells;
     sl.nq = N + 1;
+    sl.sort_shift = sort_shift_1d(N);
     sl.E = sl.alloc(sl.esz * (N + 1));
     sl.e64 = (double*)sl.alloc(8 * (N + 1));
     sl.phi64 = (double*)sl.alloc(8 * (N + 1));
@@ -1068,6 +1069,7 @@ InstDev<T> make_dev(const Slot& sl) {
   I.cell_e = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_CIC_EC ? 1 : 0;
   I.cic_amr = sl.d.dim == 2 && sl.d.field_scheme == PIC_FIELD_CIC_AMR ? 1 : 0;
   I.dipic = sl.d.dim == 1 && sl.d.field_scheme == PIC_FIELD_DIPIC ? 1 : 0;
+  I.sort_shift = sl.sort_shift;
   I.chi[0] = sl.chi[0];
   I.chi[1] = sl.chi[1];
   I.Qp = sl.Qp;
@@ -1224,7 +1226,7 @@ void sort_species(Ctx& C, Slot& sl, int sp) {
   PBuf& d = sl.pb[sp][other];
   SortDst<T> dst{(T*)d.s[0], (T*)d.s[1], (T*)d.v[0], (T*)d.v[1], (T*)d.v[2], d.w, d.id, d.cell, (T*)d.s[2],
                  (T*)d.acc};
-  const uint32_t ncell = sl.d.dim == 1 ? (uint32_t)sl.d.ncells : sl.nleaves;
+  const uint32_t ncell = sl.d.dim == 1 ? sort_bins_1d(sl) : sl.nleaves;
   hip_check(launch_sort<T>(I, sp, ncell, sl.off, sl.scan_tmp, dst, grid_for(sl.cap[sp]), C.stream), "sort");
   sl.cur[sp] = other;
 }

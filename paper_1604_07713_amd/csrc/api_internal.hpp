@@ -82,6 +82,7 @@ struct Slot {
   double kappa[2] = {0, 0};
   double inv2dx = 0;
   double chi[2] = {0, 0};                  // direct implicit: charge sum -> susceptibility per species
+  uint32_t sort_shift = 0;                 // 1D: order kept by bins of 2^sort_shift cells (sort_bins_1d bins)
   unsigned long long* Qp = nullptr;        // direct implicit: charge at the predicted positions [2][N+1]
   double* dws = nullptr;                   // direct implicit solve scratch [3][N+1]
   // particles: [species][buffer]; cur = live buffer, the other is the sort target
@@ -137,6 +138,22 @@ struct Slot {
   void release(void* p);
   void release_all();
 };
+
+// 1D order upkeep sorts by bins of consecutive cells, at most kSortBins1D of
+// them: a bin keeps a workgroup's particles within the step kernel's deposit
+// window, and a sort pass over 1024 particles then writes runs of about 16
+// particles per bin instead of one particle per cell (the electrons of a
+// discharge mix over the whole mesh between sorts).
+#ifndef PIC_SORT_BINS_1D
+#define PIC_SORT_BINS_1D 64
+#endif
+constexpr uint32_t kSortBins1D = PIC_SORT_BINS_1D;
+inline uint32_t sort_shift_1d(int ncells) {
+  uint32_t s = 0;
+  while ((((uint32_t)ncells - 1u) >> s) + 1u > kSortBins1D) ++s;
+  return s;
+}
+inline uint32_t sort_bins_1d(const Slot& sl) { return (((uint32_t)sl.d.ncells - 1u) >> sl.sort_shift) + 1u; }
 
 // Births of the slot ranked through id bins (else pairwise): by request, or
 // once its births per step are many.

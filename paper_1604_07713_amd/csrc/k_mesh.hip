@@ -119,8 +119,9 @@ hipError_t launch_build_lut3(const uint32_t* key, uint32_t n, uint32_t* lut, int
 }
 
 // ---------------------------------------------------------------------------
-// Counting sort of one species by cell (1D: floor(s N); 2D: leaf), dropping
-// holes.  hist/off has ncell + 1 entries.
+// Counting sort of one species by cell (1D: the bin floor(s N) >> sort_shift
+// of consecutive cells; 2D and 3D: the leaf), dropping holes.  hist/off has
+// ncell + 1 entries (1D: one per bin).
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint32_t i) {
@@ -128,7 +129,8 @@ __device__ __forceinline__ uint32_t sort_cell(const InstDev<T>& I, int sp, uint3
   const T g = G(I.s[sp][0])[i] * (T)I.N;
   int ic = (int)floor(g);
   if (ic > I.N - 1) ic = I.N - 1;
-  return (uint32_t)ic;
+  if (ic < 0) ic = 0;
+  return (uint32_t)ic >> I.sort_shift;
 }
 
 constexpr uint32_t kSortWin = 1024;
@@ -226,7 +228,10 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n) { s
 template <class T>
 __device__ void sort_scatter_range(const InstDev<T>& I, int sp, uint32_t* off, uint32_t begin, uint32_t end,
                                    const SortDst<T>& d) {
-  constexpr uint32_t kSub = 4;   // particles per lane per window pass
+#ifndef PIC_SORT_SUB
+#define PIC_SORT_SUB 4
+#endif
+  constexpr uint32_t kSub = PIC_SORT_SUB;   // particles per lane per window pass
   __shared__ uint32_t lcnt[kSortWin];
   __shared__ uint32_t gbase[kSortWin];
   __shared__ uint32_t base_s;

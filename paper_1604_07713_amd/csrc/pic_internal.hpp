@@ -92,6 +92,7 @@ struct InstDev {
   double kappa[2];               // charge-sum -> Poisson right-hand side factor per species
   double inv2dx;                 // 1D: 1 / (2 dx)
   int dipic;                     // 1D direct implicit step (D1 scheme)
+  uint32_t sort_shift;           // 1D: particles are kept ordered by bins of 2^sort_shift cells
   double chi[2];                 // direct implicit: charge-sum -> susceptibility factor per species
   unsigned long long* Qp;        // direct implicit: charge at the predicted positions [2][N+1]
   double* dws;                   // direct implicit solve scratch [3][N+1] (meshes beyond one LDS chunk)
