@@ -223,7 +223,7 @@ typedef struct {
   const double* v_next; /* ... phi(0) = v_next[k*ninst_sel + j] for step k, slot j */
                         /* (a direct implicit slot solves within the step, at the */
                         /* same drive value, and needs both)                        */
-  int sort_every;       /* re-sort particles by cell every n steps (0 = never)    */
+  int sort_every;       /* re-sort particles by cell every n steps (0 = never; 1D: by bins of cells) */
   int batched;          /* 0: launches per slot; > 0: one persistent launch over   */
                         /* all selected slots of one dimension and precision, with */
                         /* this many particles per work item (1 = 4096); quadtree  */
@@ -439,8 +439,9 @@ int pic_field_read(pic_ctx c, int slot, double* out);
 /* the field E the step's gather gives at n points s[n*dim] (normalised, in
  * [0,1)): out[n*dim], V/m (Sec. 3 / 3.1 gather); PIC_E_ARG for a point outside */
 int pic_gather(pic_ctx c, int slot, int64_t n, const double* s, double* out);
-/* drop holes and order the particles by cell (Sec. 3.1 cell-based lists;
- * the results of later steps do not depend on it) */
+/* drop holes and order the particles by cell (Sec. 3.1 cell-based lists; in
+ * 1D by bins of consecutive cells, at most 64 bins; the results of later
+ * steps do not depend on it) */
 int pic_sort(pic_ctx c, int slot);
 /* leaf[n] containing each point s[n*2] in [0,1)^2 (Sec. 3.1 location on the
  * tree); PIC_E_ARG for a point outside */
