@@ -528,40 +528,28 @@ constexpr uint32_t q_cap() {
   return kQDrain + (uint32_t)K * kBlock;
 }
 
+// An entry holds the process, the particle's index and its draws so far;
+// the drain reads the particle's state back from its arrays, where the
+// batch has stored it (its position, velocity after the push, weight, id
+// and leaf), so the queue stays small enough in LDS for one more workgroup
+// per compute unit.
 template <class T, int DIM>
 struct CollQueue {
   uint32_t* n;
-  uint32_t *kind, *i, *id, *r1, *wa, *wb, *w, *leaf;
-  T *s0, *s1, *v0, *v1, *v2;
+  uint32_t *kind, *i, *r1, *wa, *wb;
 };
 template <class T, int DIM, int K>
 __device__ __forceinline__ CollQueue<T, DIM> coll_queue() {
   constexpr uint32_t kQCap = q_cap<K>();
   __shared__ uint32_t qn;
-  __shared__ uint32_t qkind[kQCap], qi[kQCap], qid[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap], qw[kQCap];
-  __shared__ T qs0[kQCap], qv0[kQCap], qv1[kQCap], qv2[kQCap];
+  __shared__ uint32_t qkind[kQCap], qi[kQCap], qr1[kQCap], qwa[kQCap], qwb[kQCap];
   CollQueue<T, DIM> q;
   q.n = &qn;
   q.kind = qkind;
   q.i = qi;
-  q.id = qid;
   q.r1 = qr1;
   q.wa = qwa;
   q.wb = qwb;
-  q.w = qw;
-  q.s0 = qs0;
-  q.v0 = qv0;
-  q.v1 = qv1;
-  q.v2 = qv2;
-  if constexpr (DIM == 2) {
-    __shared__ uint32_t qleaf[kQCap];
-    __shared__ T qs1[kQCap];
-    q.leaf = qleaf;
-    q.s1 = qs1;
-  } else {
-    q.leaf = nullptr;
-    q.s1 = nullptr;
-  }
   return q;
 }
 
@@ -582,14 +570,14 @@ __device__ __forceinline__ void drain_queue(const InstDev<T>& I, const HotK<T>& 
     T s0 = (T)0, s1 = (T)0;
     if (t < n) {
       const uint32_t kind = Q.kind[t], i = Q.i[t];
-      id = Q.id[t];
-      w = Q.w[t];
-      s0 = Q.s0[t];
+      id = *at(P.id, i);
+      w = *at(P.w, i);
+      s0 = *at(P.s0, i);
       if constexpr (DIM == 2) {
-        s1 = Q.s1[t];
-        leaf = Q.leaf[t];
+        s1 = *at(P.s1, i);
+        leaf = *at(P.cell, i);
       }
-      T vx = Q.v0[t], vy = Q.v1[t], vz = Q.v2[t];
+      T vx = *at(P.v0, i), vy = *at(P.v1, i), vz = *at(P.v2, i);
       WordStream ws(H.key0, H.key1, id, step, Q.wa[t], Q.wb[t]);
       if (kind == kCollIonize) {
         collide_ionize<T>(H.k, ws, vx, vy, vz, rec);
@@ -748,19 +736,9 @@ __device__ __forceinline__ void process_batch(const InstDev<T>& I, const HotK<T>
         const uint32_t t = base + (uint32_t)__popcll(bm & (lanes_le(lane) >> 1));
         Q.kind[t] = kind;
         Q.i[t] = i;
-        Q.id[t] = p[j].id;
         Q.r1[t] = ci[j].r1;
         Q.wa[t] = ci[j].wa;
         Q.wb[t] = ci[j].wb;
-        Q.w[t] = p[j].w;
-        Q.s0[t] = p[j].s0;
-        Q.v0[t] = p[j].v0;
-        Q.v1[t] = vy;
-        Q.v2[t] = vz;
-        if constexpr (DIM == 2) {
-          Q.s1[t] = p[j].s1;
-          Q.leaf[t] = leaf[j];
-        }
       }
     }
   }
@@ -1052,8 +1030,16 @@ __global__ __launch_bounds__(kBlock) PIC_STEP_ATTR void k_step(InstDev<T> I, int
 
 // Batched 1D launch: a persistent grid walks a list of (instance, species,
 // range) work items; per-instance constants come from the descriptor table.
+#ifndef PIC_BATCHED_WAVES
+#define PIC_BATCHED_WAVES 0
+#endif
+#if PIC_BATCHED_WAVES > 0
+#define PIC_BATCHED_ATTR __attribute__((amdgpu_waves_per_eu(PIC_BATCHED_WAVES)))
+#else
+#define PIC_BATCHED_ATTR
+#endif
 template <class T, bool MCC>
-__global__ __launch_bounds__(kBlock) void k_step1d_batched(const InstDev<T>* __restrict__ insts,
+__global__ __launch_bounds__(kBlock) PIC_BATCHED_ATTR void k_step1d_batched(const InstDev<T>* __restrict__ insts,
                                                            const WorkItem* __restrict__ items, uint32_t nitems,
                                                            unsigned long long* bpart) {
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
