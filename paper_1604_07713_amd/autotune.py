@@ -44,7 +44,7 @@ def save_cache(c):
         pass
 
 
-def tune(make_ctx, descs, v_next=None, steps=8, tiles=TILES, grids=GRIDS, use_cache=True, passes=3,
+def tune(make_ctx, descs, v_next=None, steps=16, tiles=TILES, grids=GRIDS, use_cache=True, passes=3,
          nparticles=None):
     """make_ctx(): a fresh, loaded and started context of the ensemble.
     v_next: [steps][nslots] drive table of 1D slots (the field is solved on
