@@ -365,10 +365,13 @@ def ensemble_bench(nsteps, ninst=96, tune=True,
         if graph_rate is not None:
             out[mode]["graph_replay_updates_per_s"] = graph_rate
         if batched and prec == 32:
-            # the persistent particle-loop launch: 24 B per update + 16 B per collision
+            # the particle loop of a step (the persistent step launch and the
+            # births kernels after it, timed together): 24 B per update + 16 B
+            # per collision
             per = (BYTES_PER_UPDATE_1D_MCC * upd_t + BYTES_PER_COLLISION_1D * coll_t) / nsteps
             out[mode]["roofline"] = roofline(per, kern / nsteps)
-            out[mode]["roofline"]["per"] = "k_step1d_batched<float,true> launch, 24 B per update + 16 B per collision"
+            out[mode]["roofline"]["per"] = ("batched particle loop of a step (k_step1d_batched<float,true> + births kernels), "
+                                            "24 B per update + 16 B per collision")
         if tuned:
             out[mode]["tile"] = tuned["tile"]
             out[mode]["grid"] = tuned["grid"]
