@@ -14,14 +14,16 @@ rather than a launch):
     reads and pic_retire returns PIC_E_STATE, and the context's other slot
     goes on equal to a context that never failed;
   - a particle load: PIC_E_NOMEM leaves the slot as it was, and loading again
-    gives the state of a load that never failed."""
+    gives the state of a load that never failed;
+  - a batched step of three ionizing 1D discharges: every slot stays at its
+    last committed step, and each slot's retry ends bit-identical."""
 import numpy as np
 import pytest
 import torch
 
 from paper_1604_07713_amd import binding as B
 from paper_1604_07713_amd import inputs as I
-from tests.test_gpu_contract import TIGHT_5000, fast_ionizing, same_state
+from tests.test_gpu_contract import TIGHT_5000, TIGHT_8192, fast_ionizing, same_state
 
 pytestmark = pytest.mark.gpu
 
@@ -169,5 +171,49 @@ def test_load_failures_leave_the_slot_as_it_was():
                 g.load(0, sp, s, v, w, ids)       # again, now granted
         assert failed, k
         same_state(ref, g, what=f"load failed at request {k} of {sites}")
+        g.close()
+    ref.close()
+
+
+def ionizing_ensemble(alloc):
+    descs = [dict(fast_ionizing(I.ccp_desc(ncells=128, ppc=64, precision=32, instance_key=k, voltage=450.0 + 50 * k)),
+                  capacity=TIGHT_8192) for k in range(3)]
+    g = B.Context(descs, allocator=alloc)
+    for j, d in enumerate(descs):
+        for sp, (s, v, w, ids) in enumerate(I.ccp_particles(d)):
+            g.load(j, sp, s, v, w, ids)
+        g.deposit(j)
+        g.field_solve_1d(j, float(I.drive_voltage(d, 0)))
+        g.leapfrog_start(j)
+    vn = np.stack([I.drive_voltage(d, np.arange(1, 121)) for d in descs], axis=1)
+    return g, vn
+
+
+def test_batched_step_failures_leave_every_slot_at_its_last_committed_step():
+    """Three ionizing discharges stepped by one persistent launch per step
+    (launch tables, births staging and growth all take device memory): each
+    refused request ends the call with every slot at its last committed
+    step, and each slot's retry from there ends bit-identical to a run that
+    never failed."""
+    ra = FailingAllocator()
+    ref, vn = ionizing_ensemble(ra)
+    r0 = ra.requests
+    st = ref.step(0, 120, vn, solve_field=True, sort_every=20, batched=4096)
+    sites = ra.requests - r0
+    print("requests in the batched step call", sites, "room stops", st["room_stops"], flush=True)
+    assert st["room_stops"] > 0 and sites >= 5
+    for k in range(1, sites + 1):
+        a = FailingAllocator(fail_at=r0 + k)
+        g, _ = ionizing_ensemble(a)
+        assert a.requests == r0
+        with pytest.raises(B.PicError) as e:
+            g.step(0, 120, vn, solve_field=True, sort_every=20, batched=4096)
+        assert e.value.code == B.PIC_E_NOMEM, (k, e.value)
+        for j in range(3):
+            done = g.step_index(j)
+            assert 0 <= done <= 120, (k, j, done)
+            if done < 120:
+                g.step(-1, 120 - done, vn[done:, j:j + 1], solve_field=True, sort_every=20, batched=4096, slots=[j])
+            same_state(ref, g, j, j, what=f"slot {j}, failure at request {k} of {sites}, stopped at step {done}")
         g.close()
     ref.close()
