@@ -980,6 +980,8 @@ int pic_field_solve(pic_ctx c, int slot, double phi_left, const double* phi_init
   if (!sl.stencil_ok) {
     for (void* p : {(void*)sl.st.nbr, (void*)sl.st.code, (void*)sl.st.diag, (void*)sl.st.bnd, (void*)sl.cg_ws})
       sl.release(p);
+    sl.st = Stencil2D{nullptr, nullptr, nullptr, nullptr};   // (a failed allocation below leaves them null;
+    sl.cg_ws = nullptr;                                        // stencil_ok stays false until all are built)
     sl.st.nbr = (uint32_t*)sl.alloc(4 * 8 * (size_t)n);
     sl.st.code = (uint32_t*)sl.alloc(4 * ((size_t)n + 1));
     sl.st.diag = (double*)sl.alloc(8 * (size_t)n);

@@ -15,8 +15,11 @@ rather than a launch):
     goes on equal to a context that never failed;
   - a particle load: PIC_E_NOMEM leaves the slot as it was, and loading again
     gives the state of a load that never failed;
-  - a batched step of three ionizing 1D discharges: every slot stays at its
-    last committed step, and each slot's retry ends bit-identical."""
+  - batched steps of three ionizing 1D discharges and of two avalanches:
+    every slot stays at its last committed step, and each slot's retry ends
+    bit-identical;
+  - a 2D field solve after an adaptation: PIC_E_NOMEM, and solving again
+    gives the same potential bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -214,6 +217,86 @@ def test_batched_step_failures_leave_every_slot_at_its_last_committed_step():
             assert 0 <= done <= 120, (k, j, done)
             if done < 120:
                 g.step(-1, 120 - done, vn[done:, j:j + 1], solve_field=True, sort_every=20, batched=4096, slots=[j])
+            same_state(ref, g, j, j, what=f"slot {j}, failure at request {k} of {sites}, stopped at step {done}")
+        g.close()
+    ref.close()
+
+
+def adapted_avalanche(alloc):
+    d = I.streamer_desc(precision=32, max_level=8)
+    g = B.Context(d, allocator=alloc)
+    for sp, (s, v, w, ids) in enumerate(I.streamer_particles(d, npairs=3000)):
+        g.load(0, sp, s, v, w, ids)
+    g.field_solve_2d(0, rtol=1e-10)
+    g.leapfrog_start(0)
+    g.step(0, 20)
+    g.adapt(0)   # a new tree: the next solve builds its stencil anew
+    return g
+
+
+def test_field_solve_failures_leave_the_slot_usable():
+    """The 2D solve's stencil and CG workspace (Sec. 3.1 finite volumes on
+    the tree) are built after an adaptation: a refused request returns
+    PIC_E_NOMEM, and the solve called again gives the same potential and
+    field bit for bit, and the same steps after it."""
+    ra = FailingAllocator()
+    ref = adapted_avalanche(ra)
+    r0 = ra.requests
+    phi_ref = ref.field_solve_2d(0, rtol=1e-10)[0]
+    sites = ra.requests - r0
+    print("requests in the field solve", sites, flush=True)
+    assert sites >= 5
+    ref.step(-1, 10)
+    for k in range(1, sites + 1):
+        a = FailingAllocator(fail_at=r0 + k)
+        g = adapted_avalanche(a)
+        assert a.requests == r0
+        with pytest.raises(B.PicError) as e:
+            g.field_solve_2d(0, rtol=1e-10)
+        assert e.value.code == B.PIC_E_NOMEM, (k, e.value)
+        phi = g.field_solve_2d(0, rtol=1e-10)[0]
+        assert np.array_equal(phi, phi_ref), k
+        g.step(-1, 10)
+        same_state(ref, g, what=f"field solve failed at request {k} of {sites}")
+        g.close()
+    ref.close()
+
+
+def two_avalanches(alloc):
+    d = fast_ionizing(I.streamer_desc(precision=32, max_level=8))
+    descs = [dict(d, seed=21, capacity=TIGHT_5000), dict(d, seed=22, capacity=TIGHT_5000)]
+    g = B.Context(descs, allocator=alloc)
+    for j, dd in enumerate(descs):
+        for sp, (s, v, w, ids) in enumerate(I.streamer_particles(dd, npairs=5000, rng_seed=[50 + j])):
+            g.load(j, sp, s, v, w, ids)
+        g.field_solve_2d(j, rtol=1e-10)
+        g.leapfrog_start(j)
+    return g
+
+
+def test_batched_2d_step_failures_leave_every_slot_at_its_last_committed_step():
+    """Two growing avalanches stepped by one persistent launch per step: each
+    refused request ends the call with both slots at their last committed
+    steps, and each slot's retry ends bit-identical."""
+    ra = FailingAllocator()
+    ref = two_avalanches(ra)
+    r0 = ra.requests
+    st = ref.step(-1, 96, slots=[0, 1], batched=2048, grid=2048)
+    sites = ra.requests - r0
+    print("requests in the batched 2D step call", sites, "room stops", st["room_stops"], flush=True)
+    assert st["room_stops"] > 0 and sites >= 5
+    for k in range(1, sites + 1):
+        a = FailingAllocator(fail_at=r0 + k)
+        g = two_avalanches(a)
+        assert a.requests == r0
+        with pytest.raises(B.PicError) as e:
+            g.step(-1, 96, slots=[0, 1], batched=2048, grid=2048)
+        assert e.value.code == B.PIC_E_NOMEM, (k, e.value)
+        for j in range(2):
+            done = g.step_index(j)
+            assert 0 <= done <= 96, (k, j, done)
+            if done < 96:
+                g.step(-1, 96 - done, slots=[j], batched=2048, grid=2048)
             same_state(ref, g, j, j, what=f"slot {j}, failure at request {k} of {sites}, stopped at step {done}")
         g.close()
     ref.close()
