@@ -56,8 +56,9 @@
  *    does the overflow guard above.  Every later call on a failed slot
  *    returns PIC_E_STATE, except pic_count, pic_next_id, pic_step_index,
  *    pic_nleaves, pic_nq, pic_slot_bytes and pic_retire; the context's other
- *    slots are unaffected.  Device memory running out in pic_step or
- *    pic_particles_load leaves the slot usable (see above and below).
+ *    slots are unaffected.  Device memory running out in pic_step,
+ *    pic_particles_load or pic_field_solve leaves the slot usable (see
+ *    above and below).
  *  - Launch checks: with PIC_CHECK_LAUNCHES=1 in the environment, every
  *    kernel-side view of a slot is checked on the host against the slot's
  *    live device blocks before it is used (each array inside one block with
