@@ -40,7 +40,7 @@ def draw_1d(seed):
     return d, int(rng.choice([0, 7, 20]))
 
 
-@pytest.mark.parametrize("seed", range(9))
+@pytest.mark.parametrize("seed", range(15))
 def test_random_1d(seed):
     d, sort_every = draw_1d(seed)
     what = f"seed {seed}: {d['ncells']} cells, ppc {d['extra']['ppc']}, fp{d['precision']}, scheme {d['field_scheme']}"
@@ -74,7 +74,7 @@ def draw_tree(seed, dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(9))
 def test_random_static_tree(dim, seed):
     d, n, scale, sort_every = draw_tree(seed, dim)
     what = (f"seed {seed}: dim {dim}, levels {d['min_level']}-{d['max_level']}, {n} particles, "
@@ -111,7 +111,7 @@ def adapt_both(o, g):
         assert so[k] == sg[k], (k, so[k], sg[k])
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(6))
 def test_random_avalanche_with_adaptation(seed):
     """The 2D collision path with births on a dynamic tree: random domain,
     field, levels, seed size and precision; 40 steps with an adaptation every
