@@ -3,8 +3,10 @@ stepped on the GPU through the C ABI and by the oracle.  The draws cover
 meshes from 2 cells up, particle counts from 1, both precisions, every 1D
 coupling (momentum- and energy-conserving CIC, direct implicit), both wall
 rules, sort periods, quadtrees and octrees of random depth and refinement
-(including octrees deeper than the point-location table), and the 2D
-collision path with births and adaptation.  Discrete results bit for bit;
+(including octrees deeper than the point-location table), the 2D
+collision path with births and adaptation, and batched launches over
+several 1D discharges or several avalanches (random work-item sizes, grids,
+sort periods and graph replay).  Discrete results bit for bit;
 positions and velocities to 1e-12 (FP64) / 1e-5 (FP32) relative."""
 import numpy as np
 import pytest
@@ -148,3 +150,108 @@ def test_random_avalanche_with_adaptation(seed):
         assert_same_particles(o.read(sp), g.read(0, sp), TOL[d["precision"]], f"{what} species {sp}")
     assert o.next_id == g.next_id(0)
     assert np.array_equal(o.deposit(), g.deposit(0)), what
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_batched_1d(seed):
+    """Two to six uneven discharges of one precision stepped by one
+    persistent launch per step: random meshes, particles per cell,
+    couplings, wall rules, work-item size, grid, sort period and graph
+    replay, against the oracle slot by slot."""
+    rng = np.random.Generator(np.random.PCG64(4000 + seed))
+    prec = int(rng.choice([32, 64]))
+    descs = []
+    for k in range(int(rng.integers(2, 7))):
+        d = I.ccp_desc(ncells=int(rng.choice([2, 5, 17, 64, 300, 1000])), ppc=int(rng.integers(1, 25)), precision=prec,
+                       voltage=float(rng.uniform(50.0, 600.0)), pressure_mtorr=float(rng.uniform(10.0, 100.0)),
+                       seed=int(rng.integers(1, 1000)), instance_key=k)
+        d["field_scheme"] = int(rng.choice([I.FIELD_CIC_EM, I.FIELD_CIC_EC]))
+        d["particle_bc"] = int(rng.choice([I.ABSORB, I.REFLECT]))
+        descs.append(d)
+    tile, grid = int(rng.choice([256, 1024, 4096])), int(rng.choice([16, 256, 2048]))
+    graph, sort_every = int(rng.choice([0, 0, 5])), int(rng.choice([0, 10, 20]))
+    what = f"seed {seed}: {len(descs)} slots fp{prec}, tile {tile}, grid {grid}, graph {graph}, sort {sort_every}"
+    nsteps = 40
+    vn = np.stack([I.drive_voltage(d, np.arange(1, nsteps + 1)) for d in descs], axis=1)
+    g = B.Context(descs)
+    orc = [oracle.Oracle(d) for d in descs]
+    for j, d in enumerate(descs):
+        v0 = float(I.drive_voltage(d, 0))
+        for sp, (s, v, w, ids) in enumerate(I.ccp_particles(d)):
+            g.load(j, sp, s, v, w, ids)
+            orc[j].load(sp, s, v, w, ids)
+        g.deposit(j)
+        orc[j].deposit()
+        g.field_solve_1d(j, v0)
+        orc[j].field_solve_1d(v0)
+        g.leapfrog_start(j)
+        orc[j].leapfrog_start()
+    sg = g.step(0, nsteps, vn, solve_field=True, batched=tile, grid=grid, sort_every=sort_every, graph_steps=graph)
+    so = [o.step(0, nsteps, vn[:, j], True) for j, o in enumerate(orc)]
+    for k in ("elastic", "ionization", "cx", "births", "lost_reflect"):
+        assert sg[k] == sum(s[k] for s in so), (what, k)
+    for k in ("alive_start", "absorbed", "numax_violations"):
+        assert list(sg[k]) == [sum(s[k][i] for s in so) for i in range(2)], (what, k)
+    for j, o in enumerate(orc):
+        for sp in range(2):
+            assert_same_particles(o.read(sp), g.read(j, sp), TOL[prec], f"{what} slot {j} species {sp}")
+        assert o.next_id == g.next_id(j), (what, j)
+        a, b = o.field_table(), g.field_table(j)
+        assert np.allclose(a, b, rtol=TOL[prec], atol=TOL[prec] * np.abs(a).max()), (what, j)
+        assert np.array_equal(o.deposit(), g.deposit_read(j)), (what, j)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_batched_avalanches(seed):
+    """Two to four avalanches of one precision on dynamic trees stepped by
+    one persistent launch per step (random domains, fields, levels, seed
+    sizes, work-item size and grid), with an adaptation every 10 steps,
+    against the oracle slot by slot."""
+    rng = np.random.Generator(np.random.PCG64(5000 + seed))
+    prec = int(rng.choice([32, 64]))
+    descs, parts, fields = [], [], []
+    for k in range(int(rng.integers(2, 5))):
+        lo = int(rng.integers(3, 6))
+        side, e0 = float(rng.uniform(0.002, 0.01)), float(rng.uniform(2e6, 4e6))
+        d = I.streamer_desc(side=side, precision=prec, seed=int(rng.integers(1, 1000)), e0=e0, min_level=lo,
+                            max_level=min(lo + int(rng.integers(2, 5)), 10))
+        descs.append(d)
+        parts.append(I.streamer_particles(d, npairs=int(rng.integers(200, 2000)),
+                                          sigma=float(rng.uniform(2e-4, 1e-3)) * side / 0.01, rng_seed=[5000 + 10 * seed + k]))
+        fields.append((e0, side))
+    tile, grid = int(rng.choice([256, 1024, 2048])), int(rng.choice([64, 512, 2048]))
+    what = f"seed {seed}: {len(descs)} slots fp{prec}, tile {tile}, grid {grid}"
+    g = B.Context(descs)
+    orc = [oracle.Oracle(d) for d in descs]
+    for j in range(len(descs)):
+        for sp, (s, v, w, ids) in enumerate(parts[j]):
+            g.load(j, sp, s, v, w, ids)
+            orc[j].load(sp, s, v, w, ids)
+    slots = list(range(len(descs)))
+    for n in range(0, 30, 10):
+        for j, o in enumerate(orc):
+            so, sg = o.adapt(), g.adapt(j)
+            for k in ("refined", "coarsened", "balance_refined", "split_parents", "merged_pairs", "nleaves"):
+                assert so[k] == sg[k], (what, j, k)
+            keys, lv = o.leaves()
+            cx, cy = I.leaf_corners(keys, lv)
+            e0, side = fields[j]
+            o.field_set(oracle.CORNER_PHI_2D, e0 * cy * side)
+            g.field_set(j, B.CORNER_PHI_2D, e0 * cy * side)
+            if n == 0:
+                o.leapfrog_start()
+                g.leapfrog_start(j)
+        sg = g.step(n, 10, slots=slots, batched=tile, grid=grid, sort_every=4)
+        so = [o.step(n, 10) for o in orc]
+        for k in ("elastic", "ionization", "cx", "births", "lost_reflect"):
+            assert sg[k] == sum(s[k] for s in so), (what, n, k)
+        for k in ("alive_start", "absorbed", "numax_violations"):
+            assert list(sg[k]) == [sum(s[k][i] for s in so) for i in range(2)], (what, n, k)
+    for j, o in enumerate(orc):
+        ko, lo_ = o.leaves()
+        kg, lg = g.leaves(j)
+        assert np.array_equal(ko, kg) and np.array_equal(lo_, lg), (what, j)
+        for sp in range(2):
+            assert_same_particles(o.read(sp), g.read(j, sp), TOL[prec], f"{what} slot {j} species {sp}")
+        assert o.next_id == g.next_id(j), (what, j)
+        assert np.array_equal(o.deposit(), g.deposit(j)), (what, j)
