@@ -255,3 +255,39 @@ def test_random_batched_avalanches(seed):
             assert_same_particles(o.read(sp), g.read(j, sp), TOL[prec], f"{what} slot {j} species {sp}")
         assert o.next_id == g.next_id(j), (what, j)
         assert np.array_equal(o.deposit(), g.deposit(j)), (what, j)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_octree_avalanche(seed):
+    """Electron avalanches on static octrees (paper Sec. 4.1 3D runs): random
+    cube side, field, refinement depth (past the point-location table for
+    some), seed size and spread, precision, births ranking and sort period;
+    40 steps with collisions and births against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(6000 + seed))
+    top = int(rng.integers(5, 9))
+    d = I.octree_avalanche_desc(precision=int(rng.choice([32, 64])), seed=int(rng.integers(1, 1000)),
+                                side=float(rng.uniform(0.002, 0.008)), e0=float(rng.uniform(2e6, 4e6)), top=top)
+    d["disk_r"] = float(rng.uniform(0.05, 0.1)) if top == 8 else float(rng.uniform(0.1, 0.25))   # refined ball
+    parts = I.octree_avalanche_particles(d, npairs=int(rng.integers(100, 3000)), sigma=float(rng.uniform(0.05, 0.2)))
+    ranking, sort_every = int(rng.choice([0, 1, 2])), int(rng.choice([0, 7, 16]))
+    what = f"seed {seed}: levels 4-{top}, fp{d['precision']}, ranking {ranking}, sort {sort_every}"
+    o, g = load_both(d, parts)
+    g.set_births_ranking(0, ranking)
+    keys, lv = o.leaves()
+    x, y, z = I.leaf_corners3(keys, lv)
+    phi = I.octree_avalanche_phi(d, x * d["length"], y * d["length"], z * d["length"])
+    o.field_set(oracle.CORNER_PHI_3D, phi)
+    g.field_set(0, B.CORNER_PHI_3D, phi)
+    o.leapfrog_start()
+    g.leapfrog_start(0)
+    births = 0
+    for k in range(0, 40, 20):
+        so = o.step(k, 20)
+        sg = g.step(-1, 20, sort_every=sort_every)
+        same_stats(so, sg, f"{what} steps {k}..{k + 19}")
+        births += so["births"]
+    assert births > 0, what
+    for sp in range(2):
+        assert_same_particles(o.read(sp), g.read(0, sp), TOL[d["precision"]], f"{what} species {sp}")
+    assert o.next_id == g.next_id(0), what
+    assert np.array_equal(o.deposit(), g.deposit_read(0)), what
