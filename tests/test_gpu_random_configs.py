@@ -116,17 +116,21 @@ def adapt_both(o, g):
 @pytest.mark.parametrize("seed", range(6))
 def test_random_avalanche_with_adaptation(seed):
     """The 2D collision path with births on a dynamic tree: random domain,
-    field, levels, seed size and precision; 40 steps with an adaptation every
-    10 (refine, coarsen, balance, split, merge), both sides on the same field
-    table (the analytic uniform field set at the new leaves' corners)."""
+    field, levels, seed size and precision, with either coupling (NGP with
+    nodal E, or the cloud-in-cell on the tree, Sec. 3.1); 40 steps with an
+    adaptation every 10 (refine, coarsen, balance, split, merge), both sides
+    on the same field table (the analytic uniform field set at the new
+    leaves' corners)."""
     rng = np.random.Generator(np.random.PCG64(3000 + seed))
     lo = int(rng.integers(3, 6))
     side, e0 = float(rng.uniform(0.002, 0.01)), float(rng.uniform(2e6, 4e6))
     d = I.streamer_desc(side=side, precision=int(rng.choice([32, 64])), seed=int(rng.integers(1, 1000)), e0=e0,
                         min_level=lo, max_level=min(lo + int(rng.integers(2, 5)), 10))
+    d["field_scheme"] = (I.FIELD_CIC_EM, I.FIELD_CIC_AMR)[seed % 2]   # NGP with nodal E, or the tree cloud-in-cell
     parts = I.streamer_particles(d, npairs=int(rng.integers(200, 3000)), sigma=float(rng.uniform(2e-4, 1e-3)) * side / 0.01,
                                  rng_seed=[3000 + seed])
-    what = f"seed {seed}: levels {d['min_level']}-{d['max_level']}, side {side:.4f}, fp{d['precision']}"
+    what = (f"seed {seed}: levels {d['min_level']}-{d['max_level']}, side {side:.4f}, fp{d['precision']}, "
+            f"scheme {d['field_scheme']}")
     o, g = load_both(d, parts)
     births = 0
     for n in range(0, 40, 10):
