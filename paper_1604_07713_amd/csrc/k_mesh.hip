@@ -142,13 +142,29 @@ constexpr uint32_t kSortWin = 1024;
 // move can change a leaf index a lot; a window anchored on one sample would
 // miss the whole range whenever that sample has jumped.  Window slots map to
 // cells base + slot.
+// The three samples are taken by lanes 0-2 at once (each loads the weight
+// and the cell together), then every thread forms the same base after a
+// barrier; smp is a three-word LDS array.  Every thread of the workgroup
+// calls it.
 template <class T>
-__device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end) {
+__device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp, uint32_t begin, uint32_t end,
+                                                     uint32_t* smp) {
+  if (threadIdx.x < 3u) {
+    const uint32_t k = threadIdx.x;
+    uint32_t key = kNoKey;
+    if (begin < end) {
+      const uint32_t at = k == 0u ? begin : k == 1u ? begin + (end - begin) / 2u : end - 1u;
+      const uint32_t w = G(I.w[sp])[at];
+      const uint32_t c = sort_cell<T>(I, sp, at);
+      key = w != 0u ? c : kNoKey;
+    }
+    smp[k] = key;
+  }
+  __syncthreads();
   uint32_t c[3];
   int n = 0;
-  const uint32_t at3[3] = {begin, begin + (end - begin) / 2u, end - 1u};
   for (int k = 0; k < 3; ++k)
-    if (G(I.w[sp])[at3[k]] != 0u) c[n++] = sort_cell<T>(I, sp, at3[k]);
+    if (smp[k] != kNoKey) c[n++] = smp[k];
   uint32_t m = 0u;
   if (n == 1) m = c[0];
   else if (n == 2) m = c[0] < c[1] ? c[0] : c[1];
@@ -163,14 +179,10 @@ __device__ __forceinline__ uint32_t sort_window_base(const InstDev<T>& I, int sp
 template <class T>
 __device__ void sort_hist_range(const InstDev<T>& I, int sp, uint32_t* hist, uint32_t begin, uint32_t end) {
   __shared__ uint32_t win[kSortWin];
-  __shared__ uint32_t base_s;
+  __shared__ uint32_t smp[3];
   __syncthreads();   // the window may still be read by a previous range
   for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) win[j] = 0u;
-  if (threadIdx.x == 0) {
-    base_s = begin < end ? sort_window_base<T>(I, sp, begin, end) : 0u;
-  }
-  __syncthreads();
-  const uint32_t base = base_s;
+  const uint32_t base = sort_window_base<T>(I, sp, begin, end, smp);   // (its barrier also orders the zeroing)
   for (uint32_t i0 = begin; i0 < end; i0 += kBlock) {
     const uint32_t i = i0 + threadIdx.x;
     const bool live = i < end && G(I.w[sp])[i] != 0u;
@@ -234,12 +246,11 @@ __device__ void sort_scatter_range(const InstDev<T>& I, int sp, uint32_t* off, u
   constexpr uint32_t kSub = PIC_SORT_SUB;   // particles per lane per window pass
   __shared__ uint32_t lcnt[kSortWin];
   __shared__ uint32_t gbase[kSortWin];
-  __shared__ uint32_t base_s;
+  __shared__ uint32_t smp[3];
   for (uint32_t t0 = begin; t0 < end; t0 += kSub * kBlock) {
     for (uint32_t j = threadIdx.x; j < kSortWin; j += kBlock) lcnt[j] = 0u;
-    if (threadIdx.x == 0) base_s = sort_window_base<T>(I, sp, t0, t0 + kSub * kBlock < end ? t0 + kSub * kBlock : end);
-    __syncthreads();
-    const uint32_t base = base_s;
+    // (the sampling's barrier also orders the zeroing)
+    const uint32_t base = sort_window_base<T>(I, sp, t0, t0 + kSub * kBlock < end ? t0 + kSub * kBlock : end, smp);
     uint32_t o[kSub], slot[kSub];
     bool live[kSub], inwin[kSub];
 #pragma unroll
